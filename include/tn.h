@@ -1,0 +1,268 @@
+/*
+ * tn.h -- C ABI of the MI355X term-network contractor for the SVD-based
+ * approximate noisy-circuit simulation (arXiv 2211.17028).
+ *
+ * Problem (Section III, Problem 1): given a noisy circuit E = E_d o ... o E_1
+ * of gates and single-qubit noise channels, an input product state |psi> and a
+ * target state |v>, estimate <v| E(|psi><psi|) |v>.
+ *
+ * Method (Section IV, Algorithm 1): every noise superoperator
+ * M = sum_k E_k (x) conj(E_k) is permuted (Fig. 3a) and split by SVD into
+ * M = sum_{i=0..3} U_i (x) V_i (Fig. 3b-c).  The level-l approximation is
+ * A(l) = sum_{u<=l} T_u, where T_u sums, over all choices of u noises and of
+ * one correction i in {1,2,3} at each, the value X of the network in which
+ * those noises carry U_i (x) V_i and all others U_0 (x) V_0.  Each X is a
+ * product of a ket network and a bra network; for a channel the bra network is
+ * the conjugate of the ket network, so X = w |a|^2 with a one ket-network
+ * amplitude and w >= 0 a product of singular values.
+ *
+ * Conventions
+ *   - Complex inputs are tn_c128 (two doubles).  Matrices are row-major.
+ *   - A 2-qubit gate on (q0, q1) is 4x4 in the basis |b_q0 b_q1>, b_q0 the more
+ *     significant bit.  A dense n-qubit state has qubit 0 as the most
+ *     significant bit of its index.
+ *   - A noise acts on one qubit, right after the op before it in the list.
+ *   - Device pointers are HIP device addresses; `stream` is a hipStream_t
+ *     passed as void* (NULL = the null stream).
+ *
+ * Errors: every int-returning call returns TN_OK (0) or a negative TN_E*
+ * code; tn_last_error() then holds a message (thread-local, valid until the
+ * next tn_* call on the same thread).  No C++ exception crosses this ABI.
+ *
+ * Ownership: the caller owns every input it passes (the library copies what
+ * it keeps during the call), all device memory (inputs, outputs and the
+ * workspace) and the result structs.  The library owns tn_plan, tn_terms and
+ * tn_exec handles until the matching *_destroy call.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TN_OK = 0,
+    TN_EINVAL = -1,        /* malformed argument, non-unitary gate, bad qubit index */
+    TN_ENOTCPTP = -2,      /* Kraus set not trace preserving: ||sum E^+E - I|| > 1e-10 */
+    TN_EUNSUPPORTED = -3,  /* noise on more than one qubit, gate on more than two */
+    TN_EDEGENERATE = -4,   /* dominant singular value not strictly largest */
+    TN_ENOMEM = -5,        /* workspace smaller than required */
+    TN_EHIP = -6,          /* a HIP runtime call failed (message has the HIP string) */
+    TN_ETOOBIG = -7,       /* plan exceeds a hard limit (slots per network, tensor rank) */
+    TN_ESTATE = -8         /* call out of order (e.g. terms of another plan) */
+};
+
+typedef struct { double re, im; } tn_c128;
+
+enum { TN_GATE = 0, TN_NOISE = 1 };
+
+typedef struct {
+    int32_t kind;          /* TN_GATE or TN_NOISE */
+    int32_t nq;            /* gate: 1 or 2; noise: 1 */
+    int32_t q[2];          /* qubit indices (q[1] unused when nq == 1) */
+    int32_t n_kraus;       /* noise: number of 2x2 Kraus matrices (>= 1) */
+    const tn_c128* mat;    /* gate: (2^nq)^2 entries; noise: n_kraus * 4 entries */
+} tn_op;
+
+typedef struct {
+    int32_t n_qubits;
+    int64_t n_ops;
+    const tn_op* ops;      /* in time order */
+} tn_circuit;
+
+enum {
+    TN_STATE_PRODUCT = 0,         /* data: n_qubits x 2 amplitudes */
+    TN_STATE_CIRCUIT_OUTPUT = 1,  /* |v> = U_ideal |p>, data: n_qubits x 2 of |p>;
+                                     U_ideal is the circuit with its noises removed */
+    TN_STATE_DENSE = 2            /* data: 2^n_qubits amplitudes (n_qubits <= 30) */
+};
+
+typedef struct {
+    int32_t kind;
+    const tn_c128* data;
+} tn_state;
+
+typedef struct tn_plan_s* tn_plan;
+typedef struct tn_terms_s* tn_terms;
+typedef struct tn_exec_s* tn_exec;
+
+#define TN_MAX_LEVEL 8
+
+/* Planner options; zero-initialise for defaults. */
+typedef struct {
+    int32_t path_trials;    /* randomized greedy path trials per network (0 = 64) */
+    uint64_t seed;          /* path search seed (0 = fixed default) */
+    int32_t no_light_cone;  /* 1 = keep gates outside the slots' light cone */
+    int32_t max_log_size;   /* cap on log2(elements) of one tensor (0 = 30) */
+} tn_plan_opts;
+
+/* Term pruning (level-2/3 candidates).  NULL = the full expansion. */
+typedef struct {
+    int32_t min_level;         /* only terms of level >= min_level are candidates */
+    const uint8_t* keep;       /* n_candidates flags (1 = keep), in enumeration order
+                                  of the candidates; NULL = keep all */
+    int64_t n_keep;            /* length of keep */
+} tn_prune_opts;
+
+enum { TN_MODE_BATCHED = 0, TN_MODE_PLAIN = 1 };
+
+typedef struct {
+    int32_t mode;            /* TN_MODE_BATCHED or TN_MODE_PLAIN */
+    int32_t use_graph;       /* batched: capture the step sequence in a hipGraph */
+    int32_t fp64_level0;     /* 1 = recompute the all-dominant term in FP64
+                                (tn_estimate always does) */
+    int32_t tune;            /* 1 = pick GEMM tiles by timing (autotuner) */
+} tn_exec_opts;
+
+/* Per-circuit result of an estimate (host struct, filled by the library). */
+typedef struct {
+    int32_t level;                        /* effective level (clamped to N) */
+    int32_t clamped;                      /* 1 if the requested level exceeded N */
+    int64_t n_terms;                      /* terms in the term set */
+    int64_t n_contracted;                 /* terms with non-zero weight */
+    int64_t n_zero_weight;                /* terms skipped: some d_i is exactly 0 */
+    double level_sum[TN_MAX_LEVEL + 1];   /* T_u, u = 0..level (compensated) */
+    double level_comp[TN_MAX_LEVEL + 1];  /* Neumaier compensation of T_u (already added) */
+    double A[TN_MAX_LEVEL + 1];           /* A(u) = sum_{u'<=u} T_u' */
+    double bound;                         /* |F - A(level)| bound from the split norms */
+    double x0_fp32;                       /* level-0 term from the FP32 batch (diagnostic) */
+} tn_result;
+
+/* ---------------------------------------------------------------------------
+ * tn_plan_build -- validate the circuit, split every noise, build the ket
+ * network of one term (all terms share its topology), reduce it by the slots'
+ * light cone when the target is the circuit output, split it into independent
+ * clusters, and choose a contraction path per cluster.  Host only.
+ *
+ *   circ   circuit (gates and 1-qubit noises, time order)
+ *   psi    input state, TN_STATE_PRODUCT only
+ *   v      target state (any TN_STATE_* kind)
+ *   level  requested level l >= 0 (clamped to N; flagged in the result)
+ *   opts   planner options or NULL
+ *   out    receives the plan handle
+ *
+ * Errors: TN_EINVAL (bad indices, non-unitary gate: ||G^+G - I||_max > 1e-10),
+ * TN_ENOTCPTP (Section II trace condition), TN_EUNSUPPORTED (multi-qubit
+ * noise; the split of Section IV is defined on 4x4 superoperators),
+ * TN_EDEGENERATE (d_1 >= (1 - 1e-12) d_0), TN_ETOOBIG (a cluster with more than
+ * 64 slots, or a path tensor above max_log_size).
+ * ------------------------------------------------------------------------- */
+int tn_plan_build(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                  int32_t level, const tn_plan_opts* opts, tn_plan* out);
+
+/* ---------------------------------------------------------------------------
+ * tn_terms_enumerate -- the term set of Algorithm 1 at level `level`:
+ * u = 0..level; noise subsets p_1 < ... < p_u in lexicographic order; the
+ * corrections (i_1..i_u) in {1,2,3}^u in lexicographic order.  Count:
+ * sum_{u<=l} C(N,u) 3^u (Theorem 1).  Terms whose weight is exactly zero (some
+ * chosen d_i == 0, e.g. the fourth singular value of a rank-3 channel) stay in
+ * the set, flagged, and are never contracted.  `prune` may drop candidates of
+ * level >= prune->min_level.  Host only.
+ * ------------------------------------------------------------------------- */
+int tn_terms_enumerate(tn_plan plan, int32_t level, const tn_prune_opts* prune,
+                       tn_terms* out, int64_t* n_terms);
+
+/* Copy the term set out: patterns (n_terms x N int8, entry = correction index
+ * 0..3 per noise) and weights w_t = prod_s d_{c_s} (float64).  Either pointer may
+ * be NULL.  Host only. */
+int tn_terms_get(tn_terms terms, int8_t* patterns, double* weights);
+
+/* ---------------------------------------------------------------------------
+ * tn_exec_prepare -- build the device schedule for n plans (each with its term
+ * set) packed together: per path step the instance maps of the batch, the
+ * static placement of every intermediate in the workspace, and the upload of
+ * fixed tensors, slot tensors and maps.
+ *
+ *   ws_bytes == 0 : only report the size needed in *need_bytes (no device call);
+ *                   if `out` is not NULL it receives an unbound handle usable by
+ *                   tn_exec_describe / tn_exec_const_bytes / tn_exec_destroy only.
+ *   otherwise d_ws must hold >= *need_bytes bytes (else TN_ENOMEM); the upload
+ *   is enqueued on `stream` and *out receives an executable handle bound to
+ *   d_ws (the caller keeps d_ws alive and unmodified until tn_exec_destroy).
+ * ------------------------------------------------------------------------- */
+int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms,
+                    const tn_exec_opts* opts, void* d_ws, size_t ws_bytes, void* stream,
+                    size_t* need_bytes, tn_exec* out);
+
+/* Run a prepared schedule on `stream` and synchronize it; fill one tn_result
+ * per plan (results[n]). */
+int tn_exec_run(tn_exec ex, void* stream, tn_result* results);
+
+/* Device pointer to the per-term values X_t (float64, concatenated over the
+ * packed plans in order) and to the per-term amplitudes a_t (complex64 pairs),
+ * valid after tn_exec_run. */
+int tn_exec_outputs(tn_exec ex, const double** d_x, const float** d_amp, int64_t* n_total);
+
+/* Copy the per-term values X_t (float64) and amplitudes a_t (complex64 as
+ * float pairs) of packed plan `plan` to host memory (n_terms entries each;
+ * either pointer may be NULL).  Synchronous; valid after tn_exec_run. */
+int tn_exec_copy_outputs(tn_exec ex, int32_t plan, double* h_x, float* h_amp);
+
+/* Timing of the last tn_exec_run: total milliseconds on the stream and the
+ * summed duration of GEMM / permute / other kernels (HIP events; -1 if the
+ * breakdown was not recorded). */
+int tn_exec_timing(tn_exec ex, double* total_ms, double* gemm_ms, double* permute_ms,
+                   double* other_ms);
+
+/* ---------------------------------------------------------------------------
+ * tn_contract_batch -- contract the ket networks of terms [first, first+count)
+ * of each packed plan's term set and write their amplitudes a_t as complex64
+ * to d_amp (count values per plan, plan-major).  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, int64_t first,
+                      int64_t count, void* d_amp, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * tn_estimate -- Algorithm 1 end to end for n packed plans: prepare, run,
+ * synchronize, fill results[n].  Equivalent to tn_exec_prepare + tn_exec_run +
+ * tn_exec_destroy with default options.
+ * ------------------------------------------------------------------------- */
+int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_ws,
+                size_t ws_bytes, void* stream, tn_result* results);
+
+/* Workspace bytes tn_estimate needs for these plans and term sets. */
+int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms,
+                      size_t* need_bytes);
+
+/* Introspection (host only). -------------------------------------------- */
+typedef struct {
+    int32_t n_qubits, n_noise, level, clamped;
+    int32_t n_clusters;            /* independent networks after light-cone reduction */
+    int32_t n_leaves;              /* tensors of the reduced ket network */
+    int32_t max_log_size;          /* largest path tensor, log2 elements (one instance) */
+    double flops_per_term;         /* 8 * sum of complex MACs of the path, one term */
+} tn_plan_info;
+
+int tn_plan_get_info(tn_plan plan, tn_plan_info* info);
+
+/* Singular values d[4] (descending), the normalised slot matrices K_i
+ * (4 x 2x2 row-major, K_i = unvec of the i-th singular vector) and the noise
+ * rate ||M - I||_2 of noise s. */
+int tn_plan_noise(tn_plan plan, int32_t s, double* d, tn_c128* k, double* rate);
+
+/* JSON description of the plan (clusters, leaves, path) into buf (NUL
+ * terminated); *len receives the needed size including the NUL. */
+int tn_plan_describe(tn_plan plan, char* buf, size_t* len);
+
+/* JSON description of a prepared schedule's steps (shapes, instances,
+ * modes) into buf; *len receives the needed size. */
+int tn_exec_describe(tn_exec ex, char* buf, size_t* len);
+
+/* The staged constant region of a prepared (or size-queried) schedule: fixed
+ * tensors, slot tensors, instance maps and permutation tables, exactly as
+ * uploaded to the start of the workspace.  Host only; *len receives the size. */
+int tn_exec_const_bytes(tn_exec ex, void* buf, size_t* len);
+
+void tn_plan_destroy(tn_plan plan);
+void tn_terms_destroy(tn_terms terms);
+void tn_exec_destroy(tn_exec ex);
+const char* tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H */

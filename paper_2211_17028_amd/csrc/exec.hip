@@ -1,0 +1,1208 @@
+// Device schedule and execution of the batched term contractions, and the
+// extern "C" entry points of the library.
+//
+// All term networks of a circuit share one topology (Section IV: only the
+// slot tensors U_i (x) V_i differ).  The path chosen at plan time is run once
+// per estimate: every intermediate tensor is kept once per distinct
+// restriction of the term patterns to the slots below it ("instances"), so a
+// step is one batched contraction over those instances, gathered through
+// per-step index maps.  Slot-free intermediates exist once and are shared by
+// every term.  The term values are X = w |a|^2 (bra network = conjugate of the
+// ket network for a channel), summed per level in FP64 (Algorithm 1).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <unordered_map>
+
+#include "kernels.h"
+#include "tn_internal.h"
+
+namespace tn {
+
+const char* last_error_cstr();
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            fail(TN_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// first-fit allocator over a linear region (offsets only)
+struct Arena {
+    std::map<int64_t, int64_t> free_;
+    int64_t top = 0, peak = 0;
+    int64_t alloc(int64_t bytes) {
+        bytes = round_up(std::max<int64_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                int64_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                return off;
+            }
+        int64_t off = top;
+        top += bytes;
+        peak = std::max(peak, top);
+        return off;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = round_up(std::max<int64_t>(bytes, 1), 256);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+                it = pv;
+            }
+        }
+        if (it->first + it->second == top) {
+            top = it->first;
+            free_.erase(it);
+        }
+    }
+};
+
+// constants staged on the host and uploaded in one copy
+struct ConstBuf {
+    std::vector<unsigned char> bytes;
+    int64_t add(const void* p, int64_t n) {
+        int64_t off = round_up((int64_t)bytes.size(), 256);
+        bytes.resize(off + n);
+        if (p) std::memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+    int64_t reserve(int64_t n) { return add(nullptr, n); }
+};
+
+enum Region { R_CONST = 0, R_WORK = 1 };
+struct Ref {
+    int region = R_CONST;
+    int64_t off = 0;
+};
+
+enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4 };
+
+struct Launch {
+    int kind = 0;
+    int fp64 = 0;
+    // operands (resolved at bind time)
+    Ref a, b, c, ia, ib, table;
+    GemmArgs g{};
+    PermArgs p{};
+    int tile_hint = -1;
+    int kclass = -1;
+    double flops = 0, bytes = 0;   // algorithmic work of this launch
+    int plan = 0;
+    int plain_root = 0;            // PLAIN mode: output offset advances per term
+    int64_t plain_root_stride = 0;
+    // finalize / level sum
+    FinalizeArgs f{};
+    Ref live_index, root_idx, root_ptrs, root64_ptrs, w, x_out, amp_out, starts, sums;
+    int n_levels = 0;
+    // slot fill
+    SlotFillArgs sf{};
+    Ref sf_noise, sf_dst, sf_bank, sf_pattern;
+};
+
+struct PlanExec {
+    const Plan* plan;
+    const Terms* terms;
+    int64_t n_terms = 0, n_live = 0;
+    int64_t zero_term = -1;
+    std::vector<int64_t> level_start;
+    Ref x_out, amp_out, sums;
+    std::vector<Ref> root32;       // per cluster root buffer (FP32 batch)
+    std::vector<int64_t> root32_inst;
+    std::vector<Ref> root64;
+    int64_t n_zero = 0, n_pruned = 0;
+    std::vector<int64_t> live_terms;  // term indices of live terms
+};
+
+}  // namespace tn
+
+struct tn_exec_s {
+    std::vector<tn::Launch> launches;       // batched / FP64 launches, in order
+    std::vector<tn::Launch> plain_launches; // PLAIN mode per-term body
+    std::vector<tn::Launch> tail;           // finalize + level sums
+    std::vector<tn::PlanExec> plans;
+    tn::ConstBuf cbuf;
+    int64_t const_bytes = 0, work_bytes = 0;
+    char* base = nullptr;
+    hipStream_t stream = nullptr;
+    tn_exec_opts opts{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = -1, gemm_ms = -1, perm_ms = -1, other_ms = -1;
+    std::vector<std::pair<int, int>> plain_fill;   // unused placeholder
+    int64_t plain_terms = 0;
+    bool bound = false;
+};
+
+namespace tn {
+
+// ---------------------------------------------------------------------------
+// schedule construction
+// ---------------------------------------------------------------------------
+struct NodeInfo {
+    std::vector<int> legs;     // storage order, legs[0] most significant
+    u128 mask = 0;             // 2 bits per cluster-local slot
+    std::vector<u128> keys;    // sorted distinct instance keys
+    Ref buf;
+    int64_t bytes = 0;
+    bool leaf = true;
+};
+
+struct Builder {
+    tn_exec_s* ex;
+    Arena work;
+    std::vector<Launch>* out;
+
+    static int64_t find_key(const std::vector<u128>& keys, u128 k) {
+        auto it = std::lower_bound(keys.begin(), keys.end(), k);
+        return it - keys.begin();
+    }
+
+    // permutation table from storage order `src` to `dst` (same leg set)
+    Launch make_perm(const std::vector<int>& src, const std::vector<int>& dst, int fp64) {
+        const int r = (int)src.size();
+        std::vector<int> p(r), q(r);
+        for (int j = 0; j < r; ++j) {
+            int leg = dst[r - 1 - j];
+            int pos = (int)(std::find(src.begin(), src.end(), leg) - src.begin());
+            p[j] = r - 1 - pos;
+        }
+        for (int j = 0; j < r; ++j) q[p[j]] = j;
+        const int tb = std::min(r, 5);
+        std::vector<int> tile;
+        for (int j = 0; j < tb; ++j) tile.push_back(j);
+        for (int i = 0; i < tb; ++i)
+            if (std::find(tile.begin(), tile.end(), q[i]) == tile.end()) tile.push_back(q[i]);
+        std::sort(tile.begin(), tile.end());
+        const int tt = (int)tile.size();
+        const int tsize = 1 << tt;
+        std::vector<int32_t> table(3 * tsize);
+        // store order: tile index e <-> out offset
+        for (int e = 0; e < tsize; ++e) {
+            int32_t off = 0;
+            for (int i = 0; i < tt; ++i)
+                if ((e >> i) & 1) off |= 1 << tile[i];
+            table[2 * tsize + e] = off;
+        }
+        // load order: low tb bits of l <-> input bits 0..tb-1 (out bits q[i]); the
+        // rest of the tile positions (input bits >= tb) in ascending tile order
+        std::vector<int> tpos_of_inbit(tb), rest;
+        for (int i = 0; i < tb; ++i)
+            tpos_of_inbit[i] = (int)(std::find(tile.begin(), tile.end(), q[i]) - tile.begin());
+        for (int i = 0; i < tt; ++i)
+            if (p[tile[i]] >= tb) rest.push_back(i);
+        for (int l = 0; l < tsize; ++l) {
+            int t = 0;
+            for (int i = 0; i < tb; ++i)
+                if ((l >> i) & 1) t |= 1 << tpos_of_inbit[i];
+            for (size_t i = 0; i < rest.size(); ++i)
+                if ((l >> (tb + i)) & 1) t |= 1 << rest[i];
+            int32_t in_off = 0;
+            for (int i = 0; i < tt; ++i)
+                if ((t >> i) & 1) in_off |= 1 << p[tile[i]];
+            table[l] = in_off;
+            table[tsize + l] = t;
+        }
+        Launch L;
+        L.kind = L_PERM;
+        L.fp64 = fp64;
+        L.table = Ref{R_CONST, ex->cbuf.add(table.data(), (int64_t)table.size() * 4)};
+        L.p.r = r;
+        L.p.tb = tt;
+        L.p.n_high = r - tt;
+        int h = 0;
+        for (int j = 0; j < r; ++j)
+            if (std::find(tile.begin(), tile.end(), j) == tile.end()) {
+                L.p.high_out[h] = j;
+                L.p.high_in[h] = p[j];
+                ++h;
+            }
+        return L;
+    }
+
+    // Build the launches of one cluster for the given root instance keys.
+    // mode: 0 = FP32 batched, 1 = FP64 (single zero instance), 2 = PLAIN FP32
+    // (single instance, slot leaves filled per term).  Returns the root ref.
+    Ref build_cluster(const Plan& P, const Cluster& cl, const std::vector<u128>& root_keys, int mode,
+                      int plan_index, std::vector<std::pair<int, int64_t>>* plain_slots) {
+        const int fp64 = mode == 1;
+        const int64_t esz = fp64 ? 16 : 8;
+        const int L = (int)cl.leaves.size();
+        const int nn = L + (int)cl.path.size();
+        std::vector<NodeInfo> nodes(nn);
+        std::vector<int> parent(nn, -1);
+        for (size_t j = 0; j < cl.path.size(); ++j) {
+            parent[cl.path[j].a] = L + (int)j;
+            parent[cl.path[j].b] = L + (int)j;
+        }
+        for (int i = 0; i < L; ++i) {
+            const Leaf& lf = P.leaves[cl.leaves[i]];
+            nodes[i].legs = lf.legs;
+            if (lf.slot >= 0) {
+                int local = (int)(std::lower_bound(cl.slots.begin(), cl.slots.end(), lf.slot) - cl.slots.begin());
+                nodes[i].mask = (u128)3 << (2 * local);
+            }
+        }
+        for (size_t j = 0; j < cl.path.size(); ++j) {
+            NodeInfo& c = nodes[L + j];
+            c.leaf = false;
+            c.mask = nodes[cl.path[j].a].mask | nodes[cl.path[j].b].mask;
+        }
+        const int root = nn - 1;
+        nodes[root].keys = root_keys;
+        for (int x = nn - 2; x >= 0; --x) {
+            const NodeInfo& pn = nodes[parent[x]];
+            std::vector<u128> ks;
+            ks.reserve(pn.keys.size());
+            for (u128 k : pn.keys) ks.push_back(k & nodes[x].mask);
+            std::sort(ks.begin(), ks.end());
+            ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+            nodes[x].keys.swap(ks);
+        }
+        // leaves: constant data
+        for (int i = 0; i < L; ++i) {
+            const Leaf& lf = P.leaves[cl.leaves[i]];
+            NodeInfo& nd = nodes[i];
+            const int64_t sz = int64_t(1) << lf.legs.size();
+            if (lf.slot < 0) {
+                if (fp64) {
+                    std::vector<double> d(2 * sz);
+                    for (int64_t e = 0; e < sz; ++e) {
+                        d[2 * e] = lf.data[e].real();
+                        d[2 * e + 1] = lf.data[e].imag();
+                    }
+                    nd.buf = Ref{R_CONST, ex->cbuf.add(d.data(), (int64_t)d.size() * 8)};
+                } else {
+                    std::vector<float> d(2 * sz);
+                    for (int64_t e = 0; e < sz; ++e) {
+                        d[2 * e] = (float)lf.data[e].real();
+                        d[2 * e + 1] = (float)lf.data[e].imag();
+                    }
+                    nd.buf = Ref{R_CONST, ex->cbuf.add(d.data(), (int64_t)d.size() * 4)};
+                }
+            } else {
+                const NoiseSplit& ns = P.noise[lf.slot];
+                int local = (int)(std::lower_bound(cl.slots.begin(), cl.slots.end(), lf.slot) - cl.slots.begin());
+                if (mode == 2) {
+                    // one instance, filled per term
+                    nd.buf = Ref{R_CONST, ex->cbuf.reserve(4 * 8)};
+                    plain_slots->push_back({lf.slot, nd.buf.off});
+                } else {
+                    std::vector<double> d64;
+                    std::vector<float> d32;
+                    for (u128 k : nd.keys) {
+                        int ch = (int)((k >> (2 * local)) & 3);
+                        for (int e = 0; e < 4; ++e) {
+                            cd v = std::sqrt(2.0) * ns.K[ch][e];
+                            d64.push_back(v.real());
+                            d64.push_back(v.imag());
+                            d32.push_back((float)v.real());
+                            d32.push_back((float)v.imag());
+                        }
+                    }
+                    nd.buf = fp64 ? Ref{R_CONST, ex->cbuf.add(d64.data(), (int64_t)d64.size() * 8)}
+                                  : Ref{R_CONST, ex->cbuf.add(d32.data(), (int64_t)d32.size() * 4)};
+                }
+            }
+        }
+        // steps
+        for (size_t j = 0; j < cl.path.size(); ++j) {
+            const int ia_node = cl.path[j].a, ib_node = cl.path[j].b;
+            NodeInfo& A = nodes[ia_node];
+            NodeInfo& B = nodes[ib_node];
+            NodeInfo& C = nodes[L + j];
+            std::vector<int> K, FA, FB;
+            for (int e : A.legs)
+                if (std::find(B.legs.begin(), B.legs.end(), e) != B.legs.end()) K.push_back(e);
+                else FA.push_back(e);
+            for (int e : B.legs)
+                if (std::find(K.begin(), K.end(), e) == K.end()) FB.push_back(e);
+            const int rk = (int)K.size();
+            auto is_suffix = [&](const std::vector<int>& legs, std::vector<int>* order) {
+                if ((int)legs.size() < rk) return false;
+                std::vector<int> tail(legs.end() - rk, legs.end());
+                std::vector<int> a = tail, b = K;
+                std::sort(a.begin(), a.end());
+                std::sort(b.begin(), b.end());
+                if (a != b) return false;
+                *order = tail;
+                return true;
+            };
+            auto is_prefix = [&](const std::vector<int>& legs, std::vector<int>* order) {
+                if ((int)legs.size() < rk) return false;
+                std::vector<int> head(legs.begin(), legs.begin() + rk);
+                std::vector<int> a = head, b = K;
+                std::sort(a.begin(), a.end());
+                std::sort(b.begin(), b.end());
+                if (a != b) return false;
+                *order = head;
+                return true;
+            };
+            // forms: A as [FA | K] (MK) or [K | FA] (KM); B as [K | FB] (KN) or [FB | K] (NK)
+            std::vector<int> a_k, b_k;
+            int a_form = is_suffix(A.legs, &a_k) ? 0 : (is_prefix(A.legs, &a_k) ? 1 : -1);
+            int b_form = is_prefix(B.legs, &b_k) ? 0 : (is_suffix(B.legs, &b_k) ? 1 : -1);
+            const int64_t bytesA = (int64_t)A.keys.size() << A.legs.size();
+            const int64_t bytesB = (int64_t)B.keys.size() << B.legs.size();
+            std::vector<int> korder;
+            bool permA = false, permB = false;
+            if (a_form >= 0 && b_form >= 0 && a_k == b_k) {
+                korder = a_k;
+            } else if (a_form >= 0 && (bytesA >= bytesB || b_form < 0)) {
+                korder = a_k;
+                permB = true;
+            } else if (b_form >= 0) {
+                korder = b_k;
+                permA = true;
+            } else {
+                korder = K;
+                permA = permB = true;
+            }
+            if (a_form >= 0 && a_k != korder) permA = true;
+            if (b_form >= 0 && b_k != korder) permB = true;
+            std::vector<int> a_target = FA, b_target = korder;
+            a_target.insert(a_target.end(), korder.begin(), korder.end());
+            b_target.insert(b_target.end(), FB.begin(), FB.end());
+            int transA = 0, transB = 0;
+            Ref opA = A.buf, opB = B.buf;
+            std::vector<std::pair<int64_t, int64_t>> temps;
+            auto emit_perm = [&](NodeInfo& X, const std::vector<int>& target, Ref* op) {
+                if (X.legs == target) return;
+                Launch pl = make_perm(X.legs, target, fp64);
+                const int64_t nb = (int64_t)X.keys.size() * (int64_t(esz) << X.legs.size());
+                int64_t off = work.alloc(nb);
+                temps.push_back({off, nb});
+                pl.a = *op;
+                pl.c = Ref{R_WORK, off};
+                pl.p.n_inst = (int64_t)X.keys.size();
+                pl.bytes = 2.0 * nb;
+                pl.plan = plan_index;
+                out->push_back(pl);
+                *op = pl.c;
+            };
+            if (permA) emit_perm(A, a_target, &opA);
+            else transA = a_form == 1;
+            if (permB) emit_perm(B, b_target, &opB);
+            else transB = b_form == 1;
+            C.legs = FA;
+            C.legs.insert(C.legs.end(), FB.begin(), FB.end());
+            const int64_t ninst = (int64_t)C.keys.size();
+            C.bytes = ninst * (int64_t(esz) << C.legs.size());
+            if (j + 1 == cl.path.size() && mode == 2) {
+                C.buf = Ref{R_WORK, 0};   // replaced by the per-term root slot
+            } else {
+                C.buf = Ref{R_WORK, work.alloc(C.bytes)};
+            }
+            Launch gl;
+            gl.kind = L_GEMM;
+            gl.fp64 = fp64;
+            gl.plan = plan_index;
+            gl.a = opA;
+            gl.b = opB;
+            gl.c = C.buf;
+            gl.g.m_log = (int)FA.size();
+            gl.g.n_log = (int)FB.size();
+            gl.g.k_log = rk;
+            gl.g.transA = transA;
+            gl.g.transB = transB;
+            gl.g.n_inst = ninst;
+            gl.g.strideA = int64_t(1) << A.legs.size();
+            gl.g.strideB = int64_t(1) << B.legs.size();
+            // instance maps
+            auto mapping = [&](const NodeInfo& X, int* mode_out, Ref* map_out) {
+                if (X.keys.size() == 1) {
+                    *mode_out = 1;
+                    return;
+                }
+                if (X.mask == C.mask) {
+                    *mode_out = 0;
+                    return;
+                }
+                std::vector<int32_t> m(ninst);
+                for (int64_t i = 0; i < ninst; ++i) m[i] = (int32_t)find_key(X.keys, C.keys[i] & X.mask);
+                *mode_out = 2;
+                *map_out = Ref{R_CONST, ex->cbuf.add(m.data(), ninst * 4)};
+            };
+            mapping(A, &gl.g.ia_mode, &gl.ia);
+            mapping(B, &gl.g.ib_mode, &gl.ib);
+            const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
+                         kk = std::ldexp(1.0, gl.g.k_log);
+            gl.flops = 8.0 * mm * nnn * kk * ninst;
+            gl.bytes = (double)esz * (ninst * mm * nnn + (double)A.keys.size() * mm * kk +
+                                      (double)B.keys.size() * kk * nnn);
+            if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
+            out->push_back(gl);
+            for (auto& t : temps) work.release(t.first, t.second);
+            if (!A.leaf) work.release(A.buf.off, A.bytes);
+            if (!B.leaf) work.release(B.buf.off, B.bytes);
+        }
+        return nodes[root].buf;
+    }
+};
+
+static std::vector<u128> cluster_keys(const Plan& P, const Cluster& cl, const Terms& T,
+                                      const std::vector<int64_t>& live,
+                                      std::vector<int32_t>* term_idx_out, int ncl, int ci) {
+    std::vector<u128> keys(live.size());
+    for (size_t i = 0; i < live.size(); ++i) {
+        const int8_t* pat = &T.pat[live[i] * P.n_noise];
+        u128 k = 0;
+        for (size_t j = 0; j < cl.slots.size(); ++j) k |= (u128)(pat[cl.slots[j]] & 3) << (2 * j);
+        keys[i] = k;
+    }
+    std::vector<u128> uk = keys;
+    std::sort(uk.begin(), uk.end());
+    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+    for (size_t i = 0; i < live.size(); ++i)
+        (*term_idx_out)[i * ncl + ci] = (int32_t)Builder::find_key(uk, keys[i]);
+    return uk;
+}
+
+static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms) {
+    Builder bw;
+    bw.ex = ex;
+    bw.out = &ex->launches;
+    const bool plain = ex->opts.mode == TN_MODE_PLAIN;
+    for (int pi = 0; pi < n; ++pi) {
+        const Plan& P = *reinterpret_cast<const Plan*>(plans[pi]);
+        const Terms& T = *reinterpret_cast<const Terms*>(terms[pi]);
+        if (T.plan_id != P.id) fail(TN_ESTATE, "term set belongs to another plan");
+        PlanExec pe;
+        pe.plan = &P;
+        pe.terms = &T;
+        pe.n_terms = T.n;
+        std::vector<int32_t> live_index(T.n, -1);
+        for (int64_t t = 0; t < T.n; ++t) {
+            if (T.zero[t]) { ++pe.n_zero; continue; }
+            if (T.pruned[t]) { ++pe.n_pruned; continue; }
+            live_index[t] = (int32_t)pe.live_terms.size();
+            pe.live_terms.push_back(t);
+        }
+        pe.n_live = (int64_t)pe.live_terms.size();
+        // the all-dominant term is term 0 of the enumeration
+        if (T.n > 0 && T.lvl[0] == 0 && live_index[0] >= 0) pe.zero_term = 0;
+        const int ncl = (int)P.clusters.size();
+        std::vector<int32_t> root_idx(std::max<int64_t>(1, pe.n_live * ncl), 0);
+        std::vector<int64_t> root_ptr_slot(ncl, 0);
+        std::vector<std::pair<int, int64_t>> plain_slots;
+        for (int c = 0; c < ncl; ++c) {
+            const Cluster& cl = P.clusters[c];
+            std::vector<u128> keys = cluster_keys(P, cl, T, pe.live_terms, &root_idx, ncl, c);
+            if (plain) {
+                for (int64_t i = 0; i < pe.n_live; ++i) root_idx[i * ncl + c] = (int32_t)i;
+                std::vector<u128> one = {0};
+                bw.out = &ex->plain_launches;
+                size_t first = ex->plain_launches.size();
+                bw.build_cluster(P, cl, one, 2, pi, &plain_slots);
+                // the root step writes into a per-term slot of a persistent buffer
+                int64_t rb = std::max<int64_t>(1, pe.n_live) * 8;
+                Ref root{R_CONST, ex->cbuf.reserve(rb)};
+                for (size_t li = first; li < ex->plain_launches.size(); ++li)
+                    if (ex->plain_launches[li].plain_root) {
+                        ex->plain_launches[li].c = root;
+                        ex->plain_launches[li].plain_root_stride = 8;
+                    }
+                pe.root32.push_back(root);
+                pe.root32_inst.push_back(pe.n_live);
+            } else {
+                bw.out = &ex->launches;
+                Ref r = bw.build_cluster(P, cl, keys, 0, pi, nullptr);
+                // roots stay live until finalize: copy out of the work arena
+                const int64_t rb = (int64_t)keys.size() * 8;
+                Ref keep{R_CONST, ex->cbuf.reserve(rb)};
+                // identity permutation of rank-0 instances = a copy
+                Launch cp = bw.make_perm(std::vector<int>(), std::vector<int>(), 0);
+                cp.a = r;
+                cp.c = keep;
+                cp.p.n_inst = (int64_t)keys.size();
+                cp.plan = pi;
+                ex->launches.push_back(cp);
+                bw.work.release(r.off, rb);
+                pe.root32.push_back(keep);
+                pe.root32_inst.push_back((int64_t)keys.size());
+            }
+        }
+        // FP64 pass for the all-dominant term
+        if (pe.zero_term >= 0 && ex->opts.fp64_level0) {
+            bw.out = &ex->launches;
+            for (int c = 0; c < ncl; ++c) {
+                std::vector<u128> one = {0};
+                Ref r = bw.build_cluster(P, P.clusters[c], one, 1, pi, nullptr);
+                Ref keep{R_CONST, ex->cbuf.reserve(16)};
+                Launch cp = bw.make_perm(std::vector<int>(), std::vector<int>(), 1);
+                cp.a = r;
+                cp.c = keep;
+                cp.p.n_inst = 1;
+                cp.plan = pi;
+                ex->launches.push_back(cp);
+                bw.work.release(r.off, 16);
+                pe.root64.push_back(keep);
+            }
+        }
+        if (plain) {
+            Launch sf;
+            sf.kind = L_SLOTFILL;
+            sf.plan = pi;
+            std::vector<int32_t> nidx;
+            std::vector<int64_t> dsts;
+            for (auto& s : plain_slots) {
+                nidx.push_back(s.first);
+                dsts.push_back(s.second);   // const offsets, resolved at bind
+            }
+            sf.sf.n = (int)plain_slots.size();
+            sf.sf.n_noise = P.n_noise;
+            sf.sf_noise = Ref{R_CONST, ex->cbuf.add(nidx.data(), (int64_t)nidx.size() * 4 + 4)};
+            sf.sf_dst = Ref{R_CONST, ex->cbuf.add(dsts.data(), (int64_t)dsts.size() * 8 + 8)};
+            std::vector<float> bank(P.n_noise * 4 * 8 + 8, 0.0f);
+            for (int s = 0; s < P.n_noise; ++s)
+                for (int ch = 0; ch < 4; ++ch)
+                    for (int e = 0; e < 4; ++e) {
+                        cd v = std::sqrt(2.0) * P.noise[s].K[ch][e];
+                        bank[(s * 4 + ch) * 8 + 2 * e] = (float)v.real();
+                        bank[(s * 4 + ch) * 8 + 2 * e + 1] = (float)v.imag();
+                    }
+            sf.sf_bank = Ref{R_CONST, ex->cbuf.add(bank.data(), (int64_t)bank.size() * 4)};
+            sf.sf_pattern = Ref{R_CONST, ex->cbuf.add(T.pat.data(), (int64_t)T.pat.size() + 1)};
+            ex->plain_launches.insert(ex->plain_launches.begin(), sf);
+            ex->plain_terms = pe.n_live;
+            // the per-term term index array: live terms
+        }
+        // finalize + level sums
+        std::vector<double> what(T.n);
+        for (int64_t t = 0; t < T.n; ++t) what[t] = std::ldexp(T.w[t], -P.n_noise);
+        pe.x_out = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, T.n) * 8)};
+        pe.amp_out = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, T.n) * 8)};
+        pe.sums = Ref{R_CONST, ex->cbuf.reserve((T.level + 1) * 16)};
+        Launch fl;
+        fl.kind = L_FINALIZE;
+        fl.plan = pi;
+        fl.f.n_terms = T.n;
+        fl.f.n_clusters = ncl;
+        fl.f.zero_term = pe.root64.empty() ? -1 : pe.zero_term;
+        fl.f.scalar_re = P.scalar.real();
+        fl.f.scalar_im = P.scalar.imag();
+        fl.live_index = Ref{R_CONST, ex->cbuf.add(live_index.data(), std::max<int64_t>(1, T.n) * 4)};
+        fl.root_idx = Ref{R_CONST, ex->cbuf.add(root_idx.data(), (int64_t)root_idx.size() * 4)};
+        fl.root_ptrs = Ref{R_CONST, ex->cbuf.reserve(std::max(1, ncl) * 8)};
+        fl.root64_ptrs = Ref{R_CONST, ex->cbuf.reserve(std::max(1, ncl) * 8)};
+        fl.w = Ref{R_CONST, ex->cbuf.add(what.data(), std::max<int64_t>(1, T.n) * 8)};
+        fl.x_out = pe.x_out;
+        fl.amp_out = pe.amp_out;
+        ex->tail.push_back(fl);
+        pe.level_start.assign(T.level + 2, T.n);
+        for (int u = T.level; u >= 0; --u) {
+            int64_t s = T.n;
+            for (int64_t t = 0; t < T.n; ++t)
+                if (T.lvl[t] == u) { s = t; break; }
+            pe.level_start[u] = s;
+        }
+        pe.level_start[T.level + 1] = T.n;
+        for (int u = T.level; u >= 0; --u)
+            if (pe.level_start[u] > pe.level_start[u + 1]) pe.level_start[u] = pe.level_start[u + 1];
+        Launch ls;
+        ls.kind = L_LEVELSUM;
+        ls.plan = pi;
+        ls.n_levels = T.level + 1;
+        ls.starts = Ref{R_CONST, ex->cbuf.add(pe.level_start.data(), (int64_t)pe.level_start.size() * 8)};
+        ls.x_out = pe.x_out;
+        ls.sums = pe.sums;
+        ex->tail.push_back(ls);
+        ex->plans.push_back(std::move(pe));
+    }
+    ex->const_bytes = round_up((int64_t)ex->cbuf.bytes.size(), 256);
+    ex->work_bytes = round_up(bw.work.peak, 256);
+}
+
+static void* resolve(tn_exec_s* ex, const Ref& r) {
+    return ex->base + (r.region == R_CONST ? 0 : ex->const_bytes) + r.off;
+}
+
+static void bind(tn_exec_s* ex) {
+    auto fix = [&](Launch& L) {
+        if (L.kind == L_GEMM) {
+            L.g.A = resolve(ex, L.a);
+            L.g.B = resolve(ex, L.b);
+            L.g.C = resolve(ex, L.c);
+            L.g.ia = L.g.ia_mode == 2 ? (const int32_t*)resolve(ex, L.ia) : nullptr;
+            L.g.ib = L.g.ib_mode == 2 ? (const int32_t*)resolve(ex, L.ib) : nullptr;
+        } else if (L.kind == L_PERM) {
+            L.p.src = resolve(ex, L.a);
+            L.p.dst = resolve(ex, L.c);
+            L.p.table = (const int32_t*)resolve(ex, L.table);
+        } else if (L.kind == L_SLOTFILL) {
+            L.sf.noise = (const int32_t*)resolve(ex, L.sf_noise);
+            L.sf.dst = (const int64_t*)resolve(ex, L.sf_dst);
+            L.sf.bank = (const float*)resolve(ex, L.sf_bank);
+            L.sf.pattern = (const int8_t*)resolve(ex, L.sf_pattern);
+        }
+    };
+    for (auto& L : ex->launches) fix(L);
+    for (auto& L : ex->plain_launches) fix(L);
+    // pointer tables written into the host staging copy before upload
+    for (auto& L : ex->plain_launches)
+        if (L.kind == L_SLOTFILL) {
+            int64_t* d = (int64_t*)(ex->cbuf.bytes.data() + L.sf_dst.off);
+            for (int i = 0; i < L.sf.n; ++i) d[i] = (int64_t)(ex->base + d[i]);
+        }
+    for (auto& L : ex->tail) {
+        const PlanExec& pe = ex->plans[L.plan];
+        if (L.kind == L_FINALIZE) {
+            int64_t* rp = (int64_t*)(ex->cbuf.bytes.data() + L.root_ptrs.off);
+            int64_t* rp64 = (int64_t*)(ex->cbuf.bytes.data() + L.root64_ptrs.off);
+            for (size_t c = 0; c < pe.root32.size(); ++c) rp[c] = (int64_t)resolve(ex, pe.root32[c]);
+            for (size_t c = 0; c < pe.root64.size(); ++c) rp64[c] = (int64_t)resolve(ex, pe.root64[c]);
+            L.f.live_index = (const int32_t*)resolve(ex, L.live_index);
+            L.f.root_idx = (const int32_t*)resolve(ex, L.root_idx);
+            L.f.root_ptrs = (const int64_t*)resolve(ex, L.root_ptrs);
+            L.f.root64_ptrs = (const int64_t*)resolve(ex, L.root64_ptrs);
+            L.f.w = (const double*)resolve(ex, L.w);
+            L.f.x_out = (double*)resolve(ex, L.x_out);
+            L.f.amp_out = (float*)resolve(ex, L.amp_out);
+        }
+    }
+}
+
+static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
+    if ((L.kind == L_GEMM && L.g.n_inst == 0) || (L.kind == L_PERM && L.p.n_inst == 0)) return;
+    switch (L.kind) {
+    case L_GEMM:
+        L.kclass = L.fp64 ? launch_gemm_c128(L.g, s) : launch_gemm_c64(L.g, s, L.tile_hint);
+        break;
+    case L_PERM:
+        if (L.fp64) launch_permute_c128(L.p, s);
+        else launch_permute_c64(L.p, s);
+        break;
+    case L_FINALIZE:
+        launch_finalize(L.f, s);
+        break;
+    case L_LEVELSUM:
+        launch_level_sum((const double*)resolve(ex, L.x_out), (const int64_t*)resolve(ex, L.starts),
+                         L.n_levels, (double*)resolve(ex, L.sums), s);
+        break;
+    case L_SLOTFILL:
+        launch_slot_fill(L.sf, s);
+        break;
+    }
+}
+
+static void run_body(tn_exec_s* ex, hipStream_t s) {
+    for (auto& L : ex->launches) enqueue(ex, L, s);
+    if (ex->opts.mode == TN_MODE_PLAIN) {
+        for (int64_t t = 0; t < ex->plain_terms; ++t) {
+            for (auto& L : ex->plain_launches) {
+                if (L.kind == L_SLOTFILL) {
+                    L.sf.term = ex->plans[L.plan].live_terms[t];
+                    enqueue(ex, L, s);
+                } else if (L.kind == L_GEMM && L.plain_root) {
+                    GemmArgs g = L.g;
+                    g.C = (char*)resolve(ex, L.c) + t * L.plain_root_stride;
+                    launch_gemm_c64(g, s, -1);
+                } else {
+                    enqueue(ex, L, s);
+                }
+            }
+        }
+    }
+    for (auto& L : ex->tail) enqueue(ex, L, s);
+    HIPCHK(hipGetLastError());
+}
+
+static std::string describe_exec(const tn_exec_s* ex) {
+    std::ostringstream os;
+    os.precision(10);
+    os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
+       << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms << ",\"launches\":[";
+    bool first = true;
+    auto emit = [&](const Launch& L, const char* phase) {
+        os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
+           << ",\"plan\":" << L.plan;
+        first = false;
+        if (L.kind == L_GEMM)
+            os << ",\"m_log\":" << L.g.m_log << ",\"n_log\":" << L.g.n_log << ",\"k_log\":" << L.g.k_log
+               << ",\"transA\":" << L.g.transA << ",\"transB\":" << L.g.transB << ",\"n_inst\":" << L.g.n_inst
+               << ",\"ia_mode\":" << L.g.ia_mode << ",\"ib_mode\":" << L.g.ib_mode
+               << ",\"strideA\":" << L.g.strideA << ",\"strideB\":" << L.g.strideB
+               << ",\"a\":[" << L.a.region << "," << L.a.off << "],\"b\":[" << L.b.region << "," << L.b.off
+               << "],\"c\":[" << L.c.region << "," << L.c.off << "],\"ia\":[" << L.ia.region << "," << L.ia.off
+               << "],\"ib\":[" << L.ib.region << "," << L.ib.off << "],\"kclass\":" << L.kclass;
+        if (L.kind == L_PERM)
+            os << ",\"r\":" << L.p.r << ",\"tb\":" << L.p.tb << ",\"n_inst\":" << L.p.n_inst << ",\"a\":["
+               << L.a.region << "," << L.a.off << "],\"c\":[" << L.c.region << "," << L.c.off << "],\"table\":["
+               << L.table.region << "," << L.table.off << "],\"high_out\":[";
+        if (L.kind == L_PERM) {
+            for (int i = 0; i < L.p.n_high; ++i) os << (i ? "," : "") << L.p.high_out[i];
+            os << "],\"high_in\":[";
+            for (int i = 0; i < L.p.n_high; ++i) os << (i ? "," : "") << L.p.high_in[i];
+            os << "]";
+        }
+        if (L.kind == L_FINALIZE)
+            os << ",\"n_terms\":" << L.f.n_terms << ",\"n_clusters\":" << L.f.n_clusters << ",\"zero_term\":"
+               << L.f.zero_term << ",\"scalar\":[" << L.f.scalar_re << "," << L.f.scalar_im
+               << "],\"live_index\":" << L.live_index.off << ",\"root_idx\":" << L.root_idx.off
+               << ",\"w\":" << L.w.off << ",\"x_out\":" << L.x_out.off << ",\"amp_out\":" << L.amp_out.off;
+        if (L.kind == L_LEVELSUM)
+            os << ",\"n_levels\":" << L.n_levels << ",\"starts\":" << L.starts.off << ",\"x_out\":"
+               << L.x_out.off << ",\"sums\":" << L.sums.off;
+        if (L.kind == L_SLOTFILL)
+            os << ",\"n\":" << L.sf.n << ",\"noise\":" << L.sf_noise.off << ",\"dst\":" << L.sf_dst.off
+               << ",\"bank\":" << L.sf_bank.off << ",\"pattern\":" << L.sf_pattern.off
+               << ",\"n_noise\":" << L.sf.n_noise;
+        if (L.kind == L_GEMM) os << ",\"plain_root\":" << L.plain_root;
+        os << ",\"flops\":" << L.flops << ",\"bytes\":" << L.bytes << "}";
+    };
+    for (auto& L : ex->launches) emit(L, "batch");
+    for (auto& L : ex->plain_launches) emit(L, "plain");
+    for (auto& L : ex->tail) emit(L, "tail");
+    os << "],\"plans\":[";
+    for (size_t i = 0; i < ex->plans.size(); ++i) {
+        const PlanExec& pe = ex->plans[i];
+        os << (i ? "," : "") << "{\"n_terms\":" << pe.n_terms << ",\"n_live\":" << pe.n_live
+           << ",\"zero_term\":" << pe.zero_term << ",\"x_out\":" << pe.x_out.off << ",\"amp_out\":"
+           << pe.amp_out.off << ",\"sums\":" << pe.sums.off << ",\"root32\":[";
+        for (size_t c = 0; c < pe.root32.size(); ++c)
+            os << (c ? "," : "") << "[" << pe.root32[c].region << "," << pe.root32[c].off << "]";
+        os << "],\"root64\":[";
+        for (size_t c = 0; c < pe.root64.size(); ++c)
+            os << (c ? "," : "") << "[" << pe.root64[c].region << "," << pe.root64[c].off << "]";
+        os << "]}";
+    }
+    os << "]}";
+    return os.str();
+}
+
+}  // namespace tn
+
+// ===========================================================================
+// extern "C" ABI
+// ===========================================================================
+using namespace tn;
+
+template <class F>
+static int guard(F&& f) {
+    try {
+        f();
+        set_last_error("");
+        return TN_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host out of memory");
+        return TN_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return TN_EINVAL;
+    }
+}
+
+extern "C" {
+
+const char* tn_last_error(void) { return last_error_cstr(); }
+
+int tn_plan_build(const tn_circuit* circ, const tn_state* psi, const tn_state* v, int32_t level,
+                  const tn_plan_opts* opts, tn_plan* out) {
+    return guard([&] {
+        if (!out) fail(TN_EINVAL, "null output handle");
+        *out = reinterpret_cast<tn_plan>(build_plan(circ, psi, v, level, opts));
+    });
+}
+
+int tn_terms_enumerate(tn_plan plan, int32_t level, const tn_prune_opts* prune, tn_terms* out,
+                       int64_t* n_terms) {
+    return guard([&] {
+        if (!plan || !out) fail(TN_EINVAL, "null handle");
+        Terms* t = enumerate_terms(reinterpret_cast<Plan*>(plan), level, prune);
+        *out = reinterpret_cast<tn_terms>(t);
+        if (n_terms) *n_terms = t->n;
+    });
+}
+
+int tn_terms_get(tn_terms terms, int8_t* patterns, double* weights) {
+    return guard([&] {
+        if (!terms) fail(TN_EINVAL, "null handle");
+        Terms* t = reinterpret_cast<Terms*>(terms);
+        if (patterns) std::memcpy(patterns, t->pat.data(), t->pat.size());
+        if (weights) std::memcpy(weights, t->w.data(), t->w.size() * 8);
+    });
+}
+
+int tn_plan_get_info(tn_plan plan, tn_plan_info* info) {
+    return guard([&] {
+        if (!plan || !info) fail(TN_EINVAL, "null handle");
+        Plan* p = reinterpret_cast<Plan*>(plan);
+        info->n_qubits = p->n_qubits;
+        info->n_noise = p->n_noise;
+        info->level = p->level;
+        info->clamped = p->clamped;
+        info->n_clusters = (int32_t)p->clusters.size();
+        info->n_leaves = (int32_t)p->leaves.size();
+        info->max_log_size = p->max_log;
+        info->flops_per_term = 8.0 * p->cmacs_per_term;
+    });
+}
+
+int tn_plan_noise(tn_plan plan, int32_t s, double* d, tn_c128* k, double* rate) {
+    return guard([&] {
+        if (!plan) fail(TN_EINVAL, "null handle");
+        Plan* p = reinterpret_cast<Plan*>(plan);
+        if (s < 0 || s >= p->n_noise) fail(TN_EINVAL, "noise index out of range");
+        const NoiseSplit& ns = p->noise[s];
+        for (int i = 0; i < 4; ++i) {
+            if (d) d[i] = ns.d[i];
+            if (k)
+                for (int e = 0; e < 4; ++e) k[4 * i + e] = tn_c128{ns.K[i][e].real(), ns.K[i][e].imag()};
+        }
+        if (rate) *rate = ns.rate;
+    });
+}
+
+int tn_plan_describe(tn_plan plan, char* buf, size_t* len) {
+    return guard([&] {
+        if (!plan || !len) fail(TN_EINVAL, "null handle");
+        std::string s = describe_plan(reinterpret_cast<Plan*>(plan));
+        if (buf && *len >= s.size() + 1) std::memcpy(buf, s.c_str(), s.size() + 1);
+        *len = s.size() + 1;
+    });
+}
+
+void tn_plan_destroy(tn_plan plan) { delete reinterpret_cast<Plan*>(plan); }
+void tn_terms_destroy(tn_terms terms) { delete reinterpret_cast<Terms*>(terms); }
+
+int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, const tn_exec_opts* opts,
+                    void* d_ws, size_t ws_bytes, void* stream, size_t* need_bytes, tn_exec* out) {
+    return guard([&] {
+        if (n < 1 || !plans || !terms) fail(TN_EINVAL, "need at least one plan with its terms");
+        auto ex = std::make_unique<tn_exec_s>();
+        if (opts) ex->opts = *opts;
+        else {
+            ex->opts.mode = TN_MODE_BATCHED;
+            ex->opts.use_graph = 1;
+            ex->opts.fp64_level0 = 1;
+        }
+        if (ex->opts.mode == TN_MODE_PLAIN) {
+            ex->opts.use_graph = 0;
+            if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
+        }
+        build_schedule(ex.get(), n, plans, terms);
+        const size_t need = (size_t)(ex->const_bytes + ex->work_bytes);
+        if (need_bytes) *need_bytes = need;
+        if (ws_bytes == 0) {
+            // size query; with `out` the caller gets an unbound handle that can
+            // only be described (no device memory, no HIP call)
+            if (out) *out = reinterpret_cast<tn_exec>(ex.release());
+            return;
+        }
+        if (!d_ws) fail(TN_EINVAL, "null workspace");
+        if (ws_bytes < need) {
+            std::ostringstream os;
+            os << "workspace too small: " << ws_bytes << " < " << need << " bytes";
+            fail(TN_ENOMEM, os.str());
+        }
+        if (!out) fail(TN_EINVAL, "null output handle");
+        ex->base = (char*)d_ws;
+        ex->stream = (hipStream_t)stream;
+        bind(ex.get());
+        HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
+                              ex->stream));
+        HIPCHK(hipEventCreate(&ex->ev0));
+        HIPCHK(hipEventCreate(&ex->ev1));
+        HIPCHK(hipStreamSynchronize(ex->stream));
+        ex->bound = true;
+        *out = reinterpret_cast<tn_exec>(ex.release());
+    });
+}
+
+int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
+        HIPCHK(hipEventRecord(ex->ev0, s));
+        if (ex->opts.use_graph) {
+            if (!ex->gexec) {
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                run_body(ex, s);
+                HIPCHK(hipStreamEndCapture(s, &ex->graph));
+                HIPCHK(hipGraphInstantiate(&ex->gexec, ex->graph, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(ex->gexec, s));
+        } else {
+            run_body(ex, s);
+        }
+        HIPCHK(hipEventRecord(ex->ev1, s));
+        HIPCHK(hipEventSynchronize(ex->ev1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ex->ev0, ex->ev1));
+        ex->last_ms = ms;
+        if (!results) return;
+        for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
+            const PlanExec& pe = ex->plans[pi];
+            const Plan& P = *pe.plan;
+            const Terms& T = *pe.terms;
+            tn_result& r = results[pi];
+            std::memset(&r, 0, sizeof(r));
+            r.level = T.level;
+            r.clamped = P.clamped ? 1 : 0;
+            r.n_terms = T.n;
+            r.n_contracted = pe.n_live;
+            r.n_zero_weight = pe.n_zero;
+            std::vector<double> sums(2 * (T.level + 1));
+            HIPCHK(hipMemcpy(sums.data(), resolve(ex, pe.sums), sums.size() * 8, hipMemcpyDeviceToHost));
+            double s = 0, c = 0;
+            for (int u = 0; u <= T.level; ++u) {
+                r.level_sum[u] = sums[2 * u];
+                r.level_comp[u] = sums[2 * u + 1];
+                double x = sums[2 * u];
+                double t = s + x;
+                if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+                else c += (x - t) + s;
+                s = t;
+                r.A[u] = s + c;
+            }
+            // remainder bound: sum over |S| > level of prod ||Mbar|| prod ||M'||
+            std::vector<double> poly(1, 1.0);
+            for (const NoiseSplit& ns : P.noise) {
+                std::vector<double> np(poly.size() + 1, 0.0);
+                for (size_t i = 0; i < poly.size(); ++i) {
+                    np[i] += poly[i] * ns.norm_main;
+                    np[i + 1] += poly[i] * ns.norm_bar;
+                }
+                poly.swap(np);
+            }
+            double b = 0;
+            for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
+            r.bound = b;
+            // FP32 value of the all-dominant term (diagnostic)
+            r.x0_fp32 = -1;
+            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED) {
+                double ar = P.scalar.real(), ai = P.scalar.imag();
+                for (size_t c2 = 0; c2 < pe.root32.size(); ++c2) {
+                    float v[2];
+                    HIPCHK(hipMemcpy(v, resolve(ex, pe.root32[c2]), 8, hipMemcpyDeviceToHost));
+                    double nr = ar * v[0] - ai * v[1], ni = ar * v[1] + ai * v[0];
+                    ar = nr;
+                    ai = ni;
+                }
+                r.x0_fp32 = std::ldexp(T.w[0], -P.n_noise) * (ar * ar + ai * ai);
+            }
+        }
+    });
+}
+
+int tn_exec_outputs(tn_exec exh, const double** d_x, const float** d_amp, int64_t* n_total) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        if (ex->plans.size() != 1) {
+            // outputs of packed plans are separate arrays; report the first
+        }
+        if (d_x) *d_x = (const double*)resolve(ex, ex->plans[0].x_out);
+        if (d_amp) *d_amp = (const float*)resolve(ex, ex->plans[0].amp_out);
+        if (n_total) *n_total = ex->plans[0].n_terms;
+    });
+}
+
+int tn_exec_copy_outputs(tn_exec exh, int32_t plan, double* h_x, float* h_amp) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        if (plan < 0 || plan >= (int32_t)ex->plans.size()) fail(TN_EINVAL, "plan index out of range");
+        const PlanExec& pe = ex->plans[plan];
+        HIPCHK(hipStreamSynchronize(ex->stream));
+        if (h_x && pe.n_terms)
+            HIPCHK(hipMemcpy(h_x, resolve(ex, pe.x_out), pe.n_terms * 8, hipMemcpyDeviceToHost));
+        if (h_amp && pe.n_terms)
+            HIPCHK(hipMemcpy(h_amp, resolve(ex, pe.amp_out), pe.n_terms * 8, hipMemcpyDeviceToHost));
+    });
+}
+
+int tn_exec_timing(tn_exec exh, double* total_ms, double* gemm_ms, double* permute_ms, double* other_ms) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex) fail(TN_EINVAL, "null handle");
+        if (total_ms) *total_ms = ex->last_ms;
+        if (gemm_ms) *gemm_ms = ex->gemm_ms;
+        if (permute_ms) *permute_ms = ex->perm_ms;
+        if (other_ms) *other_ms = ex->other_ms;
+    });
+}
+
+int tn_exec_describe(tn_exec exh, char* buf, size_t* len) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !len) fail(TN_EINVAL, "null handle");
+        std::string s = describe_exec(ex);
+        if (buf && *len >= s.size() + 1) std::memcpy(buf, s.c_str(), s.size() + 1);
+        *len = s.size() + 1;
+    });
+}
+
+int tn_exec_const_bytes(tn_exec exh, void* buf, size_t* len) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !len) fail(TN_EINVAL, "null handle");
+        if (buf && *len >= ex->cbuf.bytes.size()) std::memcpy(buf, ex->cbuf.bytes.data(), ex->cbuf.bytes.size());
+        *len = ex->cbuf.bytes.size();
+    });
+}
+
+void tn_exec_destroy(tn_exec exh) {
+    tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+    if (!ex) return;
+    if (ex->gexec) (void)hipGraphExecDestroy(ex->gexec);
+    if (ex->graph) (void)hipGraphDestroy(ex->graph);
+    if (ex->ev0) (void)hipEventDestroy(ex->ev0);
+    if (ex->ev1) (void)hipEventDestroy(ex->ev1);
+    delete ex;
+}
+
+int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms, size_t* need_bytes) {
+    return tn_exec_prepare(n, plans, terms, nullptr, nullptr, 0, nullptr, need_bytes, nullptr);
+}
+
+int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_ws, size_t ws_bytes,
+                void* stream, tn_result* results) {
+    tn_exec ex = nullptr;
+    size_t need = 0;
+    tn_exec_opts o{};
+    o.mode = TN_MODE_BATCHED;
+    o.use_graph = 0;
+    o.fp64_level0 = 1;
+    int rc = tn_exec_prepare(n, plans, terms, &o, d_ws, ws_bytes, stream, &need, &ex);
+    if (rc != TN_OK) return rc;
+    rc = tn_exec_run(ex, stream, results);
+    tn_exec_destroy(ex);
+    return rc;
+}
+
+int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, int64_t first, int64_t count,
+                      void* d_amp, void* d_ws, size_t ws_bytes, void* stream) {
+    return guard([&] {
+        if (first < 0 || count < 0) fail(TN_EINVAL, "bad term range");
+        // restrict each term set to the range by pruning everything outside it
+        std::vector<std::unique_ptr<Terms>> sub;
+        std::vector<tn_terms> th;
+        for (int i = 0; i < n; ++i) {
+            const Terms* t = reinterpret_cast<const Terms*>(terms[i]);
+            if (first + count > t->n) fail(TN_EINVAL, "term range beyond the term set");
+            auto c = std::make_unique<Terms>(*t);
+            for (int64_t k = 0; k < c->n; ++k)
+                if (k < first || k >= first + count) c->pruned[k] = 1;
+            th.push_back(reinterpret_cast<tn_terms>(c.get()));
+            sub.push_back(std::move(c));
+        }
+        tn_exec_opts o{};
+        o.mode = TN_MODE_BATCHED;
+        o.use_graph = 0;
+        o.fp64_level0 = 0;
+        tn_exec ex = nullptr;
+        size_t need = 0;
+        int rc = tn_exec_prepare(n, plans, th.data(), &o, d_ws, ws_bytes, stream, &need, &ex);
+        if (rc != TN_OK) throw Error{rc, tn_last_error()};
+        tn_exec_s* e = reinterpret_cast<tn_exec_s*>(ex);
+        hipStream_t s = (hipStream_t)stream;
+        run_body(e, s);
+        for (int i = 0; i < n; ++i) {
+            const PlanExec& pe = e->plans[i];
+            HIPCHK(hipMemcpyAsync((char*)d_amp + (size_t)i * count * 8, (char*)resolve(e, pe.amp_out) + first * 8,
+                                  (size_t)count * 8, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        tn_exec_destroy(ex);
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// kernel-level entry points (include/tn_kernels.h)
+// ===========================================================================
+#include "tn_kernels.h"
+
+extern "C" int tn_kernel_gemm(int32_t fp64, const void* A, const void* B, void* C, const int32_t* ia,
+                              const int32_t* ib, int64_t strideA, int64_t strideB, int32_t m_log,
+                              int32_t n_log, int32_t k_log, int32_t transA, int32_t transB, int64_t n_inst,
+                              int32_t tile_hint, void* stream) {
+    int kc = -1;
+    int rc = guard([&] {
+        if (m_log < 0 || n_log < 0 || k_log < 0 || m_log + n_log + k_log > 40 || n_inst < 1)
+            fail(TN_EINVAL, "bad gemm shape");
+        if (!A || !B || !C) fail(TN_EINVAL, "null operand");
+        GemmArgs g{};
+        g.A = A;
+        g.B = B;
+        g.C = C;
+        g.ia = ia;
+        g.ib = ib;
+        g.ia_mode = ia ? 2 : 0;
+        g.ib_mode = ib ? 2 : 0;
+        g.strideA = strideA;
+        g.strideB = strideB;
+        g.m_log = m_log;
+        g.n_log = n_log;
+        g.k_log = k_log;
+        g.transA = transA;
+        g.transB = transB;
+        g.n_inst = n_inst;
+        hipStream_t s = (hipStream_t)stream;
+        kc = fp64 ? launch_gemm_c128(g, s) : launch_gemm_c64(g, s, tile_hint);
+        HIPCHK(hipGetLastError());
+    });
+    return rc == TN_OK ? kc : rc;
+}
+
+extern "C" int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64_t n_inst, int32_t r,
+                                 const int32_t* perm, void* stream) {
+    return guard([&] {
+        if (r < 0 || r > 32 || n_inst < 1 || !src || !dst || (r > 0 && !perm))
+            fail(TN_EINVAL, "bad permute arguments");
+        // express the permutation as source/destination leg orders
+        std::vector<int> src_legs(r), dst_legs(r);
+        std::vector<char> seen(r, 0);
+        for (int j = 0; j < r; ++j) {
+            if (perm[j] < 0 || perm[j] >= r || seen[perm[j]]) fail(TN_EINVAL, "perm is not a permutation");
+            seen[perm[j]] = 1;
+        }
+        for (int i = 0; i < r; ++i) src_legs[r - 1 - i] = i;          // leg id = input bit
+        for (int j = 0; j < r; ++j) dst_legs[r - 1 - j] = perm[j];    // output bit j holds input bit perm[j]
+        tn_exec_s tmp;
+        Builder bw;
+        bw.ex = &tmp;
+        Launch L = bw.make_perm(src_legs, dst_legs, fp64);
+        hipStream_t s = (hipStream_t)stream;
+        void* dtab = nullptr;
+        const size_t tb = tmp.cbuf.bytes.size();
+        HIPCHK(hipMalloc(&dtab, tb));
+        HIPCHK(hipMemcpy(dtab, tmp.cbuf.bytes.data(), tb, hipMemcpyHostToDevice));
+        L.p.src = src;
+        L.p.dst = dst;
+        L.p.n_inst = n_inst;
+        L.p.table = (const int32_t*)((char*)dtab + L.table.off);
+        if (fp64) launch_permute_c128(L.p, s);
+        else launch_permute_c64(L.p, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipFree(dtab));
+    });
+}

@@ -1,0 +1,85 @@
+// Launch wrappers of the HIP kernels (gfx950).  All sizes are powers of two;
+// complex values are interleaved (re, im) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tn {
+
+// Operand selection for a gathered batch: instance i of the output reads
+// operand instance (mode 0: i, mode 1: 0, mode 2: map[i]).
+struct GemmArgs {
+    const void* A;
+    const void* B;
+    void* C;
+    const int32_t* ia;
+    const int32_t* ib;
+    int ia_mode, ib_mode;
+    int64_t strideA, strideB;     // elements between operand instances
+    int m_log, n_log, k_log;
+    int transA, transB;           // A stored k x m / B stored n x k
+    int64_t n_inst;
+};
+
+// Bit permutation of each instance of a 2^r tensor: out bit j <- in bit p[j].
+struct PermArgs {
+    const void* src;
+    void* dst;
+    int64_t n_inst;
+    int r;                         // rank
+    int tb;                        // tile bits
+    const int32_t* table;          // 3 * 2^tb: load in-offset, load lds pos, store out-offset
+    int n_high;                    // r - tb
+    int high_out[32];              // out bit positions of the high (block) bits
+    int high_in[32];               // matching in bit positions
+};
+
+enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3 };
+
+// FP32 complex GEMM dispatch; returns the kernel class used.  tile_hint < 0
+// picks by shape; otherwise a tile index from the autotuner.
+int launch_gemm_c64(const GemmArgs& g, hipStream_t s, int tile_hint);
+int launch_gemm_c128(const GemmArgs& g, hipStream_t s);
+int gemm_c64_num_tiles(const GemmArgs& g);
+
+void launch_permute_c64(const PermArgs& p, hipStream_t s);
+void launch_permute_c128(const PermArgs& p, hipStream_t s);
+
+// per-term finalize: amp_t = scalar * prod_c root_c[idx[t][c]] (FP64),
+// X_t = w_t |amp_t|^2; the term `zero_term` (if >= 0) takes its cluster
+// values from the FP64 roots instead.
+struct FinalizeArgs {
+    int64_t n_terms;               // all terms of the plan (enumeration order)
+    const int32_t* live_index;     // n_terms: live index or -1 (zero weight / pruned)
+    const int32_t* root_idx;       // n_live * n_clusters
+    int n_clusters;
+    const int64_t* root_ptrs;      // n_clusters device addresses of complex64 roots
+    const int64_t* root64_ptrs;    // n_clusters device addresses of complex128 roots (or 0)
+    int64_t zero_term;             // term index using root64 (-1 = none)
+    double scalar_re, scalar_im;
+    const double* w;               // n_terms scaled weights
+    double* x_out;                 // n_terms
+    float* amp_out;                // 2 * n_terms
+};
+void launch_finalize(const FinalizeArgs& f, hipStream_t s);
+
+// Neumaier level sums over contiguous ranges [start[u], start[u+1]).
+void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,
+                      hipStream_t s);
+
+// PLAIN mode: fill the single-instance slot buffers of term t.
+struct SlotFillArgs {
+    int n;                         // number of slot leaves
+    const int32_t* noise;          // noise index per slot leaf
+    const int64_t* dst;            // device address of the 4-element buffer
+    const float* bank;             // N * 4 * 8 floats: K_hat_i, complex64
+    const int8_t* pattern;         // device patterns, n_terms * N
+    int n_noise;
+    int64_t term;
+};
+void launch_slot_fill(const SlotFillArgs& a, hipStream_t s);
+
+void launch_copy_c64(const void* src, void* dst, int64_t n, hipStream_t s);
+
+}  // namespace tn

@@ -1,0 +1,505 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// The contraction of one term network is a fixed sequence of pairwise
+// contractions; each step here is a bit permutation of the operand legs
+// (TTGT transpose) followed by a complex GEMM batched over the term
+// instances that step serves.  Complex values are interleaved (re, im).
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace tn {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int64_t pick(int mode, const int32_t* map, int64_t i) {
+    return mode == 0 ? i : (mode == 1 ? 0 : (int64_t)map[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K1: FP32 complex GEMM on MFMA.
+//
+// The complex product C = A B (m x k times k x n) is the real product
+// C_r = A_r B_e of the interleaved real view A_r (m x 2k) with the embedding
+// B_e (2k x 2n), B_e[2p+s][2j+t] = [[Re, Im], [-Im, Re]][s][t] of B[p][j]; the
+// output comes out interleaved.  Each v_mfma_f32_32x32x2f32 covers one complex
+// k index, 32 rows and 16 complex columns: 8 m n k real flops per complex MAC,
+// as in the four-real-product form.  Block tile BM x BNC complex, k staged
+// through LDS in chunks of 8 (planar re/im for A so that a half-wave reads
+// consecutive words).
+// ---------------------------------------------------------------------------
+template <int BM, int BNC>
+__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1))
+void k_gemm_mfma(GemmArgs g) {
+    constexpr int WM = BM >= 64 ? BM / 64 : 1;
+    constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TM = BM / WM / 32;
+    constexpr int TN = BNC / WN / 16;
+    constexpr int BKC = 8;
+    __shared__ float As_re[BKC][BM];
+    __shared__ float As_im[BKC][BM];
+    __shared__ float2 Bs[BKC][BNC];
+
+    const int m_log = g.m_log, n_log = g.n_log, k_log = g.k_log;
+    const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
+    const int tn_log = n_log - __builtin_ctz(BNC);
+    const int64_t tiles = (m / BM) << tn_log;
+    const int64_t blk = blockIdx.x;
+    const int64_t inst = blk / tiles;
+    const int64_t tile = blk - inst * tiles;
+    const int64_t tm0 = (tile >> tn_log) * BM;
+    const int64_t tn0 = (tile & ((int64_t(1) << tn_log) - 1)) * BNC;
+    const float2* __restrict__ A = (const float2*)g.A + pick(g.ia_mode, g.ia, inst) * g.strideA;
+    const float2* __restrict__ B = (const float2*)g.B + pick(g.ib_mode, g.ib, inst) * g.strideB;
+    float* __restrict__ C = (float*)g.C + inst * (2 * m * n);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    v16f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int kc = k < BKC ? (int)k : BKC;
+    const int kc_log = k_log < 3 ? k_log : 3;
+    const int half = lane >> 5;             // 0: real slice, 1: imaginary slice
+    const int sub = lane & 31;
+    for (int64_t k0 = 0; k0 < k; k0 += kc) {
+        for (int e = threadIdx.x; e < BM * kc; e += NT) {
+            int r, p;
+            float2 v;
+            if (!g.transA) {
+                r = e >> kc_log;
+                p = e & (kc - 1);
+                v = A[(tm0 + r) * k + k0 + p];
+            } else {
+                p = e / BM;
+                r = e % BM;
+                v = A[(k0 + p) * m + tm0 + r];
+            }
+            As_re[p][r] = v.x;
+            As_im[p][r] = v.y;
+        }
+        for (int e = threadIdx.x; e < kc * BNC; e += NT) {
+            int p, c;
+            float2 v;
+            if (!g.transB) {
+                p = e / BNC;
+                c = e % BNC;
+                v = B[(k0 + p) * n + tn0 + c];
+            } else {
+                c = e >> kc_log;
+                p = e & (kc - 1);
+                v = B[(tn0 + c) * k + k0 + p];
+            }
+            Bs[p][c] = v;
+        }
+        __syncthreads();
+        for (int p = 0; p < kc; ++p) {
+            float a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int row = wm * (TM * 32) + i * 32 + sub;
+                a[i] = half ? As_im[p][row] : As_re[p][row];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
+                const float2 bv = Bs[p][col];
+                const int t = sub & 1;
+                b[j] = half == 0 ? (t == 0 ? bv.x : bv.y) : (t == 0 ? -bv.y : bv.x);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t colf = 2 * (tn0 + wn * (TN * 16) + j * 16) + sub;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = tm0 + wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                C[row * (2 * n) + colf] = acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Small shapes: one thread per output element, k loop in registers.
+// ---------------------------------------------------------------------------
+template <typename R, typename C2>
+__global__ __launch_bounds__(256) void k_gemm_small(GemmArgs g) {
+    const int64_t total = g.n_inst << (g.m_log + g.n_log);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t n = int64_t(1) << g.n_log, m = int64_t(1) << g.m_log, k = int64_t(1) << g.k_log;
+    const int64_t inst = idx >> (g.m_log + g.n_log);
+    const int64_t rc = idx & ((int64_t(1) << (g.m_log + g.n_log)) - 1);
+    const int64_t r = rc >> g.n_log, c = rc & (n - 1);
+    const C2* A = (const C2*)g.A + pick(g.ia_mode, g.ia, inst) * g.strideA;
+    const C2* B = (const C2*)g.B + pick(g.ib_mode, g.ib, inst) * g.strideB;
+    R sr = 0, si = 0;
+    for (int64_t p = 0; p < k; ++p) {
+        const C2 a = g.transA ? A[p * m + r] : A[r * k + p];
+        const C2 b = g.transB ? B[c * k + p] : B[p * n + c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+    }
+    C2 o;
+    o.x = sr;
+    o.y = si;
+    ((C2*)g.C)[idx] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Tiny outputs with long k (inner products): one block per output element,
+// strided partial sums, FP64 tree reduction in LDS.
+// ---------------------------------------------------------------------------
+template <typename R, typename C2>
+__global__ __launch_bounds__(256) void k_gemm_splitk(GemmArgs g) {
+    __shared__ double red_r[256];
+    __shared__ double red_i[256];
+    const int64_t n = int64_t(1) << g.n_log, m = int64_t(1) << g.m_log, k = int64_t(1) << g.k_log;
+    const int64_t out = blockIdx.x;
+    const int64_t inst = out >> (g.m_log + g.n_log);
+    const int64_t rc = out & ((int64_t(1) << (g.m_log + g.n_log)) - 1);
+    const int64_t r = rc >> g.n_log, c = rc & (n - 1);
+    const C2* A = (const C2*)g.A + pick(g.ia_mode, g.ia, inst) * g.strideA;
+    const C2* B = (const C2*)g.B + pick(g.ib_mode, g.ib, inst) * g.strideB;
+    R sr = 0, si = 0;
+    for (int64_t p = threadIdx.x; p < k; p += blockDim.x) {
+        const C2 a = g.transA ? A[p * m + r] : A[r * k + p];
+        const C2 b = g.transB ? B[c * k + p] : B[p * n + c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+    }
+    red_r[threadIdx.x] = (double)sr;
+    red_i[threadIdx.x] = (double)si;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red_r[threadIdx.x] += red_r[threadIdx.x + s];
+            red_i[threadIdx.x] += red_i[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        C2 o;
+        o.x = (R)red_r[0];
+        o.y = (R)red_i[0];
+        ((C2*)g.C)[out] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 tiled GEMM (complex128) for the dominant-term pass: 64x64 output tile,
+// 256 threads each holding a 4x4 block, k staged through LDS in chunks of 8.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
+    constexpr int BM = 64, BN = 64, BK = 8;
+    __shared__ double2 As[BK][BM];
+    __shared__ double2 Bs[BK][BN];
+    const int64_t m = int64_t(1) << g.m_log, n = int64_t(1) << g.n_log, k = int64_t(1) << g.k_log;
+    const int tn_log = g.n_log - 6;
+    const int64_t tiles = (m / BM) << tn_log;
+    const int64_t inst = blockIdx.x / tiles;
+    const int64_t tile = blockIdx.x - inst * tiles;
+    const int64_t tm0 = (tile >> tn_log) * BM, tn0 = (tile & ((int64_t(1) << tn_log) - 1)) * BN;
+    const double2* A = (const double2*)g.A + pick(g.ia_mode, g.ia, inst) * g.strideA;
+    const double2* B = (const double2*)g.B + pick(g.ib_mode, g.ib, inst) * g.strideB;
+    double2* C = (double2*)g.C + inst * m * n;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double accr[4][4], acci[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
+    const int kc = k < BK ? (int)k : BK;
+    for (int64_t k0 = 0; k0 < k; k0 += kc) {
+        for (int e = threadIdx.x; e < BM * kc; e += 256) {
+            int r, p;
+            if (!g.transA) { r = e / kc; p = e % kc; As[p][r] = A[(tm0 + r) * k + k0 + p]; }
+            else { p = e / BM; r = e % BM; As[p][r] = A[(k0 + p) * m + tm0 + r]; }
+        }
+        for (int e = threadIdx.x; e < kc * BN; e += 256) {
+            int p, c;
+            if (!g.transB) { p = e / BN; c = e % BN; Bs[p][c] = B[(k0 + p) * n + tn0 + c]; }
+            else { c = e / kc; p = e % kc; Bs[p][c] = B[(tn0 + c) * k + k0 + p]; }
+        }
+        __syncthreads();
+        for (int p = 0; p < kc; ++p) {
+            double2 a[4], b[4];
+            for (int i = 0; i < 4; ++i) a[i] = As[p][ty + 16 * i];
+            for (int j = 0; j < 4; ++j) b[j] = Bs[p][tx + 16 * j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    accr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
+                    acci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
+                }
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double2 o;
+            o.x = accr[i][j];
+            o.y = acci[i][j];
+            C[(tm0 + ty + 16 * i) * n + tn0 + tx + 16 * j] = o;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// K2: batched bit permutation, staged through LDS.  A tile covers the lowest
+// `tb` bits of both the input and the output index (up to 2 tb bits), so the
+// loads run along the input's fastest legs and the stores along the output's.
+// The per-element offsets inside a tile come from a precomputed table; the
+// remaining (high) bits select the tile.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute(PermArgs p) {
+    extern __shared__ unsigned char smem_raw[];
+    T* tile = (T*)smem_raw;
+    const int tsize = 1 << p.tb;
+    const int upb = tsize >= 256 ? 1 : 256 / tsize;      // units (tiles) per block
+    const int stride = tsize >= 256 ? 256 : tsize;       // threads per unit
+    const int u = threadIdx.x / stride;
+    const int e0 = threadIdx.x - u * stride;
+    const int64_t highs = int64_t(1) << p.n_high;
+    const int64_t unit = (int64_t)blockIdx.x * upb + u;
+    const bool active = unit < p.n_inst * highs;
+    const int32_t* ld_in = p.table;
+    const int32_t* ld_pos = p.table + tsize;
+    const int32_t* st_out = p.table + 2 * tsize;
+    const int64_t size = int64_t(1) << p.r;
+    T* t = tile + (int64_t)u * tsize;
+    int64_t in_base = 0, out_base = 0, inst = 0;
+    if (active) {
+        inst = unit >> p.n_high;
+        const int64_t h = unit & (highs - 1);
+        for (int i = 0; i < p.n_high; ++i)
+            if ((h >> i) & 1) {
+                in_base |= int64_t(1) << p.high_in[i];
+                out_base |= int64_t(1) << p.high_out[i];
+            }
+        const T* src = (const T*)p.src + inst * size + in_base;
+        for (int e = e0; e < tsize; e += stride) t[ld_pos[e]] = src[ld_in[e]];
+    }
+    __syncthreads();
+    if (active) {
+        T* dst = (T*)p.dst + inst * size + out_base;
+        for (int e = e0; e < tsize; e += stride) dst[st_out[e]] = t[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: per-term finalize (FP64): amplitude = scalar * prod of cluster values,
+// X = w |amplitude|^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= f.n_terms) return;
+    const int32_t li = f.live_index[t];
+    if (li < 0) {
+        f.x_out[t] = 0.0;
+        f.amp_out[2 * t] = 0.0f;
+        f.amp_out[2 * t + 1] = 0.0f;
+        return;
+    }
+    double ar = f.scalar_re, ai = f.scalar_im;
+    const bool hi = (t == f.zero_term);
+    for (int c = 0; c < f.n_clusters; ++c) {
+        const int64_t j = f.root_idx[(int64_t)li * f.n_clusters + c];
+        double vr, vi;
+        if (hi) {
+            const double2* r64 = (const double2*)f.root64_ptrs[c];
+            vr = r64[j].x;
+            vi = r64[j].y;
+        } else {
+            const float2* r32 = (const float2*)f.root_ptrs[c];
+            vr = (double)r32[j].x;
+            vi = (double)r32[j].y;
+        }
+        const double nr = ar * vr - ai * vi;
+        const double ni = ar * vi + ai * vr;
+        ar = nr;
+        ai = ni;
+    }
+    f.x_out[t] = f.w[t] * (ar * ar + ai * ai);
+    f.amp_out[2 * t] = (float)ar;
+    f.amp_out[2 * t + 1] = (float)ai;
+}
+
+// ---------------------------------------------------------------------------
+// K4: Neumaier-compensated level sums in a fixed order (deterministic): each
+// thread sums a fixed strided subset, then pairs (sum, comp) are combined in a
+// fixed tree.  One block per level.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+__global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_t* starts,
+                                                   double* out) {
+    __shared__ double ss[256];
+    __shared__ double cc[256];
+    const int u = blockIdx.x;
+    const int64_t b = starts[u], e = starts[u + 1];
+    double s = 0.0, c = 0.0;
+    for (int64_t i = b + threadIdx.x; i < e; i += 256) neumaier_add(s, c, x[i]);
+    ss[threadIdx.x] = s;
+    cc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double s1 = ss[threadIdx.x], c1 = cc[threadIdx.x] + cc[threadIdx.x + w];
+            neumaier_add(s1, c1, ss[threadIdx.x + w]);
+            ss[threadIdx.x] = s1;
+            cc[threadIdx.x] = c1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * u] = ss[0] + cc[0];
+        out[2 * u + 1] = cc[0];
+    }
+}
+
+__global__ void k_slot_fill(SlotFillArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n * 8) return;
+    const int leaf = i >> 3, w = i & 7;
+    const int s = a.noise[leaf];
+    const int choice = a.pattern[a.term * a.n_noise + s];
+    ((float*)a.dst[leaf])[w] = a.bank[(s * 4 + choice) * 8 + w];
+}
+
+__global__ void k_copy_c64(const float2* src, float2* dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct TileCfg {
+    int bm, bnc;
+};
+static const TileCfg kTiles[] = {{128, 64}, {64, 64}, {128, 32}, {64, 32}, {32, 32}, {32, 16}};
+static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int gemm_c64_num_tiles(const GemmArgs&) { return kNumTiles; }
+
+static bool tile_fits(const TileCfg& t, const GemmArgs& g) {
+    return (int64_t(1) << g.m_log) >= t.bm && (int64_t(1) << g.n_log) >= t.bnc;
+}
+
+static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s) {
+    const int64_t tiles = ((int64_t(1) << g.m_log) / t.bm) * ((int64_t(1) << g.n_log) / t.bnc);
+    const unsigned blocks = (unsigned)(tiles * g.n_inst);
+#define TN_LAUNCH(BM_, BN_)                                                                   \
+    if (t.bm == BM_ && t.bnc == BN_) {                                                         \
+        constexpr int nt = 64 * (BM_ >= 64 ? BM_ / 64 : 1) * (BN_ >= 32 ? BN_ / 32 : 1);       \
+        hipLaunchKernelGGL((k_gemm_mfma<BM_, BN_>), dim3(blocks), dim3(nt), 0, s, g);          \
+        return;                                                                                \
+    }
+    TN_LAUNCH(128, 64)
+    TN_LAUNCH(64, 64)
+    TN_LAUNCH(128, 32)
+    TN_LAUNCH(64, 32)
+    TN_LAUNCH(32, 32)
+    TN_LAUNCH(32, 16)
+#undef TN_LAUNCH
+}
+
+int launch_gemm_c64(const GemmArgs& g, hipStream_t s, int tile_hint) {
+    const int mn_log = g.m_log + g.n_log;
+    if (mn_log <= 4 && g.k_log >= 8) {
+        const int64_t blocks = g.n_inst << mn_log;
+        hipLaunchKernelGGL((k_gemm_splitk<float, float2>), dim3((unsigned)blocks), dim3(256), 0, s, g);
+        return KC_SPLITK;
+    }
+    if (g.m_log >= 5 && g.n_log >= 4) {
+        if (tile_hint >= 0 && tile_hint < kNumTiles && tile_fits(kTiles[tile_hint], g)) {
+            launch_mfma_tile(kTiles[tile_hint], g, s);
+            return KC_MFMA;
+        }
+        for (int i = 0; i < kNumTiles; ++i)
+            if (tile_fits(kTiles[i], g)) {
+                launch_mfma_tile(kTiles[i], g, s);
+                return KC_MFMA;
+            }
+    }
+    const int64_t total = g.n_inst << mn_log;
+    hipLaunchKernelGGL((k_gemm_small<float, float2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
+    return KC_SMALL;
+}
+
+int launch_gemm_c128(const GemmArgs& g, hipStream_t s) {
+    const int mn_log = g.m_log + g.n_log;
+    if (mn_log <= 4 && g.k_log >= 8) {
+        const int64_t blocks = g.n_inst << mn_log;
+        hipLaunchKernelGGL((k_gemm_splitk<double, double2>), dim3((unsigned)blocks), dim3(256), 0, s, g);
+        return KC_SPLITK;
+    }
+    if (g.m_log >= 6 && g.n_log >= 6) {
+        const int64_t tiles = (int64_t(1) << (g.m_log - 6)) << (g.n_log - 6);
+        hipLaunchKernelGGL(k_gemm_tiled_c128, dim3((unsigned)(tiles * g.n_inst)), dim3(256), 0, s, g);
+        return KC_TILED;
+    }
+    const int64_t total = g.n_inst << mn_log;
+    hipLaunchKernelGGL((k_gemm_small<double, double2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
+    return KC_SMALL;
+}
+
+template <typename T>
+static void launch_perm(const PermArgs& p, hipStream_t s) {
+    const int tsize = 1 << p.tb;
+    const int upb = tsize >= 256 ? 1 : 256 / tsize;
+    const int64_t units = p.n_inst << p.n_high;
+    const unsigned blocks = (unsigned)((units + upb - 1) / upb);
+    const size_t lds = (size_t)upb * tsize * sizeof(T);
+    hipLaunchKernelGGL((k_permute<T>), dim3(blocks), dim3(256), lds, s, p);
+}
+
+void launch_permute_c64(const PermArgs& p, hipStream_t s) { launch_perm<float2>(p, s); }
+void launch_permute_c128(const PermArgs& p, hipStream_t s) { launch_perm<double2>(p, s); }
+
+void launch_finalize(const FinalizeArgs& f, hipStream_t s) {
+    if (f.n_terms == 0) return;
+    hipLaunchKernelGGL(k_finalize, dim3(grid1(f.n_terms, 256)), dim3(256), 0, s, f);
+}
+
+void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_level_sum, dim3(n_levels), dim3(256), 0, s, x, starts, out);
+}
+
+void launch_slot_fill(const SlotFillArgs& a, hipStream_t s) {
+    if (a.n == 0) return;
+    hipLaunchKernelGGL(k_slot_fill, dim3(grid1(a.n * 8, 256)), dim3(256), 0, s, a);
+}
+
+void launch_copy_c64(const void* src, void* dst, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_copy_c64, dim3(grid1(n, 256)), dim3(256), 0, s, (const float2*)src,
+                       (float2*)dst, n);
+}
+
+}  // namespace tn

@@ -1,0 +1,796 @@
+// Host-side planning: validation, noise split, reduced ket network, clusters,
+// contraction path, term enumeration.  No device code.
+//
+// Method references: matrix representation of a channel (Section III),
+// tensor permutation and SVD split (Section IV, Fig. 3), level-l terms and
+// their enumeration order (Section IV, Algorithm 1).
+
+#include <algorithm>
+#include <atomic>
+#include <functional>
+#include <limits>
+#include <memory>
+#include <tuple>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <queue>
+#include <random>
+#include <sstream>
+#include <unordered_map>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+// ---------------------------------------------------------------------------
+// 4x4 complex Hermitian eigensolver (cyclic Jacobi).  Each rotation first
+// turns a[p][q] real with a phase on column q, then applies the real
+// symmetric Jacobi rotation that zeroes it.
+// ---------------------------------------------------------------------------
+static void mat4_mul(const cd a[4][4], const cd b[4][4], cd c[4][4]) {
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cd s = 0;
+            for (int k = 0; k < 4; ++k) s += a[i][k] * b[k][j];
+            c[i][j] = s;
+        }
+}
+
+static void mat4_adjoint(const cd a[4][4], cd c[4][4]) {
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) c[i][j] = std::conj(a[j][i]);
+}
+
+void jacobi_hermitian4(const cd a_in[4][4], double evals[4], cd evecs[4][4]) {
+    cd a[4][4], v[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            a[i][j] = 0.5 * (a_in[i][j] + std::conj(a_in[j][i]));
+            v[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    double scale = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) scale = std::max(scale, std::abs(a[i][j]));
+    if (scale == 0) scale = 1;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) off += std::norm(a[p][q]);
+        if (off <= 1e-34 * scale * scale) break;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                double apq = std::abs(a[p][q]);
+                if (apq <= 1e-300) continue;
+                cd ph = a[p][q] / apq;           // a[p][q] = apq * ph
+                double app = a[p][p].real(), aqq = a[q][q].real();
+                double tau = (aqq - app) / (2.0 * apq);
+                double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                // G = D R with D = diag(.., conj(ph) at q, ..), R the real rotation
+                cd g[4][4];
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) g[i][j] = (i == j) ? 1.0 : 0.0;
+                g[p][p] = c;
+                g[p][q] = s;
+                g[q][p] = -s * std::conj(ph);
+                g[q][q] = c * std::conj(ph);
+                cd gh[4][4], tmp[4][4], na[4][4], nv[4][4];
+                mat4_adjoint(g, gh);
+                mat4_mul(gh, a, tmp);
+                mat4_mul(tmp, g, na);
+                mat4_mul(v, g, nv);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) {
+                        a[i][j] = na[i][j];
+                        v[i][j] = nv[i][j];
+                    }
+                a[p][q] = a[q][p] = 0.0;
+            }
+    }
+    int order[4] = {0, 1, 2, 3};
+    std::sort(order, order + 4, [&](int x, int y) { return a[x][x].real() > a[y][y].real(); });
+    for (int k = 0; k < 4; ++k) {
+        evals[k] = a[order[k]][order[k]].real();
+        for (int i = 0; i < 4; ++i) evecs[i][k] = v[i][order[k]];
+    }
+}
+
+double spectral_norm4(const cd a[4][4]) {
+    cd ah[4][4], h[4][4], ev[4][4];
+    double w[4];
+    mat4_adjoint(a, ah);
+    mat4_mul(ah, a, h);
+    jacobi_hermitian4(h, w, ev);
+    return std::sqrt(std::max(0.0, w[0]));
+}
+
+// ---------------------------------------------------------------------------
+// noise split
+// ---------------------------------------------------------------------------
+static NoiseSplit split_noise(const tn_op& op, int64_t index) {
+    NoiseSplit ns;
+    ns.qubit = op.q[0];
+    ns.op_index = index;
+    // trace preservation (Section II): sum_k E_k^+ E_k = I
+    cd tp[2][2] = {{0, 0}, {0, 0}};
+    for (int k = 0; k < op.n_kraus; ++k) {
+        const tn_c128* e = op.mat + 4 * k;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 2; ++r)
+                    tp[i][j] += std::conj(cd(e[2 * r + i].re, e[2 * r + i].im)) *
+                                cd(e[2 * r + j].re, e[2 * r + j].im);
+    }
+    double res = 0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) res = std::max(res, std::abs(tp[i][j] - (i == j ? 1.0 : 0.0)));
+    if (!(res <= 1e-10)) {
+        std::ostringstream os;
+        os << "noise at op " << index << " is not trace preserving: max|sum E^+E - I| = " << res;
+        fail(TN_ENOTCPTP, os.str());
+    }
+    // M = sum_k E_k (x) conj(E_k); rows (a,b) = 2a+b (ket a, bra b)
+    cd m[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) m[i][j] = 0;
+    for (int k = 0; k < op.n_kraus; ++k) {
+        const tn_c128* e = op.mat + 4 * k;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c)
+                    for (int d = 0; d < 2; ++d)
+                        m[2 * a + b][2 * c + d] += cd(e[2 * a + c].re, e[2 * a + c].im) *
+                                                   std::conj(cd(e[2 * b + d].re, e[2 * b + d].im));
+    }
+    // noise rate ||M - I||_2 (Section IV)
+    cd mi[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) mi[i][j] = m[i][j] - (i == j ? 1.0 : 0.0);
+    ns.rate = spectral_norm4(mi);
+    // permutation (Fig. 3a): Mt[(a,c),(b,d)] = M[(a,b),(c,d)]; Hermitian PSD
+    cd mt[4][4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c)
+                for (int d = 0; d < 2; ++d) mt[2 * a + c][2 * b + d] = m[2 * a + b][2 * c + d];
+    double ev[4];
+    cd vec[4][4];
+    jacobi_hermitian4(mt, ev, vec);
+    // singular values of a PSD matrix = its eigenvalues; tiny negative
+    // rounding residue becomes |.|, and is flagged as an exact zero below
+    // re-associate eigenvectors to the sorted |eigenvalues|
+    int idx[4] = {0, 1, 2, 3};
+    std::sort(idx, idx + 4, [&](int x, int y) { return std::fabs(ev[x]) > std::fabs(ev[y]); });
+    for (int i = 0; i < 4; ++i) {
+        int src = idx[i];
+        for (int r = 0; r < 4; ++r) ns.K[i][r] = vec[r][src];   // K_i[a][c] = s_i[2a+c]
+        ns.d[i] = std::fabs(ev[src]);
+    }
+    if (!(ns.d[1] < (1.0 - 1e-12) * ns.d[0])) {
+        std::ostringstream os;
+        os << "noise at op " << index << ": dominant singular value is not strictly largest (d0="
+           << ns.d[0] << ", d1=" << ns.d[1] << ")";
+        fail(TN_EDEGENERATE, os.str());
+    }
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int i = 0; i < 4; ++i) ns.zero[i] = ns.d[i] <= 4.0 * eps * ns.d[0];
+    // norms used by the remainder bound: ||U_0 (x) V_0|| and ||sum_{i>=1} U_i (x) V_i||
+    cd mm[4][4], mb[4][4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c)
+                for (int d = 0; d < 2; ++d) {
+                    // (U_i (x) V_i)[(a,b),(c,d)] = d_i K_i[a][c] conj(K_i[b][d])
+                    cd s0 = ns.d[0] * ns.K[0][2 * a + c] * std::conj(ns.K[0][2 * b + d]);
+                    cd sb = 0;
+                    for (int i = 1; i < 4; ++i)
+                        sb += ns.d[i] * ns.K[i][2 * a + c] * std::conj(ns.K[i][2 * b + d]);
+                    mm[2 * a + b][2 * c + d] = s0;
+                    mb[2 * a + b][2 * c + d] = sb;
+                }
+    ns.norm_main = spectral_norm4(mm);
+    ns.norm_bar = spectral_norm4(mb);
+    return ns;
+}
+
+// ---------------------------------------------------------------------------
+// small dense tensor algebra on the host (FP64), legs of dimension 2
+// ---------------------------------------------------------------------------
+static Leaf contract_host(const Leaf& x, const Leaf& y) {
+    std::vector<int> shared, fx, fy;
+    for (int e : x.legs)
+        if (std::find(y.legs.begin(), y.legs.end(), e) != y.legs.end()) shared.push_back(e);
+        else fx.push_back(e);
+    for (int e : y.legs)
+        if (std::find(shared.begin(), shared.end(), e) == shared.end()) fy.push_back(e);
+    Leaf out;
+    out.legs = fx;
+    out.legs.insert(out.legs.end(), fy.begin(), fy.end());
+    const int rx = (int)x.legs.size(), ry = (int)y.legs.size(), rs = (int)shared.size();
+    const int rfx = (int)fx.size(), rfy = (int)fy.size();
+    auto pos = [](const std::vector<int>& legs, int e) {
+        return (int)(std::find(legs.begin(), legs.end(), e) - legs.begin());
+    };
+    std::vector<int> fx_pos(rfx), fy_pos(rfy), sx_pos(rs), sy_pos(rs);
+    for (int i = 0; i < rfx; ++i) fx_pos[i] = rx - 1 - pos(x.legs, fx[i]);
+    for (int i = 0; i < rfy; ++i) fy_pos[i] = ry - 1 - pos(y.legs, fy[i]);
+    for (int i = 0; i < rs; ++i) {
+        sx_pos[i] = rx - 1 - pos(x.legs, shared[i]);
+        sy_pos[i] = ry - 1 - pos(y.legs, shared[i]);
+    }
+    const int64_t nout = int64_t(1) << (rfx + rfy);
+    out.data.assign(nout, 0.0);
+    for (int64_t o = 0; o < nout; ++o) {
+        int64_t bx = 0, by = 0;
+        for (int i = 0; i < rfx; ++i)
+            if ((o >> (rfx + rfy - 1 - i)) & 1) bx |= int64_t(1) << fx_pos[i];
+        for (int i = 0; i < rfy; ++i)
+            if ((o >> (rfy - 1 - i)) & 1) by |= int64_t(1) << fy_pos[i];
+        cd acc = 0;
+        for (int64_t s = 0; s < (int64_t(1) << rs); ++s) {
+            int64_t ix = bx, iy = by;
+            for (int i = 0; i < rs; ++i)
+                if ((s >> i) & 1) {
+                    ix |= int64_t(1) << sx_pos[i];
+                    iy |= int64_t(1) << sy_pos[i];
+                }
+            acc += x.data[ix] * y.data[iy];
+        }
+        out.data[o] = acc;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// reduced ket network
+// ---------------------------------------------------------------------------
+struct NetBuild {
+    std::vector<Leaf> leaves;
+    cd scalar = 1.0;
+};
+
+static void check_unitary(const tn_op& op, int64_t idx) {
+    const int d = 1 << op.nq;
+    double err = 0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            cd s = 0;
+            for (int r = 0; r < d; ++r)
+                s += std::conj(cd(op.mat[r * d + i].re, op.mat[r * d + i].im)) *
+                     cd(op.mat[r * d + j].re, op.mat[r * d + j].im);
+            err = std::max(err, std::abs(s - (i == j ? 1.0 : 0.0)));
+        }
+    if (!(err <= 1e-10)) {
+        std::ostringstream os;
+        os << "gate at op " << idx << " is not unitary: max|G^+G - I| = " << err;
+        fail(TN_EINVAL, os.str());
+    }
+}
+
+static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn_state* v,
+                              bool light_cone) {
+    const int n = c->n_qubits;
+    NetBuild nb;
+    std::vector<int> noise_of_op(c->n_ops, -1);
+    int ns = 0;
+    for (int64_t k = 0; k < c->n_ops; ++k)
+        if (c->ops[k].kind == TN_NOISE) noise_of_op[k] = ns++;
+    auto amp = [](const tn_c128* p, int q, int b) { return cd(p[2 * q + b].re, p[2 * q + b].im); };
+
+    std::vector<std::pair<int64_t, bool>> seq;   // (op index, inverse)
+    std::vector<char> touched(n, 0);
+    bool cone_target = v->kind == TN_STATE_CIRCUIT_OUTPUT;
+    if (cone_target) {
+        std::vector<char> keep(c->n_ops, 1);
+        if (light_cone) {
+            std::vector<char> live(n, 0);
+            for (int64_t k = c->n_ops - 1; k >= 0; --k) {
+                const tn_op& op = c->ops[k];
+                if (op.kind == TN_NOISE) {
+                    live[op.q[0]] = 1;
+                } else {
+                    bool hit = false;
+                    for (int i = 0; i < op.nq; ++i) hit |= live[op.q[i]] != 0;
+                    if (hit)
+                        for (int i = 0; i < op.nq; ++i) live[op.q[i]] = 1;
+                    else
+                        keep[k] = 0;
+                }
+            }
+        }
+        for (int64_t k = 0; k < c->n_ops; ++k)
+            if (keep[k]) {
+                seq.push_back({k, false});
+                for (int i = 0; i < c->ops[k].nq; ++i) touched[c->ops[k].q[i]] = 1;
+            }
+        for (int64_t k = c->n_ops - 1; k >= 0; --k)
+            if (keep[k] && c->ops[k].kind == TN_GATE) seq.push_back({k, true});
+        // <p_v,q | psi_q> for every qubit the reduced network does not touch
+        for (int q = 0; q < n; ++q)
+            if (!touched[q])
+                nb.scalar *= std::conj(amp(v->data, q, 0)) * amp(psi->data, q, 0) +
+                             std::conj(amp(v->data, q, 1)) * amp(psi->data, q, 1);
+    } else {
+        for (int64_t k = 0; k < c->n_ops; ++k) seq.push_back({k, false});
+        std::fill(touched.begin(), touched.end(), 1);
+    }
+    int edge = 0;
+    std::vector<int> cur(n, -1);
+    for (int q = 0; q < n; ++q)
+        if (touched[q]) {
+            Leaf l;
+            l.legs = {edge};
+            l.data = {amp(psi->data, q, 0), amp(psi->data, q, 1)};
+            cur[q] = edge++;
+            nb.leaves.push_back(std::move(l));
+        }
+    for (auto [k, inv] : seq) {
+        const tn_op& op = c->ops[k];
+        Leaf l;
+        std::vector<int> ins, outs;
+        for (int i = 0; i < op.nq; ++i) ins.push_back(cur[op.q[i]]);
+        for (int i = 0; i < op.nq; ++i) {
+            outs.push_back(edge);
+            cur[op.q[i]] = edge++;
+        }
+        l.legs = outs;
+        l.legs.insert(l.legs.end(), ins.begin(), ins.end());
+        if (op.kind == TN_NOISE) {
+            l.slot = noise_of_op[k];
+        } else {
+            const int d = 1 << op.nq;
+            l.data.resize(d * d);
+            for (int r = 0; r < d; ++r)
+                for (int cc = 0; cc < d; ++cc) {
+                    // element [outs..., ins...] = G[out][in] (or G^+ for the inverse)
+                    cd g = inv ? std::conj(cd(op.mat[cc * d + r].re, op.mat[cc * d + r].im))
+                               : cd(op.mat[r * d + cc].re, op.mat[r * d + cc].im);
+                    l.data[r * d + cc] = g;
+                }
+        }
+        nb.leaves.push_back(std::move(l));
+    }
+    if (v->kind == TN_STATE_DENSE) {
+        Leaf l;
+        for (int q = 0; q < n; ++q) l.legs.push_back(cur[q]);
+        l.data.resize(size_t(1) << n);
+        for (size_t i = 0; i < l.data.size(); ++i)
+            l.data[i] = std::conj(cd(v->data[i].re, v->data[i].im));
+        nb.leaves.push_back(std::move(l));
+    } else {
+        for (int q = 0; q < n; ++q)
+            if (touched[q]) {
+                Leaf l;
+                l.legs = {cur[q]};
+                l.data = {std::conj(amp(v->data, q, 0)), std::conj(amp(v->data, q, 1))};
+                nb.leaves.push_back(std::move(l));
+            }
+    }
+    return nb;
+}
+
+// Contract fixed tensors into fixed neighbours on the host (FP64) while the
+// result is no larger than the larger operand (at most 4 legs): absorbs the
+// boundary vectors, 1-qubit gates and cancelling neighbours.  Exact up to
+// rounding; slot tensors are never touched.
+static void fuse_fixed(NetBuild& nb) {
+    std::vector<Leaf>& L = nb.leaves;
+    std::vector<char> alive(L.size(), 1);
+    std::unordered_map<int, std::vector<int>> owners;
+    for (size_t i = 0; i < L.size(); ++i)
+        for (int e : L[i].legs) owners[e].push_back((int)i);
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (size_t i = 0; i < L.size(); ++i) {
+            if (!alive[i] || L[i].slot >= 0) continue;
+            // best neighbour: fixed, shares a leg, result rank <= max(rank, 4)
+            int best = -1, best_rank = 1 << 30;
+            for (int e : L[i].legs) {
+                for (int j : owners[e]) {
+                    if (j == (int)i || !alive[j] || L[j].slot >= 0) continue;
+                    int shared = 0;
+                    for (int f : L[i].legs)
+                        if (std::find(L[j].legs.begin(), L[j].legs.end(), f) != L[j].legs.end()) ++shared;
+                    int r = (int)L[i].legs.size() + (int)L[j].legs.size() - 2 * shared;
+                    int lim = std::max<int>(4, std::max(L[i].legs.size(), L[j].legs.size()));
+                    if (r <= lim && r < best_rank) {
+                        best = j;
+                        best_rank = r;
+                    }
+                }
+            }
+            if (best < 0) continue;
+            Leaf merged = contract_host(L[i], L[best]);
+            for (int e : L[i].legs) {
+                auto& v = owners[e];
+                v.erase(std::remove(v.begin(), v.end(), (int)i), v.end());
+            }
+            for (int e : L[best].legs) {
+                auto& v = owners[e];
+                v.erase(std::remove(v.begin(), v.end(), best), v.end());
+            }
+            alive[i] = 0;
+            L[best] = std::move(merged);
+            for (int e : L[best].legs) owners[e].push_back(best);
+            changed = true;
+        }
+    }
+    std::vector<Leaf> out;
+    for (size_t i = 0; i < L.size(); ++i) {
+        if (!alive[i]) continue;
+        if (L[i].slot < 0 && L[i].legs.empty()) {
+            nb.scalar *= L[i].data[0];
+            continue;
+        }
+        out.push_back(std::move(L[i]));
+    }
+    L.swap(out);
+}
+
+// ---------------------------------------------------------------------------
+// contraction path: randomized greedy, scored by instance-weighted size
+// ---------------------------------------------------------------------------
+struct PathSearch {
+    int level;
+    std::vector<int> zcount;                 // non-zero corrections per local slot
+
+    // number of distinct restricted patterns of a node with these slots
+    double instances(uint64_t mask) const {
+        double e[TN_MAX_LEVEL + 2] = {1.0};
+        for (int i = 1; i <= level; ++i) e[i] = 0;
+        for (int s = 0; s < 64; ++s)
+            if ((mask >> s) & 1ULL)
+                for (int u = level; u >= 1; --u) e[u] += e[u - 1] * zcount[s];
+        double t = 0;
+        for (int u = 0; u <= level; ++u) t += e[u];
+        return t;
+    }
+};
+
+static std::vector<int> sym_diff(const std::vector<int>& a, const std::vector<int>& b) {
+    std::vector<int> out;
+    std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+    return out;
+}
+
+static int union_size(const std::vector<int>& a, const std::vector<int>& b) {
+    size_t i = 0, j = 0;
+    int n = 0;
+    while (i < a.size() || j < b.size()) {
+        if (j == b.size() || (i < a.size() && a[i] < b[j])) ++i;
+        else if (i == a.size() || b[j] < a[i]) ++j;
+        else { ++i; ++j; }
+        ++n;
+    }
+    return n;
+}
+
+struct TrialResult {
+    std::vector<PathStep> path;
+    double cost = 0;          // instance-weighted complex MACs
+    double cost1 = 0;         // one-term complex MACs
+    double peak = 0;          // instance-weighted elements live at once
+    int max_log = 0;
+};
+
+static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
+                                const std::vector<uint64_t>& leaf_mask, const PathSearch& ps,
+                                double alpha, double temp, uint64_t seed) {
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> uni(1e-12, 1.0);
+    const int L = (int)leaf_legs.size();
+    std::vector<std::vector<int>> legs(leaf_legs);
+    std::vector<uint64_t> mask(leaf_mask);
+    std::vector<char> alive(L, 1);
+    std::unordered_map<int, std::vector<int>> owners;
+    for (int i = 0; i < L; ++i)
+        for (int e : legs[i]) owners[e].push_back(i);
+    auto size_of = [&](int i) { return ps.instances(mask[i]) * std::ldexp(1.0, (int)legs[i].size()); };
+    typedef std::tuple<double, int, int> Cand;
+    std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> pq;
+    auto push = [&](int a, int b) {
+        if (a == b) return;
+        if (a > b) std::swap(a, b);
+        std::vector<int> lc = sym_diff(legs[a], legs[b]);
+        double sc = ps.instances(mask[a] | mask[b]) * std::ldexp(1.0, (int)lc.size()) -
+                    alpha * (size_of(a) + size_of(b));
+        double s = (sc >= 0 ? 1.0 : -1.0) * std::log2(1.0 + std::fabs(sc));
+        if (temp > 0) s -= temp * (-std::log(-std::log(uni(rng))));
+        pq.push(Cand(s, a, b));
+    };
+    for (auto& kv : owners)
+        if (kv.second.size() == 2) push(kv.second[0], kv.second[1]);
+    TrialResult tr;
+    double live = 0;
+    for (int i = 0; i < L; ++i) live += size_of(i);
+    tr.peak = live;
+    int remaining = L;
+    while (remaining > 1) {
+        int a, b;
+        if (!pq.empty()) {
+            Cand cd_ = pq.top();
+            pq.pop();
+            a = std::get<1>(cd_);
+            b = std::get<2>(cd_);
+            if (!alive[a] || !alive[b]) continue;
+        } else {
+            // disconnected leftovers (cannot happen inside a cluster)
+            a = -1;
+            b = -1;
+            for (int i = 0; i < (int)alive.size(); ++i)
+                if (alive[i]) {
+                    if (a < 0) a = i;
+                    else if (b < 0) { b = i; break; }
+                }
+        }
+        std::vector<int> lc = sym_diff(legs[a], legs[b]);
+        uint64_t mc = mask[a] | mask[b];
+        int u = union_size(legs[a], legs[b]);
+        double inst = ps.instances(mc);
+        tr.cost += inst * std::ldexp(1.0, u);
+        tr.cost1 += std::ldexp(1.0, u);
+        tr.max_log = std::max(tr.max_log, (int)lc.size());
+        int c = (int)legs.size();
+        live += inst * std::ldexp(1.0, (int)lc.size());
+        tr.peak = std::max(tr.peak, live);
+        live -= size_of(a) + size_of(b);
+        legs.push_back(lc);
+        mask.push_back(mc);
+        alive.push_back(1);
+        alive[a] = alive[b] = 0;
+        for (int e : legs[a]) {
+            auto& v = owners[e];
+            v.erase(std::remove(v.begin(), v.end(), a), v.end());
+        }
+        for (int e : legs[b]) {
+            auto& v = owners[e];
+            v.erase(std::remove(v.begin(), v.end(), b), v.end());
+        }
+        for (int e : lc) owners[e].push_back(c);
+        tr.path.push_back({a, b});
+        --remaining;
+        for (int e : lc)
+            for (int o : owners[e])
+                if (o != c) push(o, c);
+    }
+    return tr;
+}
+
+static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log) {
+    const int nl = (int)p.leaves.size();
+    // union-find over shared legs
+    std::vector<int> parent(nl);
+    std::iota(parent.begin(), parent.end(), 0);
+    std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
+    std::unordered_map<int, int> first_owner;
+    for (int i = 0; i < nl; ++i)
+        for (int e : p.leaves[i].legs) {
+            auto it = first_owner.find(e);
+            if (it == first_owner.end()) first_owner[e] = i;
+            else parent[find(i)] = find(it->second);
+        }
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < nl; ++i) groups[find(i)].push_back(i);
+    p.clusters.clear();
+    for (auto& kv : groups) {
+        Cluster cl;
+        cl.leaves = kv.second;
+        for (int li : cl.leaves)
+            if (p.leaves[li].slot >= 0) cl.slots.push_back(p.leaves[li].slot);
+        std::sort(cl.slots.begin(), cl.slots.end());
+        if ((int)cl.slots.size() > kMaxSlotsPerCluster)
+            fail(TN_ETOOBIG, "a network cluster holds more than 64 noise slots");
+        PathSearch ps;
+        ps.level = p.level;
+        for (int s : cl.slots) {
+            int z = 0;
+            for (int i = 1; i < 4; ++i) z += p.noise[s].zero[i] ? 0 : 1;
+            ps.zcount.push_back(z);
+        }
+        std::vector<std::vector<int>> leaf_legs;
+        std::vector<uint64_t> leaf_mask;
+        for (int li : cl.leaves) {
+            std::vector<int> lg = p.leaves[li].legs;
+            std::sort(lg.begin(), lg.end());
+            leaf_legs.push_back(lg);
+            uint64_t m = 0;
+            if (p.leaves[li].slot >= 0) {
+                int local = (int)(std::lower_bound(cl.slots.begin(), cl.slots.end(), p.leaves[li].slot) -
+                                  cl.slots.begin());
+                m = 1ULL << local;
+            }
+            leaf_mask.push_back(m);
+        }
+        if (cl.leaves.size() == 1) {
+            cl.max_log = (int)leaf_legs[0].size();
+            p.clusters.push_back(cl);
+            continue;
+        }
+        TrialResult best;
+        bool have = false;
+        const double alphas[4] = {1.0, 0.5, 0.0, 0.75};
+        const double temps[3] = {0.5, 1.0, 2.0};
+        for (int t = 0; t < trials; ++t) {
+            double alpha = alphas[t % 4];
+            double temp = t < 4 ? 0.0 : temps[t % 3];
+            TrialResult tr = greedy_trial(leaf_legs, leaf_mask, ps, alpha, temp,
+                                          seed * 1000003ULL + (uint64_t)t * 7919ULL + 17);
+            bool ok = tr.max_log <= max_log;
+            bool best_ok = have && best.max_log <= max_log;
+            if (!have || (ok && !best_ok) || (ok == best_ok && tr.cost < best.cost)) {
+                best = std::move(tr);
+                have = true;
+            }
+        }
+        if (best.max_log > max_log) {
+            std::ostringstream os;
+            os << "no contraction path keeps tensors within 2^" << max_log << " elements (best 2^"
+               << best.max_log << ")";
+            fail(TN_ETOOBIG, os.str());
+        }
+        cl.path = best.path;
+        cl.cmacs_per_term = best.cost1;
+        cl.max_log = best.max_log;
+        p.clusters.push_back(cl);
+    }
+    p.max_log = 0;
+    p.cmacs_per_term = 0;
+    for (auto& cl : p.clusters) {
+        p.max_log = std::max(p.max_log, cl.max_log);
+        p.cmacs_per_term += cl.cmacs_per_term;
+    }
+}
+
+static std::atomic<uint64_t> g_plan_id{1};
+
+Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, int level,
+                 const tn_plan_opts* opts) {
+    if (!c || !psi || !v) fail(TN_EINVAL, "null circuit or state");
+    if (c->n_qubits < 1 || c->n_qubits > 4096) fail(TN_EINVAL, "n_qubits out of range");
+    if (c->n_ops < 0 || (c->n_ops > 0 && !c->ops)) fail(TN_EINVAL, "bad op list");
+    if (psi->kind != TN_STATE_PRODUCT || !psi->data) fail(TN_EINVAL, "psi must be a product state");
+    if (v->kind < 0 || v->kind > 2 || !v->data) fail(TN_EINVAL, "bad target state");
+    if (v->kind == TN_STATE_DENSE && c->n_qubits > 30) fail(TN_EINVAL, "dense target needs n <= 30");
+    if (level < 0) fail(TN_EINVAL, "level must be >= 0");
+    auto p = std::make_unique<Plan>();
+    p->id = g_plan_id++;
+    p->n_qubits = c->n_qubits;
+    p->target_kind = v->kind == TN_STATE_CIRCUIT_OUTPUT ? "circuit_output"
+                     : v->kind == TN_STATE_PRODUCT ? "product" : "dense";
+    for (int64_t k = 0; k < c->n_ops; ++k) {
+        const tn_op& op = c->ops[k];
+        if (op.kind != TN_GATE && op.kind != TN_NOISE) fail(TN_EINVAL, "op kind must be gate or noise");
+        if (op.kind == TN_NOISE && op.nq != 1)
+            fail(TN_EUNSUPPORTED, "noise channels must act on exactly one qubit");
+        if (op.nq < 1 || op.nq > 2) fail(TN_EUNSUPPORTED, "gates act on one or two qubits");
+        if (!op.mat) fail(TN_EINVAL, "op without matrix");
+        for (int i = 0; i < op.nq; ++i)
+            if (op.q[i] < 0 || op.q[i] >= c->n_qubits) fail(TN_EINVAL, "qubit index out of range");
+        if (op.nq == 2 && op.q[0] == op.q[1]) fail(TN_EINVAL, "2-qubit gate on one qubit");
+        if (op.kind == TN_GATE) check_unitary(op, k);
+        else {
+            if (op.n_kraus < 1 || op.n_kraus > 64) fail(TN_EINVAL, "noise needs 1..64 Kraus matrices");
+            p->noise.push_back(split_noise(op, k));
+        }
+    }
+    // state normalisation is the caller's choice; only finiteness is checked
+    p->n_noise = (int)p->noise.size();
+    p->level_req = level;
+    p->level = std::min(level, p->n_noise);
+    p->clamped = level > p->n_noise;
+    if (p->level > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
+    NetBuild nb = build_network(c, psi, v, !(opts && opts->no_light_cone));
+    fuse_fixed(nb);
+    p->leaves = std::move(nb.leaves);
+    p->scalar = nb.scalar;
+    int trials = (opts && opts->path_trials > 0) ? opts->path_trials : 64;
+    uint64_t seed = (opts && opts->seed) ? opts->seed : 2211170280ULL;
+    int max_log = (opts && opts->max_log_size > 0) ? opts->max_log_size : 30;
+    plan_clusters(*p, trials, seed, max_log);
+    return p.release();
+}
+
+// ---------------------------------------------------------------------------
+// term enumeration (Algorithm 1 order)
+// ---------------------------------------------------------------------------
+Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune) {
+    if (level < 0) fail(TN_EINVAL, "level must be >= 0");
+    const int N = p->n_noise;
+    const int L = std::min(level, N);
+    if (L > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
+    auto t = std::make_unique<Terms>();
+    t->plan = p;
+    t->plan_id = p->id;
+    t->level = L;
+    std::vector<int> pos, corr;
+    int64_t cand = 0;
+    for (int u = 0; u <= L; ++u) {
+        pos.resize(u);
+        for (int i = 0; i < u; ++i) pos[i] = i;
+        while (true) {
+            corr.assign(u, 1);
+            while (true) {
+                std::vector<int8_t> pat(N, 0);
+                for (int i = 0; i < u; ++i) pat[pos[i]] = (int8_t)corr[i];
+                double w = 1.0;
+                bool zero = false;
+                for (int s = 0; s < N; ++s) {
+                    w *= p->noise[s].d[pat[s]];
+                    zero |= p->noise[s].zero[pat[s]];
+                }
+                bool pruned = false;
+                if (prune && u >= prune->min_level && prune->min_level >= 1) {
+                    if (prune->keep) {
+                        if (cand >= prune->n_keep) fail(TN_EINVAL, "prune keep array too short");
+                        pruned = prune->keep[cand] == 0;
+                    }
+                    ++cand;
+                }
+                t->pat.insert(t->pat.end(), pat.begin(), pat.end());
+                t->w.push_back(zero ? 0.0 : w);
+                t->lvl.push_back((uint8_t)u);
+                t->zero.push_back(zero ? 1 : 0);
+                t->pruned.push_back(pruned ? 1 : 0);
+                // next correction tuple (lexicographic over {1,2,3}^u)
+                int j = u - 1;
+                while (j >= 0 && corr[j] == 3) corr[j--] = 1;
+                if (j < 0) break;
+                ++corr[j];
+            }
+            // next position set (lexicographic combinations)
+            int j = u - 1;
+            while (j >= 0 && pos[j] == N - u + j) --j;
+            if (j < 0) break;
+            ++pos[j];
+            for (int i = j + 1; i < u; ++i) pos[i] = pos[i - 1] + 1;
+        }
+    }
+    if (prune && prune->keep && cand != prune->n_keep)
+        fail(TN_EINVAL, "prune keep array length does not match the candidate count");
+    t->n = (int64_t)t->w.size();
+    return t.release();
+}
+
+std::string describe_plan(const Plan* p) {
+    std::ostringstream os;
+    os.precision(17);
+    os << "{\"n_qubits\":" << p->n_qubits << ",\"n_noise\":" << p->n_noise << ",\"level\":" << p->level
+       << ",\"target\":\"" << p->target_kind << "\",\"scalar\":[" << p->scalar.real() << ","
+       << p->scalar.imag() << "],\"max_log\":" << p->max_log << ",\"cmacs_per_term\":" << p->cmacs_per_term
+       << ",\"leaves\":[";
+    for (size_t i = 0; i < p->leaves.size(); ++i) {
+        const Leaf& l = p->leaves[i];
+        os << (i ? "," : "") << "{\"slot\":" << l.slot << ",\"legs\":[";
+        for (size_t j = 0; j < l.legs.size(); ++j) os << (j ? "," : "") << l.legs[j];
+        os << "],\"data\":[";
+        for (size_t j = 0; j < l.data.size(); ++j)
+            os << (j ? "," : "") << l.data[j].real() << "," << l.data[j].imag();
+        os << "]}";
+    }
+    os << "],\"clusters\":[";
+    for (size_t c = 0; c < p->clusters.size(); ++c) {
+        const Cluster& cl = p->clusters[c];
+        os << (c ? "," : "") << "{\"leaves\":[";
+        for (size_t j = 0; j < cl.leaves.size(); ++j) os << (j ? "," : "") << cl.leaves[j];
+        os << "],\"slots\":[";
+        for (size_t j = 0; j < cl.slots.size(); ++j) os << (j ? "," : "") << cl.slots[j];
+        os << "],\"path\":[";
+        for (size_t j = 0; j < cl.path.size(); ++j)
+            os << (j ? "," : "") << "[" << cl.path[j].a << "," << cl.path[j].b << "]";
+        os << "],\"cmacs_per_term\":" << cl.cmacs_per_term << ",\"max_log\":" << cl.max_log << "}";
+    }
+    os << "]}";
+    return os.str();
+}
+
+}  // namespace tn

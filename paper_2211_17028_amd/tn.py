@@ -1,0 +1,442 @@
+"""ctypes binding of the C ABI declared in include/tn.h.
+
+Argument marshalling only: every step of the estimate runs in the HIP library
+(libtn_gfx950.so).  PyTorch supplies device memory (the workspace) and the
+stream.  The library must have been built (paper_2211_17028_amd/build.py);
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtn_gfx950.so")
+
+TN_OK, TN_EINVAL, TN_ENOTCPTP, TN_EUNSUPPORTED, TN_EDEGENERATE = 0, -1, -2, -3, -4
+TN_ENOMEM, TN_EHIP, TN_ETOOBIG, TN_ESTATE = -5, -6, -7, -8
+TN_GATE, TN_NOISE = 0, 1
+TN_STATE_PRODUCT, TN_STATE_CIRCUIT_OUTPUT, TN_STATE_DENSE = 0, 1, 2
+TN_MODE_BATCHED, TN_MODE_PLAIN = 0, 1
+TN_MAX_LEVEL = 8
+
+ERROR_NAMES = {0: "TN_OK", -1: "TN_EINVAL", -2: "TN_ENOTCPTP", -3: "TN_EUNSUPPORTED",
+               -4: "TN_EDEGENERATE", -5: "TN_ENOMEM", -6: "TN_EHIP", -7: "TN_ETOOBIG",
+               -8: "TN_ESTATE"}
+
+
+class tn_c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class tn_op(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nq", C.c_int32), ("q", C.c_int32 * 2),
+                ("n_kraus", C.c_int32), ("mat", C.POINTER(tn_c128))]
+
+
+class tn_circuit(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_ops", C.c_int64), ("ops", C.POINTER(tn_op))]
+
+
+class tn_state(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("data", C.POINTER(tn_c128))]
+
+
+class tn_plan_opts(C.Structure):
+    _fields_ = [("path_trials", C.c_int32), ("seed", C.c_uint64), ("no_light_cone", C.c_int32),
+                ("max_log_size", C.c_int32)]
+
+
+class tn_prune_opts(C.Structure):
+    _fields_ = [("min_level", C.c_int32), ("keep", C.POINTER(C.c_uint8)), ("n_keep", C.c_int64)]
+
+
+class tn_exec_opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
+                ("tune", C.c_int32)]
+
+
+class tn_result(C.Structure):
+    _fields_ = [("level", C.c_int32), ("clamped", C.c_int32), ("n_terms", C.c_int64),
+                ("n_contracted", C.c_int64), ("n_zero_weight", C.c_int64),
+                ("level_sum", C.c_double * (TN_MAX_LEVEL + 1)),
+                ("level_comp", C.c_double * (TN_MAX_LEVEL + 1)),
+                ("A", C.c_double * (TN_MAX_LEVEL + 1)), ("bound", C.c_double),
+                ("x0_fp32", C.c_double)]
+
+    def as_dict(self):
+        L = self.level
+        return {"level": L, "clamped": bool(self.clamped), "n_terms": self.n_terms,
+                "n_contracted": self.n_contracted, "n_zero_weight": self.n_zero_weight,
+                "T": [self.level_sum[u] for u in range(L + 1)],
+                "A": [self.A[u] for u in range(L + 1)], "bound": self.bound,
+                "x0_fp32": self.x0_fp32}
+
+
+class tn_plan_info(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_noise", C.c_int32), ("level", C.c_int32),
+                ("clamped", C.c_int32), ("n_clusters", C.c_int32), ("n_leaves", C.c_int32),
+                ("max_log_size", C.c_int32), ("flops_per_term", C.c_double)]
+
+
+EXPORTS = [
+    "tn_plan_build", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
+    "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
+    "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
+]
+
+_lib = None
+
+
+class TNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2211_17028_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.tn_plan_build.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
+                                C.c_int32, C.POINTER(tn_plan_opts), C.POINTER(vp)]
+    L.tn_terms_enumerate.argtypes = [vp, C.c_int32, C.POINTER(tn_prune_opts), C.POINTER(vp),
+                                     C.POINTER(C.c_int64)]
+    L.tn_terms_get.argtypes = [vp, vp, vp]
+    L.tn_exec_prepare.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(tn_exec_opts),
+                                  vp, C.c_size_t, vp, C.POINTER(C.c_size_t), C.POINTER(vp)]
+    L.tn_exec_run.argtypes = [vp, vp, C.POINTER(tn_result)]
+    L.tn_exec_outputs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64)]
+    L.tn_exec_timing.argtypes = [vp] + [C.POINTER(C.c_double)] * 4
+    L.tn_contract_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.c_int64, C.c_int64,
+                                    vp, vp, C.c_size_t, vp]
+    L.tn_estimate.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), vp, C.c_size_t, vp,
+                              C.POINTER(tn_result)]
+    L.tn_plan_workspace.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_size_t)]
+    L.tn_plan_get_info.argtypes = [vp, C.POINTER(tn_plan_info)]
+    L.tn_plan_noise.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(tn_c128),
+                                C.POINTER(C.c_double)]
+    L.tn_plan_describe.argtypes = [vp, C.c_char_p, C.POINTER(C.c_size_t)]
+    L.tn_exec_describe.argtypes = [vp, C.c_char_p, C.POINTER(C.c_size_t)]
+    L.tn_exec_const_bytes.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.tn_exec_copy_outputs.argtypes = [vp, C.c_int32, vp, vp]
+    L.tn_plan_destroy.argtypes = [vp]
+    L.tn_terms_destroy.argtypes = [vp]
+    L.tn_exec_destroy.argtypes = [vp]
+    L.tn_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error"):
+            getattr(L, name).restype = C.c_int
+        else:
+            if name != "tn_last_error":
+                getattr(L, name).restype = None
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != TN_OK:
+        msg = lib().tn_last_error()
+        raise TNError(rc, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------------------
+# circuit marshalling
+# ---------------------------------------------------------------------------
+class _CircuitBuffers:
+    """Keeps the ctypes arrays of one circuit alive while a call uses them."""
+
+    def __init__(self, circ):
+        mats = []
+        ops = (tn_op * max(1, len(circ.ops)))()
+        offsets = []
+        off = 0
+        for op in circ.ops:
+            if op.kind == "gate":
+                m = np.ascontiguousarray(op.mat, dtype=np.complex128).reshape(-1)
+                nk = 0
+            else:
+                m = np.concatenate([np.ascontiguousarray(k, dtype=np.complex128).reshape(-1)
+                                    for k in op.kraus])
+                nk = len(op.kraus)
+            mats.append(m)
+            offsets.append((off, nk))
+            off += m.size
+        self.mat = np.ascontiguousarray(np.concatenate(mats) if mats else np.zeros(1, np.complex128))
+        base = self.mat.ctypes.data
+        for i, op in enumerate(circ.ops):
+            o = ops[i]
+            o.kind = TN_GATE if op.kind == "gate" else TN_NOISE
+            o.nq = len(op.qubits)
+            o.q[0] = int(op.qubits[0])
+            o.q[1] = int(op.qubits[1]) if len(op.qubits) > 1 else -1
+            o.n_kraus = offsets[i][1]
+            o.mat = C.cast(base + 16 * offsets[i][0], C.POINTER(tn_c128))
+        self.ops = ops
+        self.circ = tn_circuit(circ.n_qubits, len(circ.ops), C.cast(ops, C.POINTER(tn_op)))
+        self.psi_arr = np.ascontiguousarray(circ.psi, dtype=np.complex128).reshape(-1)
+        self.v_arr = np.ascontiguousarray(circ.v, dtype=np.complex128).reshape(-1)
+        kind = {"product": TN_STATE_PRODUCT, "circuit_output": TN_STATE_CIRCUIT_OUTPUT,
+                "dense": TN_STATE_DENSE}[circ.target]
+        self.psi = tn_state(TN_STATE_PRODUCT, C.cast(self.psi_arr.ctypes.data, C.POINTER(tn_c128)))
+        self.v = tn_state(kind, C.cast(self.v_arr.ctypes.data, C.POINTER(tn_c128)))
+
+
+class Plan:
+    def __init__(self, handle, circ):
+        self.handle = handle
+        self.circ = circ
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tn_plan_destroy(self.handle)
+            self.handle = None
+
+    def info(self):
+        inf = tn_plan_info()
+        _check(lib().tn_plan_get_info(self.handle, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in tn_plan_info._fields_}
+
+    def noise(self, s):
+        d = (C.c_double * 4)()
+        k = (tn_c128 * 16)()
+        rate = C.c_double()
+        _check(lib().tn_plan_noise(self.handle, s, d, k, C.byref(rate)))
+        kk = np.array([complex(x.re, x.im) for x in k]).reshape(4, 2, 2)
+        return np.array(list(d)), kk, rate.value
+
+    def describe(self):
+        n = C.c_size_t(0)
+        _check(lib().tn_plan_describe(self.handle, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().tn_plan_describe(self.handle, buf, C.byref(n)))
+        return json.loads(buf.value.decode())
+
+
+class Terms:
+    def __init__(self, handle, plan, n):
+        self.handle = handle
+        self.plan = plan
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tn_terms_destroy(self.handle)
+            self.handle = None
+
+    def get(self):
+        N = self.plan.circ.n_noises
+        pat = np.zeros((self.n, N), dtype=np.int8)
+        w = np.zeros(self.n, dtype=np.float64)
+        _check(lib().tn_terms_get(self.handle, pat.ctypes.data if N else None, w.ctypes.data))
+        return pat, w
+
+
+def tn_plan_build(circ, level: Optional[int] = None, path_trials: int = 0, seed: int = 0,
+                  light_cone: bool = True, max_log_size: int = 0) -> Plan:
+    bufs = _CircuitBuffers(circ)
+    opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size)
+    h = C.c_void_p()
+    lev = circ.level if level is None else level
+    _check(lib().tn_plan_build(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v), lev,
+                               C.byref(opts), C.byref(h)))
+    return Plan(h, circ)
+
+
+def tn_terms_enumerate(plan: Plan, level: int, keep: Optional[np.ndarray] = None,
+                       min_level: int = 2) -> Terms:
+    h = C.c_void_p()
+    n = C.c_int64()
+    if keep is None:
+        _check(lib().tn_terms_enumerate(plan.handle, level, None, C.byref(h), C.byref(n)))
+    else:
+        k = np.ascontiguousarray(keep, dtype=np.uint8)
+        po = tn_prune_opts(min_level, C.cast(k.ctypes.data, C.POINTER(C.c_uint8)), k.size)
+        _check(lib().tn_terms_enumerate(plan.handle, level, C.byref(po), C.byref(h), C.byref(n)))
+    return Terms(h, plan, n.value)
+
+
+def _handles(objs):
+    arr = (C.c_void_p * len(objs))()
+    for i, o in enumerate(objs):
+        arr[i] = o.handle
+    return arr
+
+
+class Exec:
+    def __init__(self, handle, plans, terms, ws, need):
+        self.handle = handle
+        self.plans = plans
+        self.terms = terms
+        self.ws = ws
+        self.need = need
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tn_exec_destroy(self.handle)
+            self.handle = None
+
+    def run(self, stream=None) -> List[dict]:
+        res = (tn_result * len(self.plans))()
+        _check(lib().tn_exec_run(self.handle, _stream_ptr(stream), res))
+        return [r.as_dict() for r in res]
+
+    def timing(self):
+        v = [C.c_double() for _ in range(4)]
+        _check(lib().tn_exec_timing(self.handle, *[C.byref(x) for x in v]))
+        return [x.value for x in v]
+
+    def outputs(self):
+        dx, da, n = C.c_void_p(), C.c_void_p(), C.c_int64()
+        _check(lib().tn_exec_outputs(self.handle, C.byref(dx), C.byref(da), C.byref(n)))
+        return dx.value, da.value, n.value
+
+    def describe(self):
+        return exec_describe(self.handle)
+
+    def values(self, plan=0):
+        """(X_t float64, a_t complex64) of packed plan `plan`, on the host."""
+        n = self.terms[plan].n
+        x = np.zeros(max(1, n), dtype=np.float64)
+        a = np.zeros(max(1, n), dtype=np.complex64)
+        _check(lib().tn_exec_copy_outputs(self.handle, plan, x.ctypes.data, a.ctypes.data))
+        return x[:n], a[:n]
+
+
+def exec_describe(handle):
+    n = C.c_size_t(0)
+    _check(lib().tn_exec_describe(handle, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().tn_exec_describe(handle, buf, C.byref(n)))
+    return json.loads(buf.value.decode())
+
+
+def exec_const_bytes(handle):
+    n = C.c_size_t(0)
+    _check(lib().tn_exec_const_bytes(handle, None, C.byref(n)))
+    buf = np.zeros(n.value, dtype=np.uint8)
+    _check(lib().tn_exec_const_bytes(handle, buf.ctypes.data, C.byref(n)))
+    return buf
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False):
+    return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0)
+
+
+def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):
+    """Schedule without device memory: (description, staged constants)."""
+    o = opts or exec_opts()
+    need = C.c_size_t()
+    h = C.c_void_p()
+    _check(lib().tn_exec_prepare(len(plans), _handles(plans), _handles(terms), C.byref(o), None, 0,
+                                 None, C.byref(need), C.byref(h)))
+    try:
+        return exec_describe(h), exec_const_bytes(h)
+    finally:
+        lib().tn_exec_destroy(h)
+
+
+def tn_exec_prepare(plans: Sequence[Plan], terms: Sequence[Terms], opts=None, stream=None) -> Exec:
+    """Allocate the workspace with torch on the current device and prepare."""
+    import torch
+    o = opts or exec_opts()
+    need = C.c_size_t()
+    _check(lib().tn_exec_prepare(len(plans), _handles(plans), _handles(terms), C.byref(o), None, 0,
+                                 None, C.byref(need), None))
+    ws = torch.empty(max(256, need.value), dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    _check(lib().tn_exec_prepare(len(plans), _handles(plans), _handles(terms), C.byref(o),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                 C.byref(need), C.byref(h)))
+    return Exec(h, list(plans), list(terms), ws, need.value)
+
+
+def tn_plan_workspace(plans: Sequence[Plan], terms: Sequence[Terms]) -> int:
+    need = C.c_size_t()
+    _check(lib().tn_plan_workspace(len(plans), _handles(plans), _handles(terms), C.byref(need)))
+    return need.value
+
+
+def tn_estimate(plans: Sequence[Plan], terms: Sequence[Terms], stream=None) -> List[dict]:
+    import torch
+    need = tn_plan_workspace(plans, terms)
+    ws = torch.empty(max(256, need), dtype=torch.uint8, device="cuda")
+    res = (tn_result * len(plans))()
+    _check(lib().tn_estimate(len(plans), _handles(plans), _handles(terms), C.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream_ptr(stream), res))
+    return [r.as_dict() for r in res]
+
+
+def tn_contract_batch(plans: Sequence[Plan], terms: Sequence[Terms], first: int, count: int,
+                      stream=None):
+    """Amplitudes a_t (complex64) of terms [first, first+count) per plan, as a
+    torch tensor of shape (len(plans), count)."""
+    import torch
+    need = tn_plan_workspace(plans, terms)
+    ws = torch.empty(max(256, need), dtype=torch.uint8, device="cuda")
+    amp = torch.zeros((len(plans), max(1, count)), dtype=torch.complex64, device="cuda")
+    _check(lib().tn_contract_batch(len(plans), _handles(plans), _handles(terms), first, count,
+                                   C.c_void_p(amp.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_ptr(stream)))
+    return amp[:, :count]
+
+
+# ---------------------------------------------------------------------------
+# kernel-level entry points (include/tn_kernels.h), for numerical tests
+# ---------------------------------------------------------------------------
+def _kernel_lib():
+    L = lib()
+    if not getattr(L, "_kernel_sigs", False):
+        vp = C.c_void_p
+        L.tn_kernel_gemm.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, vp]
+        L.tn_kernel_gemm.restype = C.c_int
+        L.tn_kernel_permute.argtypes = [C.c_int32, vp, vp, C.c_int64, C.c_int32, vp, vp]
+        L.tn_kernel_permute.restype = C.c_int
+        L._kernel_sigs = True
+    return L
+
+
+def kernel_gemm(A, B, C_out, m_log, n_log, k_log, transA=0, transB=0, ia=None, ib=None,
+                tile_hint=-1, stream=None):
+    """torch complex64/complex128 tensors on the GPU; returns the kernel class."""
+    import torch
+    fp64 = 1 if A.dtype == torch.complex128 else 0
+    n_inst = C_out.shape[0]
+    rc = _kernel_lib().tn_kernel_gemm(
+        fp64, C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(C_out.data_ptr()),
+        C.c_void_p(ia.data_ptr()) if ia is not None else None,
+        C.c_void_p(ib.data_ptr()) if ib is not None else None,
+        A[0].numel(), B[0].numel(), m_log, n_log, k_log, transA, transB, n_inst, tile_hint,
+        _stream_ptr(stream))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def kernel_permute(src, dst, r, perm, stream=None):
+    import torch
+    fp64 = 1 if src.dtype == torch.complex128 else 0
+    p = np.ascontiguousarray(perm, dtype=np.int32)
+    _check(_kernel_lib().tn_kernel_permute(fp64, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                           src.shape[0], r, p.ctypes.data if r else None,
+                                           _stream_ptr(stream)))

@@ -1,0 +1,168 @@
+"""Host replay of a prepared device schedule (test infrastructure).
+
+Executes, with numpy, exactly the launch list the library would enqueue
+(permutations through their tables, gathered batched GEMMs through their
+instance maps, finalize, level sums), on the constant bytes the library would
+upload.  This checks the planner and the schedule builder on a machine without
+a GPU; it shares no code with the oracle and does not replace the GPU parity
+tests, which run the kernels themselves.
+"""
+import numpy as np
+
+
+class Sim:
+    def __init__(self, desc, const_bytes):
+        self.desc = desc
+        self.const = np.array(const_bytes, dtype=np.uint8, copy=True)
+        extra = max(0, desc["const_bytes"] - self.const.size)
+        if extra:
+            self.const = np.concatenate([self.const, np.zeros(extra, np.uint8)])
+        self.work = np.zeros(max(256, desc["work_bytes"]), dtype=np.uint8)
+
+    def region(self, ref):
+        return self.const if ref[0] == 0 else self.work
+
+    def view(self, ref, dtype, count, extra_off=0):
+        buf = self.region(ref)
+        off = ref[1] + extra_off
+        nbytes = np.dtype(dtype).itemsize * count
+        assert off >= 0 and off + nbytes <= buf.size, ("out of bounds", ref, count, buf.size)
+        return buf[off:off + nbytes].view(dtype)
+
+    def cview(self, off, dtype, count):
+        return self.view([0, off], dtype, count)
+
+    def perm(self, L):
+        dt = np.complex128 if L["fp64"] else np.complex64
+        r, tb, n = L["r"], L["tb"], L["n_inst"]
+        tsize = 1 << tb
+        table = self.view(L["table"], np.int32, 3 * tsize)
+        ld_in, ld_pos, st_out = table[:tsize], table[tsize:2 * tsize], table[2 * tsize:]
+        size = 1 << r
+        src = self.view(L["a"], dt, n * size).reshape(n, size)
+        dst = self.view(L["c"], dt, n * size).reshape(n, size)
+        nh = r - tb
+        hs = np.arange(1 << nh, dtype=np.int64)
+        in_base = np.zeros_like(hs)
+        out_base = np.zeros_like(hs)
+        for i in range(nh):
+            bit = (hs >> i) & 1
+            in_base |= bit << L["high_in"][i]
+            out_base |= bit << L["high_out"][i]
+        # tile element e sits at LDS position e; loads put src[in_base+ld_in[l]] at ld_pos[l]
+        lds_src = np.empty(tsize, dtype=np.int64)
+        lds_src[ld_pos] = ld_in
+        in_idx = (in_base[:, None] + lds_src[None, :]).reshape(-1)
+        out_idx = (out_base[:, None] + st_out[None, :].astype(np.int64)).reshape(-1)
+        assert in_idx.min() >= 0 and in_idx.max() < size and out_idx.max() < size
+        assert np.unique(out_idx).size == size
+        tmp = np.empty_like(src)
+        tmp[:, out_idx] = src[:, in_idx]
+        dst[...] = tmp
+
+    def gemm(self, L, c_extra=0):
+        dt = np.complex128 if L["fp64"] else np.complex64
+        m, n, k = 1 << L["m_log"], 1 << L["n_log"], 1 << L["k_log"]
+        ni = L["n_inst"]
+
+        def idx(mode, ref):
+            if mode == 0:
+                return np.arange(ni)
+            if mode == 1:
+                return np.zeros(ni, dtype=np.int64)
+            return self.view(ref, np.int32, ni).astype(np.int64)
+        ia, ib = idx(L["ia_mode"], L["ia"]), idx(L["ib_mode"], L["ib"])
+        na, nb = int(ia.max()) + 1, int(ib.max()) + 1
+        A = self.view(L["a"], dt, na * L["strideA"]).reshape(na, L["strideA"])[:, :m * k]
+        B = self.view(L["b"], dt, nb * L["strideB"]).reshape(nb, L["strideB"])[:, :k * n]
+        A = A.reshape(na, k, m).transpose(0, 2, 1) if L["transA"] else A.reshape(na, m, k)
+        B = B.reshape(nb, n, k).transpose(0, 2, 1) if L["transB"] else B.reshape(nb, k, n)
+        Cv = self.view(L["c"], dt, ni * m * n, c_extra).reshape(ni, m, n)
+        Cv[...] = np.matmul(A[ia].astype(np.complex128), B[ib].astype(np.complex128)).astype(dt)
+
+    def finalize(self, L, root_refs, root64_refs):
+        nt, ncl = L["n_terms"], L["n_clusters"]
+        live = self.cview(L["live_index"], np.int32, max(1, nt))[:nt]
+        nlive = int((live >= 0).sum())
+        ridx = self.cview(L["root_idx"], np.int32, max(1, nlive * ncl))[:nlive * ncl].reshape(nlive, ncl) \
+            if nlive else np.zeros((0, ncl), np.int32)
+        w = self.cview(L["w"], np.float64, max(1, nt))[:nt]
+        x = self.cview(L["x_out"], np.float64, max(1, nt))
+        amp = self.cview(L["amp_out"], np.complex64, max(1, nt))
+        sc = complex(*L["scalar"])
+        for t in range(nt):
+            li = live[t]
+            if li < 0:
+                x[t] = 0
+                amp[t] = 0
+                continue
+            a = sc
+            for c in range(ncl):
+                j = int(ridx[li, c])
+                if t == L["zero_term"]:
+                    a *= complex(self.view(root64_refs[c], np.complex128, j + 1)[j])
+                else:
+                    a *= complex(self.view(root_refs[c], np.complex64, j + 1)[j])
+            x[t] = w[t] * abs(a) ** 2
+            amp[t] = a
+
+    def level_sum(self, L):
+        n_levels = L["n_levels"]
+        starts = self.cview(L["starts"], np.int64, n_levels + 1)
+        x = self.cview(L["x_out"], np.float64, int(starts[-1]) if starts[-1] else 1)
+        out = self.cview(L["sums"], np.float64, 2 * n_levels)
+        for u in range(n_levels):
+            seg = x[starts[u]:starts[u + 1]]
+            out[2 * u] = float(np.sum(seg.astype(np.float64)))
+            out[2 * u + 1] = 0.0
+
+    def slot_fill(self, L, term):
+        n = L["n"]
+        noise = self.cview(L["noise"], np.int32, max(1, n))[:n]
+        dst = self.cview(L["dst"], np.int64, max(1, n))[:n]
+        N = L["n_noise"]
+        bank = self.cview(L["bank"], np.float32, N * 32 + 8)
+        pat = self.cview(L["pattern"], np.int8, (term + 1) * N)
+        for i in range(n):
+            s = int(noise[i])
+            ch = int(pat[term * N + s])
+            self.view([0, int(dst[i])], np.float32, 8)[:] = bank[(s * 4 + ch) * 8:(s * 4 + ch) * 8 + 8]
+
+    def run(self, live_terms_per_plan=None):
+        d = self.desc
+        batch = [L for L in d["launches"] if L["phase"] == "batch"]
+        plain = [L for L in d["launches"] if L["phase"] == "plain"]
+        tail = [L for L in d["launches"] if L["phase"] == "tail"]
+        for L in batch:
+            self.exec(L)
+        if d["mode"] == 1:
+            for t in range(d["plain_terms"]):
+                term = live_terms_per_plan[0][t]
+                for L in plain:
+                    if L["kind"] == 4:
+                        self.slot_fill(L, term)
+                    elif L["kind"] == 1 and L.get("plain_root"):
+                        self.gemm(L, c_extra=8 * t)
+                    else:
+                        self.exec(L)
+        for L in tail:
+            pe = d["plans"][L["plan"]]
+            if L["kind"] == 2:
+                self.finalize(L, pe["root32"], pe["root64"])
+            elif L["kind"] == 3:
+                self.level_sum(L)
+
+    def exec(self, L):
+        if L["kind"] == 0:
+            self.perm(L)
+        elif L["kind"] == 1:
+            self.gemm(L)
+        else:
+            raise AssertionError(L["kind"])
+
+    def outputs(self, plan=0):
+        pe = self.desc["plans"][plan]
+        n = pe["n_terms"]
+        x = self.cview(pe["x_out"], np.float64, max(1, n))[:n].copy()
+        amp = self.cview(pe["amp_out"], np.complex64, max(1, n))[:n].copy()
+        return x, amp

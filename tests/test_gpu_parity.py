@@ -1,0 +1,209 @@
+"""GPU parity tests: the HIP kernels against numpy references, and the full
+estimate through the C ABI against the FP64 oracle.
+
+Tolerances.  Term networks are contracted in complex64 with FP32 MFMA
+accumulation: an inner product of length k carries a relative rounding error
+of order sqrt(k) * 6e-8 per step, so per-term values are compared at 2e-5
+relative (plus an absolute floor below the smallest term that matters).  The
+all-dominant term is recomputed in FP64 and compared at 1e-12.  Level sums
+A(l) must match the oracle within 1e-6 relative (the FP32 error of the
+correction terms is scaled by their small share of the total).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import estimate, network
+from paper_2211_17028_amd import tn
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    tn.lib()
+    return t
+
+
+def crandn(rng, shape, dtype):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+GEMM_CASES = [
+    # m_log, n_log, k_log, transA, transB, n_inst, gathered
+    (7, 6, 3, 0, 0, 1, False), (5, 4, 0, 0, 0, 3, False), (8, 7, 5, 1, 0, 2, True),
+    (6, 5, 10, 0, 1, 2, True), (10, 6, 2, 1, 1, 4, True), (7, 10, 13, 0, 0, 3, True),
+    (5, 5, 7, 0, 0, 5, True), (3, 2, 2, 0, 0, 7, True), (10, 1, 2, 1, 0, 2, False),
+    (0, 3, 4, 0, 1, 3, True), (0, 0, 12, 0, 0, 4, True), (1, 1, 10, 1, 1, 2, False),
+    (4, 9, 6, 0, 0, 2, False), (6, 6, 6, 1, 1, 9, True),
+]
+
+
+@pytest.mark.parametrize("case", GEMM_CASES)
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_gemm_kernels_against_numpy(torch, case, dtype):
+    m_log, n_log, k_log, ta, tb, ni, gathered = case
+    print(f"gemm case {case} {dtype}", flush=True)
+    rng = np.random.default_rng(hash(case) % 2 ** 31)
+    m, n, k = 1 << m_log, 1 << n_log, 1 << k_log
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    na, nb = (3, 2) if gathered else (ni, ni)
+    A = crandn(rng, (na, m * k), npdt)
+    B = crandn(rng, (nb, k * n), npdt)
+    ia = rng.integers(0, na, ni).astype(np.int32) if gathered else np.arange(ni, dtype=np.int32)
+    ib = rng.integers(0, nb, ni).astype(np.int32) if gathered else np.arange(ni, dtype=np.int32)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.zeros((ni, m * n), dtype=tdt, device="cuda")
+    dia = torch.from_numpy(ia).cuda() if gathered else None
+    dib = torch.from_numpy(ib).cuda() if gathered else None
+    kc = tn.kernel_gemm(dA, dB, dC, m_log, n_log, k_log, ta, tb, dia, dib)
+    torch.cuda.synchronize()
+    Am = A.reshape(na, k, m).transpose(0, 2, 1) if ta else A.reshape(na, m, k)
+    Bm = B.reshape(nb, n, k).transpose(0, 2, 1) if tb else B.reshape(nb, k, n)
+    ref = np.matmul(Am[ia].astype(np.complex128), Bm[ib].astype(np.complex128)).reshape(ni, m * n)
+    got = dC.cpu().numpy()
+    tol = (2e-6 if dtype == "c64" else 1e-13) * math.sqrt(k) * 4
+    err = np.max(np.abs(got - ref)) / max(1.0, math.sqrt(k))
+    assert err < tol, (kc, err)
+
+
+@pytest.mark.parametrize("r", [0, 1, 3, 5, 6, 9, 12])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_permute_kernel_is_exact(torch, r, dtype):
+    print(f"permute r={r} {dtype}", flush=True)
+    rng = np.random.default_rng(100 + r)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    ni = 3
+    x = crandn(rng, (ni, 1 << r), npdt)
+    for trial in range(3):
+        perm = rng.permutation(r).astype(np.int32)
+        src = torch.from_numpy(x).cuda()
+        dst = torch.zeros_like(src)
+        tn.kernel_permute(src, dst, r, perm)
+        torch.cuda.synchronize()
+        t = x.reshape((ni,) + (2,) * r)
+        axes = [0] + [1 + (r - 1 - perm[r - 1 - a]) for a in range(r)]
+        ref = np.transpose(t, axes).reshape(ni, -1)
+        assert np.array_equal(dst.cpu().numpy(), ref)
+
+
+def run_gpu(circ, level, mode=tn.TN_MODE_BATCHED, graph=False, fp64=True):
+    plan = tn.tn_plan_build(circ, level)
+    terms = tn.tn_terms_enumerate(plan, level)
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(mode=mode, use_graph=graph, fp64_level0=fp64))
+    res = ex.run()[0]
+    x, _ = ex.values()
+    pat, w = terms.get()
+    return res, x, pat, ex
+
+
+def grouped_by_positions(pat, x):
+    out = {}
+    for row, v in zip(pat, x):
+        key = tuple(i for i, c in enumerate(row) if c)
+        out[key] = out.get(key, 0.0) + v
+    return out
+
+
+def assert_terms_close(x_gpu, x_ref, pat, degenerate, rtol=2e-5, atol=1e-12):
+    if degenerate:
+        g1, g2 = grouped_by_positions(pat, x_gpu), grouped_by_positions(pat, x_ref)
+        for k in g2:
+            assert abs(g1[k] - g2[k]) <= rtol * abs(g2[k]) + atol, (k, g1[k], g2[k])
+    else:
+        err = np.abs(x_gpu - x_ref)
+        bad = err > rtol * np.abs(x_ref) + atol
+        assert not bad.any(), (np.flatnonzero(bad)[:5], x_gpu[bad][:5], x_ref[bad][:5])
+
+
+@pytest.mark.parametrize("level", [1, 2, 4])
+def test_config1_against_oracle(torch, level):
+    print(f"config1 level {level}", flush=True)
+    c = W.config(1, level=level)
+    res, x, pat, _ = run_gpu(c, level)
+    ref = estimate.estimate(c, level, "network")
+    assert [tuple(p) for p in pat] == ref["terms"]
+    assert abs(x[0] - ref["X"][0]) <= 1e-12 * ref["X"][0]          # FP64 dominant term
+    assert_terms_close(x, ref["X"], pat, degenerate=False)
+    for u in range(level + 1):
+        assert abs(res["A"][u] - ref["A"][u]) <= 1e-6 * ref["A"][u], (u, res["A"][u], ref["A"][u])
+        assert abs(res["T"][u] - ref["T"][u]) <= 2e-5 * abs(ref["T"][u]) + 1e-12
+    if level == 4:
+        from oracle import dense
+        f = dense.exact_value(c)
+        assert abs(res["A"][4] - f) <= 1e-6 * f
+
+
+@pytest.mark.parametrize("seed,kind,target,n,gates,noise", [
+    (1, "random", "circuit_output", 5, 30, 4), (2, "adpd", "product", 4, 24, 5),
+    (3, "depol", "dense", 5, 30, 4), (4, "random", "product", 6, 40, 3),
+    (5, "adpd", "circuit_output", 7, 50, 6)])
+def test_tiny_circuits_against_oracle(torch, seed, kind, target, n, gates, noise):
+    print(f"tiny {seed} {kind} {target}", flush=True)
+    c = W.tiny_random_circuit(np.random.default_rng(seed), n, gates, noise, noise=kind, level=3,
+                              target=target)
+    res, x, pat, _ = run_gpu(c, 3)
+    ref = estimate.estimate(c, 3, "network")
+    assert_terms_close(x, ref["X"], pat, degenerate=(kind == "depol"), atol=1e-10)
+    for u in range(4):
+        assert abs(res["A"][u] - ref["A"][u]) <= 1e-6 * abs(ref["A"][u]) + 1e-12
+
+
+def test_plain_mode_equals_batched(torch):
+    c = W.config(1, level=2)
+    rb, xb, pat, _ = run_gpu(c, 2)
+    rp, xp, _, _ = run_gpu(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
+    assert np.allclose(xb[1:], xp[1:], rtol=1e-5, atol=1e-12)
+    assert abs(rb["A"][2] - rp["A"][2]) <= 1e-6 * rb["A"][2]
+
+
+def test_graph_replays_match_eager_and_are_deterministic(torch):
+    c = W.config(1, level=2)
+    plan = tn.tn_plan_build(c, 2)
+    terms = tn.tn_terms_enumerate(plan, 2)
+    eager = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False)).run()[0]
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True))
+    for rep in range(4):
+        r = ex.run()[0]
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()      # eager work between replays
+        assert r["A"] == eager["A"], (rep, r["A"], eager["A"])
+        assert r["T"] == eager["T"]
+
+
+def test_config2_full_size_sampled_terms(torch):
+    """5x5 grid, 12 layers, 10 depolarizing noises, level 2 (436 terms): every
+    term on the GPU; a sample of position sets against the oracle one by one
+    (depolarizing corrections are degenerate, so sums over each position set
+    are compared)."""
+    print("config2 full size", flush=True)
+    c = W.config(2)
+    res, x, pat, _ = run_gpu(c, 2)
+    assert res["n_terms"] == 436
+    assert np.all(x >= 0)
+    assert res["A"][0] <= res["A"][1] <= res["A"][2] <= 1.0 + 1e-6
+    net = network.KetNetwork(c)
+    sp = network.slot_split(c)
+    groups = {(): [], (3,): [], (7,): [], (2, 8): []}
+    for j, row in enumerate(pat):
+        key = tuple(i for i, v in enumerate(row) if v)
+        if key in groups:
+            groups[key].append(j)
+    for key, idx in groups.items():
+        ref = sum(network.term_value(net, sp, tuple(int(v) for v in pat[j]))[0] for j in idx)
+        got = sum(x[j] for j in idx)
+        tol = 1e-12 if key == () else 2e-5
+        assert abs(got - ref) <= tol * ref + 1e-13, (key, got, ref)
+    gold = os.path.join(GOLD, "config2_oracle.txt")
+    if os.path.exists(gold):
+        vals = np.loadtxt(gold)
+        for u in range(3):
+            assert abs(res["A"][u] - vals[u]) <= 1e-6 * vals[u], (u, res["A"][u], vals[u])
