@@ -1,0 +1,182 @@
+"""Benchmark: batched term-network contraction of the level-2 approximation.
+
+Workload: 25 qubits on a 5x5 grid, 12 layers of Haar SU(2) + CZ (4-colour
+schedule), 10 single-qubit depolarizing noises (p ~ U[1e-4, 5e-3]) at seeded
+random gate locations, input |0...0>, target = the noiseless output state,
+level-2 expansion (436 term networks).  Synthetic, seeded (see workloads/).
+
+One step = one full estimate (every term network contracted, FP64 dominant
+term, per-term values, level sums) with the plan and its schedule prepared
+and all inputs resident in HBM.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "term-network contractions/s and time-to-estimate at |err|<=1e-6, batched vs plain"
+FP32_MFMA_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(circ, level, budget_s):
+    """The oracle as it stands, timed on the host on a seeded sample of the
+    same term set: one FP64 network contraction per term."""
+    import numpy as np
+    from oracle import network, terms as oterms
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = 1
+    tl = oterms.enumerate_terms(circ.n_noises, level)
+    rng = np.random.default_rng(2211170280)
+    order = rng.permutation(len(tl))
+    t0 = time.perf_counter()
+    net = network.KetNetwork(circ)
+    sp = network.slot_split(circ)
+    setup = time.perf_counter() - t0
+    done = 0
+    t1 = time.perf_counter()
+    for j in order:
+        network.term_value(net, sp, tl[j])
+        done += 1
+        if time.perf_counter() - t1 > budget_s:
+            break
+    el = time.perf_counter() - t1
+    return {"value": done / el, "unit": "contractions/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} of {len(tl)} terms of the same workload, seeded random order, "
+                      f"{el:.1f} s of contraction after {setup:.1f} s of network setup; one FP64 "
+                      f"ket-network contraction per term (numpy tensordot, greedy order)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "
+              f"shard across GPUs with one all-reduce of the level sums, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2211_17028_amd import tn
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    circ = W.config(2)
+    level = circ.level
+    t0 = time.perf_counter()
+    plan = tn.tn_plan_build(circ, level)
+    plan_s = time.perf_counter() - t0
+    terms = tn.tn_terms_enumerate(plan, level)
+    t0 = time.perf_counter()
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=not args.no_graph, time_kernels=True))
+    prep_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        res = ex.run()[0]
+    ex.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ex.run()[0]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stats = ex.kernel_stats(reset=True)
+    n_contracted = res["n_contracted"]
+    ms_per_step = 1000.0 * el / args.steps
+    value = n_contracted * args.steps / el
+
+    # parity of the estimate against the stored oracle values
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.txt")
+    if os.path.exists(gold):
+        g = np.loadtxt(gold)
+        err = max(abs(res["A"][u] - g[u]) / abs(g[u]) for u in range(level + 1))
+
+    # dominant kernel: largest accumulated time in the timed region
+    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    if dom_name.startswith("k_permute"):
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    else:
+        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS}
+    roof.update({"kernel": dom_name, "launches_per_step": dom["launches"] / args.steps,
+                 "avg_launch_us": 1000.0 * dom["ms"] / dom["launches"],
+                 "algorithmic_per_launch": (dom["flops"] if roof["bound"] == "mfma" else dom["bytes"])
+                 / dom["launches"], "traffic": None})
+    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                   "tflops": v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12,
+                   "gbs": v["bytes"] / max(1e-9, v["ms"] * 1e-3) / 1e9}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+
+    plain = None
+    if not args.no_plain:
+        exp = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(mode=tn.TN_MODE_PLAIN, use_graph=False,
+                                                                fp64_level0=False))
+        exp.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp = exp.run()[0]
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        plain = {"value": rp["n_contracted"] / pel, "ms_per_estimate": 1000 * pel,
+                 "speedup_batched_vs_plain": (rp["n_contracted"] / pel and value / (rp["n_contracted"] / pel))}
+        del exp
+
+    cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
+    info = plan.info()
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "contractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "time_to_estimate_ms": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "dtype_detail": "complex64 term contractions on FP32 MFMA; complex128 all-dominant term; FP64 sums",
+        "data": "synthetic",
+        "config": {"workload": "grid5x5_12L_10depol_level2", "qubits": 25, "layers": 12, "noises": 10,
+                   "level": level, "terms": res["n_terms"], "contracted": n_contracted,
+                   "graph": not args.no_graph},
+        "err_vs_oracle": err,
+        "A": res["A"],
+        "paper_unit_value": 2 * value,
+        "plan_s": plan_s,
+        "prepare_s": prep_s,
+        "flops_per_estimate": sum(v["flops"] for v in stats.values()) / args.steps,
+        "flops_per_term_plain": info["flops_per_term"],
+        "roofline": roof,
+        "kernels": kernels,
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -116,7 +116,21 @@ typedef struct {
     int32_t fp64_level0;     /* 1 = recompute the all-dominant term in FP64
                                 (tn_estimate always does) */
     int32_t tune;            /* 1 = pick GEMM tiles by timing (autotuner) */
+    int32_t time_kernels;    /* 1 = HIP events around every batched GEMM / permute
+                                launch, accumulated per kernel (tn_exec_kernel_stats) */
 } tn_exec_opts;
+
+/* Accumulated per-kernel timing of the runs since the last reset (needs
+ * time_kernels).  flops / bytes are the algorithmic work of those launches
+ * (8 real flops per complex MAC; operand + result bytes; permute: read +
+ * write). */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double ms;
+    double flops;
+    double bytes;
+} tn_kernel_stat;
 
 /* Per-circuit result of an estimate (host struct, filled by the library). */
 typedef struct {
@@ -196,6 +210,10 @@ int tn_exec_run(tn_exec ex, void* stream, tn_result* results);
  * packed plans in order) and to the per-term amplitudes a_t (complex64 pairs),
  * valid after tn_exec_run. */
 int tn_exec_outputs(tn_exec ex, const double** d_x, const float** d_amp, int64_t* n_total);
+
+/* Fill up to `max` entries of per-kernel statistics; *n receives the count.
+ * reset != 0 clears the accumulators after reading. */
+int tn_exec_kernel_stats(tn_exec ex, int32_t max, tn_kernel_stat* out, int32_t* n, int32_t reset);
 
 /* Copy the per-term values X_t (float64) and amplitudes a_t (complex64 as
  * float pairs) of packed plan `plan` to host memory (n_terms entries each;

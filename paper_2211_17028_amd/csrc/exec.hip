@@ -118,6 +118,7 @@ struct Launch {
     // slot fill
     SlotFillArgs sf{};
     Ref sf_noise, sf_dst, sf_bank, sf_pattern;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // per-launch timing (optional)
 };
 
 struct PlanExec {
@@ -149,9 +150,12 @@ struct tn_exec_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only to record the graph
     double last_ms = -1, gemm_ms = -1, perm_ms = -1, other_ms = -1;
-    std::vector<std::pair<int, int>> plain_fill;   // unused placeholder
     int64_t plain_terms = 0;
+    int time_kernels = 0;
+    std::map<int, std::pair<int64_t, double>> kstat;  // kernel id -> (launches, ms) accumulated
+    std::map<int, double> kflops, kbytes;             // kernel id -> algorithmic work accumulated
     bool bound = false;
 };
 
@@ -227,6 +231,7 @@ struct Builder {
         Launch L;
         L.kind = L_PERM;
         L.fp64 = fp64;
+        L.kclass = fp64 ? K_PERM64 : K_PERM32;
         L.table = Ref{R_CONST, ex->cbuf.add(table.data(), (int64_t)table.size() * 4)};
         L.p.r = r;
         L.p.tb = tt;
@@ -397,6 +402,7 @@ struct Builder {
                 pl.c = Ref{R_WORK, off};
                 pl.p.n_inst = (int64_t)X.keys.size();
                 pl.bytes = 2.0 * nb;
+                pl.kclass = fp64 ? K_PERM64 : K_PERM32;
                 pl.plan = plan_index;
                 out->push_back(pl);
                 *op = pl.c;
@@ -452,6 +458,7 @@ struct Builder {
             gl.bytes = (double)esz * (ninst * mm * nnn + (double)A.keys.size() * mm * kk +
                                       (double)B.keys.size() * kk * nnn);
             if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
+            gl.kclass = select_gemm(gl.g, fp64, -1);
             out->push_back(gl);
             for (auto& t : temps) work.release(t.first, t.second);
             if (!A.leaf) work.release(A.buf.off, A.bytes);
@@ -687,7 +694,7 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
     if ((L.kind == L_GEMM && L.g.n_inst == 0) || (L.kind == L_PERM && L.p.n_inst == 0)) return;
     switch (L.kind) {
     case L_GEMM:
-        L.kclass = L.fp64 ? launch_gemm_c128(L.g, s) : launch_gemm_c64(L.g, s, L.tile_hint);
+        launch_gemm_id(L.kclass, L.g, s);
         break;
     case L_PERM:
         if (L.fp64) launch_permute_c128(L.p, s);
@@ -707,7 +714,11 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
 }
 
 static void run_body(tn_exec_s* ex, hipStream_t s) {
-    for (auto& L : ex->launches) enqueue(ex, L, s);
+    for (auto& L : ex->launches) {
+        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, s));
+        enqueue(ex, L, s);
+        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, s));
+    }
     if (ex->opts.mode == TN_MODE_PLAIN) {
         for (int64_t t = 0; t < ex->plain_terms; ++t) {
             for (auto& L : ex->plain_launches) {
@@ -745,7 +756,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
                << ",\"strideA\":" << L.g.strideA << ",\"strideB\":" << L.g.strideB
                << ",\"a\":[" << L.a.region << "," << L.a.off << "],\"b\":[" << L.b.region << "," << L.b.off
                << "],\"c\":[" << L.c.region << "," << L.c.off << "],\"ia\":[" << L.ia.region << "," << L.ia.off
-               << "],\"ib\":[" << L.ib.region << "," << L.ib.off << "],\"kclass\":" << L.kclass;
+               << "],\"ib\":[" << L.ib.region << "," << L.ib.off << "],\"kernel\":\"" << kernel_name(L.kclass) << "\"";
         if (L.kind == L_PERM)
             os << ",\"r\":" << L.p.r << ",\"tb\":" << L.p.tb << ",\"n_inst\":" << L.p.n_inst << ",\"a\":["
                << L.a.region << "," << L.a.off << "],\"c\":[" << L.c.region << "," << L.c.off << "],\"table\":["
@@ -923,6 +934,12 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
         bind(ex.get());
+        if (ex->opts.time_kernels)
+            for (auto& L : ex->launches)
+                if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0)) {
+                    HIPCHK(hipEventCreate(&L.ev_a));
+                    HIPCHK(hipEventCreate(&L.ev_b));
+                }
         HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
                               ex->stream));
         HIPCHK(hipEventCreate(&ex->ev0));
@@ -941,9 +958,12 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         HIPCHK(hipEventRecord(ex->ev0, s));
         if (ex->opts.use_graph) {
             if (!ex->gexec) {
-                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                run_body(ex, s);
-                HIPCHK(hipStreamEndCapture(s, &ex->graph));
+                // record on a private stream (the caller's may be the null
+                // stream, which cannot be captured); launch on the caller's
+                if (!ex->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ex->cap_stream, hipStreamNonBlocking));
+                HIPCHK(hipStreamBeginCapture(ex->cap_stream, hipStreamCaptureModeThreadLocal));
+                run_body(ex, ex->cap_stream);
+                HIPCHK(hipStreamEndCapture(ex->cap_stream, &ex->graph));
                 HIPCHK(hipGraphInstantiate(&ex->gexec, ex->graph, nullptr, nullptr, 0));
             }
             HIPCHK(hipGraphLaunch(ex->gexec, s));
@@ -955,6 +975,16 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, ex->ev0, ex->ev1));
         ex->last_ms = ms;
+        for (auto& L : ex->launches)
+            if (L.ev_a) {
+                float dt = 0;
+                HIPCHK(hipEventElapsedTime(&dt, L.ev_a, L.ev_b));
+                auto& st = ex->kstat[L.kclass];
+                st.first += 1;
+                st.second += dt;
+                ex->kflops[L.kclass] += L.flops;
+                ex->kbytes[L.kclass] += L.bytes;
+            }
         if (!results) return;
         for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
             const PlanExec& pe = ex->plans[pi];
@@ -1023,6 +1053,32 @@ int tn_exec_outputs(tn_exec exh, const double** d_x, const float** d_amp, int64_
     });
 }
 
+int tn_exec_kernel_stats(tn_exec exh, int32_t max, tn_kernel_stat* out, int32_t* n, int32_t reset) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !n) fail(TN_EINVAL, "null handle");
+        int32_t i = 0;
+        for (auto& kv : ex->kstat) {
+            if (out && i < max) {
+                tn_kernel_stat& k = out[i];
+                std::memset(&k, 0, sizeof(k));
+                std::strncpy(k.name, kernel_name(kv.first), sizeof(k.name) - 1);
+                k.launches = kv.second.first;
+                k.ms = kv.second.second;
+                k.flops = ex->kflops[kv.first];
+                k.bytes = ex->kbytes[kv.first];
+            }
+            ++i;
+        }
+        *n = i;
+        if (reset) {
+            ex->kstat.clear();
+            ex->kflops.clear();
+            ex->kbytes.clear();
+        }
+    });
+}
+
 int tn_exec_copy_outputs(tn_exec exh, int32_t plan, double* h_x, float* h_amp) {
     return guard([&] {
         tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
@@ -1074,6 +1130,11 @@ void tn_exec_destroy(tn_exec exh) {
     if (ex->graph) (void)hipGraphDestroy(ex->graph);
     if (ex->ev0) (void)hipEventDestroy(ex->ev0);
     if (ex->ev1) (void)hipEventDestroy(ex->ev1);
+    if (ex->cap_stream) (void)hipStreamDestroy(ex->cap_stream);
+    for (auto& L : ex->launches) {
+        if (L.ev_a) (void)hipEventDestroy(L.ev_a);
+        if (L.ev_b) (void)hipEventDestroy(L.ev_b);
+    }
     delete ex;
 }
 

@@ -37,11 +37,24 @@ struct PermArgs {
 
 enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3 };
 
-// FP32 complex GEMM dispatch; returns the kernel class used.  tile_hint < 0
-// picks by shape; otherwise a tile index from the autotuner.
+// Kernel ids: 0..K_MFMA_TILES-1 = FP32 MFMA GEMM tile configurations,
+// then the other variants.  The choice is a pure function of the shape (and
+// of the tile hint for MFMA), so it is fixed when a schedule is prepared.
+enum KernelId {
+    K_MFMA_TILES = 6,
+    K_SMALL32 = 10, K_SPLITK32 = 11,
+    K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
+    K_PERM32 = 30, K_PERM64 = 31,
+};
+int select_gemm(const GemmArgs& g, int fp64, int tile_hint);
+bool mfma_tile_fits(int tile, const GemmArgs& g);
+void launch_gemm_id(int id, const GemmArgs& g, hipStream_t s);
+const char* kernel_name(int id);
+int kernel_class(int id);
+
+// FP32 / FP64 complex GEMM dispatch by shape; returns the kernel id.
 int launch_gemm_c64(const GemmArgs& g, hipStream_t s, int tile_hint);
 int launch_gemm_c128(const GemmArgs& g, hipStream_t s);
-int gemm_c64_num_tiles(const GemmArgs& g);
 
 void launch_permute_c64(const PermArgs& p, hipStream_t s);
 void launch_permute_c128(const PermArgs& p, hipStream_t s);

@@ -401,13 +401,45 @@ static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) /
 struct TileCfg {
     int bm, bnc;
 };
-static const TileCfg kTiles[] = {{128, 64}, {64, 64}, {128, 32}, {64, 32}, {32, 32}, {32, 16}};
-static const int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+static const TileCfg kTiles[K_MFMA_TILES] = {{128, 64}, {64, 64}, {128, 32}, {64, 32}, {32, 32}, {32, 16}};
 
-int gemm_c64_num_tiles(const GemmArgs&) { return kNumTiles; }
+bool mfma_tile_fits(int tile, const GemmArgs& g) {
+    if (tile < 0 || tile >= K_MFMA_TILES) return false;
+    return g.m_log >= 5 && g.n_log >= 4 && (int64_t(1) << g.m_log) >= kTiles[tile].bm &&
+           (int64_t(1) << g.n_log) >= kTiles[tile].bnc;
+}
 
-static bool tile_fits(const TileCfg& t, const GemmArgs& g) {
-    return (int64_t(1) << g.m_log) >= t.bm && (int64_t(1) << g.n_log) >= t.bnc;
+int select_gemm(const GemmArgs& g, int fp64, int tile_hint) {
+    const int mn_log = g.m_log + g.n_log;
+    if (mn_log <= 4 && g.k_log >= 8) return fp64 ? K_SPLITK64 : K_SPLITK32;
+    if (fp64) return (g.m_log >= 6 && g.n_log >= 6) ? K_TILED64 : K_SMALL64;
+    if (mfma_tile_fits(tile_hint, g)) return tile_hint;
+    for (int i = 0; i < K_MFMA_TILES; ++i)
+        if (mfma_tile_fits(i, g)) return i;
+    return K_SMALL32;
+}
+
+const char* kernel_name(int id) {
+    static const char* mf[K_MFMA_TILES] = {"k_gemm_mfma<128,64>", "k_gemm_mfma<64,64>", "k_gemm_mfma<128,32>",
+                                           "k_gemm_mfma<64,32>", "k_gemm_mfma<32,32>", "k_gemm_mfma<32,16>"};
+    if (id >= 0 && id < K_MFMA_TILES) return mf[id];
+    switch (id) {
+    case K_SMALL32: return "k_gemm_small<float>";
+    case K_SPLITK32: return "k_gemm_splitk<float>";
+    case K_SMALL64: return "k_gemm_small<double>";
+    case K_SPLITK64: return "k_gemm_splitk<double>";
+    case K_TILED64: return "k_gemm_tiled_c128";
+    case K_PERM32: return "k_permute<float2>";
+    case K_PERM64: return "k_permute<double2>";
+    }
+    return "unknown";
+}
+
+int kernel_class(int id) {
+    if (id >= 0 && id < K_MFMA_TILES) return KC_MFMA;
+    if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
+    if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
+    return KC_TILED;
 }
 
 static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s) {
@@ -428,44 +460,44 @@ static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s)
 #undef TN_LAUNCH
 }
 
-int launch_gemm_c64(const GemmArgs& g, hipStream_t s, int tile_hint) {
+void launch_gemm_id(int id, const GemmArgs& g, hipStream_t s) {
     const int mn_log = g.m_log + g.n_log;
-    if (mn_log <= 4 && g.k_log >= 8) {
-        const int64_t blocks = g.n_inst << mn_log;
-        hipLaunchKernelGGL((k_gemm_splitk<float, float2>), dim3((unsigned)blocks), dim3(256), 0, s, g);
-        return KC_SPLITK;
-    }
-    if (g.m_log >= 5 && g.n_log >= 4) {
-        if (tile_hint >= 0 && tile_hint < kNumTiles && tile_fits(kTiles[tile_hint], g)) {
-            launch_mfma_tile(kTiles[tile_hint], g, s);
-            return KC_MFMA;
-        }
-        for (int i = 0; i < kNumTiles; ++i)
-            if (tile_fits(kTiles[i], g)) {
-                launch_mfma_tile(kTiles[i], g, s);
-                return KC_MFMA;
-            }
-    }
     const int64_t total = g.n_inst << mn_log;
-    hipLaunchKernelGGL((k_gemm_small<float, float2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
-    return KC_SMALL;
+    if (id >= 0 && id < K_MFMA_TILES) {
+        launch_mfma_tile(kTiles[id], g, s);
+        return;
+    }
+    switch (id) {
+    case K_SMALL32:
+        hipLaunchKernelGGL((k_gemm_small<float, float2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
+        return;
+    case K_SPLITK32:
+        hipLaunchKernelGGL((k_gemm_splitk<float, float2>), dim3((unsigned)total), dim3(256), 0, s, g);
+        return;
+    case K_SMALL64:
+        hipLaunchKernelGGL((k_gemm_small<double, double2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
+        return;
+    case K_SPLITK64:
+        hipLaunchKernelGGL((k_gemm_splitk<double, double2>), dim3((unsigned)total), dim3(256), 0, s, g);
+        return;
+    case K_TILED64: {
+        const int64_t tiles = (int64_t(1) << (g.m_log - 6)) << (g.n_log - 6);
+        hipLaunchKernelGGL(k_gemm_tiled_c128, dim3((unsigned)(tiles * g.n_inst)), dim3(256), 0, s, g);
+        return;
+    }
+    }
+}
+
+int launch_gemm_c64(const GemmArgs& g, hipStream_t s, int tile_hint) {
+    const int id = select_gemm(g, 0, tile_hint);
+    launch_gemm_id(id, g, s);
+    return id;
 }
 
 int launch_gemm_c128(const GemmArgs& g, hipStream_t s) {
-    const int mn_log = g.m_log + g.n_log;
-    if (mn_log <= 4 && g.k_log >= 8) {
-        const int64_t blocks = g.n_inst << mn_log;
-        hipLaunchKernelGGL((k_gemm_splitk<double, double2>), dim3((unsigned)blocks), dim3(256), 0, s, g);
-        return KC_SPLITK;
-    }
-    if (g.m_log >= 6 && g.n_log >= 6) {
-        const int64_t tiles = (int64_t(1) << (g.m_log - 6)) << (g.n_log - 6);
-        hipLaunchKernelGGL(k_gemm_tiled_c128, dim3((unsigned)(tiles * g.n_inst)), dim3(256), 0, s, g);
-        return KC_TILED;
-    }
-    const int64_t total = g.n_inst << mn_log;
-    hipLaunchKernelGGL((k_gemm_small<double, double2>), dim3(grid1(total, 256)), dim3(256), 0, s, g);
-    return KC_SMALL;
+    const int id = select_gemm(g, 1, -1);
+    launch_gemm_id(id, g, s);
+    return id;
 }
 
 template <typename T>

@@ -57,7 +57,12 @@ class tn_prune_opts(C.Structure):
 
 class tn_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
-                ("tune", C.c_int32)]
+                ("tune", C.c_int32), ("time_kernels", C.c_int32)]
+
+
+class tn_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class tn_result(C.Structure):
@@ -87,7 +92,7 @@ EXPORTS = [
     "tn_plan_build", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
-    "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
+    "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
 ]
 
 _lib = None
@@ -130,6 +135,8 @@ def lib():
     L.tn_exec_describe.argtypes = [vp, C.c_char_p, C.POINTER(C.c_size_t)]
     L.tn_exec_const_bytes.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
     L.tn_exec_copy_outputs.argtypes = [vp, C.c_int32, vp, vp]
+    L.tn_exec_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(tn_kernel_stat), C.POINTER(C.c_int32),
+                                       C.c_int32]
     L.tn_plan_destroy.argtypes = [vp]
     L.tn_terms_destroy.argtypes = [vp]
     L.tn_exec_destroy.argtypes = [vp]
@@ -291,6 +298,16 @@ class Exec:
         _check(lib().tn_exec_run(self.handle, _stream_ptr(stream), res))
         return [r.as_dict() for r in res]
 
+    def kernel_stats(self, reset=False):
+        """{kernel name: dict(launches, ms, flops, bytes)} accumulated over runs."""
+        n = C.c_int32()
+        _check(lib().tn_exec_kernel_stats(self.handle, 0, None, C.byref(n), 0))
+        arr = (tn_kernel_stat * max(1, n.value))()
+        _check(lib().tn_exec_kernel_stats(self.handle, n.value, arr, C.byref(n), 1 if reset else 0))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms,
+                                       "flops": arr[i].flops, "bytes": arr[i].bytes}
+                for i in range(n.value)}
+
     def timing(self):
         v = [C.c_double() for _ in range(4)]
         _check(lib().tn_exec_timing(self.handle, *[C.byref(x) for x in v]))
@@ -338,8 +355,9 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False):
-    return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0)
+def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False):
+    return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
+                        1 if time_kernels else 0)
 
 
 def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):
