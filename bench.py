@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "
@@ -80,14 +82,23 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     circ = W.config(2)
     level = circ.level
     t0 = time.perf_counter()
     plan = tn.tn_plan_build(circ, level)
     plan_s = time.perf_counter() - t0
     terms = tn.tn_terms_enumerate(plan, level)
+    # timed region: eager launches with a HIP event pair around every GEMM /
+    # permute launch on the launch stream (per-kernel durations for the roofline)
     t0 = time.perf_counter()
-    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=not args.no_graph, time_kernels=True))
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, time_kernels=True))
     prep_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         res = ex.run()[0]
@@ -102,6 +113,22 @@ def main():
     n_contracted = res["n_contracted"]
     ms_per_step = 1000.0 * el / args.steps
     value = n_contracted * args.steps / el
+    del ex
+    # the same schedule captured once in a hipGraph and replayed
+    graph = None
+    if not args.no_graph:
+        exg = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True))
+        for _ in range(args.warmup):
+            exg.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rg = exg.run()[0]
+        torch.cuda.synchronize()
+        gel = time.perf_counter() - t0
+        graph = {"value": n_contracted * args.steps / gel, "ms_per_step": 1000.0 * gel / args.steps,
+                 "A_equal_eager": rg["A"] == res["A"]}
+        del exg
 
     # parity of the estimate against the stored oracle values
     err = None
@@ -161,8 +188,7 @@ def main():
         "dtype_detail": "complex64 term contractions on FP32 MFMA; complex128 all-dominant term; FP64 sums",
         "data": "synthetic",
         "config": {"workload": "grid5x5_12L_10depol_level2", "qubits": 25, "layers": 12, "noises": 10,
-                   "level": level, "terms": res["n_terms"], "contracted": n_contracted,
-                   "graph": not args.no_graph},
+                   "level": level, "terms": res["n_terms"], "contracted": n_contracted},
         "err_vs_oracle": err,
         "A": res["A"],
         "paper_unit_value": 2 * value,
@@ -172,6 +198,7 @@ def main():
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
         "kernels": kernels,
+        "graph": graph,
         "plain": plain,
         "cpu_baseline": cpu,
     }

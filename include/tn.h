@@ -117,7 +117,8 @@ typedef struct {
                                 (tn_estimate always does) */
     int32_t tune;            /* 1 = pick GEMM tiles by timing (autotuner) */
     int32_t time_kernels;    /* 1 = HIP events around every batched GEMM / permute
-                                launch, accumulated per kernel (tn_exec_kernel_stats) */
+                                launch, accumulated per kernel (tn_exec_kernel_stats);
+                                needs use_graph = 0 (TN_EINVAL otherwise) */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs

@@ -911,6 +911,9 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             ex->opts.use_graph = 1;
             ex->opts.fp64_level0 = 1;
         }
+        if (ex->opts.time_kernels && ex->opts.use_graph)
+            fail(TN_EINVAL, "per-launch kernel timing needs eager launches (use_graph = 0): events "
+                            "recorded inside a captured graph cannot be timed");
         if (ex->opts.mode == TN_MODE_PLAIN) {
             ex->opts.use_graph = 0;
             if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
