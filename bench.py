@@ -57,6 +57,23 @@ def cpu_baseline(circ, level, budget_s):
                       f"ket-network contraction per term (numpy tensordot, greedy order)"}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    record (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
+    or None when there is no record or the kernel source changed since."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "traffic_grid5x5_level2.json")
+    if not os.path.exists(rec):
+        return None
+    with open(rec) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, "paper_2211_17028_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if t.get("kernel") != kernel or t.get("kernels_hip_sha256") != sha:
+        return None
+    return t["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,7 +167,8 @@ def main():
     roof.update({"kernel": dom_name, "launches_per_step": dom["launches"] / args.steps,
                  "avg_launch_us": 1000.0 * dom["ms"] / dom["launches"],
                  "algorithmic_per_launch": (dom["flops"] if roof["bound"] == "mfma" else dom["bytes"])
-                 / dom["launches"], "traffic": None})
+                 / dom["launches"], "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+                 "traffic": measured_traffic(dom_name)})
     kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "tflops": v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12,
                    "gbs": v["bytes"] / max(1e-9, v["ms"] * 1e-3) / 1e9}
