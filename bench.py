@@ -40,7 +40,7 @@ def cpu_baseline(circ, level, budget_s):
     rng = np.random.default_rng(2211170280)
     order = rng.permutation(len(tl))
     t0 = time.perf_counter()
-    net = network.KetNetwork(circ)
+    net = network.KetNetwork(circ, diagonal=True)
     sp = network.slot_split(circ)
     setup = time.perf_counter() - t0
     done = 0
@@ -54,7 +54,7 @@ def cpu_baseline(circ, level, budget_s):
     return {"value": done / el, "unit": "contractions/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{done} of {len(tl)} terms of the same workload, seeded random order, "
                       f"{el:.1f} s of contraction after {setup:.1f} s of network setup; one FP64 "
-                      f"ket-network contraction per term (numpy tensordot, greedy order)"}
+                      f"ket-network contraction per term (numpy matmul pairs, greedy order, diagonal gates as shared indices)"}
 
 
 def measured_traffic(kernel):

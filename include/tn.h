@@ -98,6 +98,10 @@ typedef struct {
     uint64_t seed;          /* path search seed (0 = fixed default) */
     int32_t no_light_cone;  /* 1 = keep gates outside the slots' light cone */
     int32_t max_log_size;   /* cap on log2(elements) of one tensor (0 = 30) */
+    int32_t no_diagonal_hyperedges;  /* 1 = give diagonal gates their own output legs
+                                        instead of sharing their wires' index */
+    double max_work_bytes;  /* cap on the complex64 live set of one cluster's path,
+                               all instances of the full level-l expansion (0 = 64 GiB) */
 } tn_plan_opts;
 
 /* Term pruning (level-2/3 candidates).  NULL = the full expansion. */
@@ -164,7 +168,7 @@ typedef struct {
  * TN_ENOTCPTP (Section II trace condition), TN_EUNSUPPORTED (multi-qubit
  * noise; the split of Section IV is defined on 4x4 superoperators),
  * TN_EDEGENERATE (d_1 >= (1 - 1e-12) d_0), TN_ETOOBIG (a cluster with more than
- * 64 slots, or a path tensor above max_log_size).
+ * 64 slots, a path tensor above max_log_size, or a live set above max_work_bytes).
  * ------------------------------------------------------------------------- */
 int tn_plan_build(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
                   int32_t level, const tn_plan_opts* opts, tn_plan* out);

@@ -15,6 +15,13 @@ the circuit's own ideal output (gates with no slot in their causal future
 cancel against their inverses in <psi_v| U^dagger U~ |psi>), and contracted
 pairwise with numpy.tensordot in a greedy order (smallest growth first, fixed
 tie-break).  The order changes rounding only.
+
+With ``diagonal=True`` a gate whose matrix is diagonal keeps the basis index
+of its wires: it becomes a tensor of its diagonal on the wires' current
+indices, which are then shared by more than two tensors.  Pairs are then
+contracted with numpy.einsum, summing an index only when no other remaining
+tensor carries it.  Same value, far smaller intermediates for CZ / RZZ
+circuits.
 """
 from __future__ import annotations
 
@@ -30,8 +37,9 @@ class KetNetwork:
     """Topology + fixed tensors of the ket network of a circuit; slot tensors
     are filled in per term."""
 
-    def __init__(self, circ, reduce: bool = True):
+    def __init__(self, circ, reduce: bool = True, diagonal: bool = False):
         self.circ = circ
+        self.diagonal = diagonal
         n = circ.n_qubits
         tensors: List[Tuple[object, list]] = []   # (array or ("slot", s), legs)
         scalar = 1.0 + 0.0j
@@ -81,6 +89,12 @@ class KetNetwork:
         for k, inverse in seq:
             op = ops[k]
             qs = list(op.qubits)
+            if diagonal and op.kind == "gate" and np.count_nonzero(op.mat - np.diag(np.diag(op.mat))) == 0:
+                dg = np.diag(op.mat)
+                dg = dg.conj() if inverse else dg
+                tensors.append((np.asarray(dg, dtype=np.complex128).reshape((2,) * len(qs)),
+                                [cur[q] for q in qs]))
+                continue
             ins = [cur[q] for q in qs]
             outs = list(range(edge, edge + len(qs)))
             edge += len(qs)
@@ -103,7 +117,10 @@ class KetNetwork:
             tensors.append((vv, [cur[q] for q in range(n)]))
         self.tensors = tensors
         self.scalar = scalar
-        self.path = greedy_path([legs for _, legs in tensors])
+        if diagonal:
+            self.path = hyper_greedy_path([legs for _, legs in tensors])
+        else:
+            self.path = greedy_path([legs for _, legs in tensors])
 
     def value(self, slot_mats) -> complex:
         """Contract with slot s set to the 2x2 matrix slot_mats[s]."""
@@ -115,6 +132,8 @@ class KetNetwork:
             else:
                 arrs.append(t)
             legs.append(list(lg))
+        if self.diagonal:
+            return self.scalar * contract_hyper(arrs, legs, self.path)
         return self.scalar * contract_path(arrs, legs, self.path)
 
 
@@ -177,6 +196,111 @@ def greedy_path(legs_list: List[List[int]]):
         rest = [nxt] + rest[2:]
         nxt += 1
     return path
+
+
+def _hyper_greedy_once(legs_list, rng, temp):
+    legs = {i: frozenset(l) for i, l in enumerate(legs_list)}
+    owners = {}
+    for i, l in legs.items():
+        for e in l:
+            owners.setdefault(e, set()).add(i)
+
+    def result(a, b):
+        return frozenset(e for e in legs[a] | legs[b] if owners[e] - {a, b})
+
+    heap = []
+
+    def push(a, b):
+        if a > b:
+            a, b = b, a
+        lc = result(a, b)
+        score = 2.0 ** len(lc) - 2.0 ** len(legs[a]) - 2.0 ** len(legs[b])
+        if temp > 0:
+            score = np.sign(score) * np.log2(1 + abs(score)) - temp * rng.gumbel()
+        heapq.heappush(heap, (score, a, b))
+
+    for e, os in owners.items():
+        os = sorted(os)
+        for i in range(len(os)):
+            for j in range(i + 1, len(os)):
+                push(os[i], os[j])
+    alive = set(legs)
+    nxt = len(legs_list)
+    path = []
+    cost = 0.0
+    while heap:
+        _, a, b = heapq.heappop(heap)
+        if a not in alive or b not in alive:
+            continue
+        lc = result(a, b)
+        cost += 2.0 ** len(legs[a] | legs[b])
+        for e in legs[a] | legs[b]:
+            owners[e] -= {a, b}
+        legs[nxt] = lc
+        for e in lc:
+            owners[e].add(nxt)
+        alive -= {a, b}
+        alive.add(nxt)
+        path.append((a, b, nxt, lc))
+        for e in lc:
+            for o in owners[e]:
+                if o != nxt:
+                    push(o, nxt)
+        nxt += 1
+    rest = sorted(alive)
+    while len(rest) > 1:
+        a, b = rest[0], rest[1]
+        lc = frozenset(e for e in legs[a] | legs[b] if owners.get(e, set()) - {a, b})
+        for e in legs[a] | legs[b]:
+            owners[e] = owners.get(e, set()) - {a, b}
+        legs[nxt] = lc
+        path.append((a, b, nxt, lc))
+        rest = [nxt] + rest[2:]
+        nxt += 1
+    return cost, path
+
+
+def hyper_greedy_path(legs_list: List[List[int]], trials: int = 16):
+    """Greedy order for networks whose indices may be shared by more than two
+    tensors: repeatedly merge a pair (sharing an index) whose result grows the
+    total size least; an index survives a merge while any other tensor still
+    carries it.  The first trial is deterministic, the others add seeded
+    Gumbel noise to the scores; the cheapest (sum of 2^|legs of both|) wins.
+    Returns [(id_a, id_b, id_new, result_legs)]."""
+    rng = np.random.default_rng(12345)
+    best = None
+    for t in range(trials):
+        cost, path = _hyper_greedy_once(legs_list, rng, 0.0 if t == 0 else 1.0)
+        if best is None or cost < best[0]:
+            best = (cost, path)
+    return best[1]
+
+
+def contract_hyper(arrs, legs, path) -> complex:
+    """Apply a hyper_greedy_path: each pair is transposed to
+    [kept shared | own | summed] x [kept shared | summed | own] and multiplied
+    with numpy.matmul (complex128), batched over the kept shared indices."""
+    store = {i: (a, list(l)) for i, (a, l) in enumerate(zip(arrs, legs))}
+    if not store:
+        return 1.0 + 0.0j
+    for a, b, c, lc in path:
+        ta, la = store.pop(a)
+        tb, lb = store.pop(b)
+        shared = [e for e in la if e in lb]
+        batch = [e for e in shared if e in lc]
+        summed = [e for e in shared if e not in lc]
+        fa = [e for e in la if e not in lb]
+        fb = [e for e in lb if e not in la]
+        pa = np.transpose(ta, [la.index(e) for e in batch + fa + summed])
+        pb = np.transpose(tb, [lb.index(e) for e in batch + summed + fb])
+        nb, na, nk, nf = 2 ** len(batch), 2 ** len(fa), 2 ** len(summed), 2 ** len(fb)
+        tc = np.matmul(pa.reshape(nb, na, nk), pb.reshape(nb, nk, nf))
+        out = batch + fa + fb
+        store[c] = (tc.reshape((2,) * len(out)), out)
+    assert len(store) == 1
+    (t, l), = store.values()
+    assert len(l) == 0
+    return complex(np.asarray(t).reshape(()))
 
 
 def contract_path(arrs, legs, path) -> complex:

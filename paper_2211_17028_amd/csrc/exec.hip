@@ -331,65 +331,115 @@ struct Builder {
                 }
             }
         }
+        // remaining holders of every leg (a diagonal gate's wire index can be
+        // held by more than two tensors)
+        std::unordered_map<int, int> holders;
+        for (int i = 0; i < L; ++i)
+            for (int e : nodes[i].legs) holders[e] += 1;
         // steps
         for (size_t j = 0; j < cl.path.size(); ++j) {
             const int ia_node = cl.path[j].a, ib_node = cl.path[j].b;
             NodeInfo& A = nodes[ia_node];
             NodeInfo& B = nodes[ib_node];
             NodeInfo& C = nodes[L + j];
-            std::vector<int> K, FA, FB;
-            for (int e : A.legs)
-                if (std::find(B.legs.begin(), B.legs.end(), e) != B.legs.end()) K.push_back(e);
-                else FA.push_back(e);
+            // K: shared and held by nobody else (summed); Bt: shared and still
+            // held elsewhere (kept, a batch dimension of this step)
+            std::vector<int> K, Bt, FA, FB;
+            for (int e : A.legs) {
+                bool in_b = std::find(B.legs.begin(), B.legs.end(), e) != B.legs.end();
+                if (!in_b) FA.push_back(e);
+                else if (holders[e] > 2) Bt.push_back(e);
+                else K.push_back(e);
+            }
             for (int e : B.legs)
-                if (std::find(K.begin(), K.end(), e) == K.end()) FB.push_back(e);
-            const int rk = (int)K.size();
-            auto is_suffix = [&](const std::vector<int>& legs, std::vector<int>* order) {
-                if ((int)legs.size() < rk) return false;
-                std::vector<int> tail(legs.end() - rk, legs.end());
-                std::vector<int> a = tail, b = K;
+                if (std::find(A.legs.begin(), A.legs.end(), e) == A.legs.end()) FB.push_back(e);
+            for (int e : K) holders[e] = 0;
+            for (int e : Bt) holders[e] -= 1;
+            const int rk = (int)K.size(), rb = (int)Bt.size();
+            auto same_set = [](std::vector<int> a, std::vector<int> b) {
                 std::sort(a.begin(), a.end());
                 std::sort(b.begin(), b.end());
-                if (a != b) return false;
-                *order = tail;
-                return true;
+                return a == b;
             };
-            auto is_prefix = [&](const std::vector<int>& legs, std::vector<int>* order) {
-                if ((int)legs.size() < rk) return false;
-                std::vector<int> head(legs.begin(), legs.begin() + rk);
-                std::vector<int> a = head, b = K;
-                std::sort(a.begin(), a.end());
-                std::sort(b.begin(), b.end());
-                if (a != b) return false;
-                *order = head;
-                return true;
+            // legs == bt ++ X ++ Y with set(X) = first, set(Y) = second?
+            struct Layout {
+                bool ok = false;
+                std::vector<int> bt, k;
+                int trans = 0;
             };
-            // forms: A as [FA | K] (MK) or [K | FA] (KM); B as [K | FB] (KN) or [FB | K] (NK)
-            std::vector<int> a_k, b_k;
-            int a_form = is_suffix(A.legs, &a_k) ? 0 : (is_prefix(A.legs, &a_k) ? 1 : -1);
-            int b_form = is_prefix(B.legs, &b_k) ? 0 : (is_suffix(B.legs, &b_k) ? 1 : -1);
+            auto match = [&](const std::vector<int>& legs, const std::vector<int>& F, bool k_first) {
+                Layout lo;
+                if (legs.size() != (size_t)(rb + rk + F.size())) return lo;
+                std::vector<int> bt(legs.begin(), legs.begin() + rb);
+                if (!same_set(bt, Bt)) return lo;
+                std::vector<int> x, y;
+                if (k_first) {
+                    x.assign(legs.begin() + rb, legs.begin() + rb + rk);
+                    y.assign(legs.begin() + rb + rk, legs.end());
+                    if (!same_set(x, K) || !same_set(y, F)) return lo;
+                    lo.k = x;
+                } else {
+                    x.assign(legs.begin() + rb, legs.end() - rk);
+                    y.assign(legs.end() - rk, legs.end());
+                    if (!same_set(x, F) || !same_set(y, K)) return lo;
+                    lo.k = y;
+                }
+                lo.ok = true;
+                lo.bt = bt;
+                return lo;
+            };
+            // A: [Bt|FA|K] (trans 0) or [Bt|K|FA] (trans 1); B: [Bt|K|FB] (0) or [Bt|FB|K] (1)
+            std::vector<Layout> la, lb;
+            for (int t = 0; t < 2; ++t) {
+                Layout x = match(A.legs, FA, t == 1);
+                x.trans = t;
+                if (x.ok) la.push_back(x);
+                Layout y = match(B.legs, FB, t == 0);
+                y.trans = t;
+                if (y.ok) lb.push_back(y);
+            }
             const int64_t bytesA = (int64_t)A.keys.size() << A.legs.size();
             const int64_t bytesB = (int64_t)B.keys.size() << B.legs.size();
-            std::vector<int> korder;
-            bool permA = false, permB = false;
-            if (a_form >= 0 && b_form >= 0 && a_k == b_k) {
-                korder = a_k;
-            } else if (a_form >= 0 && (bytesA >= bytesB || b_form < 0)) {
-                korder = a_k;
-                permB = true;
-            } else if (b_form >= 0) {
-                korder = b_k;
-                permA = true;
-            } else {
-                korder = K;
-                permA = permB = true;
-            }
-            if (a_form >= 0 && a_k != korder) permA = true;
-            if (b_form >= 0 && b_k != korder) permB = true;
-            std::vector<int> a_target = FA, b_target = korder;
-            a_target.insert(a_target.end(), korder.begin(), korder.end());
-            b_target.insert(b_target.end(), FB.begin(), FB.end());
+            bool permA = true, permB = true;
             int transA = 0, transB = 0;
+            std::vector<int> bt_order = Bt, k_order = K;
+            bool done = false;
+            for (auto& x : la)
+                for (auto& y : lb)
+                    if (!done && x.bt == y.bt && x.k == y.k) {
+                        permA = permB = false;
+                        transA = x.trans;
+                        transB = y.trans;
+                        bt_order = x.bt;
+                        k_order = x.k;
+                        done = true;
+                    }
+            if (!done) {
+                if (!la.empty() && (bytesA >= bytesB || lb.empty())) {
+                    permA = false;
+                    transA = la[0].trans;
+                    bt_order = la[0].bt;
+                    k_order = la[0].k;
+                } else if (!lb.empty()) {
+                    permB = false;
+                    transB = lb[0].trans;
+                    bt_order = lb[0].bt;
+                    k_order = lb[0].k;
+                }
+            }
+            // free legs keep their operand's relative order
+            auto ordered_free = [](const std::vector<int>& legs, const std::vector<int>& F) {
+                std::vector<int> out;
+                for (int e : legs)
+                    if (std::find(F.begin(), F.end(), e) != F.end()) out.push_back(e);
+                return out;
+            };
+            std::vector<int> fa_order = ordered_free(A.legs, FA), fb_order = ordered_free(B.legs, FB);
+            std::vector<int> a_target = bt_order, b_target = bt_order;
+            a_target.insert(a_target.end(), fa_order.begin(), fa_order.end());
+            a_target.insert(a_target.end(), k_order.begin(), k_order.end());
+            b_target.insert(b_target.end(), k_order.begin(), k_order.end());
+            b_target.insert(b_target.end(), fb_order.begin(), fb_order.end());
             Ref opA = A.buf, opB = B.buf;
             std::vector<std::pair<int64_t, int64_t>> temps;
             auto emit_perm = [&](NodeInfo& X, const std::vector<int>& target, Ref* op) {
@@ -407,13 +457,27 @@ struct Builder {
                 out->push_back(pl);
                 *op = pl.c;
             };
-            if (permA) emit_perm(A, a_target, &opA);
-            else transA = a_form == 1;
-            if (permB) emit_perm(B, b_target, &opB);
-            else transB = b_form == 1;
-            C.legs = FA;
-            C.legs.insert(C.legs.end(), FB.begin(), FB.end());
+            if (permA) {
+                emit_perm(A, a_target, &opA);
+                transA = 0;
+            }
+            if (permB) {
+                emit_perm(B, b_target, &opB);
+                transB = 0;
+            }
+            // orientation: C = A B (legs bt|FA|FB) or, when A is too short for an
+            // MFMA row tile and B is not, C^T = B^T A^T (legs bt|FB|FA)
+            const bool swap = FA.size() < 5 && FB.size() >= 5;
+            C.legs = bt_order;
+            if (!swap) {
+                C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
+                C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
+            } else {
+                C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
+                C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
+            }
             const int64_t ninst = (int64_t)C.keys.size();
+            const int64_t nbatch = int64_t(1) << rb;
             C.bytes = ninst * (int64_t(esz) << C.legs.size());
             if (j + 1 == cl.path.size() && mode == 2) {
                 C.buf = Ref{R_WORK, 0};   // replaced by the per-term root slot
@@ -432,31 +496,46 @@ struct Builder {
             gl.g.k_log = rk;
             gl.g.transA = transA;
             gl.g.transB = transB;
-            gl.g.n_inst = ninst;
-            gl.g.strideA = int64_t(1) << A.legs.size();
-            gl.g.strideB = int64_t(1) << B.legs.size();
-            // instance maps
+            // every (instance, batch index) pair is one GEMM; operand slices of
+            // one batch index are m k (n k) elements apart
+            gl.g.n_inst = ninst * nbatch;
+            gl.g.strideA = int64_t(1) << (A.legs.size() - rb);
+            gl.g.strideB = int64_t(1) << (B.legs.size() - rb);
             auto mapping = [&](const NodeInfo& X, int* mode_out, Ref* map_out) {
-                if (X.keys.size() == 1) {
+                if (X.keys.size() == 1 && rb == 0) {
                     *mode_out = 1;
                     return;
                 }
                 if (X.mask == C.mask) {
-                    *mode_out = 0;
+                    *mode_out = 0;     // same instances; (i, b) -> i * nbatch + b
                     return;
                 }
-                std::vector<int32_t> m(ninst);
-                for (int64_t i = 0; i < ninst; ++i) m[i] = (int32_t)find_key(X.keys, C.keys[i] & X.mask);
+                std::vector<int32_t> m(ninst * nbatch);
+                for (int64_t i = 0; i < ninst; ++i) {
+                    const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
+                    for (int64_t b2 = 0; b2 < nbatch; ++b2) m[i * nbatch + b2] = (int32_t)(xi * nbatch + b2);
+                }
                 *mode_out = 2;
-                *map_out = Ref{R_CONST, ex->cbuf.add(m.data(), ninst * 4)};
+                *map_out = Ref{R_CONST, ex->cbuf.add(m.data(), (int64_t)m.size() * 4)};
             };
             mapping(A, &gl.g.ia_mode, &gl.ia);
             mapping(B, &gl.g.ib_mode, &gl.ib);
+            if (swap) {
+                // C^T[j][i] = sum_p B^T[j][p] A^T[p][i]: B becomes the row operand
+                std::swap(gl.a, gl.b);
+                std::swap(gl.g.ia_mode, gl.g.ib_mode);
+                std::swap(gl.ia, gl.ib);
+                std::swap(gl.g.strideA, gl.g.strideB);
+                std::swap(gl.g.m_log, gl.g.n_log);
+                const int ta = gl.g.transA, tb2 = gl.g.transB;
+                gl.g.transA = 1 - tb2;
+                gl.g.transB = 1 - ta;
+            }
             const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
                          kk = std::ldexp(1.0, gl.g.k_log);
-            gl.flops = 8.0 * mm * nnn * kk * ninst;
-            gl.bytes = (double)esz * (ninst * mm * nnn + (double)A.keys.size() * mm * kk +
-                                      (double)B.keys.size() * kk * nnn);
+            gl.flops = 8.0 * mm * nnn * kk * (double)gl.g.n_inst;
+            gl.bytes = (double)esz * ((double)gl.g.n_inst * mm * nnn + (double)A.keys.size() * nbatch * mm * kk +
+                                      (double)B.keys.size() * nbatch * kk * nnn);
             if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
             gl.kclass = select_gemm(gl.g, fp64, -1);
             out->push_back(gl);

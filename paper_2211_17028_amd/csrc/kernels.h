@@ -41,7 +41,7 @@ enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3 };
 // then the other variants.  The choice is a pure function of the shape (and
 // of the tile hint for MFMA), so it is fixed when a schedule is prepared.
 enum KernelId {
-    K_MFMA_TILES = 6,
+    K_MFMA_TILES = 8,
     K_SMALL32 = 10, K_SPLITK32 = 11,
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,

@@ -401,7 +401,8 @@ static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) /
 struct TileCfg {
     int bm, bnc;
 };
-static const TileCfg kTiles[K_MFMA_TILES] = {{128, 64}, {64, 64}, {128, 32}, {64, 32}, {32, 32}, {32, 16}};
+static const TileCfg kTiles[K_MFMA_TILES] = {{128, 64}, {64, 64}, {128, 32}, {64, 32},
+                                               {32, 32}, {128, 16}, {64, 16}, {32, 16}};
 
 bool mfma_tile_fits(int tile, const GemmArgs& g) {
     if (tile < 0 || tile >= K_MFMA_TILES) return false;
@@ -421,7 +422,8 @@ int select_gemm(const GemmArgs& g, int fp64, int tile_hint) {
 
 const char* kernel_name(int id) {
     static const char* mf[K_MFMA_TILES] = {"k_gemm_mfma<128,64>", "k_gemm_mfma<64,64>", "k_gemm_mfma<128,32>",
-                                           "k_gemm_mfma<64,32>", "k_gemm_mfma<32,32>", "k_gemm_mfma<32,16>"};
+                                           "k_gemm_mfma<64,32>",  "k_gemm_mfma<32,32>", "k_gemm_mfma<128,16>",
+                                           "k_gemm_mfma<64,16>",  "k_gemm_mfma<32,16>"};
     if (id >= 0 && id < K_MFMA_TILES) return mf[id];
     switch (id) {
     case K_SMALL32: return "k_gemm_small<float>";
@@ -456,6 +458,8 @@ static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s)
     TN_LAUNCH(128, 32)
     TN_LAUNCH(64, 32)
     TN_LAUNCH(32, 32)
+    TN_LAUNCH(128, 16)
+    TN_LAUNCH(64, 16)
     TN_LAUNCH(32, 16)
 #undef TN_LAUNCH
 }

@@ -205,49 +205,67 @@ static NoiseSplit split_noise(const tn_op& op, int64_t index) {
 // ---------------------------------------------------------------------------
 // small dense tensor algebra on the host (FP64), legs of dimension 2
 // ---------------------------------------------------------------------------
-static Leaf contract_host(const Leaf& x, const Leaf& y) {
-    std::vector<int> shared, fx, fy;
-    for (int e : x.legs)
-        if (std::find(y.legs.begin(), y.legs.end(), e) != y.legs.end()) shared.push_back(e);
-        else fx.push_back(e);
+// Contract two fixed tensors.  A leg they share is summed unless `keep`
+// says another tensor still holds it (a diagonal gate's wire index), in which
+// case it stays, once, in the result.  Result legs: x's kept legs in x order,
+// then y's own legs in y order.
+static Leaf contract_host(const Leaf& x, const Leaf& y, const std::function<bool(int)>& keep) {
+    std::vector<int> out_legs, summed;
+    for (int e : x.legs) {
+        bool in_y = std::find(y.legs.begin(), y.legs.end(), e) != y.legs.end();
+        if (in_y && !keep(e)) summed.push_back(e);
+        else out_legs.push_back(e);
+    }
     for (int e : y.legs)
-        if (std::find(shared.begin(), shared.end(), e) == shared.end()) fy.push_back(e);
+        if (std::find(x.legs.begin(), x.legs.end(), e) == x.legs.end()) out_legs.push_back(e);
     Leaf out;
-    out.legs = fx;
-    out.legs.insert(out.legs.end(), fy.begin(), fy.end());
-    const int rx = (int)x.legs.size(), ry = (int)y.legs.size(), rs = (int)shared.size();
-    const int rfx = (int)fx.size(), rfy = (int)fy.size();
+    out.legs = out_legs;
+    const int rx = (int)x.legs.size(), ry = (int)y.legs.size(), ro = (int)out_legs.size();
+    const int rs = (int)summed.size();
     auto pos = [](const std::vector<int>& legs, int e) {
         return (int)(std::find(legs.begin(), legs.end(), e) - legs.begin());
     };
-    std::vector<int> fx_pos(rfx), fy_pos(rfy), sx_pos(rs), sy_pos(rs);
-    for (int i = 0; i < rfx; ++i) fx_pos[i] = rx - 1 - pos(x.legs, fx[i]);
-    for (int i = 0; i < rfy; ++i) fy_pos[i] = ry - 1 - pos(y.legs, fy[i]);
-    for (int i = 0; i < rs; ++i) {
-        sx_pos[i] = rx - 1 - pos(x.legs, shared[i]);
-        sy_pos[i] = ry - 1 - pos(y.legs, shared[i]);
+    // for every output leg: its bit in x (or -1) and in y (or -1)
+    std::vector<int> ox(ro, -1), oy(ro, -1), sx(rs), sy(rs);
+    for (int i = 0; i < ro; ++i) {
+        int px = pos(x.legs, out_legs[i]), py = pos(y.legs, out_legs[i]);
+        if (px < rx) ox[i] = rx - 1 - px;
+        if (py < ry) oy[i] = ry - 1 - py;
     }
-    const int64_t nout = int64_t(1) << (rfx + rfy);
+    for (int i = 0; i < rs; ++i) {
+        sx[i] = rx - 1 - pos(x.legs, summed[i]);
+        sy[i] = ry - 1 - pos(y.legs, summed[i]);
+    }
+    const int64_t nout = int64_t(1) << ro;
     out.data.assign(nout, 0.0);
     for (int64_t o = 0; o < nout; ++o) {
         int64_t bx = 0, by = 0;
-        for (int i = 0; i < rfx; ++i)
-            if ((o >> (rfx + rfy - 1 - i)) & 1) bx |= int64_t(1) << fx_pos[i];
-        for (int i = 0; i < rfy; ++i)
-            if ((o >> (rfy - 1 - i)) & 1) by |= int64_t(1) << fy_pos[i];
+        for (int i = 0; i < ro; ++i)
+            if ((o >> (ro - 1 - i)) & 1) {
+                if (ox[i] >= 0) bx |= int64_t(1) << ox[i];
+                if (oy[i] >= 0) by |= int64_t(1) << oy[i];
+            }
         cd acc = 0;
-        for (int64_t s = 0; s < (int64_t(1) << rs); ++s) {
+        for (int64_t t = 0; t < (int64_t(1) << rs); ++t) {
             int64_t ix = bx, iy = by;
             for (int i = 0; i < rs; ++i)
-                if ((s >> i) & 1) {
-                    ix |= int64_t(1) << sx_pos[i];
-                    iy |= int64_t(1) << sy_pos[i];
+                if ((t >> i) & 1) {
+                    ix |= int64_t(1) << sx[i];
+                    iy |= int64_t(1) << sy[i];
                 }
             acc += x.data[ix] * y.data[iy];
         }
         out.data[o] = acc;
     }
     return out;
+}
+
+static bool is_diagonal(const tn_op& op) {
+    const int d = 1 << op.nq;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && (op.mat[r * d + c].re != 0.0 || op.mat[r * d + c].im != 0.0)) return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +295,7 @@ static void check_unitary(const tn_op& op, int64_t idx) {
 }
 
 static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn_state* v,
-                              bool light_cone) {
+                              bool light_cone, bool diag_hyper) {
     const int n = c->n_qubits;
     NetBuild nb;
     std::vector<int> noise_of_op(c->n_ops, -1);
@@ -336,6 +354,20 @@ static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn
     for (auto [k, inv] : seq) {
         const tn_op& op = c->ops[k];
         Leaf l;
+        if (diag_hyper && op.kind == TN_GATE && is_diagonal(op)) {
+            // a diagonal gate does not change the basis index of its wires: it is
+            // a tensor on the current wire indices, shared with whatever else
+            // touches them (hyperedge)
+            const int d = 1 << op.nq;
+            for (int i = 0; i < op.nq; ++i) l.legs.push_back(cur[op.q[i]]);
+            l.data.resize(d);
+            for (int r = 0; r < d; ++r) {
+                cd g(op.mat[r * d + r].re, op.mat[r * d + r].im);
+                l.data[r] = inv ? std::conj(g) : g;
+            }
+            nb.leaves.push_back(std::move(l));
+            continue;
+        }
         std::vector<int> ins, outs;
         for (int i = 0; i < op.nq; ++i) ins.push_back(cur[op.q[i]]);
         for (int i = 0; i < op.nq; ++i) {
@@ -398,10 +430,13 @@ static void fuse_fixed(NetBuild& nb) {
             for (int e : L[i].legs) {
                 for (int j : owners[e]) {
                     if (j == (int)i || !alive[j] || L[j].slot >= 0) continue;
-                    int shared = 0;
+                    int shared = 0, kept = 0;
                     for (int f : L[i].legs)
-                        if (std::find(L[j].legs.begin(), L[j].legs.end(), f) != L[j].legs.end()) ++shared;
-                    int r = (int)L[i].legs.size() + (int)L[j].legs.size() - 2 * shared;
+                        if (std::find(L[j].legs.begin(), L[j].legs.end(), f) != L[j].legs.end()) {
+                            ++shared;
+                            if (owners[f].size() > 2) ++kept;
+                        }
+                    int r = (int)L[i].legs.size() + (int)L[j].legs.size() - 2 * shared + kept;
                     int lim = std::max<int>(4, std::max(L[i].legs.size(), L[j].legs.size()));
                     if (r <= lim && r < best_rank) {
                         best = j;
@@ -410,7 +445,12 @@ static void fuse_fixed(NetBuild& nb) {
                 }
             }
             if (best < 0) continue;
-            Leaf merged = contract_host(L[i], L[best]);
+            const int ii = (int)i, jj = best;
+            Leaf merged = contract_host(L[i], L[best], [&](int e) {
+                for (int o : owners[e])
+                    if (o != ii && o != jj) return true;
+                return false;
+            });
             for (int e : L[i].legs) {
                 auto& v = owners[e];
                 v.erase(std::remove(v.begin(), v.end(), (int)i), v.end());
@@ -457,12 +497,6 @@ struct PathSearch {
     }
 };
 
-static std::vector<int> sym_diff(const std::vector<int>& a, const std::vector<int>& b) {
-    std::vector<int> out;
-    std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
-    return out;
-}
-
 static int union_size(const std::vector<int>& a, const std::vector<int>& b) {
     size_t i = 0, j = 0;
     int n = 0;
@@ -496,12 +530,28 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
     for (int i = 0; i < L; ++i)
         for (int e : legs[i]) owners[e].push_back(i);
     auto size_of = [&](int i) { return ps.instances(mask[i]) * std::ldexp(1.0, (int)legs[i].size()); };
+    // legs of the result of merging a and b: every leg of either that some
+    // other live tensor still holds (shared legs held only by a and b are summed)
+    auto result_legs = [&](int a, int b) {
+        std::vector<int> out;
+        std::vector<int> un;
+        std::set_union(legs[a].begin(), legs[a].end(), legs[b].begin(), legs[b].end(), std::back_inserter(un));
+        for (int e : un) {
+            const auto& ow = owners[e];
+            for (int o : ow)
+                if (o != a && o != b) {
+                    out.push_back(e);
+                    break;
+                }
+        }
+        return out;
+    };
     typedef std::tuple<double, int, int> Cand;
     std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> pq;
     auto push = [&](int a, int b) {
         if (a == b) return;
         if (a > b) std::swap(a, b);
-        std::vector<int> lc = sym_diff(legs[a], legs[b]);
+        std::vector<int> lc = result_legs(a, b);
         double sc = ps.instances(mask[a] | mask[b]) * std::ldexp(1.0, (int)lc.size()) -
                     alpha * (size_of(a) + size_of(b));
         double s = (sc >= 0 ? 1.0 : -1.0) * std::log2(1.0 + std::fabs(sc));
@@ -509,7 +559,8 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
         pq.push(Cand(s, a, b));
     };
     for (auto& kv : owners)
-        if (kv.second.size() == 2) push(kv.second[0], kv.second[1]);
+        for (size_t x = 0; x < kv.second.size(); ++x)
+            for (size_t y = x + 1; y < kv.second.size(); ++y) push(kv.second[x], kv.second[y]);
     TrialResult tr;
     double live = 0;
     for (int i = 0; i < L; ++i) live += size_of(i);
@@ -533,7 +584,7 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
                     else if (b < 0) { b = i; break; }
                 }
         }
-        std::vector<int> lc = sym_diff(legs[a], legs[b]);
+        std::vector<int> lc = result_legs(a, b);
         uint64_t mc = mask[a] | mask[b];
         int u = union_size(legs[a], legs[b]);
         double inst = ps.instances(mc);
@@ -566,7 +617,7 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
     return tr;
 }
 
-static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log) {
+static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, double max_peak) {
     const int nl = (int)p.leaves.size();
     // union-find over shared legs
     std::vector<int> parent(nl);
@@ -620,22 +671,28 @@ static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log) {
         bool have = false;
         const double alphas[4] = {1.0, 0.5, 0.0, 0.75};
         const double temps[3] = {0.5, 1.0, 2.0};
+        // a path is admissible when one instance of every tensor fits in 2^max_log
+        // elements and the instance-weighted live set fits in max_peak elements;
+        // among admissible paths the cheapest wins, else the smallest peak
+        auto admissible = [&](const TrialResult& r) { return r.max_log <= max_log && r.peak <= max_peak; };
         for (int t = 0; t < trials; ++t) {
             double alpha = alphas[t % 4];
             double temp = t < 4 ? 0.0 : temps[t % 3];
             TrialResult tr = greedy_trial(leaf_legs, leaf_mask, ps, alpha, temp,
                                           seed * 1000003ULL + (uint64_t)t * 7919ULL + 17);
-            bool ok = tr.max_log <= max_log;
-            bool best_ok = have && best.max_log <= max_log;
-            if (!have || (ok && !best_ok) || (ok == best_ok && tr.cost < best.cost)) {
+            bool ok = admissible(tr);
+            bool best_ok = have && admissible(best);
+            bool better = ok ? tr.cost < best.cost : (tr.max_log < best.max_log ||
+                                                     (tr.max_log == best.max_log && tr.peak < best.peak));
+            if (!have || (ok && !best_ok) || (ok == best_ok && better)) {
                 best = std::move(tr);
                 have = true;
             }
         }
-        if (best.max_log > max_log) {
+        if (!admissible(best)) {
             std::ostringstream os;
-            os << "no contraction path keeps tensors within 2^" << max_log << " elements (best 2^"
-               << best.max_log << ")";
+            os << "no contraction path keeps tensors within 2^" << max_log << " elements and the live set "
+               << "within " << max_peak << " elements (best: 2^" << best.max_log << ", " << best.peak << ")";
             fail(TN_ETOOBIG, os.str());
         }
         cl.path = best.path;
@@ -689,14 +746,16 @@ Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, in
     p->level = std::min(level, p->n_noise);
     p->clamped = level > p->n_noise;
     if (p->level > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
-    NetBuild nb = build_network(c, psi, v, !(opts && opts->no_light_cone));
+    NetBuild nb = build_network(c, psi, v, !(opts && opts->no_light_cone),
+                                !(opts && opts->no_diagonal_hyperedges));
     fuse_fixed(nb);
     p->leaves = std::move(nb.leaves);
     p->scalar = nb.scalar;
     int trials = (opts && opts->path_trials > 0) ? opts->path_trials : 64;
     uint64_t seed = (opts && opts->seed) ? opts->seed : 2211170280ULL;
     int max_log = (opts && opts->max_log_size > 0) ? opts->max_log_size : 30;
-    plan_clusters(*p, trials, seed, max_log);
+    double max_bytes = (opts && opts->max_work_bytes > 0) ? opts->max_work_bytes : 64.0 * (1ULL << 30);
+    plan_clusters(*p, trials, seed, max_log, max_bytes / 8.0);
     return p.release();
 }
 

@@ -48,7 +48,8 @@ class tn_state(C.Structure):
 
 class tn_plan_opts(C.Structure):
     _fields_ = [("path_trials", C.c_int32), ("seed", C.c_uint64), ("no_light_cone", C.c_int32),
-                ("max_log_size", C.c_int32)]
+                ("max_log_size", C.c_int32), ("no_diagonal_hyperedges", C.c_int32),
+                ("max_work_bytes", C.c_double)]
 
 
 class tn_prune_opts(C.Structure):
@@ -250,9 +251,11 @@ class Terms:
 
 
 def tn_plan_build(circ, level: Optional[int] = None, path_trials: int = 0, seed: int = 0,
-                  light_cone: bool = True, max_log_size: int = 0) -> Plan:
+                  light_cone: bool = True, max_log_size: int = 0, diagonal_hyperedges: bool = True,
+                  max_work_bytes: float = 0.0) -> Plan:
     bufs = _CircuitBuffers(circ)
-    opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size)
+    opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size,
+                        0 if diagonal_hyperedges else 1, max_work_bytes)
     h = C.c_void_p()
     lev = circ.level if level is None else level
     _check(lib().tn_plan_build(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v), lev,

@@ -190,7 +190,7 @@ def test_config2_full_size_sampled_terms(torch):
     assert res["n_terms"] == 436
     assert np.all(x >= 0)
     assert res["A"][0] <= res["A"][1] <= res["A"][2] <= 1.0 + 1e-6
-    net = network.KetNetwork(c)
+    net = network.KetNetwork(c, diagonal=True)
     sp = network.slot_split(c)
     groups = {(): [], (3,): [], (7,): [], (2, 8): []}
     for j, row in enumerate(pat):
@@ -207,3 +207,79 @@ def test_config2_full_size_sampled_terms(torch):
         vals = np.loadtxt(gold)
         for u in range(3):
             assert abs(res["A"][u] - vals[u]) <= 1e-6 * vals[u], (u, res["A"][u], vals[u])
+
+
+def _sample_terms(pat, w, rng, per_level):
+    """A few live terms of every level (always the all-dominant one)."""
+    lv = (pat != 0).sum(axis=1)
+    out = [0]
+    for u in range(1, lv.max() + 1):
+        idx = np.flatnonzero((lv == u) & (w > 0))
+        if idx.size:
+            out += list(rng.choice(idx, size=min(per_level, idx.size), replace=False))
+    return out
+
+
+@pytest.mark.parametrize("cfg", [3, 5])
+def test_full_size_config_against_oracle(torch, cfg):
+    """Config 3 (QAOA p=2, 36 qubits, 20 AD+PD, level 2, 1771 terms) and
+    config 5 (15x15 grid, 6 layers, 20 AD+PD, level 3, 32551 terms): every
+    term on the GPU; A(l) against the oracle's stored full sums; sampled
+    terms of every level against the oracle one by one."""
+    print(f"config{cfg} full size", flush=True)
+    c = W.config(cfg)
+    res, x, pat, _ = run_gpu(c, c.level)
+    assert res["n_terms"] == {3: 1771, 5: 32551}[cfg]
+    assert np.all(x >= 0)
+    assert all(res["A"][u] <= res["A"][u + 1] + 1e-12 for u in range(c.level))
+    gold = np.loadtxt(os.path.join(GOLD, f"config{cfg}_oracle.txt"))
+    for u in range(c.level + 1):
+        assert abs(res["A"][u] - gold[u]) <= 1e-6 * gold[u], (u, res["A"][u], gold[u])
+    net = network.KetNetwork(c, diagonal=True)
+    sp = network.slot_split(c)
+    w = terms_weights(c)
+    for j in _sample_terms(pat, w, np.random.default_rng(cfg), 4):
+        ref, _ = network.term_value(net, sp, tuple(int(v) for v in pat[j]))
+        tol = 1e-12 if j == 0 else 2e-5
+        assert abs(x[j] - ref) <= tol * ref + 1e-15, (j, x[j], ref)
+
+
+def terms_weights(c):
+    sp = network.slot_split(c)
+    from oracle import terms as oterms
+    tl = oterms.enumerate_terms(c.n_noises, c.level)
+    return np.array([np.prod([sp[s][0][t[s]] for s in range(len(t))]) for t in tl])
+
+
+def test_packed_uneven_batch_against_oracle(torch):
+    """Config 4: 64 chain / grid circuits of 16..100 qubits packed into one
+    prepared schedule; per circuit: terms non-negative, levels monotone,
+    sampled terms against the oracle one by one; full A(l) against the oracle
+    for the circuits with at most 300 terms."""
+    print("config4 packed", flush=True)
+    cs = W.config(4)
+    plans = [tn.tn_plan_build(c, c.level) for c in cs]
+    terms = [tn.tn_terms_enumerate(p, c.level) for p, c in zip(plans, cs)]
+    ex = tn.tn_exec_prepare(plans, terms, tn.exec_opts(use_graph=False))
+    results = ex.run()
+    rng = np.random.default_rng(4)
+    n_full = 0
+    for i, (c, r) in enumerate(zip(cs, results)):
+        x, _ = ex.values(i)
+        pat, w = terms[i].get()
+        assert r["n_terms"] == terms[i].n
+        assert np.all(x >= 0)
+        assert all(r["A"][u] <= r["A"][u + 1] + 1e-12 for u in range(r["level"]))
+        net = network.KetNetwork(c, diagonal=True)
+        sp = network.slot_split(c)
+        if terms[i].n <= 300 and n_full < 6:
+            n_full += 1
+            ref = estimate.estimate(c, c.level, "network")
+            for u in range(r["level"] + 1):
+                assert abs(r["A"][u] - ref["A"][u]) <= 1e-6 * ref["A"][u], (c.name, u)
+        else:
+            for j in _sample_terms(pat, w, rng, 1):
+                ref, _ = network.term_value(net, sp, tuple(int(v) for v in pat[j]))
+                tol = 1e-12 if j == 0 else 2e-5
+                assert abs(x[j] - ref) <= tol * ref + 1e-15, (c.name, j, x[j], ref)
+    assert n_full >= 3

@@ -108,7 +108,7 @@ def test_level_above_noise_count_is_clamped():
     assert t.n == 16
 
 
-def test_plan_leaves_cover_each_leg_exactly_twice_and_paths_are_trees():
+def test_plan_legs_are_closed_and_paths_are_trees():
     for cfg in (1, 2, 5):
         c = W.config(cfg)
         plan = tn.tn_plan_build(c)
@@ -117,7 +117,9 @@ def test_plan_leaves_cover_each_leg_exactly_twice_and_paths_are_trees():
         for lf in d["leaves"]:
             for e in lf["legs"]:
                 cnt[e] = cnt.get(e, 0) + 1
-        assert set(cnt.values()) == {2}
+        # every leg is held by at least two tensors (more for the wire index
+        # of diagonal gates, which stays shared)
+        assert min(cnt.values()) >= 2
         for cl in d["clusters"]:
             L = len(cl["leaves"])
             used = set()

@@ -191,3 +191,28 @@ def test_table4_structure_matches_nonnegative_terms():
     assert abs(implied[0] - implied[2]) < 1e-5       # 4.59e-3 is known to +-5e-6
     assert abs(implied[1] - implied[2]) < 2e-7
     assert rows[3, 2] > implied[2] + 1e-6
+
+
+def test_diagonal_gates_as_shared_indices_give_the_same_terms():
+    # QAOA-like circuit (H, RZZ, RX) and a grid circuit with CZ: the
+    # shared-index form of diagonal gates must reproduce every term
+    rng = np.random.default_rng(91)
+    gates = [W.Op("gate", (q,), W.gate_h()) for q in range(5)]
+    for (a, b) in [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4), (1, 3)]:
+        gates.append(W.Op("gate", (a, b), W.gate_rzz(0.7)))
+    gates += [W.Op("gate", (q,), W.gate_rx(0.3)) for q in range(5)]
+    gates += [W.Op("gate", (q,), W.gate_rz(0.4 * q)) for q in range(5)]
+    kr = [W.kraus_ad_pd(0.01, 0.02), W.kraus_depolarizing(0.01), W.random_isometry_kraus(rng, 3)]
+    ops = W.circuits.place_noises(gates, kr, rng)
+    z = W.circuits.zero_product(5)
+    circs = [W.Circuit(5, ops, z, "circuit_output", z, 3),
+             W.tiny_random_circuit(np.random.default_rng(92), 5, 30, 3, noise="adpd", level=3,
+                                   target="product")]
+    for c in circs:
+        a = network.KetNetwork(c)
+        b = network.KetNetwork(c, diagonal=True)
+        sp = network.slot_split(c)
+        for t in terms.enumerate_terms(3, 3):
+            x1, _ = network.term_value(a, sp, t)
+            x2, _ = network.term_value(b, sp, t)
+            assert abs(x1 - x2) <= 1e-13 * max(1.0, x1)

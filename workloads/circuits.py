@@ -321,28 +321,39 @@ def config(c: int, level: Optional[int] = None, sub: Optional[int] = None):
 
 
 def mixed_batch(count: int = 64, level: Optional[int] = None, sub: Optional[int] = None,
-                max_qubits: int = 100):
+                max_qubits: int = 100, grid_budget: int = 200):
     """Uneven batch: chains and near-square grids of 16..max_qubits qubits,
     6..16 layers, 5..20 noises each (depolarizing U[1e-4, 5e-3] or AD+PD
     U[1e-4, 1e-3], chosen per noise), level 2 or 3 per circuit.  Circuit k is
-    drawn from SeedSequence(2211170284).spawn(count)[k]."""
+    drawn from SeedSequence(2211170284).spawn(count)[k].
+
+    Resampling rule: a grid whose qubits x layers exceeds `grid_budget` has no
+    contraction path of bounded width (random 2D circuits of that depth), so
+    its shape (qubits, layers) is redrawn from the same stream until it fits;
+    chains are never redrawn."""
     seqs = np.random.SeedSequence(CONFIG_SEED_BASE + 4).spawn(count)
     out = []
     for k, ss in enumerate(seqs):
         if sub is not None and k != sub:
             continue
         rng = np.random.Generator(np.random.PCG64(ss))
-        n = int(rng.integers(16, max_qubits + 1))
-        layers = int(rng.integers(6, 17))
+        while True:
+            n = int(rng.integers(16, max_qubits + 1))
+            layers = int(rng.integers(6, 17))
+            grid = rng.uniform() >= 0.5
+            if grid:
+                rows = int(math.floor(math.sqrt(n)))
+                cols = int(math.ceil(n / rows))
+                n = rows * cols
+                if n * layers > grid_budget:
+                    continue
+            break
         n_noise = int(rng.integers(5, 21))
         lev = int(rng.integers(2, 4)) if level is None else level
-        if rng.uniform() < 0.5:
+        if not grid:
             gates = chain_layers(n, layers, rng)
             shape = f"chain{n}"
         else:
-            rows = int(math.floor(math.sqrt(n)))
-            cols = int(math.ceil(n / rows))
-            n = rows * cols
             gates = grid_layers(rows, cols, layers, "ABCD", rng)
             shape = f"grid{rows}x{cols}"
         kr = []
