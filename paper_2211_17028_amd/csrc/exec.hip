@@ -90,7 +90,7 @@ struct ConstBuf {
     int64_t reserve(int64_t n) { return add(nullptr, n); }
 };
 
-enum Region { R_CONST = 0, R_WORK = 1 };
+enum Region { R_CONST = 0, R_WORK = 1, R_WORK2 = 2 };   // R_WORK2: the FP64 pass (side stream)
 struct Ref {
     int region = R_CONST;
     int64_t off = 0;
@@ -138,12 +138,15 @@ struct PlanExec {
 }  // namespace tn
 
 struct tn_exec_s {
-    std::vector<tn::Launch> launches;       // batched / FP64 launches, in order
+    std::vector<tn::Launch> launches;       // FP32 batched launches, in order (main stream)
+    std::vector<tn::Launch> launches64;     // FP64 dominant-term pass (side stream)
     std::vector<tn::Launch> plain_launches; // PLAIN mode per-term body
     std::vector<tn::Launch> tail;           // finalize + level sums
     std::vector<tn::PlanExec> plans;
     tn::ConstBuf cbuf;
-    int64_t const_bytes = 0, work_bytes = 0;
+    int64_t const_bytes = 0, work_bytes = 0, work1_bytes = 0;
+    hipStream_t side = nullptr;             // side stream for the FP64 pass (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char* base = nullptr;
     hipStream_t stream = nullptr;
     tn_exec_opts opts{};
@@ -175,7 +178,8 @@ struct NodeInfo {
 
 struct Builder {
     tn_exec_s* ex;
-    Arena work;
+    Arena work;                // FP32 batch (main stream)
+    Arena work2;               // FP64 dominant-term pass (side stream, runs concurrently)
     std::vector<Launch>* out;
 
     static int64_t find_key(const std::vector<u128>& keys, u128 k) {
@@ -236,6 +240,12 @@ struct Builder {
         L.p.r = r;
         L.p.tb = tt;
         L.p.n_high = r - tt;
+        // element pairs: load slots 2i, 2i+1 differ in input bit 0 and store
+        // slots 2i, 2i+1 in output bit 0 exactly when both tile sides have >= 2 bits
+        L.p.pair = tb >= 1 ? 1 : 0;
+        for (int l = 0; l + 1 < tsize && L.p.pair; l += 2)
+            if (table[l + 1] != table[l] + 1 || table[2 * tsize + l + 1] != table[2 * tsize + l] + 1)
+                L.p.pair = 0;
         int h = 0;
         for (int j = 0; j < r; ++j)
             if (std::find(tile.begin(), tile.end(), j) == tile.end()) {
@@ -253,6 +263,8 @@ struct Builder {
                       int plan_index, std::vector<std::pair<int, int64_t>>* plain_slots) {
         const int fp64 = mode == 1;
         const int64_t esz = fp64 ? 16 : 8;
+        Arena& work = fp64 ? this->work2 : this->work;
+        const int wreg = fp64 ? R_WORK2 : R_WORK;
         const int L = (int)cl.leaves.size();
         const int nn = L + (int)cl.path.size();
         std::vector<NodeInfo> nodes(nn);
@@ -449,7 +461,7 @@ struct Builder {
                 int64_t off = work.alloc(nb);
                 temps.push_back({off, nb});
                 pl.a = *op;
-                pl.c = Ref{R_WORK, off};
+                pl.c = Ref{wreg, off};
                 pl.p.n_inst = (int64_t)X.keys.size();
                 pl.bytes = 2.0 * nb;
                 pl.kclass = fp64 ? K_PERM64 : K_PERM32;
@@ -480,9 +492,9 @@ struct Builder {
             const int64_t nbatch = int64_t(1) << rb;
             C.bytes = ninst * (int64_t(esz) << C.legs.size());
             if (j + 1 == cl.path.size() && mode == 2) {
-                C.buf = Ref{R_WORK, 0};   // replaced by the per-term root slot
+                C.buf = Ref{wreg, 0};     // replaced by the per-term root slot
             } else {
-                C.buf = Ref{R_WORK, work.alloc(C.bytes)};
+                C.buf = Ref{wreg, work.alloc(C.bytes)};
             }
             Launch gl;
             gl.kind = L_GEMM;
@@ -631,7 +643,7 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         }
         // FP64 pass for the all-dominant term
         if (pe.zero_term >= 0 && ex->opts.fp64_level0) {
-            bw.out = &ex->launches;
+            bw.out = &ex->launches64;
             for (int c = 0; c < ncl; ++c) {
                 std::vector<u128> one = {0};
                 Ref r = bw.build_cluster(P, P.clusters[c], one, 1, pi, nullptr);
@@ -641,8 +653,8 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
                 cp.c = keep;
                 cp.p.n_inst = 1;
                 cp.plan = pi;
-                ex->launches.push_back(cp);
-                bw.work.release(r.off, 16);
+                ex->launches64.push_back(cp);
+                bw.work2.release(r.off, 16);
                 pe.root64.push_back(keep);
             }
         }
@@ -717,11 +729,15 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         ex->plans.push_back(std::move(pe));
     }
     ex->const_bytes = round_up((int64_t)ex->cbuf.bytes.size(), 256);
-    ex->work_bytes = round_up(bw.work.peak, 256);
+    ex->work1_bytes = round_up(bw.work.peak, 256);
+    ex->work_bytes = ex->work1_bytes + round_up(bw.work2.peak, 256);
 }
 
 static void* resolve(tn_exec_s* ex, const Ref& r) {
-    return ex->base + (r.region == R_CONST ? 0 : ex->const_bytes) + r.off;
+    const int64_t region_off = r.region == R_CONST ? 0
+                               : r.region == R_WORK ? ex->const_bytes
+                                                    : ex->const_bytes + ex->work1_bytes;
+    return ex->base + region_off + r.off;
 }
 
 static void bind(tn_exec_s* ex) {
@@ -744,6 +760,7 @@ static void bind(tn_exec_s* ex) {
         }
     };
     for (auto& L : ex->launches) fix(L);
+    for (auto& L : ex->launches64) fix(L);
     for (auto& L : ex->plain_launches) fix(L);
     // pointer tables written into the host staging copy before upload
     for (auto& L : ex->plain_launches)
@@ -793,11 +810,24 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
 }
 
 static void run_body(tn_exec_s* ex, hipStream_t s) {
+    // the FP64 pass forks onto the side stream and joins before the finalize
+    const bool side = !ex->launches64.empty();
+    if (side) {
+        HIPCHK(hipEventRecord(ex->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(ex->side, ex->ev_fork, 0));
+        for (auto& L : ex->launches64) {
+            if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, ex->side));
+            enqueue(ex, L, ex->side);
+            if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, ex->side));
+        }
+        HIPCHK(hipEventRecord(ex->ev_join, ex->side));
+    }
     for (auto& L : ex->launches) {
         if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, s));
         enqueue(ex, L, s);
         if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, s));
     }
+    if (side) HIPCHK(hipStreamWaitEvent(s, ex->ev_join, 0));
     if (ex->opts.mode == TN_MODE_PLAIN) {
         for (int64_t t = 0; t < ex->plain_terms; ++t) {
             for (auto& L : ex->plain_launches) {
@@ -822,6 +852,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
     std::ostringstream os;
     os.precision(10);
     os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
+       << ",\"work1_bytes\":" << ex->work1_bytes
        << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms << ",\"launches\":[";
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
@@ -839,7 +870,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
         if (L.kind == L_PERM)
             os << ",\"r\":" << L.p.r << ",\"tb\":" << L.p.tb << ",\"n_inst\":" << L.p.n_inst << ",\"a\":["
                << L.a.region << "," << L.a.off << "],\"c\":[" << L.c.region << "," << L.c.off << "],\"table\":["
-               << L.table.region << "," << L.table.off << "],\"high_out\":[";
+               << L.table.region << "," << L.table.off << "],\"pair\":" << L.p.pair << ",\"high_out\":[";
         if (L.kind == L_PERM) {
             for (int i = 0; i < L.p.n_high; ++i) os << (i ? "," : "") << L.p.high_out[i];
             os << "],\"high_in\":[";
@@ -861,6 +892,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
         if (L.kind == L_GEMM) os << ",\"plain_root\":" << L.plain_root;
         os << ",\"flops\":" << L.flops << ",\"bytes\":" << L.bytes << "}";
     };
+    for (auto& L : ex->launches64) emit(L, "batch64");
     for (auto& L : ex->launches) emit(L, "batch");
     for (auto& L : ex->plain_launches) emit(L, "plain");
     for (auto& L : ex->tail) emit(L, "tail");
@@ -1016,12 +1048,18 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
         bind(ex.get());
+        if (!ex->launches64.empty()) {
+            HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ex->ev_join, hipEventDisableTiming));
+        }
         if (ex->opts.time_kernels)
-            for (auto& L : ex->launches)
-                if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0)) {
-                    HIPCHK(hipEventCreate(&L.ev_a));
-                    HIPCHK(hipEventCreate(&L.ev_b));
-                }
+            for (auto* list : {&ex->launches, &ex->launches64})
+                for (auto& L : *list)
+                    if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0)) {
+                        HIPCHK(hipEventCreate(&L.ev_a));
+                        HIPCHK(hipEventCreate(&L.ev_b));
+                    }
         HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
                               ex->stream));
         HIPCHK(hipEventCreate(&ex->ev0));
@@ -1057,7 +1095,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, ex->ev0, ex->ev1));
         ex->last_ms = ms;
-        for (auto& L : ex->launches)
+        for (auto* list : {&ex->launches, &ex->launches64})
+          for (auto& L : *list)
             if (L.ev_a) {
                 float dt = 0;
                 HIPCHK(hipEventElapsedTime(&dt, L.ev_a, L.ev_b));
@@ -1213,10 +1252,14 @@ void tn_exec_destroy(tn_exec exh) {
     if (ex->ev0) (void)hipEventDestroy(ex->ev0);
     if (ex->ev1) (void)hipEventDestroy(ex->ev1);
     if (ex->cap_stream) (void)hipStreamDestroy(ex->cap_stream);
-    for (auto& L : ex->launches) {
-        if (L.ev_a) (void)hipEventDestroy(L.ev_a);
-        if (L.ev_b) (void)hipEventDestroy(L.ev_b);
-    }
+    for (auto* list : {&ex->launches, &ex->launches64})
+        for (auto& L : *list) {
+            if (L.ev_a) (void)hipEventDestroy(L.ev_a);
+            if (L.ev_b) (void)hipEventDestroy(L.ev_b);
+        }
+    if (ex->ev_fork) (void)hipEventDestroy(ex->ev_fork);
+    if (ex->ev_join) (void)hipEventDestroy(ex->ev_join);
+    if (ex->side) (void)hipStreamDestroy(ex->side);
     delete ex;
 }
 

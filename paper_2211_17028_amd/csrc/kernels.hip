@@ -262,44 +262,95 @@ __global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
 
 // ---------------------------------------------------------------------------
 // K2: batched bit permutation, staged through LDS.  A tile covers the lowest
-// `tb` bits of both the input and the output index (up to 2 tb bits), so the
-// loads run along the input's fastest legs and the stores along the output's.
-// The per-element offsets inside a tile come from a precomputed table; the
-// remaining (high) bits select the tile.
+// bits of both the input and the output index (up to 10 bits), so loads run
+// along the input's fastest legs and stores along the output's.  The offsets
+// inside a tile come from a precomputed table (staged in LDS once per block);
+// the remaining (high) bits select the tile, whose base is computed once.
+// A block moves kPermElems elements (several tiles when tiles are small).
+// Consecutive load slots are consecutive input addresses and consecutive
+// store slots consecutive output addresses, so when the tile has at least two
+// low bits each thread moves element pairs (16 B for complex64).
 // ---------------------------------------------------------------------------
+// elements per block: 32 KB of tile data; at most 256 tiles per block, so the
+// whole LDS use (tiles, 12 KB table, bases) stays under 48 KB
+template <typename T>
+__host__ __device__ constexpr int perm_elems() { return 32768 / (int)sizeof(T); }
+__host__ __device__ inline int perm_tiles_per_block(int tsize, int elems) {
+    const int u = tsize >= elems ? 1 : elems / tsize;
+    return u > 256 ? 256 : u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
     extern __shared__ unsigned char smem_raw[];
-    T* tile = (T*)smem_raw;
     const int tsize = 1 << p.tb;
-    const int upb = tsize >= 256 ? 1 : 256 / tsize;      // units (tiles) per block
-    const int stride = tsize >= 256 ? 256 : tsize;       // threads per unit
-    const int u = threadIdx.x / stride;
-    const int e0 = threadIdx.x - u * stride;
+    const int upb = perm_tiles_per_block(tsize, perm_elems<T>());  // tiles per block
+    T* tile = (T*)smem_raw;                                          // upb * tsize elements
+    int32_t* tab = (int32_t*)(tile + (int64_t)upb * tsize);          // 3 * tsize
+    int64_t* in_base = (int64_t*)(tab + 3 * tsize);                  // upb
+    int64_t* out_base = in_base + upb;                               // upb
     const int64_t highs = int64_t(1) << p.n_high;
-    const int64_t unit = (int64_t)blockIdx.x * upb + u;
-    const bool active = unit < p.n_inst * highs;
-    const int32_t* ld_in = p.table;
-    const int32_t* ld_pos = p.table + tsize;
-    const int32_t* st_out = p.table + 2 * tsize;
+    const int64_t units = p.n_inst * highs;
+    const int64_t unit0 = (int64_t)blockIdx.x * upb;
     const int64_t size = int64_t(1) << p.r;
-    T* t = tile + (int64_t)u * tsize;
-    int64_t in_base = 0, out_base = 0, inst = 0;
-    if (active) {
-        inst = unit >> p.n_high;
-        const int64_t h = unit & (highs - 1);
-        for (int i = 0; i < p.n_high; ++i)
-            if ((h >> i) & 1) {
-                in_base |= int64_t(1) << p.high_in[i];
-                out_base |= int64_t(1) << p.high_out[i];
-            }
-        const T* src = (const T*)p.src + inst * size + in_base;
-        for (int e = e0; e < tsize; e += stride) t[ld_pos[e]] = src[ld_in[e]];
+    for (int i = threadIdx.x; i < 3 * tsize; i += blockDim.x) tab[i] = p.table[i];
+    for (int u = threadIdx.x; u < upb; u += blockDim.x) {
+        const int64_t unit = unit0 + u;
+        int64_t ib = 0, ob = 0;
+        if (unit < units) {
+            const int64_t inst = unit >> p.n_high;
+            const int64_t h = unit & (highs - 1);
+            for (int i = 0; i < p.n_high; ++i)
+                if ((h >> i) & 1) {
+                    ib |= int64_t(1) << p.high_in[i];
+                    ob |= int64_t(1) << p.high_out[i];
+                }
+            ib += inst * size;
+            ob += inst * size;
+        }
+        in_base[u] = unit < units ? ib : -1;
+        out_base[u] = ob;
     }
     __syncthreads();
-    if (active) {
-        T* dst = (T*)p.dst + inst * size + out_base;
-        for (int e = e0; e < tsize; e += stride) dst[st_out[e]] = t[e];
+    const int32_t* ld_in = tab;
+    const int32_t* ld_pos = tab + tsize;
+    const int32_t* st_out = tab + 2 * tsize;
+    const int total = upb * tsize;
+    const T* __restrict__ src = (const T*)p.src;
+    T* __restrict__ dst = (T*)p.dst;
+    if (p.pair) {
+        for (int e2 = threadIdx.x; e2 < total / 2; e2 += blockDim.x) {
+            const int e = 2 * e2;
+            const int u = e >> p.tb, l = e & (tsize - 1);
+            if (in_base[u] < 0) continue;
+            const T* s2 = src + in_base[u] + ld_in[l];
+            const T a = s2[0], b = s2[1];
+            tile[u * tsize + ld_pos[l]] = a;
+            tile[u * tsize + ld_pos[l + 1]] = b;
+        }
+    } else {
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const int u = e >> p.tb, l = e & (tsize - 1);
+            if (in_base[u] < 0) continue;
+            tile[u * tsize + ld_pos[l]] = src[in_base[u] + ld_in[l]];
+        }
+    }
+    __syncthreads();
+    if (p.pair) {
+        for (int e2 = threadIdx.x; e2 < total / 2; e2 += blockDim.x) {
+            const int e = 2 * e2;
+            const int u = e >> p.tb, l = e & (tsize - 1);
+            if (in_base[u] < 0) continue;
+            T* d2 = dst + out_base[u] + st_out[l];
+            d2[0] = tile[u * tsize + l];
+            d2[1] = tile[u * tsize + l + 1];
+        }
+    } else {
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const int u = e >> p.tb, l = e & (tsize - 1);
+            if (in_base[u] < 0) continue;
+            dst[out_base[u] + st_out[l]] = tile[u * tsize + l];
+        }
     }
 }
 
@@ -507,10 +558,10 @@ int launch_gemm_c128(const GemmArgs& g, hipStream_t s) {
 template <typename T>
 static void launch_perm(const PermArgs& p, hipStream_t s) {
     const int tsize = 1 << p.tb;
-    const int upb = tsize >= 256 ? 1 : 256 / tsize;
+    const int upb = perm_tiles_per_block(tsize, perm_elems<T>());
     const int64_t units = p.n_inst << p.n_high;
     const unsigned blocks = (unsigned)((units + upb - 1) / upb);
-    const size_t lds = (size_t)upb * tsize * sizeof(T);
+    const size_t lds = (size_t)upb * tsize * sizeof(T) + 3 * tsize * sizeof(int32_t) + 2 * upb * sizeof(int64_t);
     hipLaunchKernelGGL((k_permute<T>), dim3(blocks), dim3(256), lds, s, p);
 }
 

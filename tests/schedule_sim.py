@@ -22,7 +22,14 @@ class Sim:
     def region(self, ref):
         return self.const if ref[0] == 0 else self.work
 
+    def _ref(self, ref):
+        # the FP64 pass lives after the FP32 work region
+        if ref[0] == 2:
+            return [1, ref[1] + self.desc["work1_bytes"]]
+        return ref
+
     def view(self, ref, dtype, count, extra_off=0):
+        ref = self._ref(ref)
         buf = self.region(ref)
         off = ref[1] + extra_off
         nbytes = np.dtype(dtype).itemsize * count
@@ -130,7 +137,7 @@ class Sim:
 
     def run(self, live_terms_per_plan=None):
         d = self.desc
-        batch = [L for L in d["launches"] if L["phase"] == "batch"]
+        batch = [L for L in d["launches"] if L["phase"] in ("batch", "batch64")]
         plain = [L for L in d["launches"] if L["phase"] == "plain"]
         tail = [L for L in d["launches"] if L["phase"] == "tail"]
         for L in batch:
