@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtn_gfx950.so")
-SOURCES = ["plan.cpp", "exec.hip", "kernels.hip"]
+SOURCES = ["plan.cpp", "exec.hip", "kernels.hip", "mlp.hip"]
 
 
 def hipcc():

@@ -1322,6 +1322,40 @@ int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, in
 }  // extern "C"
 
 // ===========================================================================
+// pruning features and threshold (include/tn_mlp.h)
+// ===========================================================================
+#include "tn_mlp.h"
+
+extern "C" int tn_terms_features(tn_plan plan, tn_terms terms, const double* level1_x, float* out) {
+    return guard([&] {
+        if (!plan || !terms || !out) fail(TN_EINVAL, "null argument");
+        const Plan* p = reinterpret_cast<const Plan*>(plan);
+        const Terms* t = reinterpret_cast<const Terms*>(terms);
+        if (t->plan_id != p->id) fail(TN_ESTATE, "term set belongs to another plan");
+        term_features(p, t, level1_x, out);
+    });
+}
+
+extern "C" int tn_prune_threshold(const float* pred, const double* x, int64_t n, double budget, float* tau) {
+    return guard([&] {
+        if (!pred || !x || !tau || n < 0 || budget < 0) fail(TN_EINVAL, "bad threshold arguments");
+        std::vector<int64_t> idx(n);
+        for (int64_t i = 0; i < n; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return pred[a] < pred[b]; });
+        // drop candidates in increasing predicted value while the dropped mass fits
+        double mass = 0;
+        float t = -INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t i = idx[j];
+            if (mass + x[i] > budget) break;
+            mass += x[i];
+            t = (j + 1 < n) ? pred[idx[j + 1]] : INFINITY;
+        }
+        *tau = t;
+    });
+}
+
+// ===========================================================================
 // kernel-level entry points (include/tn_kernels.h)
 // ===========================================================================
 #include "tn_kernels.h"

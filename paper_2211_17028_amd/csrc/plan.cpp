@@ -199,6 +199,15 @@ static NoiseSplit split_noise(const tn_op& op, int64_t index) {
                 }
     ns.norm_main = spectral_norm4(mm);
     ns.norm_bar = spectral_norm4(mb);
+    // ||sqrt(2) K_i||_2^2 = 2 sigma_max(K_i)^2, from the 2x2 Gram matrix
+    for (int i = 0; i < 4; ++i) {
+        const cd a = ns.K[i][0], b = ns.K[i][1], c = ns.K[i][2], d = ns.K[i][3];
+        const double g11 = std::norm(a) + std::norm(c), g22 = std::norm(b) + std::norm(d);
+        const double g12 = std::abs(std::conj(a) * b + std::conj(c) * d);
+        const double tr = g11 + g22, det = g11 * g22 - g12 * g12;
+        const double smax2 = 0.5 * (tr + std::sqrt(std::max(0.0, tr * tr - 4.0 * det)));
+        ns.khat_norm2[i] = 2.0 * smax2;
+    }
     return ns;
 }
 
@@ -740,7 +749,32 @@ Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, in
             p->noise.push_back(split_noise(op, k));
         }
     }
-    // state normalisation is the caller's choice; only finiteness is checked
+    // past light cone of every noise slot (features of the pruning policy)
+    p->n_ops = c->n_ops;
+    for (int64_t k = 0; k < c->n_ops; ++k)
+        if (c->ops[k].kind == TN_GATE && c->ops[k].nq == 2) ++p->n_2q_gates;
+    {
+        const int words = (c->n_qubits + 63) / 64;
+        for (NoiseSplit& ns : p->noise) {
+            std::vector<uint64_t> cone(words, 0);
+            cone[ns.qubit >> 6] |= 1ULL << (ns.qubit & 63);
+            int g2 = 0;
+            for (int64_t k = ns.op_index - 1; k >= 0; --k) {
+                const tn_op& op = c->ops[k];
+                if (op.kind != TN_GATE) continue;
+                bool hit = false;
+                for (int i = 0; i < op.nq; ++i) hit |= (cone[op.q[i] >> 6] >> (op.q[i] & 63)) & 1;
+                if (!hit) continue;
+                for (int i = 0; i < op.nq; ++i) cone[op.q[i] >> 6] |= 1ULL << (op.q[i] & 63);
+                if (op.nq == 2) ++g2;
+            }
+            int cnt = 0;
+            for (uint64_t w : cone) cnt += __builtin_popcountll(w);
+            ns.cone = std::move(cone);
+            ns.cone_qubits = cnt;
+            ns.cone_2q_gates = g2;
+        }
+    }
     p->n_noise = (int)p->noise.size();
     p->level_req = level;
     p->level = std::min(level, p->n_noise);
@@ -818,6 +852,67 @@ Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune) {
         fail(TN_EINVAL, "prune keep array length does not match the candidate count");
     t->n = (int64_t)t->w.size();
     return t.release();
+}
+
+// ---------------------------------------------------------------------------
+// pruning features of every term (kNumFeatures floats per term)
+//   per corrected slot j = 0..2 (in position order; zeros when absent), 9:
+//     present, log(d_i / d_0), one-hot(i) x3, position op_index / n_ops,
+//     cone qubits / n, cone 2-qubit gates / all 2-qubit gates,
+//     log X of the level-1 term with the same (slot, correction) (0 if absent)
+//   per pair (0,1), (0,2), (1,2), 2: cone overlap / smaller cone, |position
+//     difference| / n_ops
+//   global, 3: log of the term weight prod d / 2^N, level, and log of the
+//     rigorous bound of the term, weight * prod_s ||K_hat_{c_s}||_2^2
+//     (|a| <= prod of the slot norms for unit boundary states)
+// ---------------------------------------------------------------------------
+int term_features(const Plan* p, const Terms* t, const double* level1_x, float* out) {
+    const int N = p->n_noise;
+    const double tiny = 1e-300;
+    for (int64_t k = 0; k < t->n; ++k) {
+        float* f = out + k * kNumFeatures;
+        for (int i = 0; i < kNumFeatures; ++i) f[i] = 0.0f;
+        const int8_t* pat = &t->pat[k * N];
+        int slots[3], corr[3], u = 0;
+        for (int s = 0; s < N && u < 3; ++s)
+            if (pat[s]) {
+                slots[u] = s;
+                corr[u] = pat[s];
+                ++u;
+            }
+        for (int j = 0; j < u; ++j) {
+            const NoiseSplit& ns = p->noise[slots[j]];
+            float* g = f + 9 * j;
+            g[0] = 1.0f;
+            g[1] = (float)std::log(std::max(ns.d[corr[j]], tiny) / ns.d[0]);
+            g[2 + (corr[j] - 1)] = 1.0f;
+            g[5] = (float)((double)ns.op_index / std::max<int64_t>(1, p->n_ops));
+            g[6] = (float)((double)ns.cone_qubits / p->n_qubits);
+            g[7] = (float)((double)ns.cone_2q_gates / std::max(1, p->n_2q_gates));
+            if (level1_x) {
+                const double x1 = level1_x[1 + 3 * slots[j] + (corr[j] - 1)];
+                g[8] = (float)std::log(std::max(x1, tiny));
+            }
+        }
+        const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int q = 0; q < 3; ++q) {
+            const int a = pairs[q][0], b = pairs[q][1];
+            if (b >= u) continue;
+            const NoiseSplit& na = p->noise[slots[a]];
+            const NoiseSplit& nb = p->noise[slots[b]];
+            int inter = 0;
+            for (size_t w = 0; w < na.cone.size(); ++w) inter += __builtin_popcountll(na.cone[w] & nb.cone[w]);
+            f[27 + 2 * q] = (float)inter / (float)std::max(1, std::min(na.cone_qubits, nb.cone_qubits));
+            f[28 + 2 * q] = (float)((double)std::llabs(na.op_index - nb.op_index) / std::max<int64_t>(1, p->n_ops));
+        }
+        const double what = std::ldexp(t->w[k], -N);
+        f[33] = (float)std::log(std::max(what, tiny));
+        f[34] = (float)t->lvl[k];
+        double lb = std::log(std::max(what, tiny));
+        for (int s = 0; s < N; ++s) lb += std::log(p->noise[s].khat_norm2[pat[s]]);
+        f[35] = (float)lb;
+    }
+    return kNumFeatures;
 }
 
 std::string describe_plan(const Plan* p) {

@@ -35,6 +35,11 @@ struct NoiseSplit {
     double rate = 0;              // ||M - I||_2
     double norm_main = 0;         // ||U_0 (x) V_0||_2
     double norm_bar = 0;          // ||sum_{i>=1} U_i (x) V_i||_2
+    // structure of the slot's past light cone (pruning features)
+    std::vector<uint64_t> cone;   // bitset of qubits in the past light cone
+    int cone_qubits = 0;
+    int cone_2q_gates = 0;        // 2-qubit gates in the past light cone
+    double khat_norm2[4] = {0, 0, 0, 0};  // ||sqrt(2) K_i||_2^2 (term bound factor)
 };
 
 // One tensor of the reduced ket network.  All legs have dimension 2;
@@ -60,6 +65,8 @@ struct Cluster {
 struct Plan {
     uint64_t id = 0;
     int n_qubits = 0;
+    int64_t n_ops = 0;
+    int n_2q_gates = 0;
     int n_noise = 0;
     int level_req = 0;
     int level = 0;
@@ -90,6 +97,8 @@ Plan* build_plan(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
                  const tn_plan_opts* opts);
 Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune);
 std::string describe_plan(const Plan* p);
+int term_features(const Plan* p, const Terms* t, const double* level1_x, float* out);
+constexpr int kNumFeatures = 36;
 void jacobi_hermitian4(const cd a_in[4][4], double evals[4], cd evecs[4][4]);
 double spectral_norm4(const cd a[4][4]);
 

@@ -461,3 +461,109 @@ def kernel_permute(src, dst, r, perm, stream=None):
     _check(_kernel_lib().tn_kernel_permute(fp64, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
                                            src.shape[0], r, p.ctypes.data if r else None,
                                            _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------------------
+# learned pruning (include/tn_mlp.h)
+# ---------------------------------------------------------------------------
+TN_N_FEATURES = 36
+
+
+class tn_mlp_shape(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32)]
+
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_sigs", False):
+        vp = C.c_void_p
+        sp = C.POINTER(tn_mlp_shape)
+        L.tn_mlp_sizes.argtypes = [sp, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_size_t),
+                                   C.POINTER(C.c_size_t)]
+        L.tn_mlp_init.argtypes = [sp, C.c_uint64, vp, vp]
+        L.tn_mlp_fit_normalizer.argtypes = [sp, vp, vp, C.c_int64, vp]
+        L.tn_mlp_forward.argtypes = [sp, vp, vp, C.c_int64, vp, vp, vp]
+        L.tn_mlp_gradients.argtypes = [sp, vp, vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.tn_mlp_adam.argtypes = [sp, vp, C.c_float, C.c_int32, vp]
+        L.tn_mlp_train_step.argtypes = [sp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_int32, vp, vp, vp]
+        L.tn_terms_features.argtypes = [vp, vp, vp, vp]
+        L.tn_prune_threshold.argtypes = [vp, vp, C.c_int64, C.c_double, C.POINTER(C.c_float)]
+        L.tn_mlp_log_targets.argtypes = [vp, vp, C.c_int64, C.c_double, vp]
+        for n in ("tn_mlp_sizes", "tn_mlp_init", "tn_mlp_fit_normalizer", "tn_mlp_forward", "tn_mlp_gradients",
+                  "tn_mlp_adam", "tn_mlp_train_step", "tn_terms_features", "tn_prune_threshold",
+                  "tn_mlp_log_targets"):
+            getattr(L, n).restype = C.c_int
+        L._mlp_sigs = True
+    return L
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def tn_terms_features(plan: Plan, terms: Terms, level1_x: Optional[np.ndarray] = None) -> np.ndarray:
+    out = np.zeros((max(1, terms.n), TN_N_FEATURES), dtype=np.float32)
+    lx = None if level1_x is None else np.ascontiguousarray(level1_x, dtype=np.float64)
+    _check(_mlp_lib().tn_terms_features(plan.handle, terms.handle, lx.ctypes.data if lx is not None else None,
+                                        out.ctypes.data))
+    return out[:terms.n]
+
+
+def tn_prune_threshold(pred: np.ndarray, x: np.ndarray, budget: float) -> float:
+    p = np.ascontiguousarray(pred, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    tau = C.c_float()
+    _check(_mlp_lib().tn_prune_threshold(p.ctypes.data, xx.ctypes.data, p.size, budget, C.byref(tau)))
+    return tau.value
+
+
+class MLP:
+    """Device state of the pruning network (torch-allocated)."""
+
+    def __init__(self, n_in=TN_N_FEATURES, width=128, depth=3, seed=2211170280, max_batch=1 << 16, stream=None):
+        import torch
+        self.shape = tn_mlp_shape(n_in, width, depth)
+        npar, sb, wb = C.c_int64(), C.c_size_t(), C.c_size_t()
+        _check(_mlp_lib().tn_mlp_sizes(C.byref(self.shape), max_batch, C.byref(npar), C.byref(sb), C.byref(wb)))
+        self.n_params = npar.value
+        self.max_batch = max_batch
+        self.state = torch.zeros(sb.value // 4, dtype=torch.float32, device="cuda")
+        self.ws = torch.zeros(wb.value // 4, dtype=torch.float32, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.step = 0
+        _check(_mlp_lib().tn_mlp_init(C.byref(self.shape), seed, _ptr(self.state), _stream_ptr(stream)))
+
+    def fit_normalizer(self, x, stream=None):
+        _check(_mlp_lib().tn_mlp_fit_normalizer(C.byref(self.shape), _ptr(self.state), _ptr(x), x.shape[0],
+                                                _stream_ptr(stream)))
+
+    def forward(self, x, stream=None):
+        import torch
+        out = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        for s in range(0, x.shape[0], self.max_batch):
+            e = min(x.shape[0], s + self.max_batch)
+            _check(_mlp_lib().tn_mlp_forward(C.byref(self.shape), _ptr(self.state), _ptr(x[s:e]), e - s,
+                                              _ptr(out[s:e]), _ptr(self.ws), _stream_ptr(stream)))
+        return out
+
+    def gradients(self, x, t, w=None, stream=None):
+        _check(_mlp_lib().tn_mlp_gradients(C.byref(self.shape), _ptr(self.state), _ptr(x), _ptr(t), _ptr(w),
+                                           x.shape[0], _ptr(self.ws), _ptr(self.loss), _stream_ptr(stream)))
+
+    def adam(self, lr, stream=None):
+        self.step += 1
+        _check(_mlp_lib().tn_mlp_adam(C.byref(self.shape), _ptr(self.state), lr, self.step, _stream_ptr(stream)))
+
+    def train_step(self, x, t, w=None, lr=1e-3, stream=None):
+        self.step += 1
+        _check(_mlp_lib().tn_mlp_train_step(C.byref(self.shape), _ptr(self.state), _ptr(x), _ptr(t), _ptr(w),
+                                            x.shape[0], lr, self.step, _ptr(self.ws), _ptr(self.loss),
+                                            _stream_ptr(stream)))
+
+
+def tn_mlp_log_targets(x_dev, floor=1e-30, stream=None):
+    """float32 log(max(x, floor)) of a float64 device tensor, computed on the device."""
+    import torch
+    t = torch.empty(x_dev.shape[0], dtype=torch.float32, device="cuda")
+    _check(_mlp_lib().tn_mlp_log_targets(_ptr(x_dev), _ptr(t), x_dev.shape[0], floor, _stream_ptr(stream)))
+    return t

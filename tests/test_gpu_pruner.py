@@ -1,0 +1,98 @@
+"""GPU tests of the learned pruning (a policy on top of Algorithm 1):
+network kernels against the FP64 reference network, and what the trained
+network gains over pruning by the rigorous per-term bound."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as omlp
+from paper_2211_17028_amd import pruner, tn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def test_mlp_kernels_match_the_fp64_reference(torch):
+    print("mlp gradient check", flush=True)
+    rng = np.random.default_rng(5)
+    n_in, width, depth, n = 36, 128, 3, 777
+    net = tn.MLP(n_in=n_in, width=width, depth=depth, seed=11, max_batch=1024)
+    x = rng.standard_normal((n, n_in)).astype(np.float32) * 3 + 1
+    t = rng.standard_normal(n).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    xd, td, wd = (torch.from_numpy(a).cuda() for a in (x, t, w))
+    net.fit_normalizer(xd)
+    net.gradients(xd, td, wd)
+    torch.cuda.synchronize()
+    st = net.state.cpu().numpy().astype(np.float64)
+    # normalizer = column mean and 1/std
+    assert np.allclose(st[:n_in], x.mean(0), rtol=1e-5, atol=1e-5)
+    assert np.allclose(st[n_in:2 * n_in], 1 / x.std(0), rtol=1e-4)
+    P = net.n_params
+    y_ref, _ = omlp.forward(st, x, n_in, width, depth)
+    y_gpu = net.forward(xd).cpu().numpy()
+    assert np.allclose(y_gpu, y_ref, rtol=1e-4, atol=1e-4)
+    g_ref = omlp.gradients(st, x, t, w, n_in, width, depth)
+    g_gpu = st[2 * n_in + P:2 * n_in + 2 * P]
+    rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
+    assert rel <= 1e-4, rel
+    loss_ref = omlp.loss(st, x, t, w, n_in, width, depth)
+    assert abs(net.loss.item() - loss_ref) <= 1e-4 * loss_ref
+    # one Adam step
+    params = st[2 * n_in:2 * n_in + P]
+    net.adam(1e-3)
+    torch.cuda.synchronize()
+    p_ref, _, _ = omlp.adam(params, g_gpu, np.zeros(P), np.zeros(P), 1e-3, 1)
+    p_gpu = net.state.cpu().numpy().astype(np.float64)[2 * n_in:2 * n_in + P]
+    assert np.allclose(p_gpu, p_ref, rtol=1e-5, atol=1e-6)
+
+
+def test_learned_pruning_beats_the_bound_policy(torch):
+    """Train on the term values of configs 2-4 (config 4: 16 of its circuits),
+    then prune the level-2/3 candidates of config 5 (15x15 grid, level 3).
+    At the same pruned-mass budget the trained network must keep fewer terms
+    than ranking by the rigorous per-term bound, and at the same kept count its
+    pruning error must be smaller.  The pruned estimate never exceeds the full
+    one (terms are non-negative) and its error stays within the budget."""
+    print("pruner training", flush=True)
+    data = [pruner.training_data(W.config(2)), pruner.training_data(W.config(3))]
+    for c in W.config(4)[:16]:
+        data.append(pruner.training_data(c))
+    net, hist, (f_dev, xs) = pruner.train(data, epochs=30)
+    assert hist[-1] < 0.5 * hist[0]
+    feats = f_dev.cpu().numpy()
+    total = sum(d[2]["A"][-1] for d in data)
+    budget = 1e-7 * total
+    tau_mlp = pruner.threshold(pruner.score_candidates(net, feats, "mlp"), xs, budget)
+    tau_bnd = pruner.threshold(pruner.score_candidates(net, feats, "bound"), xs, budget)
+    c5 = W.config(5)
+    plan, terms, full, x = pruner.full_run(c5)
+    a_full = full["A"][-1]
+    rm = pruner.pruned_estimate(c5, net, tau_mlp, "mlp")
+    rb = pruner.pruned_estimate(c5, net, tau_bnd, "bound")
+    err_m = a_full - rm["result"]["A"][-1]
+    err_b = a_full - rb["result"]["A"][-1]
+    print(f"full {a_full:.12f}; mlp kept {rm['kept']}/{rm['candidates']} err {err_m:.3e}; "
+          f"bound kept {rb['kept']}/{rb['candidates']} err {err_b:.3e}", flush=True)
+    assert err_m >= -1e-12 and err_b >= -1e-12
+    assert err_m <= 1e-6 * a_full
+    assert rm["kept"] < rb["kept"]
+    # matched kept count: the bound policy keeps the same number of top-ranked terms
+    cand, live = pruner.candidate_mask(terms)
+    n1 = 1 + 3 * c5.n_noises
+    x1 = x[:n1]
+    f5 = tn.tn_terms_features(plan, terms, x1)[cand]
+    xc = x[cand]
+    s_m = pruner.score_candidates(net, f5, "mlp")
+    s_b = pruner.score_candidates(net, f5, "bound")
+    k = rm["kept"]
+    drop_m = xc[np.argsort(-s_m)[k:]].sum()
+    drop_b = xc[np.argsort(-s_b)[k:]].sum()
+    print(f"matched count {k}: dropped mass mlp {drop_m:.3e} bound {drop_b:.3e}", flush=True)
+    assert drop_m < drop_b

@@ -184,3 +184,37 @@ def test_schedule_replay_config1_against_oracle():
     r = estimate.estimate(c, 2, "network")
     assert np.allclose(x, r["X"], rtol=2e-5, atol=1e-10)
     assert abs(x.sum() - r["A"][2]) < 1e-6 * r["A"][2]
+
+
+def test_bound_feature_bounds_every_term_and_features_are_finite():
+    # |a| <= prod of the slot spectral norms for unit states and unitary gates,
+    # so X_t <= w_t prod ||K_hat||^2 = exp(feature 35) for every term
+    for seed, kind in ((41, "adpd"), (42, "random"), (43, "depol")):
+        c = W.tiny_random_circuit(np.random.default_rng(seed), 4, 20, 5, noise=kind, level=3)
+        plan = tn.tn_plan_build(c, 3)
+        t = tn.tn_terms_enumerate(plan, 3)
+        r = estimate.estimate(c, 3, "network")
+        f = tn.tn_terms_features(plan, t, r["X"][:16])
+        assert f.shape == (t.n, tn.TN_N_FEATURES) and np.all(np.isfinite(f))
+        pat, w = t.get()
+        # terms whose weight the library takes as exactly zero (a singular
+        # value at rounding level) are excluded; the oracle gives them ~1e-18
+        live = (r["X"] > 0) & (w > 0)
+        assert np.all(r["X"][live] <= np.exp(f[live, 35].astype(np.float64)) * (1 + 1e-5))
+        assert np.all(r["X"][w == 0] < 1e-15)
+        assert np.array_equal(f[:, 34], (pat != 0).sum(1))
+
+
+def test_prune_threshold_respects_the_budget():
+    rng = np.random.default_rng(9)
+    x = rng.exponential(1.0, 1000)
+    pred = np.log(x) + rng.normal(0, 0.5, 1000)
+    for budget in (0.0, 1.0, 10.0, 100.0, 1e9):
+        tau = tn.tn_prune_threshold(pred, x, budget)
+        dropped = x[pred.astype(np.float32) < np.float32(tau)].sum()
+        assert dropped <= budget + 1e-9
+        # dropping one more candidate (the next by score) would exceed the budget
+        rest = np.sort(pred.astype(np.float32)[pred.astype(np.float32) >= np.float32(tau)])
+        if rest.size and budget < 1e9:
+            nxt = pred.astype(np.float32) == rest[0]
+            assert dropped + x[nxt].sum() > budget
