@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -40,13 +41,18 @@ void k_gemm_mfma(GemmArgs g) {
     constexpr int TM = BM / WM / 32;
     constexpr int TN = BNC / WN / 16;
     constexpr int BKC = 8;
-    __shared__ float As_re[BKC][BM];
-    __shared__ float As_im[BKC][BM];
-    __shared__ float2 Bs[BKC][BNC];
+    constexpr int AE = (BM * BKC + NT - 1) / NT;     // A elements per thread per chunk
+    constexpr int BE = (BKC * BNC + NT - 1) / NT;    // B elements per thread per chunk
+    // double-buffered LDS: A planar (re, im) [k][row], B interleaved [k][col]
+    __shared__ float As_re[2][BKC][BM];
+    __shared__ float As_im[2][BKC][BM];
+    __shared__ float2 Bs[2][BKC][BNC];
 
     const int m_log = g.m_log, n_log = g.n_log, k_log = g.k_log;
     const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
-    const int tn_log = n_log - __builtin_ctz(BNC);
+    // n < BNC happens only for the 16-column tiles: the tile is padded with
+    // zero columns that are never stored
+    const int tn_log = n_log >= __builtin_ctz(BNC) ? n_log - __builtin_ctz(BNC) : 0;
     const int64_t tiles = (m / BM) << tn_log;
     const int64_t blk = blockIdx.x;
     const int64_t inst = blk / tiles;
@@ -72,48 +78,94 @@ void k_gemm_mfma(GemmArgs g) {
     const int kc_log = k_log < 3 ? k_log : 3;
     const int half = lane >> 5;             // 0: real slice, 1: imaginary slice
     const int sub = lane & 31;
-    for (int64_t k0 = 0; k0 < k; k0 += kc) {
-        for (int e = threadIdx.x; e < BM * kc; e += NT) {
-            int r, p;
-            float2 v;
-            if (!g.transA) {
-                r = e >> kc_log;
-                p = e & (kc - 1);
-                v = A[(tm0 + r) * k + k0 + p];
-            } else {
-                p = e / BM;
-                r = e % BM;
-                v = A[(k0 + p) * m + tm0 + r];
+    float2 ra[AE], rb[BE];
+    // global -> registers for the chunk starting at k0
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (e < BM * kc) {
+                if (!g.transA) {
+                    const int r = e >> kc_log, p = e & (kc - 1);
+                    v = A[(tm0 + r) * k + k0 + p];
+                } else {
+                    const int p = e / BM, r = e % BM;
+                    v = A[(k0 + p) * m + tm0 + r];
+                }
             }
-            As_re[p][r] = v.x;
-            As_im[p][r] = v.y;
+            ra[q] = v;
         }
-        for (int e = threadIdx.x; e < kc * BNC; e += NT) {
-            int p, c;
-            float2 v;
-            if (!g.transB) {
-                p = e / BNC;
-                c = e % BNC;
-                v = B[(k0 + p) * n + tn0 + c];
-            } else {
-                c = e >> kc_log;
-                p = e & (kc - 1);
-                v = B[(tn0 + c) * k + k0 + p];
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (e < kc * BNC) {
+                int p, c;
+                if (!g.transB) {
+                    p = e / BNC;
+                    c = e % BNC;
+                } else {
+                    c = e >> kc_log;
+                    p = e & (kc - 1);
+                }
+                if (tn0 + c < n) v = g.transB ? B[(tn0 + c) * k + k0 + p] : B[(k0 + p) * n + tn0 + c];
             }
-            Bs[p][c] = v;
+            rb[q] = v;
         }
-        __syncthreads();
+    };
+    // registers -> LDS buffer `buf`
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < BM * kc) {
+                int r, p;
+                if (!g.transA) {
+                    r = e >> kc_log;
+                    p = e & (kc - 1);
+                } else {
+                    p = e / BM;
+                    r = e % BM;
+                }
+                As_re[buf][p][r] = ra[q].x;
+                As_im[buf][p][r] = ra[q].y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < kc * BNC) {
+                int p, c;
+                if (!g.transB) {
+                    p = e / BNC;
+                    c = e % BNC;
+                } else {
+                    c = e >> kc_log;
+                    p = e & (kc - 1);
+                }
+                Bs[buf][p][c] = rb[q];
+            }
+        }
+    };
+    const int64_t nchunks = k / kc;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int buf = (int)(ch & 1);
+        if (ch + 1 < nchunks) load((ch + 1) * kc);     // in flight during the MFMAs below
         for (int p = 0; p < kc; ++p) {
             float a[TM], b[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int row = wm * (TM * 32) + i * 32 + sub;
-                a[i] = half ? As_im[p][row] : As_re[p][row];
+                a[i] = half ? As_im[buf][p][row] : As_re[buf][p][row];
             }
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
-                const float2 bv = Bs[p][col];
+                const float2 bv = Bs[buf][p][col];
                 const int t = sub & 1;
                 b[j] = half == 0 ? (t == 0 ? bv.x : bv.y) : (t == 0 ? -bv.y : bv.x);
             }
@@ -123,6 +175,7 @@ void k_gemm_mfma(GemmArgs g) {
                 for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        if (ch + 1 < nchunks) stash(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
@@ -130,6 +183,7 @@ void k_gemm_mfma(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const int64_t colf = 2 * (tn0 + wn * (TN * 16) + j * 16) + sub;
+            if (colf >= 2 * n) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = tm0 + wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -285,9 +339,11 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
     extern __shared__ unsigned char smem_raw[];
     const int tsize = 1 << p.tb;
     const int upb = perm_tiles_per_block(tsize, perm_elems<T>());  // tiles per block
-    T* tile = (T*)smem_raw;                                          // upb * tsize elements
-    int32_t* tab = (int32_t*)(tile + (int64_t)upb * tsize);          // 3 * tsize
-    int64_t* in_base = (int64_t*)(tab + 3 * tsize);                  // upb
+    // tile elements, one padding element after every 32 (transposes write the
+    // tile with a stride of 32 elements)
+    T* tile = (T*)smem_raw;                                          // upb * tsize * 33 / 32 elements
+    int32_t* tab = (int32_t*)(tile + (int64_t)upb * tsize + ((int64_t)upb * tsize >> 5));  // 3 * tsize
+    int64_t* in_base = (int64_t*)(tab + ((3 * tsize + 1) & ~1));     // upb (8-byte aligned)
     int64_t* out_base = in_base + upb;                               // upb
     const int64_t highs = int64_t(1) << p.n_high;
     const int64_t units = p.n_inst * highs;
@@ -325,14 +381,16 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
             if (in_base[u] < 0) continue;
             const T* s2 = src + in_base[u] + ld_in[l];
             const T a = s2[0], b = s2[1];
-            tile[u * tsize + ld_pos[l]] = a;
-            tile[u * tsize + ld_pos[l + 1]] = b;
+            const int t0 = u * tsize + ld_pos[l], t1 = u * tsize + ld_pos[l + 1];
+            tile[t0 + (t0 >> 5)] = a;
+            tile[t1 + (t1 >> 5)] = b;
         }
     } else {
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
             const int u = e >> p.tb, l = e & (tsize - 1);
             if (in_base[u] < 0) continue;
-            tile[u * tsize + ld_pos[l]] = src[in_base[u] + ld_in[l]];
+            const int t0 = u * tsize + ld_pos[l];
+            tile[t0 + (t0 >> 5)] = src[in_base[u] + ld_in[l]];
         }
     }
     __syncthreads();
@@ -342,14 +400,16 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
             const int u = e >> p.tb, l = e & (tsize - 1);
             if (in_base[u] < 0) continue;
             T* d2 = dst + out_base[u] + st_out[l];
-            d2[0] = tile[u * tsize + l];
-            d2[1] = tile[u * tsize + l + 1];
+            const int t0 = u * tsize + l;
+            d2[0] = tile[t0 + (t0 >> 5)];
+            d2[1] = tile[t0 + 1 + ((t0 + 1) >> 5)];
         }
     } else {
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
             const int u = e >> p.tb, l = e & (tsize - 1);
             if (in_base[u] < 0) continue;
-            dst[out_base[u] + st_out[l]] = tile[u * tsize + l];
+            const int t0 = u * tsize + l;
+            dst[out_base[u] + st_out[l]] = tile[t0 + (t0 >> 5)];
         }
     }
 }
@@ -457,8 +517,11 @@ static const TileCfg kTiles[K_MFMA_TILES] = {{128, 64}, {64, 64}, {128, 32}, {64
 
 bool mfma_tile_fits(int tile, const GemmArgs& g) {
     if (tile < 0 || tile >= K_MFMA_TILES) return false;
-    return g.m_log >= 5 && g.n_log >= 4 && (int64_t(1) << g.m_log) >= kTiles[tile].bm &&
-           (int64_t(1) << g.n_log) >= kTiles[tile].bnc;
+    if (g.m_log < 5 || (int64_t(1) << g.m_log) < kTiles[tile].bm) return false;
+    // 16-column tiles also take n < 16 (zero-padded columns) when the GEMM is
+    // long enough in m and k to be worth the matrix cores
+    if (kTiles[tile].bnc == 16 && g.n_log < 4) return g.n_log >= 1 && g.m_log >= 7 && g.k_log >= 3;
+    return (int64_t(1) << g.n_log) >= kTiles[tile].bnc;
 }
 
 int select_gemm(const GemmArgs& g, int fp64, int tile_hint) {
@@ -496,7 +559,8 @@ int kernel_class(int id) {
 }
 
 static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s) {
-    const int64_t tiles = ((int64_t(1) << g.m_log) / t.bm) * ((int64_t(1) << g.n_log) / t.bnc);
+    const int64_t ntiles = std::max<int64_t>(1, (int64_t(1) << g.n_log) / t.bnc);
+    const int64_t tiles = ((int64_t(1) << g.m_log) / t.bm) * ntiles;
     const unsigned blocks = (unsigned)(tiles * g.n_inst);
 #define TN_LAUNCH(BM_, BN_)                                                                   \
     if (t.bm == BM_ && t.bnc == BN_) {                                                         \
@@ -561,7 +625,9 @@ static void launch_perm(const PermArgs& p, hipStream_t s) {
     const int upb = perm_tiles_per_block(tsize, perm_elems<T>());
     const int64_t units = p.n_inst << p.n_high;
     const unsigned blocks = (unsigned)((units + upb - 1) / upb);
-    const size_t lds = (size_t)upb * tsize * sizeof(T) + 3 * tsize * sizeof(int32_t) + 2 * upb * sizeof(int64_t);
+    const size_t elems = (size_t)upb * tsize;
+    const size_t lds = (elems + (elems >> 5)) * sizeof(T) + ((3 * tsize + 1) & ~1) * sizeof(int32_t) +
+                       2 * upb * sizeof(int64_t);
     hipLaunchKernelGGL((k_permute<T>), dim3(blocks), dim3(256), lds, s, p);
 }
 
