@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -115,7 +116,8 @@ def main():
     # timed region: eager launches with a HIP event pair around every GEMM /
     # permute launch on the launch stream (per-kernel durations for the roofline)
     t0 = time.perf_counter()
-    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, time_kernels=True))
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, time_kernels=True,
+                                                          tune=not args.no_tune))
     prep_s = time.perf_counter() - t0
     for _ in range(args.warmup):
         res = ex.run()[0]
@@ -134,7 +136,7 @@ def main():
     # the same schedule captured once in a hipGraph and replayed
     graph = None
     if not args.no_graph:
-        exg = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True))
+        exg = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True, tune=not args.no_tune))
         for _ in range(args.warmup):
             exg.run()
         torch.cuda.synchronize()

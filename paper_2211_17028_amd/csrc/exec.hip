@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <sstream>
+#include <tuple>
 #include <unordered_map>
 
 #include "kernels.h"
@@ -848,6 +849,55 @@ static void run_body(tn_exec_s* ex, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
+// Autotuner: time every MFMA tile that fits each FP32 batched GEMM of the
+// schedule (HIP events, median of a few launches on the real operands) and
+// keep the fastest.  Choices are cached per (shape, transposes, batch count).
+// Only the work region is written (GEMM outputs never live in the constant
+// region), and it holds no data before the first run.
+static void autotune(tn_exec_s* ex) {
+    hipStream_t s = ex->stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::map<std::tuple<int, int, int, int, int, int64_t>, int> cache;
+    for (auto& L : ex->launches) {
+        if (L.kind != L_GEMM || L.fp64 || L.g.n_inst == 0 || kernel_class(L.kclass) != KC_MFMA) continue;
+        auto key = std::make_tuple(L.g.m_log, L.g.n_log, L.g.k_log, L.g.transA, L.g.transB, L.g.n_inst);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            L.kclass = it->second;
+            continue;
+        }
+        int best = L.kclass;
+        float best_ms = 1e30f;
+        for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+            if (!mfma_tile_fits(tile, L.g)) continue;
+            float med = 0;
+            std::vector<float> ts;
+            for (int rep = 0; rep < 4; ++rep) {
+                HIPCHK(hipEventRecord(e0, s));
+                launch_gemm_id(tile, L.g, s);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ts.push_back(ms);    // first launch warms caches
+            }
+            std::sort(ts.begin(), ts.end());
+            med = ts[ts.size() / 2];
+            if (med < best_ms) {
+                best_ms = med;
+                best = tile;
+            }
+        }
+        L.kclass = best;
+        cache[key] = best;
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
 static std::string describe_exec(const tn_exec_s* ex) {
     std::ostringstream os;
     os.precision(10);
@@ -1062,6 +1112,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
                     }
         HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
                               ex->stream));
+        if (ex->opts.tune) autotune(ex.get());
         HIPCHK(hipEventCreate(&ex->ev0));
         HIPCHK(hipEventCreate(&ex->ev1));
         HIPCHK(hipStreamSynchronize(ex->stream));

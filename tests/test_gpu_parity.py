@@ -288,3 +288,20 @@ def test_packed_uneven_batch_against_oracle(torch):
                 tol = 1e-12 if j == 0 else 2e-5
                 assert abs(got - ref) <= tol * ref + 1e-15, (c.name, keys[j], got, ref)
     assert n_full >= 3
+
+
+def test_autotuned_schedule_gives_the_same_estimate(torch):
+    """Tiles chosen by timing change rounding only: the estimate stays within
+    the parity bar of the oracle's stored sums and of the untuned run."""
+    c = W.config(2)
+    plan = tn.tn_plan_build(c, 2)
+    terms = tn.tn_terms_enumerate(plan, 2)
+    r0 = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False)).run()[0]
+    ext = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True, tune=True))
+    r1 = ext.run()[0]
+    gold = np.loadtxt(os.path.join(GOLD, "config2_oracle.txt"))
+    for u in range(3):
+        assert abs(r1["A"][u] - gold[u]) <= 1e-6 * gold[u]
+        assert abs(r1["A"][u] - r0["A"][u]) <= 1e-9 * gold[u]
+    kernels = {L.get("kernel") for L in ext.describe()["launches"] if L["kind"] == 1}
+    assert any(k and k.startswith("k_gemm_mfma") for k in kernels)
