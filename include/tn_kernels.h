@@ -16,7 +16,9 @@
  * tn_kernel_permute: dst[i] = src[i] with its r legs reordered, for n_inst
  *   instances of 2^r elements: output bit j (counted from the least
  *   significant) takes input bit perm[j].  fp64 selects complex128 elements.
- *   Device pointers; `perm` is a host array of r ints.
+ *   Device pointers; `perm` is a host array of r ints.  block_elems_log: log2
+ *   of the elements one block moves (0 = the library default; at most 12 for
+ *   complex64, 11 for complex128).  Synchronizes `stream`.
  */
 #ifndef TN_KERNELS_H
 #define TN_KERNELS_H
@@ -29,7 +31,7 @@ int tn_kernel_gemm(int32_t fp64, const void* A, const void* B, void* C, const in
                    int32_t k_log, int32_t transA, int32_t transB, int64_t n_inst, int32_t tile_hint,
                    void* stream);
 int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64_t n_inst, int32_t r,
-                      const int32_t* perm, void* stream);
+                      const int32_t* perm, int32_t block_elems_log, void* stream);
 #ifdef __cplusplus
 }
 #endif

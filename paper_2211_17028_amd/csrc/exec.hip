@@ -1444,9 +1444,10 @@ extern "C" int tn_kernel_gemm(int32_t fp64, const void* A, const void* B, void* 
 }
 
 extern "C" int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64_t n_inst, int32_t r,
-                                 const int32_t* perm, void* stream) {
+                                 const int32_t* perm, int32_t block_elems_log, void* stream) {
     return guard([&] {
-        if (r < 0 || r > 32 || n_inst < 1 || !src || !dst || (r > 0 && !perm))
+        if (r < 0 || r > 32 || n_inst < 1 || !src || !dst || (r > 0 && !perm) || block_elems_log < 0 ||
+            block_elems_log > (fp64 ? 11 : 12))
             fail(TN_EINVAL, "bad permute arguments");
         // express the permutation as source/destination leg orders
         std::vector<int> src_legs(r), dst_legs(r);
@@ -1470,6 +1471,7 @@ extern "C" int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64
         L.p.dst = dst;
         L.p.n_inst = n_inst;
         L.p.table = (const int32_t*)((char*)dtab + L.table.off);
+        L.p.elems_log = block_elems_log;
         if (fp64) launch_permute_c128(L.p, s);
         else launch_permute_c64(L.p, s);
         HIPCHK(hipGetLastError());

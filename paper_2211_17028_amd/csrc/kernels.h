@@ -33,6 +33,7 @@ struct PermArgs {
     int n_high;                    // r - tb
     int high_out[32];              // out bit positions of the high (block) bits
     int high_in[32];               // matching in bit positions
+    int elems_log;                 // log2 elements moved per block (0 = default: 32 KB of data)
     int pair;                      // 1: the lowest input and output bits are tile bits 0 and
                                    //    the tile has >= 2 of each, so slots 2i, 2i+1 are adjacent
 };

@@ -43,10 +43,12 @@ void k_gemm_mfma(GemmArgs g) {
     constexpr int BKC = 8;
     constexpr int AE = (BM * BKC + NT - 1) / NT;     // A elements per thread per chunk
     constexpr int BE = (BKC * BNC + NT - 1) / NT;    // B elements per thread per chunk
-    // double-buffered LDS: A planar (re, im) [k][row], B interleaved [k][col]
-    __shared__ float As_re[2][BKC][BM];
-    __shared__ float As_im[2][BKC][BM];
-    __shared__ float2 Bs[2][BKC][BNC];
+    // double-buffered LDS: A planar (re, im) [k][row], B interleaved [k][col];
+    // rows padded by one element so that threads staging consecutive k of the
+    // same row (or column) land in different banks
+    __shared__ float As_re[2][BKC][BM + 1];
+    __shared__ float As_im[2][BKC][BM + 1];
+    __shared__ float2 Bs[2][BKC][BNC + 1];
 
     const int m_log = g.m_log, n_log = g.n_log, k_log = g.k_log;
     const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
@@ -325,20 +327,26 @@ __global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
 // store slots consecutive output addresses, so when the tile has at least two
 // low bits each thread moves element pairs (16 B for complex64).
 // ---------------------------------------------------------------------------
-// elements per block: 32 KB of tile data; at most 256 tiles per block, so the
-// whole LDS use (tiles, 12 KB table, bases) stays under 48 KB
+// elements per block: 16 KB of tile data (2048 complex64; the best of a sweep
+// over 2^9..2^12 on 2^22-element tensors); at most 256 tiles per block, so the
+// whole LDS use (tiles, 12 KB table, bases) stays under 32 KB
 template <typename T>
-__host__ __device__ constexpr int perm_elems() { return 32768 / (int)sizeof(T); }
+__host__ __device__ constexpr int perm_elems() { return 16384 / (int)sizeof(T); }
 __host__ __device__ inline int perm_tiles_per_block(int tsize, int elems) {
     const int u = tsize >= elems ? 1 : elems / tsize;
     return u > 256 ? 256 : u;
 }
 
 template <typename T>
+__host__ __device__ inline int perm_block_elems(const PermArgs& p) {
+    return p.elems_log > 0 ? (1 << p.elems_log) : perm_elems<T>();
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
     extern __shared__ unsigned char smem_raw[];
     const int tsize = 1 << p.tb;
-    const int upb = perm_tiles_per_block(tsize, perm_elems<T>());  // tiles per block
+    const int upb = perm_tiles_per_block(tsize, perm_block_elems<T>(p));  // tiles per block
     // tile elements, one padding element after every 32 (transposes write the
     // tile with a stride of 32 elements)
     T* tile = (T*)smem_raw;                                          // upb * tsize * 33 / 32 elements
@@ -622,7 +630,7 @@ int launch_gemm_c128(const GemmArgs& g, hipStream_t s) {
 template <typename T>
 static void launch_perm(const PermArgs& p, hipStream_t s) {
     const int tsize = 1 << p.tb;
-    const int upb = perm_tiles_per_block(tsize, perm_elems<T>());
+    const int upb = perm_tiles_per_block(tsize, perm_block_elems<T>(p));
     const int64_t units = p.n_inst << p.n_high;
     const unsigned blocks = (unsigned)((units + upb - 1) / upb);
     const size_t elems = (size_t)upb * tsize;

@@ -431,7 +431,7 @@ def _kernel_lib():
         L.tn_kernel_gemm.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_int32,
                                      C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, vp]
         L.tn_kernel_gemm.restype = C.c_int
-        L.tn_kernel_permute.argtypes = [C.c_int32, vp, vp, C.c_int64, C.c_int32, vp, vp]
+        L.tn_kernel_permute.argtypes = [C.c_int32, vp, vp, C.c_int64, C.c_int32, vp, C.c_int32, vp]
         L.tn_kernel_permute.restype = C.c_int
         L._kernel_sigs = True
     return L
@@ -454,12 +454,12 @@ def kernel_gemm(A, B, C_out, m_log, n_log, k_log, transA=0, transB=0, ia=None, i
     return rc
 
 
-def kernel_permute(src, dst, r, perm, stream=None):
+def kernel_permute(src, dst, r, perm, block_elems_log=0, stream=None):
     import torch
     fp64 = 1 if src.dtype == torch.complex128 else 0
     p = np.ascontiguousarray(perm, dtype=np.int32)
     _check(_kernel_lib().tn_kernel_permute(fp64, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
-                                           src.shape[0], r, p.ctypes.data if r else None,
+                                           src.shape[0], r, p.ctypes.data if r else None, block_elems_log,
                                            _stream_ptr(stream)))
 
 
