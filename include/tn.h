@@ -123,6 +123,8 @@ typedef struct {
     int32_t time_kernels;    /* 1 = HIP events around every batched GEMM / permute
                                 launch, accumulated per kernel (tn_exec_kernel_stats);
                                 needs use_graph = 0 (TN_EINVAL otherwise) */
+    int32_t no_gather;       /* 1 = always transpose operands into GEMM order instead of
+                                letting MFMA steps read them in stored order */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs

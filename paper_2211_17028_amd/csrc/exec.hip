@@ -120,6 +120,8 @@ struct Launch {
     SlotFillArgs sf{};
     Ref sf_noise, sf_dst, sf_bank, sf_pattern;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // per-launch timing (optional)
+    int gather = 0;                               // GEMM reads operands in stored order
+    Ref oa, ob;                                   // gathered operands: slice offsets (int64)
 };
 
 struct PlanExec {
@@ -455,103 +457,186 @@ struct Builder {
             b_target.insert(b_target.end(), fb_order.begin(), fb_order.end());
             Ref opA = A.buf, opB = B.buf;
             std::vector<std::pair<int64_t, int64_t>> temps;
-            auto emit_perm = [&](NodeInfo& X, const std::vector<int>& target, Ref* op) {
-                if (X.legs == target) return;
-                Launch pl = make_perm(X.legs, target, fp64);
-                const int64_t nb = (int64_t)X.keys.size() * (int64_t(esz) << X.legs.size());
-                int64_t off = work.alloc(nb);
-                temps.push_back({off, nb});
-                pl.a = *op;
-                pl.c = Ref{wreg, off};
-                pl.p.n_inst = (int64_t)X.keys.size();
-                pl.bytes = 2.0 * nb;
-                pl.kclass = fp64 ? K_PERM64 : K_PERM32;
-                pl.plan = plan_index;
-                out->push_back(pl);
-                *op = pl.c;
-            };
-            if (permA) {
-                emit_perm(A, a_target, &opA);
-                transA = 0;
-            }
-            if (permB) {
-                emit_perm(B, b_target, &opB);
-                transB = 0;
-            }
             // orientation: C = A B (legs bt|FA|FB) or, when A is too short for an
             // MFMA row tile and B is not, C^T = B^T A^T (legs bt|FB|FA)
             const bool swap = FA.size() < 5 && FB.size() >= 5;
-            C.legs = bt_order;
-            if (!swap) {
-                C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
-                C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
-            } else {
-                C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
-                C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
-            }
             const int64_t ninst = (int64_t)C.keys.size();
             const int64_t nbatch = int64_t(1) << rb;
-            C.bytes = ninst * (int64_t(esz) << C.legs.size());
-            if (j + 1 == cl.path.size() && mode == 2) {
-                C.buf = Ref{wreg, 0};     // replaced by the per-term root slot
-            } else {
-                C.buf = Ref{wreg, work.alloc(C.bytes)};
+            // Gathered operands: an FP32 step that runs on an MFMA tile and would
+            // need a transpose reads both operands in their stored order instead.
+            // Logical bits are ordered by stored position (lowest first), so the
+            // stored layout's lowest bit is row / column / inner bit 0 and the
+            // loads along it stay coalesced.  Not when that lowest bit is a batch
+            // leg (the slices would interleave).
+            bool gather = false;
+            if (!fp64 && (permA || permB) && ex->opts.no_gather == 0) {
+                GemmArgs probe{};
+                probe.m_log = (int)(swap ? FB.size() : FA.size());
+                probe.n_log = (int)(swap ? FA.size() : FB.size());
+                probe.k_log = rk;
+                const NodeInfo& R0 = swap ? B : A;
+                const NodeInfo& Q0 = swap ? A : B;
+                const bool bt_low = std::find(Bt.begin(), Bt.end(), R0.legs.back()) != Bt.end() ||
+                                    std::find(Bt.begin(), Bt.end(), Q0.legs.back()) != Bt.end();
+                gather = kernel_class(select_gemm(probe, 0, -1)) == KC_MFMA && !bt_low;
             }
             Launch gl;
             gl.kind = L_GEMM;
             gl.fp64 = fp64;
             gl.plan = plan_index;
-            gl.a = opA;
-            gl.b = opB;
-            gl.c = C.buf;
-            gl.g.m_log = (int)FA.size();
-            gl.g.n_log = (int)FB.size();
-            gl.g.k_log = rk;
-            gl.g.transA = transA;
-            gl.g.transB = transB;
-            // every (instance, batch index) pair is one GEMM; operand slices of
-            // one batch index are m k (n k) elements apart
-            gl.g.n_inst = ninst * nbatch;
-            gl.g.strideA = int64_t(1) << (A.legs.size() - rb);
-            gl.g.strideB = int64_t(1) << (B.legs.size() - rb);
-            auto mapping = [&](const NodeInfo& X, int* mode_out, Ref* map_out) {
-                if (X.keys.size() == 1 && rb == 0) {
-                    *mode_out = 1;
-                    return;
+            if (gather) {
+                const NodeInfo& R = swap ? B : A;       // row operand
+                const NodeInfo& Q = swap ? A : B;       // column operand
+                const std::vector<int>& FR = swap ? FB : FA;
+                const std::vector<int>& FQ = swap ? FA : FB;
+                auto posin = [](const NodeInfo& X, int e) {
+                    return (int)X.legs.size() - 1 - (int)(std::find(X.legs.begin(), X.legs.end(), e) - X.legs.begin());
+                };
+                auto by_pos = [&](std::vector<int> v, const NodeInfo& X) {
+                    std::sort(v.begin(), v.end(), [&](int a, int b) { return posin(X, a) < posin(X, b); });
+                    return v;
+                };
+                const int64_t bytesR = (int64_t)R.keys.size() << R.legs.size();
+                const int64_t bytesQ = (int64_t)Q.keys.size() << Q.legs.size();
+                std::vector<int> row_bits = by_pos(FR, R), col_bits = by_pos(FQ, Q);
+                std::vector<int> k_bits = by_pos(K, bytesR >= bytesQ ? R : Q);
+                std::vector<int> bt_bits(bt_order.rbegin(), bt_order.rend());
+                C.legs = bt_order;
+                C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
+                C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
+                C.bytes = ninst * (int64_t(esz) << C.legs.size());
+                C.buf = (j + 1 == cl.path.size() && mode == 2) ? Ref{wreg, 0} : Ref{wreg, work.alloc(C.bytes)};
+                gl.a = R.buf;
+                gl.b = Q.buf;
+                gl.c = C.buf;
+                gl.g.m_log = (int)FR.size();
+                gl.g.n_log = (int)FQ.size();
+                gl.g.k_log = rk;
+                gl.g.n_inst = ninst * nbatch;
+                for (size_t q = 0; q < row_bits.size(); ++q) gl.g.a_row[q] = (int8_t)posin(R, row_bits[q]);
+                for (size_t q = 0; q < k_bits.size(); ++q) {
+                    gl.g.a_k[q] = (int8_t)posin(R, k_bits[q]);
+                    gl.g.b_k[q] = (int8_t)posin(Q, k_bits[q]);
                 }
-                if (X.mask == C.mask) {
-                    *mode_out = 0;     // same instances; (i, b) -> i * nbatch + b
-                    return;
+                for (size_t q = 0; q < col_bits.size(); ++q) gl.g.b_col[q] = (int8_t)posin(Q, col_bits[q]);
+                gl.g.a_rowfast = std::find(FR.begin(), FR.end(), R.legs.back()) != FR.end();
+                gl.g.b_colfast = std::find(FQ.begin(), FQ.end(), Q.legs.back()) != FQ.end();
+                // slice offsets: operand instance base + the batch bits' stored offset
+                auto offsets = [&](const NodeInfo& X) {
+                    std::vector<int64_t> o(ninst * nbatch);
+                    const int64_t isz = int64_t(1) << X.legs.size();
+                    for (int64_t i = 0; i < ninst; ++i) {
+                        const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
+                        for (int64_t b2 = 0; b2 < nbatch; ++b2) {
+                            int64_t off = xi * isz;
+                            for (int q = 0; q < rb; ++q)
+                                if ((b2 >> q) & 1) off += int64_t(1) << posin(X, bt_bits[q]);
+                            o[i * nbatch + b2] = off;
+                        }
+                    }
+                    return Ref{R_CONST, ex->cbuf.add(o.data(), (int64_t)o.size() * 8)};
+                };
+                gl.oa = offsets(R);
+                gl.ob = offsets(Q);
+                gl.gather = 1;
+                const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
+                             kk = std::ldexp(1.0, gl.g.k_log);
+                gl.flops = 8.0 * mm * nnn * kk * (double)gl.g.n_inst;
+                gl.bytes = (double)esz * ((double)gl.g.n_inst * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
+                                          (double)Q.keys.size() * nbatch * kk * nnn);
+                if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
+                gl.kclass = K_GATHER_BASE + select_gemm(gl.g, 0, -1);
+                out->push_back(gl);
+            } else {
+                auto emit_perm = [&](NodeInfo& X, const std::vector<int>& target, Ref* op) {
+                    if (X.legs == target) return;
+                    Launch pl = make_perm(X.legs, target, fp64);
+                    const int64_t nb = (int64_t)X.keys.size() * (int64_t(esz) << X.legs.size());
+                    int64_t off = work.alloc(nb);
+                    temps.push_back({off, nb});
+                    pl.a = *op;
+                    pl.c = Ref{wreg, off};
+                    pl.p.n_inst = (int64_t)X.keys.size();
+                    pl.bytes = 2.0 * nb;
+                    pl.kclass = fp64 ? K_PERM64 : K_PERM32;
+                    pl.plan = plan_index;
+                    out->push_back(pl);
+                    *op = pl.c;
+                };
+                if (permA) {
+                    emit_perm(A, a_target, &opA);
+                    transA = 0;
                 }
-                std::vector<int32_t> m(ninst * nbatch);
-                for (int64_t i = 0; i < ninst; ++i) {
-                    const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
-                    for (int64_t b2 = 0; b2 < nbatch; ++b2) m[i * nbatch + b2] = (int32_t)(xi * nbatch + b2);
+                if (permB) {
+                    emit_perm(B, b_target, &opB);
+                    transB = 0;
                 }
-                *mode_out = 2;
-                *map_out = Ref{R_CONST, ex->cbuf.add(m.data(), (int64_t)m.size() * 4)};
-            };
-            mapping(A, &gl.g.ia_mode, &gl.ia);
-            mapping(B, &gl.g.ib_mode, &gl.ib);
-            if (swap) {
-                // C^T[j][i] = sum_p B^T[j][p] A^T[p][i]: B becomes the row operand
-                std::swap(gl.a, gl.b);
-                std::swap(gl.g.ia_mode, gl.g.ib_mode);
-                std::swap(gl.ia, gl.ib);
-                std::swap(gl.g.strideA, gl.g.strideB);
-                std::swap(gl.g.m_log, gl.g.n_log);
-                const int ta = gl.g.transA, tb2 = gl.g.transB;
-                gl.g.transA = 1 - tb2;
-                gl.g.transB = 1 - ta;
+                C.legs = bt_order;
+                if (!swap) {
+                    C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
+                    C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
+                } else {
+                    C.legs.insert(C.legs.end(), fb_order.begin(), fb_order.end());
+                    C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
+                }
+                C.bytes = ninst * (int64_t(esz) << C.legs.size());
+                if (j + 1 == cl.path.size() && mode == 2) {
+                    C.buf = Ref{wreg, 0};     // replaced by the per-term root slot
+                } else {
+                    C.buf = Ref{wreg, work.alloc(C.bytes)};
+                }
+                gl.a = opA;
+                gl.b = opB;
+                gl.c = C.buf;
+                gl.g.m_log = (int)FA.size();
+                gl.g.n_log = (int)FB.size();
+                gl.g.k_log = rk;
+                gl.g.transA = transA;
+                gl.g.transB = transB;
+                // every (instance, batch index) pair is one GEMM; operand slices of
+                // one batch index are m k (n k) elements apart
+                gl.g.n_inst = ninst * nbatch;
+                gl.g.strideA = int64_t(1) << (A.legs.size() - rb);
+                gl.g.strideB = int64_t(1) << (B.legs.size() - rb);
+                auto mapping = [&](const NodeInfo& X, int* mode_out, Ref* map_out) {
+                    if (X.keys.size() == 1 && rb == 0) {
+                        *mode_out = 1;
+                        return;
+                    }
+                    if (X.mask == C.mask) {
+                        *mode_out = 0;     // same instances; (i, b) -> i * nbatch + b
+                        return;
+                    }
+                    std::vector<int32_t> m(ninst * nbatch);
+                    for (int64_t i = 0; i < ninst; ++i) {
+                        const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
+                        for (int64_t b2 = 0; b2 < nbatch; ++b2) m[i * nbatch + b2] = (int32_t)(xi * nbatch + b2);
+                    }
+                    *mode_out = 2;
+                    *map_out = Ref{R_CONST, ex->cbuf.add(m.data(), (int64_t)m.size() * 4)};
+                };
+                mapping(A, &gl.g.ia_mode, &gl.ia);
+                mapping(B, &gl.g.ib_mode, &gl.ib);
+                if (swap) {
+                    // C^T[j][i] = sum_p B^T[j][p] A^T[p][i]: B becomes the row operand
+                    std::swap(gl.a, gl.b);
+                    std::swap(gl.g.ia_mode, gl.g.ib_mode);
+                    std::swap(gl.ia, gl.ib);
+                    std::swap(gl.g.strideA, gl.g.strideB);
+                    std::swap(gl.g.m_log, gl.g.n_log);
+                    const int ta = gl.g.transA, tb2 = gl.g.transB;
+                    gl.g.transA = 1 - tb2;
+                    gl.g.transB = 1 - ta;
+                }
+                const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
+                             kk = std::ldexp(1.0, gl.g.k_log);
+                gl.flops = 8.0 * mm * nnn * kk * (double)gl.g.n_inst;
+                gl.bytes = (double)esz * ((double)gl.g.n_inst * mm * nnn + (double)A.keys.size() * nbatch * mm * kk +
+                                          (double)B.keys.size() * nbatch * kk * nnn);
+                if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
+                gl.kclass = select_gemm(gl.g, fp64, -1);
+                out->push_back(gl);
             }
-            const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
-                         kk = std::ldexp(1.0, gl.g.k_log);
-            gl.flops = 8.0 * mm * nnn * kk * (double)gl.g.n_inst;
-            gl.bytes = (double)esz * ((double)gl.g.n_inst * mm * nnn + (double)A.keys.size() * nbatch * mm * kk +
-                                      (double)B.keys.size() * nbatch * kk * nnn);
-            if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
-            gl.kclass = select_gemm(gl.g, fp64, -1);
-            out->push_back(gl);
             for (auto& t : temps) work.release(t.first, t.second);
             if (!A.leaf) work.release(A.buf.off, A.bytes);
             if (!B.leaf) work.release(B.buf.off, B.bytes);
@@ -749,6 +834,10 @@ static void bind(tn_exec_s* ex) {
             L.g.C = resolve(ex, L.c);
             L.g.ia = L.g.ia_mode == 2 ? (const int32_t*)resolve(ex, L.ia) : nullptr;
             L.g.ib = L.g.ib_mode == 2 ? (const int32_t*)resolve(ex, L.ib) : nullptr;
+            if (L.gather) {
+                L.g.oa = (const int64_t*)resolve(ex, L.oa);
+                L.g.ob = (const int64_t*)resolve(ex, L.ob);
+            }
         } else if (L.kind == L_PERM) {
             L.p.src = resolve(ex, L.a);
             L.p.dst = resolve(ex, L.c);
@@ -859,10 +948,39 @@ static void autotune(tn_exec_s* ex) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    std::map<std::tuple<int, int, int, int, int, int64_t>, int> cache;
+    std::map<std::tuple<int, int, int, int, int, int64_t, int>, int> cache;
     for (auto& L : ex->launches) {
         if (L.kind != L_GEMM || L.fp64 || L.g.n_inst == 0 || kernel_class(L.kclass) != KC_MFMA) continue;
-        auto key = std::make_tuple(L.g.m_log, L.g.n_log, L.g.k_log, L.g.transA, L.g.transB, L.g.n_inst);
+        auto time_gemm = [&](int id) {
+            std::vector<float> ts;
+            for (int rep = 0; rep < 4; ++rep) {
+                HIPCHK(hipEventRecord(e0, s));
+                launch_gemm_id(id, L.g, s);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ts.push_back(ms);    // first launch warms caches
+            }
+            std::sort(ts.begin(), ts.end());
+            return ts[ts.size() / 2];
+        };
+        // gathered steps of one shape differ in their operand layouts; each is timed
+        if (L.gather) {
+            int best = L.kclass;
+            float best_ms = 1e30f;
+            for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+                if (!mfma_tile_fits(tile, L.g)) continue;
+                const float med = time_gemm(K_GATHER_BASE + tile);
+                if (med < best_ms) {
+                    best_ms = med;
+                    best = K_GATHER_BASE + tile;
+                }
+            }
+            L.kclass = best;
+            continue;
+        }
+        auto key = std::make_tuple(L.g.m_log, L.g.n_log, L.g.k_log, L.g.transA, L.g.transB, L.g.n_inst, 0);
         auto it = cache.find(key);
         if (it != cache.end()) {
             L.kclass = it->second;
@@ -872,19 +990,7 @@ static void autotune(tn_exec_s* ex) {
         float best_ms = 1e30f;
         for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
             if (!mfma_tile_fits(tile, L.g)) continue;
-            float med = 0;
-            std::vector<float> ts;
-            for (int rep = 0; rep < 4; ++rep) {
-                HIPCHK(hipEventRecord(e0, s));
-                launch_gemm_id(tile, L.g, s);
-                HIPCHK(hipEventRecord(e1, s));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) ts.push_back(ms);    // first launch warms caches
-            }
-            std::sort(ts.begin(), ts.end());
-            med = ts[ts.size() / 2];
+            const float med = time_gemm(tile);
             if (med < best_ms) {
                 best_ms = med;
                 best = tile;
@@ -939,7 +1045,22 @@ static std::string describe_exec(const tn_exec_s* ex) {
             os << ",\"n\":" << L.sf.n << ",\"noise\":" << L.sf_noise.off << ",\"dst\":" << L.sf_dst.off
                << ",\"bank\":" << L.sf_bank.off << ",\"pattern\":" << L.sf_pattern.off
                << ",\"n_noise\":" << L.sf.n_noise;
-        if (L.kind == L_GEMM) os << ",\"plain_root\":" << L.plain_root;
+        if (L.kind == L_GEMM) {
+            os << ",\"plain_root\":" << L.plain_root << ",\"gather\":" << L.gather;
+            if (L.gather) {
+                os << ",\"oa\":[" << L.oa.region << "," << L.oa.off << "],\"ob\":[" << L.ob.region << ","
+                   << L.ob.off << "],\"a_rowfast\":" << L.g.a_rowfast << ",\"b_colfast\":" << L.g.b_colfast;
+                auto arr = [&](const char* nm, const int8_t* v, int n) {
+                    os << ",\"" << nm << "\":[";
+                    for (int q = 0; q < n; ++q) os << (q ? "," : "") << (int)v[q];
+                    os << "]";
+                };
+                arr("a_row", L.g.a_row, L.g.m_log);
+                arr("a_k", L.g.a_k, L.g.k_log);
+                arr("b_k", L.g.b_k, L.g.k_log);
+                arr("b_col", L.g.b_col, L.g.n_log);
+            }
+        }
         os << ",\"flops\":" << L.flops << ",\"bytes\":" << L.bytes << "}";
     };
     for (auto& L : ex->launches64) emit(L, "batch64");

@@ -20,6 +20,17 @@ struct GemmArgs {
     int m_log, n_log, k_log;
     int transA, transB;           // A stored k x m / B stored n x k
     int64_t n_inst;
+    // Gathered operands (MFMA kernels, ids >= K_GATHER_BASE): slice i of A
+    // starts at element oa[i] of A and its element (row r, inner index p) sits
+    // at oa[i] + sum_j bit_j(r) << a_row[j] + sum_j bit_j(p) << a_k[j]; slice i
+    // of B element (p, column c) at ob[i] + sum_j bit_j(p) << b_k[j] +
+    // sum_j bit_j(c) << b_col[j].  a_rowfast / b_colfast: the operand's lowest
+    // stored bit is row / column bit 0 (else it is inner bit 0), which decides
+    // the load order that keeps the loads coalesced.
+    const int64_t* oa;
+    const int64_t* ob;
+    int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+    int a_rowfast, b_colfast;
 };
 
 // Bit permutation of each instance of a 2^r tensor: out bit j <- in bit p[j].
@@ -48,6 +59,7 @@ enum KernelId {
     K_SMALL32 = 10, K_SPLITK32 = 11,
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
+    K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };
 int select_gemm(const GemmArgs& g, int fp64, int tile_hint);
 bool mfma_tile_fits(int tile, const GemmArgs& g);

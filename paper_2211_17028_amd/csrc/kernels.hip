@@ -195,6 +195,186 @@ void k_gemm_mfma(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// K1 with gathered operands: the same MFMA tiling, but A and B are read in
+// their stored leg order (no transpose pass).  Offsets of the low row /
+// column / inner bits come from small LDS tables; the high parts are added
+// once per tile and per k chunk.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int lo, int hi) {
+    int64_t o = 0;
+    for (int j = lo; j < hi; ++j)
+        if ((x >> j) & 1) o |= int64_t(1) << pos[j];
+    return o;
+}
+
+template <int BM, int BNC>
+__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1))
+void k_gemm_mfma_g(GemmArgs g) {
+    constexpr int WM = BM >= 64 ? BM / 64 : 1;
+    constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TM = BM / WM / 32;
+    constexpr int TN = BNC / WN / 16;
+    constexpr int BKC = 8;
+    constexpr int BM_LOG = __builtin_ctz(BM), BN_LOG = __builtin_ctz(BNC);
+    constexpr int AE = (BM * BKC + NT - 1) / NT;
+    constexpr int BE = (BKC * BNC + NT - 1) / NT;
+    __shared__ float As_re[2][BKC][BM + 1];
+    __shared__ float As_im[2][BKC][BM + 1];
+    __shared__ float2 Bs[2][BKC][BNC + 1];
+    __shared__ int64_t row_lo[BM], col_lo[BNC], ak_lo[BKC], bk_lo[BKC];
+
+    const int m_log = g.m_log, n_log = g.n_log, k_log = g.k_log;
+    const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
+    const int tn_log = n_log >= BN_LOG ? n_log - BN_LOG : 0;
+    const int64_t tiles = (m / BM) << tn_log;
+    const int64_t inst = (int64_t)blockIdx.x / tiles;
+    const int64_t tile = (int64_t)blockIdx.x - inst * tiles;
+    const int64_t tm0 = (tile >> tn_log) * BM;
+    const int64_t tn0 = (tile & ((int64_t(1) << tn_log) - 1)) * BNC;
+    const int kc = k < BKC ? (int)k : BKC;
+    const int kc_log = k_log < 3 ? k_log : 3;
+    const int nb_bits = n_log < BN_LOG ? n_log : BN_LOG;
+    for (int i = threadIdx.x; i < BM; i += NT) row_lo[i] = deposit(i, g.a_row, 0, BM_LOG);
+    for (int i = threadIdx.x; i < BNC; i += NT) col_lo[i] = deposit(i, g.b_col, 0, nb_bits);
+    for (int i = threadIdx.x; i < BKC; i += NT) {
+        ak_lo[i] = deposit(i, g.a_k, 0, kc_log);
+        bk_lo[i] = deposit(i, g.b_k, 0, kc_log);
+    }
+    const float2* __restrict__ A = (const float2*)g.A + g.oa[inst] + deposit(tm0, g.a_row, BM_LOG, m_log);
+    const float2* __restrict__ B = (const float2*)g.B + g.ob[inst] + deposit(tn0, g.b_col, nb_bits, n_log);
+    float* __restrict__ C = (float*)g.C + inst * (2 * m * n);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    v16f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int half = lane >> 5;
+    const int sub = lane & 31;
+    float2 ra[AE], rb[BE];
+    auto load = [&](int64_t k0) {
+        const int64_t akh = deposit(k0, g.a_k, kc_log, k_log);
+        const int64_t bkh = deposit(k0, g.b_k, kc_log, k_log);
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (e < BM * kc) {
+                int r, p;
+                if (g.a_rowfast) {
+                    r = e & (BM - 1);
+                    p = e >> BM_LOG;
+                } else {
+                    p = e & (kc - 1);
+                    r = e >> kc_log;
+                }
+                v = A[row_lo[r] + ak_lo[p] + akh];
+            }
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (e < kc * BNC) {
+                int p, c;
+                if (g.b_colfast) {
+                    c = e & (BNC - 1);
+                    p = e >> BN_LOG;
+                } else {
+                    p = e & (kc - 1);
+                    c = e >> kc_log;
+                }
+                if (tn0 + c < n) v = B[col_lo[c] + bk_lo[p] + bkh];
+            }
+            rb[q] = v;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < BM * kc) {
+                int r, p;
+                if (g.a_rowfast) {
+                    r = e & (BM - 1);
+                    p = e >> BM_LOG;
+                } else {
+                    p = e & (kc - 1);
+                    r = e >> kc_log;
+                }
+                As_re[buf][p][r] = ra[q].x;
+                As_im[buf][p][r] = ra[q].y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < kc * BNC) {
+                int p, c;
+                if (g.b_colfast) {
+                    c = e & (BNC - 1);
+                    p = e >> BN_LOG;
+                } else {
+                    p = e & (kc - 1);
+                    c = e >> kc_log;
+                }
+                Bs[buf][p][c] = rb[q];
+            }
+        }
+    };
+    const int64_t nchunks = k / kc;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int buf = (int)(ch & 1);
+        if (ch + 1 < nchunks) load((ch + 1) * kc);
+        for (int p = 0; p < kc; ++p) {
+            float a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int row = wm * (TM * 32) + i * 32 + sub;
+                a[i] = half ? As_im[buf][p][row] : As_re[buf][p][row];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
+                const float2 bv = Bs[buf][p][col];
+                const int t = sub & 1;
+                b[j] = half == 0 ? (t == 0 ? bv.x : bv.y) : (t == 0 ? -bv.y : bv.x);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (ch + 1 < nchunks) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t colf = 2 * (tn0 + wn * (TN * 16) + j * 16) + sub;
+            if (colf >= 2 * n) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = tm0 + wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                C[row * (2 * n) + colf] = acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Small shapes: one thread per output element, k loop in registers.
 // ---------------------------------------------------------------------------
 template <typename R, typename C2>
@@ -543,6 +723,10 @@ int select_gemm(const GemmArgs& g, int fp64, int tile_hint) {
 }
 
 const char* kernel_name(int id) {
+    static const char* mg[K_MFMA_TILES] = {"k_gemm_mfma_g<128,64>", "k_gemm_mfma_g<64,64>", "k_gemm_mfma_g<128,32>",
+                                           "k_gemm_mfma_g<64,32>",  "k_gemm_mfma_g<32,32>", "k_gemm_mfma_g<128,16>",
+                                           "k_gemm_mfma_g<64,16>",  "k_gemm_mfma_g<32,16>"};
+    if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return mg[id - K_GATHER_BASE];
     static const char* mf[K_MFMA_TILES] = {"k_gemm_mfma<128,64>", "k_gemm_mfma<64,64>", "k_gemm_mfma<128,32>",
                                            "k_gemm_mfma<64,32>",  "k_gemm_mfma<32,32>", "k_gemm_mfma<128,16>",
                                            "k_gemm_mfma<64,16>",  "k_gemm_mfma<32,16>"};
@@ -561,19 +745,23 @@ const char* kernel_name(int id) {
 
 int kernel_class(int id) {
     if (id >= 0 && id < K_MFMA_TILES) return KC_MFMA;
+    if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return KC_MFMA;
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
     return KC_TILED;
 }
 
-static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s) {
+static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s, bool gather) {
     const int64_t ntiles = std::max<int64_t>(1, (int64_t(1) << g.n_log) / t.bnc);
     const int64_t tiles = ((int64_t(1) << g.m_log) / t.bm) * ntiles;
     const unsigned blocks = (unsigned)(tiles * g.n_inst);
 #define TN_LAUNCH(BM_, BN_)                                                                   \
     if (t.bm == BM_ && t.bnc == BN_) {                                                         \
         constexpr int nt = 64 * (BM_ >= 64 ? BM_ / 64 : 1) * (BN_ >= 32 ? BN_ / 32 : 1);       \
-        hipLaunchKernelGGL((k_gemm_mfma<BM_, BN_>), dim3(blocks), dim3(nt), 0, s, g);          \
+        if (gather)                                                                            \
+            hipLaunchKernelGGL((k_gemm_mfma_g<BM_, BN_>), dim3(blocks), dim3(nt), 0, s, g);    \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_gemm_mfma<BM_, BN_>), dim3(blocks), dim3(nt), 0, s, g);      \
         return;                                                                                \
     }
     TN_LAUNCH(128, 64)
@@ -591,7 +779,11 @@ void launch_gemm_id(int id, const GemmArgs& g, hipStream_t s) {
     const int mn_log = g.m_log + g.n_log;
     const int64_t total = g.n_inst << mn_log;
     if (id >= 0 && id < K_MFMA_TILES) {
-        launch_mfma_tile(kTiles[id], g, s);
+        launch_mfma_tile(kTiles[id], g, s, false);
+        return;
+    }
+    if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) {
+        launch_mfma_tile(kTiles[id - K_GATHER_BASE], g, s, true);
         return;
     }
     switch (id) {

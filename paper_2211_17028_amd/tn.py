@@ -58,7 +58,7 @@ class tn_prune_opts(C.Structure):
 
 class tn_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
-                ("tune", C.c_int32), ("time_kernels", C.c_int32)]
+                ("tune", C.c_int32), ("time_kernels", C.c_int32), ("no_gather", C.c_int32)]
 
 
 class tn_kernel_stat(C.Structure):
@@ -358,9 +358,10 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False):
+def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False,
+              gather=True):
     return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
-                        1 if time_kernels else 0)
+                        1 if time_kernels else 0, 0 if gather else 1)
 
 
 def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):

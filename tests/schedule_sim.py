@@ -68,6 +68,8 @@ class Sim:
         dst[...] = tmp
 
     def gemm(self, L, c_extra=0):
+        if L.get("gather"):
+            return self.gemm_gather(L, c_extra)
         dt = np.complex128 if L["fp64"] else np.complex64
         m, n, k = 1 << L["m_log"], 1 << L["n_log"], 1 << L["k_log"]
         ni = L["n_inst"]
@@ -86,6 +88,37 @@ class Sim:
         B = B.reshape(nb, n, k).transpose(0, 2, 1) if L["transB"] else B.reshape(nb, k, n)
         Cv = self.view(L["c"], dt, ni * m * n, c_extra).reshape(ni, m, n)
         Cv[...] = np.matmul(A[ia].astype(np.complex128), B[ib].astype(np.complex128)).astype(dt)
+
+    def gemm_gather(self, L, c_extra=0):
+        """Operands read in stored order: logical bit j of the row / inner /
+        column index sits at the stored position a_row[j] / a_k[j] (b_k[j]) /
+        b_col[j]; instance i starts at offset oa[i] (ob[i])."""
+        assert not L["fp64"]
+        dt = np.complex64
+        m, n, k = 1 << L["m_log"], 1 << L["n_log"], 1 << L["k_log"]
+        ni = L["n_inst"]
+
+        def deposit(count, pos):
+            x = np.arange(count, dtype=np.int64)
+            o = np.zeros(count, dtype=np.int64)
+            for j, p in enumerate(pos):
+                o |= ((x >> j) & 1) << p
+            return o
+        assert len(L["a_row"]) == L["m_log"] and len(L["b_col"]) == L["n_log"]
+        assert len(L["a_k"]) == L["k_log"] == len(L["b_k"])
+        for pos in (L["a_row"] + L["a_k"], L["b_k"] + L["b_col"]):
+            assert len(set(pos)) == len(pos), "stored positions must be distinct"
+        oa = self.view(L["oa"], np.int64, ni)
+        ob = self.view(L["ob"], np.int64, ni)
+        ra, ka = deposit(m, L["a_row"]), deposit(k, L["a_k"])
+        kb, cb = deposit(k, L["b_k"]), deposit(n, L["b_col"])
+        a_idx = oa[:, None, None] + ra[None, :, None] + ka[None, None, :]
+        b_idx = ob[:, None, None] + kb[None, :, None] + cb[None, None, :]
+        assert a_idx.min() >= 0 and b_idx.min() >= 0
+        A = self.view(L["a"], dt, int(a_idx.max()) + 1)
+        B = self.view(L["b"], dt, int(b_idx.max()) + 1)
+        Cv = self.view(L["c"], dt, ni * m * n, c_extra).reshape(ni, m, n)
+        Cv[...] = np.matmul(A[a_idx].astype(np.complex128), B[b_idx].astype(np.complex128)).astype(dt)
 
     def finalize(self, L, root_refs, root64_refs):
         nt, ncl = L["n_terms"], L["n_clusters"]

@@ -142,11 +142,11 @@ def grouped_by_positions(pat, x):
     return out
 
 
-def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True):
+def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True):
     plan = tn.tn_plan_build(circ, level)
     t = tn.tn_terms_enumerate(plan, level)
     desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
-                                                                  fp64_level0=fp64))
+                                                                  fp64_level0=fp64, gather=gather))
     pat, w = t.get()
     live = [i for i in range(t.n) if w[i] != 0.0]
     sim = Sim(desc, cb)
@@ -176,6 +176,28 @@ def test_schedule_replay_plain_mode_matches_batched():
     xb, _, _ = _replay(c, 2)
     xp, _, _ = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
     assert np.allclose(xb, xp, rtol=2e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,gates,noises,target,seed", [(14, 120, 4, "circuit_output", 2),
+                                                         (14, 120, 4, "circuit_output", 3),
+                                                         (16, 120, 3, "product", 2)])
+def test_schedule_replay_gathered_operands(n, gates, noises, target, seed):
+    """Circuits wide enough for MFMA-tile steps whose operands are read in
+    stored order (no transpose pass): the replay matches the oracle and the
+    schedule that transposes instead."""
+    c = W.tiny_random_circuit(np.random.default_rng(seed), n, gates, noises, noise="adpd", level=2,
+                              target=target)
+    x, pat, desc = _replay(c, 2)
+    gl = [L for L in desc["launches"] if L["kind"] == 1 and L.get("gather")]
+    assert gl, "no gathered step in this schedule"
+    x_t, _, desc_t = _replay(c, 2, gather=False)
+    assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
+    r = estimate.estimate(c, 2, "network", reduce=True)
+    assert np.allclose(x, r["X"], rtol=2e-5, atol=1e-10)
+    assert np.allclose(x, x_t, rtol=2e-5, atol=1e-10)
+    x_p, _, desc_p = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
+    assert any(L.get("gather") for L in desc_p["launches"] if L["kind"] == 1)
+    assert np.allclose(x_p, x, rtol=2e-5, atol=1e-10)
 
 
 def test_schedule_replay_config1_against_oracle():
