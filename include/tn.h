@@ -94,7 +94,7 @@ typedef struct tn_exec_s* tn_exec;
 
 /* Planner options; zero-initialise for defaults. */
 typedef struct {
-    int32_t path_trials;    /* randomized greedy path trials per network (0 = 64) */
+    int32_t path_trials;    /* randomized greedy path trials per network (0 = 1024) */
     uint64_t seed;          /* path search seed (0 = fixed default) */
     int32_t no_light_cone;  /* 1 = keep gates outside the slots' light cone */
     int32_t max_log_size;   /* cap on log2(elements) of one tensor (0 = 30) */
@@ -102,6 +102,8 @@ typedef struct {
                                         instead of sharing their wires' index */
     double max_work_bytes;  /* cap on the complex64 live set of one cluster's path,
                                all instances of the full level-l expansion (0 = 64 GiB) */
+    int32_t no_reconfigure; /* 1 = keep the best greedy path as found (no subtree
+                               reconfiguration by dynamic programming) */
 } tn_plan_opts;
 
 /* Term pruning (level-2/3 candidates).  NULL = the full expansion. */
@@ -125,6 +127,8 @@ typedef struct {
                                 needs use_graph = 0 (TN_EINVAL otherwise) */
     int32_t no_gather;       /* 1 = always transpose operands into GEMM order instead of
                                 letting MFMA steps read them in stored order */
+    int32_t no_group;        /* 1 = one launch per contraction step instead of one grouped
+                                launch for the small steps of each tree level */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs

@@ -97,7 +97,8 @@ struct Ref {
     int64_t off = 0;
 };
 
-enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4 };
+enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4, L_GROUP = 5 };
+struct GroupJob;
 
 struct Launch {
     int kind = 0;
@@ -122,6 +123,11 @@ struct Launch {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // per-launch timing (optional)
     int gather = 0;                               // GEMM reads operands in stored order
     Ref oa, ob;                                   // gathered operands: slice offsets (int64)
+    // grouped launch (L_GROUP): device job records in the constant region
+    Ref jobs;
+    int n_jobs = 0;
+    int64_t blocks = 0;
+    std::vector<struct GroupJob> hjobs;
 };
 
 struct PlanExec {
@@ -174,16 +180,56 @@ struct NodeInfo {
     std::vector<int> legs;     // storage order, legs[0] most significant
     u128 mask = 0;             // 2 bits per cluster-local slot
     std::vector<u128> keys;    // sorted distinct instance keys
-    Ref buf;
+    Ref buf;                   // symbolic: Ref{R_NODE, gid}
+    int gid = -1;              // node id in the builder's node table
+    int level = 0;             // 0 for leaves, else 1 + max over the operands
     int64_t bytes = 0;
     bool leaf = true;
+};
+
+// Symbolic buffer references used while steps are planned; replaced by
+// concrete ones when the steps are placed in memory (level by level).
+enum { R_NODE = 10, R_TEMP = 11 };
+
+// One grouped contraction (host side of a GettJob).
+struct GroupJob {
+    Ref a, b, c, oa, ob;
+    int64_t n_inst = 0;
+    int m_log = 0, n_log = 0, k_log = 0, split = 0;
+    int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
+    double flops = 0, bytes = 0;
+};
+
+// One pairwise step before memory assignment.
+struct StepRec {
+    int level = 0;
+    int plan = 0;
+    int a_node = -1, b_node = -1, c_node = -1;
+    int64_t c_bytes = 0;
+    bool has_fixed = false;    // output location fixed (cluster root)
+    Ref c_fixed;
+    std::vector<int> temp_ids;
+    std::vector<int64_t> temp_bytes;
+    std::vector<Launch> launches;   // transposes, then the GEMM unless grouped
+    bool grouped = false;
+    GroupJob job;
 };
 
 struct Builder {
     tn_exec_s* ex;
     Arena work;                // FP32 batch (main stream)
     Arena work2;               // FP64 dominant-term pass (side stream, runs concurrently)
-    std::vector<Launch>* out;
+    bool grouping = true;      // small steps of one tree level share one launch
+    std::vector<Ref> node_ref;         // concrete buffer of every node (once placed)
+    std::vector<char> node_leaf;
+    std::vector<int64_t> node_bytes;
+    std::vector<Ref> temp_ref;
+    int add_node(Ref r, bool leaf, int64_t bytes) {
+        node_ref.push_back(r);
+        node_leaf.push_back(leaf ? 1 : 0);
+        node_bytes.push_back(bytes);
+        return (int)node_ref.size() - 1;
+    }
 
     static int64_t find_key(const std::vector<u128>& keys, u128 k) {
         auto it = std::lower_bound(keys.begin(), keys.end(), k);
@@ -259,14 +305,16 @@ struct Builder {
         return L;
     }
 
-    // Build the launches of one cluster for the given root instance keys.
+    // Plan the steps of one cluster for the given root instance keys.
     // mode: 0 = FP32 batched, 1 = FP64 (single zero instance), 2 = PLAIN FP32
-    // (single instance, slot leaves filled per term).  Returns the root ref.
+    // (single instance, slot leaves filled per term).  The root step writes to
+    // root_out (modes 0 / 1).  Returns where the root value will be (root_out,
+    // or the leaf's constant buffer when the cluster has no step).
     Ref build_cluster(const Plan& P, const Cluster& cl, const std::vector<u128>& root_keys, int mode,
-                      int plan_index, std::vector<std::pair<int, int64_t>>* plain_slots) {
+                      int plan_index, std::vector<std::pair<int, int64_t>>* plain_slots, Ref root_out,
+                      std::vector<StepRec>* steps) {
         const int fp64 = mode == 1;
         const int64_t esz = fp64 ? 16 : 8;
-        Arena& work = fp64 ? this->work2 : this->work;
         const int wreg = fp64 ? R_WORK2 : R_WORK;
         const int L = (int)cl.leaves.size();
         const int nn = L + (int)cl.path.size();
@@ -346,6 +394,12 @@ struct Builder {
                 }
             }
         }
+        for (int i = 0; i < L; ++i) {
+            NodeInfo& nd = nodes[i];
+            nd.gid = add_node(nd.buf, true, 0);
+            nd.buf = Ref{R_NODE, nd.gid};
+        }
+        if (cl.path.empty()) return node_ref[nodes[0].gid];
         // remaining holders of every leg (a diagonal gate's wire index can be
         // held by more than two tensors)
         std::unordered_map<int, int> holders;
@@ -357,6 +411,18 @@ struct Builder {
             NodeInfo& A = nodes[ia_node];
             NodeInfo& B = nodes[ib_node];
             NodeInfo& C = nodes[L + j];
+            StepRec st;
+            st.plan = plan_index;
+            st.level = C.level = 1 + std::max(A.level, B.level);
+            C.gid = add_node(Ref{}, false, 0);
+            st.a_node = A.gid;
+            st.b_node = B.gid;
+            st.c_node = C.gid;
+            const bool is_root = j + 1 == cl.path.size();
+            if (is_root) {
+                st.has_fixed = true;
+                st.c_fixed = mode == 2 ? Ref{wreg, 0} : root_out;   // PLAIN: replaced per term
+            }
             // K: shared and held by nobody else (summed); Bt: shared and still
             // held elsewhere (kept, a batch dimension of this step)
             std::vector<int> K, Bt, FA, FB;
@@ -456,12 +522,93 @@ struct Builder {
             b_target.insert(b_target.end(), k_order.begin(), k_order.end());
             b_target.insert(b_target.end(), fb_order.begin(), fb_order.end());
             Ref opA = A.buf, opB = B.buf;
-            std::vector<std::pair<int64_t, int64_t>> temps;
             // orientation: C = A B (legs bt|FA|FB) or, when A is too short for an
             // MFMA row tile and B is not, C^T = B^T A^T (legs bt|FB|FA)
             const bool swap = FA.size() < 5 && FB.size() >= 5;
             const int64_t ninst = (int64_t)C.keys.size();
             const int64_t nbatch = int64_t(1) << rb;
+            auto posin = [](const NodeInfo& X, int e) {
+                return (int)X.legs.size() - 1 - (int)(std::find(X.legs.begin(), X.legs.end(), e) - X.legs.begin());
+            };
+            auto by_pos = [&](std::vector<int> v, const NodeInfo& X) {
+                std::sort(v.begin(), v.end(), [&](int a, int b) { return posin(X, a) < posin(X, b); });
+                return v;
+            };
+            // slice offsets of an operand: instance base + the batch bits' stored offset
+            auto slice_offsets = [&](const NodeInfo& X, const std::vector<int>& bt_bits) {
+                std::vector<int64_t> o(ninst * nbatch);
+                const int64_t isz = int64_t(1) << X.legs.size();
+                for (int64_t i = 0; i < ninst; ++i) {
+                    const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
+                    for (int64_t b2 = 0; b2 < nbatch; ++b2) {
+                        int64_t off = xi * isz;
+                        for (int q = 0; q < rb; ++q)
+                            if ((b2 >> q) & 1) off += int64_t(1) << posin(X, bt_bits[q]);
+                        o[i * nbatch + b2] = off;
+                    }
+                }
+                return Ref{R_CONST, ex->cbuf.add(o.data(), (int64_t)o.size() * 8)};
+            };
+            // Small steps (below a matrix-core tile in FP32, below the tiled
+            // kernel's shape in FP64) become jobs of their tree level's grouped
+            // launch, with operands read in stored order (no transpose pass).
+            bool big;
+            {
+                GemmArgs g0{};
+                g0.m_log = (int)(swap ? FB.size() : FA.size());
+                g0.n_log = (int)(swap ? FA.size() : FB.size());
+                g0.k_log = rk;
+                const int id = select_gemm(g0, fp64, -1);
+                big = fp64 ? id == K_TILED64 : kernel_class(id) == KC_MFMA;
+            }
+            if (grouping && mode != 2 && !big) {
+                // column operand: one whose lowest stored leg is a free leg, so
+                // that consecutive threads (consecutive columns) read adjacent elements
+                const bool qa = std::find(FA.begin(), FA.end(), A.legs.back()) != FA.end();
+                const bool qb = std::find(FB.begin(), FB.end(), B.legs.back()) != FB.end();
+                const bool sw = qa && !qb;
+                const NodeInfo& R = sw ? B : A;
+                const NodeInfo& Q = sw ? A : B;
+                const std::vector<int>& FR = sw ? FB : FA;
+                const std::vector<int>& FQ = sw ? FA : FB;
+                const int64_t bytesR = (int64_t)R.keys.size() << R.legs.size();
+                const int64_t bytesQ = (int64_t)Q.keys.size() << Q.legs.size();
+                const NodeInfo& big_op = bytesR >= bytesQ ? R : Q;
+                std::vector<int> row_bits = by_pos(FR, R), col_bits = by_pos(FQ, Q);
+                std::vector<int> k_bits = by_pos(K, big_op), bt_bits = by_pos(Bt, big_op);
+                C.legs.assign(bt_bits.rbegin(), bt_bits.rend());
+                C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
+                C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
+                C.bytes = ninst * (int64_t(esz) << C.legs.size());
+                C.buf = Ref{R_NODE, C.gid};
+                GroupJob& jb = st.job;
+                jb.a = R.buf;
+                jb.b = Q.buf;
+                jb.c = C.buf;
+                jb.m_log = (int)FR.size();
+                jb.n_log = (int)FQ.size();
+                jb.k_log = rk;
+                jb.n_inst = ninst * nbatch;
+                jb.split = (jb.m_log + jb.n_log <= 4 && rk >= 8) ? 1 : 0;
+                for (size_t q = 0; q < row_bits.size(); ++q) jb.a_row[q] = (int8_t)posin(R, row_bits[q]);
+                for (size_t q = 0; q < k_bits.size(); ++q) {
+                    jb.a_k[q] = (int8_t)posin(R, k_bits[q]);
+                    jb.b_k[q] = (int8_t)posin(Q, k_bits[q]);
+                }
+                for (size_t q = 0; q < col_bits.size(); ++q) jb.b_col[q] = (int8_t)posin(Q, col_bits[q]);
+                jb.oa = slice_offsets(R, bt_bits);
+                jb.ob = slice_offsets(Q, bt_bits);
+                const double mm = std::ldexp(1.0, jb.m_log), nnn = std::ldexp(1.0, jb.n_log),
+                             kk = std::ldexp(1.0, jb.k_log);
+                jb.flops = 8.0 * mm * nnn * kk * (double)jb.n_inst;
+                jb.bytes = (double)esz * ((double)jb.n_inst * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
+                                          (double)Q.keys.size() * nbatch * kk * nnn);
+                st.grouped = true;
+                st.c_bytes = C.bytes;
+                node_bytes[C.gid] = C.bytes;
+                steps->push_back(std::move(st));
+                continue;
+            }
             // Gathered operands: an FP32 step that runs on an MFMA tile and would
             // need a transpose reads both operands in their stored order instead.
             // Logical bits are ordered by stored position (lowest first), so the
@@ -489,13 +636,6 @@ struct Builder {
                 const NodeInfo& Q = swap ? A : B;       // column operand
                 const std::vector<int>& FR = swap ? FB : FA;
                 const std::vector<int>& FQ = swap ? FA : FB;
-                auto posin = [](const NodeInfo& X, int e) {
-                    return (int)X.legs.size() - 1 - (int)(std::find(X.legs.begin(), X.legs.end(), e) - X.legs.begin());
-                };
-                auto by_pos = [&](std::vector<int> v, const NodeInfo& X) {
-                    std::sort(v.begin(), v.end(), [&](int a, int b) { return posin(X, a) < posin(X, b); });
-                    return v;
-                };
                 const int64_t bytesR = (int64_t)R.keys.size() << R.legs.size();
                 const int64_t bytesQ = (int64_t)Q.keys.size() << Q.legs.size();
                 std::vector<int> row_bits = by_pos(FR, R), col_bits = by_pos(FQ, Q);
@@ -505,7 +645,7 @@ struct Builder {
                 C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
                 C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
                 C.bytes = ninst * (int64_t(esz) << C.legs.size());
-                C.buf = (j + 1 == cl.path.size() && mode == 2) ? Ref{wreg, 0} : Ref{wreg, work.alloc(C.bytes)};
+                C.buf = Ref{R_NODE, C.gid};
                 gl.a = R.buf;
                 gl.b = Q.buf;
                 gl.c = C.buf;
@@ -521,23 +661,8 @@ struct Builder {
                 for (size_t q = 0; q < col_bits.size(); ++q) gl.g.b_col[q] = (int8_t)posin(Q, col_bits[q]);
                 gl.g.a_rowfast = std::find(FR.begin(), FR.end(), R.legs.back()) != FR.end();
                 gl.g.b_colfast = std::find(FQ.begin(), FQ.end(), Q.legs.back()) != FQ.end();
-                // slice offsets: operand instance base + the batch bits' stored offset
-                auto offsets = [&](const NodeInfo& X) {
-                    std::vector<int64_t> o(ninst * nbatch);
-                    const int64_t isz = int64_t(1) << X.legs.size();
-                    for (int64_t i = 0; i < ninst; ++i) {
-                        const int64_t xi = X.keys.size() == 1 ? 0 : find_key(X.keys, C.keys[i] & X.mask);
-                        for (int64_t b2 = 0; b2 < nbatch; ++b2) {
-                            int64_t off = xi * isz;
-                            for (int q = 0; q < rb; ++q)
-                                if ((b2 >> q) & 1) off += int64_t(1) << posin(X, bt_bits[q]);
-                            o[i * nbatch + b2] = off;
-                        }
-                    }
-                    return Ref{R_CONST, ex->cbuf.add(o.data(), (int64_t)o.size() * 8)};
-                };
-                gl.oa = offsets(R);
-                gl.ob = offsets(Q);
+                gl.oa = slice_offsets(R, bt_bits);
+                gl.ob = slice_offsets(Q, bt_bits);
                 gl.gather = 1;
                 const double mm = std::ldexp(1.0, gl.g.m_log), nnn = std::ldexp(1.0, gl.g.n_log),
                              kk = std::ldexp(1.0, gl.g.k_log);
@@ -546,21 +671,23 @@ struct Builder {
                                           (double)Q.keys.size() * nbatch * kk * nnn);
                 if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
                 gl.kclass = K_GATHER_BASE + select_gemm(gl.g, 0, -1);
-                out->push_back(gl);
+                st.launches.push_back(gl);
             } else {
                 auto emit_perm = [&](NodeInfo& X, const std::vector<int>& target, Ref* op) {
                     if (X.legs == target) return;
                     Launch pl = make_perm(X.legs, target, fp64);
                     const int64_t nb = (int64_t)X.keys.size() * (int64_t(esz) << X.legs.size());
-                    int64_t off = work.alloc(nb);
-                    temps.push_back({off, nb});
+                    const int tid = (int)temp_ref.size();
+                    temp_ref.push_back(Ref{});
+                    st.temp_ids.push_back(tid);
+                    st.temp_bytes.push_back(nb);
                     pl.a = *op;
-                    pl.c = Ref{wreg, off};
+                    pl.c = Ref{R_TEMP, tid};
                     pl.p.n_inst = (int64_t)X.keys.size();
                     pl.bytes = 2.0 * nb;
                     pl.kclass = fp64 ? K_PERM64 : K_PERM32;
                     pl.plan = plan_index;
-                    out->push_back(pl);
+                    st.launches.push_back(pl);
                     *op = pl.c;
                 };
                 if (permA) {
@@ -580,11 +707,7 @@ struct Builder {
                     C.legs.insert(C.legs.end(), fa_order.begin(), fa_order.end());
                 }
                 C.bytes = ninst * (int64_t(esz) << C.legs.size());
-                if (j + 1 == cl.path.size() && mode == 2) {
-                    C.buf = Ref{wreg, 0};     // replaced by the per-term root slot
-                } else {
-                    C.buf = Ref{wreg, work.alloc(C.bytes)};
-                }
+                C.buf = Ref{R_NODE, C.gid};
                 gl.a = opA;
                 gl.b = opB;
                 gl.c = C.buf;
@@ -635,13 +758,90 @@ struct Builder {
                                           (double)B.keys.size() * nbatch * kk * nnn);
                 if (j + 1 == cl.path.size() && mode == 2) gl.plain_root = 1;
                 gl.kclass = select_gemm(gl.g, fp64, -1);
-                out->push_back(gl);
+                st.launches.push_back(gl);
             }
-            for (auto& t : temps) work.release(t.first, t.second);
-            if (!A.leaf) work.release(A.buf.off, A.bytes);
-            if (!B.leaf) work.release(B.buf.off, B.bytes);
+            st.c_bytes = C.bytes;
+            node_bytes[C.gid] = C.bytes;
+            steps->push_back(std::move(st));
         }
-        return nodes[root].buf;
+        return root_out;
+    }
+
+    // Place planned steps in memory and emit their launches.  by_level: the
+    // steps of one tree level (over all clusters and plans given) run together:
+    // their transposes, then their GEMMs, then one grouped launch for all small
+    // steps; buffers are released after the level.  Otherwise the steps run one
+    // by one in the given order, each releasing its operands.
+    void emit(std::vector<StepRec>& steps, int fp64, bool by_level, std::vector<Launch>* out) {
+        Arena& wk = fp64 ? work2 : work;
+        const int wreg = fp64 ? R_WORK2 : R_WORK;
+        auto subst = [&](Ref& r) {
+            if (r.region == R_NODE) r = node_ref[r.off];
+            else if (r.region == R_TEMP) r = temp_ref[r.off];
+        };
+        std::vector<std::vector<int>> groups;
+        if (by_level) {
+            int maxl = 0;
+            for (auto& st : steps) maxl = std::max(maxl, st.level);
+            groups.resize(maxl + 1);
+            for (size_t i = 0; i < steps.size(); ++i) groups[steps[i].level].push_back((int)i);
+        } else {
+            for (size_t i = 0; i < steps.size(); ++i) groups.push_back({(int)i});
+        }
+        for (auto& grp : groups) {
+            if (grp.empty()) continue;
+            for (int i : grp) {
+                StepRec& st = steps[i];
+                node_ref[st.c_node] = st.has_fixed ? st.c_fixed : Ref{wreg, wk.alloc(st.c_bytes)};
+                for (size_t q = 0; q < st.temp_ids.size(); ++q)
+                    temp_ref[st.temp_ids[q]] = Ref{wreg, wk.alloc(st.temp_bytes[q])};
+            }
+            for (int i : grp)
+                for (auto& L : steps[i].launches)
+                    if (L.kind == L_PERM) {
+                        subst(L.a);
+                        subst(L.c);
+                        out->push_back(L);
+                    }
+            for (int i : grp)
+                for (auto& L : steps[i].launches)
+                    if (L.kind == L_GEMM) {
+                        subst(L.a);
+                        subst(L.b);
+                        subst(L.c);
+                        out->push_back(L);
+                    }
+            Launch G;
+            G.kind = L_GROUP;
+            G.fp64 = fp64;
+            G.kclass = fp64 ? K_GROUP64 : K_GROUP32;
+            for (int i : grp) {
+                if (!steps[i].grouped) continue;
+                GroupJob jb = steps[i].job;
+                subst(jb.a);
+                subst(jb.b);
+                subst(jb.c);
+                const int64_t outs = jb.n_inst << (jb.m_log + jb.n_log);
+                G.blocks += jb.split ? outs : (outs + 255) / 256;
+                G.flops += jb.flops;
+                G.bytes += jb.bytes;
+                G.hjobs.push_back(jb);
+            }
+            if (!G.hjobs.empty()) {
+                if (G.blocks >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 blocks");
+                G.n_jobs = (int)G.hjobs.size();
+                G.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)G.n_jobs * (int64_t)sizeof(GettJob))};
+                G.plan = steps[grp[0]].plan;
+                out->push_back(std::move(G));
+            }
+            for (int i : grp) {
+                StepRec& st = steps[i];
+                for (size_t q = 0; q < st.temp_ids.size(); ++q)
+                    wk.release(temp_ref[st.temp_ids[q]].off, st.temp_bytes[q]);
+                for (int nd : {st.a_node, st.b_node})
+                    if (!node_leaf[nd]) wk.release(node_ref[nd].off, node_bytes[nd]);
+            }
+        }
     }
 };
 
@@ -666,8 +866,9 @@ static std::vector<u128> cluster_keys(const Plan& P, const Cluster& cl, const Te
 static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms) {
     Builder bw;
     bw.ex = ex;
-    bw.out = &ex->launches;
+    bw.grouping = ex->opts.no_group == 0;
     const bool plain = ex->opts.mode == TN_MODE_PLAIN;
+    std::vector<StepRec> steps32, steps64;
     for (int pi = 0; pi < n; ++pi) {
         const Plan& P = *reinterpret_cast<const Plan*>(plans[pi]);
         const Terms& T = *reinterpret_cast<const Terms*>(terms[pi]);
@@ -696,9 +897,10 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
             if (plain) {
                 for (int64_t i = 0; i < pe.n_live; ++i) root_idx[i * ncl + c] = (int32_t)i;
                 std::vector<u128> one = {0};
-                bw.out = &ex->plain_launches;
                 size_t first = ex->plain_launches.size();
-                bw.build_cluster(P, cl, one, 2, pi, &plain_slots);
+                std::vector<StepRec> sp;
+                bw.build_cluster(P, cl, one, 2, pi, &plain_slots, Ref{}, &sp);
+                bw.emit(sp, 0, false, &ex->plain_launches);
                 // the root step writes into a per-term slot of a persistent buffer
                 int64_t rb = std::max<int64_t>(1, pe.n_live) * 8;
                 Ref root{R_CONST, ex->cbuf.reserve(rb)};
@@ -710,38 +912,18 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
                 pe.root32.push_back(root);
                 pe.root32_inst.push_back(pe.n_live);
             } else {
-                bw.out = &ex->launches;
-                Ref r = bw.build_cluster(P, cl, keys, 0, pi, nullptr);
-                // roots stay live until finalize: copy out of the work arena
-                const int64_t rb = (int64_t)keys.size() * 8;
-                Ref keep{R_CONST, ex->cbuf.reserve(rb)};
-                // identity permutation of rank-0 instances = a copy
-                Launch cp = bw.make_perm(std::vector<int>(), std::vector<int>(), 0);
-                cp.a = r;
-                cp.c = keep;
-                cp.p.n_inst = (int64_t)keys.size();
-                cp.plan = pi;
-                ex->launches.push_back(cp);
-                bw.work.release(r.off, rb);
-                pe.root32.push_back(keep);
+                // roots stay live until finalize: the root step writes outside the work arena
+                Ref keep{R_CONST, ex->cbuf.reserve((int64_t)keys.size() * 8)};
+                pe.root32.push_back(bw.build_cluster(P, cl, keys, 0, pi, nullptr, keep, &steps32));
                 pe.root32_inst.push_back((int64_t)keys.size());
             }
         }
         // FP64 pass for the all-dominant term
         if (pe.zero_term >= 0 && ex->opts.fp64_level0) {
-            bw.out = &ex->launches64;
             for (int c = 0; c < ncl; ++c) {
                 std::vector<u128> one = {0};
-                Ref r = bw.build_cluster(P, P.clusters[c], one, 1, pi, nullptr);
                 Ref keep{R_CONST, ex->cbuf.reserve(16)};
-                Launch cp = bw.make_perm(std::vector<int>(), std::vector<int>(), 1);
-                cp.a = r;
-                cp.c = keep;
-                cp.p.n_inst = 1;
-                cp.plan = pi;
-                ex->launches64.push_back(cp);
-                bw.work2.release(r.off, 16);
-                pe.root64.push_back(keep);
+                pe.root64.push_back(bw.build_cluster(P, P.clusters[c], one, 1, pi, nullptr, keep, &steps64));
             }
         }
         if (plain) {
@@ -814,6 +996,8 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         ex->tail.push_back(ls);
         ex->plans.push_back(std::move(pe));
     }
+    bw.emit(steps32, 0, true, &ex->launches);
+    bw.emit(steps64, 1, true, &ex->launches64);
     ex->const_bytes = round_up((int64_t)ex->cbuf.bytes.size(), 256);
     ex->work1_bytes = round_up(bw.work.peak, 256);
     ex->work_bytes = ex->work1_bytes + round_up(bw.work2.peak, 256);
@@ -842,6 +1026,30 @@ static void bind(tn_exec_s* ex) {
             L.p.src = resolve(ex, L.a);
             L.p.dst = resolve(ex, L.c);
             L.p.table = (const int32_t*)resolve(ex, L.table);
+        } else if (L.kind == L_GROUP) {
+            GettJob* d = (GettJob*)(ex->cbuf.bytes.data() + L.jobs.off);
+            int64_t b0 = 0;
+            for (int i = 0; i < L.n_jobs; ++i) {
+                const GroupJob& h = L.hjobs[i];
+                GettJob j{};
+                j.A = resolve(ex, h.a);
+                j.B = resolve(ex, h.b);
+                j.C = resolve(ex, h.c);
+                j.oa = (const int64_t*)resolve(ex, h.oa);
+                j.ob = (const int64_t*)resolve(ex, h.ob);
+                j.n_inst = h.n_inst;
+                j.block0 = b0;
+                j.m_log = h.m_log;
+                j.n_log = h.n_log;
+                j.k_log = h.k_log;
+                j.split = h.split;
+                std::memcpy(j.a_row, h.a_row, 32);
+                std::memcpy(j.a_k, h.a_k, 32);
+                std::memcpy(j.b_k, h.b_k, 32);
+                std::memcpy(j.b_col, h.b_col, 32);
+                b0 += gett_job_blocks(j);
+                std::memcpy(d + i, &j, sizeof(GettJob));
+            }
         } else if (L.kind == L_SLOTFILL) {
             L.sf.noise = (const int32_t*)resolve(ex, L.sf_noise);
             L.sf.dst = (const int64_t*)resolve(ex, L.sf_dst);
@@ -885,6 +1093,9 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
     case L_PERM:
         if (L.fp64) launch_permute_c128(L.p, s);
         else launch_permute_c64(L.p, s);
+        break;
+    case L_GROUP:
+        launch_gett_group((const GettJob*)resolve(ex, L.jobs), L.n_jobs, L.blocks, L.fp64, s);
         break;
     case L_FINALIZE:
         launch_finalize(L.f, s);
@@ -1045,6 +1256,28 @@ static std::string describe_exec(const tn_exec_s* ex) {
             os << ",\"n\":" << L.sf.n << ",\"noise\":" << L.sf_noise.off << ",\"dst\":" << L.sf_dst.off
                << ",\"bank\":" << L.sf_bank.off << ",\"pattern\":" << L.sf_pattern.off
                << ",\"n_noise\":" << L.sf.n_noise;
+        if (L.kind == L_GROUP) {
+            os << ",\"kernel\":\"" << kernel_name(L.kclass) << "\",\"blocks\":" << L.blocks << ",\"jobs\":[";
+            for (int i = 0; i < L.n_jobs; ++i) {
+                const GroupJob& h = L.hjobs[i];
+                os << (i ? "," : "") << "{\"a\":[" << h.a.region << "," << h.a.off << "],\"b\":[" << h.b.region
+                   << "," << h.b.off << "],\"c\":[" << h.c.region << "," << h.c.off << "],\"oa\":[" << h.oa.region
+                   << "," << h.oa.off << "],\"ob\":[" << h.ob.region << "," << h.ob.off << "],\"n_inst\":"
+                   << h.n_inst << ",\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log << ",\"k_log\":" << h.k_log
+                   << ",\"split\":" << h.split;
+                auto arr = [&](const char* nm, const int8_t* v, int n) {
+                    os << ",\"" << nm << "\":[";
+                    for (int q = 0; q < n; ++q) os << (q ? "," : "") << (int)v[q];
+                    os << "]";
+                };
+                arr("a_row", h.a_row, h.m_log);
+                arr("a_k", h.a_k, h.k_log);
+                arr("b_k", h.b_k, h.k_log);
+                arr("b_col", h.b_col, h.n_log);
+                os << ",\"flops\":" << h.flops << ",\"bytes\":" << h.bytes << "}";
+            }
+            os << "]";
+        }
         if (L.kind == L_GEMM) {
             os << ",\"plain_root\":" << L.plain_root << ",\"gather\":" << L.gather;
             if (L.gather) {
@@ -1227,7 +1460,8 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         if (ex->opts.time_kernels)
             for (auto* list : {&ex->launches, &ex->launches64})
                 for (auto& L : *list)
-                    if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0)) {
+                    if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0) ||
+                        (L.kind == L_GROUP && L.blocks > 0)) {
                         HIPCHK(hipEventCreate(&L.ev_a));
                         HIPCHK(hipEventCreate(&L.ev_b));
                     }

@@ -49,7 +49,29 @@ struct PermArgs {
                                    //    the tile has >= 2 of each, so slots 2i, 2i+1 are adjacent
 };
 
-enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3 };
+// One contraction of a grouped launch: C[i][r][c] = sum_p A_i[r][p] B_i[p][c]
+// for every slice i < n_inst, operands addressed in their stored order as in
+// GemmArgs' gathered form (slice offsets oa / ob, per-bit stored positions).
+// C is written row-major per slice.  Jobs of one launch are independent (one
+// level of the contraction trees) and sorted by block0.
+struct GettJob {
+    const void* A;
+    const void* B;
+    void* C;
+    const int64_t* oa;
+    const int64_t* ob;
+    int64_t n_inst;
+    int64_t block0;                // first block of this job in the launch
+    int32_t m_log, n_log, k_log;
+    int32_t split;                 // 1: one block per output element (long inner sums)
+    int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+};
+// blocks one job takes in a grouped launch
+int64_t gett_job_blocks(const GettJob& j);
+// One launch for all jobs; d_jobs holds n_jobs records in device memory.
+void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s);
+
+enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3, KC_GROUP = 4 };
 
 // Kernel ids: 0..K_MFMA_TILES-1 = FP32 MFMA GEMM tile configurations,
 // then the other variants.  The choice is a pure function of the shape (and
@@ -59,6 +81,7 @@ enum KernelId {
     K_SMALL32 = 10, K_SPLITK32 = 11,
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
+    K_GROUP32 = 40, K_GROUP64 = 41,
     K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };
 int select_gemm(const GemmArgs& g, int fp64, int tile_hint);

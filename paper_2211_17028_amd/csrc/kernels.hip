@@ -375,6 +375,103 @@ void k_gemm_mfma_g(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Grouped gathered contractions: every small step of one tree level (all
+// clusters, all plans) in one launch.  A block finds its job by binary search
+// over the jobs' first blocks.  Operands are read in their stored order
+// through the per-bit positions (no transpose pass); the low inner bits' offsets
+// come from an LDS table, the high ones are added once per 256-wide chunk.
+//   split == 0: one thread per output element, inner loop in registers;
+//   split == 1: one block per output element (few outputs, long inner sums),
+//               partial sums reduced in FP64 through LDS.
+// ---------------------------------------------------------------------------
+template <typename R, typename C2>
+__global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ jobs, int n_jobs) {
+    __shared__ GettJob J;
+    __shared__ int64_t ak_lo[256], bk_lo[256];
+    __shared__ double red_r[256], red_i[256];
+    const int64_t bid = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].block0 <= bid) lo = mid;
+            else hi = mid - 1;
+        }
+        J = jobs[lo];
+    }
+    __syncthreads();
+    const int m_log = J.m_log, n_log = J.n_log, k_log = J.k_log;
+    const int mn_log = m_log + n_log;
+    const int64_t k = int64_t(1) << k_log;
+    const int kc_log = k_log < 8 ? k_log : 8;
+    const int kc = 1 << kc_log;
+    for (int i = threadIdx.x; i < kc; i += 256) {
+        ak_lo[i] = deposit(i, J.a_k, 0, kc_log);
+        bk_lo[i] = deposit(i, J.b_k, 0, kc_log);
+    }
+    __syncthreads();
+    const int64_t local = bid - J.block0;
+    if (J.split) {
+        // one output element per block; thread t takes inner indices t + 256 h
+        const int64_t o = local;
+        const int64_t inst = o >> mn_log;
+        const int64_t rc = o & ((int64_t(1) << mn_log) - 1);
+        const int64_t r = rc >> n_log, c = rc & ((int64_t(1) << n_log) - 1);
+        const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r, J.a_row, 0, m_log);
+        const C2* __restrict__ Bp = (const C2*)J.B + J.ob[inst] + deposit(c, J.b_col, 0, n_log);
+        R sr = 0, si = 0;
+        if ((int)threadIdx.x < kc) {
+            const int64_t alo = ak_lo[threadIdx.x], blo = bk_lo[threadIdx.x];
+            for (int64_t h = 0; h < k; h += kc) {
+                const C2 a = Ap[deposit(h, J.a_k, kc_log, k_log) + alo];
+                const C2 b = Bp[deposit(h, J.b_k, kc_log, k_log) + blo];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
+        }
+        red_r[threadIdx.x] = (double)sr;
+        red_i[threadIdx.x] = (double)si;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                red_r[threadIdx.x] += red_r[threadIdx.x + w];
+                red_i[threadIdx.x] += red_i[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            C2 out;
+            out.x = (R)red_r[0];
+            out.y = (R)red_i[0];
+            ((C2*)J.C)[o] = out;
+        }
+        return;
+    }
+    const int64_t o = local * 256 + threadIdx.x;
+    if (o >= (J.n_inst << mn_log)) return;
+    const int64_t inst = o >> mn_log;
+    const int64_t rc = o & ((int64_t(1) << mn_log) - 1);
+    const int64_t r = rc >> n_log, c = rc & ((int64_t(1) << n_log) - 1);
+    const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r, J.a_row, 0, m_log);
+    const C2* __restrict__ Bp = (const C2*)J.B + J.ob[inst] + deposit(c, J.b_col, 0, n_log);
+    R sr = 0, si = 0;
+    for (int64_t h = 0; h < k; h += kc) {
+        const C2* __restrict__ Ah = Ap + deposit(h, J.a_k, kc_log, k_log);
+        const C2* __restrict__ Bh = Bp + deposit(h, J.b_k, kc_log, k_log);
+        for (int p = 0; p < kc; ++p) {
+            const C2 a = Ah[ak_lo[p]];
+            const C2 b = Bh[bk_lo[p]];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+        }
+    }
+    C2 out;
+    out.x = sr;
+    out.y = si;
+    ((C2*)J.C)[o] = out;
+}
+
+// ---------------------------------------------------------------------------
 // Small shapes: one thread per output element, k loop in registers.
 // ---------------------------------------------------------------------------
 template <typename R, typename C2>
@@ -739,6 +836,8 @@ const char* kernel_name(int id) {
     case K_TILED64: return "k_gemm_tiled_c128";
     case K_PERM32: return "k_permute<float2>";
     case K_PERM64: return "k_permute<double2>";
+    case K_GROUP32: return "k_gett_group<float>";
+    case K_GROUP64: return "k_gett_group<double>";
     }
     return "unknown";
 }
@@ -748,7 +847,21 @@ int kernel_class(int id) {
     if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return KC_MFMA;
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
+    if (id == K_GROUP32 || id == K_GROUP64) return KC_GROUP;
     return KC_TILED;
+}
+
+int64_t gett_job_blocks(const GettJob& j) {
+    const int64_t outs = j.n_inst << (j.m_log + j.n_log);
+    return j.split ? outs : (outs + 255) / 256;
+}
+
+void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s) {
+    if (n_jobs == 0 || blocks == 0) return;
+    if (fp64)
+        hipLaunchKernelGGL((k_gett_group<double, double2>), dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs);
+    else
+        hipLaunchKernelGGL((k_gett_group<float, float2>), dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs);
 }
 
 static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s, bool gather) {

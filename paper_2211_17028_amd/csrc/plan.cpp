@@ -18,6 +18,7 @@
 #include <queue>
 #include <random>
 #include <sstream>
+#include <thread>
 #include <unordered_map>
 
 #include "tn_internal.h"
@@ -518,17 +519,95 @@ static int union_size(const std::vector<int>& a, const std::vector<int>& b) {
     return n;
 }
 
+// Cost of one pairwise step, in units of one complex multiply-add: the MACs of
+// every instance plus kWriteCost per element written (an element written and
+// read back costs about as much time as this many MACs on the matrix cores).
+constexpr double kWriteCost = 16.0;
+
 struct TrialResult {
     std::vector<PathStep> path;
-    double cost = 0;          // instance-weighted complex MACs
+    double cost = 0;          // instance-weighted step cost (MACs + write cost)
     double cost1 = 0;         // one-term complex MACs
     double peak = 0;          // instance-weighted elements live at once
     int max_log = 0;
+    bool aborted = false;     // stopped once dearer than the best known path
 };
+
+// Leg bookkeeping of a contraction tree: a node's result keeps every leg that
+// some leaf outside its subtree still holds; `total[e]` = leaves holding e.
+struct LegCount {
+    std::vector<std::pair<int, int>> v;   // (leg, holders inside), sorted by leg
+};
+
+static LegCount merge_counts(const LegCount& x, const LegCount& y, const std::unordered_map<int, int>& total,
+                             std::vector<int>* union_legs, std::vector<int>* result_legs) {
+    LegCount out;
+    size_t i = 0, j = 0;
+    while (i < x.v.size() || j < y.v.size()) {
+        int e, c;
+        if (j == y.v.size() || (i < x.v.size() && x.v[i].first < y.v[j].first)) {
+            e = x.v[i].first;
+            c = x.v[i].second;
+            ++i;
+        } else if (i == x.v.size() || y.v[j].first < x.v[i].first) {
+            e = y.v[j].first;
+            c = y.v[j].second;
+            ++j;
+        } else {
+            e = x.v[i].first;
+            c = x.v[i].second + y.v[j].second;
+            ++i;
+            ++j;
+        }
+        if (union_legs) union_legs->push_back(e);
+        if (c < total.at(e)) {
+            out.v.push_back({e, c});
+            if (result_legs) result_legs->push_back(e);
+        }
+    }
+    return out;
+}
+
+// Cost, per-term MACs, max tensor size and instance-weighted live-set peak of
+// a path (steps in execution order).
+static TrialResult evaluate_path(const std::vector<std::vector<int>>& leaf_legs,
+                                 const std::vector<uint64_t>& leaf_mask, const PathSearch& ps,
+                                 const std::vector<PathStep>& path, const std::unordered_map<int, int>& total) {
+    const int L = (int)leaf_legs.size();
+    std::vector<LegCount> cnt(L + path.size());
+    std::vector<uint64_t> mask(L + path.size());
+    std::vector<double> size(L + path.size());
+    TrialResult tr;
+    double live = 0;
+    for (int i = 0; i < L; ++i) {
+        for (int e : leaf_legs[i]) cnt[i].v.push_back({e, 1});
+        mask[i] = leaf_mask[i];
+        size[i] = ps.instances(mask[i]) * std::ldexp(1.0, (int)leaf_legs[i].size());
+        live += size[i];
+        tr.max_log = std::max(tr.max_log, (int)leaf_legs[i].size());
+    }
+    tr.peak = live;
+    for (size_t j = 0; j < path.size(); ++j) {
+        const int a = path[j].a, b = path[j].b, c = L + (int)j;
+        std::vector<int> un, res;
+        cnt[c] = merge_counts(cnt[a], cnt[b], total, &un, &res);
+        mask[c] = mask[a] | mask[b];
+        const double inst = ps.instances(mask[c]);
+        size[c] = inst * std::ldexp(1.0, (int)res.size());
+        tr.cost += inst * std::ldexp(1.0, (int)un.size()) + kWriteCost * size[c];
+        tr.cost1 += std::ldexp(1.0, (int)un.size());
+        tr.max_log = std::max(tr.max_log, (int)res.size());
+        live += size[c];
+        tr.peak = std::max(tr.peak, live);
+        live -= size[a] + size[b];
+    }
+    tr.path = path;
+    return tr;
+}
 
 static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
                                 const std::vector<uint64_t>& leaf_mask, const PathSearch& ps,
-                                double alpha, double temp, uint64_t seed) {
+                                double alpha, double temp, uint64_t seed, const std::atomic<double>* abort_cost) {
     std::mt19937_64 rng(seed);
     std::uniform_real_distribution<double> uni(1e-12, 1.0);
     const int L = (int)leaf_legs.size();
@@ -571,9 +650,6 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
         for (size_t x = 0; x < kv.second.size(); ++x)
             for (size_t y = x + 1; y < kv.second.size(); ++y) push(kv.second[x], kv.second[y]);
     TrialResult tr;
-    double live = 0;
-    for (int i = 0; i < L; ++i) live += size_of(i);
-    tr.peak = live;
     int remaining = L;
     while (remaining > 1) {
         int a, b;
@@ -597,13 +673,12 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
         uint64_t mc = mask[a] | mask[b];
         int u = union_size(legs[a], legs[b]);
         double inst = ps.instances(mc);
-        tr.cost += inst * std::ldexp(1.0, u);
-        tr.cost1 += std::ldexp(1.0, u);
-        tr.max_log = std::max(tr.max_log, (int)lc.size());
+        tr.cost += inst * (std::ldexp(1.0, u) + kWriteCost * std::ldexp(1.0, (int)lc.size()));
+        if (abort_cost && tr.cost > abort_cost->load(std::memory_order_relaxed)) {
+            tr.aborted = true;
+            return tr;
+        }
         int c = (int)legs.size();
-        live += inst * std::ldexp(1.0, (int)lc.size());
-        tr.peak = std::max(tr.peak, live);
-        live -= size_of(a) + size_of(b);
         legs.push_back(lc);
         mask.push_back(mc);
         alive.push_back(1);
@@ -626,7 +701,188 @@ static TrialResult greedy_trial(const std::vector<std::vector<int>>& leaf_legs,
     return tr;
 }
 
-static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, double max_peak) {
+// Subtree reconfiguration: for every internal node of the tree, cut its
+// subtree at up to kReconfLeaves pieces (expanding the dearest steps first),
+// find the cheapest binary tree over those pieces by dynamic programming over
+// subsets (same cost model, result sizes capped at 2^max_log) and keep it when
+// it is cheaper.  Repeated until a pass changes nothing.
+constexpr int kReconfLeaves = 8;
+constexpr int kReconfCandidates = 8;      // distinct greedy paths reconfigured per cluster
+
+static std::vector<PathStep> reconfigure(const std::vector<std::vector<int>>& leaf_legs,
+                                         const std::vector<uint64_t>& leaf_mask, const PathSearch& ps,
+                                         const std::vector<PathStep>& path,
+                                         const std::unordered_map<int, int>& total, int max_log) {
+    const int L = (int)leaf_legs.size();
+    const int NN = L + (int)path.size();
+    if (path.size() < 2) return path;
+    std::vector<int> ca(NN, -1), cb(NN, -1), par(NN, -1);
+    for (size_t j = 0; j < path.size(); ++j) {
+        ca[L + j] = path[j].a;
+        cb[L + j] = path[j].b;
+        par[path[j].a] = par[path[j].b] = L + (int)j;
+    }
+    const int root = NN - 1;
+    std::vector<LegCount> cnt(NN);
+    std::vector<uint64_t> mask(NN);
+    std::vector<double> step(NN, 0.0);
+    std::vector<int> nres(NN, 0);
+    for (int i = 0; i < L; ++i) {
+        for (int e : leaf_legs[i]) cnt[i].v.push_back({e, 1});
+        mask[i] = leaf_mask[i];
+        nres[i] = (int)leaf_legs[i].size();
+    }
+    auto update = [&](int n) {
+        std::vector<int> un, res;
+        cnt[n] = merge_counts(cnt[ca[n]], cnt[cb[n]], total, &un, &res);
+        mask[n] = mask[ca[n]] | mask[cb[n]];
+        nres[n] = (int)res.size();
+        const double inst = ps.instances(mask[n]);
+        step[n] = inst * (std::ldexp(1.0, (int)un.size()) + kWriteCost * std::ldexp(1.0, nres[n]));
+    };
+    // bottom-up (path order is a valid topological order)
+    for (int n = L; n < NN; ++n) update(n);
+    std::function<void(int, std::vector<int>&)> postorder = [&](int n, std::vector<int>& out) {
+        if (n < L) return;
+        postorder(ca[n], out);
+        postorder(cb[n], out);
+        out.push_back(n);
+    };
+    for (int pass = 0; pass < 8; ++pass) {
+        bool changed = false;
+        std::vector<int> order;
+        postorder(root, order);
+        for (int node : order) {
+            // region: node plus the internal nodes expanded below it
+            std::vector<int> region{node}, items{ca[node], cb[node]};
+            while ((int)items.size() < kReconfLeaves) {
+                int pick = -1;
+                for (size_t q = 0; q < items.size(); ++q)
+                    if (items[q] >= L && (pick < 0 || step[items[q]] > step[items[pick]])) pick = (int)q;
+                if (pick < 0) break;
+                const int x = items[pick];
+                region.push_back(x);
+                items[pick] = ca[x];
+                items.push_back(cb[x]);
+            }
+            const int k = (int)items.size();
+            if (k < 3) continue;
+            double old = 0;
+            for (int r : region) old += step[r];
+            // local leg ids of the legs the pieces hold
+            std::vector<int> lid;
+            for (int it : items)
+                for (auto& pr : cnt[it].v) lid.push_back(pr.first);
+            std::sort(lid.begin(), lid.end());
+            lid.erase(std::unique(lid.begin(), lid.end()), lid.end());
+            if (lid.size() > 256) continue;
+            const int S = 1 << k;
+            struct Bits {
+                uint64_t w[4] = {0, 0, 0, 0};
+                int pop() const {
+                    return __builtin_popcountll(w[0]) + __builtin_popcountll(w[1]) + __builtin_popcountll(w[2]) +
+                           __builtin_popcountll(w[3]);
+                }
+            };
+            std::vector<Bits> res(S), held(S);
+            std::vector<double> inst(S);
+            std::vector<uint64_t> smask(S, 0);
+            std::vector<std::vector<int>> cin(S, std::vector<int>(lid.size(), 0));
+            for (int T = 1; T < S; ++T) {
+                const int low = __builtin_ctz(T);
+                const int rest = T & (T - 1);
+                cin[T] = cin[rest];
+                smask[T] = smask[rest] | mask[items[low]];
+                for (auto& pr : cnt[items[low]].v) {
+                    const int li = (int)(std::lower_bound(lid.begin(), lid.end(), pr.first) - lid.begin());
+                    cin[T][li] += pr.second;
+                }
+                for (size_t li = 0; li < lid.size(); ++li)
+                    if (cin[T][li] > 0 && cin[T][li] < total.at(lid[li])) res[T].w[li >> 6] |= 1ULL << (li & 63);
+                inst[T] = ps.instances(smask[T]);
+            }
+            std::vector<double> best(S, std::numeric_limits<double>::infinity());
+            std::vector<int> split(S, 0);
+            for (int q = 0; q < k; ++q) best[1 << q] = 0;
+            for (int T = 1; T < S; ++T) {
+                if (__builtin_popcount(T) < 2) continue;
+                const int nr = res[T].pop();
+                if (T != S - 1 && nr > max_log) continue;
+                const double wcost = kWriteCost * std::ldexp(1.0, nr);
+                const int low = T & -T;
+                for (int T1 = (T - 1) & T; T1 > 0; T1 = (T1 - 1) & T) {
+                    if (!(T1 & low)) continue;
+                    const int T2 = T ^ T1;
+                    const double sub = best[T1] + best[T2];
+                    if (!(sub < best[T])) continue;
+                    Bits u;
+                    for (int w = 0; w < 4; ++w) u.w[w] = res[T1].w[w] | res[T2].w[w];
+                    const double c = sub + inst[T] * (std::ldexp(1.0, u.pop()) + wcost);
+                    if (c < best[T]) {
+                        best[T] = c;
+                        split[T] = T1;
+                    }
+                }
+            }
+            if (!(best[S - 1] < old * (1.0 - 1e-9))) continue;
+            // rebuild the region: reuse its node ids, node keeps the root id
+            std::vector<int> free_ids(region.begin() + 1, region.end());
+            std::function<int(int, bool)> build = [&](int T, bool is_root) -> int {
+                if (__builtin_popcount(T) == 1) return items[__builtin_ctz(T)];
+                const int n = is_root ? node : free_ids.back();
+                if (!is_root) free_ids.pop_back();
+                const int l = build(split[T], false), r = build(T ^ split[T], false);
+                ca[n] = l;
+                cb[n] = r;
+                par[l] = par[r] = n;
+                return n;
+            };
+            build(S - 1, true);
+            // refresh the region bottom-up
+            std::vector<int> sub_order;
+            std::function<void(int)> walk = [&](int n) {
+                if (n < L || std::find(items.begin(), items.end(), n) != items.end()) return;
+                walk(ca[n]);
+                walk(cb[n]);
+                sub_order.push_back(n);
+            };
+            walk(node);
+            for (int n : sub_order) update(n);
+            changed = true;
+        }
+        if (!changed) break;
+    }
+    // emit: post-order, the larger subtree first
+    std::vector<int> nleaves(NN, 1);
+    std::vector<int> order;
+    std::function<void(int)> count = [&](int n) {
+        if (n < L) return;
+        count(ca[n]);
+        count(cb[n]);
+        nleaves[n] = nleaves[ca[n]] + nleaves[cb[n]];
+    };
+    count(root);
+    std::function<void(int)> emit = [&](int n) {
+        if (n < L) return;
+        int x = ca[n], y = cb[n];
+        if (nleaves[y] > nleaves[x]) std::swap(x, y);
+        emit(x);
+        emit(y);
+        order.push_back(n);
+    };
+    emit(root);
+    std::vector<int> newid(NN, -1);
+    for (int i = 0; i < L; ++i) newid[i] = i;
+    std::vector<PathStep> out;
+    for (size_t j = 0; j < order.size(); ++j) {
+        const int n = order[j];
+        out.push_back({newid[ca[n]], newid[cb[n]]});
+        newid[n] = L + (int)j;
+    }
+    return out;
+}
+
+static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, double max_peak, bool reconf) {
     const int nl = (int)p.leaves.size();
     // union-find over shared legs
     std::vector<int> parent(nl);
@@ -676,27 +932,86 @@ static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, doubl
             p.clusters.push_back(cl);
             continue;
         }
-        TrialResult best;
-        bool have = false;
+        std::unordered_map<int, int> total;
+        for (auto& lg : leaf_legs)
+            for (int e : lg) ++total[e];
         const double alphas[4] = {1.0, 0.5, 0.0, 0.75};
         const double temps[3] = {0.5, 1.0, 2.0};
         // a path is admissible when one instance of every tensor fits in 2^max_log
         // elements and the instance-weighted live set fits in max_peak elements;
-        // among admissible paths the cheapest wins, else the smallest peak
+        // among admissible paths the cheapest wins (lowest trial index on ties),
+        // else the smallest peak.  Trials run on all host threads; a trial stops
+        // once it costs more than twice the best admissible path so far.  That
+        // never stops a trial within twice the final best, so the candidates
+        // below (the cheapest trials within that factor) do not depend on timing.
         auto admissible = [&](const TrialResult& r) { return r.max_log <= max_log && r.peak <= max_peak; };
+        std::vector<TrialResult> results(trials);
+        std::atomic<double> abort_cost{std::numeric_limits<double>::infinity()};
+        std::atomic<int> next{0};
+        const int nth = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, trials}));
+        auto run_pool = [&](const std::function<void()>& fn) {
+            std::vector<std::thread> pool;
+            for (int q = 1; q < nth; ++q) pool.emplace_back(fn);
+            fn();
+            for (auto& th : pool) th.join();
+        };
+        run_pool([&]() {
+            for (int t = next++; t < trials; t = next++) {
+                const double alpha = alphas[t % 4];
+                const double temp = t < 4 ? 0.0 : temps[t % 3];
+                TrialResult tr = greedy_trial(leaf_legs, leaf_mask, ps, alpha, temp,
+                                              seed * 1000003ULL + (uint64_t)t * 7919ULL + 17, &abort_cost);
+                if (!tr.aborted) {
+                    tr = evaluate_path(leaf_legs, leaf_mask, ps, tr.path, total);
+                    if (admissible(tr)) {
+                        double cur = abort_cost.load();
+                        while (2.0 * tr.cost < cur && !abort_cost.compare_exchange_weak(cur, 2.0 * tr.cost)) {
+                        }
+                    }
+                }
+                results[t] = std::move(tr);
+            }
+        });
+        TrialResult best;
+        bool have = false;
         for (int t = 0; t < trials; ++t) {
-            double alpha = alphas[t % 4];
-            double temp = t < 4 ? 0.0 : temps[t % 3];
-            TrialResult tr = greedy_trial(leaf_legs, leaf_mask, ps, alpha, temp,
-                                          seed * 1000003ULL + (uint64_t)t * 7919ULL + 17);
+            TrialResult& tr = results[t];
+            if (tr.aborted) continue;
             bool ok = admissible(tr);
             bool best_ok = have && admissible(best);
             bool better = ok ? tr.cost < best.cost : (tr.max_log < best.max_log ||
                                                      (tr.max_log == best.max_log && tr.peak < best.peak));
             if (!have || (ok && !best_ok) || (ok == best_ok && better)) {
-                best = std::move(tr);
+                best = tr;
                 have = true;
             }
+        }
+        if (have && admissible(best) && reconf) {
+            // reconfigure the cheapest few distinct trials within twice the best
+            std::vector<int> cand;
+            for (int t = 0; t < trials; ++t)
+                if (!results[t].aborted && admissible(results[t]) && results[t].cost <= 2.0 * best.cost)
+                    cand.push_back(t);
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](int x, int y) { return results[x].cost < results[y].cost; });
+            std::vector<int> pick;
+            for (int t : cand) {
+                bool dup = false;
+                for (int q : pick) dup |= results[q].cost == results[t].cost;
+                if (!dup) pick.push_back(t);
+                if ((int)pick.size() == kReconfCandidates) break;
+            }
+            std::vector<TrialResult> rc(pick.size());
+            std::atomic<int> nx{0};
+            run_pool([&]() {
+                for (int q = nx++; q < (int)pick.size(); q = nx++) {
+                    const TrialResult& src = results[pick[q]];
+                    rc[q] = evaluate_path(leaf_legs, leaf_mask, ps,
+                                          reconfigure(leaf_legs, leaf_mask, ps, src.path, total, max_log), total);
+                }
+            });
+            for (auto& r : rc)
+                if (admissible(r) && r.cost < best.cost) best = std::move(r);
         }
         if (!admissible(best)) {
             std::ostringstream os;
@@ -785,11 +1100,11 @@ Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, in
     fuse_fixed(nb);
     p->leaves = std::move(nb.leaves);
     p->scalar = nb.scalar;
-    int trials = (opts && opts->path_trials > 0) ? opts->path_trials : 64;
+    int trials = (opts && opts->path_trials > 0) ? opts->path_trials : 1024;
     uint64_t seed = (opts && opts->seed) ? opts->seed : 2211170280ULL;
     int max_log = (opts && opts->max_log_size > 0) ? opts->max_log_size : 30;
     double max_bytes = (opts && opts->max_work_bytes > 0) ? opts->max_work_bytes : 64.0 * (1ULL << 30);
-    plan_clusters(*p, trials, seed, max_log, max_bytes / 8.0);
+    plan_clusters(*p, trials, seed, max_log, max_bytes / 8.0, !(opts && opts->no_reconfigure));
     return p.release();
 }
 

@@ -49,7 +49,7 @@ class tn_state(C.Structure):
 class tn_plan_opts(C.Structure):
     _fields_ = [("path_trials", C.c_int32), ("seed", C.c_uint64), ("no_light_cone", C.c_int32),
                 ("max_log_size", C.c_int32), ("no_diagonal_hyperedges", C.c_int32),
-                ("max_work_bytes", C.c_double)]
+                ("max_work_bytes", C.c_double), ("no_reconfigure", C.c_int32)]
 
 
 class tn_prune_opts(C.Structure):
@@ -58,7 +58,8 @@ class tn_prune_opts(C.Structure):
 
 class tn_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
-                ("tune", C.c_int32), ("time_kernels", C.c_int32), ("no_gather", C.c_int32)]
+                ("tune", C.c_int32), ("time_kernels", C.c_int32), ("no_gather", C.c_int32),
+                ("no_group", C.c_int32)]
 
 
 class tn_kernel_stat(C.Structure):
@@ -252,10 +253,10 @@ class Terms:
 
 def tn_plan_build(circ, level: Optional[int] = None, path_trials: int = 0, seed: int = 0,
                   light_cone: bool = True, max_log_size: int = 0, diagonal_hyperedges: bool = True,
-                  max_work_bytes: float = 0.0) -> Plan:
+                  max_work_bytes: float = 0.0, reconfigure: bool = True) -> Plan:
     bufs = _CircuitBuffers(circ)
     opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size,
-                        0 if diagonal_hyperedges else 1, max_work_bytes)
+                        0 if diagonal_hyperedges else 1, max_work_bytes, 0 if reconfigure else 1)
     h = C.c_void_p()
     lev = circ.level if level is None else level
     _check(lib().tn_plan_build(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v), lev,
@@ -359,9 +360,9 @@ def _stream_ptr(stream):
 
 
 def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False,
-              gather=True):
+              gather=True, group=True):
     return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
-                        1 if time_kernels else 0, 0 if gather else 1)
+                        1 if time_kernels else 0, 0 if gather else 1, 0 if group else 1)
 
 
 def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):

@@ -10,6 +10,10 @@ tests, which run the kernels themselves.
 import numpy as np
 
 
+def _overlap(x, y):
+    return x[0] == y[0] and x[1] < y[2] and y[1] < x[2]
+
+
 class Sim:
     def __init__(self, desc, const_bytes):
         self.desc = desc
@@ -89,12 +93,10 @@ class Sim:
         Cv = self.view(L["c"], dt, ni * m * n, c_extra).reshape(ni, m, n)
         Cv[...] = np.matmul(A[ia].astype(np.complex128), B[ib].astype(np.complex128)).astype(dt)
 
-    def gemm_gather(self, L, c_extra=0):
+    def gemm_gather(self, L, c_extra=0, dt=np.complex64):
         """Operands read in stored order: logical bit j of the row / inner /
         column index sits at the stored position a_row[j] / a_k[j] (b_k[j]) /
         b_col[j]; instance i starts at offset oa[i] (ob[i])."""
-        assert not L["fp64"]
-        dt = np.complex64
         m, n, k = 1 << L["m_log"], 1 << L["n_log"], 1 << L["k_log"]
         ni = L["n_inst"]
 
@@ -192,7 +194,41 @@ class Sim:
             elif L["kind"] == 3:
                 self.level_sum(L)
 
+    def group(self, L):
+        """One grouped launch: every job is an independent gathered contraction
+        (same addressing as the gathered GEMM); jobs of one launch never write
+        what another job of it reads."""
+        dt = np.complex128 if L["fp64"] else np.complex64
+        esz = np.dtype(dt).itemsize
+        spans = []
+        for jb in L["jobs"]:
+            spans.append(self._job_spans(jb, esz))
+        for i, (wi, _) in enumerate(spans):
+            for j, (wj, rj) in enumerate(spans):
+                for other in ([wj] if i != j else []) + rj:
+                    assert not _overlap(wi, other), ("grouped jobs race", i, j, wi, other)
+        for jb in L["jobs"]:
+            self.gemm_gather(jb, dt=dt)
+
+    def _job_spans(self, jb, esz):
+        """(write span, [read spans]) of one grouped job, as (region, start, end) bytes."""
+        m, n, k = 1 << jb["m_log"], 1 << jb["n_log"], 1 << jb["k_log"]
+        ni = jb["n_inst"]
+        oa = self.view(jb["oa"], np.int64, ni)
+        ob = self.view(jb["ob"], np.int64, ni)
+        amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
+        bmax = int(ob.max()) + sum(1 << p for p in jb["b_k"] + jb["b_col"])
+
+        def span(ref, lo, hi):
+            r = self._ref(ref)
+            return (min(r[0], 1), r[1] + lo * esz, r[1] + hi * esz)
+        return (span(jb["c"], 0, ni * m * n),
+                [span(jb["a"], int(oa.min()), amax + 1), span(jb["b"], int(ob.min()), bmax + 1)])
+
     def exec(self, L):
+        if L["kind"] == 5:
+            self.group(L)
+            return
         if L["kind"] == 0:
             self.perm(L)
         elif L["kind"] == 1:
