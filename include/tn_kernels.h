@@ -19,7 +19,35 @@
  *   Device pointers; `perm` is a host array of r ints.  block_elems_log: log2
  *   of the elements one block moves (0 = the library default; at most 12 for
  *   complex64, 11 for complex128).  Synchronizes `stream`.
+ *
+ * tn_kernel_mfma_group: one grouped matrix-core launch (complex64 data, FP32
+ *   MFMA), the kernel batched execution runs for the contraction steps of one
+ *   tree level.  Job j: slices s < n_slices with C_s = A_s B_s; the element
+ *   (row r, inner p) of slice s of A sits at oa[s] + sum_i bit_i(r) << a_row[i]
+ *   + sum_i bit_i(p) << a_k[i] (B likewise with ob, b_k, b_col); C_s is an
+ *   m x n row-major block at oc[s].  merge = 1: a tile's columns hold `cnt`
+ *   consecutive slices sharing A; 2: its rows hold `cnt` slices sharing B;
+ *   0: one slice per tile (origin tm0, tn0).  Jobs and tiles are device
+ *   arrays in the tn_mfma_job / tn_mfma_tile layouts; `tile` selects the tile
+ *   shape (0..7: 128x64, 64x64, 128x32, 64x32, 32x32, 128x16, 64x16, 32x16).
+ *   Asynchronous on `stream`.  Returns 0 or a negative TN_E* code.
  */
+typedef struct {
+    const void* A;
+    const void* B;
+    void* C;
+    const int64_t* oa;
+    const int64_t* ob;
+    const int64_t* oc;
+    int32_t m_log, n_log, k_log;
+    int32_t merge;
+    int32_t a_rowfast, b_colfast;  /* lowest stored bit of A is a row bit / of B a column bit */
+    int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+} tn_mfma_job;
+typedef struct {
+    int32_t job, cnt;
+    int64_t s0, tm0, tn0;
+} tn_mfma_tile;
 #ifndef TN_KERNELS_H
 #define TN_KERNELS_H
 #include <stdint.h>
@@ -32,6 +60,8 @@ int tn_kernel_gemm(int32_t fp64, const void* A, const void* B, void* C, const in
                    void* stream);
 int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64_t n_inst, int32_t r,
                       const int32_t* perm, int32_t block_elems_log, void* stream);
+int tn_kernel_mfma_group(int32_t tile, const tn_mfma_job* d_jobs, const tn_mfma_tile* d_tiles,
+                         int64_t n_tiles, void* stream);
 #ifdef __cplusplus
 }
 #endif

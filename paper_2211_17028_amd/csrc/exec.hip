@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <numeric>
 #include <memory>
 #include <sstream>
 #include <tuple>
@@ -97,8 +98,10 @@ struct Ref {
     int64_t off = 0;
 };
 
-enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4, L_GROUP = 5 };
+enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4, L_GROUP = 5,
+                  L_MGROUP = 6 };
 struct GroupJob;
+struct MJob;
 
 struct Launch {
     int kind = 0;
@@ -128,6 +131,11 @@ struct Launch {
     int n_jobs = 0;
     int64_t blocks = 0;
     std::vector<struct GroupJob> hjobs;
+    // grouped matrix-core launch (L_MGROUP)
+    int mtile = 0;
+    Ref tiles;
+    int64_t n_tiles = 0;
+    std::vector<struct MJob> mjobs;
 };
 
 struct PlanExec {
@@ -191,11 +199,26 @@ struct NodeInfo {
 // concrete ones when the steps are placed in memory (level by level).
 enum { R_NODE = 10, R_TEMP = 11 };
 
+// FP32 steps of at least this many flops run on the matrix cores whatever
+// their shape (below it, only shapes that fill a tile do), unless their
+// inner sums are long (a tile walks its inner index alone) or their slices
+// have fewer than 8 outputs (inner products: split sums in the small kernel).
+constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
+
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
     Ref a, b, c, oa, ob;
     int64_t n_inst = 0;
     int m_log = 0, n_log = 0, k_log = 0, split = 0;
+    int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
+    double flops = 0, bytes = 0;
+};
+
+// One grouped matrix-core contraction (host side of an MfmaJob).
+struct MJob {
+    Ref a, b, c, oa, ob, oc;
+    int m_log = 0, n_log = 0, k_log = 0, merge = 0, a_rowfast = 0, b_colfast = 0;
+    int64_t ns = 0;            // slices
     int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
     double flops = 0, bytes = 0;
 };
@@ -213,6 +236,10 @@ struct StepRec {
     std::vector<Launch> launches;   // transposes, then the GEMM unless grouped
     bool grouped = false;
     GroupJob job;
+    bool mgrouped = false;     // runs in its level's grouped matrix-core launch
+    int mtile = 0;
+    MJob mjob;
+    std::vector<MfmaTile> mtiles;   // job index filled at emission
 };
 
 struct Builder {
@@ -303,6 +330,161 @@ struct Builder {
                 ++h;
             }
         return L;
+    }
+
+    // Grouped matrix-core job of one FP32 step: orientation, tile shape and
+    // merge mode are chosen by the padded tile work (a per-tile-shape
+    // efficiency factor, plus a fixed cost per tile); slices are ordered so that
+    // slices sharing the merged operand are adjacent, then cut into tiles.
+    template <typename PosIn, typename ByPos, typename SliceVec>
+    void plan_mfma_job(StepRec& st, const NodeInfo& A, const NodeInfo& B, NodeInfo& C, const std::vector<int>& K,
+                       const std::vector<int>& Bt, const std::vector<int>& FA, const std::vector<int>& FB,
+                       int64_t ninst, int64_t nbatch, PosIn posin, ByPos by_pos, SliceVec slice_vec) {
+        static const double kEff[K_MFMA_TILES] = {1.0, 0.6, 0.75, 0.5, 0.35, 0.45, 0.3, 0.2};
+        const int rk = (int)K.size();
+        const int64_t ns = ninst * nbatch;
+        std::vector<int64_t> so[2][2];
+        std::vector<int> btb[2];
+        auto run_counts = [](std::vector<int64_t> v) {
+            std::sort(v.begin(), v.end());
+            std::vector<int64_t> c;
+            for (size_t i = 0; i < v.size();) {
+                size_t j = i;
+                while (j < v.size() && v[j] == v[i]) ++j;
+                c.push_back((int64_t)(j - i));
+                i = j;
+            }
+            return c;
+        };
+        double best_cost = 1e300;
+        int best_o = 0, best_tile = 0, best_merge = 0;
+        for (int o = 0; o < 2; ++o) {
+            const NodeInfo& R = o ? B : A;
+            const NodeInfo& Q = o ? A : B;
+            const int m_log = (int)(o ? FB.size() : FA.size()), n_log = (int)(o ? FA.size() : FB.size());
+            const bool r_big = ((int64_t)R.keys.size() << R.legs.size()) >= ((int64_t)Q.keys.size() << Q.legs.size());
+            btb[o] = by_pos(Bt, r_big ? R : Q);
+            so[o][0] = slice_vec(R, btb[o]);
+            so[o][1] = slice_vec(Q, btb[o]);
+            const std::vector<int64_t> ca = run_counts(so[o][0]), cb = run_counts(so[o][1]);
+            for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+                const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
+                const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
+                const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
+                const double per_tile = std::ldexp(1.0, bm_log + bn_log) * (std::ldexp(1.0, rk) + 16.0) / kEff[tile];
+                auto consider = [&](int64_t tiles, int merge) {
+                    const double cst = (double)tiles * per_tile;
+                    if (cst < best_cost) {
+                        best_cost = cst;
+                        best_o = o;
+                        best_tile = tile;
+                        best_merge = merge;
+                    }
+                };
+                consider(ns * rt * ct, 0);
+                if (n_log < bn_log) {
+                    const int64_t segs = int64_t(1) << (bn_log - n_log);
+                    int64_t t = 0;
+                    for (int64_t c : ca) t += (c + segs - 1) / segs;
+                    consider(t * rt, 1);
+                }
+                if (m_log < bm_log) {
+                    const int64_t segs = int64_t(1) << (bm_log - m_log);
+                    int64_t t = 0;
+                    for (int64_t c : cb) t += (c + segs - 1) / segs;
+                    consider(t * ct, 2);
+                }
+            }
+        }
+        const int o = best_o;
+        const NodeInfo& R = o ? B : A;
+        const NodeInfo& Q = o ? A : B;
+        const std::vector<int>& FR = o ? FB : FA;
+        const std::vector<int>& FQ = o ? FA : FB;
+        const bool r_big = ((int64_t)R.keys.size() << R.legs.size()) >= ((int64_t)Q.keys.size() << Q.legs.size());
+        std::vector<int> row_bits = by_pos(FR, R), col_bits = by_pos(FQ, Q), k_bits = by_pos(K, r_big ? R : Q);
+        const std::vector<int>& bt_bits = btb[o];
+        C.legs.assign(bt_bits.rbegin(), bt_bits.rend());
+        C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
+        C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
+        C.bytes = ninst * (int64_t(8) << C.legs.size());
+        C.buf = Ref{R_NODE, C.gid};
+        MJob& jb = st.mjob;
+        jb.m_log = (int)FR.size();
+        jb.n_log = (int)FQ.size();
+        jb.k_log = rk;
+        jb.ns = ns;
+        jb.merge = best_merge;
+        for (size_t q = 0; q < row_bits.size(); ++q) jb.a_row[q] = (int8_t)posin(R, row_bits[q]);
+        for (size_t q = 0; q < k_bits.size(); ++q) {
+            jb.a_k[q] = (int8_t)posin(R, k_bits[q]);
+            jb.b_k[q] = (int8_t)posin(Q, k_bits[q]);
+        }
+        for (size_t q = 0; q < col_bits.size(); ++q) jb.b_col[q] = (int8_t)posin(Q, col_bits[q]);
+        jb.a_rowfast = std::find(FR.begin(), FR.end(), R.legs.back()) != FR.end();
+        jb.b_colfast = std::find(FQ.begin(), FQ.end(), Q.legs.back()) != FQ.end();
+        // slice order: slices sharing the merged operand adjacent (stable)
+        std::vector<int64_t> order(ns);
+        std::iota(order.begin(), order.end(), 0);
+        const std::vector<int64_t>& oa = so[o][0];
+        const std::vector<int64_t>& ob = so[o][1];
+        if (best_merge == 1)
+            std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return oa[x] < oa[y]; });
+        if (best_merge == 2)
+            std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return ob[x] < ob[y]; });
+        std::vector<int64_t> soa(ns), sob(ns), soc(ns);
+        for (int64_t i = 0; i < ns; ++i) {
+            soa[i] = oa[order[i]];
+            sob[i] = ob[order[i]];
+            soc[i] = order[i] << (jb.m_log + jb.n_log);
+        }
+        const int bm = mfma_tile_bm(best_tile), bn = mfma_tile_bn(best_tile);
+        const int bm_log = __builtin_ctz(bm), bn_log = __builtin_ctz(bn);
+        const int64_t rt = jb.m_log >= bm_log ? int64_t(1) << (jb.m_log - bm_log) : 1;
+        const int64_t ct = jb.n_log >= bn_log ? int64_t(1) << (jb.n_log - bn_log) : 1;
+        auto tile = [&](int cnt, int64_t s0, int64_t tm0, int64_t tn0) {
+            MfmaTile t{};
+            t.job = -1;
+            t.cnt = cnt;
+            t.s0 = s0;
+            t.tm0 = tm0;
+            t.tn0 = tn0;
+            st.mtiles.push_back(t);
+        };
+        if (best_merge == 0) {
+            for (int64_t i = 0; i < ns; ++i)
+                for (int64_t r = 0; r < rt; ++r)
+                    for (int64_t c = 0; c < ct; ++c) tile(1, i, r * bm, c * bn);
+        } else {
+            const std::vector<int64_t>& key = best_merge == 1 ? soa : sob;
+            const int64_t segs = best_merge == 1 ? int64_t(1) << (bn_log - jb.n_log)
+                                                 : int64_t(1) << (bm_log - jb.m_log);
+            for (int64_t g0 = 0; g0 < ns;) {
+                int64_t g1 = g0;
+                while (g1 < ns && key[g1] == key[g0]) ++g1;
+                for (int64_t p0 = g0; p0 < g1; p0 += segs) {
+                    const int cnt = (int)std::min<int64_t>(segs, g1 - p0);
+                    if (best_merge == 1)
+                        for (int64_t r = 0; r < rt; ++r) tile(cnt, p0, r * bm, 0);
+                    else
+                        for (int64_t c = 0; c < ct; ++c) tile(cnt, p0, 0, c * bn);
+                }
+                g0 = g1;
+            }
+        }
+        jb.a = R.buf;
+        jb.b = Q.buf;
+        jb.c = C.buf;
+        jb.oa = Ref{R_CONST, ex->cbuf.add(soa.data(), ns * 8)};
+        jb.ob = Ref{R_CONST, ex->cbuf.add(sob.data(), ns * 8)};
+        jb.oc = Ref{R_CONST, ex->cbuf.add(soc.data(), ns * 8)};
+        const double mm = std::ldexp(1.0, jb.m_log), nnn = std::ldexp(1.0, jb.n_log), kk = std::ldexp(1.0, rk);
+        jb.flops = 8.0 * mm * nnn * kk * (double)ns;
+        jb.bytes = 8.0 * ((double)ns * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
+                          (double)Q.keys.size() * nbatch * kk * nnn);
+        st.mgrouped = true;
+        st.mtile = best_tile;
+        st.c_bytes = C.bytes;
     }
 
     // Plan the steps of one cluster for the given root instance keys.
@@ -535,7 +717,7 @@ struct Builder {
                 return v;
             };
             // slice offsets of an operand: instance base + the batch bits' stored offset
-            auto slice_offsets = [&](const NodeInfo& X, const std::vector<int>& bt_bits) {
+            auto slice_vec = [&](const NodeInfo& X, const std::vector<int>& bt_bits) {
                 std::vector<int64_t> o(ninst * nbatch);
                 const int64_t isz = int64_t(1) << X.legs.size();
                 for (int64_t i = 0; i < ninst; ++i) {
@@ -547,6 +729,10 @@ struct Builder {
                         o[i * nbatch + b2] = off;
                     }
                 }
+                return o;
+            };
+            auto slice_offsets = [&](const NodeInfo& X, const std::vector<int>& bt_bits) {
+                std::vector<int64_t> o = slice_vec(X, bt_bits);
                 return Ref{R_CONST, ex->cbuf.add(o.data(), (int64_t)o.size() * 8)};
             };
             // Small steps (below a matrix-core tile in FP32, below the tiled
@@ -560,6 +746,18 @@ struct Builder {
                 g0.k_log = rk;
                 const int id = select_gemm(g0, fp64, -1);
                 big = fp64 ? id == K_TILED64 : kernel_class(id) == KC_MFMA;
+            }
+            // FP32 steps with enough work go to the matrix cores even when their
+            // own shape is too small for a tile: slices that share an operand
+            // are stacked into one tile (merge modes)
+            const double step_flops = 8.0 * (double)ninst * (double)nbatch *
+                                      std::ldexp(1.0, (int)(FA.size() + FB.size()) + rk);
+            const bool heavy = step_flops >= kMfmaMinFlops && rk <= 11 && FA.size() + FB.size() >= 3;
+            if (grouping && mode == 0 && (big || heavy)) {
+                plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec);
+                node_bytes[C.gid] = C.bytes;
+                steps->push_back(std::move(st));
+                continue;
             }
             if (grouping && mode != 2 && !big) {
                 // column operand: one whose lowest stored leg is a free leg, so
@@ -827,6 +1025,37 @@ struct Builder {
                 G.bytes += jb.bytes;
                 G.hjobs.push_back(jb);
             }
+            for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+                Launch M;
+                M.kind = L_MGROUP;
+                M.mtile = tile;
+                M.kclass = K_MFMA_GROUP_BASE + tile;
+                std::vector<MfmaTile> tl;
+                for (int i : grp) {
+                    StepRec& st = steps[i];
+                    if (!st.mgrouped || st.mtile != tile) continue;
+                    MJob jb = st.mjob;
+                    subst(jb.a);
+                    subst(jb.b);
+                    subst(jb.c);
+                    const int ji = (int)M.mjobs.size();
+                    for (MfmaTile t : st.mtiles) {
+                        t.job = ji;
+                        tl.push_back(t);
+                    }
+                    M.flops += jb.flops;
+                    M.bytes += jb.bytes;
+                    M.mjobs.push_back(jb);
+                    M.plan = st.plan;
+                }
+                if (M.mjobs.empty()) continue;
+                if ((int64_t)tl.size() >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 tiles");
+                M.n_tiles = (int64_t)tl.size();
+                M.tiles = Ref{R_CONST, ex->cbuf.add(tl.data(), M.n_tiles * (int64_t)sizeof(MfmaTile))};
+                M.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)M.mjobs.size() * (int64_t)sizeof(MfmaJob))};
+                M.n_jobs = (int)M.mjobs.size();
+                out->push_back(std::move(M));
+            }
             if (!G.hjobs.empty()) {
                 if (G.blocks >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 blocks");
                 G.n_jobs = (int)G.hjobs.size();
@@ -1050,6 +1279,29 @@ static void bind(tn_exec_s* ex) {
                 b0 += gett_job_blocks(j);
                 std::memcpy(d + i, &j, sizeof(GettJob));
             }
+        } else if (L.kind == L_MGROUP) {
+            MfmaJob* d = (MfmaJob*)(ex->cbuf.bytes.data() + L.jobs.off);
+            for (int i = 0; i < L.n_jobs; ++i) {
+                const MJob& h = L.mjobs[i];
+                MfmaJob j{};
+                j.A = resolve(ex, h.a);
+                j.B = resolve(ex, h.b);
+                j.C = resolve(ex, h.c);
+                j.oa = (const int64_t*)resolve(ex, h.oa);
+                j.ob = (const int64_t*)resolve(ex, h.ob);
+                j.oc = (const int64_t*)resolve(ex, h.oc);
+                j.m_log = h.m_log;
+                j.n_log = h.n_log;
+                j.k_log = h.k_log;
+                j.merge = h.merge;
+                j.a_rowfast = h.a_rowfast;
+                j.b_colfast = h.b_colfast;
+                std::memcpy(j.a_row, h.a_row, 32);
+                std::memcpy(j.a_k, h.a_k, 32);
+                std::memcpy(j.b_k, h.b_k, 32);
+                std::memcpy(j.b_col, h.b_col, 32);
+                std::memcpy(d + i, &j, sizeof(MfmaJob));
+            }
         } else if (L.kind == L_SLOTFILL) {
             L.sf.noise = (const int32_t*)resolve(ex, L.sf_noise);
             L.sf.dst = (const int64_t*)resolve(ex, L.sf_dst);
@@ -1096,6 +1348,10 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
         break;
     case L_GROUP:
         launch_gett_group((const GettJob*)resolve(ex, L.jobs), L.n_jobs, L.blocks, L.fp64, s);
+        break;
+    case L_MGROUP:
+        launch_mfma_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
+                          L.n_tiles, s);
         break;
     case L_FINALIZE:
         launch_finalize(L.f, s);
@@ -1256,6 +1512,32 @@ static std::string describe_exec(const tn_exec_s* ex) {
             os << ",\"n\":" << L.sf.n << ",\"noise\":" << L.sf_noise.off << ",\"dst\":" << L.sf_dst.off
                << ",\"bank\":" << L.sf_bank.off << ",\"pattern\":" << L.sf_pattern.off
                << ",\"n_noise\":" << L.sf.n_noise;
+        if (L.kind == L_MGROUP) {
+            os << ",\"kernel\":\"" << kernel_name(L.kclass) << "\",\"bm\":" << mfma_tile_bm(L.mtile)
+               << ",\"bn\":" << mfma_tile_bn(L.mtile) << ",\"n_tiles\":" << L.n_tiles << ",\"tiles\":["
+               << L.tiles.region << "," << L.tiles.off << "],\"jobs\":[";
+            for (int i = 0; i < L.n_jobs; ++i) {
+                const MJob& h = L.mjobs[i];
+                os << (i ? "," : "") << "{\"a\":[" << h.a.region << "," << h.a.off << "],\"b\":[" << h.b.region
+                   << "," << h.b.off << "],\"c\":[" << h.c.region << "," << h.c.off << "],\"oa\":[" << h.oa.region
+                   << "," << h.oa.off << "],\"ob\":[" << h.ob.region << "," << h.ob.off << "],\"oc\":["
+                   << h.oc.region << "," << h.oc.off << "],\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log
+                   << ",\"k_log\":" << h.k_log << ",\"ns\":" << h.ns << ",\"merge\":" << h.merge
+                   << ",\"a_rowfast\":" << h.a_rowfast
+                   << ",\"b_colfast\":" << h.b_colfast;
+                auto arr = [&](const char* nm, const int8_t* v, int n) {
+                    os << ",\"" << nm << "\":[";
+                    for (int q = 0; q < n; ++q) os << (q ? "," : "") << (int)v[q];
+                    os << "]";
+                };
+                arr("a_row", h.a_row, h.m_log);
+                arr("a_k", h.a_k, h.k_log);
+                arr("b_k", h.b_k, h.k_log);
+                arr("b_col", h.b_col, h.n_log);
+                os << ",\"flops\":" << h.flops << ",\"bytes\":" << h.bytes << "}";
+            }
+            os << "]";
+        }
         if (L.kind == L_GROUP) {
             os << ",\"kernel\":\"" << kernel_name(L.kclass) << "\",\"blocks\":" << L.blocks << ",\"jobs\":[";
             for (int i = 0; i < L.n_jobs; ++i) {
@@ -1461,7 +1743,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             for (auto* list : {&ex->launches, &ex->launches64})
                 for (auto& L : *list)
                     if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0) ||
-                        (L.kind == L_GROUP && L.blocks > 0)) {
+                        (L.kind == L_GROUP && L.blocks > 0) || (L.kind == L_MGROUP && L.n_tiles > 0)) {
                         HIPCHK(hipEventCreate(&L.ev_a));
                         HIPCHK(hipEventCreate(&L.ev_b));
                     }
@@ -1832,5 +2114,20 @@ extern "C" int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipFree(dtab));
+    });
+}
+
+static_assert(sizeof(tn_mfma_job) == sizeof(tn::MfmaJob), "tn_mfma_job layout");
+static_assert(sizeof(tn_mfma_tile) == sizeof(tn::MfmaTile), "tn_mfma_tile layout");
+
+extern "C" int tn_kernel_mfma_group(int32_t tile, const tn_mfma_job* d_jobs, const tn_mfma_tile* d_tiles,
+                                    int64_t n_tiles, void* stream) {
+    return guard([&] {
+        if (tile < 0 || tile >= tn::K_MFMA_TILES || !d_jobs || !d_tiles || n_tiles < 0 ||
+            n_tiles >= (int64_t(1) << 31))
+            tn::fail(TN_EINVAL, "bad grouped launch arguments");
+        tn::launch_mfma_group(tile, (const tn::MfmaJob*)d_jobs, (const tn::MfmaTile*)d_tiles, n_tiles,
+                              (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
     });
 }

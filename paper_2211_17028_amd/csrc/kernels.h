@@ -71,6 +71,36 @@ int64_t gett_job_blocks(const GettJob& j);
 // One launch for all jobs; d_jobs holds n_jobs records in device memory.
 void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s);
 
+// Grouped FP32 matrix-core contractions.  A job is one step: slices
+// i < n_inst with C_i = A_i B_i, operands in stored order (per-bit positions as
+// in GettJob), slice i reading A at oa[i], B at ob[i] and writing its row-major
+// m x n block at oc[i] (elements).  merge = 1: a tile's columns hold `cnt`
+// consecutive slices that share A (n < tile width); merge = 2: its rows hold
+// `cnt` consecutive slices that share B (m < tile height); 0: one slice per
+// tile.  Rows / columns past the shape or past cnt slices are padding.
+struct MfmaJob {
+    const void* A;
+    const void* B;
+    void* C;
+    const int64_t* oa;
+    const int64_t* ob;
+    const int64_t* oc;
+    int32_t m_log, n_log, k_log;
+    int32_t merge;
+    int32_t a_rowfast, b_colfast;  // lowest stored bit of A is a row bit / of B a column bit
+    int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+};
+struct MfmaTile {                  // one block of a grouped launch
+    int32_t job, cnt;
+    int64_t s0;                    // first slice
+    int64_t tm0, tn0;              // tile origin inside the slice (unmerged dimensions)
+};
+// tile: an MFMA tile id (0..K_MFMA_TILES-1); one launch per tile shape.
+void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                       hipStream_t s);
+int mfma_tile_bm(int tile);
+int mfma_tile_bn(int tile);
+
 enum KernelClass { KC_MFMA = 0, KC_SMALL = 1, KC_SPLITK = 2, KC_TILED = 3, KC_GROUP = 4 };
 
 // Kernel ids: 0..K_MFMA_TILES-1 = FP32 MFMA GEMM tile configurations,
@@ -82,6 +112,7 @@ enum KernelId {
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
     K_GROUP32 = 40, K_GROUP64 = 41,
+    K_MFMA_GROUP_BASE = 200,   // + MFMA tile id: grouped matrix-core launch
     K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };
 int select_gemm(const GemmArgs& g, int fp64, int tile_hint);

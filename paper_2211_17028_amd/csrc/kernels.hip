@@ -375,6 +375,233 @@ void k_gemm_mfma_g(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+#ifndef MFMA_GROUP_WAVES
+#define MFMA_GROUP_WAVES 3
+#endif
+// Grouped matrix-core contractions (FP32 complex on mfma_f32_32x32x2f32, the
+// real embedding of K1).  One block per tile descriptor; the tile's row and
+// column offsets (A / B element offsets, C row / column offsets, -1 = padding)
+// are built in LDS from the job's slice tables, so slices that share an
+// operand can fill one tile (merge modes) and any stored layout is read
+// without a transpose pass.
+// ---------------------------------------------------------------------------
+template <int BM, int BNC>
+__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1), MFMA_GROUP_WAVES)
+void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__ tiles) {
+    constexpr int WM = BM >= 64 ? BM / 64 : 1;
+    constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TM = BM / WM / 32;
+    constexpr int TN = BNC / WN / 16;
+    constexpr int BKC = 8, BKC_LOG = 3;
+    constexpr int BM_LOG = __builtin_ctz(BM), BN_LOG = __builtin_ctz(BNC);
+    constexpr int AE = BM * BKC / NT;
+    constexpr int BE = (BKC * BNC + NT - 1) / NT;
+    // LDS staging, flat: A as [half][p][row] (half 0 real, 1 imaginary parts),
+    // B in its real embedding as [half][p][2 col + t] (half 0: re, im; half 1:
+    // -im, re), so every lane reads its MFMA operand with one 4-byte load.  Row
+    // pitch +8 words keeps k-fast staging writes (8 rows x 8 inner indices per
+    // 64 lanes) in distinct banks; the +32-word gap between halves keeps the two
+    // half-waves' reads apart.
+    constexpr int AP = BM + 8, AH = BKC * AP + 32, ABUF = 2 * AH;
+    constexpr int BP = 2 * BNC + 8, BH = BKC * BP + 32, BBUF = 2 * BH;
+    __shared__ __align__(16) float As[2 * ABUF];
+    __shared__ __align__(16) float Bs[2 * BBUF];
+    __shared__ int64_t row_a[BM], row_c[BM], col_b[BNC], col_c[BNC], ak_lo[BKC], bk_lo[BKC];
+    __shared__ MfmaJob J;
+    const MfmaTile T = tiles[blockIdx.x];
+    if (threadIdx.x == 0) J = jobs[T.job];
+    __syncthreads();
+    const int m_log = J.m_log, n_log = J.n_log, k_log = J.k_log;
+    const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
+    const int kc = k < BKC ? (int)k : BKC;
+    const int kc_log = k_log < BKC_LOG ? k_log : BKC_LOG;
+    for (int i = threadIdx.x; i < BM; i += NT) {
+        int64_t ra = -1, rc = -1;
+        if (J.merge == 2) {
+            const int seg = i >> m_log;
+            const int64_t r = i & (m - 1);
+            if (seg < T.cnt) {
+                ra = J.oa[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
+                rc = J.oc[T.s0 + seg] + r * n;
+            }
+        } else {
+            const int64_t r = T.tm0 + i;
+            if (r < m) {
+                ra = J.oa[T.s0] + deposit(r, J.a_row, 0, m_log);
+                rc = (J.merge == 1 ? 0 : J.oc[T.s0]) + r * n;
+            }
+        }
+        row_a[i] = ra;
+        row_c[i] = rc;
+    }
+    for (int j = threadIdx.x; j < BNC; j += NT) {
+        int64_t cb = -1, cc = -1;
+        if (J.merge == 1) {
+            const int seg = j >> n_log;
+            const int64_t c = j & (n - 1);
+            if (seg < T.cnt) {
+                cb = J.ob[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
+                cc = J.oc[T.s0 + seg] + c;
+            }
+        } else {
+            const int64_t c = T.tn0 + j;
+            if (c < n) {
+                cb = J.ob[T.s0] + deposit(c, J.b_col, 0, n_log);
+                cc = c;
+            }
+        }
+        col_b[j] = cb;
+        col_c[j] = cc;
+    }
+    for (int i = threadIdx.x; i < BKC; i += NT) {
+        ak_lo[i] = i < kc ? deposit(i, J.a_k, 0, kc_log) : 0;
+        bk_lo[i] = i < kc ? deposit(i, J.b_k, 0, kc_log) : 0;
+    }
+    __syncthreads();
+    const float2* __restrict__ A = (const float2*)J.A;
+    const float2* __restrict__ B = (const float2*)J.B;
+    float* __restrict__ C = (float*)J.C;
+    const bool a_rowfast = J.a_rowfast, b_colfast = J.b_colfast;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    v16f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int half = lane >> 5;
+    const int sub = lane & 31;
+    // staging order: element e of a chunk is (row r, inner p) with r fast when
+    // the operand's lowest stored bit is a row bit, else p fast; inner indices
+    // p >= kc (k < 8) are zero
+    auto a_rp = [&](int e, int& r, int& p) {
+        if (a_rowfast) {
+            r = e & (BM - 1);
+            p = e >> BM_LOG;
+        } else {
+            p = e & (BKC - 1);
+            r = e >> BKC_LOG;
+        }
+    };
+    auto b_pc = [&](int e, int& p, int& c) {
+        if (b_colfast) {
+            c = e & (BNC - 1);
+            p = e >> BN_LOG;
+        } else {
+            p = e & (BKC - 1);
+            c = e >> BKC_LOG;
+        }
+    };
+    auto load = [&](int64_t k0, float2* ra, float2* rb) {
+        const int64_t akh = deposit(k0, J.a_k, kc_log, k_log);
+        const int64_t bkh = deposit(k0, J.b_k, kc_log, k_log);
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            int r, p;
+            a_rp(threadIdx.x + q * NT, r, p);
+            const int64_t base = row_a[r];
+            ra[q] = (base >= 0 && p < kc) ? A[base + ak_lo[p] + akh] : make_float2(0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (e < BKC * BNC) {
+                int p, c;
+                b_pc(e, p, c);
+                const int64_t base = col_b[c];
+                if (base >= 0 && p < kc) v = B[base + bk_lo[p] + bkh];
+            }
+            rb[q] = v;
+        }
+    };
+    auto stash = [&](int buf, const float2* ra, const float2* rb) {
+        float* as = As + buf * ABUF;
+        float* bs = Bs + buf * BBUF;
+#pragma unroll
+        for (int q = 0; q < AE; ++q) {
+            int r, p;
+            a_rp(threadIdx.x + q * NT, r, p);
+            as[p * AP + r] = ra[q].x;
+            as[AH + p * AP + r] = ra[q].y;
+        }
+#pragma unroll
+        for (int q = 0; q < BE; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < BKC * BNC) {
+                int p, c;
+                b_pc(e, p, c);
+                *(float2*)&bs[p * BP + 2 * c] = rb[q];
+                *(float2*)&bs[BH + p * BP + 2 * c] = make_float2(-rb[q].y, rb[q].x);
+            }
+        }
+    };
+    // per-lane LDS offsets of the MFMA operands
+    int a_off[TM], b_off[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a_off[i] = half * AH + wm * (TM * 32) + i * 32 + sub;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b_off[j] = half * BH + 2 * (wn * (TN * 16) + j * 16) + sub;
+    auto compute = [&](int buf) {
+        const float* as = As + buf * ABUF;
+        const float* bs = Bs + buf * BBUF;
+        float a[2][TM], b[2][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[0][i] = as[a_off[i]];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[0][j] = bs[b_off[j]];
+#pragma unroll
+        for (int p = 0; p < BKC; ++p) {
+            const int cur = p & 1;
+            if (p + 1 < BKC) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) a[cur ^ 1][i] = as[(p + 1) * AP + a_off[i]];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[cur ^ 1][j] = bs[(p + 1) * BP + b_off[j]];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+        }
+    };
+    // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
+    const int64_t nchunks = k >= BKC ? k / BKC : 1;
+    float2 ra[AE], rb[BE];
+    load(0, ra, rb);
+    stash(0, ra, rb);
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int buf = (int)(ch & 1);
+        if (ch + 1 < nchunks) load((ch + 1) * BKC, ra, rb);
+        compute(buf);
+        if (ch + 1 < nchunks) stash(buf ^ 1, ra, rb);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
+            const int64_t cc = col_c[col];
+            if (cc < 0) continue;
+            const int part = sub & 1;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                const int64_t rc = row_c[row];
+                if (rc >= 0) C[2 * (rc + cc) + part] = acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Grouped gathered contractions: every small step of one tree level (all
 // clusters, all plans) in one launch.  A block finds its job by binary search
 // over the jobs' first blocks.  Operands are read in their stored order
@@ -422,11 +649,26 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
         R sr = 0, si = 0;
         if ((int)threadIdx.x < kc) {
             const int64_t alo = ak_lo[threadIdx.x], blo = bk_lo[threadIdx.x];
-            for (int64_t h = 0; h < k; h += kc) {
-                const C2 a = Ap[deposit(h, J.a_k, kc_log, k_log) + alo];
-                const C2 b = Bp[deposit(h, J.b_k, kc_log, k_log) + blo];
-                sr += a.x * b.x - a.y * b.y;
-                si += a.x * b.y + a.y * b.x;
+            // eight chunks per round: their loads are all in flight before the
+            // first product (the chunk count is a power of two)
+            constexpr int U = 8;
+            const int64_t nh = k >> kc_log;
+            const int64_t step = nh >= U ? U : nh;
+            for (int64_t h0 = 0; h0 < nh; h0 += step) {
+                C2 a[U], b[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < step) {
+                        const int64_t h = (h0 + u) << kc_log;
+                        a[u] = Ap[deposit(h, J.a_k, kc_log, k_log) + alo];
+                        b[u] = Bp[deposit(h, J.b_k, kc_log, k_log) + blo];
+                    }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (u < step) {
+                        sr += a[u].x * b[u].x - a[u].y * b[u].y;
+                        si += a[u].x * b[u].y + a[u].y * b[u].x;
+                    }
             }
         }
         red_r[threadIdx.x] = (double)sr;
@@ -458,11 +700,28 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
     for (int64_t h = 0; h < k; h += kc) {
         const C2* __restrict__ Ah = Ap + deposit(h, J.a_k, kc_log, k_log);
         const C2* __restrict__ Bh = Bp + deposit(h, J.b_k, kc_log, k_log);
-        for (int p = 0; p < kc; ++p) {
-            const C2 a = Ah[ak_lo[p]];
-            const C2 b = Bh[bk_lo[p]];
-            sr += a.x * b.x - a.y * b.y;
-            si += a.x * b.y + a.y * b.x;
+        if (kc >= 4) {
+            // four inner indices per round, loads issued together
+            for (int p = 0; p < kc; p += 4) {
+                C2 a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = Ah[ak_lo[p + u]];
+                    b[u] = Bh[bk_lo[p + u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    sr += a[u].x * b[u].x - a[u].y * b[u].y;
+                    si += a[u].x * b[u].y + a[u].y * b[u].x;
+                }
+            }
+        } else {
+            for (int p = 0; p < kc; ++p) {
+                const C2 a = Ah[ak_lo[p]];
+                const C2 b = Bh[bk_lo[p]];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
         }
     }
     C2 out;
@@ -824,6 +1083,10 @@ const char* kernel_name(int id) {
                                            "k_gemm_mfma_g<64,32>",  "k_gemm_mfma_g<32,32>", "k_gemm_mfma_g<128,16>",
                                            "k_gemm_mfma_g<64,16>",  "k_gemm_mfma_g<32,16>"};
     if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return mg[id - K_GATHER_BASE];
+    static const char* mq[K_MFMA_TILES] = {"k_mfma_group<128,64>", "k_mfma_group<64,64>", "k_mfma_group<128,32>",
+                                           "k_mfma_group<64,32>",  "k_mfma_group<32,32>", "k_mfma_group<128,16>",
+                                           "k_mfma_group<64,16>",  "k_mfma_group<32,16>"};
+    if (id >= K_MFMA_GROUP_BASE && id < K_MFMA_GROUP_BASE + K_MFMA_TILES) return mq[id - K_MFMA_GROUP_BASE];
     static const char* mf[K_MFMA_TILES] = {"k_gemm_mfma<128,64>", "k_gemm_mfma<64,64>", "k_gemm_mfma<128,32>",
                                            "k_gemm_mfma<64,32>",  "k_gemm_mfma<32,32>", "k_gemm_mfma<128,16>",
                                            "k_gemm_mfma<64,16>",  "k_gemm_mfma<32,16>"};
@@ -848,7 +1111,32 @@ int kernel_class(int id) {
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
     if (id == K_GROUP32 || id == K_GROUP64) return KC_GROUP;
+    if (id >= K_MFMA_GROUP_BASE && id < K_MFMA_GROUP_BASE + K_MFMA_TILES) return KC_GROUP;
     return KC_TILED;
+}
+
+int mfma_tile_bm(int tile) { return kTiles[tile].bm; }
+int mfma_tile_bn(int tile) { return kTiles[tile].bnc; }
+
+void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                       hipStream_t s) {
+    if (n_tiles == 0) return;
+    const TileCfg& t = kTiles[tile];
+#define TN_GLAUNCH(BM_, BN_)                                                                  \
+    if (t.bm == BM_ && t.bnc == BN_) {                                                         \
+        constexpr int nt = 64 * (BM_ >= 64 ? BM_ / 64 : 1) * (BN_ >= 32 ? BN_ / 32 : 1);       \
+        hipLaunchKernelGGL((k_mfma_group<BM_, BN_>), dim3((unsigned)n_tiles), dim3(nt), 0, s, d_jobs, d_tiles); \
+        return;                                                                                \
+    }
+    TN_GLAUNCH(128, 64)
+    TN_GLAUNCH(64, 64)
+    TN_GLAUNCH(128, 32)
+    TN_GLAUNCH(64, 32)
+    TN_GLAUNCH(32, 32)
+    TN_GLAUNCH(128, 16)
+    TN_GLAUNCH(64, 16)
+    TN_GLAUNCH(32, 16)
+#undef TN_GLAUNCH
 }
 
 int64_t gett_job_blocks(const GettJob& j) {

@@ -435,6 +435,8 @@ def _kernel_lib():
         L.tn_kernel_gemm.restype = C.c_int
         L.tn_kernel_permute.argtypes = [C.c_int32, vp, vp, C.c_int64, C.c_int32, vp, C.c_int32, vp]
         L.tn_kernel_permute.restype = C.c_int
+        L.tn_kernel_mfma_group.argtypes = [C.c_int32, vp, vp, C.c_int64, vp]
+        L.tn_kernel_mfma_group.restype = C.c_int
         L._kernel_sigs = True
     return L
 
@@ -463,6 +465,43 @@ def kernel_permute(src, dst, r, perm, block_elems_log=0, stream=None):
     _check(_kernel_lib().tn_kernel_permute(fp64, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
                                            src.shape[0], r, p.ctypes.data if r else None, block_elems_log,
                                            _stream_ptr(stream)))
+
+
+class tn_mfma_job(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("B", C.c_void_p), ("C", C.c_void_p), ("oa", C.c_void_p),
+                ("ob", C.c_void_p), ("oc", C.c_void_p), ("m_log", C.c_int32), ("n_log", C.c_int32),
+                ("k_log", C.c_int32), ("merge", C.c_int32), ("a_rowfast", C.c_int32), ("b_colfast", C.c_int32),
+                ("a_row", C.c_int8 * 32), ("a_k", C.c_int8 * 32), ("b_k", C.c_int8 * 32),
+                ("b_col", C.c_int8 * 32)]
+
+
+MFMA_TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8")])
+MFMA_TILE_SHAPES = [(128, 64), (64, 64), (128, 32), (64, 32), (32, 32), (128, 16), (64, 16), (32, 16)]
+
+
+def kernel_mfma_group(tile, jobs, tiles, stream=None):
+    """One grouped matrix-core launch.  jobs: dicts with device tensors A, B, C
+    (complex64) and oa, ob, oc (int64 slice offsets), m_log, n_log, k_log,
+    merge, a_rowfast, b_colfast and the bit-position lists a_row, a_k, b_k,
+    b_col; tiles: array of MFMA_TILE records.  Returns the device copies of
+    the descriptors (keep them alive until the stream is synchronized)."""
+    import torch
+    arr = (tn_mfma_job * len(jobs))()
+    for q, j in enumerate(jobs):
+        r = arr[q]
+        r.A, r.B, r.C = j["A"].data_ptr(), j["B"].data_ptr(), j["C"].data_ptr()
+        r.oa, r.ob, r.oc = j["oa"].data_ptr(), j["ob"].data_ptr(), j["oc"].data_ptr()
+        for f in ("m_log", "n_log", "k_log", "merge", "a_rowfast", "b_colfast"):
+            setattr(r, f, int(j[f]))
+        for f in ("a_row", "a_k", "b_k", "b_col"):
+            for i, v in enumerate(j[f]):
+                getattr(r, f)[i] = int(v)
+    dj = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
+    t = np.ascontiguousarray(tiles, dtype=MFMA_TILE)
+    dt = torch.from_numpy(t.view(np.uint8).copy()).cuda()
+    _check(_kernel_lib().tn_kernel_mfma_group(tile, C.c_void_p(dj.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                              len(t), _stream_ptr(stream)))
+    return dj, dt
 
 
 # ---------------------------------------------------------------------------

@@ -10,6 +10,17 @@ tests, which run the kernels themselves.
 import numpy as np
 
 
+def _deposit_of(x, pos):
+    o = np.zeros_like(x)
+    for j, p in enumerate(pos):
+        o |= ((x >> j) & 1) << p
+    return o
+
+
+def _deposit(count, pos):
+    return _deposit_of(np.arange(count, dtype=np.int64), pos)
+
+
 def _overlap(x, y):
     return x[0] == y[0] and x[1] < y[2] and y[1] < x[2]
 
@@ -213,7 +224,7 @@ class Sim:
     def _job_spans(self, jb, esz):
         """(write span, [read spans]) of one grouped job, as (region, start, end) bytes."""
         m, n, k = 1 << jb["m_log"], 1 << jb["n_log"], 1 << jb["k_log"]
-        ni = jb["n_inst"]
+        ni = jb["n_inst"] if "n_inst" in jb else jb["ns"]
         oa = self.view(jb["oa"], np.int64, ni)
         ob = self.view(jb["ob"], np.int64, ni)
         amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
@@ -225,9 +236,77 @@ class Sim:
         return (span(jb["c"], 0, ni * m * n),
                 [span(jb["a"], int(oa.min()), amax + 1), span(jb["b"], int(ob.min()), bmax + 1)])
 
+    TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8")])
+
+    def mgroup(self, L):
+        """Grouped matrix-core launch, tile by tile as the kernel builds its
+        row / column offset tables; every output element of every job must be
+        written exactly once, and no job may write what another job reads."""
+        bm, bn = L["bm"], L["bn"]
+        tiles = self.view(L["tiles"], np.uint8, L["n_tiles"] * self.TILE.itemsize).view(self.TILE)
+        jobs = L["jobs"]
+        spans = [self._job_spans(jb, 8) for jb in jobs]
+        for i, (wi, _) in enumerate(spans):
+            for j, (wj, rj) in enumerate(spans):
+                for other in ([wj] if i != j else []) + rj:
+                    assert not _overlap(wi, other), ("grouped jobs race", i, j, wi, other)
+        ctx = []
+        for jb in jobs:
+            m, n, k = 1 << jb["m_log"], 1 << jb["n_log"], 1 << jb["k_log"]
+            ns = jb["ns"]
+            oa = self.view(jb["oa"], np.int64, ns)
+            ob = self.view(jb["ob"], np.int64, ns)
+            oc = self.view(jb["oc"], np.int64, ns)
+            amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
+            bmax = int(ob.max()) + sum(1 << p for p in jb["b_k"] + jb["b_col"])
+            A = self.view(jb["a"], np.complex64, amax + 1)
+            B = self.view(jb["b"], np.complex64, bmax + 1)
+            C = self.view(jb["c"], np.complex64, ns * m * n)
+            ctx.append((m, n, k, oa, ob, oc, A, B, C, np.zeros(ns * m * n, np.int32),
+                        _deposit(k, jb["a_k"]), _deposit(k, jb["b_k"])))
+        for t in tiles:
+            jb = jobs[t["job"]]
+            m, n, k, oa, ob, oc, A, B, C, hits, ka, kb = ctx[t["job"]]
+            cnt, s0, tm0, tn0 = int(t["cnt"]), int(t["s0"]), int(t["tm0"]), int(t["tn0"])
+            i = np.arange(bm, dtype=np.int64)
+            j = np.arange(bn, dtype=np.int64)
+            if jb["merge"] == 2:
+                seg, r = i >> jb["m_log"], i & (m - 1)
+                ok_r = seg < cnt
+                segc = np.minimum(seg, cnt - 1)
+                ra = oa[s0 + segc] + _deposit_of(r, jb["a_row"])
+                rc = oc[s0 + segc] + r * n
+            else:
+                r = tm0 + i
+                ok_r = r < m
+                ra = oa[s0] + _deposit_of(r % m, jb["a_row"])
+                rc = (0 if jb["merge"] == 1 else oc[s0]) + r * n
+            if jb["merge"] == 1:
+                seg, c = j >> jb["n_log"], j & (n - 1)
+                ok_c = seg < cnt
+                segc = np.minimum(seg, cnt - 1)
+                cb = ob[s0 + segc] + _deposit_of(c, jb["b_col"])
+                cc = oc[s0 + segc] + c
+            else:
+                c = tn0 + j
+                ok_c = c < n
+                cb = ob[s0] + _deposit_of(c % n, jb["b_col"])
+                cc = c
+            ra, rc, cb, cc = ra[ok_r], rc[ok_r], cb[ok_c], cc[ok_c]
+            At = A[ra[:, None] + ka[None, :]].astype(np.complex128)
+            Bt = B[kb[:, None] + cb[None, :]].astype(np.complex128)
+            idx = (rc[:, None] + cc[None, :]).reshape(-1)
+            C[idx] = (At @ Bt).astype(np.complex64).reshape(-1)
+            np.add.at(hits, idx, 1)
+        for q, cx in enumerate(ctx):
+            assert cx[9].min() == 1 and cx[9].max() == 1, ("output coverage", q, cx[9].min(), cx[9].max())
+
     def exec(self, L):
         if L["kind"] == 5:
             self.group(L)
+            return
+        if L["kind"] == 6:
+            self.mgroup(L)
             return
         if L["kind"] == 0:
             self.perm(L)

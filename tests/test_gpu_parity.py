@@ -311,13 +311,14 @@ def test_packed_uneven_batch_against_oracle(torch):
 
 
 def test_autotuned_schedule_gives_the_same_estimate(torch):
-    """Tiles chosen by timing change rounding only: the estimate stays within
+    """Tiles chosen by timing (per-step launches: grouped launches take their
+    tiles from the work model) change rounding only: the estimate stays within
     the parity bar of the oracle's stored sums and of the untuned run."""
     c = W.config(2)
     plan = tn.tn_plan_build(c, 2)
     terms = tn.tn_terms_enumerate(plan, 2)
-    r0 = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False)).run()[0]
-    ext = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True, tune=True))
+    r0 = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, group=False)).run()[0]
+    ext = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=True, tune=True, group=False))
     r1 = ext.run()[0]
     gold = np.loadtxt(os.path.join(GOLD, "config2_oracle.txt"))
     for u in range(3):
@@ -325,3 +326,28 @@ def test_autotuned_schedule_gives_the_same_estimate(torch):
         assert abs(r1["A"][u] - r0["A"][u]) <= 1e-9 * gold[u]
     kernels = {L.get("kernel") for L in ext.describe()["launches"] if L["kind"] == 1}
     assert any(k and k.startswith("k_gemm_mfma") for k in kernels)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_schedule_variants_agree(torch, cfg):
+    """Level-grouped launches, per-step launches with operands gathered in
+    stored order, and per-step launches with transposes compute the same
+    terms (FP32 rounding apart) and the same level sums."""
+    print(f"schedule variants config{cfg}", flush=True)
+    c = W.config(cfg)
+    plan = tn.tn_plan_build(c, c.level)
+    terms = tn.tn_terms_enumerate(plan, c.level)
+    out = []
+    for kw in (dict(), dict(group=False), dict(group=False, gather=False)):
+        ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, **kw))
+        r = ex.run()[0]
+        x, _ = ex.values()
+        out.append((r, x))
+    gold = np.loadtxt(os.path.join(GOLD, f"config{cfg}_oracle.txt"))
+    r0, x0 = out[0]
+    for r, x in out:
+        for u in range(c.level + 1):
+            assert abs(r["A"][u] - gold[u]) <= 1e-6 * gold[u]
+        # every term: same value within FP32 rounding of the larger terms
+        scale = np.maximum(x, x0)
+        assert np.all(np.abs(x - x0) <= 1e-4 * scale + 1e-6 * x0.max() * 1e-6)

@@ -142,11 +142,12 @@ def grouped_by_positions(pat, x):
     return out
 
 
-def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True):
+def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True):
     plan = tn.tn_plan_build(circ, level)
     t = tn.tn_terms_enumerate(plan, level)
     desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
-                                                                  fp64_level0=fp64, gather=gather))
+                                                                  fp64_level0=fp64, gather=gather,
+                                                                  group=group))
     pat, w = t.get()
     live = [i for i in range(t.n) if w[i] != 0.0]
     sim = Sim(desc, cb)
@@ -182,22 +183,23 @@ def test_schedule_replay_plain_mode_matches_batched():
                                                          (14, 120, 4, "circuit_output", 3),
                                                          (16, 120, 3, "product", 2)])
 def test_schedule_replay_gathered_operands(n, gates, noises, target, seed):
-    """Circuits wide enough for MFMA-tile steps whose operands are read in
-    stored order (no transpose pass): the replay matches the oracle and the
-    schedule that transposes instead."""
+    """Circuits wide enough for matrix-core steps.  Batched mode groups each
+    tree level (small steps in one launch, matrix-core steps in one launch per
+    tile shape, operands read in stored order); without grouping the MFMA
+    steps that need a transpose read their operands in stored order instead;
+    PLAIN runs step by step.  Every schedule's replay matches the oracle."""
     c = W.tiny_random_circuit(np.random.default_rng(seed), n, gates, noises, noise="adpd", level=2,
                               target=target)
-    x, pat, desc = _replay(c, 2)
-    gl = [L for L in desc["launches"] if L["kind"] == 1 and L.get("gather")]
-    assert gl, "no gathered step in this schedule"
-    x_t, _, desc_t = _replay(c, 2, gather=False)
-    assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
     r = estimate.estimate(c, 2, "network", reduce=True)
-    assert np.allclose(x, r["X"], rtol=2e-5, atol=1e-10)
-    assert np.allclose(x, x_t, rtol=2e-5, atol=1e-10)
+    x, pat, desc = _replay(c, 2)
+    assert any(L["kind"] == 6 for L in desc["launches"]), "no grouped matrix-core launch"
+    x_g, _, desc_g = _replay(c, 2, group=False)
+    assert any(L["kind"] == 1 and L.get("gather") for L in desc_g["launches"]), "no gathered step"
+    x_t, _, desc_t = _replay(c, 2, gather=False, group=False)
+    assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
     x_p, _, desc_p = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
-    assert any(L.get("gather") for L in desc_p["launches"] if L["kind"] == 1)
-    assert np.allclose(x_p, x, rtol=2e-5, atol=1e-10)
+    for v in (x, x_g, x_t, x_p):
+        assert np.allclose(v, r["X"], rtol=2e-5, atol=1e-10)
 
 
 def test_schedule_replay_config1_against_oracle():
