@@ -209,7 +209,7 @@ constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
 struct GroupJob {
     Ref a, b, c, oa, ob;
     int64_t n_inst = 0;
-    int m_log = 0, n_log = 0, k_log = 0, split = 0;
+    int m_log = 0, n_log = 0, k_log = 0, split = 0, rpt_log = 0;
     int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
     double flops = 0, bytes = 0;
 };
@@ -788,6 +788,12 @@ struct Builder {
                 jb.k_log = rk;
                 jb.n_inst = ninst * nbatch;
                 jb.split = (jb.m_log + jb.n_log <= 4 && rk >= 8) ? 1 : 0;
+                // rows per thread: the column operand's elements are reused across
+                // them (up to 8; 1 for outer products, where there is no reuse)
+                jb.rpt_log = jb.split || rk == 0 ? 0 : std::min(jb.m_log, 3);
+                // ... but keep at least 64K threads busy
+                while (jb.rpt_log > 0 && ((jb.n_inst << (jb.m_log + jb.n_log)) >> jb.rpt_log) < (int64_t(1) << 16))
+                    --jb.rpt_log;
                 for (size_t q = 0; q < row_bits.size(); ++q) jb.a_row[q] = (int8_t)posin(R, row_bits[q]);
                 for (size_t q = 0; q < k_bits.size(); ++q) {
                     jb.a_k[q] = (int8_t)posin(R, k_bits[q]);
@@ -1020,7 +1026,7 @@ struct Builder {
                 subst(jb.b);
                 subst(jb.c);
                 const int64_t outs = jb.n_inst << (jb.m_log + jb.n_log);
-                G.blocks += jb.split ? outs : (outs + 255) / 256;
+                G.blocks += jb.split ? outs : ((outs >> jb.rpt_log) + 255) / 256;
                 G.flops += jb.flops;
                 G.bytes += jb.bytes;
                 G.hjobs.push_back(jb);
@@ -1272,6 +1278,7 @@ static void bind(tn_exec_s* ex) {
                 j.n_log = h.n_log;
                 j.k_log = h.k_log;
                 j.split = h.split;
+                j.rpt_log = h.rpt_log;
                 std::memcpy(j.a_row, h.a_row, 32);
                 std::memcpy(j.a_k, h.a_k, 32);
                 std::memcpy(j.b_k, h.b_k, 32);
@@ -1546,7 +1553,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
                    << "," << h.b.off << "],\"c\":[" << h.c.region << "," << h.c.off << "],\"oa\":[" << h.oa.region
                    << "," << h.oa.off << "],\"ob\":[" << h.ob.region << "," << h.ob.off << "],\"n_inst\":"
                    << h.n_inst << ",\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log << ",\"k_log\":" << h.k_log
-                   << ",\"split\":" << h.split;
+                   << ",\"split\":" << h.split << ",\"rpt_log\":" << h.rpt_log;
                 auto arr = [&](const char* nm, const int8_t* v, int n) {
                     os << ",\"" << nm << "\":[";
                     for (int q = 0; q < n; ++q) os << (q ? "," : "") << (int)v[q];

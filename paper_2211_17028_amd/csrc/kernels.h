@@ -64,6 +64,8 @@ struct GettJob {
     int64_t block0;                // first block of this job in the launch
     int32_t m_log, n_log, k_log;
     int32_t split;                 // 1: one block per output element (long inner sums)
+    int32_t rpt_log;               // split == 0: each thread computes 2^rpt_log rows of one column
+    int32_t pad_;
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
 };
 // blocks one job takes in a grouped launch

@@ -207,6 +207,18 @@ __device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int lo,
     return o;
 }
 
+// Offset steps of a chunk counter: with chunk index h (inner index h << lo),
+// deposit(h + 1) = deposit(h) + step[ctz(~h)], where step[t] is the offset of
+// inner bit lo + t minus the offsets of the bits below it, lo <= bit < lo + t.
+// Filled by the first threads of a block; t < 32.
+__device__ __forceinline__ void chunk_steps(const int8_t* pos, int lo, int hi, int64_t* step) {
+    for (int t = threadIdx.x; t < hi - lo; t += blockDim.x) {
+        int64_t below = 0;
+        for (int j = 0; j < t; ++j) below += int64_t(1) << pos[lo + j];
+        step[t] = (int64_t(1) << pos[lo + t]) - below;
+    }
+}
+
 template <int BM, int BNC>
 __global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1))
 void k_gemm_mfma_g(GemmArgs g) {
@@ -408,6 +420,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     __shared__ __align__(16) float As[2 * ABUF];
     __shared__ __align__(16) float Bs[2 * BBUF];
     __shared__ int64_t row_a[BM], row_c[BM], col_b[BNC], col_c[BNC], ak_lo[BKC], bk_lo[BKC];
+    __shared__ int64_t a_step[32], b_step[32];
     __shared__ MfmaJob J;
     const MfmaTile T = tiles[blockIdx.x];
     if (threadIdx.x == 0) J = jobs[T.job];
@@ -458,6 +471,8 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         ak_lo[i] = i < kc ? deposit(i, J.a_k, 0, kc_log) : 0;
         bk_lo[i] = i < kc ? deposit(i, J.b_k, 0, kc_log) : 0;
     }
+    chunk_steps(J.a_k, kc_log, k_log, a_step);
+    chunk_steps(J.b_k, kc_log, k_log, b_step);
     __syncthreads();
     const float2* __restrict__ A = (const float2*)J.A;
     const float2* __restrict__ B = (const float2*)J.B;
@@ -497,9 +512,10 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             c = e >> BKC_LOG;
         }
     };
-    auto load = [&](int64_t k0, float2* ra, float2* rb) {
-        const int64_t akh = deposit(k0, J.a_k, kc_log, k_log);
-        const int64_t bkh = deposit(k0, J.b_k, kc_log, k_log);
+    // offsets of the high inner bits of the chunk being loaded (chunks are
+    // loaded in order: advanced by the step table after each load)
+    int64_t akh = 0, bkh = 0, kchunk = 0;
+    auto load = [&](int64_t, float2* ra, float2* rb) {
 #pragma unroll
         for (int q = 0; q < AE; ++q) {
             int r, p;
@@ -519,6 +535,12 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             }
             rb[q] = v;
         }
+        const int t = __builtin_ctzll(~(uint64_t)kchunk);
+        if (t < k_log - kc_log) {
+            akh += a_step[t];
+            bkh += b_step[t];
+        }
+        ++kchunk;
     };
     auto stash = [&](int buf, const float2* ra, const float2* rb) {
         float* as = As + buf * ABUF;
@@ -616,6 +638,7 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
     __shared__ GettJob J;
     __shared__ int64_t ak_lo[256], bk_lo[256];
     __shared__ double red_r[256], red_i[256];
+    __shared__ int64_t a_step[32], b_step[32];
     const int64_t bid = blockIdx.x;
     if (threadIdx.x == 0) {
         int lo = 0, hi = n_jobs - 1;
@@ -636,7 +659,10 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
         ak_lo[i] = deposit(i, J.a_k, 0, kc_log);
         bk_lo[i] = deposit(i, J.b_k, 0, kc_log);
     }
+    chunk_steps(J.a_k, kc_log, k_log, a_step);
+    chunk_steps(J.b_k, kc_log, k_log, b_step);
     __syncthreads();
+    const int nstep = k_log - kc_log;
     const int64_t local = bid - J.block0;
     if (J.split) {
         // one output element per block; thread t takes inner indices t + 256 h
@@ -654,14 +680,19 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
             constexpr int U = 8;
             const int64_t nh = k >> kc_log;
             const int64_t step = nh >= U ? U : nh;
+            int64_t ah = alo, bh = blo;
             for (int64_t h0 = 0; h0 < nh; h0 += step) {
                 C2 a[U], b[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (u < step) {
-                        const int64_t h = (h0 + u) << kc_log;
-                        a[u] = Ap[deposit(h, J.a_k, kc_log, k_log) + alo];
-                        b[u] = Bp[deposit(h, J.b_k, kc_log, k_log) + blo];
+                        a[u] = Ap[ah];
+                        b[u] = Bp[bh];
+                        const int t = __builtin_ctzll(~(uint64_t)(h0 + u));
+                        if (t < nstep) {
+                            ah += a_step[t];
+                            bh += b_step[t];
+                        }
                     }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
@@ -689,19 +720,40 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
         }
         return;
     }
+    // one thread: column c of 2^rpt_log consecutive rows (the column operand's
+    // element is loaded once for all of them; the row operand's elements are
+    // shared by the lanes of a wave, which hold consecutive columns)
+    constexpr int RMAX = 8;
+    const int rpt_log = J.rpt_log;
+    const int rpt = 1 << rpt_log;
     const int64_t o = local * 256 + threadIdx.x;
-    if (o >= (J.n_inst << mn_log)) return;
-    const int64_t inst = o >> mn_log;
-    const int64_t rc = o & ((int64_t(1) << mn_log) - 1);
-    const int64_t r = rc >> n_log, c = rc & ((int64_t(1) << n_log) - 1);
-    const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r, J.a_row, 0, m_log);
+    if (o >= (J.n_inst << (mn_log - rpt_log))) return;
+    const int64_t c = o & ((int64_t(1) << n_log) - 1);
+    const int64_t rest = o >> n_log;
+    const int64_t rg = rest & ((int64_t(1) << (m_log - rpt_log)) - 1);
+    const int64_t inst = rest >> (m_log - rpt_log);
+    const int64_t r0 = rg << rpt_log;
+    const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r0, J.a_row, 0, m_log);
     const C2* __restrict__ Bp = (const C2*)J.B + J.ob[inst] + deposit(c, J.b_col, 0, n_log);
-    R sr = 0, si = 0;
+    int64_t rlo[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) rlo[i] = i < rpt ? deposit(i, J.a_row, 0, rpt_log) : 0;
+    R sr[RMAX], si[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) sr[i] = si[i] = 0;
+    int64_t ahh = 0, bhh = 0;
     for (int64_t h = 0; h < k; h += kc) {
-        const C2* __restrict__ Ah = Ap + deposit(h, J.a_k, kc_log, k_log);
-        const C2* __restrict__ Bh = Bp + deposit(h, J.b_k, kc_log, k_log);
-        if (kc >= 4) {
-            // four inner indices per round, loads issued together
+        const C2* __restrict__ Ah = Ap + ahh;
+        const C2* __restrict__ Bh = Bp + bhh;
+        {
+            const int t = __builtin_ctzll(~(uint64_t)(h >> kc_log));
+            if (t < nstep) {
+                ahh += a_step[t];
+                bhh += b_step[t];
+            }
+        }
+        if (rpt == 1 && kc >= 4) {
+            // one row: four inner indices per round, loads issued together
             for (int p = 0; p < kc; p += 4) {
                 C2 a[4], b[4];
 #pragma unroll
@@ -711,23 +763,36 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    sr += a[u].x * b[u].x - a[u].y * b[u].y;
-                    si += a[u].x * b[u].y + a[u].y * b[u].x;
+                    sr[0] += a[u].x * b[u].x - a[u].y * b[u].y;
+                    si[0] += a[u].x * b[u].y + a[u].y * b[u].x;
                 }
             }
         } else {
             for (int p = 0; p < kc; ++p) {
-                const C2 a = Ah[ak_lo[p]];
                 const C2 b = Bh[bk_lo[p]];
-                sr += a.x * b.x - a.y * b.y;
-                si += a.x * b.y + a.y * b.x;
+                const int64_t ap = ak_lo[p];
+                C2 a[RMAX];
+#pragma unroll
+                for (int i = 0; i < RMAX; ++i)
+                    if (i < rpt) a[i] = Ah[rlo[i] + ap];
+#pragma unroll
+                for (int i = 0; i < RMAX; ++i)
+                    if (i < rpt) {
+                        sr[i] += a[i].x * b.x - a[i].y * b.y;
+                        si[i] += a[i].x * b.y + a[i].y * b.x;
+                    }
             }
         }
     }
-    C2 out;
-    out.x = sr;
-    out.y = si;
-    ((C2*)J.C)[o] = out;
+    C2* __restrict__ Cp = (C2*)J.C + ((inst << mn_log) + (r0 << n_log) + c);
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+        if (i < rpt) {
+            C2 out;
+            out.x = sr[i];
+            out.y = si[i];
+            Cp[(int64_t)i << n_log] = out;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1141,7 +1206,7 @@ void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles,
 
 int64_t gett_job_blocks(const GettJob& j) {
     const int64_t outs = j.n_inst << (j.m_log + j.n_log);
-    return j.split ? outs : (outs + 255) / 256;
+    return j.split ? outs : ((outs >> j.rpt_log) + 255) / 256;
 }
 
 void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s) {
