@@ -199,10 +199,11 @@ struct NodeInfo {
 // concrete ones when the steps are placed in memory (level by level).
 enum { R_NODE = 10, R_TEMP = 11 };
 
-// FP32 steps of at least this many flops run on the matrix cores whatever
-// their shape (below it, only shapes that fill a tile do), unless their
-// inner sums are long (a tile walks its inner index alone) or their slices
-// have fewer than 8 outputs (inner products: split sums in the small kernel).
+// Steps of at least this many flops run on the tile kernels (matrix cores in
+// FP32, 64 x 64 FMA tiles in FP64) whatever their shape (below it, only shapes
+// that fill a tile do), unless their inner sums are long (a tile walks its
+// inner index alone: above 2^11 in FP32, 2^8 in FP64) or their slices have
+// fewer than 8 outputs (inner products: split sums in the small kernel).
 constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
 
 // One grouped contraction (host side of a GettJob).
@@ -339,7 +340,9 @@ struct Builder {
     template <typename PosIn, typename ByPos, typename SliceVec>
     void plan_mfma_job(StepRec& st, const NodeInfo& A, const NodeInfo& B, NodeInfo& C, const std::vector<int>& K,
                        const std::vector<int>& Bt, const std::vector<int>& FA, const std::vector<int>& FB,
-                       int64_t ninst, int64_t nbatch, PosIn posin, ByPos by_pos, SliceVec slice_vec) {
+                       int64_t ninst, int64_t nbatch, PosIn posin, ByPos by_pos, SliceVec slice_vec, int fp64) {
+        // FP64 steps run on the 64 x 64 FMA tiles (tile id 1's shape)
+        const int64_t esz = fp64 ? 16 : 8;
         static const double kEff[K_MFMA_TILES] = {1.0, 0.6, 0.75, 0.5, 0.35, 0.45, 0.3, 0.2};
         const int rk = (int)K.size();
         const int64_t ns = ninst * nbatch;
@@ -368,6 +371,7 @@ struct Builder {
             so[o][1] = slice_vec(Q, btb[o]);
             const std::vector<int64_t> ca = run_counts(so[o][0]), cb = run_counts(so[o][1]);
             for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+                if (fp64 && tile != 1) continue;
                 const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
                 const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
                 const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
@@ -407,7 +411,7 @@ struct Builder {
         C.legs.assign(bt_bits.rbegin(), bt_bits.rend());
         C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
         C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
-        C.bytes = ninst * (int64_t(8) << C.legs.size());
+        C.bytes = ninst * (esz << C.legs.size());
         C.buf = Ref{R_NODE, C.gid};
         MJob& jb = st.mjob;
         jb.m_log = (int)FR.size();
@@ -480,8 +484,8 @@ struct Builder {
         jb.oc = Ref{R_CONST, ex->cbuf.add(soc.data(), ns * 8)};
         const double mm = std::ldexp(1.0, jb.m_log), nnn = std::ldexp(1.0, jb.n_log), kk = std::ldexp(1.0, rk);
         jb.flops = 8.0 * mm * nnn * kk * (double)ns;
-        jb.bytes = 8.0 * ((double)ns * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
-                          (double)Q.keys.size() * nbatch * kk * nnn);
+        jb.bytes = (double)esz * ((double)ns * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
+                                  (double)Q.keys.size() * nbatch * kk * nnn);
         st.mgrouped = true;
         st.mtile = best_tile;
         st.c_bytes = C.bytes;
@@ -752,9 +756,9 @@ struct Builder {
             // are stacked into one tile (merge modes)
             const double step_flops = 8.0 * (double)ninst * (double)nbatch *
                                       std::ldexp(1.0, (int)(FA.size() + FB.size()) + rk);
-            const bool heavy = step_flops >= kMfmaMinFlops && rk <= 11 && FA.size() + FB.size() >= 3;
-            if (grouping && mode == 0 && (big || heavy)) {
-                plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec);
+            const bool heavy = step_flops >= kMfmaMinFlops && rk <= (fp64 ? 8 : 11) && FA.size() + FB.size() >= 3;
+            if (grouping && mode != 2 && (big || heavy)) {
+                plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec, fp64);
                 node_bytes[C.gid] = C.bytes;
                 steps->push_back(std::move(st));
                 continue;
@@ -1034,8 +1038,9 @@ struct Builder {
             for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
                 Launch M;
                 M.kind = L_MGROUP;
+                M.fp64 = fp64;
                 M.mtile = tile;
-                M.kclass = K_MFMA_GROUP_BASE + tile;
+                M.kclass = fp64 ? K_TILE64_GROUP : K_MFMA_GROUP_BASE + tile;
                 std::vector<MfmaTile> tl;
                 for (int i : grp) {
                     StepRec& st = steps[i];
@@ -1357,8 +1362,12 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
         launch_gett_group((const GettJob*)resolve(ex, L.jobs), L.n_jobs, L.blocks, L.fp64, s);
         break;
     case L_MGROUP:
-        launch_mfma_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
-                          L.n_tiles, s);
+        if (L.fp64)
+            launch_tile64_group((const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
+                                L.n_tiles, s);
+        else
+            launch_mfma_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
+                              L.n_tiles, s);
         break;
     case L_FINALIZE:
         launch_finalize(L.f, s);

@@ -100,6 +100,8 @@ struct MfmaTile {                  // one block of a grouped launch
 // tile: an MFMA tile id (0..K_MFMA_TILES-1); one launch per tile shape.
 void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
                        hipStream_t s);
+// FP64 (complex128) on the same descriptors, 64 x 64 tiles (tile id 1's shape).
+void launch_tile64_group(const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles, hipStream_t s);
 int mfma_tile_bm(int tile);
 int mfma_tile_bn(int tile);
 
@@ -113,7 +115,7 @@ enum KernelId {
     K_SMALL32 = 10, K_SPLITK32 = 11,
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
-    K_GROUP32 = 40, K_GROUP64 = 41,
+    K_GROUP32 = 40, K_GROUP64 = 41, K_TILE64_GROUP = 42,
     K_MFMA_GROUP_BASE = 200,   // + MFMA tile id: grouped matrix-core launch
     K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };

@@ -390,6 +390,9 @@ void k_gemm_mfma_g(GemmArgs g) {
 #ifndef MFMA_GROUP_WAVES
 #define MFMA_GROUP_WAVES 3
 #endif
+#ifndef MFMA_GROUP_BKC
+#define MFMA_GROUP_BKC 8
+#endif
 // Grouped matrix-core contractions (FP32 complex on mfma_f32_32x32x2f32, the
 // real embedding of K1).  One block per tile descriptor; the tile's row and
 // column offsets (A / B element offsets, C row / column offsets, -1 = padding)
@@ -405,7 +408,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = BM / WM / 32;
     constexpr int TN = BNC / WN / 16;
-    constexpr int BKC = 8, BKC_LOG = 3;
+    constexpr int BKC = MFMA_GROUP_BKC, BKC_LOG = __builtin_ctz(MFMA_GROUP_BKC);
     constexpr int BM_LOG = __builtin_ctz(BM), BN_LOG = __builtin_ctz(BNC);
     constexpr int AE = BM * BKC / NT;
     constexpr int BE = (BKC * BNC + NT - 1) / NT;
@@ -918,6 +921,152 @@ __global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Grouped FP64 tiles (complex128 FMA): the descriptors of the grouped
+// matrix-core launch (merge modes, slice tables, per-bit positions) on 64 x 64
+// output tiles; 256 threads, 4 x 4 outputs each, inner chunks of 8 staged in
+// LDS through the tile's row / column offset tables.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict__ jobs,
+                                                      const MfmaTile* __restrict__ tiles) {
+    constexpr int BM = 64, BN = 64, BK = 8, BK_LOG = 3;
+    // +2 elements per row: k-fast staging writes of 16 lanes fall in distinct banks
+    __shared__ double2 As[BK][BM + 2];
+    __shared__ double2 Bs[BK][BN + 2];
+    __shared__ int64_t row_a[BM], row_c[BM], col_b[BN], col_c[BN], ak_lo[BK], bk_lo[BK];
+    __shared__ int64_t a_step[32], b_step[32];
+    __shared__ MfmaJob J;
+    const MfmaTile T = tiles[blockIdx.x];
+    if (threadIdx.x == 0) J = jobs[T.job];
+    __syncthreads();
+    const int m_log = J.m_log, n_log = J.n_log, k_log = J.k_log;
+    const int64_t m = int64_t(1) << m_log, n = int64_t(1) << n_log, k = int64_t(1) << k_log;
+    const int kc = k < BK ? (int)k : BK;
+    const int kc_log = k_log < BK_LOG ? k_log : BK_LOG;
+    for (int i = threadIdx.x; i < BM; i += 256) {
+        int64_t ra = -1, rc = -1;
+        if (J.merge == 2) {
+            const int seg = i >> m_log;
+            const int64_t r = i & (m - 1);
+            if (seg < T.cnt) {
+                ra = J.oa[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
+                rc = J.oc[T.s0 + seg] + r * n;
+            }
+        } else {
+            const int64_t r = T.tm0 + i;
+            if (r < m) {
+                ra = J.oa[T.s0] + deposit(r, J.a_row, 0, m_log);
+                rc = (J.merge == 1 ? 0 : J.oc[T.s0]) + r * n;
+            }
+        }
+        row_a[i] = ra;
+        row_c[i] = rc;
+    }
+    for (int j = threadIdx.x; j < BN; j += 256) {
+        int64_t cb = -1, cc = -1;
+        if (J.merge == 1) {
+            const int seg = j >> n_log;
+            const int64_t c = j & (n - 1);
+            if (seg < T.cnt) {
+                cb = J.ob[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
+                cc = J.oc[T.s0 + seg] + c;
+            }
+        } else {
+            const int64_t c = T.tn0 + j;
+            if (c < n) {
+                cb = J.ob[T.s0] + deposit(c, J.b_col, 0, n_log);
+                cc = c;
+            }
+        }
+        col_b[j] = cb;
+        col_c[j] = cc;
+    }
+    for (int i = threadIdx.x; i < BK; i += 256) {
+        ak_lo[i] = i < kc ? deposit(i, J.a_k, 0, kc_log) : 0;
+        bk_lo[i] = i < kc ? deposit(i, J.b_k, 0, kc_log) : 0;
+    }
+    chunk_steps(J.a_k, kc_log, k_log, a_step);
+    chunk_steps(J.b_k, kc_log, k_log, b_step);
+    __syncthreads();
+    const double2* __restrict__ A = (const double2*)J.A;
+    const double2* __restrict__ B = (const double2*)J.B;
+    double2* __restrict__ C = (double2*)J.C;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double accr[4][4], acci[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
+    const int64_t nchunks = k >= BK ? k / BK : 1;
+    int64_t akh = 0, bkh = 0;
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        // staging: 2 A and 2 B elements per thread (row or column fast as stored)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = threadIdx.x + q * 256;
+            int r, p;
+            if (J.a_rowfast) {
+                r = e & (BM - 1);
+                p = e >> 6;
+            } else {
+                p = e & (BK - 1);
+                r = e >> BK_LOG;
+            }
+            const int64_t base = row_a[r];
+            As[p][r] = (base >= 0 && p < kc) ? A[base + ak_lo[p] + akh] : make_double2(0.0, 0.0);
+            int pb, c;
+            if (J.b_colfast) {
+                c = e & (BN - 1);
+                pb = e >> 6;
+            } else {
+                pb = e & (BK - 1);
+                c = e >> BK_LOG;
+            }
+            const int64_t bb = col_b[c];
+            Bs[pb][c] = (bb >= 0 && pb < kc) ? B[bb + bk_lo[pb] + bkh] : make_double2(0.0, 0.0);
+        }
+        {
+            const int t = __builtin_ctzll(~(uint64_t)ch);
+            if (t < k_log - kc_log) {
+                akh += a_step[t];
+                bkh += b_step[t];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < BK; ++p) {
+            double2 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[p][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[p][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    accr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
+                    acci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t rc = row_c[ty + 16 * i];
+        if (rc < 0) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t cc = col_c[tx + 16 * j];
+            if (cc >= 0) C[rc + cc] = make_double2(accr[i][j], acci[i][j]);
+        }
+    }
+}
+
+void launch_tile64_group(const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles, hipStream_t s) {
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL(k_tile64_group, dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+}
+
+// ---------------------------------------------------------------------------
 // K2: batched bit permutation, staged through LDS.  A tile covers the lowest
 // bits of both the input and the output index (up to 10 bits), so loads run
 // along the input's fastest legs and stores along the output's.  The offsets
@@ -1166,6 +1315,7 @@ const char* kernel_name(int id) {
     case K_PERM64: return "k_permute<double2>";
     case K_GROUP32: return "k_gett_group<float>";
     case K_GROUP64: return "k_gett_group<double>";
+    case K_TILE64_GROUP: return "k_tile64_group";
     }
     return "unknown";
 }
@@ -1175,7 +1325,7 @@ int kernel_class(int id) {
     if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return KC_MFMA;
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
-    if (id == K_GROUP32 || id == K_GROUP64) return KC_GROUP;
+    if (id == K_GROUP32 || id == K_GROUP64 || id == K_TILE64_GROUP) return KC_GROUP;
     if (id >= K_MFMA_GROUP_BASE && id < K_MFMA_GROUP_BASE + K_MFMA_TILES) return KC_GROUP;
     return KC_TILED;
 }

@@ -479,12 +479,11 @@ MFMA_TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i
 MFMA_TILE_SHAPES = [(128, 64), (64, 64), (128, 32), (64, 32), (32, 32), (128, 16), (64, 16), (32, 16)]
 
 
-def kernel_mfma_group(tile, jobs, tiles, stream=None):
-    """One grouped matrix-core launch.  jobs: dicts with device tensors A, B, C
-    (complex64) and oa, ob, oc (int64 slice offsets), m_log, n_log, k_log,
-    merge, a_rowfast, b_colfast and the bit-position lists a_row, a_k, b_k,
-    b_col; tiles: array of MFMA_TILE records.  Returns the device copies of
-    the descriptors (keep them alive until the stream is synchronized)."""
+def mfma_group_descriptors(jobs, tiles):
+    """Device copies of grouped matrix-core job and tile descriptors.  jobs:
+    dicts with device tensors A, B, C (complex64) and oa, ob, oc (int64 slice
+    offsets), m_log, n_log, k_log, merge, a_rowfast, b_colfast and the
+    bit-position lists a_row, a_k, b_k, b_col; tiles: array of MFMA_TILE."""
     import torch
     arr = (tn_mfma_job * len(jobs))()
     for q, j in enumerate(jobs):
@@ -499,9 +498,15 @@ def kernel_mfma_group(tile, jobs, tiles, stream=None):
     dj = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
     t = np.ascontiguousarray(tiles, dtype=MFMA_TILE)
     dt = torch.from_numpy(t.view(np.uint8).copy()).cuda()
+    return dj, dt, len(t)
+
+
+def kernel_mfma_group(tile, descriptors, stream=None):
+    """One grouped matrix-core launch over descriptors from
+    mfma_group_descriptors (asynchronous on the stream)."""
+    dj, dt, n = descriptors
     _check(_kernel_lib().tn_kernel_mfma_group(tile, C.c_void_p(dj.data_ptr()), C.c_void_p(dt.data_ptr()),
-                                              len(t), _stream_ptr(stream)))
-    return dj, dt
+                                              n, _stream_ptr(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -243,9 +243,11 @@ class Sim:
         row / column offset tables; every output element of every job must be
         written exactly once, and no job may write what another job reads."""
         bm, bn = L["bm"], L["bn"]
+        dt = np.complex128 if L["fp64"] else np.complex64
+        esz = np.dtype(dt).itemsize
         tiles = self.view(L["tiles"], np.uint8, L["n_tiles"] * self.TILE.itemsize).view(self.TILE)
         jobs = L["jobs"]
-        spans = [self._job_spans(jb, 8) for jb in jobs]
+        spans = [self._job_spans(jb, esz) for jb in jobs]
         for i, (wi, _) in enumerate(spans):
             for j, (wj, rj) in enumerate(spans):
                 for other in ([wj] if i != j else []) + rj:
@@ -259,9 +261,9 @@ class Sim:
             oc = self.view(jb["oc"], np.int64, ns)
             amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
             bmax = int(ob.max()) + sum(1 << p for p in jb["b_k"] + jb["b_col"])
-            A = self.view(jb["a"], np.complex64, amax + 1)
-            B = self.view(jb["b"], np.complex64, bmax + 1)
-            C = self.view(jb["c"], np.complex64, ns * m * n)
+            A = self.view(jb["a"], dt, amax + 1)
+            B = self.view(jb["b"], dt, bmax + 1)
+            C = self.view(jb["c"], dt, ns * m * n)
             ctx.append((m, n, k, oa, ob, oc, A, B, C, np.zeros(ns * m * n, np.int32),
                         _deposit(k, jb["a_k"]), _deposit(k, jb["b_k"])))
         for t in tiles:
@@ -296,7 +298,7 @@ class Sim:
             At = A[ra[:, None] + ka[None, :]].astype(np.complex128)
             Bt = B[kb[:, None] + cb[None, :]].astype(np.complex128)
             idx = (rc[:, None] + cc[None, :]).reshape(-1)
-            C[idx] = (At @ Bt).astype(np.complex64).reshape(-1)
+            C[idx] = (At @ Bt).astype(dt).reshape(-1)
             np.add.at(hits, idx, 1)
         for q, cx in enumerate(ctx):
             assert cx[9].min() == 1 and cx[9].max() == 1, ("output coverage", q, cx[9].min(), cx[9].max())
