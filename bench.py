@@ -77,8 +77,57 @@ def measured_traffic(kernel):
     return t["traffic_bytes_per_launch"]
 
 
+def _kernel_key(name):
+    """'void tn::k_mfma_group<128, 64>(tn::MfmaJob const*, ...)' -> 'k_mfma_group<128,64>'."""
+    n = name.split("(")[0].replace("void ", "").replace("tn::", "")
+    n = n.replace("HIP_vector_type<float, 2u>", "").replace("HIP_vector_type<double, 2u>", "")
+    n = n.replace(" ", "").replace(",>", ">")
+    return n
+
+
+def traffic_from_counters(fetch_csv, write_csv, kernel, out_path):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of
+    bench.py --copy-calibration (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch).  Each counter is scaled by what it reads for the 512 MiB
+    device-to-device copy of the calibration (the dispatches that write
+    512 MiB), so the figure is in bytes moved."""
+    import csv
+    import hashlib
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        return rows
+    fr, wr = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy_ids = {r["Dispatch_Id"] for r in wr if "copyBuffer" in r["Kernel_Name"]
+                and abs(float(r["Counter_Value"]) - 524288.0) < 1.0}
+    copy_fetch = [float(r["Counter_Value"]) for r in fr if "copyBuffer" in r["Kernel_Name"]
+                  and r["Dispatch_Id"] in copy_ids]
+    copy_write = [float(r["Counter_Value"]) for r in wr if r["Dispatch_Id"] in copy_ids]
+    if not copy_fetch or not copy_write:
+        raise SystemExit("no 512 MiB calibration copy in the counter files")
+    fs = 524288.0 / (sum(copy_fetch) / len(copy_fetch))
+    ws = 524288.0 / (sum(copy_write) / len(copy_write))
+    kf = [float(r["Counter_Value"]) for r in fr if _kernel_key(r["Kernel_Name"]) == kernel]
+    kw = [float(r["Counter_Value"]) for r in wr if _kernel_key(r["Kernel_Name"]) == kernel]
+    if not kf or not kw:
+        raise SystemExit(f"kernel {kernel} not in the counter files")
+    f_kib, w_kib = sum(kf) / len(kf), sum(kw) / len(kw)
+    with open(os.path.join(ROOT, "paper_2211_17028_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"kernel": kernel, "kernels_hip_sha256": sha, "dispatches": len(kf),
+           "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib, "fetch_scale": fs,
+           "write_scale": ws, "traffic_bytes_per_launch": 1024.0 * (f_kib * fs + w_kib * ws)}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic record of --traffic-kernel from two rocprofv3 --pmc "
+                         "counter files of bench.py --copy-calibration, then exit (no GPU needed)")
+    ap.add_argument("--traffic-kernel", default="k_mfma_group<128,64>")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -90,6 +139,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.traffic_kernel,
+                              os.path.join(ROOT, "profiles", "traffic_grid5x5_level2.json"))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "
               f"shard across GPUs with one all-reduce of the level sums, which this build does not run.",
