@@ -205,6 +205,8 @@ enum { R_NODE = 10, R_TEMP = 11 };
 // inner index alone: above 2^11 in FP32, 2^8 in FP64) or their slices have
 // fewer than 8 outputs (inner products: split sums in the small kernel).
 constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
+// Below this many flops a step that fills a tile still joins the small-step launch.
+constexpr double kTileMinFlops = 2.0 * 1024 * 1024;
 
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
@@ -757,13 +759,16 @@ struct Builder {
             const double step_flops = 8.0 * (double)ninst * (double)nbatch *
                                       std::ldexp(1.0, (int)(FA.size() + FB.size()) + rk);
             const bool heavy = step_flops >= kMfmaMinFlops && rk <= (fp64 ? 8 : 11) && FA.size() + FB.size() >= 3;
-            if (grouping && mode != 2 && (big || heavy)) {
+            // tiny steps stay with their level's small-step launch even when
+            // their shape would fill a tile: a launch of their own costs more
+            const bool to_tile = (big && step_flops >= kTileMinFlops) || heavy;
+            if (grouping && mode != 2 && to_tile) {
                 plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec, fp64);
                 node_bytes[C.gid] = C.bytes;
                 steps->push_back(std::move(st));
                 continue;
             }
-            if (grouping && mode != 2 && !big) {
+            if (grouping && mode != 2) {
                 // column operand: one whose lowest stored leg is a free leg, so
                 // that consecutive threads (consecutive columns) read adjacent elements
                 const bool qa = std::find(FA.begin(), FA.end(), A.legs.back()) != FA.end();

@@ -179,9 +179,8 @@ def test_schedule_replay_plain_mode_matches_batched():
     assert np.allclose(xb, xp, rtol=2e-5, atol=1e-9)
 
 
-@pytest.mark.parametrize("n,gates,noises,target,seed", [(14, 120, 4, "circuit_output", 2),
-                                                         (14, 120, 4, "circuit_output", 3),
-                                                         (16, 120, 3, "product", 2)])
+@pytest.mark.parametrize("n,gates,noises,target,seed", [(16, 160, 4, "circuit_output", 1),
+                                                         (16, 160, 4, "circuit_output", 2)])
 def test_schedule_replay_gathered_operands(n, gates, noises, target, seed):
     """Circuits wide enough for matrix-core steps.  Batched mode groups each
     tree level (small steps in one launch, matrix-core steps in one launch per
@@ -192,7 +191,10 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed):
                               target=target)
     r = estimate.estimate(c, 2, "network", reduce=True)
     x, pat, desc = _replay(c, 2)
-    assert any(L["kind"] == 6 for L in desc["launches"]), "no grouped matrix-core launch"
+    assert any(L["kind"] == 6 and not L["fp64"] for L in desc["launches"]), "no grouped matrix-core launch"
+    assert any(L["kind"] == 6 and L["fp64"] for L in desc["launches"]), "no grouped FP64 tile launch"
+    merges = {j["merge"] for L in desc["launches"] if L["kind"] == 6 for j in L["jobs"]}
+    assert merges == {0, 1, 2}, merges
     x_g, _, desc_g = _replay(c, 2, group=False)
     assert any(L["kind"] == 1 and L.get("gather") for L in desc_g["launches"]), "no gathered step"
     x_t, _, desc_t = _replay(c, 2, gather=False, group=False)
