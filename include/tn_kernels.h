@@ -30,6 +30,11 @@
  *   0: one slice per tile (origin tm0, tn0).  Jobs and tiles are device
  *   arrays in the tn_mfma_job / tn_mfma_tile layouts; `tile` selects the tile
  *   shape (0..7: 128x64, 64x64, 128x32, 64x32, 32x32, 128x16, 64x16, 32x16).
+ *   ksplit = 2 splits each tile's inner sum over a pair of tiles (kpart 0 and
+ *   1, same pair index): the partial tiles go to `partial` (2 * BM * BNC
+ *   complex64 per pair) and are added in the order half 0 + half 1 by the
+ *   second block of the pair, so results are the same run to run; `counters`
+ *   must be zero before the launch and is zero again after it.
  *   Asynchronous on `stream`.  Returns 0 or a negative TN_E* code.
  */
 typedef struct {
@@ -43,10 +48,14 @@ typedef struct {
     int32_t merge;
     int32_t a_rowfast, b_colfast;  /* lowest stored bit of A is a row bit / of B a column bit */
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+    int32_t ksplit, pad_;          /* 2: tiles come in pairs over the two halves of the inner index */
+    void* partial;                 /* ksplit 2: 2 partial tiles per pair (device scratch) */
+    int32_t* counters;             /* ksplit 2: one zero-initialised int per pair (reset by the kernel) */
 } tn_mfma_job;
 typedef struct {
     int32_t job, cnt;
     int64_t s0, tm0, tn0;
+    int32_t kpart, pair;           /* ksplit 2: inner half (0/1) and pair index */
 } tn_mfma_tile;
 #ifndef TN_KERNELS_H
 #define TN_KERNELS_H

@@ -207,6 +207,11 @@ enum { R_NODE = 10, R_TEMP = 11 };
 constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
 // Below this many flops a step that fills a tile still joins the small-step launch.
 constexpr double kTileMinFlops = 2.0 * 1024 * 1024;
+// A tile job splits its inner sum over two blocks when the sum has at least
+// 2^kSplitMinKLog terms and the doubled tiles leave at most two per CU (more
+// tiles per CU already keep the matrix cores busy through the inner loop).
+constexpr int kSplitMinKLog = 6;
+constexpr int64_t kSplitMaxTiles = 512;
 
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
@@ -221,6 +226,8 @@ struct GroupJob {
 struct MJob {
     Ref a, b, c, oa, ob, oc;
     int m_log = 0, n_log = 0, k_log = 0, merge = 0, a_rowfast = 0, b_colfast = 0;
+    int ksplit = 1;
+    Ref partial, counters;     // ksplit 2: partial tiles (work region) and pair counters (zeroed constants)
     int64_t ns = 0;            // slices
     int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
     double flops = 0, bytes = 0;
@@ -477,6 +484,29 @@ struct Builder {
                 }
                 g0 = g1;
             }
+        }
+        // Latency-bound jobs (long inner sums, few tiles: every tile resident at
+        // once even when doubled) split the inner sum over a pair of tiles.
+        const int64_t nt = (int64_t)st.mtiles.size();
+        if (rk >= kSplitMinKLog && 2 * nt <= kSplitMaxTiles) {
+            std::vector<MfmaTile> two;
+            two.reserve(2 * nt);
+            for (int64_t q = 0; q < nt; ++q)
+                for (int h = 0; h < 2; ++h) {
+                    MfmaTile t = st.mtiles[q];
+                    t.kpart = h;
+                    t.pair = (int32_t)q;
+                    two.push_back(t);
+                }
+            st.mtiles.swap(two);
+            jb.ksplit = 2;
+            const int64_t pbytes = nt * 2 * (int64_t)bm * bn * 2 * (fp64 ? 8 : 4);
+            const int tid = (int)temp_ref.size();
+            temp_ref.push_back(Ref{});
+            st.temp_ids.push_back(tid);
+            st.temp_bytes.push_back(pbytes);
+            jb.partial = Ref{R_TEMP, tid};
+            jb.counters = Ref{R_CONST, ex->cbuf.reserve(nt * 4)};
         }
         jb.a = R.buf;
         jb.b = Q.buf;
@@ -1054,6 +1084,7 @@ struct Builder {
                     subst(jb.a);
                     subst(jb.b);
                     subst(jb.c);
+                    subst(jb.partial);
                     const int ji = (int)M.mjobs.size();
                     for (MfmaTile t : st.mtiles) {
                         t.job = ji;
@@ -1313,6 +1344,9 @@ static void bind(tn_exec_s* ex) {
                 j.merge = h.merge;
                 j.a_rowfast = h.a_rowfast;
                 j.b_colfast = h.b_colfast;
+                j.ksplit = h.ksplit;
+                j.partial = h.ksplit == 2 ? resolve(ex, h.partial) : nullptr;
+                j.counters = h.ksplit == 2 ? (int32_t*)resolve(ex, h.counters) : nullptr;
                 std::memcpy(j.a_row, h.a_row, 32);
                 std::memcpy(j.a_k, h.a_k, 32);
                 std::memcpy(j.b_k, h.b_k, 32);
@@ -1544,6 +1578,8 @@ static std::string describe_exec(const tn_exec_s* ex) {
                    << "," << h.oa.off << "],\"ob\":[" << h.ob.region << "," << h.ob.off << "],\"oc\":["
                    << h.oc.region << "," << h.oc.off << "],\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log
                    << ",\"k_log\":" << h.k_log << ",\"ns\":" << h.ns << ",\"merge\":" << h.merge
+                   << ",\"ksplit\":" << h.ksplit << ",\"partial\":[" << h.partial.region << "," << h.partial.off
+                   << "],\"counters\":[" << h.counters.region << "," << h.counters.off << "]"
                    << ",\"a_rowfast\":" << h.a_rowfast
                    << ",\"b_colfast\":" << h.b_colfast;
                 auto arr = [&](const char* nm, const int8_t* v, int n) {

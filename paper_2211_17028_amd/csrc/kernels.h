@@ -91,11 +91,20 @@ struct MfmaJob {
     int32_t merge;
     int32_t a_rowfast, b_colfast;  // lowest stored bit of A is a row bit / of B a column bit
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
+    // Split inner sums (ksplit = 2): tile pair p runs the two halves of the
+    // inner index in two blocks; each writes its partial tile to
+    // partial[p][half], then counts in counters[p]; the second to arrive adds
+    // the two partials in the fixed order half 0 + half 1 (so the result does
+    // not depend on which arrives first), writes C and resets the counter.
+    int32_t ksplit, pad_;
+    void* partial;
+    int32_t* counters;
 };
 struct MfmaTile {                  // one block of a grouped launch
     int32_t job, cnt;
     int64_t s0;                    // first slice
     int64_t tm0, tn0;              // tile origin inside the slice (unmerged dimensions)
+    int32_t kpart, pair;           // ksplit = 2: inner half and tile-pair index
 };
 // tile: an MFMA tile id (0..K_MFMA_TILES-1); one launch per tile shape.
 void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,

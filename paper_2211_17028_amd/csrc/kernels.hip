@@ -515,9 +515,15 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             c = e >> BKC_LOG;
         }
     };
+    // chunks of this block: all, or one half of them (split inner sum)
+    const int64_t nch_all = k >= BKC ? k / BKC : 1;
+    const int64_t c_begin = (J.ksplit == 2 && T.kpart) ? nch_all / 2 : 0;
+    const int64_t c_end = (J.ksplit == 2 && !T.kpart) ? nch_all / 2 : nch_all;
     // offsets of the high inner bits of the chunk being loaded (chunks are
     // loaded in order: advanced by the step table after each load)
-    int64_t akh = 0, bkh = 0, kchunk = 0;
+    int64_t kchunk = c_begin;
+    int64_t akh = deposit(c_begin << kc_log, J.a_k, kc_log, k_log);
+    int64_t bkh = deposit(c_begin << kc_log, J.b_k, kc_log, k_log);
     auto load = [&](int64_t, float2* ra, float2* rb) {
 #pragma unroll
         for (int q = 0; q < AE; ++q) {
@@ -597,7 +603,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         }
     };
     // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
-    const int64_t nchunks = k >= BKC ? k / BKC : 1;
+    const int64_t nchunks = c_end - c_begin;
     float2 ra[AE], rb[BE];
     load(0, ra, rb);
     stash(0, ra, rb);
@@ -608,6 +614,34 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         compute(buf);
         if (ch + 1 < nchunks) stash(buf ^ 1, ra, rb);
         __syncthreads();
+    }
+    if (J.ksplit == 2) {
+        // partial tile in the accumulators' own layout (coalesced per lane)
+        constexpr int64_t PT = int64_t(BM) * BNC * 2;
+        float* mine = (float*)J.partial + ((int64_t)T.pair * 2 + T.kpart) * PT;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    mine[(((int64_t)(wave * TM + i) * TN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
+        __threadfence();
+        __syncthreads();
+        __shared__ int arrived;
+        if (threadIdx.x == 0) arrived = atomicAdd(&J.counters[T.pair], 1);
+        __syncthreads();
+        if (arrived == 0) return;           // the other half finishes the tile
+        if (threadIdx.x == 0) J.counters[T.pair] = 0;
+        __threadfence();
+        const float* other = (const float*)J.partial + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc[i][j][r] += other[(((int64_t)(wave * TM + i) * TN + j) * 16 + r) * 64 + lane];
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -996,9 +1030,12 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
-    const int64_t nchunks = k >= BK ? k / BK : 1;
-    int64_t akh = 0, bkh = 0;
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int64_t nch_all = k >= BK ? k / BK : 1;
+    const int64_t c_begin = (J.ksplit == 2 && T.kpart) ? nch_all / 2 : 0;
+    const int64_t c_end = (J.ksplit == 2 && !T.kpart) ? nch_all / 2 : nch_all;
+    int64_t akh = deposit(c_begin << kc_log, J.a_k, kc_log, k_log);
+    int64_t bkh = deposit(c_begin << kc_log, J.b_k, kc_log, k_log);
+    for (int64_t ch = c_begin; ch < c_end; ++ch) {
         // staging: 2 A and 2 B elements per thread (row or column fast as stored)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -1048,6 +1085,34 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
                 }
         }
         __syncthreads();
+    }
+    if (J.ksplit == 2) {
+        // partial tile, 32 doubles per thread, thread-fastest
+        constexpr int64_t PT = 64 * 64 * 2;
+        double* mine = (double*)J.partial + ((int64_t)T.pair * 2 + T.kpart) * PT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                mine[(i * 4 + j) * 256 + threadIdx.x] = accr[i][j];
+                mine[(16 + i * 4 + j) * 256 + threadIdx.x] = acci[i][j];
+            }
+        __threadfence();
+        __syncthreads();
+        __shared__ int arrived;
+        if (threadIdx.x == 0) arrived = atomicAdd(&J.counters[T.pair], 1);
+        __syncthreads();
+        if (arrived == 0) return;           // the other half finishes the tile
+        if (threadIdx.x == 0) J.counters[T.pair] = 0;
+        __threadfence();
+        const double* other = (const double*)J.partial + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                accr[i][j] += other[(i * 4 + j) * 256 + threadIdx.x];
+                acci[i][j] += other[(16 + i * 4 + j) * 256 + threadIdx.x];
+            }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -472,10 +472,12 @@ class tn_mfma_job(C.Structure):
                 ("ob", C.c_void_p), ("oc", C.c_void_p), ("m_log", C.c_int32), ("n_log", C.c_int32),
                 ("k_log", C.c_int32), ("merge", C.c_int32), ("a_rowfast", C.c_int32), ("b_colfast", C.c_int32),
                 ("a_row", C.c_int8 * 32), ("a_k", C.c_int8 * 32), ("b_k", C.c_int8 * 32),
-                ("b_col", C.c_int8 * 32)]
+                ("b_col", C.c_int8 * 32), ("ksplit", C.c_int32), ("pad_", C.c_int32),
+                ("partial", C.c_void_p), ("counters", C.c_void_p)]
 
 
-MFMA_TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8")])
+MFMA_TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8"),
+                      ("kpart", "<i4"), ("pair", "<i4")])
 MFMA_TILE_SHAPES = [(128, 64), (64, 64), (128, 32), (64, 32), (32, 32), (128, 16), (64, 16), (32, 16)]
 
 
@@ -495,6 +497,9 @@ def mfma_group_descriptors(jobs, tiles):
         for f in ("a_row", "a_k", "b_k", "b_col"):
             for i, v in enumerate(j[f]):
                 getattr(r, f)[i] = int(v)
+        r.ksplit = int(j.get("ksplit", 1))
+        if r.ksplit == 2:
+            r.partial, r.counters = j["partial"].data_ptr(), j["counters"].data_ptr()
     dj = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
     t = np.ascontiguousarray(tiles, dtype=MFMA_TILE)
     dt = torch.from_numpy(t.view(np.uint8).copy()).cuda()

@@ -236,7 +236,8 @@ class Sim:
         return (span(jb["c"], 0, ni * m * n),
                 [span(jb["a"], int(oa.min()), amax + 1), span(jb["b"], int(ob.min()), bmax + 1)])
 
-    TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8")])
+    TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8"),
+                     ("kpart", "<i4"), ("pair", "<i4")])
 
     def mgroup(self, L):
         """Grouped matrix-core launch, tile by tile as the kernel builds its
@@ -266,9 +267,16 @@ class Sim:
             C = self.view(jb["c"], dt, ns * m * n)
             ctx.append((m, n, k, oa, ob, oc, A, B, C, np.zeros(ns * m * n, np.int32),
                         _deposit(k, jb["a_k"]), _deposit(k, jb["b_k"])))
+        halves = {}
         for t in tiles:
             jb = jobs[t["job"]]
             m, n, k, oa, ob, oc, A, B, C, hits, ka, kb = ctx[t["job"]]
+            if jb.get("ksplit", 1) == 2:
+                # the inner sum of a tile pair is split in two halves, added in
+                # the order half 0 + half 1 by whichever block arrives second
+                h = k // 2
+                sel = slice(0, h) if t["kpart"] == 0 else slice(h, k)
+                ka, kb = ka[sel], kb[sel]
             cnt, s0, tm0, tn0 = int(t["cnt"]), int(t["s0"]), int(t["tm0"]), int(t["tn0"])
             i = np.arange(bm, dtype=np.int64)
             j = np.arange(bn, dtype=np.int64)
@@ -298,7 +306,18 @@ class Sim:
             At = A[ra[:, None] + ka[None, :]].astype(np.complex128)
             Bt = B[kb[:, None] + cb[None, :]].astype(np.complex128)
             idx = (rc[:, None] + cc[None, :]).reshape(-1)
-            C[idx] = (At @ Bt).astype(dt).reshape(-1)
+            part = (At @ Bt).astype(dt).reshape(-1)
+            if jb.get("ksplit", 1) == 2:
+                key = (int(t["job"]), int(t["pair"]))
+                got = halves.setdefault(key, {})
+                assert int(t["kpart"]) not in got, ("tile half listed twice", key)
+                got[int(t["kpart"])] = (idx, part)
+                if len(got) < 2:
+                    continue
+                (i0, p0), (i1, p1) = got[0], got[1]
+                assert np.array_equal(i0, i1), ("the halves of a pair cover different outputs", key)
+                part = (p0 + p1).astype(dt)
+            C[idx] = part
             np.add.at(hits, idx, 1)
         for q, cx in enumerate(ctx):
             assert cx[9].min() == 1 and cx[9].max() == 1, ("output coverage", q, cx[9].min(), cx[9].max())

@@ -351,3 +351,102 @@ def test_schedule_variants_agree(torch, cfg):
         # every term: same value within FP32 rounding of the larger terms
         scale = np.maximum(x, x0)
         assert np.all(np.abs(x - x0) <= 1e-4 * scale + 1e-6 * x0.max() * 1e-6)
+
+
+def _deposit_np(count, pos):
+    x = np.arange(count, dtype=np.int64)
+    o = np.zeros(count, dtype=np.int64)
+    for j, p in enumerate(pos):
+        o |= ((x >> j) & 1) << p
+    return o
+
+
+def _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit):
+    """A job whose operands sit in random stored bit orders; slices share the
+    merged operand in groups of `share`; tiles cut as the planner does."""
+    m, n, k = 1 << m_log, 1 << n_log, 1 << k_log
+    pa = list(rng.permutation(m_log + k_log))
+    pb = list(rng.permutation(k_log + n_log))
+    a_row, a_k = [int(v) for v in pa[:m_log]], [int(v) for v in pa[m_log:]]
+    b_k, b_col = [int(v) for v in pb[:k_log]], [int(v) for v in pb[k_log:]]
+    sa, sb = m * k, k * n
+    if merge == 1:
+        ka = np.arange(n_slices) // share
+        kb = np.arange(n_slices)
+    elif merge == 2:
+        ka = np.arange(n_slices)
+        kb = np.arange(n_slices) // share
+    else:
+        ka = kb = np.arange(n_slices)
+    na, nb = int(ka.max()) + 1, int(kb.max()) + 1
+    A = (rng.standard_normal(na * sa) + 1j * rng.standard_normal(na * sa)).astype(np.complex64)
+    B = (rng.standard_normal(nb * sb) + 1j * rng.standard_normal(nb * sb)).astype(np.complex64)
+    oa, ob = ka * sa, kb * sb
+    oc = np.arange(n_slices) * m * n
+    ref = np.empty((n_slices, m, n), np.complex128)
+    ar, ak, bk, bc = (_deposit_np(m, a_row), _deposit_np(k, a_k), _deposit_np(k, b_k), _deposit_np(n, b_col))
+    for s in range(n_slices):
+        As = A[oa[s] + ar[:, None] + ak[None, :]].astype(np.complex128)
+        Bs = B[ob[s] + bk[:, None] + bc[None, :]].astype(np.complex128)
+        ref[s] = As @ Bs
+    bm, bn = tn.MFMA_TILE_SHAPES[tile]
+    tiles = []
+    if merge == 0:
+        for s in range(n_slices):
+            for r in range(max(1, m // bm)):
+                for c in range(max(1, n // bn)):
+                    tiles.append((0, 1, s, r * bm, c * bn, 0, 0))
+    else:
+        segs = (bn // n) if merge == 1 else (bm // m)
+        for g0 in range(0, n_slices, share):
+            g1 = min(n_slices, g0 + share)
+            for p0 in range(g0, g1, segs):
+                cnt = min(segs, g1 - p0)
+                if merge == 1:
+                    for r in range(max(1, m // bm)):
+                        tiles.append((0, cnt, p0, r * bm, 0, 0, 0))
+                else:
+                    for c in range(max(1, n // bn)):
+                        tiles.append((0, cnt, p0, 0, c * bn, 0, 0))
+    job = dict(A=torch.from_numpy(A).cuda(), B=torch.from_numpy(B).cuda(),
+               C=torch.zeros(n_slices * m * n, dtype=torch.complex64, device="cuda"),
+               oa=torch.from_numpy(oa.astype(np.int64)).cuda(), ob=torch.from_numpy(ob.astype(np.int64)).cuda(),
+               oc=torch.from_numpy(oc.astype(np.int64)).cuda(), m_log=m_log, n_log=n_log, k_log=k_log,
+               merge=merge, a_rowfast=int(a_row[0] == 0) if m_log else 0,
+               b_colfast=int(b_col[0] == 0) if n_log else 0, a_row=a_row, a_k=a_k, b_k=b_k, b_col=b_col)
+    if ksplit == 2:
+        pairs = []
+        for q, t in enumerate(tiles):
+            pairs += [t[:5] + (0, q), t[:5] + (1, q)]
+        tiles = pairs
+        job.update(ksplit=2, partial=torch.empty(len(pairs) * bm * bn * 2, dtype=torch.float32, device="cuda"),
+                   counters=torch.zeros(len(pairs) // 2, dtype=torch.int32, device="cuda"))
+    return job, np.array(tiles, dtype=tn.MFMA_TILE), ref
+
+
+@pytest.mark.parametrize("m_log,n_log,k_log,n_slices,share,merge,tile,ksplit", [
+    (8, 6, 5, 3, 1, 0, 0, 1),       # plain slices, 128 x 64 tiles
+    (7, 4, 6, 9, 3, 1, 0, 1),       # columns hold 4 slices sharing A (ragged groups of 3)
+    (3, 5, 4, 10, 4, 2, 2, 1),      # rows hold 16 slices sharing B, 128 x 32 tiles
+    (6, 3, 2, 5, 5, 1, 6, 1),       # k < 8 (padded inner chunk), n < 16
+    (8, 4, 8, 12, 3, 1, 0, 2),      # split inner sum over tile pairs
+    (5, 5, 7, 4, 1, 0, 4, 2),       # split, 32 x 32 tiles
+])
+def test_grouped_mfma_kernel_against_numpy(torch, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit):
+    """tn_kernel_mfma_group on operands in random stored bit orders, against a
+    complex128 numpy product of the gathered slices; FP32 accumulation over k
+    products of O(1) numbers bounds the error by ~k u32 of the row norms."""
+    print(f"mfma group {m_log} {n_log} {k_log} x{n_slices} merge {merge} tile {tile} split {ksplit}", flush=True)
+    rng = np.random.default_rng(1000 + m_log * 100 + k_log * 10 + merge)
+    job, tiles, ref = _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit)
+    d = tn.mfma_group_descriptors([job], tiles)
+    for rep in range(2):     # the second launch reuses the (reset) pair counters
+        job["C"].zero_()
+        tn.kernel_mfma_group(tile, d)
+        torch.cuda.synchronize()
+        got = job["C"].cpu().numpy().reshape(ref.shape)
+        err = np.abs(got - ref).max()
+        scale = np.sqrt(2.0 * (1 << k_log)) * 2.0
+        assert err <= 4e-6 * scale * max(1.0, np.sqrt(1 << k_log) / 4), (rep, err)
+    if ksplit == 2:
+        assert int(job["counters"].abs().sum().item()) == 0
