@@ -159,6 +159,11 @@ struct tn_exec_s {
     std::vector<tn::Launch> launches64;     // FP64 dominant-term pass (side stream)
     std::vector<tn::Launch> plain_launches; // PLAIN mode per-term body
     std::vector<tn::Launch> tail;           // finalize + level sums
+    // packed circuits: the tail runs as one finalize and one level-sum launch
+    bool multi_tail = false;
+    tn::Ref fin_args, fin_block0, ls_jobs;
+    int64_t fin_blocks = 0;
+    int n_ls_jobs = 0;
     std::vector<tn::PlanExec> plans;
     tn::ConstBuf cbuf;
     int64_t const_bytes = 0, work_bytes = 0, work1_bytes = 0;
@@ -205,6 +210,7 @@ enum { R_NODE = 10, R_TEMP = 11 };
 // inner index alone: above 2^11 in FP32, 2^8 in FP64) or their slices have
 // fewer than 8 outputs (inner products: split sums in the small kernel).
 constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
+constexpr int64_t kNumCUs = 256;     // MI355X compute units
 // Below this many flops a step that fills a tile still joins the small-step launch.
 constexpr double kTileMinFlops = 2.0 * 1024 * 1024;
 // A tile job splits its inner sum over two blocks when the sum has at least
@@ -385,8 +391,14 @@ struct Builder {
                 const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
                 const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
                 const double per_tile = std::ldexp(1.0, bm_log + bn_log) * (std::ldexp(1.0, rk) + 16.0) / kEff[tile];
+                // tiles on one CU share its matrix cores, so a launch lasts as long
+                // as its busiest CU: a job large enough to fill the chip has its
+                // tile count rounded up to whole rounds over the 256 CUs (smaller
+                // jobs share their launch with the level's other jobs)
                 auto consider = [&](int64_t tiles, int merge) {
-                    const double cst = (double)tiles * per_tile;
+                    const int64_t eff_tiles =
+                        tiles < kNumCUs ? tiles : ((tiles + kNumCUs - 1) / kNumCUs) * kNumCUs;
+                    const double cst = (double)eff_tiles * per_tile;
                     if (cst < best_cost) {
                         best_cost = cst;
                         best_o = o;
@@ -1274,6 +1286,14 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
     }
     bw.emit(steps32, 0, true, &ex->launches);
     bw.emit(steps64, 1, true, &ex->launches64);
+    if (n > 1) {
+        ex->multi_tail = true;
+        ex->fin_args = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(FinalizeArgs))};
+        ex->fin_block0 = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * 8)};
+        for (auto& L : ex->tail)
+            if (L.kind == L_LEVELSUM) ex->n_ls_jobs += L.n_levels;
+        ex->ls_jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)ex->n_ls_jobs * (int64_t)sizeof(LevelSumJob))};
+    }
     ex->const_bytes = round_up((int64_t)ex->cbuf.bytes.size(), 256);
     ex->work1_bytes = round_up(bw.work.peak, 256);
     ex->work_bytes = ex->work1_bytes + round_up(bw.work2.peak, 256);
@@ -1387,6 +1407,35 @@ static void bind(tn_exec_s* ex) {
     }
 }
 
+// packed circuits: the per-circuit finalize / level-sum records as two launches
+static void bind_multi_tail(tn_exec_s* ex) {
+    if (!ex->multi_tail) return;
+    FinalizeArgs* fa = (FinalizeArgs*)(ex->cbuf.bytes.data() + ex->fin_args.off);
+    int64_t* b0 = (int64_t*)(ex->cbuf.bytes.data() + ex->fin_block0.off);
+    LevelSumJob* lj = (LevelSumJob*)(ex->cbuf.bytes.data() + ex->ls_jobs.off);
+    int nf = 0, nl = 0;
+    int64_t blocks = 0;
+    for (auto& L : ex->tail) {
+        if (L.kind == L_FINALIZE) {
+            std::memcpy(fa + nf, &L.f, sizeof(FinalizeArgs));
+            b0[nf] = blocks;
+            blocks += (L.f.n_terms + 255) / 256;
+            ++nf;
+        } else if (L.kind == L_LEVELSUM) {
+            for (int u = 0; u < L.n_levels; ++u) {
+                LevelSumJob j{};
+                j.x = (const double*)resolve(ex, L.x_out);
+                j.starts = (const int64_t*)resolve(ex, L.starts);
+                j.out = (double*)resolve(ex, L.sums);
+                j.u = u;
+                std::memcpy(lj + nl, &j, sizeof(LevelSumJob));
+                ++nl;
+            }
+        }
+    }
+    ex->fin_blocks = blocks;
+}
+
 static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
     if ((L.kind == L_GEMM && L.g.n_inst == 0) || (L.kind == L_PERM && L.p.n_inst == 0)) return;
     switch (L.kind) {
@@ -1456,7 +1505,14 @@ static void run_body(tn_exec_s* ex, hipStream_t s) {
             }
         }
     }
-    for (auto& L : ex->tail) enqueue(ex, L, s);
+    if (ex->multi_tail) {
+        const int nf = (int)(ex->tail.size() / 2);
+        launch_finalize_multi((const FinalizeArgs*)resolve(ex, ex->fin_args), (const int64_t*)resolve(ex, ex->fin_block0),
+                              nf, ex->fin_blocks, s);
+        launch_level_sum_multi((const LevelSumJob*)resolve(ex, ex->ls_jobs), ex->n_ls_jobs, s);
+    } else {
+        for (auto& L : ex->tail) enqueue(ex, L, s);
+    }
     HIPCHK(hipGetLastError());
 }
 
@@ -1791,6 +1847,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
         bind(ex.get());
+        bind_multi_tail(ex.get());
         if (!ex->launches64.empty()) {
             HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));

@@ -158,6 +158,16 @@ struct FinalizeArgs {
     float* amp_out;                // 2 * n_terms
 };
 void launch_finalize(const FinalizeArgs& f, hipStream_t s);
+// packed circuits: one launch; d_block0[i] = first block of circuit i (256 terms per block)
+void launch_finalize_multi(const FinalizeArgs* d_args, const int64_t* d_block0, int n_plans, int64_t blocks,
+                           hipStream_t s);
+struct LevelSumJob {               // one (circuit, level) block of a packed level-sum launch
+    const double* x;
+    const int64_t* starts;
+    double* out;
+    int32_t u, pad_;
+};
+void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s);
 
 // Neumaier level sums over contiguous ranges [start[u], start[u+1]).
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,

@@ -200,6 +200,42 @@ void k_gemm_mfma(GemmArgs g) {
 // column / inner bits come from small LDS tables; the high parts are added
 // once per tile and per k chunk.
 // ---------------------------------------------------------------------------
+// Device-memory (global address space) views of pointers read from job
+// descriptors: generic pointers would compile to flat loads, which count on
+// the LDS wait counter as well, so every LDS wait would also wait for the
+// global prefetch in flight.
+#define TN_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const TN_GLOBAL T* gload(const void* p) {
+    return (const TN_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ TN_GLOBAL T* gstore(void* p) {
+    return (TN_GLOBAL T*)p;
+}
+// element loads from global views (HIP's vector types do not copy across
+// address spaces): one 8-byte load for complex64, two for complex128
+__device__ __forceinline__ float2 gld(const TN_GLOBAL float2* p) {
+    const uint64_t u = *(const TN_GLOBAL uint64_t*)p;
+    float2 r;
+    __builtin_memcpy(&r, &u, 8);
+    return r;
+}
+__device__ __forceinline__ double2 gld(const TN_GLOBAL double2* p) {
+    const TN_GLOBAL double* q = (const TN_GLOBAL double*)p;
+    return make_double2(q[0], q[1]);
+}
+__device__ __forceinline__ void gst(TN_GLOBAL float2* p, float2 v) {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    *(TN_GLOBAL uint64_t*)p = u;
+}
+__device__ __forceinline__ void gst(TN_GLOBAL double2* p, double2 v) {
+    TN_GLOBAL double* q = (TN_GLOBAL double*)p;
+    q[0] = v.x;
+    q[1] = v.y;
+}
+
 __device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int lo, int hi) {
     int64_t o = 0;
     for (int j = lo; j < hi; ++j)
@@ -393,6 +429,9 @@ void k_gemm_mfma_g(GemmArgs g) {
 #ifndef MFMA_GROUP_BKC
 #define MFMA_GROUP_BKC 8
 #endif
+#ifndef MFMA_GROUP_SCHED
+#define MFMA_GROUP_SCHED 1
+#endif
 // Grouped matrix-core contractions (FP32 complex on mfma_f32_32x32x2f32, the
 // real embedding of K1).  One block per tile descriptor; the tile's row and
 // column offsets (A / B element offsets, C row / column offsets, -1 = padding)
@@ -438,14 +477,14 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             const int seg = i >> m_log;
             const int64_t r = i & (m - 1);
             if (seg < T.cnt) {
-                ra = J.oa[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
-                rc = J.oc[T.s0 + seg] + r * n;
+                ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
+                rc = gload<int64_t>(J.oc)[T.s0 + seg] + r * n;
             }
         } else {
             const int64_t r = T.tm0 + i;
             if (r < m) {
-                ra = J.oa[T.s0] + deposit(r, J.a_row, 0, m_log);
-                rc = (J.merge == 1 ? 0 : J.oc[T.s0]) + r * n;
+                ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
+                rc = (J.merge == 1 ? 0 : gload<int64_t>(J.oc)[T.s0]) + r * n;
             }
         }
         row_a[i] = ra;
@@ -457,13 +496,13 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             const int seg = j >> n_log;
             const int64_t c = j & (n - 1);
             if (seg < T.cnt) {
-                cb = J.ob[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
-                cc = J.oc[T.s0 + seg] + c;
+                cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
+                cc = gload<int64_t>(J.oc)[T.s0 + seg] + c;
             }
         } else {
             const int64_t c = T.tn0 + j;
             if (c < n) {
-                cb = J.ob[T.s0] + deposit(c, J.b_col, 0, n_log);
+                cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
                 cc = c;
             }
         }
@@ -477,9 +516,9 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     chunk_steps(J.a_k, kc_log, k_log, a_step);
     chunk_steps(J.b_k, kc_log, k_log, b_step);
     __syncthreads();
-    const float2* __restrict__ A = (const float2*)J.A;
-    const float2* __restrict__ B = (const float2*)J.B;
-    float* __restrict__ C = (float*)J.C;
+    const TN_GLOBAL float2* __restrict__ A = gload<float2>(J.A);
+    const TN_GLOBAL float2* __restrict__ B = gload<float2>(J.B);
+    TN_GLOBAL float* __restrict__ C = gstore<float>(J.C);
     const bool a_rowfast = J.a_rowfast, b_colfast = J.b_colfast;
 
     const int lane = threadIdx.x & 63;
@@ -524,26 +563,34 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     int64_t kchunk = c_begin;
     int64_t akh = deposit(c_begin << kc_log, J.a_k, kc_log, k_log);
     int64_t bkh = deposit(c_begin << kc_log, J.b_k, kc_log, k_log);
+    // offsets of this thread's staged elements inside a chunk (fixed over the
+    // chunks; -1 = padding, loaded from element 0 and replaced by zero)
+    int64_t aoff[AE], boff[BE];
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+        int r, p;
+        a_rp(threadIdx.x + q * NT, r, p);
+        const int64_t base = row_a[r];
+        aoff[q] = (base >= 0 && p < kc) ? base + ak_lo[p] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+        const int e = threadIdx.x + q * NT;
+        boff[q] = -1;
+        if (e < BKC * BNC) {
+            int p, c;
+            b_pc(e, p, c);
+            const int64_t base = col_b[c];
+            if (base >= 0 && p < kc) boff[q] = base + bk_lo[p];
+        }
+    }
+    // raw loads (padding lanes read element 0); padding is zeroed when staged,
+    // so nothing waits on a load before the chunk's MFMAs
     auto load = [&](int64_t, float2* ra, float2* rb) {
 #pragma unroll
-        for (int q = 0; q < AE; ++q) {
-            int r, p;
-            a_rp(threadIdx.x + q * NT, r, p);
-            const int64_t base = row_a[r];
-            ra[q] = (base >= 0 && p < kc) ? A[base + ak_lo[p] + akh] : make_float2(0.0f, 0.0f);
-        }
+        for (int q = 0; q < AE; ++q) ra[q] = gld(A + (aoff[q] >= 0 ? aoff[q] + akh : 0));
 #pragma unroll
-        for (int q = 0; q < BE; ++q) {
-            const int e = threadIdx.x + q * NT;
-            float2 v = make_float2(0.0f, 0.0f);
-            if (e < BKC * BNC) {
-                int p, c;
-                b_pc(e, p, c);
-                const int64_t base = col_b[c];
-                if (base >= 0 && p < kc) v = B[base + bk_lo[p] + bkh];
-            }
-            rb[q] = v;
-        }
+        for (int q = 0; q < BE; ++q) rb[q] = gld(B + (boff[q] >= 0 ? boff[q] + bkh : 0));
         const int t = __builtin_ctzll(~(uint64_t)kchunk);
         if (t < k_log - kc_log) {
             akh += a_step[t];
@@ -558,8 +605,9 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         for (int q = 0; q < AE; ++q) {
             int r, p;
             a_rp(threadIdx.x + q * NT, r, p);
-            as[p * AP + r] = ra[q].x;
-            as[AH + p * AP + r] = ra[q].y;
+            const bool ok = aoff[q] >= 0;
+            as[p * AP + r] = ok ? ra[q].x : 0.0f;
+            as[AH + p * AP + r] = ok ? ra[q].y : 0.0f;
         }
 #pragma unroll
         for (int q = 0; q < BE; ++q) {
@@ -567,8 +615,9 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             if (e < BKC * BNC) {
                 int p, c;
                 b_pc(e, p, c);
-                *(float2*)&bs[p * BP + 2 * c] = rb[q];
-                *(float2*)&bs[BH + p * BP + 2 * c] = make_float2(-rb[q].y, rb[q].x);
+                const float2 v = boff[q] >= 0 ? rb[q] : make_float2(0.0f, 0.0f);
+                *(float2*)&bs[p * BP + 2 * c] = v;
+                *(float2*)&bs[BH + p * BP + 2 * c] = make_float2(-v.y, v.x);
             }
         }
     };
@@ -581,29 +630,36 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     auto compute = [&](int buf) {
         const float* as = As + buf * ABUF;
         const float* bs = Bs + buf * BBUF;
-        float a[2][TM], b[2][TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) a[0][i] = as[a_off[i]];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) b[0][j] = bs[b_off[j]];
+        // all operands of the chunk read first, so the LDS reads of later inner
+        // indices are in flight while the MFMAs of earlier ones run
+        float a[BKC][TM], b[BKC][TN];
 #pragma unroll
         for (int p = 0; p < BKC; ++p) {
-            const int cur = p & 1;
-            if (p + 1 < BKC) {
 #pragma unroll
-                for (int i = 0; i < TM; ++i) a[cur ^ 1][i] = as[(p + 1) * AP + a_off[i]];
+            for (int i = 0; i < TM; ++i) a[p][i] = as[p * AP + a_off[i]];
 #pragma unroll
-                for (int j = 0; j < TN; ++j) b[cur ^ 1][j] = bs[(p + 1) * BP + b_off[j]];
-            }
+            for (int j = 0; j < TN; ++j) b[p][j] = bs[p * BP + b_off[j]];
+        }
+#pragma unroll
+        for (int p = 0; p < BKC; ++p)
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][j], acc[i][j], 0, 0, 0);
+        // keep the reads ahead of the MFMAs: DS reads of inner index p + 1 are
+        // scheduled before the MFMAs of inner index p
+#if MFMA_GROUP_SCHED
+        __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+#pragma unroll
+        for (int p = 0; p < BKC; ++p) {
+            if (p + 1 < BKC) __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
         }
+#endif
     };
-    // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
     const int64_t nchunks = c_end - c_begin;
+    // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
     float2 ra[AE], rb[BE];
     load(0, ra, rb);
     stash(0, ra, rb);
@@ -615,10 +671,11 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         if (ch + 1 < nchunks) stash(buf ^ 1, ra, rb);
         __syncthreads();
     }
+
     if (J.ksplit == 2) {
         // partial tile in the accumulators' own layout (coalesced per lane)
         constexpr int64_t PT = int64_t(BM) * BNC * 2;
-        float* mine = (float*)J.partial + ((int64_t)T.pair * 2 + T.kpart) * PT;
+        TN_GLOBAL float* mine = gstore<float>(J.partial) + ((int64_t)T.pair * 2 + T.kpart) * PT;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -634,7 +691,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         if (arrived == 0) return;           // the other half finishes the tile
         if (threadIdx.x == 0) J.counters[T.pair] = 0;
         __threadfence();
-        const float* other = (const float*)J.partial + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
+        const TN_GLOBAL float* other = gload<float>(J.partial) + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -707,8 +764,8 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
         const int64_t inst = o >> mn_log;
         const int64_t rc = o & ((int64_t(1) << mn_log) - 1);
         const int64_t r = rc >> n_log, c = rc & ((int64_t(1) << n_log) - 1);
-        const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r, J.a_row, 0, m_log);
-        const C2* __restrict__ Bp = (const C2*)J.B + J.ob[inst] + deposit(c, J.b_col, 0, n_log);
+        const TN_GLOBAL C2* __restrict__ Ap = gload<C2>(J.A) + gload<int64_t>(J.oa)[inst] + deposit(r, J.a_row, 0, m_log);
+        const TN_GLOBAL C2* __restrict__ Bp = gload<C2>(J.B) + gload<int64_t>(J.ob)[inst] + deposit(c, J.b_col, 0, n_log);
         R sr = 0, si = 0;
         if ((int)threadIdx.x < kc) {
             const int64_t alo = ak_lo[threadIdx.x], blo = bk_lo[threadIdx.x];
@@ -723,8 +780,8 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (u < step) {
-                        a[u] = Ap[ah];
-                        b[u] = Bp[bh];
+                        a[u] = gld(Ap + ah);
+                        b[u] = gld(Bp + bh);
                         const int t = __builtin_ctzll(~(uint64_t)(h0 + u));
                         if (t < nstep) {
                             ah += a_step[t];
@@ -753,7 +810,7 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
             C2 out;
             out.x = (R)red_r[0];
             out.y = (R)red_i[0];
-            ((C2*)J.C)[o] = out;
+            gst(gstore<C2>(J.C) + o, out);
         }
         return;
     }
@@ -770,8 +827,8 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
     const int64_t rg = rest & ((int64_t(1) << (m_log - rpt_log)) - 1);
     const int64_t inst = rest >> (m_log - rpt_log);
     const int64_t r0 = rg << rpt_log;
-    const C2* __restrict__ Ap = (const C2*)J.A + J.oa[inst] + deposit(r0, J.a_row, 0, m_log);
-    const C2* __restrict__ Bp = (const C2*)J.B + J.ob[inst] + deposit(c, J.b_col, 0, n_log);
+    const TN_GLOBAL C2* __restrict__ Ap = gload<C2>(J.A) + gload<int64_t>(J.oa)[inst] + deposit(r0, J.a_row, 0, m_log);
+    const TN_GLOBAL C2* __restrict__ Bp = gload<C2>(J.B) + gload<int64_t>(J.ob)[inst] + deposit(c, J.b_col, 0, n_log);
     int64_t rlo[RMAX];
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) rlo[i] = i < rpt ? deposit(i, J.a_row, 0, rpt_log) : 0;
@@ -780,8 +837,8 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
     for (int i = 0; i < RMAX; ++i) sr[i] = si[i] = 0;
     int64_t ahh = 0, bhh = 0;
     for (int64_t h = 0; h < k; h += kc) {
-        const C2* __restrict__ Ah = Ap + ahh;
-        const C2* __restrict__ Bh = Bp + bhh;
+        const TN_GLOBAL C2* __restrict__ Ah = Ap + ahh;
+        const TN_GLOBAL C2* __restrict__ Bh = Bp + bhh;
         {
             const int t = __builtin_ctzll(~(uint64_t)(h >> kc_log));
             if (t < nstep) {
@@ -795,8 +852,8 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
                 C2 a[4], b[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    a[u] = Ah[ak_lo[p + u]];
-                    b[u] = Bh[bk_lo[p + u]];
+                    a[u] = gld(Ah + ak_lo[p + u]);
+                    b[u] = gld(Bh + bk_lo[p + u]);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -806,12 +863,12 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
             }
         } else {
             for (int p = 0; p < kc; ++p) {
-                const C2 b = Bh[bk_lo[p]];
+                const C2 b = gld(Bh + bk_lo[p]);
                 const int64_t ap = ak_lo[p];
                 C2 a[RMAX];
 #pragma unroll
                 for (int i = 0; i < RMAX; ++i)
-                    if (i < rpt) a[i] = Ah[rlo[i] + ap];
+                    if (i < rpt) a[i] = gld(Ah + (rlo[i] + ap));
 #pragma unroll
                 for (int i = 0; i < RMAX; ++i)
                     if (i < rpt) {
@@ -821,14 +878,14 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
             }
         }
     }
-    C2* __restrict__ Cp = (C2*)J.C + ((inst << mn_log) + (r0 << n_log) + c);
+    TN_GLOBAL C2* __restrict__ Cp = gstore<C2>(J.C) + ((inst << mn_log) + (r0 << n_log) + c);
 #pragma unroll
     for (int i = 0; i < RMAX; ++i)
         if (i < rpt) {
             C2 out;
             out.x = sr[i];
             out.y = si[i];
-            Cp[(int64_t)i << n_log] = out;
+            gst(Cp + ((int64_t)i << n_log), out);
         }
 }
 
@@ -982,14 +1039,14 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
             const int seg = i >> m_log;
             const int64_t r = i & (m - 1);
             if (seg < T.cnt) {
-                ra = J.oa[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
-                rc = J.oc[T.s0 + seg] + r * n;
+                ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
+                rc = gload<int64_t>(J.oc)[T.s0 + seg] + r * n;
             }
         } else {
             const int64_t r = T.tm0 + i;
             if (r < m) {
-                ra = J.oa[T.s0] + deposit(r, J.a_row, 0, m_log);
-                rc = (J.merge == 1 ? 0 : J.oc[T.s0]) + r * n;
+                ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
+                rc = (J.merge == 1 ? 0 : gload<int64_t>(J.oc)[T.s0]) + r * n;
             }
         }
         row_a[i] = ra;
@@ -1001,13 +1058,13 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
             const int seg = j >> n_log;
             const int64_t c = j & (n - 1);
             if (seg < T.cnt) {
-                cb = J.ob[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
-                cc = J.oc[T.s0 + seg] + c;
+                cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
+                cc = gload<int64_t>(J.oc)[T.s0 + seg] + c;
             }
         } else {
             const int64_t c = T.tn0 + j;
             if (c < n) {
-                cb = J.ob[T.s0] + deposit(c, J.b_col, 0, n_log);
+                cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
                 cc = c;
             }
         }
@@ -1021,9 +1078,9 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     chunk_steps(J.a_k, kc_log, k_log, a_step);
     chunk_steps(J.b_k, kc_log, k_log, b_step);
     __syncthreads();
-    const double2* __restrict__ A = (const double2*)J.A;
-    const double2* __restrict__ B = (const double2*)J.B;
-    double2* __restrict__ C = (double2*)J.C;
+    const TN_GLOBAL double2* __restrict__ A = gload<double2>(J.A);
+    const TN_GLOBAL double2* __restrict__ B = gload<double2>(J.B);
+    TN_GLOBAL double2* __restrict__ C = gstore<double2>(J.C);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     double accr[4][4], acci[4][4];
 #pragma unroll
@@ -1049,7 +1106,9 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
                 r = e >> BK_LOG;
             }
             const int64_t base = row_a[r];
-            As[p][r] = (base >= 0 && p < kc) ? A[base + ak_lo[p] + akh] : make_double2(0.0, 0.0);
+            double2 va = make_double2(0.0, 0.0);
+            if (base >= 0 && p < kc) va = gld(A + (base + ak_lo[p] + akh));
+            As[p][r] = va;
             int pb, c;
             if (J.b_colfast) {
                 c = e & (BN - 1);
@@ -1059,7 +1118,9 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
                 c = e >> BK_LOG;
             }
             const int64_t bb = col_b[c];
-            Bs[pb][c] = (bb >= 0 && pb < kc) ? B[bb + bk_lo[pb] + bkh] : make_double2(0.0, 0.0);
+            double2 vb = make_double2(0.0, 0.0);
+            if (bb >= 0 && pb < kc) vb = gld(B + (bb + bk_lo[pb] + bkh));
+            Bs[pb][c] = vb;
         }
         {
             const int t = __builtin_ctzll(~(uint64_t)ch);
@@ -1089,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     if (J.ksplit == 2) {
         // partial tile, 32 doubles per thread, thread-fastest
         constexpr int64_t PT = 64 * 64 * 2;
-        double* mine = (double*)J.partial + ((int64_t)T.pair * 2 + T.kpart) * PT;
+        TN_GLOBAL double* mine = gstore<double>(J.partial) + ((int64_t)T.pair * 2 + T.kpart) * PT;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1105,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
         if (arrived == 0) return;           // the other half finishes the tile
         if (threadIdx.x == 0) J.counters[T.pair] = 0;
         __threadfence();
-        const double* other = (const double*)J.partial + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
+        const TN_GLOBAL double* other = gload<double>(J.partial) + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1121,7 +1182,7 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t cc = col_c[tx + 16 * j];
-            if (cc >= 0) C[rc + cc] = make_double2(accr[i][j], acci[i][j]);
+            if (cc >= 0) gst(C + (rc + cc), make_double2(accr[i][j], acci[i][j]));
         }
     }
 }
@@ -1241,9 +1302,7 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 // K3: per-term finalize (FP64): amplitude = scalar * prod of cluster values,
 // X = w |amplitude|^2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= f.n_terms) return;
+__device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) {
     const int32_t li = f.live_index[t];
     if (li < 0) {
         f.x_out[t] = 0.0;
@@ -1275,6 +1334,27 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
     f.amp_out[2 * t + 1] = (float)ai;
 }
 
+__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < f.n_terms) finalize_term(f, t);
+}
+
+// All packed circuits in one launch: block b belongs to the circuit whose
+// first block is the largest block0 <= b.
+__global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeArgs* __restrict__ fs,
+                                                        const int64_t* __restrict__ block0, int n) {
+    int lo = 0, hi = n - 1;
+    const int64_t b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const FinalizeArgs f = fs[lo];
+    const int64_t t = (b - block0[lo]) * 256 + threadIdx.x;
+    if (t < f.n_terms) finalize_term(f, t);
+}
+
 // ---------------------------------------------------------------------------
 // K4: Neumaier-compensated level sums in a fixed order (deterministic): each
 // thread sums a fixed strided subset, then pairs (sum, comp) are combined in a
@@ -1287,11 +1367,9 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
     s = t;
 }
 
-__global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_t* starts,
-                                                   double* out) {
+__device__ __forceinline__ void level_sum_block(const double* x, const int64_t* starts, double* out, int u) {
     __shared__ double ss[256];
     __shared__ double cc[256];
-    const int u = blockIdx.x;
     const int64_t b = starts[u], e = starts[u + 1];
     double s = 0.0, c = 0.0;
     for (int64_t i = b + threadIdx.x; i < e; i += 256) neumaier_add(s, c, x[i]);
@@ -1311,6 +1389,16 @@ __global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_
         out[2 * u] = ss[0] + cc[0];
         out[2 * u + 1] = cc[0];
     }
+}
+
+__global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_t* starts, double* out) {
+    level_sum_block(x, starts, out, blockIdx.x);
+}
+
+// One block per (circuit, level) of all packed circuits.
+__global__ __launch_bounds__(256) void k_level_sum_multi(const LevelSumJob* __restrict__ jobs) {
+    const LevelSumJob j = jobs[blockIdx.x];
+    level_sum_block(j.x, j.starts, j.out, j.u);
 }
 
 __global__ void k_slot_fill(SlotFillArgs a) {
@@ -1518,6 +1606,17 @@ void launch_permute_c128(const PermArgs& p, hipStream_t s) { launch_perm<double2
 void launch_finalize(const FinalizeArgs& f, hipStream_t s) {
     if (f.n_terms == 0) return;
     hipLaunchKernelGGL(k_finalize, dim3(grid1(f.n_terms, 256)), dim3(256), 0, s, f);
+}
+
+void launch_finalize_multi(const FinalizeArgs* d_args, const int64_t* d_block0, int n_plans, int64_t blocks,
+                           hipStream_t s) {
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(k_finalize_multi, dim3((unsigned)blocks), dim3(256), 0, s, d_args, d_block0, n_plans);
+}
+
+void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs == 0) return;
+    hipLaunchKernelGGL(k_level_sum_multi, dim3(n_jobs), dim3(256), 0, s, d_jobs);
 }
 
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,

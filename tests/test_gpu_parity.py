@@ -450,3 +450,38 @@ def test_grouped_mfma_kernel_against_numpy(torch, m_log, n_log, k_log, n_slices,
         assert err <= 4e-6 * scale * max(1.0, np.sqrt(1 << k_log) / 4), (rep, err)
     if ksplit == 2:
         assert int(job["counters"].abs().sum().item()) == 0
+
+
+def test_degenerate_cases_against_oracle(torch):
+    """Edge cases of the method: no noise (one term, the noiseless value),
+    level 0 (only the all-dominant term), every level-2 candidate pruned
+    (levels 0-1 contracted, the level-2 sum equals the level-1 sum), and a
+    level above the noise count (clamped, every term, the exact value)."""
+    from oracle import dense
+    print("degenerate cases", flush=True)
+    # no noise
+    c0 = W.tiny_random_circuit(np.random.default_rng(3), 5, 20, 0, noise="adpd", level=0)
+    res, x, pat, _ = run_gpu(c0, 0)
+    assert res["n_terms"] == 1
+    assert abs(res["A"][0] - dense.exact_value(c0)) <= 1e-12
+    # level 0 of C1
+    c1 = W.config(1, level=2)
+    res, x, pat, _ = run_gpu(c1, 0)
+    r = estimate.estimate(c1, 0, "network")
+    assert res["n_terms"] == 1 and abs(res["A"][0] - r["A"][0]) <= 1e-12 * r["A"][0]
+    # all level-2 candidates pruned
+    plan = tn.tn_plan_build(c1, 2)
+    full = tn.tn_terms_enumerate(plan, 2)
+    pat, w = full.get()
+    ncand = int(((pat != 0).sum(axis=1) >= 2).sum())
+    tp = tn.tn_terms_enumerate(plan, 2, keep=np.zeros(ncand, np.uint8), min_level=2)
+    ex = tn.tn_exec_prepare([plan], [tp], tn.exec_opts(use_graph=True))
+    rp = ex.run()[0]
+    r2 = estimate.estimate(c1, 2, "network")
+    assert abs(rp["A"][1] - r2["A"][1]) <= 1e-6 * r2["A"][1]
+    assert rp["A"][2] == rp["A"][1]
+    # level above the noise count: clamped to the full expansion = exact value
+    c3 = W.tiny_random_circuit(np.random.default_rng(8), 4, 14, 2, noise="random", level=5)
+    res, x, pat, _ = run_gpu(c3, 5)
+    assert res["clamped"] and res["level"] == 2
+    assert abs(res["A"][2] - dense.exact_value(c3)) <= 1e-6 * abs(dense.exact_value(c3)) + 1e-12
