@@ -263,6 +263,7 @@ struct Builder {
     Arena work;                // FP32 batch (main stream)
     Arena work2;               // FP64 dominant-term pass (side stream, runs concurrently)
     bool grouping = true;      // small steps of one tree level share one launch
+    bool quantize_tiles = true;  // tile model: whole rounds over the CUs (one circuit)
     std::vector<Ref> node_ref;         // concrete buffer of every node (once placed)
     std::vector<char> node_leaf;
     std::vector<int64_t> node_bytes;
@@ -356,9 +357,10 @@ struct Builder {
     void plan_mfma_job(StepRec& st, const NodeInfo& A, const NodeInfo& B, NodeInfo& C, const std::vector<int>& K,
                        const std::vector<int>& Bt, const std::vector<int>& FA, const std::vector<int>& FB,
                        int64_t ninst, int64_t nbatch, PosIn posin, ByPos by_pos, SliceVec slice_vec, int fp64) {
-        // FP64 steps run on the 64 x 64 FMA tiles (tile id 1's shape)
+        // FP64 steps run on the 64 x 64 or 32 x 32 FMA tiles (tile ids 1 and 4's shapes)
         const int64_t esz = fp64 ? 16 : 8;
         static const double kEff[K_MFMA_TILES] = {1.0, 0.6, 0.75, 0.5, 0.35, 0.45, 0.3, 0.2};
+        static const double kEff64[K_MFMA_TILES] = {0, 1.0, 0, 0, 0.7, 0, 0, 0};
         const int rk = (int)K.size();
         const int64_t ns = ninst * nbatch;
         std::vector<int64_t> so[2][2];
@@ -386,18 +388,21 @@ struct Builder {
             so[o][1] = slice_vec(Q, btb[o]);
             const std::vector<int64_t> ca = run_counts(so[o][0]), cb = run_counts(so[o][1]);
             for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
-                if (fp64 && tile != 1) continue;
+                if (fp64 && tile != 1 && tile != 4) continue;
                 const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
                 const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
                 const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
-                const double per_tile = std::ldexp(1.0, bm_log + bn_log) * (std::ldexp(1.0, rk) + 16.0) / kEff[tile];
+                const double per_tile = std::ldexp(1.0, bm_log + bn_log) * (std::ldexp(1.0, rk) + 16.0) /
+                                        (fp64 ? kEff64[tile] : kEff[tile]);
                 // tiles on one CU share its matrix cores, so a launch lasts as long
-                // as its busiest CU: a job large enough to fill the chip has its
-                // tile count rounded up to whole rounds over the 256 CUs (smaller
-                // jobs share their launch with the level's other jobs)
+                // as its busiest CU.  With one circuit a job mostly has its level to
+                // itself: its tile count is rounded up to whole rounds over the 256
+                // CUs (at least one round, so below 256 tiles smaller tiles finish
+                // sooner).  Packed circuits share each level's launch, so their jobs
+                // are costed by tile work alone.
                 auto consider = [&](int64_t tiles, int merge) {
                     const int64_t eff_tiles =
-                        tiles < kNumCUs ? tiles : ((tiles + kNumCUs - 1) / kNumCUs) * kNumCUs;
+                        !quantize_tiles ? tiles : std::max<int64_t>(1, (tiles + kNumCUs - 1) / kNumCUs) * kNumCUs;
                     const double cst = (double)eff_tiles * per_tile;
                     if (cst < best_cost) {
                         best_cost = cst;
@@ -1155,6 +1160,7 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
     Builder bw;
     bw.ex = ex;
     bw.grouping = ex->opts.no_group == 0;
+    bw.quantize_tiles = n == 1;
     const bool plain = ex->opts.mode == TN_MODE_PLAIN;
     std::vector<StepRec> steps32, steps64;
     for (int pi = 0; pi < n; ++pi) {
@@ -1451,7 +1457,7 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
         break;
     case L_MGROUP:
         if (L.fp64)
-            launch_tile64_group((const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
+            launch_tile64_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
                                 L.n_tiles, s);
         else
             launch_mfma_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),

@@ -109,8 +109,10 @@ struct MfmaTile {                  // one block of a grouped launch
 // tile: an MFMA tile id (0..K_MFMA_TILES-1); one launch per tile shape.
 void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
                        hipStream_t s);
-// FP64 (complex128) on the same descriptors, 64 x 64 tiles (tile id 1's shape).
-void launch_tile64_group(const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles, hipStream_t s);
+// FP64 (complex128) on the same descriptors: 64 x 64 tiles (tile id 1's shape)
+// or 32 x 32 (tile id 4's shape).
+void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                         hipStream_t s);
 int mfma_tile_bm(int tile);
 int mfma_tile_bn(int tile);
 

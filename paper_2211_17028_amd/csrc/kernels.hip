@@ -1013,13 +1013,17 @@ __global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
 
 // ---------------------------------------------------------------------------
 // Grouped FP64 tiles (complex128 FMA): the descriptors of the grouped
-// matrix-core launch (merge modes, slice tables, per-bit positions) on 64 x 64
-// output tiles; 256 threads, 4 x 4 outputs each, inner chunks of 8 staged in
-// LDS through the tile's row / column offset tables.
+// matrix-core launch (merge modes, slice tables, per-bit positions) on
+// 16TT x 16TT output tiles (TT = 4: 64 x 64; TT = 2: 32 x 32, four times the tiles
+// for jobs that would leave CUs idle); 256 threads, TT x TT outputs each, inner
+// chunks of 8 staged in LDS through the tile's row / column offset tables.
 // ---------------------------------------------------------------------------
+template <int TT>
 __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict__ jobs,
                                                       const MfmaTile* __restrict__ tiles) {
-    constexpr int BM = 64, BN = 64, BK = 8, BK_LOG = 3;
+    constexpr int BM = 16 * TT, BN = 16 * TT, BK = 8, BK_LOG = 3;
+    constexpr int BM_LOG = __builtin_ctz(BM), BN_LOG = __builtin_ctz(BN);
+    constexpr int SE = (BM * BK + 255) / 256;   // staged elements per thread and operand
     // +2 elements per row: k-fast staging writes of 16 lanes fall in distinct banks
     __shared__ double2 As[BK][BM + 2];
     __shared__ double2 Bs[BK][BN + 2];
@@ -1082,25 +1086,26 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     const TN_GLOBAL double2* __restrict__ B = gload<double2>(J.B);
     TN_GLOBAL double2* __restrict__ C = gstore<double2>(J.C);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double accr[4][4], acci[4][4];
+    double accr[TT][TT], acci[TT][TT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0;
+        for (int j = 0; j < TT; ++j) accr[i][j] = acci[i][j] = 0.0;
     const int64_t nch_all = k >= BK ? k / BK : 1;
     const int64_t c_begin = (J.ksplit == 2 && T.kpart) ? nch_all / 2 : 0;
     const int64_t c_end = (J.ksplit == 2 && !T.kpart) ? nch_all / 2 : nch_all;
     int64_t akh = deposit(c_begin << kc_log, J.a_k, kc_log, k_log);
     int64_t bkh = deposit(c_begin << kc_log, J.b_k, kc_log, k_log);
     for (int64_t ch = c_begin; ch < c_end; ++ch) {
-        // staging: 2 A and 2 B elements per thread (row or column fast as stored)
+        // staging: SE A and SE B elements per thread (row or column fast as stored)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < SE; ++q) {
             const int e = threadIdx.x + q * 256;
+            if (e >= BM * BK) break;
             int r, p;
             if (J.a_rowfast) {
                 r = e & (BM - 1);
-                p = e >> 6;
+                p = e >> BM_LOG;
             } else {
                 p = e & (BK - 1);
                 r = e >> BK_LOG;
@@ -1112,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
             int pb, c;
             if (J.b_colfast) {
                 c = e & (BN - 1);
-                pb = e >> 6;
+                pb = e >> BN_LOG;
             } else {
                 pb = e & (BK - 1);
                 c = e >> BK_LOG;
@@ -1132,15 +1137,15 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < BK; ++p) {
-            double2 a[4], b[4];
+            double2 a[TT], b[TT];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[p][ty + 16 * i];
+            for (int i = 0; i < TT; ++i) a[i] = As[p][ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[p][tx + 16 * j];
+            for (int j = 0; j < TT; ++j) b[j] = Bs[p][tx + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TT; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < TT; ++j) {
                     accr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
                     acci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
                 }
@@ -1148,15 +1153,15 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
         __syncthreads();
     }
     if (J.ksplit == 2) {
-        // partial tile, 32 doubles per thread, thread-fastest
-        constexpr int64_t PT = 64 * 64 * 2;
+        // partial tile, 2 TT^2 doubles per thread, thread-fastest
+        constexpr int64_t PT = int64_t(BM) * BN * 2;
         TN_GLOBAL double* mine = gstore<double>(J.partial) + ((int64_t)T.pair * 2 + T.kpart) * PT;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TT; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                mine[(i * 4 + j) * 256 + threadIdx.x] = accr[i][j];
-                mine[(16 + i * 4 + j) * 256 + threadIdx.x] = acci[i][j];
+            for (int j = 0; j < TT; ++j) {
+                mine[(i * TT + j) * 256 + threadIdx.x] = accr[i][j];
+                mine[(TT * TT + i * TT + j) * 256 + threadIdx.x] = acci[i][j];
             }
         __threadfence();
         __syncthreads();
@@ -1168,28 +1173,32 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
         __threadfence();
         const TN_GLOBAL double* other = gload<double>(J.partial) + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TT; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                accr[i][j] += other[(i * 4 + j) * 256 + threadIdx.x];
-                acci[i][j] += other[(16 + i * 4 + j) * 256 + threadIdx.x];
+            for (int j = 0; j < TT; ++j) {
+                accr[i][j] += other[(i * TT + j) * 256 + threadIdx.x];
+                acci[i][j] += other[(TT * TT + i * TT + j) * 256 + threadIdx.x];
             }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TT; ++i) {
         const int64_t rc = row_c[ty + 16 * i];
         if (rc < 0) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TT; ++j) {
             const int64_t cc = col_c[tx + 16 * j];
             if (cc >= 0) gst(C + (rc + cc), make_double2(accr[i][j], acci[i][j]));
         }
     }
 }
 
-void launch_tile64_group(const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles, hipStream_t s) {
+void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                         hipStream_t s) {
     if (n_tiles == 0) return;
-    hipLaunchKernelGGL(k_tile64_group, dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+    if (tile == 4)
+        hipLaunchKernelGGL((k_tile64_group<2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+    else
+        hipLaunchKernelGGL((k_tile64_group<4>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
 }
 
 // ---------------------------------------------------------------------------
