@@ -129,6 +129,8 @@ typedef struct {
                                 letting MFMA steps read them in stored order */
     int32_t no_group;        /* 1 = one launch per contraction step instead of one grouped
                                 launch for the small steps of each tree level */
+    int32_t max_ksplit;      /* largest number of blocks one tile's inner sum is split
+                                over (0 = default 16, 1 = no split, at most 32) */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs

@@ -30,12 +30,21 @@
  *   0: one slice per tile (origin tm0, tn0).  Jobs and tiles are device
  *   arrays in the tn_mfma_job / tn_mfma_tile layouts; `tile` selects the tile
  *   shape (0..7: 128x64, 64x64, 128x32, 64x32, 32x32, 128x16, 64x16, 32x16).
- *   ksplit = 2 splits each tile's inner sum over a pair of tiles (kpart 0 and
- *   1, same pair index): the partial tiles go to `partial` (2 * BM * BNC
- *   complex64 per pair) and are added in the order half 0 + half 1 by the
- *   second block of the pair, so results are the same run to run; `counters`
- *   must be zero before the launch and is zero again after it.
+ *   ksplit = S (a power of two dividing the job's count of 8-term inner chunks,
+ *   at most the tile's row count; 1 = no split) splits each tile's inner sum
+ *   over S tiles (kpart 0..S-1, same group index `pair`, listed S in a row):
+ *   each writes its partial tile, row-major BM x BNC complex64, to
+ *   partial + (pair * S + kpart) * BM * BNC (padding elements skipped), and
+ *   C is written by tn_kernel_mfma_split_reduce on the same lists afterwards.
  *   Asynchronous on `stream`.  Returns 0 or a negative TN_E* code.
+ *
+ * tn_kernel_mfma_split_reduce: for every tile group of a split job in the
+ *   lists of a preceding tn_kernel_mfma_group launch (same `tile`, jobs and
+ *   tiles; enqueue it after that launch on the same stream), adds the S
+ *   partial tiles in part order 0, 1, ..., S-1 (so results are the same run to
+ *   run) and writes the job's C.  fp64 = 1 for complex128 partials and output
+ *   (the library's FP64 tiles), 0 for complex64.  Tiles of unsplit jobs are
+ *   skipped.  Asynchronous on `stream`.  Returns 0 or a negative TN_E* code.
  */
 typedef struct {
     const void* A;
@@ -48,14 +57,13 @@ typedef struct {
     int32_t merge;
     int32_t a_rowfast, b_colfast;  /* lowest stored bit of A is a row bit / of B a column bit */
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
-    int32_t ksplit, pad_;          /* 2: tiles come in pairs over the two halves of the inner index */
-    void* partial;                 /* ksplit 2: 2 partial tiles per pair (device scratch) */
-    int32_t* counters;             /* ksplit 2: one zero-initialised int per pair (reset by the kernel) */
+    int32_t ksplit, pad_;          /* S >= 1: tiles come in groups of S over S parts of the inner index */
+    void* partial;                 /* ksplit > 1: S partial tiles per group (device scratch) */
 } tn_mfma_job;
 typedef struct {
     int32_t job, cnt;
     int64_t s0, tm0, tn0;
-    int32_t kpart, pair;           /* ksplit 2: inner half (0/1) and pair index */
+    int32_t kpart, pair;           /* ksplit > 1: inner part (0..S-1) and group index */
 } tn_mfma_tile;
 #ifndef TN_KERNELS_H
 #define TN_KERNELS_H
@@ -71,6 +79,8 @@ int tn_kernel_permute(int32_t fp64, const void* src, void* dst, int64_t n_inst, 
                       const int32_t* perm, int32_t block_elems_log, void* stream);
 int tn_kernel_mfma_group(int32_t tile, const tn_mfma_job* d_jobs, const tn_mfma_tile* d_tiles,
                          int64_t n_tiles, void* stream);
+int tn_kernel_mfma_split_reduce(int32_t tile, int32_t fp64, const tn_mfma_job* d_jobs,
+                                const tn_mfma_tile* d_tiles, int64_t n_tiles, void* stream);
 #ifdef __cplusplus
 }
 #endif

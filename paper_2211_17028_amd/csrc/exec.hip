@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <climits>
 #include <memory>
 #include <sstream>
 #include <tuple>
@@ -99,13 +100,14 @@ struct Ref {
 };
 
 enum LaunchKind { L_PERM = 0, L_GEMM = 1, L_FINALIZE = 2, L_LEVELSUM = 3, L_SLOTFILL = 4, L_GROUP = 5,
-                  L_MGROUP = 6 };
+                  L_MGROUP = 6, L_MREDUCE = 7 };
 struct GroupJob;
 struct MJob;
 
 struct Launch {
     int kind = 0;
     int fp64 = 0;
+    int level = -1;                // tree level of a level-grouped launch (-1: none)
     // operands (resolved at bind time)
     Ref a, b, c, ia, ib, table;
     GemmArgs g{};
@@ -131,7 +133,8 @@ struct Launch {
     int n_jobs = 0;
     int64_t blocks = 0;
     std::vector<struct GroupJob> hjobs;
-    // grouped matrix-core launch (L_MGROUP)
+    // grouped matrix-core launch (L_MGROUP); L_MREDUCE shares its job and tile
+    // records (written by the L_MGROUP launch it follows)
     int mtile = 0;
     Ref tiles;
     int64_t n_tiles = 0;
@@ -213,11 +216,15 @@ constexpr double kMfmaMinFlops = 16.0 * 1024 * 1024;
 constexpr int64_t kNumCUs = 256;     // MI355X compute units
 // Below this many flops a step that fills a tile still joins the small-step launch.
 constexpr double kTileMinFlops = 2.0 * 1024 * 1024;
-// A tile job splits its inner sum over two blocks when the sum has at least
-// 2^kSplitMinKLog terms and the doubled tiles leave at most two per CU (more
-// tiles per CU already keep the matrix cores busy through the inner loop).
+// A tile job splits its inner sum over S blocks (S a power of two) when the
+// sum has at least 2^kSplitMinKLog terms and the multiplied tiles leave at
+// most two per CU (more tiles per CU already keep the matrix cores busy
+// through the inner loop); S grows while that holds, each part keeps at least
+// 2^kSplitMinPartLog terms and S stays within the executor's limit.
 constexpr int kSplitMinKLog = 6;
+constexpr int kSplitMinPartLog = 5;
 constexpr int64_t kSplitMaxTiles = 512;
+constexpr int kSplitDefaultMax = 16;
 
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
@@ -233,10 +240,11 @@ struct MJob {
     Ref a, b, c, oa, ob, oc;
     int m_log = 0, n_log = 0, k_log = 0, merge = 0, a_rowfast = 0, b_colfast = 0;
     int ksplit = 1;
-    Ref partial, counters;     // ksplit 2: partial tiles (work region) and pair counters (zeroed constants)
+    Ref partial;               // ksplit > 1: partial tiles (work region)
     int64_t ns = 0;            // slices
     int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
     double flops = 0, bytes = 0;
+    double out_bytes = 0;      // bytes of C (the split reduction's unit)
 };
 
 // One pairwise step before memory assignment.
@@ -264,6 +272,7 @@ struct Builder {
     Arena work2;               // FP64 dominant-term pass (side stream, runs concurrently)
     bool grouping = true;      // small steps of one tree level share one launch
     bool quantize_tiles = true;  // tile model: whole rounds over the CUs (one circuit)
+    int max_ksplit = kSplitDefaultMax;  // largest split of a tile job's inner sum (1 = none)
     std::vector<Ref> node_ref;         // concrete buffer of every node (once placed)
     std::vector<char> node_leaf;
     std::vector<int64_t> node_bytes;
@@ -503,27 +512,31 @@ struct Builder {
             }
         }
         // Latency-bound jobs (long inner sums, few tiles: every tile resident at
-        // once even when doubled) split the inner sum over a pair of tiles.
+        // once even when multiplied) split the inner sum over S tiles.
         const int64_t nt = (int64_t)st.mtiles.size();
-        if (rk >= kSplitMinKLog && 2 * nt <= kSplitMaxTiles) {
-            std::vector<MfmaTile> two;
-            two.reserve(2 * nt);
+        int split = 1;
+        if (rk >= kSplitMinKLog)
+            while (2 * split <= max_ksplit && 2 * split * nt <= kSplitMaxTiles &&
+                   rk - __builtin_ctz(2 * split) >= kSplitMinPartLog)
+                split *= 2;
+        if (split > 1) {
+            std::vector<MfmaTile> parts;
+            parts.reserve(split * nt);
             for (int64_t q = 0; q < nt; ++q)
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < split; ++h) {
                     MfmaTile t = st.mtiles[q];
                     t.kpart = h;
                     t.pair = (int32_t)q;
-                    two.push_back(t);
+                    parts.push_back(t);
                 }
-            st.mtiles.swap(two);
-            jb.ksplit = 2;
-            const int64_t pbytes = nt * 2 * (int64_t)bm * bn * 2 * (fp64 ? 8 : 4);
+            st.mtiles.swap(parts);
+            jb.ksplit = split;
+            const int64_t pbytes = nt * split * (int64_t)bm * bn * 2 * (fp64 ? 8 : 4);
             const int tid = (int)temp_ref.size();
             temp_ref.push_back(Ref{});
             st.temp_ids.push_back(tid);
             st.temp_bytes.push_back(pbytes);
             jb.partial = Ref{R_TEMP, tid};
-            jb.counters = Ref{R_CONST, ex->cbuf.reserve(nt * 4)};
         }
         jb.a = R.buf;
         jb.b = Q.buf;
@@ -533,6 +546,7 @@ struct Builder {
         jb.oc = Ref{R_CONST, ex->cbuf.add(soc.data(), ns * 8)};
         const double mm = std::ldexp(1.0, jb.m_log), nnn = std::ldexp(1.0, jb.n_log), kk = std::ldexp(1.0, rk);
         jb.flops = 8.0 * mm * nnn * kk * (double)ns;
+        jb.out_bytes = (double)esz * mm * nnn * (double)ns;
         jb.bytes = (double)esz * ((double)ns * mm * nnn + (double)R.keys.size() * nbatch * mm * kk +
                                   (double)Q.keys.size() * nbatch * kk * nnn);
         st.mgrouped = true;
@@ -1048,8 +1062,10 @@ struct Builder {
         } else {
             for (size_t i = 0; i < steps.size(); ++i) groups.push_back({(int)i});
         }
-        for (auto& grp : groups) {
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const std::vector<int>& grp = groups[gi];
             if (grp.empty()) continue;
+            const size_t first_launch = out->size();
             for (int i : grp) {
                 StepRec& st = steps[i];
                 node_ref[st.c_node] = st.has_fixed ? st.c_fixed : Ref{wreg, wk.alloc(st.c_bytes)};
@@ -1118,7 +1134,26 @@ struct Builder {
                 M.tiles = Ref{R_CONST, ex->cbuf.add(tl.data(), M.n_tiles * (int64_t)sizeof(MfmaTile))};
                 M.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)M.mjobs.size() * (int64_t)sizeof(MfmaJob))};
                 M.n_jobs = (int)M.mjobs.size();
+                double split_bytes = 0;
+                for (const MJob& jb : M.mjobs)
+                    if (jb.ksplit > 1)    // partial tiles read, outputs written
+                        split_bytes += (double)jb.ksplit * jb.out_bytes + jb.out_bytes;
+                Launch R;
+                if (split_bytes > 0) {
+                    R.kind = L_MREDUCE;
+                    R.fp64 = fp64;
+                    R.mtile = tile;
+                    R.kclass = fp64 ? K_SPLIT_REDUCE64 : K_SPLIT_REDUCE32;
+                    R.plan = M.plan;
+                    R.jobs = M.jobs;
+                    R.tiles = M.tiles;
+                    R.n_tiles = M.n_tiles;
+                    R.n_jobs = M.n_jobs;
+                    R.mjobs = M.mjobs;
+                    R.bytes = split_bytes;
+                }
                 out->push_back(std::move(M));
+                if (split_bytes > 0) out->push_back(std::move(R));
             }
             if (!G.hjobs.empty()) {
                 if (G.blocks >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 blocks");
@@ -1127,6 +1162,8 @@ struct Builder {
                 G.plan = steps[grp[0]].plan;
                 out->push_back(std::move(G));
             }
+            if (by_level)
+                for (size_t q = first_launch; q < out->size(); ++q) (*out)[q].level = (int)gi;
             for (int i : grp) {
                 StepRec& st = steps[i];
                 for (size_t q = 0; q < st.temp_ids.size(); ++q)
@@ -1161,6 +1198,7 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
     bw.ex = ex;
     bw.grouping = ex->opts.no_group == 0;
     bw.quantize_tiles = n == 1;
+    if (ex->opts.max_ksplit > 0) bw.max_ksplit = std::min(ex->opts.max_ksplit, 32);
     const bool plain = ex->opts.mode == TN_MODE_PLAIN;
     std::vector<StepRec> steps32, steps64;
     for (int pi = 0; pi < n; ++pi) {
@@ -1371,8 +1409,7 @@ static void bind(tn_exec_s* ex) {
                 j.a_rowfast = h.a_rowfast;
                 j.b_colfast = h.b_colfast;
                 j.ksplit = h.ksplit;
-                j.partial = h.ksplit == 2 ? resolve(ex, h.partial) : nullptr;
-                j.counters = h.ksplit == 2 ? (int32_t*)resolve(ex, h.counters) : nullptr;
+                j.partial = h.ksplit > 1 ? resolve(ex, h.partial) : nullptr;
                 std::memcpy(j.a_row, h.a_row, 32);
                 std::memcpy(j.a_k, h.a_k, 32);
                 std::memcpy(j.b_k, h.b_k, 32);
@@ -1463,6 +1500,10 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
             launch_mfma_group(L.mtile, (const MfmaJob*)resolve(ex, L.jobs), (const MfmaTile*)resolve(ex, L.tiles),
                               L.n_tiles, s);
         break;
+    case L_MREDUCE:
+        launch_split_reduce(L.fp64, L.mtile, (const MfmaJob*)resolve(ex, L.jobs),
+                            (const MfmaTile*)resolve(ex, L.tiles), L.n_tiles, s);
+        break;
     case L_FINALIZE:
         launch_finalize(L.f, s);
         break;
@@ -1477,22 +1518,31 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
 }
 
 static void run_body(tn_exec_s* ex, hipStream_t s) {
-    // the FP64 pass forks onto the side stream and joins before the finalize
+    // The FP64 pass forks onto the side stream and joins before the finalize.
+    // Launches are issued level by level, alternating between the two chains
+    // (the FP32 chain first at each level), so that neither waits for the
+    // other's whole chain to be issued (a captured graph keeps this order).
     const bool side = !ex->launches64.empty();
     if (side) {
         HIPCHK(hipEventRecord(ex->ev_fork, s));
         HIPCHK(hipStreamWaitEvent(ex->side, ex->ev_fork, 0));
-        for (auto& L : ex->launches64) {
-            if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, ex->side));
-            enqueue(ex, L, ex->side);
-            if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, ex->side));
-        }
-        HIPCHK(hipEventRecord(ex->ev_join, ex->side));
     }
-    for (auto& L : ex->launches) {
-        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, s));
-        enqueue(ex, L, s);
-        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, s));
+    auto key = [](const Launch& L) { return L.level >= 0 ? L.level : INT_MAX; };
+    auto issue = [&](Launch& L, hipStream_t st) {
+        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, st));
+        enqueue(ex, L, st);
+        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, st));
+    };
+    std::vector<Launch>& l32 = ex->launches;
+    std::vector<Launch>& l64 = ex->launches64;
+    size_t i32 = 0, i64 = 0;
+    while (i32 < l32.size() || i64 < l64.size()) {
+        if (i64 < l64.size() && (i32 == l32.size() || key(l64[i64]) < key(l32[i32]))) {
+            issue(l64[i64], ex->side);
+            if (++i64 == l64.size()) HIPCHK(hipEventRecord(ex->ev_join, ex->side));
+        } else {
+            issue(l32[i32++], s);
+        }
     }
     if (side) HIPCHK(hipStreamWaitEvent(s, ex->ev_join, 0));
     if (ex->opts.mode == TN_MODE_PLAIN) {
@@ -1629,7 +1679,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
             os << ",\"n\":" << L.sf.n << ",\"noise\":" << L.sf_noise.off << ",\"dst\":" << L.sf_dst.off
                << ",\"bank\":" << L.sf_bank.off << ",\"pattern\":" << L.sf_pattern.off
                << ",\"n_noise\":" << L.sf.n_noise;
-        if (L.kind == L_MGROUP) {
+        if (L.kind == L_MGROUP || L.kind == L_MREDUCE) {
             os << ",\"kernel\":\"" << kernel_name(L.kclass) << "\",\"bm\":" << mfma_tile_bm(L.mtile)
                << ",\"bn\":" << mfma_tile_bn(L.mtile) << ",\"n_tiles\":" << L.n_tiles << ",\"tiles\":["
                << L.tiles.region << "," << L.tiles.off << "],\"jobs\":[";
@@ -1641,7 +1691,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
                    << h.oc.region << "," << h.oc.off << "],\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log
                    << ",\"k_log\":" << h.k_log << ",\"ns\":" << h.ns << ",\"merge\":" << h.merge
                    << ",\"ksplit\":" << h.ksplit << ",\"partial\":[" << h.partial.region << "," << h.partial.off
-                   << "],\"counters\":[" << h.counters.region << "," << h.counters.off << "]"
+                   << "]"
                    << ",\"a_rowfast\":" << h.a_rowfast
                    << ",\"b_colfast\":" << h.b_colfast;
                 auto arr = [&](const char* nm, const int8_t* v, int n) {
@@ -1863,7 +1913,8 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             for (auto* list : {&ex->launches, &ex->launches64})
                 for (auto& L : *list)
                     if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0) ||
-                        (L.kind == L_GROUP && L.blocks > 0) || (L.kind == L_MGROUP && L.n_tiles > 0)) {
+                        (L.kind == L_GROUP && L.blocks > 0) ||
+                        ((L.kind == L_MGROUP || L.kind == L_MREDUCE) && L.n_tiles > 0)) {
                         HIPCHK(hipEventCreate(&L.ev_a));
                         HIPCHK(hipEventCreate(&L.ev_b));
                     }
@@ -2248,6 +2299,18 @@ extern "C" int tn_kernel_mfma_group(int32_t tile, const tn_mfma_job* d_jobs, con
             tn::fail(TN_EINVAL, "bad grouped launch arguments");
         tn::launch_mfma_group(tile, (const tn::MfmaJob*)d_jobs, (const tn::MfmaTile*)d_tiles, n_tiles,
                               (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+extern "C" int tn_kernel_mfma_split_reduce(int32_t tile, int32_t fp64, const tn_mfma_job* d_jobs,
+                                           const tn_mfma_tile* d_tiles, int64_t n_tiles, void* stream) {
+    return guard([&] {
+        if (tile < 0 || tile >= tn::K_MFMA_TILES || (fp64 != 0 && fp64 != 1) || !d_jobs || !d_tiles ||
+            n_tiles < 0 || n_tiles >= (int64_t(1) << 31))
+            tn::fail(TN_EINVAL, "bad split-reduce launch arguments");
+        tn::launch_split_reduce(fp64, tile, (const tn::MfmaJob*)d_jobs, (const tn::MfmaTile*)d_tiles, n_tiles,
+                                (hipStream_t)stream);
         HIPCHK(hipGetLastError());
     });
 }

@@ -91,20 +91,19 @@ struct MfmaJob {
     int32_t merge;
     int32_t a_rowfast, b_colfast;  // lowest stored bit of A is a row bit / of B a column bit
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
-    // Split inner sums (ksplit = 2): tile pair p runs the two halves of the
-    // inner index in two blocks; each writes its partial tile to
-    // partial[p][half], then counts in counters[p]; the second to arrive adds
-    // the two partials in the fixed order half 0 + half 1 (so the result does
-    // not depend on which arrives first), writes C and resets the counter.
+    // Split inner sums (ksplit = S, a power of two, 1 = none): tile group p
+    // runs S equal parts of the inner index in S blocks; each writes its
+    // partial tile, row-major [BM][BN] complex, to partial[p][part]; the
+    // split-reduce launch that follows adds the S partials in part order
+    // 0, 1, ..., S-1 and writes C (no block waits on another).
     int32_t ksplit, pad_;
     void* partial;
-    int32_t* counters;
 };
 struct MfmaTile {                  // one block of a grouped launch
     int32_t job, cnt;
     int64_t s0;                    // first slice
     int64_t tm0, tn0;              // tile origin inside the slice (unmerged dimensions)
-    int32_t kpart, pair;           // ksplit = 2: inner half and tile-pair index
+    int32_t kpart, pair;           // ksplit > 1: inner part and tile-group index
 };
 // tile: an MFMA tile id (0..K_MFMA_TILES-1); one launch per tile shape.
 void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
@@ -112,6 +111,10 @@ void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles,
 // FP64 (complex128) on the same descriptors: 64 x 64 tiles (tile id 1's shape)
 // or 32 x 32 (tile id 4's shape).
 void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                         hipStream_t s);
+// After a grouped tile launch with split jobs (same job and tile lists, same
+// stream): adds each group's partial tiles in part order and writes C.
+void launch_split_reduce(int fp64, int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
                          hipStream_t s);
 int mfma_tile_bm(int tile);
 int mfma_tile_bn(int tile);
@@ -126,7 +129,7 @@ enum KernelId {
     K_SMALL32 = 10, K_SPLITK32 = 11,
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
-    K_GROUP32 = 40, K_GROUP64 = 41, K_TILE64_GROUP = 42,
+    K_GROUP32 = 40, K_GROUP64 = 41, K_TILE64_GROUP = 42, K_SPLIT_REDUCE32 = 43, K_SPLIT_REDUCE64 = 44,
     K_MFMA_GROUP_BASE = 200,   // + MFMA tile id: grouped matrix-core launch
     K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };

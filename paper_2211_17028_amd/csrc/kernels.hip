@@ -255,6 +255,31 @@ __device__ __forceinline__ void chunk_steps(const int8_t* pos, int lo, int hi, i
     }
 }
 
+// Output offset (element index into C) of row i / column j of a grouped tile,
+// -1 for padding: merge 2 stacks `cnt` slices along the rows, merge 1 along
+// the columns, merge 0 holds one slice at origin (tm0, tn0).  Shared by the
+// tile kernels and the split-sum reduction, so both address the same outputs.
+__device__ __forceinline__ int64_t tile_out_row(const MfmaJob& J, const MfmaTile& T, int i) {
+    const int m_log = J.m_log;
+    const int64_t m = int64_t(1) << m_log, n = int64_t(1) << J.n_log;
+    if (J.merge == 2) {
+        const int seg = i >> m_log;
+        return seg < T.cnt ? gload<int64_t>(J.oc)[T.s0 + seg] + (i & (m - 1)) * n : -1;
+    }
+    const int64_t r = T.tm0 + i;
+    return r < m ? (J.merge == 1 ? 0 : gload<int64_t>(J.oc)[T.s0]) + r * n : -1;
+}
+__device__ __forceinline__ int64_t tile_out_col(const MfmaJob& J, const MfmaTile& T, int j) {
+    const int n_log = J.n_log;
+    const int64_t n = int64_t(1) << n_log;
+    if (J.merge == 1) {
+        const int seg = j >> n_log;
+        return seg < T.cnt ? gload<int64_t>(J.oc)[T.s0 + seg] + (j & (n - 1)) : -1;
+    }
+    const int64_t c = T.tn0 + j;
+    return c < n ? c : -1;
+}
+
 template <int BM, int BNC>
 __global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1))
 void k_gemm_mfma_g(GemmArgs g) {
@@ -472,42 +497,28 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     const int kc = k < BKC ? (int)k : BKC;
     const int kc_log = k_log < BKC_LOG ? k_log : BKC_LOG;
     for (int i = threadIdx.x; i < BM; i += NT) {
-        int64_t ra = -1, rc = -1;
+        int64_t ra = -1;
         if (J.merge == 2) {
             const int seg = i >> m_log;
-            const int64_t r = i & (m - 1);
-            if (seg < T.cnt) {
-                ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
-                rc = gload<int64_t>(J.oc)[T.s0 + seg] + r * n;
-            }
+            if (seg < T.cnt) ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(i & (m - 1), J.a_row, 0, m_log);
         } else {
             const int64_t r = T.tm0 + i;
-            if (r < m) {
-                ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
-                rc = (J.merge == 1 ? 0 : gload<int64_t>(J.oc)[T.s0]) + r * n;
-            }
+            if (r < m) ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
         }
         row_a[i] = ra;
-        row_c[i] = rc;
+        row_c[i] = tile_out_row(J, T, i);
     }
     for (int j = threadIdx.x; j < BNC; j += NT) {
-        int64_t cb = -1, cc = -1;
+        int64_t cb = -1;
         if (J.merge == 1) {
             const int seg = j >> n_log;
-            const int64_t c = j & (n - 1);
-            if (seg < T.cnt) {
-                cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
-                cc = gload<int64_t>(J.oc)[T.s0 + seg] + c;
-            }
+            if (seg < T.cnt) cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(j & (n - 1), J.b_col, 0, n_log);
         } else {
             const int64_t c = T.tn0 + j;
-            if (c < n) {
-                cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
-                cc = c;
-            }
+            if (c < n) cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
         }
         col_b[j] = cb;
-        col_c[j] = cc;
+        col_c[j] = tile_out_col(J, T, j);
     }
     for (int i = threadIdx.x; i < BKC; i += NT) {
         ak_lo[i] = i < kc ? deposit(i, J.a_k, 0, kc_log) : 0;
@@ -554,10 +565,11 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             c = e >> BKC_LOG;
         }
     };
-    // chunks of this block: all, or one half of them (split inner sum)
+    // chunks of this block: all, or part kpart of ksplit equal parts (split
+    // inner sum; the host keeps ksplit a power of two dividing the chunk count)
     const int64_t nch_all = k >= BKC ? k / BKC : 1;
-    const int64_t c_begin = (J.ksplit == 2 && T.kpart) ? nch_all / 2 : 0;
-    const int64_t c_end = (J.ksplit == 2 && !T.kpart) ? nch_all / 2 : nch_all;
+    const int64_t c_begin = nch_all / J.ksplit * T.kpart;
+    const int64_t c_end = c_begin + nch_all / J.ksplit;
     // offsets of the high inner bits of the chunk being loaded (chunks are
     // loaded in order: advanced by the step table after each load)
     int64_t kchunk = c_begin;
@@ -672,34 +684,11 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         __syncthreads();
     }
 
-    if (J.ksplit == 2) {
-        // partial tile in the accumulators' own layout (coalesced per lane)
-        constexpr int64_t PT = int64_t(BM) * BNC * 2;
-        TN_GLOBAL float* mine = gstore<float>(J.partial) + ((int64_t)T.pair * 2 + T.kpart) * PT;
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    mine[(((int64_t)(wave * TM + i) * TN + j) * 16 + r) * 64 + lane] = acc[i][j][r];
-        __threadfence();
-        __syncthreads();
-        __shared__ int arrived;
-        if (threadIdx.x == 0) arrived = atomicAdd(&J.counters[T.pair], 1);
-        __syncthreads();
-        if (arrived == 0) return;           // the other half finishes the tile
-        if (threadIdx.x == 0) J.counters[T.pair] = 0;
-        __threadfence();
-        const TN_GLOBAL float* other = gload<float>(J.partial) + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    acc[i][j][r] += other[(((int64_t)(wave * TM + i) * TN + j) * 16 + r) * 64 + lane];
-    }
+    // split inner sum: this block's part goes to its row-major [BM][BNC] partial
+    // tile (padding skipped), added to the others' by k_split_reduce
+    const bool to_partial = J.ksplit > 1;
+    TN_GLOBAL float* __restrict__ O =
+        to_partial ? gstore<float>(J.partial) + ((int64_t)T.pair * J.ksplit + T.kpart) * (2 * BM * BNC) : C;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -712,7 +701,9 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             for (int r = 0; r < 16; ++r) {
                 const int row = wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 const int64_t rc = row_c[row];
-                if (rc >= 0) C[2 * (rc + cc) + part] = acc[i][j][r];
+                if (rc < 0) continue;
+                const int64_t o = to_partial ? (int64_t)row * BNC + col : rc + cc;
+                O[2 * o + part] = acc[i][j][r];
             }
         }
 }
@@ -1038,42 +1029,28 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     const int kc = k < BK ? (int)k : BK;
     const int kc_log = k_log < BK_LOG ? k_log : BK_LOG;
     for (int i = threadIdx.x; i < BM; i += 256) {
-        int64_t ra = -1, rc = -1;
+        int64_t ra = -1;
         if (J.merge == 2) {
             const int seg = i >> m_log;
-            const int64_t r = i & (m - 1);
-            if (seg < T.cnt) {
-                ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(r, J.a_row, 0, m_log);
-                rc = gload<int64_t>(J.oc)[T.s0 + seg] + r * n;
-            }
+            if (seg < T.cnt) ra = gload<int64_t>(J.oa)[T.s0 + seg] + deposit(i & (m - 1), J.a_row, 0, m_log);
         } else {
             const int64_t r = T.tm0 + i;
-            if (r < m) {
-                ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
-                rc = (J.merge == 1 ? 0 : gload<int64_t>(J.oc)[T.s0]) + r * n;
-            }
+            if (r < m) ra = gload<int64_t>(J.oa)[T.s0] + deposit(r, J.a_row, 0, m_log);
         }
         row_a[i] = ra;
-        row_c[i] = rc;
+        row_c[i] = tile_out_row(J, T, i);
     }
     for (int j = threadIdx.x; j < BN; j += 256) {
-        int64_t cb = -1, cc = -1;
+        int64_t cb = -1;
         if (J.merge == 1) {
             const int seg = j >> n_log;
-            const int64_t c = j & (n - 1);
-            if (seg < T.cnt) {
-                cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(c, J.b_col, 0, n_log);
-                cc = gload<int64_t>(J.oc)[T.s0 + seg] + c;
-            }
+            if (seg < T.cnt) cb = gload<int64_t>(J.ob)[T.s0 + seg] + deposit(j & (n - 1), J.b_col, 0, n_log);
         } else {
             const int64_t c = T.tn0 + j;
-            if (c < n) {
-                cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
-                cc = c;
-            }
+            if (c < n) cb = gload<int64_t>(J.ob)[T.s0] + deposit(c, J.b_col, 0, n_log);
         }
         col_b[j] = cb;
-        col_c[j] = cc;
+        col_c[j] = tile_out_col(J, T, j);
     }
     for (int i = threadIdx.x; i < BK; i += 256) {
         ak_lo[i] = i < kc ? deposit(i, J.a_k, 0, kc_log) : 0;
@@ -1092,49 +1069,72 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
 #pragma unroll
         for (int j = 0; j < TT; ++j) accr[i][j] = acci[i][j] = 0.0;
     const int64_t nch_all = k >= BK ? k / BK : 1;
-    const int64_t c_begin = (J.ksplit == 2 && T.kpart) ? nch_all / 2 : 0;
-    const int64_t c_end = (J.ksplit == 2 && !T.kpart) ? nch_all / 2 : nch_all;
+    const int64_t c_begin = nch_all / J.ksplit * T.kpart;
+    const int64_t c_end = c_begin + nch_all / J.ksplit;
     int64_t akh = deposit(c_begin << kc_log, J.a_k, kc_log, k_log);
     int64_t bkh = deposit(c_begin << kc_log, J.b_k, kc_log, k_log);
-    for (int64_t ch = c_begin; ch < c_end; ++ch) {
-        // staging: SE A and SE B elements per thread (row or column fast as stored)
+    // this thread's staged elements: LDS slots and offsets inside a chunk
+    // (fixed over the chunks; -1 = padding, staged as zero)
+    int sa_r[SE], sa_p[SE], sb_c[SE], sb_p[SE];
+    int64_t aoff[SE], boff[SE];
+#pragma unroll
+    for (int q = 0; q < SE; ++q) {
+        const int e = threadIdx.x + q * 256;
+        int r = 0, p = 0, pb = 0, c = 0;
+        if (J.a_rowfast) {
+            r = e & (BM - 1);
+            p = e >> BM_LOG;
+        } else {
+            p = e & (BK - 1);
+            r = e >> BK_LOG;
+        }
+        if (J.b_colfast) {
+            c = e & (BN - 1);
+            pb = e >> BN_LOG;
+        } else {
+            pb = e & (BK - 1);
+            c = e >> BK_LOG;
+        }
+        const bool in = e < BM * BK;
+        sa_r[q] = r;
+        sa_p[q] = p;
+        sb_c[q] = c;
+        sb_p[q] = pb;
+        aoff[q] = (in && row_a[r] >= 0 && p < kc) ? row_a[r] + ak_lo[p] : -1;
+        boff[q] = (in && col_b[c] >= 0 && pb < kc) ? col_b[c] + bk_lo[pb] : -1;
+    }
+    // chunk ch + 1 is loaded into registers while chunk ch is multiplied
+    double2 ra[SE], rb[SE];
+    auto load = [&]() {
 #pragma unroll
         for (int q = 0; q < SE; ++q) {
-            const int e = threadIdx.x + q * 256;
-            if (e >= BM * BK) break;
-            int r, p;
-            if (J.a_rowfast) {
-                r = e & (BM - 1);
-                p = e >> BM_LOG;
-            } else {
-                p = e & (BK - 1);
-                r = e >> BK_LOG;
-            }
-            const int64_t base = row_a[r];
-            double2 va = make_double2(0.0, 0.0);
-            if (base >= 0 && p < kc) va = gld(A + (base + ak_lo[p] + akh));
-            As[p][r] = va;
-            int pb, c;
-            if (J.b_colfast) {
-                c = e & (BN - 1);
-                pb = e >> BN_LOG;
-            } else {
-                pb = e & (BK - 1);
-                c = e >> BK_LOG;
-            }
-            const int64_t bb = col_b[c];
-            double2 vb = make_double2(0.0, 0.0);
-            if (bb >= 0 && pb < kc) vb = gld(B + (bb + bk_lo[pb] + bkh));
-            Bs[pb][c] = vb;
+            ra[q] = aoff[q] >= 0 ? gld(A + (aoff[q] + akh)) : make_double2(0.0, 0.0);
+            rb[q] = boff[q] >= 0 ? gld(B + (boff[q] + bkh)) : make_double2(0.0, 0.0);
         }
-        {
-            const int t = __builtin_ctzll(~(uint64_t)ch);
-            if (t < k_log - kc_log) {
-                akh += a_step[t];
-                bkh += b_step[t];
-            }
+    };
+    auto advance = [&](int64_t ch) {
+        const int t = __builtin_ctzll(~(uint64_t)ch);
+        if (t < k_log - kc_log) {
+            akh += a_step[t];
+            bkh += b_step[t];
+        }
+    };
+    if (c_begin < c_end) {
+        load();
+        advance(c_begin);
+    }
+    for (int64_t ch = c_begin; ch < c_end; ++ch) {
+#pragma unroll
+        for (int q = 0; q < SE; ++q) {
+            if (threadIdx.x + q * 256 >= BM * BK) break;
+            As[sa_p[q]][sa_r[q]] = ra[q];
+            Bs[sb_p[q]][sb_c[q]] = rb[q];
         }
         __syncthreads();
+        if (ch + 1 < c_end) {
+            load();
+            advance(ch + 1);
+        }
 #pragma unroll
         for (int p = 0; p < BK; ++p) {
             double2 a[TT], b[TT];
@@ -1152,42 +1152,21 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
         }
         __syncthreads();
     }
-    if (J.ksplit == 2) {
-        // partial tile, 2 TT^2 doubles per thread, thread-fastest
-        constexpr int64_t PT = int64_t(BM) * BN * 2;
-        TN_GLOBAL double* mine = gstore<double>(J.partial) + ((int64_t)T.pair * 2 + T.kpart) * PT;
-#pragma unroll
-        for (int i = 0; i < TT; ++i)
-#pragma unroll
-            for (int j = 0; j < TT; ++j) {
-                mine[(i * TT + j) * 256 + threadIdx.x] = accr[i][j];
-                mine[(TT * TT + i * TT + j) * 256 + threadIdx.x] = acci[i][j];
-            }
-        __threadfence();
-        __syncthreads();
-        __shared__ int arrived;
-        if (threadIdx.x == 0) arrived = atomicAdd(&J.counters[T.pair], 1);
-        __syncthreads();
-        if (arrived == 0) return;           // the other half finishes the tile
-        if (threadIdx.x == 0) J.counters[T.pair] = 0;
-        __threadfence();
-        const TN_GLOBAL double* other = gload<double>(J.partial) + ((int64_t)T.pair * 2 + (1 - T.kpart)) * PT;
-#pragma unroll
-        for (int i = 0; i < TT; ++i)
-#pragma unroll
-            for (int j = 0; j < TT; ++j) {
-                accr[i][j] += other[(i * TT + j) * 256 + threadIdx.x];
-                acci[i][j] += other[(TT * TT + i * TT + j) * 256 + threadIdx.x];
-            }
-    }
+    // split inner sum: this block's part goes to its row-major [BM][BN] partial
+    // tile (padding skipped), added to the others' by k_split_reduce
+    const bool to_partial = J.ksplit > 1;
+    TN_GLOBAL double2* __restrict__ O =
+        to_partial ? gstore<double2>(J.partial) + ((int64_t)T.pair * J.ksplit + T.kpart) * (BM * BN) : C;
 #pragma unroll
     for (int i = 0; i < TT; ++i) {
-        const int64_t rc = row_c[ty + 16 * i];
+        const int row = ty + 16 * i;
+        const int64_t rc = row_c[row];
         if (rc < 0) continue;
 #pragma unroll
         for (int j = 0; j < TT; ++j) {
-            const int64_t cc = col_c[tx + 16 * j];
-            if (cc >= 0) gst(C + (rc + cc), make_double2(accr[i][j], acci[i][j]));
+            const int col = tx + 16 * j;
+            const int64_t cc = col_c[col];
+            if (cc >= 0) gst(O + (to_partial ? (int64_t)row * BN + col : rc + cc), make_double2(accr[i][j], acci[i][j]));
         }
     }
 }
@@ -1199,6 +1178,57 @@ void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tile
         hipLaunchKernelGGL((k_tile64_group<2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
     else
         hipLaunchKernelGGL((k_tile64_group<4>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+}
+
+// ---------------------------------------------------------------------------
+// Split inner sums: the S blocks of a tile group each wrote one partial tile;
+// this launch (same job and tile lists, after the tile launch on the same
+// stream, so the partials are complete and visible) adds them in part order
+// 0, 1, ..., S-1 and writes C.  Block b takes rows [kpart BM / S, (kpart + 1)
+// BM / S) of its group's tile; tiles of unsplit jobs return at once.
+// ---------------------------------------------------------------------------
+template <typename C2>
+__global__ __launch_bounds__(256) void k_split_reduce(const MfmaJob* __restrict__ jobs,
+                                                      const MfmaTile* __restrict__ tiles, int bm_log,
+                                                      int bn_log) {
+    __shared__ int64_t rc_s[128], cc_s[64];
+    const MfmaTile T = tiles[blockIdx.x];
+    const MfmaJob& J = jobs[T.job];
+    const int S = J.ksplit;
+    if (S <= 1) return;
+    const int BM = 1 << bm_log, BN = 1 << bn_log;
+    const int rows = BM / S, r0 = T.kpart * rows;
+    for (int i = threadIdx.x; i < rows; i += 256) rc_s[i] = tile_out_row(J, T, r0 + i);
+    for (int j = threadIdx.x; j < BN; j += 256) cc_s[j] = tile_out_col(J, T, j);
+    __syncthreads();
+    const TN_GLOBAL C2* __restrict__ P = gload<C2>(J.partial) + (int64_t)T.pair * S * (BM * BN);
+    TN_GLOBAL C2* __restrict__ C = gstore<C2>(J.C);
+    const int64_t PT = (int64_t)BM * BN;
+    for (int e = threadIdx.x; e < rows * BN; e += 256) {
+        const int i = e >> bn_log, j = e & (BN - 1);
+        const int64_t rc = rc_s[i], cc = cc_s[j];
+        if (rc < 0 || cc < 0) continue;
+        const int64_t o = (int64_t)(r0 + i) * BN + j;
+        C2 t = gld(P + o);
+        for (int q = 1; q < S; ++q) {
+            const C2 v = gld(P + (q * PT + o));
+            t.x += v.x;
+            t.y += v.y;
+        }
+        gst(C + (rc + cc), t);
+    }
+}
+
+void launch_split_reduce(int fp64, int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles, int64_t n_tiles,
+                         hipStream_t s) {
+    if (n_tiles == 0) return;
+    const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
+    if (fp64)
+        hipLaunchKernelGGL((k_split_reduce<double2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles,
+                           bm_log, bn_log);
+    else
+        hipLaunchKernelGGL((k_split_reduce<float2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles,
+                           bm_log, bn_log);
 }
 
 // ---------------------------------------------------------------------------
@@ -1478,6 +1508,8 @@ const char* kernel_name(int id) {
     case K_GROUP32: return "k_gett_group<float>";
     case K_GROUP64: return "k_gett_group<double>";
     case K_TILE64_GROUP: return "k_tile64_group";
+    case K_SPLIT_REDUCE32: return "k_split_reduce<float>";
+    case K_SPLIT_REDUCE64: return "k_split_reduce<double>";
     }
     return "unknown";
 }
@@ -1487,7 +1519,9 @@ int kernel_class(int id) {
     if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return KC_MFMA;
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
-    if (id == K_GROUP32 || id == K_GROUP64 || id == K_TILE64_GROUP) return KC_GROUP;
+    if (id == K_GROUP32 || id == K_GROUP64 || id == K_TILE64_GROUP || id == K_SPLIT_REDUCE32 ||
+        id == K_SPLIT_REDUCE64)
+        return KC_GROUP;
     if (id >= K_MFMA_GROUP_BASE && id < K_MFMA_GROUP_BASE + K_MFMA_TILES) return KC_GROUP;
     return KC_TILED;
 }

@@ -59,7 +59,7 @@ class tn_prune_opts(C.Structure):
 class tn_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
                 ("tune", C.c_int32), ("time_kernels", C.c_int32), ("no_gather", C.c_int32),
-                ("no_group", C.c_int32)]
+                ("no_group", C.c_int32), ("max_ksplit", C.c_int32)]
 
 
 class tn_kernel_stat(C.Structure):
@@ -360,9 +360,9 @@ def _stream_ptr(stream):
 
 
 def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False,
-              gather=True, group=True):
+              gather=True, group=True, max_ksplit=0):
     return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
-                        1 if time_kernels else 0, 0 if gather else 1, 0 if group else 1)
+                        1 if time_kernels else 0, 0 if gather else 1, 0 if group else 1, int(max_ksplit))
 
 
 def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):
@@ -437,6 +437,8 @@ def _kernel_lib():
         L.tn_kernel_permute.restype = C.c_int
         L.tn_kernel_mfma_group.argtypes = [C.c_int32, vp, vp, C.c_int64, vp]
         L.tn_kernel_mfma_group.restype = C.c_int
+        L.tn_kernel_mfma_split_reduce.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int64, vp]
+        L.tn_kernel_mfma_split_reduce.restype = C.c_int
         L._kernel_sigs = True
     return L
 
@@ -473,7 +475,7 @@ class tn_mfma_job(C.Structure):
                 ("k_log", C.c_int32), ("merge", C.c_int32), ("a_rowfast", C.c_int32), ("b_colfast", C.c_int32),
                 ("a_row", C.c_int8 * 32), ("a_k", C.c_int8 * 32), ("b_k", C.c_int8 * 32),
                 ("b_col", C.c_int8 * 32), ("ksplit", C.c_int32), ("pad_", C.c_int32),
-                ("partial", C.c_void_p), ("counters", C.c_void_p)]
+                ("partial", C.c_void_p)]
 
 
 MFMA_TILE = np.dtype([("job", "<i4"), ("cnt", "<i4"), ("s0", "<i8"), ("tm0", "<i8"), ("tn0", "<i8"),
@@ -498,8 +500,8 @@ def mfma_group_descriptors(jobs, tiles):
             for i, v in enumerate(j[f]):
                 getattr(r, f)[i] = int(v)
         r.ksplit = int(j.get("ksplit", 1))
-        if r.ksplit == 2:
-            r.partial, r.counters = j["partial"].data_ptr(), j["counters"].data_ptr()
+        if r.ksplit > 1:
+            r.partial = j["partial"].data_ptr()
     dj = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
     t = np.ascontiguousarray(tiles, dtype=MFMA_TILE)
     dt = torch.from_numpy(t.view(np.uint8).copy()).cuda()
@@ -508,10 +510,19 @@ def mfma_group_descriptors(jobs, tiles):
 
 def kernel_mfma_group(tile, descriptors, stream=None):
     """One grouped matrix-core launch over descriptors from
-    mfma_group_descriptors (asynchronous on the stream)."""
+    mfma_group_descriptors (asynchronous on the stream).  Jobs with ksplit > 1
+    leave partial tiles: follow with kernel_mfma_split_reduce."""
     dj, dt, n = descriptors
     _check(_kernel_lib().tn_kernel_mfma_group(tile, C.c_void_p(dj.data_ptr()), C.c_void_p(dt.data_ptr()),
                                               n, _stream_ptr(stream)))
+
+
+def kernel_mfma_split_reduce(tile, descriptors, fp64=False, stream=None):
+    """Adds the partial tiles of the split jobs of a preceding grouped launch
+    on the same descriptors, in part order, and writes their outputs."""
+    dj, dt, n = descriptors
+    _check(_kernel_lib().tn_kernel_mfma_split_reduce(tile, 1 if fp64 else 0, C.c_void_p(dj.data_ptr()),
+                                                     C.c_void_p(dt.data_ptr()), n, _stream_ptr(stream)))
 
 
 # ---------------------------------------------------------------------------

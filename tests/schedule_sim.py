@@ -33,6 +33,7 @@ class Sim:
         if extra:
             self.const = np.concatenate([self.const, np.zeros(extra, np.uint8)])
         self.work = np.zeros(max(256, desc["work_bytes"]), dtype=np.uint8)
+        self.partials = {}      # split partial tiles written and not yet reduced
 
     def region(self, ref):
         return self.const if ref[0] == 0 else self.work
@@ -188,6 +189,7 @@ class Sim:
         tail = [L for L in d["launches"] if L["phase"] == "tail"]
         for L in batch:
             self.exec(L)
+        assert not self.partials, ("partial tiles never reduced", sorted(self.partials)[:4])
         if d["mode"] == 1:
             for t in range(d["plain_terms"]):
                 term = live_terms_per_plan[0][t]
@@ -253,74 +255,130 @@ class Sim:
             for j, (wj, rj) in enumerate(spans):
                 for other in ([wj] if i != j else []) + rj:
                     assert not _overlap(wi, other), ("grouped jobs race", i, j, wi, other)
-        ctx = []
-        for jb in jobs:
-            m, n, k = 1 << jb["m_log"], 1 << jb["n_log"], 1 << jb["k_log"]
-            ns = jb["ns"]
-            oa = self.view(jb["oa"], np.int64, ns)
-            ob = self.view(jb["ob"], np.int64, ns)
-            oc = self.view(jb["oc"], np.int64, ns)
-            amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
-            bmax = int(ob.max()) + sum(1 << p for p in jb["b_k"] + jb["b_col"])
-            A = self.view(jb["a"], dt, amax + 1)
-            B = self.view(jb["b"], dt, bmax + 1)
-            C = self.view(jb["c"], dt, ns * m * n)
-            ctx.append((m, n, k, oa, ob, oc, A, B, C, np.zeros(ns * m * n, np.int32),
-                        _deposit(k, jb["a_k"]), _deposit(k, jb["b_k"])))
-        halves = {}
+        ctx = [self._mjob_ctx(jb, dt) for jb in jobs]
         for t in tiles:
             jb = jobs[t["job"]]
             m, n, k, oa, ob, oc, A, B, C, hits, ka, kb = ctx[t["job"]]
-            if jb.get("ksplit", 1) == 2:
-                # the inner sum of a tile pair is split in two halves, added in
-                # the order half 0 + half 1 by whichever block arrives second
-                h = k // 2
-                sel = slice(0, h) if t["kpart"] == 0 else slice(h, k)
+            S = int(jb.get("ksplit", 1))
+            if S > 1:
+                # the inner sum of a tile group is split in S equal parts of whole
+                # 8-term chunks; each block leaves its partial tile
+                assert S & (S - 1) == 0 and k >= 8 and (k // 8) % S == 0 and S <= bm, ("split", S, k)
+                assert 0 <= int(t["kpart"]) < S, ("part index", int(t["kpart"]), S)
+                h = k // S
+                sel = slice(int(t["kpart"]) * h, (int(t["kpart"]) + 1) * h)
                 ka, kb = ka[sel], kb[sel]
-            cnt, s0, tm0, tn0 = int(t["cnt"]), int(t["s0"]), int(t["tm0"]), int(t["tn0"])
-            i = np.arange(bm, dtype=np.int64)
-            j = np.arange(bn, dtype=np.int64)
-            if jb["merge"] == 2:
-                seg, r = i >> jb["m_log"], i & (m - 1)
-                ok_r = seg < cnt
-                segc = np.minimum(seg, cnt - 1)
-                ra = oa[s0 + segc] + _deposit_of(r, jb["a_row"])
-                rc = oc[s0 + segc] + r * n
-            else:
-                r = tm0 + i
-                ok_r = r < m
-                ra = oa[s0] + _deposit_of(r % m, jb["a_row"])
-                rc = (0 if jb["merge"] == 1 else oc[s0]) + r * n
-            if jb["merge"] == 1:
-                seg, c = j >> jb["n_log"], j & (n - 1)
-                ok_c = seg < cnt
-                segc = np.minimum(seg, cnt - 1)
-                cb = ob[s0 + segc] + _deposit_of(c, jb["b_col"])
-                cc = oc[s0 + segc] + c
-            else:
-                c = tn0 + j
-                ok_c = c < n
-                cb = ob[s0] + _deposit_of(c % n, jb["b_col"])
-                cc = c
-            ra, rc, cb, cc = ra[ok_r], rc[ok_r], cb[ok_c], cc[ok_c]
+            ok_r, rc, ok_c, cc = self._tile_out(jb, t, bm, bn, m, n, oc)
+            ra, cb = self._tile_in(jb, t, bm, bn, m, n, oa, ob)
+            ra, cb = ra[ok_r], cb[ok_c]
             At = A[ra[:, None] + ka[None, :]].astype(np.complex128)
             Bt = B[kb[:, None] + cb[None, :]].astype(np.complex128)
-            idx = (rc[:, None] + cc[None, :]).reshape(-1)
             part = (At @ Bt).astype(dt).reshape(-1)
-            if jb.get("ksplit", 1) == 2:
-                key = (int(t["job"]), int(t["pair"]))
-                got = halves.setdefault(key, {})
-                assert int(t["kpart"]) not in got, ("tile half listed twice", key)
-                got[int(t["kpart"])] = (idx, part)
-                if len(got) < 2:
-                    continue
-                (i0, p0), (i1, p1) = got[0], got[1]
-                assert np.array_equal(i0, i1), ("the halves of a pair cover different outputs", key)
-                part = (p0 + p1).astype(dt)
+            if S > 1:
+                # row-major [bm][bn] partial tile of group `pair`, part `kpart`
+                slot = int(t["pair"]) * S + int(t["kpart"])
+                P = self.view(jb["partial"], dt, (slot + 1) * bm * bn)[slot * bm * bn:]
+                rows, cols = np.nonzero(ok_r)[0], np.nonzero(ok_c)[0]
+                P[(rows[:, None] * bn + cols[None, :]).reshape(-1)] = part
+                self.partials[(tuple(jb["partial"]), slot)] = (rows, cols)
+                continue
+            idx = (rc[ok_r][:, None] + cc[ok_c][None, :]).reshape(-1)
             C[idx] = part
             np.add.at(hits, idx, 1)
         for q, cx in enumerate(ctx):
-            assert cx[9].min() == 1 and cx[9].max() == 1, ("output coverage", q, cx[9].min(), cx[9].max())
+            if int(jobs[q].get("ksplit", 1)) == 1:
+                assert cx[9].min() == 1 and cx[9].max() == 1, ("output coverage", q, cx[9].min(), cx[9].max())
+
+    def mreduce(self, L):
+        """Split-sum reduction after a grouped launch: block (group, part) adds
+        the rows [part bm / S, (part + 1) bm / S) of the group's S partial tiles
+        in part order and writes C; every output of every split job exactly once."""
+        bm, bn = L["bm"], L["bn"]
+        dt = np.complex128 if L["fp64"] else np.complex64
+        tiles = self.view(L["tiles"], np.uint8, L["n_tiles"] * self.TILE.itemsize).view(self.TILE)
+        jobs = L["jobs"]
+        ctx = [self._mjob_ctx(jb, dt) for jb in jobs]
+        for t in tiles:
+            jb = jobs[t["job"]]
+            S = int(jb.get("ksplit", 1))
+            if S == 1:
+                continue
+            m, n, k, oa, ob, oc, A, B, C, hits, ka, kb = ctx[t["job"]]
+            g, h = int(t["pair"]), int(t["kpart"])
+            P = self.view(jb["partial"], dt, (g + 1) * S * bm * bn)[g * S * bm * bn:].reshape(S, bm, bn)
+            ok_r, rc, ok_c, cc = self._tile_out(jb, t, bm, bn, m, n, oc)
+            rows = np.arange(h * (bm // S), (h + 1) * (bm // S))
+            rows = rows[ok_r[rows]]
+            cols = np.nonzero(ok_c)[0]
+            for q in range(S if h == 0 else 0):      # every part wrote exactly these elements
+                got = self.partials.pop((tuple(jb["partial"]), g * S + q), None)
+                assert got is not None, ("missing partial tile", g, q)
+                assert np.array_equal(got[0], np.nonzero(ok_r)[0]) and np.array_equal(got[1], cols)
+            acc = P[0][rows[:, None], cols[None, :]]
+            for q in range(1, S):
+                acc = (acc + P[q][rows[:, None], cols[None, :]]).astype(dt)
+            idx = (rc[rows][:, None] + cc[cols][None, :]).reshape(-1)
+            C[idx] = acc.reshape(-1)
+            np.add.at(hits, idx, 1)
+        for q, cx in enumerate(ctx):
+            if int(jobs[q].get("ksplit", 1)) > 1:
+                assert cx[9].min() == 1 and cx[9].max() == 1, ("split output coverage", q, cx[9].min(), cx[9].max())
+
+    def _mjob_ctx(self, jb, dt):
+        m, n, k = 1 << jb["m_log"], 1 << jb["n_log"], 1 << jb["k_log"]
+        ns = jb["ns"]
+        oa = self.view(jb["oa"], np.int64, ns)
+        ob = self.view(jb["ob"], np.int64, ns)
+        oc = self.view(jb["oc"], np.int64, ns)
+        amax = int(oa.max()) + sum(1 << p for p in jb["a_row"] + jb["a_k"])
+        bmax = int(ob.max()) + sum(1 << p for p in jb["b_k"] + jb["b_col"])
+        A = self.view(jb["a"], dt, amax + 1)
+        B = self.view(jb["b"], dt, bmax + 1)
+        C = self.view(jb["c"], dt, ns * m * n)
+        return (m, n, k, oa, ob, oc, A, B, C, np.zeros(ns * m * n, np.int32),
+                _deposit(k, jb["a_k"]), _deposit(k, jb["b_k"]))
+
+    @staticmethod
+    def _tile_out(jb, t, bm, bn, m, n, oc):
+        """Validity and C offsets of a tile's rows and columns (as the kernels'
+        offset tables: merge 2 stacks slices along rows, merge 1 along columns)."""
+        cnt, s0, tm0, tn0 = int(t["cnt"]), int(t["s0"]), int(t["tm0"]), int(t["tn0"])
+        i = np.arange(bm, dtype=np.int64)
+        j = np.arange(bn, dtype=np.int64)
+        if jb["merge"] == 2:
+            seg, r = i >> jb["m_log"], i & (m - 1)
+            ok_r = seg < cnt
+            rc = oc[s0 + np.minimum(seg, cnt - 1)] + r * n
+        else:
+            r = tm0 + i
+            ok_r = r < m
+            rc = (0 if jb["merge"] == 1 else oc[s0]) + r * n
+        if jb["merge"] == 1:
+            seg, c = j >> jb["n_log"], j & (n - 1)
+            ok_c = seg < cnt
+            cc = oc[s0 + np.minimum(seg, cnt - 1)] + c
+        else:
+            c = tn0 + j
+            ok_c = c < n
+            cc = c
+        return ok_r, rc, ok_c, cc
+
+    @staticmethod
+    def _tile_in(jb, t, bm, bn, m, n, oa, ob):
+        cnt, s0, tm0, tn0 = int(t["cnt"]), int(t["s0"]), int(t["tm0"]), int(t["tn0"])
+        i = np.arange(bm, dtype=np.int64)
+        j = np.arange(bn, dtype=np.int64)
+        if jb["merge"] == 2:
+            seg, r = i >> jb["m_log"], i & (m - 1)
+            ra = oa[s0 + np.minimum(seg, cnt - 1)] + _deposit_of(r, jb["a_row"])
+        else:
+            ra = oa[s0] + _deposit_of((tm0 + i) % m, jb["a_row"])
+        if jb["merge"] == 1:
+            seg, c = j >> jb["n_log"], j & (n - 1)
+            cb = ob[s0 + np.minimum(seg, cnt - 1)] + _deposit_of(c, jb["b_col"])
+        else:
+            cb = ob[s0] + _deposit_of((tn0 + j) % n, jb["b_col"])
+        return ra, cb
 
     def exec(self, L):
         if L["kind"] == 5:
@@ -328,6 +386,9 @@ class Sim:
             return
         if L["kind"] == 6:
             self.mgroup(L)
+            return
+        if L["kind"] == 7:
+            self.mreduce(L)
             return
         if L["kind"] == 0:
             self.perm(L)

@@ -414,13 +414,15 @@ def _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, ti
                oc=torch.from_numpy(oc.astype(np.int64)).cuda(), m_log=m_log, n_log=n_log, k_log=k_log,
                merge=merge, a_rowfast=int(a_row[0] == 0) if m_log else 0,
                b_colfast=int(b_col[0] == 0) if n_log else 0, a_row=a_row, a_k=a_k, b_k=b_k, b_col=b_col)
-    if ksplit == 2:
-        pairs = []
+    if ksplit > 1:
+        # S tiles in a row per output tile, one per part of the inner chunks
+        assert k_log >= 3 and ((1 << k_log) // 8) % ksplit == 0
+        parts = []
         for q, t in enumerate(tiles):
-            pairs += [t[:5] + (0, q), t[:5] + (1, q)]
-        tiles = pairs
-        job.update(ksplit=2, partial=torch.empty(len(pairs) * bm * bn * 2, dtype=torch.float32, device="cuda"),
-                   counters=torch.zeros(len(pairs) // 2, dtype=torch.int32, device="cuda"))
+            parts += [t[:5] + (h, q) for h in range(ksplit)]
+        job.update(ksplit=ksplit,
+                   partial=torch.empty(len(parts) * bm * bn * 2, dtype=torch.float32, device="cuda"))
+        tiles = parts
     return job, np.array(tiles, dtype=tn.MFMA_TILE), ref
 
 
@@ -431,6 +433,9 @@ def _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, ti
     (6, 3, 2, 5, 5, 1, 6, 1),       # k < 8 (padded inner chunk), n < 16
     (8, 4, 8, 12, 3, 1, 0, 2),      # split inner sum over tile pairs
     (5, 5, 7, 4, 1, 0, 4, 2),       # split, 32 x 32 tiles
+    (8, 4, 8, 12, 3, 1, 0, 8),      # split over 8 tiles (4 chunks each)
+    (5, 5, 9, 2, 1, 0, 4, 16),      # split over 16 tiles, 32 x 32
+    (3, 5, 7, 10, 4, 2, 2, 4),      # merged rows, split over 4 tiles
 ])
 def test_grouped_mfma_kernel_against_numpy(torch, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit):
     """tn_kernel_mfma_group on operands in random stored bit orders, against a
@@ -440,16 +445,21 @@ def test_grouped_mfma_kernel_against_numpy(torch, m_log, n_log, k_log, n_slices,
     rng = np.random.default_rng(1000 + m_log * 100 + k_log * 10 + merge)
     job, tiles, ref = _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit)
     d = tn.mfma_group_descriptors([job], tiles)
-    for rep in range(2):     # the second launch reuses the (reset) pair counters
+    first = None
+    for rep in range(2):     # the second launch reuses the partial buffer
         job["C"].zero_()
         tn.kernel_mfma_group(tile, d)
+        if ksplit > 1:
+            tn.kernel_mfma_split_reduce(tile, d)
         torch.cuda.synchronize()
         got = job["C"].cpu().numpy().reshape(ref.shape)
         err = np.abs(got - ref).max()
         scale = np.sqrt(2.0 * (1 << k_log)) * 2.0
         assert err <= 4e-6 * scale * max(1.0, np.sqrt(1 << k_log) / 4), (rep, err)
-    if ksplit == 2:
-        assert int(job["counters"].abs().sum().item()) == 0
+        if first is None:
+            first = got.copy()
+        else:           # parts are added in a fixed order: the same bits every launch
+            assert np.array_equal(first.view(np.float32), got.view(np.float32))
 
 
 def test_degenerate_cases_against_oracle(torch):

@@ -142,12 +142,12 @@ def grouped_by_positions(pat, x):
     return out
 
 
-def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True):
+def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True, max_ksplit=0):
     plan = tn.tn_plan_build(circ, level)
     t = tn.tn_terms_enumerate(plan, level)
     desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
                                                                   fp64_level0=fp64, gather=gather,
-                                                                  group=group))
+                                                                  group=group, max_ksplit=max_ksplit))
     pat, w = t.get()
     live = [i for i in range(t.n) if w[i] != 0.0]
     sim = Sim(desc, cb)
@@ -179,9 +179,9 @@ def test_schedule_replay_plain_mode_matches_batched():
     assert np.allclose(xb, xp, rtol=2e-5, atol=1e-9)
 
 
-@pytest.mark.parametrize("n,gates,noises,target,seed,merge", [(16, 160, 4, "circuit_output", 1, 2),
-                                                               (16, 160, 4, "circuit_output", 4, 1)])
-def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge):
+@pytest.mark.parametrize("n,gates,noises,target,seed,merge,split", [(16, 160, 4, "circuit_output", 1, 2, 16),
+                                                                     (16, 160, 4, "circuit_output", 4, 1, 2)])
+def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge, split):
     """Circuits wide enough for matrix-core steps.  Batched mode groups each
     tree level (small steps in one launch, matrix-core steps in one launch per
     tile shape, operands read in stored order); without grouping the MFMA
@@ -195,13 +195,20 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge
     assert any(L["kind"] == 6 and L["fp64"] for L in desc["launches"]), "no grouped FP64 tile launch"
     merges = {j["merge"] for L in desc["launches"] if L["kind"] == 6 for j in L["jobs"]}
     assert merge in merges, merges          # the two circuits cover both merge modes
-    assert any(j["ksplit"] == 2 for L in desc["launches"] if L["kind"] == 6 for j in L["jobs"])
+    splits = {j["ksplit"] for L in desc["launches"] if L["kind"] == 6 for j in L["jobs"]}
+    assert max(splits) == split, splits      # inner sums split over 16 (2^9 terms) or 2 (2^6) tiles
+    kinds = [L["kind"] for L in desc["launches"]]
+    assert 7 in kinds and all(kinds[q - 1] == 6 for q, kd in enumerate(kinds) if kd == 7)
+    x_2, _, desc_2 = _replay(c, 2, max_ksplit=2)
+    assert {j["ksplit"] for L in desc_2["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1, 2}
+    x_1, _, desc_1 = _replay(c, 2, max_ksplit=1)
+    assert {j["ksplit"] for L in desc_1["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1}
     x_g, _, desc_g = _replay(c, 2, group=False)
     assert any(L["kind"] == 1 and L.get("gather") for L in desc_g["launches"]), "no gathered step"
     x_t, _, desc_t = _replay(c, 2, gather=False, group=False)
     assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
     x_p, _, desc_p = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
-    for v in (x, x_g, x_t, x_p):
+    for v in (x, x_2, x_1, x_g, x_t, x_p):
         assert np.allclose(v, r["X"], rtol=2e-5, atol=1e-10)
 
 
