@@ -7,10 +7,12 @@ level-2 expansion (436 term networks).  Synthetic, seeded (see workloads/).
 
 One step = one full estimate (every term network contracted, FP64 dominant
 term, per-term values, level sums) with the plan and its schedule prepared
-and all inputs resident in HBM.  The timed steps replay the captured
-schedule (the library's default); a second pass launches the same schedule
-eagerly with a HIP event pair around every launch for the per-kernel
-durations of the roofline entry.  Prints ONE JSON line.
+and all inputs resident in HBM.  The timed steps launch the prepared
+schedule directly (level by level; the same schedule replayed as a captured
+hipGraph is timed beside it and reported as `other_mode`; `--graph` swaps
+the two); a further pass launches it with a HIP event pair around every
+launch for the per-kernel durations of the roofline entry.  Prints ONE JSON
+line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -140,7 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper-case", action="store_true", help="skip the 225-qubit context measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
     ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
@@ -175,24 +177,33 @@ def main():
     plan = tn.tn_plan_build(circ, level)
     plan_s = time.perf_counter() - t0
     terms = tn.tn_terms_enumerate(plan, level)
-    # timed region: the schedule captured once in a hipGraph (the library's
-    # default execution) and replayed; inputs resident in HBM
-    t0 = time.perf_counter()
-    exg = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=not args.no_graph,
-                                                           tune=not args.no_tune))
-    prep_s = time.perf_counter() - t0
-    for _ in range(args.warmup):
-        res = exg.run()[0]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = exg.run()[0]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    # timed region: the prepared schedule run with direct launches (issued
+    # level by level, the FP64 pass on its own stream), inputs resident in HBM;
+    # then the same schedule captured once in a hipGraph and replayed, for
+    # comparison (`--graph` times the replay as the headline instead)
+    def timed(use_graph):
+        t0 = time.perf_counter()
+        e = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=use_graph, tune=not args.no_tune))
+        prep = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            r = e.run()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = e.run()[0]
+        torch.cuda.synchronize()
+        el_ = time.perf_counter() - t0
+        del e
+        return r, el_, prep
+
+    res, el, prep_s = timed(args.graph)
+    res_o, el_o, _ = timed(not args.graph)
     n_contracted = res["n_contracted"]
     ms_per_step = 1000.0 * el / args.steps
     value = n_contracted * args.steps / el
-    del exg
+    other = {"mode": "direct launches" if args.graph else "hipGraph replay",
+             "value": n_contracted * args.steps / el_o, "ms_per_step": 1000.0 * el_o / args.steps,
+             "A_equal": res_o["A"] == res["A"]}
     # kernel durations: the same schedule launched eagerly, a HIP event pair
     # around every launch on its own stream (events inside a captured graph
     # cannot be timed); same kernels, same inputs, same launch shapes
@@ -209,8 +220,8 @@ def main():
     eel = time.perf_counter() - t0
     stats = ex.kernel_stats(reset=True)
     eager = {"value": n_contracted * args.steps / eel, "ms_per_step": 1000.0 * eel / args.steps,
-             "A_equal_graph": re_["A"] == res["A"],
-             "note": "eager launches with a HIP event pair per launch (kernel durations below)"}
+             "A_equal": re_["A"] == res["A"],
+             "note": "direct launches with a HIP event pair per launch (kernel durations below)"}
     del ex
 
     # parity of the estimate against the stored oracle values
@@ -327,7 +338,8 @@ def main():
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
         "kernels": kernels,
-        "timed": "hipGraph replays" if not args.no_graph else "eager launches",
+        "timed": "hipGraph replays" if args.graph else "direct launches",
+        "other_mode": other,
         "eager": eager,
         "plain": plain,
         "paper_case": paper_case,

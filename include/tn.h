@@ -118,7 +118,10 @@ enum { TN_MODE_BATCHED = 0, TN_MODE_PLAIN = 1 };
 
 typedef struct {
     int32_t mode;            /* TN_MODE_BATCHED or TN_MODE_PLAIN */
-    int32_t use_graph;       /* batched: capture the step sequence in a hipGraph */
+    int32_t use_graph;       /* batched: 1 = capture the step sequence in a hipGraph and
+                                replay it; 0 = direct launches, the FP64 pass issued on
+                                its side stream by a host thread the exec owns (started
+                                at the first run, joined by tn_exec_destroy) */
     int32_t fp64_level0;     /* 1 = recompute the all-dominant term in FP64
                                 (tn_estimate always does) */
     int32_t tune;            /* 1 = pick GEMM tiles by timing (autotuner) */

@@ -19,7 +19,10 @@
 #include <map>
 #include <numeric>
 #include <climits>
+#include <condition_variable>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <sstream>
 #include <tuple>
 #include <unordered_map>
@@ -157,7 +160,23 @@ struct PlanExec {
 
 }  // namespace tn
 
+// Host thread that issues the FP64 pass's launches on the side stream while
+// the calling thread issues the FP32 chain (direct launches): issuing costs
+// host time per launch, and one thread alternating between the two chains
+// delays the FP32 chain's short early launches.
+struct SideIssuer {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t gen = 0, done = 0;   // batches requested / finished
+    bool stop = false;
+    bool failed = false;
+    tn::Error err{0, ""};
+};
+
 struct tn_exec_s {
+    std::unique_ptr<SideIssuer> issuer;     // FP64 pass issued from its own host thread
+    int device = 0;
     std::vector<tn::Launch> launches;       // FP32 batched launches, in order (main stream)
     std::vector<tn::Launch> launches64;     // FP64 dominant-term pass (side stream)
     std::vector<tn::Launch> plain_launches; // PLAIN mode per-term body
@@ -857,7 +876,17 @@ struct Builder {
                 jb.n_log = (int)FQ.size();
                 jb.k_log = rk;
                 jb.n_inst = ninst * nbatch;
-                jb.split = (jb.m_log + jb.n_log <= 4 && rk >= 8) ? 1 : 0;
+                // long inner sums: one block per output element when that is the
+                // shorter chain of dependent loads (a thread-per-output sum runs
+                // k / 4 rounds; a block per output k / 2048 rounds plus its
+                // reduction, over the outputs in batches of ~2048 resident blocks)
+                {
+                    const double kk = std::ldexp(1.0, rk);
+                    const double outs = std::ldexp((double)jb.n_inst, jb.m_log + jb.n_log);
+                    const double t_thread = kk / 4.0;
+                    const double t_block = std::ceil(outs / 2048.0) * (kk / 2048.0 + 3.0);
+                    jb.split = (rk >= 8 && t_block < t_thread) ? 1 : 0;
+                }
                 // rows per thread: the column operand's elements are reused across
                 // them (up to 8; 1 for outer products, where there is no reuse)
                 jb.rpt_log = jb.split || rk == 0 ? 0 : std::min(jb.m_log, 3);
@@ -1517,11 +1546,100 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
     }
 }
 
+static void run_tail(tn_exec_s* ex, hipStream_t s);
+
+static void issue_chain(tn_exec_s* ex, std::vector<Launch>& list, hipStream_t st) {
+    for (auto& L : list) {
+        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, st));
+        enqueue(ex, L, st);
+        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, st));
+    }
+}
+
+static void side_issuer_main(tn_exec_s* ex) {
+    SideIssuer& w = *ex->issuer;
+    (void)hipSetDevice(ex->device);
+    uint64_t seen = 0;
+    for (;;) {
+        std::unique_lock<std::mutex> lk(w.mu);
+        w.cv.wait(lk, [&] { return w.stop || w.gen > seen; });
+        if (w.stop) return;
+        seen = w.gen;
+        lk.unlock();
+        bool ok = true;
+        Error e{0, ""};
+        try {
+            HIPCHK(hipStreamWaitEvent(ex->side, ex->ev_fork, 0));
+            issue_chain(ex, ex->launches64, ex->side);
+            HIPCHK(hipEventRecord(ex->ev_join, ex->side));
+        } catch (const Error& x) {
+            ok = false;
+            e = x;
+        } catch (...) {
+            ok = false;
+            e = Error{TN_EINVAL, "FP64 pass issue failed"};
+        }
+        lk.lock();
+        w.failed = !ok;
+        w.err = e;
+        w.done = seen;
+        w.cv.notify_all();
+    }
+}
+
+static void stop_side_issuer(tn_exec_s* ex) {
+    if (!ex->issuer) return;
+    {
+        std::lock_guard<std::mutex> lk(ex->issuer->mu);
+        ex->issuer->stop = true;
+    }
+    ex->issuer->cv.notify_all();
+    if (ex->issuer->th.joinable()) ex->issuer->th.join();
+    ex->issuer.reset();
+}
+
+// Direct launches with the FP64 pass: the side thread issues it after the
+// fork event while this thread issues the FP32 chain; the join waits for both.
+static void run_body_threaded(tn_exec_s* ex, hipStream_t s) {
+    if (!ex->issuer) {
+        ex->issuer.reset(new SideIssuer());
+        ex->issuer->th = std::thread(side_issuer_main, ex);
+    }
+    SideIssuer& w = *ex->issuer;
+    HIPCHK(hipEventRecord(ex->ev_fork, s));
+    uint64_t my;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        my = ++w.gen;
+    }
+    w.cv.notify_all();
+    bool ok = true;
+    Error e{0, ""};
+    try {
+        issue_chain(ex, ex->launches, s);
+    } catch (const Error& x) {
+        ok = false;
+        e = x;
+    }
+    {
+        std::unique_lock<std::mutex> lk(w.mu);
+        w.cv.wait(lk, [&] { return w.done >= my; });
+        if (ok && w.failed) {
+            ok = false;
+            e = w.err;
+        }
+    }
+    if (!ok) throw e;
+    HIPCHK(hipStreamWaitEvent(s, ex->ev_join, 0));
+    run_tail(ex, s);
+}
+
 static void run_body(tn_exec_s* ex, hipStream_t s) {
     // The FP64 pass forks onto the side stream and joins before the finalize.
-    // Launches are issued level by level, alternating between the two chains
-    // (the FP32 chain first at each level), so that neither waits for the
-    // other's whole chain to be issued (a captured graph keeps this order).
+    // One thread (graph capture, term-range runs) issues the two chains level
+    // by level, alternating between them, the FP32 chain first at each level.
+    // (A captured graph replays each stream's branch in full before the
+    // other's.)
     const bool side = !ex->launches64.empty();
     if (side) {
         HIPCHK(hipEventRecord(ex->ev_fork, s));
@@ -1545,6 +1663,10 @@ static void run_body(tn_exec_s* ex, hipStream_t s) {
         }
     }
     if (side) HIPCHK(hipStreamWaitEvent(s, ex->ev_join, 0));
+    run_tail(ex, s);
+}
+
+static void run_tail(tn_exec_s* ex, hipStream_t s) {
     if (ex->opts.mode == TN_MODE_PLAIN) {
         for (int64_t t = 0; t < ex->plain_terms; ++t) {
             for (auto& L : ex->plain_launches) {
@@ -1902,6 +2024,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         if (!out) fail(TN_EINVAL, "null output handle");
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
+        HIPCHK(hipGetDevice(&ex->device));
         bind(ex.get());
         bind_multi_tail(ex.get());
         if (!ex->launches64.empty()) {
@@ -1946,6 +2069,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
                 HIPCHK(hipGraphInstantiate(&ex->gexec, ex->graph, nullptr, nullptr, 0));
             }
             HIPCHK(hipGraphLaunch(ex->gexec, s));
+        } else if (!ex->launches64.empty()) {
+            run_body_threaded(ex, s);
         } else {
             run_body(ex, s);
         }
@@ -2106,6 +2231,7 @@ int tn_exec_const_bytes(tn_exec exh, void* buf, size_t* len) {
 void tn_exec_destroy(tn_exec exh) {
     tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
     if (!ex) return;
+    stop_side_issuer(ex);
     if (ex->gexec) (void)hipGraphExecDestroy(ex->gexec);
     if (ex->graph) (void)hipGraphDestroy(ex->graph);
     if (ex->ev0) (void)hipEventDestroy(ex->ev0);

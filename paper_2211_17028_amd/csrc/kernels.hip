@@ -760,9 +760,9 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
         R sr = 0, si = 0;
         if ((int)threadIdx.x < kc) {
             const int64_t alo = ak_lo[threadIdx.x], blo = bk_lo[threadIdx.x];
-            // eight chunks per round: their loads are all in flight before the
-            // first product (the chunk count is a power of two)
-            constexpr int U = 8;
+            // U chunks per round (16 in FP32, 8 in FP64): their loads are all in
+            // flight before the first product (the chunk count is a power of two)
+            constexpr int U = sizeof(R) == 4 ? 16 : 8;
             const int64_t nh = k >> kc_log;
             const int64_t step = nh >= U ? U : nh;
             int64_t ah = alo, bh = blo;

@@ -359,7 +359,7 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def exec_opts(mode=TN_MODE_BATCHED, use_graph=True, fp64_level0=True, tune=False, time_kernels=False,
+def exec_opts(mode=TN_MODE_BATCHED, use_graph=False, fp64_level0=True, tune=False, time_kernels=False,
               gather=True, group=True, max_ksplit=0):
     return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
                         1 if time_kernels else 0, 0 if gather else 1, 0 if group else 1, int(max_ksplit))
