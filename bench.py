@@ -231,10 +231,13 @@ def main():
         g = np.loadtxt(gold)
         err = max(abs(res["A"][u] - g[u]) / abs(g[u]) for u in range(level + 1))
 
-    # dominant kernel: largest accumulated time in the eager pass; its bound is
-    # the matrix cores (FP32 MFMA kernels), the FP64 FMA pipes (FP64 tiles) or
-    # HBM (the small-step and transpose kernels)
-    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    # dominant kernel: largest accumulated time in the eager pass among the
+    # kernels of the FP32 chain (the critical path; the FP64 pass runs beside
+    # it on its own stream and is reported as `fp64_side_kernels`); its bound
+    # is the matrix cores (FP32 MFMA kernels) or HBM (small-step kernels)
+    fp64_names = {k for k in stats if "double" in k or k.startswith("k_tile64") or k.startswith("k_gemm_tiled_c128")}
+    main = {k: v for k, v in stats.items() if k not in fp64_names} or stats
+    dom_name, dom = max(main.items(), key=lambda kv: kv[1]["ms"])
     if dom_name.startswith("k_mfma") or dom_name.startswith("k_gemm_mfma"):
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -253,6 +256,11 @@ def main():
                  "algorithmic_per_launch": (dom["bytes"] if roof["bound"] == "hbm" else dom["flops"])
                  / dom["launches"], "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
                  "traffic": measured_traffic(dom_name)})
+    side = [stats[k] for k in fp64_names]
+    if side:
+        roof["fp64_side_kernels"] = {"kernels": sorted(fp64_names),
+                                     "ms_per_step": sum(v["ms"] for v in side) / args.steps,
+                                     "launches_per_step": sum(v["launches"] for v in side) / args.steps}
     # the FP32 matrix-core kernels together (the term contractions)
     mf = [v for k, v in stats.items() if k.startswith("k_mfma")]
     if mf:

@@ -1769,7 +1769,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
         os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
-           << ",\"plan\":" << L.plan;
+           << ",\"plan\":" << L.plan << ",\"level\":" << L.level;
         first = false;
         if (L.kind == L_GEMM)
             os << ",\"m_log\":" << L.g.m_log << ",\"n_log\":" << L.g.n_log << ",\"k_log\":" << L.g.k_log
