@@ -134,6 +134,10 @@ typedef struct {
                                 launch for the small steps of each tree level */
     int32_t max_ksplit;      /* largest number of blocks one tile's inner sum is split
                                 over (0 = default 16, 1 = no split, at most 32) */
+    int32_t mixed_shapes;    /* 1 = every matrix-core job keeps its own best tile shape;
+                                0 = with one plan, jobs with at most a quarter of the flops
+                                of their tree level's main tile shape take that shape and
+                                join its launch */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs
@@ -213,6 +217,8 @@ int tn_terms_get(tn_terms terms, int8_t* patterns, double* weights);
  *   otherwise d_ws must hold >= *need_bytes bytes (else TN_ENOMEM); the upload
  *   is enqueued on `stream` and *out receives an executable handle bound to
  *   d_ws (the caller keeps d_ws alive and unmodified until tn_exec_destroy).
+ *   opts == NULL: batched, direct launches, FP64 dominant-term pass, every
+ *   other field 0.
  * ------------------------------------------------------------------------- */
 int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms,
                     const tn_exec_opts* opts, void* d_ws, size_t ws_bytes, void* stream,

@@ -244,6 +244,9 @@ constexpr int kSplitMinKLog = 6;
 constexpr int kSplitMinPartLog = 5;
 constexpr int64_t kSplitMaxTiles = 512;
 constexpr int kSplitDefaultMax = 16;
+// A matrix-core job with at most this share of the flops of its level's main
+// tile shape takes that shape, so that it runs in the main launch.
+constexpr double kSmallJobShare = 0.25;
 
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
@@ -292,6 +295,9 @@ struct Builder {
     bool grouping = true;      // small steps of one tree level share one launch
     bool quantize_tiles = true;  // tile model: whole rounds over the CUs (one circuit)
     int max_ksplit = kSplitDefaultMax;  // largest split of a tile job's inner sum (1 = none)
+    // FP32 tile shape imposed per tree level on jobs of at most the given
+    // flops (the small jobs join the level's main matrix-core launch)
+    const std::map<int, std::pair<int, double>>* level_tile = nullptr;
     std::vector<Ref> node_ref;         // concrete buffer of every node (once placed)
     std::vector<char> node_leaf;
     std::vector<int64_t> node_bytes;
@@ -415,8 +421,15 @@ struct Builder {
             so[o][0] = slice_vec(R, btb[o]);
             so[o][1] = slice_vec(Q, btb[o]);
             const std::vector<int64_t> ca = run_counts(so[o][0]), cb = run_counts(so[o][1]);
+            int forced = -1;
+            if (!fp64 && level_tile && level_tile->count(st.level)) {
+                const std::pair<int, double>& lt = level_tile->at(st.level);
+                const double job_flops = 8.0 * std::ldexp((double)ns, (int)(FA.size() + FB.size()) + rk);
+                if (job_flops <= lt.second) forced = lt.first;
+            }
             for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
                 if (fp64 && tile != 1 && tile != 4) continue;
+                if (forced >= 0 && tile != forced) continue;
                 const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
                 const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
                 const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
@@ -1222,9 +1235,11 @@ static std::vector<u128> cluster_keys(const Plan& P, const Cluster& cl, const Te
     return uk;
 }
 
-static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms) {
+static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms,
+                           const std::map<int, std::pair<int, double>>* level_tile = nullptr) {
     Builder bw;
     bw.ex = ex;
+    bw.level_tile = level_tile;
     bw.grouping = ex->opts.no_group == 0;
     bw.quantize_tiles = n == 1;
     if (ex->opts.max_ksplit > 0) bw.max_ksplit = std::min(ex->opts.max_ksplit, 32);
@@ -1996,7 +2011,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         if (opts) ex->opts = *opts;
         else {
             ex->opts.mode = TN_MODE_BATCHED;
-            ex->opts.use_graph = 1;
+            ex->opts.use_graph = 0;
             ex->opts.fp64_level0 = 1;
         }
         if (ex->opts.time_kernels && ex->opts.use_graph)
@@ -2006,7 +2021,33 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             ex->opts.use_graph = 0;
             if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
         }
-        build_schedule(ex.get(), n, plans, terms);
+        if (n == 1 && ex->opts.mode != TN_MODE_PLAIN && !ex->opts.no_group && !ex->opts.mixed_shapes) {
+            // A level whose matrix-core jobs chose different tile shapes runs
+            // one launch per shape, one after the other.  The schedule is
+            // planned again with the shape carrying most of the level's flops
+            // imposed on the level's small jobs (each at most a quarter of
+            // that shape's flops), which then join its launch; large jobs keep
+            // their own shape (a forced shape costs them more than a launch).
+            // Packed circuits share every level's launches already and keep
+            // each job's shape (measured slower with the merge).
+            tn_exec_s probe;
+            probe.opts = ex->opts;
+            build_schedule(&probe, n, plans, terms);
+            std::map<int, std::map<int, double>> flops;   // level -> tile -> flops
+            for (const Launch& L : probe.launches)
+                if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) flops[L.level][L.mtile] += L.flops;
+            std::map<int, std::pair<int, double>> level_tile;
+            for (auto& kv : flops) {
+                if (kv.second.size() < 2) continue;
+                auto top = std::max_element(kv.second.begin(), kv.second.end(),
+                                            [](const std::pair<const int, double>& a,
+                                               const std::pair<const int, double>& b) { return a.second < b.second; });
+                level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
+            }
+            build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile);
+        } else {
+            build_schedule(ex.get(), n, plans, terms);
+        }
         const size_t need = (size_t)(ex->const_bytes + ex->work_bytes);
         if (need_bytes) *need_bytes = need;
         if (ws_bytes == 0) {

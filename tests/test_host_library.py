@@ -142,12 +142,14 @@ def grouped_by_positions(pat, x):
     return out
 
 
-def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True, max_ksplit=0):
+def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True, max_ksplit=0,
+            one_shape=True):
     plan = tn.tn_plan_build(circ, level)
     t = tn.tn_terms_enumerate(plan, level)
     desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
                                                                   fp64_level0=fp64, gather=gather,
-                                                                  group=group, max_ksplit=max_ksplit))
+                                                                  group=group, max_ksplit=max_ksplit,
+                                                                  one_shape_per_level=one_shape))
     pat, w = t.get()
     live = [i for i in range(t.n) if w[i] != 0.0]
     sim = Sim(desc, cb)
@@ -203,12 +205,21 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge
     assert {j["ksplit"] for L in desc_2["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1, 2}
     x_1, _, desc_1 = _replay(c, 2, max_ksplit=1)
     assert {j["ksplit"] for L in desc_1["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1}
+    x_m, _, desc_m = _replay(c, 2, one_shape=False)   # every job its own tile shape
+
+    def shapes_per_level(d):
+        lv = {}
+        for L in d["launches"]:
+            if L["kind"] == 6 and not L["fp64"]:
+                lv.setdefault(L["level"], set()).add((L["bm"], L["bn"]))
+        return lv
+    assert sum(map(len, shapes_per_level(desc).values())) <= sum(map(len, shapes_per_level(desc_m).values()))
     x_g, _, desc_g = _replay(c, 2, group=False)
     assert any(L["kind"] == 1 and L.get("gather") for L in desc_g["launches"]), "no gathered step"
     x_t, _, desc_t = _replay(c, 2, gather=False, group=False)
     assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
     x_p, _, desc_p = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
-    for v in (x, x_2, x_1, x_g, x_t, x_p):
+    for v in (x, x_2, x_1, x_m, x_g, x_t, x_p):
         assert np.allclose(v, r["X"], rtol=2e-5, atol=1e-10)
 
 
