@@ -187,6 +187,13 @@ struct tn_exec_s {
     int64_t fin_blocks = 0;
     int n_ls_jobs = 0;
     std::vector<tn::PlanExec> plans;
+    // results of an estimate gathered into one device buffer (level sums of
+    // every plan, then the FP32 all-dominant root values) and read back with
+    // one copy into pinned host memory
+    tn::Ref results_dev, gather_items;
+    std::vector<std::pair<tn::Ref, int32_t>> gather_src;   // source, 4-byte words
+    int64_t results_words = 0;
+    void* results_host = nullptr;
     tn::ConstBuf cbuf;
     int64_t const_bytes = 0, work_bytes = 0, work1_bytes = 0;
     hipStream_t side = nullptr;             // side stream for the FP64 pass (default priority)
@@ -1372,6 +1379,21 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         ex->tail.push_back(ls);
         ex->plans.push_back(std::move(pe));
     }
+    // result readback layout: per plan its (sum, comp) pairs, then per plan
+    // one complex64 per cluster root (the all-dominant term's FP32 value)
+    for (auto& pe : ex->plans) {
+        ex->gather_src.push_back({pe.sums, (int32_t)(4 * (pe.terms->level + 1))});
+        ex->results_words += 4 * (pe.terms->level + 1);
+    }
+    if (ex->opts.mode == TN_MODE_BATCHED)
+        for (auto& pe : ex->plans)
+            if (pe.zero_term >= 0)
+                for (const Ref& r : pe.root32) {
+                    ex->gather_src.push_back({r, 2});
+                    ex->results_words += 2;
+                }
+    ex->results_dev = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, ex->results_words) * 4)};
+    ex->gather_items = Ref{R_CONST, ex->cbuf.reserve((int64_t)ex->gather_src.size() * (int64_t)sizeof(GatherItem))};
     bw.emit(steps32, 0, true, &ex->launches);
     bw.emit(steps64, 1, true, &ex->launches64);
     if (n > 1) {
@@ -1495,6 +1517,19 @@ static void bind(tn_exec_s* ex) {
 }
 
 // packed circuits: the per-circuit finalize / level-sum records as two launches
+static void bind_gather(tn_exec_s* ex) {
+    GatherItem* it = (GatherItem*)(ex->cbuf.bytes.data() + ex->gather_items.off);
+    int32_t w = 0;
+    for (size_t i = 0; i < ex->gather_src.size(); ++i) {
+        GatherItem g{};
+        g.src = (const uint32_t*)resolve(ex, ex->gather_src[i].first);
+        g.words = ex->gather_src[i].second;
+        g.dst_word = w;
+        w += g.words;
+        std::memcpy(it + i, &g, sizeof(GatherItem));
+    }
+}
+
 static void bind_multi_tail(tn_exec_s* ex) {
     if (!ex->multi_tail) return;
     FinalizeArgs* fa = (FinalizeArgs*)(ex->cbuf.bytes.data() + ex->fin_args.off);
@@ -1706,6 +1741,8 @@ static void run_tail(tn_exec_s* ex, hipStream_t s) {
     } else {
         for (auto& L : ex->tail) enqueue(ex, L, s);
     }
+    launch_gather_words((const GatherItem*)resolve(ex, ex->gather_items), (int)ex->gather_src.size(),
+                        (uint32_t*)resolve(ex, ex->results_dev), s);
     HIPCHK(hipGetLastError());
 }
 
@@ -2068,6 +2105,8 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         HIPCHK(hipGetDevice(&ex->device));
         bind(ex.get());
         bind_multi_tail(ex.get());
+        bind_gather(ex.get());
+        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)std::max<int64_t>(1, ex->results_words) * 4, 0));
         if (!ex->launches64.empty()) {
             HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));
@@ -2115,6 +2154,9 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         } else {
             run_body(ex, s);
         }
+        if (results)
+            HIPCHK(hipMemcpyAsync(ex->results_host, resolve(ex, ex->results_dev), (size_t)ex->results_words * 4,
+                                  hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ex->ev1, s));
         HIPCHK(hipEventSynchronize(ex->ev1));
         float ms = 0;
@@ -2132,6 +2174,10 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
                 ex->kbytes[L.kclass] += L.bytes;
             }
         if (!results) return;
+        const double* res_sums = (const double*)ex->results_host;
+        const float* res_roots = (const float*)ex->results_host;
+        int64_t sum_at = 0, root_at = 0;   // doubles / floats into the readback
+        for (auto& pe : ex->plans) root_at += 4 * (pe.terms->level + 1);
         for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
             const PlanExec& pe = ex->plans[pi];
             const Plan& P = *pe.plan;
@@ -2143,8 +2189,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             r.n_terms = T.n;
             r.n_contracted = pe.n_live;
             r.n_zero_weight = pe.n_zero;
-            std::vector<double> sums(2 * (T.level + 1));
-            HIPCHK(hipMemcpy(sums.data(), resolve(ex, pe.sums), sums.size() * 8, hipMemcpyDeviceToHost));
+            std::vector<double> sums(res_sums + sum_at, res_sums + sum_at + 2 * (T.level + 1));
+            sum_at += 2 * (T.level + 1);
             double s = 0, c = 0;
             for (int u = 0; u <= T.level; ++u) {
                 r.level_sum[u] = sums[2 * u];
@@ -2174,8 +2220,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED) {
                 double ar = P.scalar.real(), ai = P.scalar.imag();
                 for (size_t c2 = 0; c2 < pe.root32.size(); ++c2) {
-                    float v[2];
-                    HIPCHK(hipMemcpy(v, resolve(ex, pe.root32[c2]), 8, hipMemcpyDeviceToHost));
+                    const float* v = res_roots + root_at;
+                    root_at += 2;
                     double nr = ar * v[0] - ai * v[1], ni = ar * v[1] + ai * v[0];
                     ar = nr;
                     ai = ni;
@@ -2283,6 +2329,7 @@ void tn_exec_destroy(tn_exec exh) {
             if (L.ev_a) (void)hipEventDestroy(L.ev_a);
             if (L.ev_b) (void)hipEventDestroy(L.ev_b);
         }
+    if (ex->results_host) (void)hipHostFree(ex->results_host);
     if (ex->ev_fork) (void)hipEventDestroy(ex->ev_fork);
     if (ex->ev_join) (void)hipEventDestroy(ex->ev_join);
     if (ex->side) (void)hipStreamDestroy(ex->side);

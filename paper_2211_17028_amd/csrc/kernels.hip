@@ -1662,6 +1662,19 @@ void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s
     hipLaunchKernelGGL(k_level_sum_multi, dim3(n_jobs), dim3(256), 0, s, d_jobs);
 }
 
+__global__ __launch_bounds__(256) void k_gather_words(const GatherItem* __restrict__ items, int n_items,
+                                                      uint32_t* __restrict__ dst) {
+    for (int i = 0; i < n_items; ++i) {
+        const GatherItem it = items[i];
+        for (int w = threadIdx.x; w < it.words; w += 256) dst[it.dst_word + w] = it.src[w];
+    }
+}
+
+void launch_gather_words(const GatherItem* d_items, int n_items, uint32_t* dst, hipStream_t s) {
+    if (n_items == 0) return;
+    hipLaunchKernelGGL(k_gather_words, dim3(1), dim3(256), 0, s, d_items, n_items, dst);
+}
+
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_level_sum, dim3(n_levels), dim3(256), 0, s, x, starts, out);
