@@ -255,6 +255,17 @@ constexpr int kSplitDefaultMax = 16;
 // tile shape takes that shape, so that it runs in the main launch.
 constexpr double kSmallJobShare = 0.25;
 
+// Long inner sums of small steps: one block per output element when that is
+// the shorter chain of dependent loads (a thread-per-output sum runs k / 4
+// rounds; a block per output k / 2048 rounds plus its reduction, over the
+// outputs in batches of ~2048 resident blocks).
+static bool split_by_block(int k_log, int64_t outs) {
+    const double kk = std::ldexp(1.0, k_log);
+    const double t_thread = kk / 4.0;
+    const double t_block = std::ceil((double)outs / 2048.0) * (kk / 2048.0 + 3.0);
+    return t_block < t_thread;
+}
+
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
     Ref a, b, c, oa, ob;
@@ -883,6 +894,23 @@ struct Builder {
                 const NodeInfo& big_op = bytesR >= bytesQ ? R : Q;
                 std::vector<int> row_bits = by_pos(FR, R), col_bits = by_pos(FQ, Q);
                 std::vector<int> k_bits = by_pos(K, big_op), bt_bits = by_pos(Bt, big_op);
+                const int64_t outs_n = (ninst * nbatch) << (FR.size() + FQ.size());
+                const bool split_sum = rk >= 8 && split_by_block(rk, outs_n);
+                if (split_sum) {
+                    // one block per output: consecutive threads take consecutive
+                    // logical inner indices, so the lowest logical bits are the
+                    // three lowest stored inner bits of each operand (a wave's 64
+                    // lanes then read runs of 8 adjacent elements of both)
+                    const std::vector<int> kr = by_pos(K, R), kq = by_pos(K, Q);
+                    std::vector<int> ord;
+                    auto take = [&](int leg) {
+                        if (std::find(ord.begin(), ord.end(), leg) == ord.end()) ord.push_back(leg);
+                    };
+                    for (size_t q = 0; q < kr.size() && q < 3; ++q) take(kr[q]);
+                    for (size_t q = 0; q < kq.size() && ord.size() < 6; ++q) take(kq[q]);
+                    for (int leg : k_bits) take(leg);
+                    k_bits = ord;
+                }
                 C.legs.assign(bt_bits.rbegin(), bt_bits.rend());
                 C.legs.insert(C.legs.end(), row_bits.rbegin(), row_bits.rend());
                 C.legs.insert(C.legs.end(), col_bits.rbegin(), col_bits.rend());
@@ -896,17 +924,7 @@ struct Builder {
                 jb.n_log = (int)FQ.size();
                 jb.k_log = rk;
                 jb.n_inst = ninst * nbatch;
-                // long inner sums: one block per output element when that is the
-                // shorter chain of dependent loads (a thread-per-output sum runs
-                // k / 4 rounds; a block per output k / 2048 rounds plus its
-                // reduction, over the outputs in batches of ~2048 resident blocks)
-                {
-                    const double kk = std::ldexp(1.0, rk);
-                    const double outs = std::ldexp((double)jb.n_inst, jb.m_log + jb.n_log);
-                    const double t_thread = kk / 4.0;
-                    const double t_block = std::ceil(outs / 2048.0) * (kk / 2048.0 + 3.0);
-                    jb.split = (rk >= 8 && t_block < t_thread) ? 1 : 0;
-                }
+                jb.split = split_sum ? 1 : 0;
                 // rows per thread: the column operand's elements are reused across
                 // them (up to 8; 1 for outer products, where there is no reuse)
                 jb.rpt_log = jb.split || rk == 0 ? 0 : std::min(jb.m_log, 3);
