@@ -254,6 +254,9 @@ constexpr int kSplitDefaultMax = 16;
 // A matrix-core job with at most this share of the flops of its level's main
 // tile shape takes that shape, so that it runs in the main launch.
 constexpr double kSmallJobShare = 0.25;
+// One launch in tile-model units (the 25-qubit workload's 512-tile 128 x 64
+// launch of k = 8 models at 1.0e8 and runs 15 us; a launch costs about 5 us).
+constexpr double kLaunchCost = 3.5e7;
 
 // Long inner sums of small steps: one block per output element when that is
 // the shorter chain of dependent loads (a thread-per-output sum runs k / 4
@@ -428,8 +431,14 @@ struct Builder {
             }
             return c;
         };
-        double best_cost = 1e300;
-        int best_o = 0, best_tile = 0, best_merge = 0;
+        int forced = -1;
+        if (!fp64 && level_tile && level_tile->count(st.level)) {
+            const std::pair<int, double>& lt = level_tile->at(st.level);
+            const double job_flops = 8.0 * std::ldexp((double)ns, (int)(FA.size() + FB.size()) + rk);
+            if (job_flops <= lt.second) forced = lt.first;
+        }
+        double best_cost = 1e300, forced_cost = 1e300;
+        int best_o = 0, best_tile = 0, best_merge = 0, forced_o = 0, forced_merge = 0;
         for (int o = 0; o < 2; ++o) {
             const NodeInfo& R = o ? B : A;
             const NodeInfo& Q = o ? A : B;
@@ -439,15 +448,9 @@ struct Builder {
             so[o][0] = slice_vec(R, btb[o]);
             so[o][1] = slice_vec(Q, btb[o]);
             const std::vector<int64_t> ca = run_counts(so[o][0]), cb = run_counts(so[o][1]);
-            int forced = -1;
-            if (!fp64 && level_tile && level_tile->count(st.level)) {
-                const std::pair<int, double>& lt = level_tile->at(st.level);
-                const double job_flops = 8.0 * std::ldexp((double)ns, (int)(FA.size() + FB.size()) + rk);
-                if (job_flops <= lt.second) forced = lt.first;
-            }
             for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
                 if (fp64 && tile != 1 && tile != 4) continue;
-                if (forced >= 0 && tile != forced) continue;
+
                 const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
                 const int64_t rt = m_log >= bm_log ? int64_t(1) << (m_log - bm_log) : 1;
                 const int64_t ct = n_log >= bn_log ? int64_t(1) << (n_log - bn_log) : 1;
@@ -469,6 +472,11 @@ struct Builder {
                         best_tile = tile;
                         best_merge = merge;
                     }
+                    if (tile == forced && cst < forced_cost) {
+                        forced_cost = cst;
+                        forced_o = o;
+                        forced_merge = merge;
+                    }
                 };
                 consider(ns * rt * ct, 0);
                 if (n_log < bn_log) {
@@ -484,6 +492,13 @@ struct Builder {
                     consider(t * ct, 2);
                 }
             }
+        }
+        // a shape imposed by the level takes over when it costs this job at most
+        // about one launch more than its own best shape (the launch it saves)
+        if (forced >= 0 && forced_cost <= best_cost + kLaunchCost) {
+            best_o = forced_o;
+            best_tile = forced;
+            best_merge = forced_merge;
         }
         const int o = best_o;
         const NodeInfo& R = o ? B : A;
