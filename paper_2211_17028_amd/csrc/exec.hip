@@ -96,7 +96,9 @@ struct ConstBuf {
     int64_t reserve(int64_t n) { return add(nullptr, n); }
 };
 
-enum Region { R_CONST = 0, R_WORK = 1, R_WORK2 = 2 };   // R_WORK2: the FP64 pass (side stream)
+// R_WORK2: the FP64 pass (side stream); R_HOST: pinned host memory the tail
+// kernels write the estimate's results into (level sums, FP32 root value)
+enum Region { R_CONST = 0, R_WORK = 1, R_WORK2 = 2, R_HOST = 3 };
 struct Ref {
     int region = R_CONST;
     int64_t off = 0;
@@ -150,7 +152,7 @@ struct PlanExec {
     int64_t n_terms = 0, n_live = 0;
     int64_t zero_term = -1;
     std::vector<int64_t> level_start;
-    Ref x_out, amp_out, sums;
+    Ref x_out, amp_out, sums, x0;  // x0: FP32 value of the all-dominant term (diagnostic)
     std::vector<Ref> root32;       // per cluster root buffer (FP32 batch)
     std::vector<int64_t> root32_inst;
     std::vector<Ref> root64;
@@ -187,13 +189,11 @@ struct tn_exec_s {
     int64_t fin_blocks = 0;
     int n_ls_jobs = 0;
     std::vector<tn::PlanExec> plans;
-    // results of an estimate gathered into one device buffer (level sums of
-    // every plan, then the FP32 all-dominant root values) and read back with
-    // one copy into pinned host memory
-    tn::Ref results_dev, gather_items;
-    std::vector<std::pair<tn::Ref, int32_t>> gather_src;   // source, 4-byte words
-    int64_t results_words = 0;
-    void* results_host = nullptr;
+    // results of an estimate (level sums, FP32 all-dominant value of every
+    // plan), written by the tail kernels into pinned host memory
+    int64_t results_bytes = 0;
+    void* results_host = nullptr;      // host address
+    void* results_dev = nullptr;       // the same memory as the device addresses it
     tn::ConstBuf cbuf;
     int64_t const_bytes = 0, work_bytes = 0, work1_bytes = 0;
     hipStream_t side = nullptr;             // side stream for the FP64 pass (default priority)
@@ -1375,7 +1375,9 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         for (int64_t t = 0; t < T.n; ++t) what[t] = std::ldexp(T.w[t], -P.n_noise);
         pe.x_out = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, T.n) * 8)};
         pe.amp_out = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, T.n) * 8)};
-        pe.sums = Ref{R_CONST, ex->cbuf.reserve((T.level + 1) * 16)};
+        pe.sums = Ref{R_HOST, ex->results_bytes};
+        pe.x0 = Ref{R_HOST, ex->results_bytes + (T.level + 1) * 16};
+        ex->results_bytes += (T.level + 1) * 16 + 8;
         Launch fl;
         fl.kind = L_FINALIZE;
         fl.plan = pi;
@@ -1412,21 +1414,6 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         ex->tail.push_back(ls);
         ex->plans.push_back(std::move(pe));
     }
-    // result readback layout: per plan its (sum, comp) pairs, then per plan
-    // one complex64 per cluster root (the all-dominant term's FP32 value)
-    for (auto& pe : ex->plans) {
-        ex->gather_src.push_back({pe.sums, (int32_t)(4 * (pe.terms->level + 1))});
-        ex->results_words += 4 * (pe.terms->level + 1);
-    }
-    if (ex->opts.mode == TN_MODE_BATCHED)
-        for (auto& pe : ex->plans)
-            if (pe.zero_term >= 0)
-                for (const Ref& r : pe.root32) {
-                    ex->gather_src.push_back({r, 2});
-                    ex->results_words += 2;
-                }
-    ex->results_dev = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, ex->results_words) * 4)};
-    ex->gather_items = Ref{R_CONST, ex->cbuf.reserve((int64_t)ex->gather_src.size() * (int64_t)sizeof(GatherItem))};
     bw.emit(steps32, 0, true, &ex->launches);
     bw.emit(steps64, 1, true, &ex->launches64);
     if (n > 1) {
@@ -1443,6 +1430,7 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
 }
 
 static void* resolve(tn_exec_s* ex, const Ref& r) {
+    if (r.region == R_HOST) return (char*)ex->results_dev + r.off;
     const int64_t region_off = r.region == R_CONST ? 0
                                : r.region == R_WORK ? ex->const_bytes
                                                     : ex->const_bytes + ex->work1_bytes;
@@ -1545,24 +1533,13 @@ static void bind(tn_exec_s* ex) {
             L.f.w = (const double*)resolve(ex, L.w);
             L.f.x_out = (double*)resolve(ex, L.x_out);
             L.f.amp_out = (float*)resolve(ex, L.amp_out);
+            L.f.x0_fp32_out = (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED)
+                                  ? (double*)resolve(ex, pe.x0) : nullptr;
         }
     }
 }
 
 // packed circuits: the per-circuit finalize / level-sum records as two launches
-static void bind_gather(tn_exec_s* ex) {
-    GatherItem* it = (GatherItem*)(ex->cbuf.bytes.data() + ex->gather_items.off);
-    int32_t w = 0;
-    for (size_t i = 0; i < ex->gather_src.size(); ++i) {
-        GatherItem g{};
-        g.src = (const uint32_t*)resolve(ex, ex->gather_src[i].first);
-        g.words = ex->gather_src[i].second;
-        g.dst_word = w;
-        w += g.words;
-        std::memcpy(it + i, &g, sizeof(GatherItem));
-    }
-}
-
 static void bind_multi_tail(tn_exec_s* ex) {
     if (!ex->multi_tail) return;
     FinalizeArgs* fa = (FinalizeArgs*)(ex->cbuf.bytes.data() + ex->fin_args.off);
@@ -1774,8 +1751,6 @@ static void run_tail(tn_exec_s* ex, hipStream_t s) {
     } else {
         for (auto& L : ex->tail) enqueue(ex, L, s);
     }
-    launch_gather_words((const GatherItem*)resolve(ex, ex->gather_items), (int)ex->gather_src.size(),
-                        (uint32_t*)resolve(ex, ex->results_dev), s);
     HIPCHK(hipGetLastError());
 }
 
@@ -2136,10 +2111,11 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
         HIPCHK(hipGetDevice(&ex->device));
+        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)std::max<int64_t>(8, ex->results_bytes),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer(&ex->results_dev, ex->results_host, 0));
         bind(ex.get());
         bind_multi_tail(ex.get());
-        bind_gather(ex.get());
-        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)std::max<int64_t>(1, ex->results_words) * 4, 0));
         if (!ex->launches64.empty()) {
             HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));
@@ -2187,9 +2163,6 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         } else {
             run_body(ex, s);
         }
-        if (results)
-            HIPCHK(hipMemcpyAsync(ex->results_host, resolve(ex, ex->results_dev), (size_t)ex->results_words * 4,
-                                  hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ex->ev1, s));
         HIPCHK(hipEventSynchronize(ex->ev1));
         float ms = 0;
@@ -2207,10 +2180,6 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
                 ex->kbytes[L.kclass] += L.bytes;
             }
         if (!results) return;
-        const double* res_sums = (const double*)ex->results_host;
-        const float* res_roots = (const float*)ex->results_host;
-        int64_t sum_at = 0, root_at = 0;   // doubles / floats into the readback
-        for (auto& pe : ex->plans) root_at += 4 * (pe.terms->level + 1);
         for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
             const PlanExec& pe = ex->plans[pi];
             const Plan& P = *pe.plan;
@@ -2222,8 +2191,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             r.n_terms = T.n;
             r.n_contracted = pe.n_live;
             r.n_zero_weight = pe.n_zero;
-            std::vector<double> sums(res_sums + sum_at, res_sums + sum_at + 2 * (T.level + 1));
-            sum_at += 2 * (T.level + 1);
+            const double* hs = (const double*)((const char*)ex->results_host + pe.sums.off);
+            std::vector<double> sums(hs, hs + 2 * (T.level + 1));
             double s = 0, c = 0;
             for (int u = 0; u <= T.level; ++u) {
                 r.level_sum[u] = sums[2 * u];
@@ -2248,19 +2217,10 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             double b = 0;
             for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
             r.bound = b;
-            // FP32 value of the all-dominant term (diagnostic)
+            // FP32 value of the all-dominant term (diagnostic, written by the finalize)
             r.x0_fp32 = -1;
-            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED) {
-                double ar = P.scalar.real(), ai = P.scalar.imag();
-                for (size_t c2 = 0; c2 < pe.root32.size(); ++c2) {
-                    const float* v = res_roots + root_at;
-                    root_at += 2;
-                    double nr = ar * v[0] - ai * v[1], ni = ar * v[1] + ai * v[0];
-                    ar = nr;
-                    ai = ni;
-                }
-                r.x0_fp32 = std::ldexp(T.w[0], -P.n_noise) * (ar * ar + ai * ai);
-            }
+            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED)
+                r.x0_fp32 = *(const double*)((const char*)ex->results_host + pe.x0.off);
         }
     });
 }

@@ -161,6 +161,7 @@ struct FinalizeArgs {
     const double* w;               // n_terms scaled weights
     double* x_out;                 // n_terms
     float* amp_out;                // 2 * n_terms
+    double* x0_fp32_out;           // X of the zero term from the FP32 roots (diagnostic) or null
 };
 void launch_finalize(const FinalizeArgs& f, hipStream_t s);
 // packed circuits: one launch; d_block0[i] = first block of circuit i (256 terms per block)
@@ -175,14 +176,6 @@ struct LevelSumJob {               // one (circuit, level) block of a packed lev
 void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s);
 
 // Neumaier level sums over contiguous ranges [start[u], start[u+1]).
-// Result readback: copies n_items runs of 4-byte words into one buffer (one
-// block, words in item order), so the host reads every result of an
-// estimate with one copy.
-struct GatherItem {
-    const uint32_t* src;
-    int32_t words, dst_word;
-};
-void launch_gather_words(const GatherItem* d_items, int n_items, uint32_t* dst, hipStream_t s);
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,
                       hipStream_t s);
 

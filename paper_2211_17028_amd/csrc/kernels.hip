@@ -1371,6 +1371,18 @@ __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) 
     f.x_out[t] = f.w[t] * (ar * ar + ai * ai);
     f.amp_out[2 * t] = (float)ar;
     f.amp_out[2 * t + 1] = (float)ai;
+    if (hi && f.x0_fp32_out) {
+        // the same term from the FP32 batch's roots (diagnostic)
+        double br = f.scalar_re, bi = f.scalar_im;
+        for (int c = 0; c < f.n_clusters; ++c) {
+            const float2 v = ((const float2*)f.root_ptrs[c])[f.root_idx[(int64_t)li * f.n_clusters + c]];
+            const double nr = br * v.x - bi * v.y;
+            const double ni = br * v.y + bi * v.x;
+            br = nr;
+            bi = ni;
+        }
+        *f.x0_fp32_out = f.w[t] * (br * br + bi * bi);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
@@ -1660,19 +1672,6 @@ void launch_finalize_multi(const FinalizeArgs* d_args, const int64_t* d_block0, 
 void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s) {
     if (n_jobs == 0) return;
     hipLaunchKernelGGL(k_level_sum_multi, dim3(n_jobs), dim3(256), 0, s, d_jobs);
-}
-
-__global__ __launch_bounds__(256) void k_gather_words(const GatherItem* __restrict__ items, int n_items,
-                                                      uint32_t* __restrict__ dst) {
-    for (int i = 0; i < n_items; ++i) {
-        const GatherItem it = items[i];
-        for (int w = threadIdx.x; w < it.words; w += 256) dst[it.dst_word + w] = it.src[w];
-    }
-}
-
-void launch_gather_words(const GatherItem* d_items, int n_items, uint32_t* dst, hipStream_t s) {
-    if (n_items == 0) return;
-    hipLaunchKernelGGL(k_gather_words, dim3(1), dim3(256), 0, s, d_items, n_items, dst);
 }
 
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,

@@ -207,6 +207,9 @@ def test_config2_full_size_sampled_terms(torch):
         vals = np.loadtxt(gold)
         for u in range(3):
             assert abs(res["A"][u] - vals[u]) <= 1e-6 * vals[u], (u, res["A"][u], vals[u])
+    # the all-dominant term from the FP32 batch (diagnostic, written by the finalize)
+    # agrees with its FP64 value to FP32 accuracy
+    assert abs(res["x0_fp32"] - x[0]) <= 2e-5 * x[0], (res["x0_fp32"], x[0])
 
 
 ETA32 = 2.0 ** -18   # FP32 amplitude error per unit of the slot-norm product (64 u32)
