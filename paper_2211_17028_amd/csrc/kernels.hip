@@ -689,23 +689,32 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     const bool to_partial = J.ksplit > 1;
     TN_GLOBAL float* __restrict__ O =
         to_partial ? gstore<float>(J.partial) + ((int64_t)T.pair * J.ksplit + T.kpart) * (2 * BM * BNC) : C;
+    // output offsets of this lane's 16 rows and TN columns read ahead of the
+    // stores (one LDS wait per row block instead of one per store)
+    const int part = sub & 1;
+    int64_t ccs[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) {
+        const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
+        ccs[j] = to_partial ? (col_c[col] < 0 ? -1 : col) : col_c[col];
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        int64_t rcs[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const int64_t rc = row_c[row];
+            rcs[r] = to_partial ? (rc < 0 ? -1 : (int64_t)row * BNC) : rc;
+        }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-            const int col = wn * (TN * 16) + j * 16 + (sub >> 1);
-            const int64_t cc = col_c[col];
-            if (cc < 0) continue;
-            const int part = sub & 1;
+            if (ccs[j] < 0) continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = wm * (TM * 32) + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                const int64_t rc = row_c[row];
-                if (rc < 0) continue;
-                const int64_t o = to_partial ? (int64_t)row * BNC + col : rc + cc;
-                O[2 * o + part] = acc[i][j][r];
-            }
+            for (int r = 0; r < 16; ++r)
+                if (rcs[r] >= 0) O[2 * (rcs[r] + ccs[j]) + part] = acc[i][j][r];
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
