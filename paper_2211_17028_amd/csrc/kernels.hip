@@ -464,8 +464,11 @@ void k_gemm_mfma_g(GemmArgs g) {
 // operand can fill one tile (merge modes) and any stored layout is read
 // without a transpose pass.
 // ---------------------------------------------------------------------------
+// (the one-wave 64 x 32 tile is held to two waves per SIMD, which it reaches
+// without spilling)
 template <int BM, int BNC>
-__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1), MFMA_GROUP_WAVES)
+__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1),
+                             (BM == 64 && BNC == 32) ? 2 : MFMA_GROUP_WAVES)
 void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__ tiles) {
     constexpr int WM = BM >= 64 ? BM / 64 : 1;
     constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
@@ -477,13 +480,14 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     constexpr int AE = BM * BKC / NT;
     constexpr int BE = (BKC * BNC + NT - 1) / NT;
     // LDS staging, flat: A as [half][p][row] (half 0 real, 1 imaginary parts),
-    // B in its real embedding as [half][p][2 col + t] (half 0: re, im; half 1:
-    // -im, re), so every lane reads its MFMA operand with one 4-byte load.  Row
-    // pitch +8 words keeps k-fast staging writes (8 rows x 8 inner indices per
-    // 64 lanes) in distinct banks; the +32-word gap between halves keeps the two
-    // half-waves' reads apart.
+    // B once as [p][2 col + t] (re, im).  The real embedding's second B row
+    // (-im, re) is read by the upper half-wave as the swapped pair with the
+    // real-part slot negated, so every lane reads its MFMA operand with one
+    // 4-byte load and B is staged once.  Row pitch +8 words keeps k-fast
+    // staging writes (8 rows x 8 inner indices per 64 lanes) in distinct banks;
+    // the +32-word gap between A's halves keeps the two half-waves' reads apart.
     constexpr int AP = BM + 8, AH = BKC * AP + 32, ABUF = 2 * AH;
-    constexpr int BP = 2 * BNC + 8, BH = BKC * BP + 32, BBUF = 2 * BH;
+    constexpr int BP = 2 * BNC + 8, BBUF = BKC * BP;
     __shared__ __align__(16) float As[2 * ABUF];
     __shared__ __align__(16) float Bs[2 * BBUF];
     __shared__ int64_t row_a[BM], row_c[BM], col_b[BNC], col_c[BNC], ak_lo[BKC], bk_lo[BKC];
@@ -627,9 +631,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
             if (e < BKC * BNC) {
                 int p, c;
                 b_pc(e, p, c);
-                const float2 v = boff[q] >= 0 ? rb[q] : make_float2(0.0f, 0.0f);
-                *(float2*)&bs[p * BP + 2 * c] = v;
-                *(float2*)&bs[BH + p * BP + 2 * c] = make_float2(-v.y, v.x);
+                *(float2*)&bs[p * BP + 2 * c] = boff[q] >= 0 ? rb[q] : make_float2(0.0f, 0.0f);
             }
         }
     };
@@ -638,7 +640,8 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
 #pragma unroll
     for (int i = 0; i < TM; ++i) a_off[i] = half * AH + wm * (TM * 32) + i * 32 + sub;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) b_off[j] = half * BH + 2 * (wn * (TN * 16) + j * 16) + sub;
+    for (int j = 0; j < TN; ++j) b_off[j] = 2 * (wn * (TN * 16) + j * 16) + (half ? (sub ^ 1) : sub);
+    const uint32_t b_sign = (half && !(sub & 1)) ? 0x80000000u : 0u;
     auto compute = [&](int buf) {
         const float* as = As + buf * ABUF;
         const float* bs = Bs + buf * BBUF;
@@ -650,7 +653,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
 #pragma unroll
             for (int i = 0; i < TM; ++i) a[p][i] = as[p * AP + a_off[i]];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) b[p][j] = bs[p * BP + b_off[j]];
+            for (int j = 0; j < TN; ++j) b[p][j] = __uint_as_float(__float_as_uint(bs[p * BP + b_off[j]]) ^ b_sign);
         }
 #pragma unroll
         for (int p = 0; p < BKC; ++p)
