@@ -15,8 +15,10 @@ Modules
                state vectors (small n)
   network   -- Algorithm 1 term by term with one network per term, contracted
                pairwise with its own light-cone reduction and greedy order
+  doubled   -- the exact baseline: the doubled (ket + bra) network with every
+               noise as its full superoperator tensor, contracted pairwise
   bounds    -- Theorem 1 (contraction count; error bound in the form its proof
                actually establishes)
   estimate  -- driver: T_u, A(l) for every l' <= l, per-term values
 """
-from . import channels, terms, dense, literal, network, bounds, estimate  # noqa: F401
+from . import channels, terms, dense, literal, network, doubled, bounds, estimate  # noqa: F401
