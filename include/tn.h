@@ -189,6 +189,29 @@ int tn_plan_build(const tn_circuit* circ, const tn_state* psi, const tn_state* v
                   int32_t level, const tn_plan_opts* opts, tn_plan* out);
 
 /* ---------------------------------------------------------------------------
+ * tn_plan_build_doubled -- the exact value <v| E(|psi><psi|) |v> as one
+ * network: the paper's exact baseline (the doubled network of Section IV,
+ * Fig. 2), in which every noise is its full superoperator
+ * M = sum_k E_k (x) conj(E_k) (Section III) joining the ket and bra halves.
+ * Built from the same reduced ket network as tn_plan_build (the bra half is
+ * its complex conjugate), with each noise slot pair replaced by the 4-leg
+ * tensor T[ko][ki][bo][bi] = sum_k E_k[ko][ki] conj(E_k[bo][bi]).  No noise is
+ * split, so a degenerate channel is accepted.  Host only.
+ *
+ * The plan has no slots: tn_terms_enumerate (any level) gives one term of
+ * weight 1, and an estimate over it reports the exact value as level_sum[0] =
+ * A[0] with bound 0 (computed in FP64 when fp64_level0 is set, which
+ * tn_estimate always does; in FP32 otherwise).  The doubled network's tensors
+ * are about the square of the ket network's, so max_log_size and
+ * max_work_bytes decide which circuits fit.
+ *
+ * Arguments as tn_plan_build (no level).  Errors: TN_EINVAL, TN_ENOTCPTP,
+ * TN_EUNSUPPORTED, TN_ETOOBIG as tn_plan_build.
+ * ------------------------------------------------------------------------- */
+int tn_plan_build_doubled(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                          const tn_plan_opts* opts, tn_plan* out);
+
+/* ---------------------------------------------------------------------------
  * tn_terms_enumerate -- the term set of Algorithm 1 at level `level`:
  * u = 0..level; noise subsets p_1 < ... < p_u in lexicographic order; the
  * corrections (i_1..i_u) in {1,2,3}^u in lexicographic order.  Count:
@@ -275,6 +298,8 @@ typedef struct {
     int32_t n_leaves;              /* tensors of the reduced ket network */
     int32_t max_log_size;          /* largest path tensor, log2 elements (one instance) */
     double flops_per_term;         /* 8 * sum of complex MACs of the path, one term */
+    int32_t doubled;               /* 1: built by tn_plan_build_doubled */
+    int32_t n_channels;            /* noise channels of the circuit */
 } tn_plan_info;
 
 int tn_plan_get_info(tn_plan plan, tn_plan_info* info);

@@ -1386,6 +1386,7 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         fl.f.zero_term = pe.root64.empty() ? -1 : pe.zero_term;
         fl.f.scalar_re = P.scalar.real();
         fl.f.scalar_im = P.scalar.imag();
+        fl.f.re_value = P.doubled ? 1 : 0;
         fl.live_index = Ref{R_CONST, ex->cbuf.add(live_index.data(), std::max<int64_t>(1, T.n) * 4)};
         fl.root_idx = Ref{R_CONST, ex->cbuf.add(root_idx.data(), (int64_t)root_idx.size() * 4)};
         fl.root_ptrs = Ref{R_CONST, ex->cbuf.reserve(std::max(1, ncl) * 8)};
@@ -1822,7 +1823,7 @@ static void autotune(tn_exec_s* ex) {
 
 static std::string describe_exec(const tn_exec_s* ex) {
     std::ostringstream os;
-    os.precision(10);
+    os.precision(17);
     os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
        << ",\"work1_bytes\":" << ex->work1_bytes
        << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms << ",\"launches\":[";
@@ -1852,7 +1853,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
         if (L.kind == L_FINALIZE)
             os << ",\"n_terms\":" << L.f.n_terms << ",\"n_clusters\":" << L.f.n_clusters << ",\"zero_term\":"
                << L.f.zero_term << ",\"scalar\":[" << L.f.scalar_re << "," << L.f.scalar_im
-               << "],\"live_index\":" << L.live_index.off << ",\"root_idx\":" << L.root_idx.off
+               << "],\"re_value\":" << L.f.re_value << ",\"live_index\":" << L.live_index.off << ",\"root_idx\":" << L.root_idx.off
                << ",\"w\":" << L.w.off << ",\"x_out\":" << L.x_out.off << ",\"amp_out\":" << L.amp_out.off;
         if (L.kind == L_LEVELSUM)
             os << ",\"n_levels\":" << L.n_levels << ",\"starts\":" << L.starts.off << ",\"x_out\":"
@@ -1987,6 +1988,14 @@ int tn_plan_build(const tn_circuit* circ, const tn_state* psi, const tn_state* v
     });
 }
 
+int tn_plan_build_doubled(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                          const tn_plan_opts* opts, tn_plan* out) {
+    return guard([&] {
+        if (!out) fail(TN_EINVAL, "null output handle");
+        *out = reinterpret_cast<tn_plan>(build_plan_doubled(circ, psi, v, opts));
+    });
+}
+
 int tn_terms_enumerate(tn_plan plan, int32_t level, const tn_prune_opts* prune, tn_terms* out,
                        int64_t* n_terms) {
     return guard([&] {
@@ -2018,6 +2027,8 @@ int tn_plan_get_info(tn_plan plan, tn_plan_info* info) {
         info->n_leaves = (int32_t)p->leaves.size();
         info->max_log_size = p->max_log;
         info->flops_per_term = 8.0 * p->cmacs_per_term;
+        info->doubled = p->doubled ? 1 : 0;
+        info->n_channels = p->doubled ? p->n_channels : p->n_noise;
     });
 }
 

@@ -162,6 +162,8 @@ struct FinalizeArgs {
     double* x_out;                 // n_terms
     float* amp_out;                // 2 * n_terms
     double* x0_fp32_out;           // X of the zero term from the FP32 roots (diagnostic) or null
+    int32_t re_value;              // 1: X = w Re(a) (doubled network), 0: X = w |a|^2
+    int32_t pad_;
 };
 void launch_finalize(const FinalizeArgs& f, hipStream_t s);
 // packed circuits: one launch; d_block0[i] = first block of circuit i (256 terms per block)

@@ -1351,7 +1351,8 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 
 // ---------------------------------------------------------------------------
 // K3: per-term finalize (FP64): amplitude = scalar * prod of cluster values,
-// X = w |amplitude|^2.
+// X = w |amplitude|^2 (a doubled network's value is the amplitude itself:
+// X = w Re(amplitude)).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) {
     const int32_t li = f.live_index[t];
@@ -1380,7 +1381,7 @@ __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) 
         ar = nr;
         ai = ni;
     }
-    f.x_out[t] = f.w[t] * (ar * ar + ai * ai);
+    f.x_out[t] = f.w[t] * (f.re_value ? ar : ar * ar + ai * ai);
     f.amp_out[2 * t] = (float)ar;
     f.amp_out[2 * t + 1] = (float)ai;
     if (hi && f.x0_fp32_out) {
@@ -1393,7 +1394,7 @@ __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) 
             br = nr;
             bi = ni;
         }
-        *f.x0_fp32_out = f.w[t] * (br * br + bi * bi);
+        *f.x0_fp32_out = f.w[t] * (f.re_value ? br : br * br + bi * bi);
     }
 }
 

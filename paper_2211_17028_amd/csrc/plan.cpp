@@ -117,11 +117,8 @@ double spectral_norm4(const cd a[4][4]) {
 // ---------------------------------------------------------------------------
 // noise split
 // ---------------------------------------------------------------------------
-static NoiseSplit split_noise(const tn_op& op, int64_t index) {
-    NoiseSplit ns;
-    ns.qubit = op.q[0];
-    ns.op_index = index;
-    // trace preservation (Section II): sum_k E_k^+ E_k = I
+// trace preservation (Section II): sum_k E_k^+ E_k = I
+static void check_cptp(const tn_op& op, int64_t index) {
     cd tp[2][2] = {{0, 0}, {0, 0}};
     for (int k = 0; k < op.n_kraus; ++k) {
         const tn_c128* e = op.mat + 4 * k;
@@ -139,6 +136,13 @@ static NoiseSplit split_noise(const tn_op& op, int64_t index) {
         os << "noise at op " << index << " is not trace preserving: max|sum E^+E - I| = " << res;
         fail(TN_ENOTCPTP, os.str());
     }
+}
+
+static NoiseSplit split_noise(const tn_op& op, int64_t index) {
+    NoiseSplit ns;
+    ns.qubit = op.q[0];
+    ns.op_index = index;
+    check_cptp(op, index);
     // M = sum_k E_k (x) conj(E_k); rows (a,b) = 2a+b (ket a, bra b)
     cd m[4][4];
     for (int i = 0; i < 4; ++i)
@@ -1034,15 +1038,15 @@ static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, doubl
 
 static std::atomic<uint64_t> g_plan_id{1};
 
-Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, int level,
-                 const tn_plan_opts* opts) {
+// Argument checks shared by both plan kinds: shapes, indices, unitary gates,
+// Kraus counts (trace preservation is checked by the callers).
+static std::unique_ptr<Plan> new_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v) {
     if (!c || !psi || !v) fail(TN_EINVAL, "null circuit or state");
     if (c->n_qubits < 1 || c->n_qubits > 4096) fail(TN_EINVAL, "n_qubits out of range");
     if (c->n_ops < 0 || (c->n_ops > 0 && !c->ops)) fail(TN_EINVAL, "bad op list");
     if (psi->kind != TN_STATE_PRODUCT || !psi->data) fail(TN_EINVAL, "psi must be a product state");
     if (v->kind < 0 || v->kind > 2 || !v->data) fail(TN_EINVAL, "bad target state");
     if (v->kind == TN_STATE_DENSE && c->n_qubits > 30) fail(TN_EINVAL, "dense target needs n <= 30");
-    if (level < 0) fail(TN_EINVAL, "level must be >= 0");
     auto p = std::make_unique<Plan>();
     p->id = g_plan_id++;
     p->n_qubits = c->n_qubits;
@@ -1059,15 +1063,38 @@ Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, in
             if (op.q[i] < 0 || op.q[i] >= c->n_qubits) fail(TN_EINVAL, "qubit index out of range");
         if (op.nq == 2 && op.q[0] == op.q[1]) fail(TN_EINVAL, "2-qubit gate on one qubit");
         if (op.kind == TN_GATE) check_unitary(op, k);
-        else {
-            if (op.n_kraus < 1 || op.n_kraus > 64) fail(TN_EINVAL, "noise needs 1..64 Kraus matrices");
-            p->noise.push_back(split_noise(op, k));
-        }
+        else if (op.n_kraus < 1 || op.n_kraus > 64) fail(TN_EINVAL, "noise needs 1..64 Kraus matrices");
     }
-    // past light cone of every noise slot (features of the pruning policy)
     p->n_ops = c->n_ops;
     for (int64_t k = 0; k < c->n_ops; ++k)
         if (c->ops[k].kind == TN_GATE && c->ops[k].nq == 2) ++p->n_2q_gates;
+    return p;
+}
+
+struct PathOpts {
+    int trials, max_log;
+    uint64_t seed;
+    double max_elems;
+    bool reconf;
+};
+
+static PathOpts path_opts(const tn_plan_opts* opts) {
+    PathOpts o;
+    o.trials = (opts && opts->path_trials > 0) ? opts->path_trials : 1024;
+    o.seed = (opts && opts->seed) ? opts->seed : 2211170280ULL;
+    o.max_log = (opts && opts->max_log_size > 0) ? opts->max_log_size : 30;
+    o.max_elems = ((opts && opts->max_work_bytes > 0) ? opts->max_work_bytes : 64.0 * (1ULL << 30)) / 8.0;
+    o.reconf = !(opts && opts->no_reconfigure);
+    return o;
+}
+
+Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, int level,
+                 const tn_plan_opts* opts) {
+    if (level < 0) fail(TN_EINVAL, "level must be >= 0");
+    auto p = new_plan(c, psi, v);
+    for (int64_t k = 0; k < c->n_ops; ++k)
+        if (c->ops[k].kind == TN_NOISE) p->noise.push_back(split_noise(c->ops[k], k));
+    // past light cone of every noise slot (features of the pruning policy)
     {
         const int words = (c->n_qubits + 63) / 64;
         for (NoiseSplit& ns : p->noise) {
@@ -1100,11 +1127,76 @@ Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, in
     fuse_fixed(nb);
     p->leaves = std::move(nb.leaves);
     p->scalar = nb.scalar;
-    int trials = (opts && opts->path_trials > 0) ? opts->path_trials : 1024;
-    uint64_t seed = (opts && opts->seed) ? opts->seed : 2211170280ULL;
-    int max_log = (opts && opts->max_log_size > 0) ? opts->max_log_size : 30;
-    double max_bytes = (opts && opts->max_work_bytes > 0) ? opts->max_work_bytes : 64.0 * (1ULL << 30);
-    plan_clusters(*p, trials, seed, max_log, max_bytes / 8.0, !(opts && opts->no_reconfigure));
+    const PathOpts po = path_opts(opts);
+    plan_clusters(*p, po.trials, po.seed, po.max_log, po.max_elems, po.reconf);
+    return p.release();
+}
+
+// Exact value (the paper's exact baseline, the doubled network of Section IV /
+// Fig. 2).  For every term the bra network is the complex conjugate of the ket
+// network, so the doubled network is the reduced ket network of one term, its
+// conjugate on fresh edge ids, and at every noise one fixed tensor joining the
+// noise's ket legs (out, in) and bra legs (out, in):
+//   T[a][c][b][d] = sum_k E_k[a][c] conj(E_k[b][d]),
+// the channel's whole superoperator, which sums every correction of that noise
+// at once.  No slots remain: one term of weight 1 whose network value a is the
+// exact <v| E(|psi><psi|) |v> (real up to rounding; the exec reports Re(a)).
+// The light-cone reduction of the ket network holds for every term and so for
+// the doubled network.
+Plan* build_plan_doubled(const tn_circuit* c, const tn_state* psi, const tn_state* v,
+                         const tn_plan_opts* opts) {
+    auto p = new_plan(c, psi, v);
+    std::vector<const tn_op*> noise_ops;
+    for (int64_t k = 0; k < c->n_ops; ++k)
+        if (c->ops[k].kind == TN_NOISE) {
+            check_cptp(c->ops[k], k);
+            noise_ops.push_back(&c->ops[k]);
+        }
+    p->doubled = true;
+    p->n_channels = (int)noise_ops.size();
+    p->n_noise = 0;
+    p->level_req = 0;
+    p->level = 0;
+    NetBuild ket = build_network(c, psi, v, !(opts && opts->no_light_cone),
+                                 !(opts && opts->no_diagonal_hyperedges));
+    fuse_fixed(ket);
+    int top = 0;
+    for (const Leaf& l : ket.leaves)
+        for (int e : l.legs) top = std::max(top, e + 1);
+    NetBuild nb;
+    nb.scalar = ket.scalar * std::conj(ket.scalar);
+    for (Leaf& l : ket.leaves) {
+        if (l.slot >= 0) {
+            const tn_op& op = *noise_ops[l.slot];
+            Leaf t;
+            t.legs = {l.legs[0], l.legs[1], l.legs[0] + top, l.legs[1] + top};
+            t.data.assign(16, cd(0.0));
+            for (int k = 0; k < op.n_kraus; ++k) {
+                const tn_c128* e = op.mat + 4 * k;
+                for (int a = 0; a < 2; ++a)
+                    for (int cc = 0; cc < 2; ++cc)
+                        for (int b = 0; b < 2; ++b)
+                            for (int d = 0; d < 2; ++d)
+                                t.data[8 * a + 4 * cc + 2 * b + d] +=
+                                    cd(e[2 * a + cc].re, e[2 * a + cc].im) *
+                                    std::conj(cd(e[2 * b + d].re, e[2 * b + d].im));
+            }
+            nb.leaves.push_back(std::move(t));
+            continue;
+        }
+        Leaf bra;
+        bra.legs = l.legs;
+        for (int& e : bra.legs) e += top;
+        bra.data = l.data;
+        for (cd& x : bra.data) x = std::conj(x);
+        nb.leaves.push_back(std::move(l));
+        nb.leaves.push_back(std::move(bra));
+    }
+    fuse_fixed(nb);
+    p->leaves = std::move(nb.leaves);
+    p->scalar = nb.scalar;
+    const PathOpts po = path_opts(opts);
+    plan_clusters(*p, po.trials, po.seed, po.max_log, po.max_elems, po.reconf);
     return p.release();
 }
 

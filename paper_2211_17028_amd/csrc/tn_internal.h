@@ -75,6 +75,10 @@ struct Plan {
     std::vector<Leaf> leaves;
     std::vector<Cluster> clusters;
     cd scalar = 1.0;              // product of factors outside every cluster
+    // doubled network (exact value): ket and bra halves joined by every noise's
+    // full superoperator tensor; no slots, one term, value Re(a) instead of |a|^2
+    bool doubled = false;
+    int n_channels = 0;           // noises of the circuit (all inside the network)
     int max_log = 0;
     double cmacs_per_term = 0;
     std::string target_kind;
@@ -95,6 +99,8 @@ struct Terms {
 // plan.cpp
 Plan* build_plan(const tn_circuit* circ, const tn_state* psi, const tn_state* v, int level,
                  const tn_plan_opts* opts);
+Plan* build_plan_doubled(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                         const tn_plan_opts* opts);
 Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune);
 std::string describe_plan(const Plan* p);
 int term_features(const Plan* p, const Terms* t, const double* level1_x, float* out);

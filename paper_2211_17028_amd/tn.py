@@ -87,11 +87,12 @@ class tn_result(C.Structure):
 class tn_plan_info(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("n_noise", C.c_int32), ("level", C.c_int32),
                 ("clamped", C.c_int32), ("n_clusters", C.c_int32), ("n_leaves", C.c_int32),
-                ("max_log_size", C.c_int32), ("flops_per_term", C.c_double)]
+                ("max_log_size", C.c_int32), ("flops_per_term", C.c_double),
+                ("doubled", C.c_int32), ("n_channels", C.c_int32)]
 
 
 EXPORTS = [
-    "tn_plan_build", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_plan_build", "tn_plan_build_doubled", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
@@ -117,6 +118,8 @@ def lib():
     vp = C.c_void_p
     L.tn_plan_build.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
                                 C.c_int32, C.POINTER(tn_plan_opts), C.POINTER(vp)]
+    L.tn_plan_build_doubled.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
+                                        C.POINTER(tn_plan_opts), C.POINTER(vp)]
     L.tn_terms_enumerate.argtypes = [vp, C.c_int32, C.POINTER(tn_prune_opts), C.POINTER(vp),
                                      C.POINTER(C.c_int64)]
     L.tn_terms_get.argtypes = [vp, vp, vp]
@@ -261,6 +264,19 @@ def tn_plan_build(circ, level: Optional[int] = None, path_trials: int = 0, seed:
     lev = circ.level if level is None else level
     _check(lib().tn_plan_build(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v), lev,
                                C.byref(opts), C.byref(h)))
+    return Plan(h, circ)
+
+
+def tn_plan_build_doubled(circ, path_trials: int = 0, seed: int = 0, light_cone: bool = True,
+                          max_log_size: int = 0, diagonal_hyperedges: bool = True,
+                          max_work_bytes: float = 0.0, reconfigure: bool = True) -> Plan:
+    """Plan of the doubled network: its one term's estimate is the exact value."""
+    bufs = _CircuitBuffers(circ)
+    opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size,
+                        0 if diagonal_hyperedges else 1, max_work_bytes, 0 if reconfigure else 1)
+    h = C.c_void_p()
+    _check(lib().tn_plan_build_doubled(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v),
+                                       C.byref(opts), C.byref(h)))
     return Plan(h, circ)
 
 

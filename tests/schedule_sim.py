@@ -157,7 +157,7 @@ class Sim:
                     a *= complex(self.view(root64_refs[c], np.complex128, j + 1)[j])
                 else:
                     a *= complex(self.view(root_refs[c], np.complex64, j + 1)[j])
-            x[t] = w[t] * abs(a) ** 2
+            x[t] = w[t] * (a.real if L.get("re_value") else abs(a) ** 2)
             amp[t] = a
 
     def level_sum(self, L):

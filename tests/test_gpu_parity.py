@@ -498,3 +498,83 @@ def test_degenerate_cases_against_oracle(torch):
     res, x, pat, _ = run_gpu(c3, 5)
     assert res["clamped"] and res["level"] == 2
     assert abs(res["A"][2] - dense.exact_value(c3)) <= 1e-6 * abs(dense.exact_value(c3)) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# exact value: the doubled network (every noise as its whole superoperator),
+# one term computed in FP64 (the dominant-term pass) or in FP32
+# ---------------------------------------------------------------------------
+def run_doubled(circ, fp64=True, **plan_kw):
+    plan = tn.tn_plan_build_doubled(circ, **plan_kw)
+    terms = tn.tn_terms_enumerate(plan, 0)
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, fp64_level0=fp64))
+    res = ex.run()[0]
+    return res, plan
+
+
+@pytest.mark.parametrize("seed,kind,target,n,gates,noise", [
+    (61, "random", "circuit_output", 5, 30, 6), (62, "adpd", "product", 4, 24, 5),
+    (63, "depol", "dense", 5, 30, 4), (64, "random", "product", 6, 40, 7)])
+def test_doubled_tiny_circuits_against_density_matrix(torch, seed, kind, target, n, gates, noise):
+    from oracle import dense
+    print(f"doubled tiny {seed} {kind} {target}", flush=True)
+    c = W.tiny_random_circuit(np.random.default_rng(seed), n, gates, noise, noise=kind, level=2,
+                              target=target)
+    f = dense.exact_value(c)
+    res, _ = run_doubled(c)
+    assert res["n_terms"] == 1 and res["bound"] == 0.0
+    assert abs(res["A"][0] - f) <= 1e-12 * max(1.0, abs(f)), (res["A"][0], f)
+    # FP32 chain only: about 1e-7 relative per step, a few dozen steps
+    res32, _ = run_doubled(c, fp64=False)
+    assert abs(res32["A"][0] - f) <= 1e-5 * max(1.0, abs(f)), (res32["A"][0], f)
+
+
+def test_doubled_wide_circuit_against_oracle(torch):
+    """16 qubits, 160 gates: the doubled network's steps reach the grouped
+    matrix-core and FP64 tile launches; the oracle's own doubled contraction
+    and its full expansion at level N pin the value."""
+    from oracle import doubled
+    print("doubled wide", flush=True)
+    c = W.tiny_random_circuit(np.random.default_rng(65), 16, 160, 4, noise="adpd", level=4,
+                              target="circuit_output")
+    want = doubled.doubled_value(c, diagonal=True).real
+    res, plan = run_doubled(c)
+    assert plan.info()["max_log_size"] >= 14
+    assert abs(res["A"][0] - want) <= 1e-12 * want, (res["A"][0], want)
+    ref = estimate.estimate(c, 4, "network")
+    assert abs(res["A"][0] - ref["A"][-1]) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("cfg", [1, 5])
+def test_doubled_configs_against_oracle(torch, cfg):
+    """Config 1 (8 qubits) and config 5 (15x15 grid, 20 AD+PD): the exact value
+    against the oracle's doubled contraction, and the level-l estimate's
+    remainder F - A(l) within Theorem 1's bound."""
+    from oracle import bounds, doubled
+    print(f"doubled config{cfg}", flush=True)
+    c = W.config(cfg)
+    want = doubled.doubled_value(c, diagonal=True).real
+    res, _ = run_doubled(c)
+    f = res["A"][0]
+    assert abs(f - want) <= 1e-12 * want, (f, want)
+    est, _, _, _ = run_gpu(c, c.level)
+    b = bounds.rigorous_bound([bounds.split_norms(op.kraus) for op in c.noise_ops()], c.level)
+    assert est["A"][c.level] - 1e-9 <= f <= est["A"][c.level] + b + 1e-12, (f, est["A"], b)
+
+
+def test_doubled_config2_brackets_the_estimate(torch):
+    """Config 2 (5x5 grid, 12 layers, 25 qubits: no density matrix): the exact
+    value lies between the oracle's full level-2 sum and that sum plus Theorem
+    1's bound; a second contraction order (another path seed) agrees."""
+    from oracle import bounds
+    print("doubled config2", flush=True)
+    c = W.config(2)
+    gold = np.loadtxt(os.path.join(GOLD, "config2_oracle.txt"))
+    b = bounds.rigorous_bound([bounds.split_norms(op.kraus) for op in c.noise_ops()], c.level)
+    res, plan = run_doubled(c, path_trials=16384)
+    f = res["A"][0]
+    print(f"F {f:.17g} A(2) {gold[-1]:.17g} F-A(2) {f - gold[-1]:.3e} bound {b:.3e} "
+          f"max_log {plan.info()['max_log_size']}", flush=True)
+    assert gold[-1] - 1e-12 <= f <= gold[-1] + b + 1e-12
+    res2, plan2 = run_doubled(c, path_trials=16384, seed=7)
+    assert abs(res2["A"][0] - f) <= 1e-12 * f, (res2["A"][0], f)

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import channels, estimate, network, terms as oterms
+from oracle import channels, dense, doubled, estimate, network, terms as oterms
 from paper_2211_17028_amd import tn
 from tests.schedule_sim import Sim
 
@@ -263,3 +263,71 @@ def test_prune_threshold_respects_the_budget():
         if rest.size and budget < 1e9:
             nxt = pred.astype(np.float32) == rest[0]
             assert dropped + x[nxt].sum() > budget
+
+
+# ---------------------------------------------------------------------------
+# exact value: the doubled network (every noise as its whole superoperator)
+# ---------------------------------------------------------------------------
+def _replay_doubled(circ, mode=tn.TN_MODE_BATCHED, fp64=True, **plan_kw):
+    plan = tn.tn_plan_build_doubled(circ, **plan_kw)
+    t = tn.tn_terms_enumerate(plan, 0)
+    desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
+                                                                  fp64_level0=fp64))
+    sim = Sim(desc, cb)
+    sim.run([[0]])
+    x, _ = sim.outputs()
+    return x, plan, t, desc
+
+
+def test_doubled_plan_has_one_term_and_no_slots():
+    c = W.tiny_random_circuit(np.random.default_rng(51), 4, 16, 5, noise="random", level=3)
+    plan = tn.tn_plan_build_doubled(c)
+    info = plan.info()
+    assert info["doubled"] == 1 and info["n_channels"] == 5 and info["n_noise"] == 0 and info["level"] == 0
+    assert all(leaf.get("slot", -1) < 0 for leaf in plan.describe().get("leaves", []))
+    for level in (0, 3):
+        t = tn.tn_terms_enumerate(plan, level)
+        pat, w = t.get()
+        assert t.n == 1 and list(w) == [1.0]
+    # the estimate's plan of the same circuit is unchanged by the doubled one
+    assert tn.tn_plan_build(c, 3).info()["doubled"] == 0
+
+
+def test_doubled_accepts_a_degenerate_channel_the_split_rejects():
+    c = W.tiny_random_circuit(np.random.default_rng(52), 3, 10, 0, noise="random", level=1)
+    ops = list(c.ops) + [W.Op("noise", (1,), kraus=W.kraus_depolarizing(0.75))]
+    c = W.Circuit(c.n_qubits, ops, c.psi, c.target, c.v, 1)
+    with pytest.raises(tn.TNError) as e:
+        tn.tn_plan_build(c, 1)
+    assert e.value.code == tn.TN_EDEGENERATE
+    x, _, _, _ = _replay_doubled(c)
+    assert abs(x[0] - dense.exact_value(c)) <= 1e-12
+
+
+@pytest.mark.parametrize("seed,kind,target", [(53, "random", "circuit_output"), (54, "adpd", "product"),
+                                               (55, "depol", "dense"), (56, "random", "product")])
+def test_doubled_replay_matches_the_exact_value(seed, kind, target):
+    """The doubled schedule replayed on the CPU (FP64 pass for its one term)
+    gives the density-matrix value and the oracle's doubled contraction."""
+    c = W.tiny_random_circuit(np.random.default_rng(seed), 4, 18, 5, noise=kind, level=2, target=target)
+    x, _, _, _ = _replay_doubled(c)
+    f = dense.exact_value(c)
+    assert abs(x[0] - f) <= 1e-12 * max(1.0, abs(f))
+    assert abs(x[0] - doubled.doubled_value(c).real) <= 1e-12 * max(1.0, abs(f))
+    # without the FP64 pass the one term runs in FP32
+    x32, _, _, _ = _replay_doubled(c, fp64=False)
+    assert abs(x32[0] - f) <= 1e-5 * max(1.0, abs(f))
+
+
+def test_doubled_replay_wide_circuit_with_matrix_core_steps():
+    """16 qubits: the doubled network's tensors reach the matrix-core and FP64
+    tile paths; no density matrix, so the oracle's doubled contraction and the
+    full expansion at level N pin the value."""
+    c = W.tiny_random_circuit(np.random.default_rng(57), 16, 160, 4, noise="adpd", level=4,
+                              target="circuit_output")
+    x, plan, _, desc = _replay_doubled(c)
+    assert any(L["kind"] in (5, 6) for L in desc["launches"])
+    want = doubled.doubled_value(c, diagonal=True).real
+    assert abs(x[0] - want) <= 1e-12 * max(1.0, abs(want))
+    r = estimate.estimate(c, 4, "network", reduce=True)
+    assert abs(x[0] - r["A"][-1]) <= 1e-12 * max(1.0, abs(want))
