@@ -129,6 +129,69 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, out_path):
     print(json.dumps(rec))
 
 
+def roofline_of(name, st, per):
+    """Roofline entry of one kernel from its accumulated event timing: FP32
+    matrix-core kernels against the FP32 MFMA peak, FP64 FMA tile kernels
+    against the FP64 peak, the rest (small steps, permutes) against HBM."""
+    if name.startswith("k_mfma") or name.startswith("k_gemm_mfma"):
+        achieved = st["flops"] / (st["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS}
+    elif name.startswith("k_tile64") or name.startswith("k_gemm_tiled_c128"):
+        achieved = st["flops"] / (st["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS,
+                "peak_note": "FP64 FMA: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz"}
+    else:
+        achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    roof.update({"kernel": name, "launches_per_step": st["launches"] / per,
+                 "avg_launch_us": 1000.0 * st["ms"] / st["launches"],
+                 "algorithmic_per_launch": (st["bytes"] if roof["bound"] == "hbm" else st["flops"])
+                 / st["launches"], "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]})
+    return roof
+
+
+def exact_value(circ, level, res, reps):
+    """The exact value of the bench workload: its doubled network (every noise
+    as its whole superoperator, ket and bra halves in one network) contracted
+    once per run by the FP64 pass; F - A(l) is the estimate's actual error."""
+    import torch
+    from paper_2211_17028_amd import tn
+    t0 = time.perf_counter()
+    pd = tn.tn_plan_build_doubled(circ, path_trials=16384)
+    td = tn.tn_terms_enumerate(pd, 0)
+    plan_s = time.perf_counter() - t0
+    ed = tn.tn_exec_prepare([pd], [td], tn.exec_opts(use_graph=False))
+    rd = ed.run()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rd = ed.run()[0]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    del ed
+    ek = tn.tn_exec_prepare([pd], [td], tn.exec_opts(use_graph=False, time_kernels=True))
+    ek.run()
+    ek.kernel_stats(reset=True)
+    for _ in range(reps):
+        ek.run()
+    st = ek.kernel_stats(reset=True)
+    del ek
+    dname, dst = max(st.items(), key=lambda kv: kv[1]["ms"])
+    info = pd.info()
+    f = rd["A"][0]
+    return {"workload": "grid5x5_12L_10depol doubled network", "F": f, "A_level": res["A"][level],
+            "F_minus_A": f - res["A"][level], "bound_of_A": res["bound"], "ms_per_value": ms,
+            "plan_s": plan_s, "flops_per_value": info["flops_per_term"],
+            "max_log_size": info["max_log_size"],
+            "tflops": info["flops_per_term"] / (ms * 1e-3) / 1e12,
+            "roofline": roofline_of(dname, dst, reps),
+            "kernels": {k: {"ms_per_value": v["ms"] / reps, "launches_per_value": v["launches"] / reps}
+                        for k, v in sorted(st.items(), key=lambda kv: -kv[1]["ms"])}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -142,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-paper-case", action="store_true", help="skip the 225-qubit context measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
     ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -238,24 +302,8 @@ def main():
     fp64_names = {k for k in stats if "double" in k or k.startswith("k_tile64") or k.startswith("k_gemm_tiled_c128")}
     main = {k: v for k, v in stats.items() if k not in fp64_names} or stats
     dom_name, dom = max(main.items(), key=lambda kv: kv[1]["ms"])
-    if dom_name.startswith("k_mfma") or dom_name.startswith("k_gemm_mfma"):
-        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS}
-    elif dom_name.startswith("k_tile64") or dom_name.startswith("k_gemm_tiled_c128"):
-        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS,
-                "peak_note": "FP64 FMA: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz"}
-    else:
-        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS}
-    roof.update({"kernel": dom_name, "launches_per_step": dom["launches"] / args.steps,
-                 "avg_launch_us": 1000.0 * dom["ms"] / dom["launches"],
-                 "algorithmic_per_launch": (dom["bytes"] if roof["bound"] == "hbm" else dom["flops"])
-                 / dom["launches"], "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
-                 "traffic": measured_traffic(dom_name)})
+    roof = roofline_of(dom_name, dom, args.steps)
+    roof["traffic"] = measured_traffic(dom_name)
     side = [stats[k] for k in fp64_names]
     if side:
         roof["fp64_side_kernels"] = {"kernels": sorted(fp64_names),
@@ -318,6 +366,8 @@ def main():
                       "with 20 noises on its own hardware and circuits (different circuits; context only)"}
         del e5
 
+    exact = None if args.no_exact else exact_value(circ, level, res, 5)
+
     cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
     info = plan.info()
     line = {
@@ -351,6 +401,7 @@ def main():
         "eager": eager,
         "plain": plain,
         "paper_case": paper_case,
+        "exact_value": exact,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

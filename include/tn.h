@@ -163,7 +163,10 @@ typedef struct {
     double level_comp[TN_MAX_LEVEL + 1];  /* Neumaier compensation of T_u (already added) */
     double A[TN_MAX_LEVEL + 1];           /* A(u) = sum_{u'<=u} T_u' */
     double bound;                         /* |F - A(level)| bound from the split norms */
-    double x0_fp32;                       /* level-0 term from the FP32 batch (diagnostic) */
+    double x0_fp32;                       /* level-0 term from the FP32 batch (diagnostic);
+                                             -1 in PLAIN mode and when the FP64 pass is the
+                                             only one (a single live term, the level-0 one,
+                                             with fp64_level0: no FP32 chain is scheduled) */
 } tn_result;
 
 /* ---------------------------------------------------------------------------

@@ -156,6 +156,7 @@ struct PlanExec {
     std::vector<Ref> root32;       // per cluster root buffer (FP32 batch)
     std::vector<int64_t> root32_inst;
     std::vector<Ref> root64;
+    bool fp32_skipped = false;     // the FP64 pass covers every live term: no FP32 chain
     int64_t n_zero = 0, n_pruned = 0;
     std::vector<int64_t> live_terms;  // term indices of live terms
 };
@@ -1304,6 +1305,9 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         // the all-dominant term is term 0 of the enumeration
         if (T.n > 0 && T.lvl[0] == 0 && live_index[0] >= 0) pe.zero_term = 0;
         const int ncl = (int)P.clusters.size();
+        // one live term, the all-dominant one, recomputed in FP64 (a level-0 term
+        // set, a doubled network): the FP32 chain would compute a value nothing reads
+        pe.fp32_skipped = !plain && ex->opts.fp64_level0 && pe.zero_term == 0 && pe.n_live == 1;
         std::vector<int32_t> root_idx(std::max<int64_t>(1, pe.n_live * ncl), 0);
         std::vector<int64_t> root_ptr_slot(ncl, 0);
         std::vector<std::pair<int, int64_t>> plain_slots;
@@ -1327,6 +1331,9 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
                     }
                 pe.root32.push_back(root);
                 pe.root32_inst.push_back(pe.n_live);
+            } else if (pe.fp32_skipped) {
+                pe.root32.push_back(Ref{R_CONST, ex->cbuf.reserve(8)});   // never read
+                pe.root32_inst.push_back(1);
             } else {
                 // roots stay live until finalize: the root step writes outside the work arena
                 Ref keep{R_CONST, ex->cbuf.reserve((int64_t)keys.size() * 8)};
@@ -1534,7 +1541,7 @@ static void bind(tn_exec_s* ex) {
             L.f.w = (const double*)resolve(ex, L.w);
             L.f.x_out = (double*)resolve(ex, L.x_out);
             L.f.amp_out = (float*)resolve(ex, L.amp_out);
-            L.f.x0_fp32_out = (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED)
+            L.f.x0_fp32_out = (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
                                   ? (double*)resolve(ex, pe.x0) : nullptr;
         }
     }
@@ -2230,7 +2237,7 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             r.bound = b;
             // FP32 value of the all-dominant term (diagnostic, written by the finalize)
             r.x0_fp32 = -1;
-            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED)
+            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
                 r.x0_fp32 = *(const double*)((const char*)ex->results_host + pe.x0.off);
         }
     });

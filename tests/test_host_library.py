@@ -326,7 +326,10 @@ def test_doubled_replay_wide_circuit_with_matrix_core_steps():
     c = W.tiny_random_circuit(np.random.default_rng(57), 16, 160, 4, noise="adpd", level=4,
                               target="circuit_output")
     x, plan, _, desc = _replay_doubled(c)
-    assert any(L["kind"] in (5, 6) for L in desc["launches"])
+    steps = [L for L in desc["launches"] if L["kind"] in (5, 6)]
+    assert steps and all(L["fp64"] for L in steps)      # the FP64 pass alone: no FP32 chain
+    _, _, _, desc32 = _replay_doubled(c, fp64=False)
+    assert any(L["kind"] == 6 and not L["fp64"] for L in desc32["launches"])
     want = doubled.doubled_value(c, diagonal=True).real
     assert abs(x[0] - want) <= 1e-12 * max(1.0, abs(want))
     r = estimate.estimate(c, 4, "network", reduce=True)
