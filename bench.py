@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--no-paper-case", action="store_true", help="skip the 225-qubit context measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
+    ap.add_argument("--exact-only", action="store_true",
+                    help="only the exact value of the workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
     ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -241,6 +243,10 @@ def main():
     plan = tn.tn_plan_build(circ, level)
     plan_s = time.perf_counter() - t0
     terms = tn.tn_terms_enumerate(plan, level)
+    if args.exact_only:
+        r1 = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False)).run()[0]
+        print(json.dumps({"exact_value": exact_value(circ, level, r1, args.steps)}), flush=True)
+        return
     # timed region: the prepared schedule run with direct launches (issued
     # level by level, the FP64 pass on its own stream), inputs resident in HBM;
     # then the same schedule captured once in a hipGraph and replayed, for
