@@ -17,8 +17,10 @@ Modules
                pairwise with its own light-cone reduction and greedy order
   doubled   -- the exact baseline: the doubled (ket + bra) network with every
                noise as its full superoperator tensor, contracted pairwise
+  offdiag   -- off-diagonal elements: density matrix, graded form, cross form of
+               Algorithm 1's terms, bond-2 polarization targets
   bounds    -- Theorem 1 (contraction count; error bound in the form its proof
                actually establishes)
   estimate  -- driver: T_u, A(l) for every l' <= l, per-term values
 """
-from . import channels, terms, dense, literal, network, doubled, bounds, estimate  # noqa: F401
+from . import channels, terms, dense, literal, network, doubled, offdiag, bounds, estimate  # noqa: F401

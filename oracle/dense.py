@@ -53,6 +53,13 @@ def target_vector(circ) -> np.ndarray:
         return product_state(circ.v)
     if circ.target == "dense":
         return np.asarray(circ.v, dtype=np.complex128).reshape(-1)
+    if circ.target in ("sum2", "circuit_output_sum2"):
+        # |p> + c |q>: v holds p (n x 2), q (n x 2), then c
+        n = circ.n_qubits
+        flat = np.asarray(circ.v, dtype=np.complex128).reshape(-1)
+        p, q, c = flat[:2 * n].reshape(n, 2), flat[2 * n:4 * n].reshape(n, 2), flat[4 * n]
+        st = product_state(p) + c * product_state(q)
+        return ideal_state(circ, st) if circ.target == "circuit_output_sum2" else st
     raise ValueError(circ.target)
 
 
@@ -82,6 +89,13 @@ def exact_value(circ) -> float:
 def graded_levels(circ, level: int):
     """[T_0, ..., T_level] by the graded density-matrix recursion."""
     n = circ.n_qubits
+    vv = target_vector(circ)
+    return [np.vdot(vv, m @ vv) for m in graded_matrices(circ, level)]
+
+
+def graded_matrices(circ, level: int):
+    """The graded density matrices rho^(0..level) as 2^n x 2^n arrays."""
+    n = circ.n_qubits
     psi = product_state(circ.psi)
     rho0 = np.outer(psi, psi.conj()).reshape((2,) * (2 * n))
     grades = [rho0] + [np.zeros_like(rho0) for _ in range(level)]
@@ -101,9 +115,22 @@ def graded_levels(circ, level: int):
                         acc = acc + apply_to_axes(apply_to_axes(grades[k - 1], u[i], ket), v[i], bra)
                 new.append(acc)
             grades = new
-    vv = target_vector(circ)
-    out = []
-    for g in grades:
-        m = g.reshape(2 ** n, 2 ** n)
-        out.append(np.vdot(vv, m @ vv))
-    return out
+    return [g.reshape(2 ** n, 2 ** n) for g in grades]
+
+
+def exact_matrix(circ) -> np.ndarray:
+    """E_N(|psi><psi|) as a 2^n x 2^n array (Kraus evolution, Section II)."""
+    n = circ.n_qubits
+    psi = product_state(circ.psi)
+    rho = np.outer(psi, psi.conj()).reshape((2,) * (2 * n))
+    for op in circ.ops:
+        ket = list(op.qubits)
+        bra = [n + q for q in op.qubits]
+        if op.kind == "gate":
+            rho = apply_to_axes(apply_to_axes(rho, op.mat, ket), np.conj(op.mat), bra)
+        else:
+            acc = np.zeros_like(rho)
+            for e in op.kraus:
+                acc += apply_to_axes(apply_to_axes(rho, e, ket), np.conj(e), bra)
+            rho = acc
+    return rho.reshape(2 ** n, 2 ** n)
