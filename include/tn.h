@@ -78,7 +78,15 @@ enum {
     TN_STATE_PRODUCT = 0,         /* data: n_qubits x 2 amplitudes */
     TN_STATE_CIRCUIT_OUTPUT = 1,  /* |v> = U_ideal |p>, data: n_qubits x 2 of |p>;
                                      U_ideal is the circuit with its noises removed */
-    TN_STATE_DENSE = 2            /* data: 2^n_qubits amplitudes (n_qubits <= 30) */
+    TN_STATE_DENSE = 2,           /* data: 2^n_qubits amplitudes (n_qubits <= 30) */
+    /* bond-2 targets |v> = |p> + c |q> with p, q product states: the targets of
+     * the polarization identity for off-diagonal elements (Section III, after
+     * Problem 1).  data: n_qubits x 2 of |p>, then n_qubits x 2 of |q>, then c
+     * (4 n_qubits + 1 entries).  In the network <v| is one 2-valued index shared
+     * by a tensor per qubit and the branch weights (1, conj c). */
+    TN_STATE_SUM2 = 3,
+    TN_STATE_CIRCUIT_OUTPUT_SUM2 = 4  /* |v> = U_ideal (|p> + c |q>), data as TN_STATE_SUM2;
+                                         reduced by the light cone like TN_STATE_CIRCUIT_OUTPUT */
 };
 
 typedef struct {
@@ -289,6 +297,19 @@ int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, in
  * ------------------------------------------------------------------------- */
 int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_ws,
                 size_t ws_bytes, void* stream, tn_result* results);
+
+/* ---------------------------------------------------------------------------
+ * tn_polarization_combine -- an off-diagonal element <x| E(|psi><psi|) |y>
+ * from four results (Section III, after Problem 1: the polarization identity
+ * <x|A|y> = 1/4 sum_{k=0..3} i^k <v_k|A|v_k>).  r[k] is the result of the same
+ * circuit and term level with the bond-2 target v_k = y + i^k x (TN_STATE_SUM2
+ * or TN_STATE_CIRCUIT_OUTPUT_SUM2 with p = y, q = x, c = i^k), e.g. the four
+ * plans of one tn_exec_run, or of four doubled plans for the exact element.
+ * Writes A_xy(u) = 1/4 sum_k i^k A_k(u) for u = 0..r[0].level into re[] and
+ * im[] (host arrays of at least level + 1 entries).  Host only.
+ * Errors: TN_EINVAL (null pointer, results of different levels).
+ * ------------------------------------------------------------------------- */
+int tn_polarization_combine(const tn_result* r, double* re, double* im);
 
 /* Workspace bytes tn_estimate needs for these plans and term sets. */
 int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms,

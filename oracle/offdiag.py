@@ -64,11 +64,12 @@ def element_graded(circ, level: int, x, y, output: bool):
     return [complex(np.vdot(X, m @ Y)) for m in dense.graded_matrices(circ, level)]
 
 
-def element_cross(circ, level: int, x, y, output: bool, reduce: bool = True):
-    """Level sums T_u and A(u) (complex) of <x|E|y> by the cross form."""
+def element_cross(circ, level: int, x, y, output: bool, reduce: bool = True, diagonal: bool = False):
+    """Level sums T_u and A(u) (complex) of <x|E|y> by the cross form
+    (``diagonal``: diagonal gates as shared indices, same values)."""
     cx, cy = _target_circuit(circ, x, output), _target_circuit(circ, y, output)
-    nx = network.KetNetwork(cx, reduce=reduce)
-    ny = network.KetNetwork(cy, reduce=reduce)
+    nx = network.KetNetwork(cx, reduce=reduce, diagonal=diagonal)
+    ny = network.KetNetwork(cy, reduce=reduce, diagonal=diagonal)
     sp = network.slot_split(circ)
     level = min(level, circ.n_noises)
     re = [Neumaier() for _ in range(level + 1)]

@@ -2003,6 +2003,26 @@ int tn_plan_build_doubled(const tn_circuit* circ, const tn_state* psi, const tn_
     });
 }
 
+int tn_polarization_combine(const tn_result* r, double* re, double* im) {
+    return guard([&] {
+        if (!r || !re || !im) fail(TN_EINVAL, "null pointer");
+        const int L = r[0].level;
+        for (int k = 1; k < 4; ++k)
+            if (r[k].level != L) fail(TN_EINVAL, "the four results have different levels");
+        // i^k for k = 0..3
+        static const double wr[4] = {1, 0, -1, 0}, wi[4] = {0, 1, 0, -1};
+        for (int u = 0; u <= L; ++u) {
+            double sr = 0, si = 0;
+            for (int k = 0; k < 4; ++k) {
+                sr += wr[k] * r[k].A[u];
+                si += wi[k] * r[k].A[u];
+            }
+            re[u] = 0.25 * sr;
+            im[u] = 0.25 * si;
+        }
+    });
+}
+
 int tn_terms_enumerate(tn_plan plan, int32_t level, const tn_prune_opts* prune, tn_terms* out,
                        int64_t* n_terms) {
     return guard([&] {

@@ -320,7 +320,12 @@ static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn
 
     std::vector<std::pair<int64_t, bool>> seq;   // (op index, inverse)
     std::vector<char> touched(n, 0);
-    bool cone_target = v->kind == TN_STATE_CIRCUIT_OUTPUT;
+    // a bond-2 target <v| = <p| + conj(c) <q| is one 2-valued index b shared by
+    // a tensor per qubit (conj of branch b's amplitudes) and the branch weights
+    const bool sum2 = v->kind == TN_STATE_SUM2 || v->kind == TN_STATE_CIRCUIT_OUTPUT_SUM2;
+    const bool cone_target = v->kind == TN_STATE_CIRCUIT_OUTPUT || v->kind == TN_STATE_CIRCUIT_OUTPUT_SUM2;
+    auto vamp = [&](int b, int q, int s) { return amp(v->data + 2 * n * b, q, s); };
+    cd branch[2] = {1.0, sum2 ? std::conj(cd(v->data[4 * n].re, v->data[4 * n].im)) : cd(0.0)};
     if (cone_target) {
         std::vector<char> keep(c->n_ops, 1);
         if (light_cone) {
@@ -347,10 +352,15 @@ static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn
         for (int64_t k = c->n_ops - 1; k >= 0; --k)
             if (keep[k] && c->ops[k].kind == TN_GATE) seq.push_back({k, true});
         // <p_v,q | psi_q> for every qubit the reduced network does not touch
+        // (per branch for a bond-2 target)
         for (int q = 0; q < n; ++q)
             if (!touched[q])
-                nb.scalar *= std::conj(amp(v->data, q, 0)) * amp(psi->data, q, 0) +
-                             std::conj(amp(v->data, q, 1)) * amp(psi->data, q, 1);
+                for (int b = 0; b < (sum2 ? 2 : 1); ++b) {
+                    const cd f = std::conj(vamp(b, q, 0)) * amp(psi->data, q, 0) +
+                                 std::conj(vamp(b, q, 1)) * amp(psi->data, q, 1);
+                    if (sum2) branch[b] *= f;
+                    else nb.scalar *= f;
+                }
     } else {
         for (int64_t k = 0; k < c->n_ops; ++k) seq.push_back({k, false});
         std::fill(touched.begin(), touched.end(), 1);
@@ -405,7 +415,28 @@ static NetBuild build_network(const tn_circuit* c, const tn_state* psi, const tn
         }
         nb.leaves.push_back(std::move(l));
     }
-    if (v->kind == TN_STATE_DENSE) {
+    if (sum2) {
+        bool any = false;
+        for (int q = 0; q < n; ++q) any |= touched[q] != 0;
+        if (!any) {
+            nb.scalar *= branch[0] + branch[1];
+        } else {
+            const int bond = edge++;
+            for (int q = 0; q < n; ++q)
+                if (touched[q]) {
+                    Leaf l;
+                    l.legs = {cur[q], bond};
+                    l.data.resize(4);
+                    for (int s = 0; s < 2; ++s)
+                        for (int b = 0; b < 2; ++b) l.data[2 * s + b] = std::conj(vamp(b, q, s));
+                    nb.leaves.push_back(std::move(l));
+                }
+            Leaf w;
+            w.legs = {bond};
+            w.data = {branch[0], branch[1]};
+            nb.leaves.push_back(std::move(w));
+        }
+    } else if (v->kind == TN_STATE_DENSE) {
         Leaf l;
         for (int q = 0; q < n; ++q) l.legs.push_back(cur[q]);
         l.data.resize(size_t(1) << n);
@@ -1045,13 +1076,13 @@ static std::unique_ptr<Plan> new_plan(const tn_circuit* c, const tn_state* psi, 
     if (c->n_qubits < 1 || c->n_qubits > 4096) fail(TN_EINVAL, "n_qubits out of range");
     if (c->n_ops < 0 || (c->n_ops > 0 && !c->ops)) fail(TN_EINVAL, "bad op list");
     if (psi->kind != TN_STATE_PRODUCT || !psi->data) fail(TN_EINVAL, "psi must be a product state");
-    if (v->kind < 0 || v->kind > 2 || !v->data) fail(TN_EINVAL, "bad target state");
+    if (v->kind < 0 || v->kind > 4 || !v->data) fail(TN_EINVAL, "bad target state");
     if (v->kind == TN_STATE_DENSE && c->n_qubits > 30) fail(TN_EINVAL, "dense target needs n <= 30");
     auto p = std::make_unique<Plan>();
     p->id = g_plan_id++;
     p->n_qubits = c->n_qubits;
-    p->target_kind = v->kind == TN_STATE_CIRCUIT_OUTPUT ? "circuit_output"
-                     : v->kind == TN_STATE_PRODUCT ? "product" : "dense";
+    static const char* kinds[5] = {"product", "circuit_output", "dense", "sum2", "circuit_output_sum2"};
+    p->target_kind = kinds[v->kind];
     for (int64_t k = 0; k < c->n_ops; ++k) {
         const tn_op& op = c->ops[k];
         if (op.kind != TN_GATE && op.kind != TN_NOISE) fail(TN_EINVAL, "op kind must be gate or noise");

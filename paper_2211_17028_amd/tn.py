@@ -21,6 +21,7 @@ TN_OK, TN_EINVAL, TN_ENOTCPTP, TN_EUNSUPPORTED, TN_EDEGENERATE = 0, -1, -2, -3, 
 TN_ENOMEM, TN_EHIP, TN_ETOOBIG, TN_ESTATE = -5, -6, -7, -8
 TN_GATE, TN_NOISE = 0, 1
 TN_STATE_PRODUCT, TN_STATE_CIRCUIT_OUTPUT, TN_STATE_DENSE = 0, 1, 2
+TN_STATE_SUM2, TN_STATE_CIRCUIT_OUTPUT_SUM2 = 3, 4
 TN_MODE_BATCHED, TN_MODE_PLAIN = 0, 1
 TN_MAX_LEVEL = 8
 
@@ -92,7 +93,7 @@ class tn_plan_info(C.Structure):
 
 
 EXPORTS = [
-    "tn_plan_build", "tn_plan_build_doubled", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
@@ -120,6 +121,7 @@ def lib():
                                 C.c_int32, C.POINTER(tn_plan_opts), C.POINTER(vp)]
     L.tn_plan_build_doubled.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
                                         C.POINTER(tn_plan_opts), C.POINTER(vp)]
+    L.tn_polarization_combine.argtypes = [C.POINTER(tn_result), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.tn_terms_enumerate.argtypes = [vp, C.c_int32, C.POINTER(tn_prune_opts), C.POINTER(vp),
                                      C.POINTER(C.c_int64)]
     L.tn_terms_get.argtypes = [vp, vp, vp]
@@ -199,7 +201,8 @@ class _CircuitBuffers:
         self.psi_arr = np.ascontiguousarray(circ.psi, dtype=np.complex128).reshape(-1)
         self.v_arr = np.ascontiguousarray(circ.v, dtype=np.complex128).reshape(-1)
         kind = {"product": TN_STATE_PRODUCT, "circuit_output": TN_STATE_CIRCUIT_OUTPUT,
-                "dense": TN_STATE_DENSE}[circ.target]
+                "dense": TN_STATE_DENSE, "sum2": TN_STATE_SUM2,
+                "circuit_output_sum2": TN_STATE_CIRCUIT_OUTPUT_SUM2}[circ.target]
         self.psi = tn_state(TN_STATE_PRODUCT, C.cast(self.psi_arr.ctypes.data, C.POINTER(tn_c128)))
         self.v = tn_state(kind, C.cast(self.v_arr.ctypes.data, C.POINTER(tn_c128)))
 
@@ -314,9 +317,13 @@ class Exec:
             self.handle = None
 
     def run(self, stream=None) -> List[dict]:
+        return [r.as_dict() for r in self.run_raw(stream)]
+
+    def run_raw(self, stream=None):
+        """tn_result array of one run (one entry per plan)."""
         res = (tn_result * len(self.plans))()
         _check(lib().tn_exec_run(self.handle, _stream_ptr(stream), res))
-        return [r.as_dict() for r in res]
+        return res
 
     def kernel_stats(self, reset=False):
         """{kernel name: dict(launches, ms, flops, bytes)} accumulated over runs."""
@@ -408,6 +415,44 @@ def tn_exec_prepare(plans: Sequence[Plan], terms: Sequence[Terms], opts=None, st
                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
                                  C.byref(need), C.byref(h)))
     return Exec(h, list(plans), list(terms), ws, need.value)
+
+
+def polarization_circuits(circ, x, y, output: bool = True):
+    """The four circuits of <x| E |y>: targets v_k = y + i^k x (bond-2 states;
+    with ``output`` the circuit's ideal outputs of them), k = 0..3."""
+    import dataclasses
+    out = []
+    for k in range(4):
+        flat = np.concatenate([np.asarray(y, dtype=np.complex128).reshape(-1),
+                               np.asarray(x, dtype=np.complex128).reshape(-1), [1j ** k]])
+        out.append(dataclasses.replace(circ, target="circuit_output_sum2" if output else "sum2", v=flat))
+    return out
+
+
+def offdiagonal(circ, x, y, level: Optional[int] = None, output: bool = True, exact: bool = False,
+                opts=None, plan_kw=None):
+    """<x| E(|psi><psi|) |y> for product states x, y (n x 2; with ``output`` the
+    circuit's ideal outputs of them).  Four estimates with the bond-2 targets of
+    the polarization identity run as one packed schedule; tn_polarization_combine
+    gives A_xy(u), u = 0..level, as a complex array.  ``exact`` uses the four
+    doubled networks instead (one value, the exact element).  Returns
+    (A_xy, the four result dicts, the exec)."""
+    lev = circ.level if level is None else level
+    circs = polarization_circuits(circ, x, y, output)
+    kw = plan_kw or {}
+    if exact:
+        plans = [tn_plan_build_doubled(c, **kw) for c in circs]
+        terms = [tn_terms_enumerate(p, 0) for p in plans]
+    else:
+        plans = [tn_plan_build(c, lev, **kw) for c in circs]
+        terms = [tn_terms_enumerate(p, lev) for p in plans]
+    ex = tn_exec_prepare(plans, terms, opts or exec_opts())
+    raw = ex.run_raw()
+    L = raw[0].level
+    re = (C.c_double * (L + 1))()
+    im = (C.c_double * (L + 1))()
+    _check(lib().tn_polarization_combine(raw, re, im))
+    return np.array([complex(re[u], im[u]) for u in range(L + 1)]), [r.as_dict() for r in raw], ex
 
 
 def tn_plan_workspace(plans: Sequence[Plan], terms: Sequence[Terms]) -> int:

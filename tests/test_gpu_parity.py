@@ -578,3 +578,82 @@ def test_doubled_config2_brackets_the_estimate(torch):
     assert gold[-1] - 1e-12 <= f <= gold[-1] + b + 1e-12
     res2, plan2 = run_doubled(c, path_trials=16384, seed=7)
     assert abs(res2["A"][0] - f) <= 1e-12 * f, (res2["A"][0], f)
+
+
+# ---------------------------------------------------------------------------
+# off-diagonal elements <x| E |y>: four bond-2 targets packed in one schedule,
+# combined by the polarization identity
+# ---------------------------------------------------------------------------
+def _rand_product(rng, n):
+    z = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
+    return z / np.linalg.norm(z, axis=1, keepdims=True)
+
+
+def _basis(n, bits):
+    out = np.zeros((n, 2), dtype=np.complex128)
+    for q in range(n):
+        out[q, bits[q]] = 1.0
+    return out
+
+
+def _offdiag_tol(parts, u):
+    # each of the four values is its FP64 all-dominant term (1e-12) plus FP32
+    # corrections (about 1e-6 of their own size; 1e-5 allowed); the element
+    # itself can be far smaller than the four values
+    corr = max(abs(p["A"][u] - p["A"][0]) for p in parts)
+    return 1e-5 * corr + 1e-12 * max(abs(p["A"][0]) for p in parts) + 1e-15
+
+
+@pytest.mark.parametrize("seed,kind,output,n", [(91, "random", True, 5), (92, "adpd", False, 4),
+                                                (93, "depol", True, 6)])
+def test_offdiagonal_tiny_circuits_against_oracle(torch, seed, kind, output, n):
+    from oracle import offdiag
+    print(f"offdiag tiny {seed} {kind} {output}", flush=True)
+    rng = np.random.default_rng(seed)
+    c = W.tiny_random_circuit(rng, n, 8 * n, 4, noise=kind, level=3,
+                              target="circuit_output" if output else "product")
+    x, y = _rand_product(rng, n), _rand_product(rng, n)
+    got, parts, _ = tn.offdiagonal(c, x, y, 3, output)
+    ref = offdiag.element_cross(c, 3, x, y, output)["A"]
+    for u in range(4):
+        assert abs(got[u] - ref[u]) <= _offdiag_tol(parts, u), (u, got[u], ref[u])
+    assert abs(got[0] - ref[0]) <= 1e-12 * max(abs(p["A"][0]) for p in parts)   # FP64 dominant terms
+    ex, _, _ = tn.offdiagonal(c, x, y, output=output, exact=True)
+    assert abs(ex[0] - offdiag.element_exact(c, x, y, output)) <= 1e-12
+
+
+def test_offdiagonal_config1_against_density_matrix(torch):
+    from oracle import offdiag
+    print("offdiag config1", flush=True)
+    c = W.config(1, level=4)
+    n = c.n_qubits
+    x, y = _basis(n, [0] * n), _basis(n, [0] * (n - 1) + [1])
+    got, parts, _ = tn.offdiagonal(c, x, y, 4, True)
+    ref = offdiag.element_cross(c, 4, x, y, True)["A"]
+    for u in range(5):
+        assert abs(got[u] - ref[u]) <= _offdiag_tol(parts, u), (u, got[u], ref[u])
+    f = offdiag.element_exact(c, x, y, True)
+    assert abs(got[4] - f) <= _offdiag_tol(parts, 4)
+    ex, _, _ = tn.offdiagonal(c, x, y, output=True, exact=True)
+    assert abs(ex[0] - f) <= 1e-12
+
+
+def test_offdiagonal_config2_against_oracle_and_exact(torch):
+    """25 qubits (no density matrix): <0..0|E|0..01> on the circuit's outputs
+    at level 2 against the oracle's cross form (every term, two networks
+    each); the exact element (four doubled networks) lies within twice
+    Theorem 1's bound of it (||v_k||^2 = 2)."""
+    from oracle import bounds, offdiag
+    print("offdiag config2", flush=True)
+    c = W.config(2)
+    n = c.n_qubits
+    x, y = _basis(n, [0] * n), _basis(n, [0] * (n - 1) + [1])
+    got, parts, _ = tn.offdiagonal(c, x, y, c.level, True)
+    ref = offdiag.element_cross(c, c.level, x, y, True, diagonal=True)["A"]
+    for u in range(c.level + 1):
+        assert abs(got[u] - ref[u]) <= _offdiag_tol(parts, u), (u, got[u], ref[u])
+    ex, _, _ = tn.offdiagonal(c, x, y, output=True, exact=True, plan_kw={"path_trials": 16384})
+    b = bounds.rigorous_bound([bounds.split_norms(op.kraus) for op in c.noise_ops()], c.level)
+    print(f"A_xy(2) {got[-1]:.6e} exact {ex[0]:.6e} diff {abs(ex[0] - got[-1]):.2e} 2 bound {2 * b:.2e}",
+          flush=True)
+    assert abs(ex[0] - got[-1]) <= 2 * b + 1e-12

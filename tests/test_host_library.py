@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import channels, dense, doubled, estimate, network, terms as oterms
+from oracle import channels, dense, doubled, estimate, network, offdiag, terms as oterms
 from paper_2211_17028_amd import tn
 from tests.schedule_sim import Sim
 
@@ -334,3 +334,65 @@ def test_doubled_replay_wide_circuit_with_matrix_core_steps():
     assert abs(x[0] - want) <= 1e-12 * max(1.0, abs(want))
     r = estimate.estimate(c, 4, "network", reduce=True)
     assert abs(x[0] - r["A"][-1]) <= 1e-12 * max(1.0, abs(want))
+
+
+# ---------------------------------------------------------------------------
+# off-diagonal elements: bond-2 targets of the polarization identity
+# ---------------------------------------------------------------------------
+def _rand_product(rng, n):
+    z = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
+    return z / np.linalg.norm(z, axis=1, keepdims=True)
+
+
+def test_polarization_combine_matches_the_identity():
+    rng = np.random.default_rng(81)
+    res = (tn.tn_result * 4)()
+    a = rng.standard_normal((4, 3))
+    for k in range(4):
+        res[k].level = 2
+        for u in range(3):
+            res[k].A[u] = a[k, u]
+    re = (ctypes.c_double * 3)()
+    im = (ctypes.c_double * 3)()
+    assert tn.lib().tn_polarization_combine(res, re, im) == tn.TN_OK
+    want = sum((1j ** k) / 4 * a[k] for k in range(4))
+    assert np.allclose([complex(re[u], im[u]) for u in range(3)], want, rtol=0, atol=1e-15)
+    res[3].level = 1
+    assert tn.lib().tn_polarization_combine(res, re, im) == tn.TN_EINVAL
+
+
+def _levels_from_replay(x, pat, level):
+    t = np.zeros(level + 1)
+    for row, v in zip(pat, x):
+        t[int(np.count_nonzero(row))] += v
+    return np.cumsum(t)
+
+
+@pytest.mark.parametrize("seed,kind,output", [(82, "random", True), (83, "adpd", False), (84, "random", False)])
+def test_bond2_targets_replay_matches_the_cross_form(seed, kind, output):
+    """Each of the four polarization targets is a bond-2 network end (one
+    shared 2-valued index); the replayed estimates combined with i^k / 4 give
+    the oracle's cross-form element level by level."""
+    rng = np.random.default_rng(seed)
+    c = W.tiny_random_circuit(rng, 4, 18, 4, noise=kind, level=3,
+                              target="circuit_output" if output else "product")
+    x, y = _rand_product(rng, 4), _rand_product(rng, 4)
+    got = np.zeros(4, dtype=np.complex128)
+    for k, ck in enumerate(tn.polarization_circuits(c, x, y, output)):
+        xs, pat, _ = _replay(ck, 3)
+        got += (1j ** k) / 4 * _levels_from_replay(xs, pat, 3)
+    want = offdiag.element_cross(c, 3, x, y, output)["A"]
+    assert np.allclose(got, want, rtol=0, atol=2e-6), (got, want)
+    # the all-dominant terms come from the FP64 pass: level 0 agrees to rounding
+    assert abs(got[0] - want[0]) <= 1e-12
+
+
+def test_bond2_doubled_networks_give_the_exact_element():
+    rng = np.random.default_rng(85)
+    c = W.tiny_random_circuit(rng, 4, 16, 5, noise="random", level=2, target="circuit_output")
+    x, y = _rand_product(rng, 4), _rand_product(rng, 4)
+    got = 0j
+    for k, ck in enumerate(tn.polarization_circuits(c, x, y, True)):
+        xs, _, _, _ = _replay_doubled(ck)
+        got += (1j ** k) / 4 * xs[0]
+    assert abs(got - offdiag.element_exact(c, x, y, True)) <= 1e-12

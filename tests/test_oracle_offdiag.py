@@ -82,3 +82,12 @@ def test_polarization_identity_on_the_graded_matrices(output):
     exact = sum(wt * dense.exact_value(offdiag.sum2_circuit(c, p, q, cc, output))
                 for (p, q, cc), wt in offdiag.polarization_targets(x, y))
     assert abs(exact - offdiag.element_exact(c, x, y, output)) <= 1e-13
+
+
+def test_cross_form_with_diagonal_hyperedges_is_the_same():
+    c = tiny(78, n=5, gates=20, noise=4, kind="random")
+    rng = np.random.default_rng(178)
+    x, y = rand_product(rng, c.n_qubits), rand_product(rng, c.n_qubits)
+    a = offdiag.element_cross(c, 2, x, y, True)["A"]
+    b = offdiag.element_cross(c, 2, x, y, True, diagonal=True)["A"]
+    assert np.allclose(a, b, rtol=0, atol=1e-14)
