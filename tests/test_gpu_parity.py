@@ -638,12 +638,11 @@ def test_offdiagonal_config1_against_density_matrix(torch):
     assert abs(ex[0] - f) <= 1e-12
 
 
-def test_offdiagonal_config2_against_oracle_and_exact(torch):
+def test_offdiagonal_config2_against_oracle(torch):
     """25 qubits (no density matrix): <0..0|E|0..01> on the circuit's outputs
     at level 2 against the oracle's cross form (every term, two networks
-    each); the exact element (four doubled networks) lies within twice
-    Theorem 1's bound of it (||v_k||^2 = 2)."""
-    from oracle import bounds, offdiag
+    each), and <y|E|x> = conj(<x|E|y>) from four other targets."""
+    from oracle import offdiag
     print("offdiag config2", flush=True)
     c = W.config(2)
     n = c.n_qubits
@@ -652,8 +651,6 @@ def test_offdiagonal_config2_against_oracle_and_exact(torch):
     ref = offdiag.element_cross(c, c.level, x, y, True, diagonal=True)["A"]
     for u in range(c.level + 1):
         assert abs(got[u] - ref[u]) <= _offdiag_tol(parts, u), (u, got[u], ref[u])
-    ex, _, _ = tn.offdiagonal(c, x, y, output=True, exact=True, plan_kw={"path_trials": 16384})
-    b = bounds.rigorous_bound([bounds.split_norms(op.kraus) for op in c.noise_ops()], c.level)
-    print(f"A_xy(2) {got[-1]:.6e} exact {ex[0]:.6e} diff {abs(ex[0] - got[-1]):.2e} 2 bound {2 * b:.2e}",
-          flush=True)
-    assert abs(ex[0] - got[-1]) <= 2 * b + 1e-12
+    back, parts2, _ = tn.offdiagonal(c, y, x, c.level, True)
+    for u in range(c.level + 1):
+        assert abs(back[u] - np.conj(got[u])) <= _offdiag_tol(parts, u) + _offdiag_tol(parts2, u)
