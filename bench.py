@@ -192,6 +192,33 @@ def exact_value(circ, level, res, reps):
                         for k, v in sorted(st.items(), key=lambda kv: -kv[1]["ms"])}}
 
 
+def offdiagonal_value(circ, level, reps):
+    """<0..0|E|0..01> on the workload's ideal outputs (last qubit flipped):
+    four estimates with the bond-2 targets of the polarization identity,
+    packed in one schedule."""
+    import numpy as np
+    import torch
+    from paper_2211_17028_amd import tn
+    n = circ.n_qubits
+    x = np.zeros((n, 2), dtype=np.complex128)
+    x[:, 0] = 1
+    y = x.copy()
+    y[n - 1] = [0, 1]
+    t0 = time.perf_counter()
+    a, parts, ex = tn.offdiagonal(circ, x, y, level, True, opts=tn.exec_opts(use_graph=False))
+    prep_s = time.perf_counter() - t0
+    ex.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ex.run()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    return {"workload": "grid5x5_12L_10depol <0..0|E|0..01> level %d" % level,
+            "A_xy": [[v.real, v.imag] for v in a], "ms_per_element": ms, "plan_prepare_s": prep_s,
+            "terms": sum(p["n_terms"] for p in parts), "targets": 4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -206,6 +233,7 @@ def main():
     ap.add_argument("--no-paper-case", action="store_true", help="skip the 225-qubit context measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
+    ap.add_argument("--no-offdiag", action="store_true", help="skip the off-diagonal element")
     ap.add_argument("--exact-only", action="store_true",
                     help="only the exact value of the workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
@@ -373,6 +401,7 @@ def main():
         del e5
 
     exact = None if args.no_exact else exact_value(circ, level, res, 5)
+    offd = None if args.no_offdiag else offdiagonal_value(circ, level, 20)
 
     cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
     info = plan.info()
@@ -408,6 +437,7 @@ def main():
         "plain": plain,
         "paper_case": paper_case,
         "exact_value": exact,
+        "offdiagonal": offd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
