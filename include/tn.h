@@ -300,6 +300,37 @@ int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_
                 size_t ws_bytes, void* stream, tn_result* results);
 
 /* ---------------------------------------------------------------------------
+ * tn_terms_enumerate_factored -- exact cross-term reuse over independent
+ * clusters.  A term's amplitude is the product of its clusters' amplitudes
+ * and its weight a product over slots, so the level sums of the full level-l
+ * expansion (Algorithm 1) are the coefficients of the product of per-cluster
+ * level polynomials: A(l) = sum_{k<=l} [prod_c g_c](k), g_c(k) the sum over
+ * cluster c's own correction patterns with k corrections.  This set holds only
+ * terms whose corrections lie in one cluster: the all-dominant term, then for
+ * u = 1..level (ascending) and each cluster with at least u slots, that
+ * cluster's level-u terms (position sets and corrections in the order of
+ * tn_terms_enumerate restricted to its slots).  Terms are grouped by (level,
+ * cluster); group 0 is the all-dominant term.  Run it through tn_exec_prepare /
+ * tn_exec_run like any term set (its level sums there mix clusters and are not
+ * the estimate), sum X per group (tn_kernel_group_sums), and combine with
+ * tn_factored_levels.  n_groups receives the group count.  Host only.
+ * Errors: TN_EINVAL (level < 0, above TN_MAX_LEVEL, a doubled plan).
+ *
+ * tn_terms_groups -- group g's terms are [starts[g], starts[g+1]) (n_groups + 1
+ * entries), of level level[g] in cluster cluster[g] (-1 for group 0).  Any
+ * output may be NULL.  TN_EINVAL for a term set that is not factored.
+ *
+ * tn_factored_levels -- A(0..level) (level + 1 doubles) from the group sums
+ * h[g] (n_groups doubles, host): with X0 = h[0], r_c(0) = 1 and
+ * r_c(k) = h_c(k) / X0 (h_c(k) equals g_c(k) X0 / g_c(0)),
+ * A(l) = X0 sum_{k<=l} [prod_c r_c](k).  TN_EDEGENERATE if X0 = 0 at level > 0.
+ * ------------------------------------------------------------------------- */
+int tn_terms_enumerate_factored(tn_plan plan, int32_t level, tn_terms* out, int64_t* n_terms,
+                                int32_t* n_groups);
+int tn_terms_groups(tn_terms terms, int64_t* starts, int32_t* level, int32_t* cluster);
+int tn_factored_levels(tn_terms terms, const double* group_sums, double* A);
+
+/* ---------------------------------------------------------------------------
  * tn_polarization_combine -- an off-diagonal element <x| E(|psi><psi|) |y>
  * from four results (Section III, after Problem 1: the polarization identity
  * <x|A|y> = 1/4 sum_{k=0..3} i^k <v_k|A|v_k>).  r[k] is the result of the same

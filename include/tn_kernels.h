@@ -81,6 +81,18 @@ int tn_kernel_mfma_group(int32_t tile, const tn_mfma_job* d_jobs, const tn_mfma_
                          int64_t n_tiles, void* stream);
 int tn_kernel_mfma_split_reduce(int32_t tile, int32_t fp64, const tn_mfma_job* d_jobs,
                                 const tn_mfma_tile* d_tiles, int64_t n_tiles, void* stream);
+
+/* tn_kernel_group_sums: the level-sum kernel of the estimate (Algorithm 1's
+ * sums, Neumaier-compensated in FP64, fixed order: deterministic) over
+ * arbitrary ranges.  Group g sums d_x[d_starts[g] .. d_starts[g+1]) and writes
+ * (sum, compensation) to d_out[2g], d_out[2g+1] (the sum already includes the
+ * compensation).  All pointers are device addresses; d_starts has n_groups + 1
+ * entries.  One block per group, asynchronous on `stream`.  Used with the
+ * factored term sets of tn_terms_enumerate_factored (their group boundaries
+ * from tn_terms_groups) on the X output of tn_exec_outputs.
+ * Returns 0 or a negative TN_E* code. */
+int tn_kernel_group_sums(const double* d_x, const int64_t* d_starts, int32_t n_groups, double* d_out,
+                         void* stream);
 #ifdef __cplusplus
 }
 #endif

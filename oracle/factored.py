@@ -8,8 +8,8 @@ Algorithm 1 are the coefficients of a product of per-part polynomials:
     A(l) = |s|^2 sum_{k<=l} [prod_c g_c](k),
     g_c(k) = sum over the part's own patterns with k corrections of
              (prod_{s in c} d_{c_s}) |a_c|^2.
-Each part is contracted on its own (its tensors only, its own greedy order),
-once per local pattern, in complex128.
+Each part is contracted on its own (its tensors only, one greedy order per
+part), once per local pattern, in complex128.
 
 Parity pinned by (tests/test_oracle_factored.py): the global enumeration of
 ``estimate.estimate`` on circuits that split into several parts, the stored
@@ -50,15 +50,20 @@ def parts(net: network.KetNetwork):
     return [groups[k] for k in sorted(groups)]
 
 
-def _part_value(net, idx, slot_mats):
+def _part_path(net, idx):
+    legs = [list(net.tensors[i][1]) for i in idx]
+    return network.hyper_greedy_path(legs, trials=1) if net.diagonal else network.greedy_path(legs)
+
+
+def _part_value(net, idx, path, slot_mats):
     arrs, legs = [], []
     for i in idx:
         t, lg = net.tensors[i]
         arrs.append(np.asarray(slot_mats[t[1]], dtype=np.complex128) if isinstance(t, tuple) else t)
         legs.append(list(lg))
     if net.diagonal:
-        return network.contract_hyper(arrs, legs, network.hyper_greedy_path(legs, trials=1))
-    return network.contract_path(arrs, legs, network.greedy_path(legs))
+        return network.contract_hyper(arrs, legs, path)
+    return network.contract_path(arrs, legs, path)
 
 
 def factored_levels(circ, level: int, diagonal: bool = True):
@@ -72,6 +77,7 @@ def factored_levels(circ, level: int, diagonal: bool = True):
     for idx in parts(net):
         slots = sorted(net.tensors[i][0][1] for i in idx if isinstance(net.tensors[i][0], tuple))
         g = [Neumaier() for _ in range(level + 1)]
+        path = _part_path(net, idx)
         for k in range(min(level, len(slots)) + 1):
             for pos in itertools.combinations(range(len(slots)), k):
                 for corr in itertools.product((1, 2, 3), repeat=k):
@@ -84,7 +90,7 @@ def factored_levels(circ, level: int, diagonal: bool = True):
                         mats[s] = kk[ch]
                     if w == 0.0:
                         continue
-                    a = _part_value(net, idx, mats)
+                    a = _part_value(net, idx, path, mats)
                     g[k].add(w * (a.real * a.real + a.imag * a.imag))
         gv = np.array([x.value for x in g])
         gs.append(gv)

@@ -2003,6 +2003,36 @@ int tn_plan_build_doubled(const tn_circuit* circ, const tn_state* psi, const tn_
     });
 }
 
+int tn_terms_enumerate_factored(tn_plan plan, int32_t level, tn_terms* out, int64_t* n_terms,
+                                int32_t* n_groups) {
+    return guard([&] {
+        if (!plan || !out) fail(TN_EINVAL, "null handle");
+        Terms* t = enumerate_terms_factored(reinterpret_cast<Plan*>(plan), level);
+        *out = reinterpret_cast<tn_terms>(t);
+        if (n_terms) *n_terms = t->n;
+        if (n_groups) *n_groups = (int32_t)t->group_level.size();
+    });
+}
+
+int tn_terms_groups(tn_terms terms, int64_t* starts, int32_t* level, int32_t* cluster) {
+    return guard([&] {
+        if (!terms) fail(TN_EINVAL, "null handle");
+        const Terms* t = reinterpret_cast<const Terms*>(terms);
+        if (!t->factored) fail(TN_EINVAL, "not a factored term set");
+        const size_t ng = t->group_level.size();
+        if (starts) std::memcpy(starts, t->group_start.data(), (ng + 1) * sizeof(int64_t));
+        if (level) std::memcpy(level, t->group_level.data(), ng * sizeof(int32_t));
+        if (cluster) std::memcpy(cluster, t->group_cluster.data(), ng * sizeof(int32_t));
+    });
+}
+
+int tn_factored_levels(tn_terms terms, const double* group_sums, double* A) {
+    return guard([&] {
+        if (!terms || !group_sums || !A) fail(TN_EINVAL, "null pointer");
+        factored_levels(reinterpret_cast<const Terms*>(terms), group_sums, A);
+    });
+}
+
 int tn_polarization_combine(const tn_result* r, double* re, double* im) {
     return guard([&] {
         if (!r || !re || !im) fail(TN_EINVAL, "null pointer");
@@ -2559,3 +2589,15 @@ extern "C" int tn_kernel_mfma_split_reduce(int32_t tile, int32_t fp64, const tn_
         HIPCHK(hipGetLastError());
     });
 }
+
+extern "C" int tn_kernel_group_sums(const double* d_x, const int64_t* d_starts, int32_t n_groups, double* d_out,
+                                    void* stream) {
+    return guard([&] {
+        if (!d_x || !d_starts || !d_out || n_groups < 0 || n_groups >= (1 << 30))
+            tn::fail(TN_EINVAL, "bad group-sum launch arguments");
+        if (n_groups == 0) return;
+        tn::launch_level_sum(d_x, d_starts, n_groups, d_out, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+

@@ -1298,6 +1298,109 @@ Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune) {
 }
 
 // ---------------------------------------------------------------------------
+// Factored term set (exact cross-term reuse over independent clusters).  A
+// term's amplitude is the product of its clusters' amplitudes and its weight
+// the product of per-slot values, so X = prod_c X_c and the level sums of the
+// full expansion are the coefficients of the product of per-cluster level
+// polynomials g_c(k) (sums of X_c over the cluster's own patterns with k
+// corrections): A(l) = sum_{k<=l} [prod_c g_c](k).  The engine evaluates only
+// terms whose corrections all lie in one cluster; with X0 the all-dominant
+// term, h_c(k) = sum of X over those of cluster c and level k equals
+// g_c(k) X0 / g_c(0), so with r_c(0) = 1 and r_c(k) = h_c(k) / X0,
+// A(l) = X0 sum_{k<=l} [prod_c r_c](k).
+// Order: the all-dominant term; then for u = 1..level, for each cluster with
+// at least u slots, its position subsets and corrections in the order of
+// tn_terms_enumerate restricted to the cluster's slots (levels ascending).
+// ---------------------------------------------------------------------------
+Terms* enumerate_terms_factored(const Plan* p, int level) {
+    if (level < 0) fail(TN_EINVAL, "level must be >= 0");
+    if (p->doubled) fail(TN_EINVAL, "a doubled network has no slots to factor");
+    const int N = p->n_noise;
+    const int L = std::min(level, N);
+    if (L > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
+    auto t = std::make_unique<Terms>();
+    t->plan = p;
+    t->plan_id = p->id;
+    t->level = L;
+    t->factored = true;
+    auto push = [&](const std::vector<int8_t>& pat, int u) {
+        double w = 1.0;
+        bool zero = false;
+        for (int s = 0; s < N; ++s) {
+            w *= p->noise[s].d[pat[s]];
+            zero |= p->noise[s].zero[pat[s]];
+        }
+        t->pat.insert(t->pat.end(), pat.begin(), pat.end());
+        t->w.push_back(zero ? 0.0 : w);
+        t->lvl.push_back((uint8_t)u);
+        t->zero.push_back(zero ? 1 : 0);
+        t->pruned.push_back(0);
+    };
+    t->group_start.push_back(0);
+    t->group_level.push_back(0);
+    t->group_cluster.push_back(-1);
+    push(std::vector<int8_t>(N, 0), 0);
+    std::vector<int> pos, corr;
+    for (int u = 1; u <= L; ++u)
+        for (size_t c = 0; c < p->clusters.size(); ++c) {
+            const std::vector<int>& sl = p->clusters[c].slots;
+            const int ns = (int)sl.size();
+            if (ns < u) continue;
+            t->group_start.push_back((int64_t)t->w.size());
+            t->group_level.push_back(u);
+            t->group_cluster.push_back((int32_t)c);
+            pos.resize(u);
+            for (int i = 0; i < u; ++i) pos[i] = i;
+            while (true) {
+                corr.assign(u, 1);
+                while (true) {
+                    std::vector<int8_t> pat(N, 0);
+                    for (int i = 0; i < u; ++i) pat[sl[pos[i]]] = (int8_t)corr[i];
+                    push(pat, u);
+                    int j = u - 1;
+                    while (j >= 0 && corr[j] == 3) corr[j--] = 1;
+                    if (j < 0) break;
+                    ++corr[j];
+                }
+                int j = u - 1;
+                while (j >= 0 && pos[j] == ns - u + j) --j;
+                if (j < 0) break;
+                ++pos[j];
+                for (int i = j + 1; i < u; ++i) pos[i] = pos[i - 1] + 1;
+            }
+        }
+    t->n = (int64_t)t->w.size();
+    t->group_start.push_back(t->n);
+    return t.release();
+}
+
+void factored_levels(const Terms* t, const double* hs, double* A) {
+    if (!t->factored) fail(TN_EINVAL, "not a factored term set");
+    const int L = t->level;
+    const double x0 = hs[0];
+    if (L > 0 && x0 == 0.0)
+        fail(TN_EDEGENERATE, "the all-dominant term is zero: the factored levels need X0 != 0");
+    // r_c(k) per cluster (groups are ordered by level, then cluster)
+    std::vector<std::vector<double>> rc(t->plan->clusters.size(), std::vector<double>(L + 1, 0.0));
+    for (auto& v : rc) v[0] = 1.0;
+    for (size_t g = 1; g < t->group_level.size(); ++g) rc[t->group_cluster[g]][t->group_level[g]] += hs[g] / x0;
+    // prod_c r_c truncated at degree L, clusters in index order
+    std::vector<double> poly(L + 1, 0.0);
+    poly[0] = 1.0;
+    for (const std::vector<double>& r : rc) {
+        std::vector<double> np(L + 1, 0.0);
+        for (int a = 0; a <= L; ++a)
+            for (int b = 0; a + b <= L; ++b) np[a + b] += poly[a] * r[b];
+        poly.swap(np);
+    }
+    double acc = 0.0;
+    for (int k = 0; k <= L; ++k) {
+        acc += poly[k];
+        A[k] = x0 * acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // pruning features of every term (kNumFeatures floats per term)
 //   per corrected slot j = 0..2 (in position order; zeros when absent), 9:
 //     present, log(d_i / d_0), one-hot(i) x3, position op_index / n_ops,

@@ -94,6 +94,12 @@ struct Terms {
     std::vector<uint8_t> lvl;     // level of each term
     std::vector<uint8_t> zero;    // weight exactly zero (never contracted)
     std::vector<uint8_t> pruned;  // dropped by the pruning policy (never contracted)
+    // factored term sets (corrections within one cluster): group g covers terms
+    // [group_start[g], group_start[g + 1]) of level group_level[g] inside cluster
+    // group_cluster[g]; group 0 is the all-dominant term (cluster -1)
+    bool factored = false;
+    std::vector<int64_t> group_start;
+    std::vector<int32_t> group_level, group_cluster;
 };
 
 // plan.cpp
@@ -102,6 +108,8 @@ Plan* build_plan(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
 Plan* build_plan_doubled(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
                          const tn_plan_opts* opts);
 Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune);
+Terms* enumerate_terms_factored(const Plan* p, int level);
+void factored_levels(const Terms* t, const double* group_sums, double* A);
 std::string describe_plan(const Plan* p);
 int term_features(const Plan* p, const Terms* t, const double* level1_x, float* out);
 constexpr int kNumFeatures = 36;

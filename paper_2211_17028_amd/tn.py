@@ -93,7 +93,8 @@ class tn_plan_info(C.Structure):
 
 
 EXPORTS = [
-    "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate",
+    "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
@@ -122,6 +123,10 @@ def lib():
     L.tn_plan_build_doubled.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
                                         C.POINTER(tn_plan_opts), C.POINTER(vp)]
     L.tn_polarization_combine.argtypes = [C.POINTER(tn_result), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.tn_terms_enumerate_factored.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int32)]
+    L.tn_terms_groups.argtypes = [vp, vp, vp, vp]
+    L.tn_factored_levels.argtypes = [vp, vp, vp]
     L.tn_terms_enumerate.argtypes = [vp, C.c_int32, C.POINTER(tn_prune_opts), C.POINTER(vp),
                                      C.POINTER(C.c_int64)]
     L.tn_terms_get.argtypes = [vp, vp, vp]
@@ -417,6 +422,59 @@ def tn_exec_prepare(plans: Sequence[Plan], terms: Sequence[Terms], opts=None, st
     return Exec(h, list(plans), list(terms), ws, need.value)
 
 
+def tn_terms_enumerate_factored(plan: Plan, level: int) -> Terms:
+    """Terms with corrections inside one cluster, grouped by (level, cluster);
+    ``.groups`` = (starts, level, cluster) arrays."""
+    h = C.c_void_p()
+    n = C.c_int64()
+    ng = C.c_int32()
+    _check(lib().tn_terms_enumerate_factored(plan.handle, level, C.byref(h), C.byref(n), C.byref(ng)))
+    t = Terms(h, plan, n.value)
+    starts = np.zeros(ng.value + 1, dtype=np.int64)
+    lv = np.zeros(ng.value, dtype=np.int32)
+    cl = np.zeros(ng.value, dtype=np.int32)
+    _check(lib().tn_terms_groups(h, starts.ctypes.data, lv.ctypes.data, cl.ctypes.data))
+    t.groups = (starts, lv, cl)
+    return t
+
+
+def kernel_group_sums(d_x, d_starts, n_groups, d_out, stream=None):
+    """Deterministic FP64 sums of d_x over [d_starts[g], d_starts[g+1]) into
+    d_out[2g] (sum) and d_out[2g+1] (compensation); device pointers."""
+    _check(_kernel_lib().tn_kernel_group_sums(C.c_void_p(d_x), C.c_void_p(d_starts), n_groups,
+                                              C.c_void_p(d_out), _stream_ptr(stream)))
+
+
+class FactoredEstimate:
+    """A(0..level) by exact cross-term reuse over independent clusters: the
+    factored term set through the prepared schedule, per-group sums on the
+    device, the per-cluster level polynomials combined on the host."""
+
+    def __init__(self, circ, level: Optional[int] = None, opts=None, plan_kw=None):
+        import torch
+        lev = circ.level if level is None else level
+        self.plan = tn_plan_build(circ, lev, **(plan_kw or {}))
+        self.terms = tn_terms_enumerate_factored(self.plan, lev)
+        self.ex = tn_exec_prepare([self.plan], [self.terms], opts or exec_opts())
+        starts = self.terms.groups[0]
+        self.n_groups = len(starts) - 1
+        self.d_starts = torch.from_numpy(starts).cuda()
+        self.d_sums = torch.zeros(2 * max(1, self.n_groups), dtype=torch.float64, device="cuda")
+        self.h_sums = torch.zeros(2 * max(1, self.n_groups), dtype=torch.float64).pin_memory()
+
+    def run(self):
+        """(A(0..level), the exec's result dict) of one estimate on the current stream."""
+        stream = None
+        res = self.ex.run(stream)[0]
+        d_x, _, _ = self.ex.outputs()
+        kernel_group_sums(d_x, self.d_starts.data_ptr(), self.n_groups, self.d_sums.data_ptr(), stream)
+        self.h_sums.copy_(self.d_sums)
+        h = np.ascontiguousarray(self.h_sums.numpy()[0::2])
+        A = np.zeros(res["level"] + 1, dtype=np.float64)
+        _check(lib().tn_factored_levels(self.terms.handle, h.ctypes.data, A.ctypes.data))
+        return A, res
+
+
 def polarization_circuits(circ, x, y, output: bool = True):
     """The four circuits of <x| E |y>: targets v_k = y + i^k x (bond-2 states;
     with ``output`` the circuit's ideal outputs of them), k = 0..3."""
@@ -501,6 +559,8 @@ def _kernel_lib():
         L.tn_kernel_mfma_group.restype = C.c_int
         L.tn_kernel_mfma_split_reduce.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int64, vp]
         L.tn_kernel_mfma_split_reduce.restype = C.c_int
+        L.tn_kernel_group_sums.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.tn_kernel_group_sums.restype = C.c_int
         L._kernel_sigs = True
     return L
 

@@ -654,3 +654,40 @@ def test_offdiagonal_config2_against_oracle(torch):
     back, parts2, _ = tn.offdiagonal(c, y, x, c.level, True)
     for u in range(c.level + 1):
         assert abs(back[u] - np.conj(got[u])) <= _offdiag_tol(parts, u) + _offdiag_tol(parts2, u)
+
+
+# ---------------------------------------------------------------------------
+# exact cross-term reuse: factored term sets over independent clusters
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,kind", [(121, "random"), (122, "adpd"), (123, "depol")])
+def test_factored_two_block_circuits_against_oracle(torch, seed, kind):
+    from tests.test_oracle_factored import two_blocks
+    print(f"factored two blocks {seed} {kind}", flush=True)
+    c = two_blocks(seed, kind=kind)
+    A, _ = tn.FactoredEstimate(c, 4).run()
+    ref = estimate.estimate(c, 4, "network")["A"]
+    assert abs(A[0] - ref[0]) <= 1e-12 * ref[0]
+    for u in range(5):
+        assert abs(A[u] - ref[u]) <= 1e-8 * ref[u], (u, A[u], ref[u])
+
+
+def test_factored_config5_against_oracle(torch):
+    """225 qubits, 20 noises in 9 independent clusters: level 3 from 2815
+    factored terms against the stored sums of all 32551; level 5 (2.0M terms
+    in the full expansion) against the oracle's per-part polynomials; the
+    levels rise toward the exact value (doubled network)."""
+    from oracle import factored
+    print("factored config5", flush=True)
+    c = W.config(5)
+    fe3 = tn.FactoredEstimate(c, 3)
+    assert fe3.terms.n == 2815
+    A3, _ = fe3.run()
+    gold = np.loadtxt(os.path.join(GOLD, "config5_oracle.txt"))
+    for u in range(4):
+        assert abs(A3[u] - gold[u]) <= 1e-8 * gold[u], (u, A3[u], gold[u])
+    A5, _ = tn.FactoredEstimate(c, 5).run()
+    ref = factored.factored_levels(c, 5)["A"]
+    for u in range(6):
+        assert abs(A5[u] - ref[u]) <= 1e-8 * ref[u], (u, A5[u], ref[u])
+    f, _ = run_doubled(c)
+    assert all(A5[u] <= A5[u + 1] + 1e-15 for u in range(5)) and A5[5] <= f["A"][0] + 1e-12

@@ -396,3 +396,52 @@ def test_bond2_doubled_networks_give_the_exact_element():
         xs, _, _, _ = _replay_doubled(ck)
         got += (1j ** k) / 4 * xs[0]
     assert abs(got - offdiag.element_exact(c, x, y, True)) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# exact cross-term reuse: factored term sets over independent clusters
+# ---------------------------------------------------------------------------
+def _two_blocks(seed, kind="random"):
+    from tests.test_oracle_factored import two_blocks
+    return two_blocks(seed, kind=kind)
+
+
+def test_factored_terms_cover_single_cluster_patterns():
+    c = W.config(5)
+    plan = tn.tn_plan_build(c, 3)
+    t = tn.tn_terms_enumerate_factored(plan, 3)
+    starts, lv, cl = t.groups
+    pat, w = t.get()
+    assert starts[0] == 0 and starts[-1] == t.n and lv[0] == 0 and cl[0] == -1
+    assert np.all(np.diff(lv) >= 0)                       # levels ascending
+    clusters = [set(x["slots"]) for x in plan.describe()["clusters"]]
+    for g in range(1, len(lv)):
+        rows = pat[starts[g]:starts[g + 1]]
+        assert np.all((rows != 0).sum(1) == lv[g])
+        assert all(set(np.flatnonzero(r)) <= clusters[cl[g]] for r in rows)
+    # every single-cluster pattern up to level 3, once
+    import math
+    want = 1 + sum(math.comb(len(s), u) * 3 ** u for s in clusters for u in range(1, 4))
+    assert t.n == want < 32551
+    with pytest.raises(tn.TNError):
+        tn.tn_terms_enumerate_factored(tn.tn_plan_build_doubled(c), 1)
+
+
+@pytest.mark.parametrize("seed,kind", [(111, "random"), (112, "adpd")])
+def test_factored_replay_matches_the_global_oracle(seed, kind):
+    c = _two_blocks(seed, kind)
+    plan = tn.tn_plan_build(c, 4)
+    assert plan.info()["n_clusters"] >= 2
+    t = tn.tn_terms_enumerate_factored(plan, 4)
+    desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(use_graph=False))
+    sim = Sim(desc, cb)
+    _, w = t.get()
+    sim.run([[i for i in range(t.n) if w[i] != 0.0]])
+    x, _ = sim.outputs()
+    starts = t.groups[0]
+    h = np.array([x[starts[g]:starts[g + 1]].sum() for g in range(len(starts) - 1)])
+    A = np.zeros(5)
+    assert tn.lib().tn_factored_levels(t.handle, h.ctypes.data, A.ctypes.data) == tn.TN_OK
+    ref = estimate.estimate(c, 4, "network")["A"]
+    assert np.allclose(A, ref, rtol=2e-6, atol=0), (A, ref)
+    assert abs(A[0] - ref[0]) <= 1e-12 * ref[0]
