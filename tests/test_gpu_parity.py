@@ -667,8 +667,8 @@ def test_factored_two_block_circuits_against_oracle(torch, seed, kind):
     A, _ = tn.FactoredEstimate(c, 4).run()
     ref = estimate.estimate(c, 4, "network")["A"]
     assert abs(A[0] - ref[0]) <= 1e-12 * ref[0]
-    for u in range(5):
-        assert abs(A[u] - ref[u]) <= 1e-8 * ref[u], (u, A[u], ref[u])
+    for u in range(5):   # FP32 corrections: the 1e-6 bar of the level sums
+        assert abs(A[u] - ref[u]) <= 1e-6 * ref[u], (u, A[u], ref[u])
 
 
 def test_factored_config5_against_oracle(torch):
