@@ -673,8 +673,8 @@ def test_factored_two_block_circuits_against_oracle(torch, seed, kind):
 
 def test_factored_config5_against_oracle(torch):
     """225 qubits, 20 noises in 9 independent clusters: level 3 from 2815
-    factored terms against the stored sums of all 32551; level 5 (2.0M terms
-    in the full expansion) against the oracle's per-part polynomials; the
+    factored terms against the stored sums of all 32551; level 5 (4.19M terms
+    in the full expansion, 43720 factored) against the oracle's per-part polynomials; the
     levels rise toward the exact value (doubled network)."""
     from oracle import factored
     print("factored config5", flush=True)
