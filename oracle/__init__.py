@@ -21,8 +21,10 @@ Modules
                Algorithm 1's terms, bond-2 polarization targets
   factored  -- level sums as a product of per-part level polynomials when the
                network splits into independent parts
+  trajectories -- the quantum-trajectories estimate (Kraus draws, one network per
+               sample), the paper's main comparison
   bounds    -- Theorem 1 (contraction count; error bound in the form its proof
                actually establishes)
   estimate  -- driver: T_u, A(l) for every l' <= l, per-term values
 """
-from . import channels, terms, dense, literal, network, doubled, offdiag, factored, bounds, estimate  # noqa: F401
+from . import channels, terms, dense, literal, network, doubled, offdiag, factored, trajectories, bounds, estimate  # noqa: F401

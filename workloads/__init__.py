@@ -10,5 +10,5 @@ from .circuits import (  # noqa: F401
     Op, Circuit, haar_su2, gate_h, gate_x, gate_y, gate_z, gate_t, gate_rx,
     gate_ry, gate_rz, gate_cz, gate_rzz, kraus_depolarizing, kraus_ad_pd,
     chain_layers, grid_layers, qaoa_3regular, place_noises, config, CONFIG_NAMES,
-    random_isometry_kraus, tiny_random_circuit,
+    random_isometry_kraus, tiny_random_circuit, trajectory_uniforms,
 )

@@ -420,3 +420,9 @@ def tiny_random_circuit(rng: np.random.Generator, n: int, n_gates: int, n_noise:
     else:
         raise ValueError(target)
     return Circuit(n, ops, psi, target, v, level=level, name=f"tiny{n}")
+
+
+def trajectory_uniforms(n_samples: int, n_noise: int, seed: int) -> np.ndarray:
+    """Seeded uniforms in [0, 1), one per (sample, noise): the random input of
+    a trajectories run (the draws are made from them by each implementation)."""
+    return np.random.default_rng(seed).random((n_samples, n_noise))
