@@ -300,6 +300,31 @@ int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_
                 size_t ws_bytes, void* stream, tn_result* results);
 
 /* ---------------------------------------------------------------------------
+ * tn_plan_build_trajectories / tn_terms_trajectories -- the quantum-trajectories
+ * estimate, the paper's comparison method (Section V), on the same engine.
+ * Noise s draws Kraus operator k with probability q_k = tr(E_k^+ E_k) / 2 (they
+ * sum to 1 for a channel, Section II) and its slot carries E_k / sqrt(q_k), so
+ * for any draws the mean of X = |<v| ... |psi>|^2 over samples has expectation
+ * <v| E(|psi><psi|) |v>.  The plan is built like tn_plan_build (same network,
+ * light cone and path search; at most 4 Kraus operators per noise, else
+ * TN_EUNSUPPORTED; degenerate channels are fine).  tn_terms_trajectories makes
+ * n_samples terms from `uniforms` (host, n_samples x n_noise values in [0, 1),
+ * row-major; the caller's random numbers): sample i takes, for noise s, the
+ * first k with q_k > 0 and uniforms[i n_noise + s] < q_0 + ... + q_k.  Every
+ * term has weight 1 / n_samples and level 0, so an estimate over the set
+ * reports the sample mean as A[0] (bound -1: not a truncation); the per-sample
+ * X are in tn_exec_outputs / tn_exec_copy_outputs (sample 0 in FP64, the rest
+ * FP32).  Repeated draws share their contraction (instances).  A trajectories
+ * plan rejects tn_terms_enumerate and tn_terms_enumerate_factored (TN_EINVAL).
+ * Errors: as tn_plan_build; TN_EINVAL for n_samples < 1, a uniform outside
+ * [0, 1), a plan that is not a trajectories plan.  Host only.
+ * ------------------------------------------------------------------------- */
+int tn_plan_build_trajectories(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                               const tn_plan_opts* opts, tn_plan* out);
+int tn_terms_trajectories(tn_plan plan, int64_t n_samples, const double* uniforms, tn_terms* out,
+                          int64_t* n_terms);
+
+/* ---------------------------------------------------------------------------
  * tn_terms_enumerate_factored -- exact cross-term reuse over independent
  * clusters.  A term's amplitude is the product of its clusters' amplitudes
  * and its weight a product over slots, so the level sums of the full level-l

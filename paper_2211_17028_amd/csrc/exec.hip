@@ -1302,8 +1302,11 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
             pe.live_terms.push_back(t);
         }
         pe.n_live = (int64_t)pe.live_terms.size();
-        // the all-dominant term is term 0 of the enumeration
-        if (T.n > 0 && T.lvl[0] == 0 && live_index[0] >= 0) pe.zero_term = 0;
+        // the all-dominant term is term 0 of the enumeration (a sampled term set
+        // has one only if its first draw is the all-first pattern)
+        if (T.n > 0 && T.lvl[0] == 0 && live_index[0] >= 0 &&
+            std::all_of(T.pat.begin(), T.pat.begin() + P.n_noise, [](int8_t c) { return c == 0; }))
+            pe.zero_term = 0;
         const int ncl = (int)P.clusters.size();
         // one live term, the all-dominant one, recomputed in FP64 (a level-0 term
         // set, a doubled network): the FP32 chain would compute a value nothing reads
@@ -2003,6 +2006,24 @@ int tn_plan_build_doubled(const tn_circuit* circ, const tn_state* psi, const tn_
     });
 }
 
+int tn_plan_build_trajectories(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                               const tn_plan_opts* opts, tn_plan* out) {
+    return guard([&] {
+        if (!out) fail(TN_EINVAL, "null output handle");
+        *out = reinterpret_cast<tn_plan>(build_plan_trajectories(circ, psi, v, opts));
+    });
+}
+
+int tn_terms_trajectories(tn_plan plan, int64_t n_samples, const double* uniforms, tn_terms* out,
+                          int64_t* n_terms) {
+    return guard([&] {
+        if (!plan || !out) fail(TN_EINVAL, "null handle");
+        Terms* t = sample_terms(reinterpret_cast<Plan*>(plan), n_samples, uniforms);
+        *out = reinterpret_cast<tn_terms>(t);
+        if (n_terms) *n_terms = t->n;
+    });
+}
+
 int tn_terms_enumerate_factored(tn_plan plan, int32_t level, tn_terms* out, int64_t* n_terms,
                                 int32_t* n_groups) {
     return guard([&] {
@@ -2284,7 +2305,7 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
             }
             double b = 0;
             for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
-            r.bound = b;
+            r.bound = P.trajectories ? -1.0 : b;   // a sample mean has no truncation bound
             // FP32 value of the all-dominant term (diagnostic, written by the finalize)
             r.x0_fp32 = -1;
             if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)

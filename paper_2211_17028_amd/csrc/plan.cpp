@@ -1119,12 +1119,63 @@ static PathOpts path_opts(const tn_plan_opts* opts) {
     return o;
 }
 
+static Plan* finish_plan(std::unique_ptr<Plan> p, const tn_circuit* c, const tn_state* psi, const tn_state* v,
+                         int level, const tn_plan_opts* opts);
+
 Plan* build_plan(const tn_circuit* c, const tn_state* psi, const tn_state* v, int level,
                  const tn_plan_opts* opts) {
     if (level < 0) fail(TN_EINVAL, "level must be >= 0");
     auto p = new_plan(c, psi, v);
     for (int64_t k = 0; k < c->n_ops; ++k)
         if (c->ops[k].kind == TN_NOISE) p->noise.push_back(split_noise(c->ops[k], k));
+    return finish_plan(std::move(p), c, psi, v, level, opts);
+}
+
+// Slot matrices of the quantum-trajectories estimate (the paper's comparison
+// method, Section V): Kraus operator k of a noise is drawn with probability
+// q_k = tr(E_k^+ E_k) / 2 and its slot carries E_k / sqrt(q_k) with weight 1,
+// so the mean of |a|^2 over draws is the exact value.  At most 4 Kraus
+// operators (the slot choices of a term); operators with q_k = 0 are never
+// drawn and flagged zero.
+static NoiseSplit kraus_slots(const tn_op& op, int64_t index) {
+    check_cptp(op, index);
+    if (op.n_kraus > 4) fail(TN_EUNSUPPORTED, "trajectories take at most 4 Kraus operators per noise");
+    NoiseSplit ns;
+    ns.qubit = op.q[0];
+    ns.op_index = index;
+    for (int k = 0; k < 4; ++k) {
+        ns.zero[k] = true;
+        ns.d[k] = 0.0;
+        for (int e = 0; e < 4; ++e) ns.K[k][e] = 0.0;
+        if (k >= op.n_kraus) continue;
+        const tn_c128* m = op.mat + 4 * k;
+        double q = 0.0;
+        for (int e = 0; e < 4; ++e) q += m[e].re * m[e].re + m[e].im * m[e].im;
+        q *= 0.5;
+        ns.q[k] = q;
+        if (!(q > 0.0)) continue;
+        ns.zero[k] = false;
+        ns.d[k] = 1.0;
+        const double r = 1.0 / std::sqrt(q);
+        for (int e = 0; e < 4; ++e) ns.K[k][e] = cd(m[e].re * r, m[e].im * r);
+    }
+    return ns;
+}
+
+Plan* build_plan_trajectories(const tn_circuit* c, const tn_state* psi, const tn_state* v,
+                              const tn_plan_opts* opts) {
+    auto p = new_plan(c, psi, v);
+    for (int64_t k = 0; k < c->n_ops; ++k)
+        if (c->ops[k].kind == TN_NOISE) p->noise.push_back(kraus_slots(c->ops[k], k));
+    p->trajectories = true;
+    // the path's instance model: samples differ from the all-first pattern in
+    // a few slots, like a level-3 term set
+    const int level = std::min<int>(3, (int)p->noise.size());
+    return finish_plan(std::move(p), c, psi, v, level, opts);
+}
+
+static Plan* finish_plan(std::unique_ptr<Plan> p, const tn_circuit* c, const tn_state* psi, const tn_state* v,
+                         int level, const tn_plan_opts* opts) {
     // past light cone of every noise slot (features of the pruning policy)
     {
         const int words = (c->n_qubits + 63) / 64;
@@ -1241,6 +1292,7 @@ Plan* build_plan_doubled(const tn_circuit* c, const tn_state* psi, const tn_stat
 // ---------------------------------------------------------------------------
 Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune) {
     if (level < 0) fail(TN_EINVAL, "level must be >= 0");
+    if (p->trajectories) fail(TN_EINVAL, "a trajectories plan takes sampled terms (tn_terms_trajectories)");
     const int N = p->n_noise;
     const int L = std::min(level, N);
     if (L > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
@@ -1315,6 +1367,7 @@ Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune) {
 Terms* enumerate_terms_factored(const Plan* p, int level) {
     if (level < 0) fail(TN_EINVAL, "level must be >= 0");
     if (p->doubled) fail(TN_EINVAL, "a doubled network has no slots to factor");
+    if (p->trajectories) fail(TN_EINVAL, "a trajectories plan takes sampled terms (tn_terms_trajectories)");
     const int N = p->n_noise;
     const int L = std::min(level, N);
     if (L > TN_MAX_LEVEL) fail(TN_EINVAL, "level above TN_MAX_LEVEL");
@@ -1371,6 +1424,43 @@ Terms* enumerate_terms_factored(const Plan* p, int level) {
         }
     t->n = (int64_t)t->w.size();
     t->group_start.push_back(t->n);
+    return t.release();
+}
+
+// Quantum-trajectories samples: sample i draws, for noise s, the first Kraus
+// index k (among those with q_k > 0) with u[i][s] < q_0 + ... + q_k; every
+// sample has weight 1 / n_samples, so the level-0 sum is the sample mean.
+Terms* sample_terms(const Plan* p, int64_t n_samples, const double* u) {
+    if (!p->trajectories) fail(TN_EINVAL, "samples need a trajectories plan");
+    if (n_samples < 1 || !u) fail(TN_EINVAL, "need at least one sample and its uniforms");
+    const int N = p->n_noise;
+    auto t = std::make_unique<Terms>();
+    t->plan = p;
+    t->plan_id = p->id;
+    t->level = 0;
+    const double w = 1.0 / (double)n_samples;
+    t->pat.resize((size_t)n_samples * N);
+    for (int64_t i = 0; i < n_samples; ++i) {
+        for (int s = 0; s < N; ++s) {
+            const NoiseSplit& ns = p->noise[s];
+            const double x = u[i * N + s];
+            if (!(x >= 0.0 && x < 1.0)) fail(TN_EINVAL, "uniforms must lie in [0, 1)");
+            double acc = 0.0;
+            int pick = -1, last = 0;
+            for (int k = 0; k < 4; ++k) {
+                if (ns.zero[k]) continue;
+                acc += ns.q[k];
+                last = k;
+                if (x < acc) { pick = k; break; }
+            }
+            t->pat[(size_t)i * N + s] = (int8_t)(pick < 0 ? last : pick);
+        }
+        t->w.push_back(w);
+        t->lvl.push_back(0);
+        t->zero.push_back(0);
+        t->pruned.push_back(0);
+    }
+    t->n = n_samples;
     return t.release();
 }
 

@@ -40,6 +40,7 @@ struct NoiseSplit {
     int cone_qubits = 0;
     int cone_2q_gates = 0;        // 2-qubit gates in the past light cone
     double khat_norm2[4] = {0, 0, 0, 0};  // ||sqrt(2) K_i||_2^2 (term bound factor)
+    double q[4] = {0, 0, 0, 0};   // trajectories: draw probabilities tr(E_k^+ E_k) / 2
 };
 
 // One tensor of the reduced ket network.  All legs have dimension 2;
@@ -79,6 +80,9 @@ struct Plan {
     // full superoperator tensor; no slots, one term, value Re(a) instead of |a|^2
     bool doubled = false;
     int n_channels = 0;           // noises of the circuit (all inside the network)
+    // quantum-trajectories plan: slot k of a noise is its Kraus operator
+    // E_k / sqrt(q_k) with weight 1 (terms are sampled, not enumerated)
+    bool trajectories = false;
     int max_log = 0;
     double cmacs_per_term = 0;
     std::string target_kind;
@@ -109,6 +113,9 @@ Plan* build_plan_doubled(const tn_circuit* circ, const tn_state* psi, const tn_s
                          const tn_plan_opts* opts);
 Terms* enumerate_terms(const Plan* p, int level, const tn_prune_opts* prune);
 Terms* enumerate_terms_factored(const Plan* p, int level);
+Plan* build_plan_trajectories(const tn_circuit* circ, const tn_state* psi, const tn_state* v,
+                              const tn_plan_opts* opts);
+Terms* sample_terms(const Plan* p, int64_t n_samples, const double* uniforms);
 void factored_levels(const Terms* t, const double* group_sums, double* A);
 std::string describe_plan(const Plan* p);
 int term_features(const Plan* p, const Terms* t, const double* level1_x, float* out);

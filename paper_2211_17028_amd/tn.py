@@ -94,7 +94,8 @@ class tn_plan_info(C.Structure):
 
 EXPORTS = [
     "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate",
-    "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels",
+    "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
@@ -126,6 +127,9 @@ def lib():
     L.tn_terms_enumerate_factored.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(C.c_int64),
                                               C.POINTER(C.c_int32)]
     L.tn_terms_groups.argtypes = [vp, vp, vp, vp]
+    L.tn_plan_build_trajectories.argtypes = [C.POINTER(tn_circuit), C.POINTER(tn_state), C.POINTER(tn_state),
+                                             C.POINTER(tn_plan_opts), C.POINTER(vp)]
+    L.tn_terms_trajectories.argtypes = [vp, C.c_int64, vp, C.POINTER(vp), C.POINTER(C.c_int64)]
     L.tn_factored_levels.argtypes = [vp, vp, vp]
     L.tn_terms_enumerate.argtypes = [vp, C.c_int32, C.POINTER(tn_prune_opts), C.POINTER(vp),
                                      C.POINTER(C.c_int64)]
@@ -420,6 +424,38 @@ def tn_exec_prepare(plans: Sequence[Plan], terms: Sequence[Terms], opts=None, st
                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
                                  C.byref(need), C.byref(h)))
     return Exec(h, list(plans), list(terms), ws, need.value)
+
+
+def tn_plan_build_trajectories(circ, path_trials: int = 0, seed: int = 0, light_cone: bool = True,
+                               max_log_size: int = 0, diagonal_hyperedges: bool = True,
+                               max_work_bytes: float = 0.0, reconfigure: bool = True) -> Plan:
+    """Plan whose slots are the Kraus operators E_k / sqrt(q_k) (quantum trajectories)."""
+    bufs = _CircuitBuffers(circ)
+    opts = tn_plan_opts(path_trials, seed, 0 if light_cone else 1, max_log_size,
+                        0 if diagonal_hyperedges else 1, max_work_bytes, 0 if reconfigure else 1)
+    h = C.c_void_p()
+    _check(lib().tn_plan_build_trajectories(C.byref(bufs.circ), C.byref(bufs.psi), C.byref(bufs.v),
+                                            C.byref(opts), C.byref(h)))
+    return Plan(h, circ)
+
+
+def tn_terms_trajectories(plan: Plan, uniforms: np.ndarray) -> Terms:
+    """Sampled terms from (n_samples, n_noise) uniforms in [0, 1)."""
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    h = C.c_void_p()
+    n = C.c_int64()
+    _check(lib().tn_terms_trajectories(plan.handle, u.shape[0], u.ctypes.data, C.byref(h), C.byref(n)))
+    return Terms(h, plan, n.value)
+
+
+def trajectories_estimate(circ, uniforms: np.ndarray, opts=None, plan_kw=None):
+    """(sample mean, per-sample X, exec) of the quantum-trajectories estimate."""
+    plan = tn_plan_build_trajectories(circ, **(plan_kw or {}))
+    terms = tn_terms_trajectories(plan, uniforms)
+    ex = tn_exec_prepare([plan], [terms], opts or exec_opts())
+    res = ex.run()[0]
+    x, _ = ex.values()                 # w X with w = 1 / n_samples
+    return res["A"][0], x * terms.n, ex
 
 
 def tn_terms_enumerate_factored(plan: Plan, level: int) -> Terms:

@@ -691,3 +691,41 @@ def test_factored_config5_against_oracle(torch):
         assert abs(A5[u] - ref[u]) <= 1e-8 * ref[u], (u, A5[u], ref[u])
     f, _ = run_doubled(c)
     assert all(A5[u] <= A5[u + 1] + 1e-15 for u in range(5)) and A5[5] <= f["A"][0] + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# quantum trajectories on the same engine
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,kind,target", [(151, "random", "circuit_output"), (152, "adpd", "product"),
+                                               (153, "depol", "dense")])
+def test_trajectories_tiny_circuits_against_oracle(torch, seed, kind, target):
+    from oracle import dense, trajectories
+    print(f"trajectories tiny {seed} {kind}", flush=True)
+    c = W.tiny_random_circuit(np.random.default_rng(seed), 5, 30, 5, noise=kind, level=1, target=target,
+                              scale=5.0)
+    u = W.trajectory_uniforms(2000, c.n_noises, seed)
+    mean, x, _ = tn.trajectories_estimate(c, u)
+    ref = trajectories.estimate(c, u)
+    assert np.allclose(x, ref["X"], rtol=2e-5, atol=1e-9)
+    assert abs(mean - ref["mean"]) <= 2e-6 * ref["mean"]
+    assert abs(mean - dense.exact_value(c)) <= 5 * ref["stderr"]
+
+
+def test_trajectories_config2_against_oracle(torch):
+    """25 qubits: 4096 draws of the 10 depolarizing noises; 64 sampled scores
+    against the oracle one by one; the mean within five standard errors of
+    the exact value (the oracle's full level-2 sum, 2.6e-11 below it)."""
+    from oracle import trajectories
+    print("trajectories config2", flush=True)
+    c = W.config(2)
+    u = W.trajectory_uniforms(4096, c.n_noises, 2211)
+    mean, x, _ = tn.trajectories_estimate(c, u)
+    net = network.KetNetwork(c, diagonal=True)
+    idx = trajectories.sample_indices(c, u)
+    for i in np.random.default_rng(5).choice(4096, 64, replace=False):
+        ref = trajectories.sample_value(net, c, idx[i])
+        assert abs(x[i] - ref) <= 2e-5 * ref + 1e-9, (i, x[i], ref)
+    gold = np.loadtxt(os.path.join(GOLD, "config2_oracle.txt"))
+    se = x.std(ddof=1) / np.sqrt(len(x))
+    print(f"mean {mean:.9f} exact {gold[-1]:.9f} stderr {se:.2e}", flush=True)
+    assert abs(mean - gold[-1]) <= 5 * se + 1e-10

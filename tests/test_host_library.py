@@ -445,3 +445,42 @@ def test_factored_replay_matches_the_global_oracle(seed, kind):
     ref = estimate.estimate(c, 4, "network")["A"]
     assert np.allclose(A, ref, rtol=2e-6, atol=0), (A, ref)
     assert abs(A[0] - ref[0]) <= 1e-12 * ref[0]
+
+
+# ---------------------------------------------------------------------------
+# quantum trajectories on the same engine
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,kind,target", [(141, "random", "circuit_output"), (142, "adpd", "product"),
+                                               (143, "depol", "dense")])
+def test_trajectories_replay_matches_the_oracle_sample_by_sample(seed, kind, target):
+    from oracle import trajectories
+    c = W.tiny_random_circuit(np.random.default_rng(seed), 4, 18, 4, noise=kind, level=1, target=target,
+                              scale=5.0)
+    u = W.trajectory_uniforms(300, c.n_noises, seed)
+    plan = tn.tn_plan_build_trajectories(c)
+    t = tn.tn_terms_trajectories(plan, u)
+    pat, w = t.get()
+    ref = trajectories.estimate(c, u)
+    assert np.array_equal(pat, ref["idx"])                  # the same draws from the same uniforms
+    assert np.allclose(w, 1.0 / 300)
+    desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(use_graph=False))
+    sim = Sim(desc, cb)
+    sim.run([list(range(t.n))])
+    x, _ = sim.outputs()
+    assert np.allclose(x * 300, ref["X"], rtol=2e-5, atol=1e-9)
+    assert abs(x.sum() - ref["mean"]) <= 2e-6 * ref["mean"]
+
+
+def test_trajectories_plan_rejects_enumeration_and_bad_input():
+    c = W.tiny_random_circuit(np.random.default_rng(144), 3, 10, 3, noise="random", level=1)
+    plan = tn.tn_plan_build_trajectories(c)
+    for call in (lambda: tn.tn_terms_enumerate(plan, 1), lambda: tn.tn_terms_enumerate_factored(plan, 1),
+                 lambda: tn.tn_terms_trajectories(plan, np.full((2, 3), 1.0)),
+                 lambda: tn.tn_terms_trajectories(tn.tn_plan_build(c, 1), np.zeros((2, 3)))):
+        with pytest.raises(tn.TNError) as e:
+            call()
+        assert e.value.code == tn.TN_EINVAL
+    ops = list(c.ops) + [W.Op("noise", (0,), kraus=[np.eye(2) * np.sqrt(0.2)] * 5)]
+    with pytest.raises(tn.TNError) as e:
+        tn.tn_plan_build_trajectories(W.Circuit(3, ops, c.psi, c.target, c.v, 1))
+    assert e.value.code == tn.TN_EUNSUPPORTED
