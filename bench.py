@@ -219,6 +219,36 @@ def offdiagonal_value(circ, level, reps):
             "terms": sum(p["n_terms"] for p in parts), "targets": 4}
 
 
+def trajectories_value(circ, f_exact, reps):
+    """The paper's comparison method on the same engine: 65536 quantum-trajectory
+    draws of the workload's noises (seeded uniforms), one network per distinct
+    draw, the sample mean through the level sums."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2211_17028_amd import tn
+    m = 65536
+    u = W.trajectory_uniforms(m, circ.n_noises, 2211)
+    t0 = time.perf_counter()
+    plan = tn.tn_plan_build_trajectories(circ)
+    terms = tn.tn_terms_trajectories(plan, u)
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False))
+    prep_s = time.perf_counter() - t0
+    r = ex.run()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ex.run()[0]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    x, _ = ex.values()
+    x = x * m
+    pat, _ = terms.get()
+    return {"samples": m, "distinct_draws": len({bytes(row) for row in pat}), "ms_per_estimate": ms,
+            "plan_prepare_s": prep_s, "mean": r["A"][0], "stderr": float(x.std(ddof=1) / np.sqrt(m)),
+            "error_vs_exact": None if f_exact is None else r["A"][0] - f_exact}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -234,6 +264,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
     ap.add_argument("--no-offdiag", action="store_true", help="skip the off-diagonal element")
+    ap.add_argument("--no-trajectories", action="store_true", help="skip the quantum-trajectories comparison")
     ap.add_argument("--exact-only", action="store_true",
                     help="only the exact value of the workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
@@ -419,6 +450,7 @@ def main():
 
     exact = None if args.no_exact else exact_value(circ, level, res, 5)
     offd = None if args.no_offdiag else offdiagonal_value(circ, level, 20)
+    traj = None if args.no_trajectories else trajectories_value(circ, exact["F"] if exact else None, 20)
 
     cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
     info = plan.info()
@@ -455,6 +487,7 @@ def main():
         "paper_case": paper_case,
         "exact_value": exact,
         "offdiagonal": offd,
+        "trajectories": traj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
