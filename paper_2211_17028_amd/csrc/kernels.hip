@@ -15,6 +15,7 @@
 namespace tn {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int64_t pick(int mode, const int32_t* map, int64_t i) {
     return mode == 0 ? i : (mode == 1 ? 0 : (int64_t)map[i]);
@@ -1021,7 +1022,16 @@ __global__ __launch_bounds__(256) void k_gemm_tiled_c128(GemmArgs g) {
 // for jobs that would leave CUs idle); 256 threads, TT x TT outputs each, inner
 // chunks of 8 staged in LDS through the tile's row / column offset tables.
 // ---------------------------------------------------------------------------
-template <int TT>
+#ifndef TILE64_MFMA
+#define TILE64_MFMA 1
+#endif
+// MF = 1: the products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64 on the
+// real embedding, as the FP32 kernel: one instruction is 16 rows x 8 complex
+// columns x 2 complex inner indices); the four waves take the tile's quadrants.
+// Operands come from the same LDS rows; each lane reads one double per operand
+// per instruction instead of a thread reading TT complex values of A and of B
+// per inner index (the FMA form reads 1 byte of LDS per flop).
+template <int TT, bool MF>
 __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict__ jobs,
                                                       const MfmaTile* __restrict__ tiles) {
     constexpr int BM = 16 * TT, BN = 16 * TT, BK = 8, BK_LOG = 3;
@@ -1075,11 +1085,26 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     const TN_GLOBAL double2* __restrict__ B = gload<double2>(J.B);
     TN_GLOBAL double2* __restrict__ C = gstore<double2>(J.C);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double accr[TT][TT], acci[TT][TT];
+    double accr[MF ? 1 : TT][MF ? 1 : TT], acci[MF ? 1 : TT][MF ? 1 : TT];
+    // matrix-core form: wave quadrant (rows wr0.., complex columns wc0..), WR x WC
+    // instructions of 16 rows x 8 complex columns each
+    constexpr int WR = MF ? BM / 32 : 1, WC = MF ? BN / 16 : 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr0 = (wave & 1) * (BM / 2), wc0 = (wave >> 1) * (BN / 2);
+    const int kpart = (lane >> 4) & 1;           // real-embedding row: 0 = Re, 1 = Im of A's element
+    const int tcol = lane & 1;                   // output component of this lane's column
+    v4d acc[WR][WC];
+    if constexpr (MF) {
 #pragma unroll
-    for (int i = 0; i < TT; ++i)
+        for (int i = 0; i < WR; ++i)
 #pragma unroll
-        for (int j = 0; j < TT; ++j) accr[i][j] = acci[i][j] = 0.0;
+            for (int j = 0; j < WC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    } else {
+#pragma unroll
+        for (int i = 0; i < TT; ++i)
+#pragma unroll
+            for (int j = 0; j < TT; ++j) accr[i][j] = acci[i][j] = 0.0;
+    }
     const int64_t nch_all = k >= BK ? k / BK : 1;
     const int64_t c_begin = nch_all / J.ksplit * T.kpart;
     const int64_t c_end = c_begin + nch_all / J.ksplit;
@@ -1147,20 +1172,44 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
             load();
             advance(ch + 1);
         }
+        if constexpr (MF) {
+            // lane: A row (lane & 15), B real column (lane & 15) of its block,
+            // real inner index lane >> 4 = 2 (complex inner) + kpart
 #pragma unroll
-        for (int p = 0; p < BK; ++p) {
-            double2 a[TT], b[TT];
+            for (int ks = 0; ks < BK / 2; ++ks) {
+                const int p = 2 * ks + (lane >> 5);
+                double a[WR], b[WC];
 #pragma unroll
-            for (int i = 0; i < TT; ++i) a[i] = As[p][ty + 16 * i];
+                for (int i = 0; i < WR; ++i)
+                    a[i] = reinterpret_cast<const double*>(&As[p][wr0 + 16 * i + (lane & 15)])[kpart];
 #pragma unroll
-            for (int j = 0; j < TT; ++j) b[j] = Bs[p][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < TT; ++i)
-#pragma unroll
-                for (int j = 0; j < TT; ++j) {
-                    accr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
-                    acci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
+                for (int j = 0; j < WC; ++j) {
+                    const double v =
+                        reinterpret_cast<const double*>(&Bs[p][wc0 + 8 * j + ((lane & 15) >> 1)])[tcol ^ kpart];
+                    b[j] = (kpart && !tcol) ? -v : v;
                 }
+#pragma unroll
+                for (int i = 0; i < WR; ++i)
+#pragma unroll
+                    for (int j = 0; j < WC; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < BK; ++p) {
+                double2 a[TT], b[TT];
+#pragma unroll
+                for (int i = 0; i < TT; ++i) a[i] = As[p][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < TT; ++j) b[j] = Bs[p][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < TT; ++i)
+#pragma unroll
+                    for (int j = 0; j < TT; ++j) {
+                        accr[i][j] += a[i].x * b[j].x - a[i].y * b[j].y;
+                        acci[i][j] += a[i].x * b[j].y + a[i].y * b[j].x;
+                    }
+            }
         }
         __syncthreads();
     }
@@ -1169,6 +1218,29 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     const bool to_partial = J.ksplit > 1;
     TN_GLOBAL double2* __restrict__ O =
         to_partial ? gstore<double2>(J.partial) + ((int64_t)T.pair * J.ksplit + T.kpart) * (BM * BN) : C;
+    if constexpr (MF) {
+        // element e of a lane's result is row (lane >> 4) + 4 e of its
+        // instruction's block (the FP64 instruction interleaves its rows, unlike
+        // the FP32 one), real column lane & 15: complex column (lane & 15) / 2,
+        // component tcol
+        TN_GLOBAL double* __restrict__ Od = reinterpret_cast<TN_GLOBAL double*>(O);
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+            const int col = wc0 + 8 * j + ((lane & 15) >> 1);
+            const int64_t cc = col_c[col];
+            if (cc < 0) continue;
+#pragma unroll
+            for (int i = 0; i < WR; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = wr0 + 16 * i + (lane >> 4) + 4 * e;
+                    const int64_t rc = row_c[row];
+                    if (rc >= 0)
+                        Od[2 * (to_partial ? (int64_t)row * BN + col : rc + cc) + tcol] = acc[i][j][e];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < TT; ++i) {
         const int row = ty + 16 * i;
@@ -1187,9 +1259,11 @@ void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tile
                          hipStream_t s) {
     if (n_tiles == 0) return;
     if (tile == 4)
-        hipLaunchKernelGGL((k_tile64_group<2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+        hipLaunchKernelGGL((k_tile64_group<2, TILE64_MFMA>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs,
+                           d_tiles);
     else
-        hipLaunchKernelGGL((k_tile64_group<4>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles);
+        hipLaunchKernelGGL((k_tile64_group<4, TILE64_MFMA>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs,
+                           d_tiles);
 }
 
 // ---------------------------------------------------------------------------
