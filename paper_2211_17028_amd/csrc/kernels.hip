@@ -1037,9 +1037,10 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
     constexpr int BM = 16 * TT, BN = 16 * TT, BK = 8, BK_LOG = 3;
     constexpr int BM_LOG = __builtin_ctz(BM), BN_LOG = __builtin_ctz(BN);
     constexpr int SE = (BM * BK + 255) / 256;   // staged elements per thread and operand
-    // +2 elements per row: k-fast staging writes of 16 lanes fall in distinct banks
-    __shared__ double2 As[BK][BM + 2];
-    __shared__ double2 Bs[BK][BN + 2];
+    // +2 elements per row: k-fast staging writes of 16 lanes fall in distinct banks;
+    // two buffers: chunk ch + 1 is stashed while chunk ch is multiplied
+    __shared__ double2 As2[2][BK][BM + 2];
+    __shared__ double2 Bs2[2][BK][BN + 2];
     __shared__ int64_t row_a[BM], row_c[BM], col_b[BN], col_c[BN], ak_lo[BK], bk_lo[BK];
     __shared__ int64_t a_step[32], b_step[32];
     __shared__ MfmaJob J;
@@ -1156,18 +1157,24 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
             bkh += b_step[t];
         }
     };
-    if (c_begin < c_end) {
-        load();
-        advance(c_begin);
-    }
-    for (int64_t ch = c_begin; ch < c_end; ++ch) {
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < SE; ++q) {
             if (threadIdx.x + q * 256 >= BM * BK) break;
-            As[sa_p[q]][sa_r[q]] = ra[q];
-            Bs[sb_p[q]][sb_c[q]] = rb[q];
+            As2[buf][sa_p[q]][sa_r[q]] = ra[q];
+            Bs2[buf][sb_p[q]][sb_c[q]] = rb[q];
         }
+    };
+    if (c_begin < c_end) {
+        load();
+        advance(c_begin);
+        stash(0);
         __syncthreads();
+    }
+    for (int64_t ch = c_begin; ch < c_end; ++ch) {
+        const int buf = (int)((ch - c_begin) & 1);
+        const double2(*As)[BM + 2] = As2[buf];
+        const double2(*Bs)[BN + 2] = Bs2[buf];
         if (ch + 1 < c_end) {
             load();
             advance(ch + 1);
@@ -1211,6 +1218,8 @@ __global__ __launch_bounds__(256) void k_tile64_group(const MfmaJob* __restrict_
                     }
             }
         }
+        // the other buffer was last read before the previous barrier
+        if (ch + 1 < c_end) stash(buf ^ 1);
         __syncthreads();
     }
     // split inner sum: this block's part goes to its row-major [BM][BN] partial
