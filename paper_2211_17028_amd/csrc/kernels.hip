@@ -452,6 +452,12 @@ void k_gemm_mfma_g(GemmArgs g) {
 #ifndef MFMA_GROUP_WAVES
 #define MFMA_GROUP_WAVES 3
 #endif
+#ifndef MFMA_GROUP_WAVES_128X64
+#define MFMA_GROUP_WAVES_128X64 4
+#endif
+#ifndef MFMA_RA_128X64
+#define MFMA_RA_128X64 2
+#endif
 #ifndef MFMA_GROUP_BKC
 #define MFMA_GROUP_BKC 8
 #endif
@@ -469,7 +475,8 @@ void k_gemm_mfma_g(GemmArgs g) {
 // without spilling)
 template <int BM, int BNC>
 __global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1),
-                             (BM == 64 && BNC == 32) ? 2 : MFMA_GROUP_WAVES)
+                             (BM == 64 && BNC == 32) ? 2 : (BM == 128 && BNC == 64) ? MFMA_GROUP_WAVES_128X64
+                                                                                       : MFMA_GROUP_WAVES)
 void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__ tiles) {
     constexpr int WM = BM >= 64 ? BM / 64 : 1;
     constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
@@ -643,36 +650,44 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
 #pragma unroll
     for (int j = 0; j < TN; ++j) b_off[j] = 2 * (wn * (TN * 16) + j * 16) + (half ? (sub ^ 1) : sub);
     const uint32_t b_sign = (half && !(sub & 1)) ? 0x80000000u : 0u;
+    // operands read ahead per group of RA inner indices: the whole chunk, or two
+    // on 128 x 64 tiles (held to four waves per SIMD, whose 128-register budget
+    // the full read-ahead would exceed; a few spills remain outside the loop)
+    constexpr int RA = (BM == 128 && BNC == 64) ? MFMA_RA_128X64 : BKC;
     auto compute = [&](int buf) {
         const float* as = As + buf * ABUF;
         const float* bs = Bs + buf * BBUF;
-        // all operands of the chunk read first, so the LDS reads of later inner
-        // indices are in flight while the MFMAs of earlier ones run
-        float a[BKC][TM], b[BKC][TN];
 #pragma unroll
-        for (int p = 0; p < BKC; ++p) {
+        for (int g = 0; g < BKC; g += RA) {
+            // all operands of the group read first, so the LDS reads of later
+            // inner indices are in flight while the MFMAs of earlier ones run
+            float a[RA][TM], b[RA][TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a[p][i] = as[p * AP + a_off[i]];
+            for (int p = 0; p < RA; ++p) {
 #pragma unroll
-            for (int j = 0; j < TN; ++j) b[p][j] = __uint_as_float(__float_as_uint(bs[p * BP + b_off[j]]) ^ b_sign);
-        }
-#pragma unroll
-        for (int p = 0; p < BKC; ++p)
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i) a[p][i] = as[(g + p) * AP + a_off[i]];
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][j], acc[i][j], 0, 0, 0);
-        // keep the reads ahead of the MFMAs: DS reads of inner index p + 1 are
-        // scheduled before the MFMAs of inner index p
-#if MFMA_GROUP_SCHED
-        __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+                    b[p][j] = __uint_as_float(__float_as_uint(bs[(g + p) * BP + b_off[j]]) ^ b_sign);
+            }
 #pragma unroll
-        for (int p = 0; p < BKC; ++p) {
-            if (p + 1 < BKC) __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
-        }
+            for (int p = 0; p < RA; ++p)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][j], acc[i][j], 0, 0, 0);
+            // keep the reads ahead of the MFMAs: DS reads of inner index p + 1
+            // are scheduled before the MFMAs of inner index p
+#if MFMA_GROUP_SCHED
+            __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+#pragma unroll
+            for (int p = 0; p < RA; ++p) {
+                if (p + 1 < RA) __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
+            }
 #endif
+        }
     };
     const int64_t nchunks = c_end - c_begin;
     // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
