@@ -41,8 +41,9 @@
  * tn_kernel_mfma_split_reduce: for every tile group of a split job in the
  *   lists of a preceding tn_kernel_mfma_group launch (same `tile`, jobs and
  *   tiles; enqueue it after that launch on the same stream), adds the S
- *   partial tiles in part order 0, 1, ..., S-1 (so results are the same run to
- *   run) and writes the job's C.  fp64 = 1 for complex128 partials and output
+ *   partial tiles in part order 0, 1, ..., S-1 (with more parts than tile
+ *   rows: strided FP64 partial sums combined by a fixed tree; either way the
+ *   results are the same run to run) and writes the job's C.  fp64 = 1 for complex128 partials and output
  *   (the library's FP64 tiles), 0 for complex64.  Tiles of unsplit jobs are
  *   skipped.  Asynchronous on `stream`.  Returns 0 or a negative TN_E* code.
  */

@@ -252,6 +252,13 @@ constexpr int kSplitMinKLog = 6;
 constexpr int kSplitMinPartLog = 5;
 constexpr int64_t kSplitMaxTiles = 512;
 constexpr int kSplitDefaultMax = 16;
+// FP64 steps whose slices fill a 32 x 32 tile but whose inner sums are longer
+// than a tile walks alone (the exact value's last inner products: 32 x 32
+// outputs over 2^21 terms) run as tile jobs split over up to this many blocks
+// (each part at least 2^kSplitMinPartLog terms, S x tiles <= kSplitMaxTiles);
+// the small kernel's block per output would stream a whole row and column of
+// the operands per output.
+constexpr int kSplitLongMax = 512;
 // A matrix-core job with at most this share of the flops of its level's main
 // tile shape takes that shape, so that it runs in the main launch.
 constexpr double kSmallJobShare = 0.25;
@@ -317,6 +324,7 @@ struct Builder {
     bool grouping = true;      // small steps of one tree level share one launch
     bool quantize_tiles = true;  // tile model: whole rounds over the CUs (one circuit)
     int max_ksplit = kSplitDefaultMax;  // largest split of a tile job's inner sum (1 = none)
+    bool ksplit_user = false;            // max_ksplit set by the caller (applies to every job)
     // FP32 tile shape imposed per tree level on jobs of at most the given
     // flops (the small jobs join the level's main matrix-core launch)
     const std::map<int, std::pair<int, double>>* level_tile = nullptr;
@@ -888,9 +896,14 @@ struct Builder {
             const bool heavy = step_flops >= kMfmaMinFlops && rk <= (fp64 ? 8 : 11) && FA.size() + FB.size() >= 3;
             // tiny steps stay with their level's small-step launch even when
             // their shape would fill a tile: a launch of their own costs more
-            const bool to_tile = (big && step_flops >= kTileMinFlops) || heavy;
+            const bool long_sum = fp64 && rk > 8 && std::min(FA.size(), FB.size()) >= 5 &&
+                                  step_flops >= kMfmaMinFlops;
+            const bool to_tile = (big && step_flops >= kTileMinFlops) || heavy || long_sum;
             if (grouping && mode != 2 && to_tile) {
+                const int saved_split = max_ksplit;
+                if (long_sum && !big && !heavy && !ksplit_user) max_ksplit = kSplitLongMax;
                 plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec, fp64);
+                max_ksplit = saved_split;
                 node_bytes[C.gid] = C.bytes;
                 steps->push_back(std::move(st));
                 continue;
@@ -1283,7 +1296,10 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
     bw.level_tile = level_tile;
     bw.grouping = ex->opts.no_group == 0;
     bw.quantize_tiles = n == 1;
-    if (ex->opts.max_ksplit > 0) bw.max_ksplit = std::min(ex->opts.max_ksplit, 32);
+    if (ex->opts.max_ksplit > 0) {
+        bw.max_ksplit = std::min(ex->opts.max_ksplit, 32);
+        bw.ksplit_user = true;
+    }
     const bool plain = ex->opts.mode == TN_MODE_PLAIN;
     std::vector<StepRec> steps32, steps64;
     for (int pi = 0; pi < n; ++pi) {

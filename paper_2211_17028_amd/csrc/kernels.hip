@@ -1302,11 +1302,53 @@ __global__ __launch_bounds__(256) void k_split_reduce(const MfmaJob* __restrict_
                                                       const MfmaTile* __restrict__ tiles, int bm_log,
                                                       int bn_log) {
     __shared__ int64_t rc_s[128], cc_s[64];
+    __shared__ double red_r[256], red_i[256];
     const MfmaTile T = tiles[blockIdx.x];
     const MfmaJob& J = jobs[T.job];
     const int S = J.ksplit;
     if (S <= 1) return;
     const int BM = 1 << bm_log, BN = 1 << bn_log;
+    if (S > BM) {
+        // more parts than tile rows (very long inner sums): block kpart takes
+        // elements [kpart E, (kpart + 1) E) of the row-major tile, E = BM BN / S,
+        // its threads add strided subsets of the S partials in FP64 and a fixed
+        // tree combines them (deterministic)
+        const int64_t E = ((int64_t)BM * BN) / S;
+        const int64_t PT = (int64_t)BM * BN;
+        const TN_GLOBAL C2* __restrict__ P = gload<C2>(J.partial) + (int64_t)T.pair * S * PT;
+        TN_GLOBAL C2* __restrict__ C = gstore<C2>(J.C);
+        for (int64_t e = 0; e < E; ++e) {
+            const int64_t o = (int64_t)T.kpart * E + e;
+            const int i = (int)(o >> bn_log), j = (int)(o & (BN - 1));
+            double sr = 0.0, si = 0.0;
+            for (int q = threadIdx.x; q < S; q += 256) {
+                const C2 v = gld(P + ((int64_t)q * PT + o));
+                sr += (double)v.x;
+                si += (double)v.y;
+            }
+            red_r[threadIdx.x] = sr;
+            red_i[threadIdx.x] = si;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) {
+                    red_r[threadIdx.x] += red_r[threadIdx.x + w];
+                    red_i[threadIdx.x] += red_i[threadIdx.x + w];
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const int64_t rc = tile_out_row(J, T, i), cc = tile_out_col(J, T, j);
+                if (rc >= 0 && cc >= 0) {
+                    C2 t;
+                    t.x = red_r[0];
+                    t.y = red_i[0];
+                    gst(C + (rc + cc), t);
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
     const int rows = BM / S, r0 = T.kpart * rows;
     for (int i = threadIdx.x; i < rows; i += 256) rc_s[i] = tile_out_row(J, T, r0 + i);
     for (int j = threadIdx.x; j < BN; j += 256) cc_s[j] = tile_out_col(J, T, j);

@@ -263,7 +263,7 @@ class Sim:
             if S > 1:
                 # the inner sum of a tile group is split in S equal parts of whole
                 # 8-term chunks; each block leaves its partial tile
-                assert S & (S - 1) == 0 and k >= 8 and (k // 8) % S == 0 and S <= bm, ("split", S, k)
+                assert S & (S - 1) == 0 and k >= 8 and (k // 8) % S == 0 and S <= bm * bn, ("split", S, k)
                 assert 0 <= int(t["kpart"]) < S, ("part index", int(t["kpart"]), S)
                 h = k // S
                 sel = slice(int(t["kpart"]) * h, (int(t["kpart"]) + 1) * h)
@@ -307,13 +307,26 @@ class Sim:
             g, h = int(t["pair"]), int(t["kpart"])
             P = self.view(jb["partial"], dt, (g + 1) * S * bm * bn)[g * S * bm * bn:].reshape(S, bm, bn)
             ok_r, rc, ok_c, cc = self._tile_out(jb, t, bm, bn, m, n, oc)
-            rows = np.arange(h * (bm // S), (h + 1) * (bm // S))
-            rows = rows[ok_r[rows]]
             cols = np.nonzero(ok_c)[0]
             for q in range(S if h == 0 else 0):      # every part wrote exactly these elements
                 got = self.partials.pop((tuple(jb["partial"]), g * S + q), None)
                 assert got is not None, ("missing partial tile", g, q)
                 assert np.array_equal(got[0], np.nonzero(ok_r)[0]) and np.array_equal(got[1], cols)
+            if S > bm:
+                # more parts than rows: block h takes elements [h E, (h + 1) E) of the
+                # row-major tile (E = bm bn / S), summed over the parts in FP64
+                E = bm * bn // S
+                flat = np.arange(h * E, (h + 1) * E)
+                ri, ci = flat // bn, flat % bn
+                keep = ok_r[ri] & ok_c[ci]
+                ri, ci = ri[keep], ci[keep]
+                acc = P[:, ri, ci].astype(np.complex128).sum(0).astype(dt)
+                idx = rc[ri] + cc[ci]
+                C[idx] = acc
+                np.add.at(hits, idx, 1)
+                continue
+            rows = np.arange(h * (bm // S), (h + 1) * (bm // S))
+            rows = rows[ok_r[rows]]
             acc = P[0][rows[:, None], cols[None, :]]
             for q in range(1, S):
                 acc = (acc + P[q][rows[:, None], cols[None, :]]).astype(dt)

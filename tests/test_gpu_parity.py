@@ -438,6 +438,7 @@ def _random_mfma_job(torch, rng, m_log, n_log, k_log, n_slices, share, merge, ti
     (5, 5, 7, 4, 1, 0, 4, 2),       # split, 32 x 32 tiles
     (8, 4, 8, 12, 3, 1, 0, 8),      # split over 8 tiles (4 chunks each)
     (5, 5, 9, 2, 1, 0, 4, 16),      # split over 16 tiles, 32 x 32
+    (5, 5, 10, 2, 1, 0, 4, 128),    # more parts than tile rows: element ranges, FP64 tree
     (3, 5, 7, 10, 4, 2, 2, 4),      # merged rows, split over 4 tiles
 ])
 def test_grouped_mfma_kernel_against_numpy(torch, m_log, n_log, k_log, n_slices, share, merge, tile, ksplit):
