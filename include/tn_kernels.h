@@ -31,7 +31,7 @@
  *   arrays in the tn_mfma_job / tn_mfma_tile layouts; `tile` selects the tile
  *   shape (0..7: 128x64, 64x64, 128x32, 64x32, 32x32, 128x16, 64x16, 32x16).
  *   ksplit = S (a power of two dividing the job's count of 8-term inner chunks,
- *   at most the tile's row count; 1 = no split) splits each tile's inner sum
+ *   at most BM x BNC; 1 = no split) splits each tile's inner sum
  *   over S tiles (kpart 0..S-1, same group index `pair`, listed S in a row):
  *   each writes its partial tile, row-major BM x BNC complex64, to
  *   partial + (pair * S + kpart) * BM * BNC (padding elements skipped), and
