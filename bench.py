@@ -278,7 +278,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "
-              f"shard across GPUs with one all-reduce of the level sums, which this build does not run.",
+              f"shard across GPUs with one all-reduce of the level sums; runs on several GPUs are not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

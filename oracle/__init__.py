@@ -25,6 +25,6 @@ Modules
                sample), the paper's main comparison
   bounds    -- Theorem 1 (contraction count; error bound in the form its proof
                actually establishes)
-  estimate  -- driver: T_u, A(l) for every l' <= l, per-term values
+  estimate  -- Algorithm 1 end to end: T_u, A(l) for every l' <= l, per-term values
 """
 from . import channels, terms, dense, literal, network, doubled, offdiag, factored, trajectories, bounds, estimate  # noqa: F401

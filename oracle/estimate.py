@@ -1,4 +1,4 @@
-"""Algorithm 1 driver: level sums T_u and the approximations A(l') for l' <= l.
+"""Algorithm 1 end to end: level sums T_u and the approximations A(l') for l' <= l.
 
 For u = 0..l, every term of level u is evaluated (``literal`` = both networks
 as dense state vectors, or ``network`` = one network per term) and summed into
