@@ -60,6 +60,25 @@ int tn_mlp_train_step(const tn_mlp_shape* s, void* d_state, const float* d_x, co
                       const float* d_w, int64_t n, float lr, int32_t step, void* d_ws,
                       float* d_loss, void* stream);
 
+/* The pruner's training and persistence exports.
+ * tn_pruner_train_step: tn_mlp_train_step under the pruner's name.
+ * tn_pruner_save: the model (normalizer and parameters, not gradients or Adam
+ *   moments) into host memory h_buf: a TN_PRUNER_HEADER_BYTES header (the
+ *   bytes "TNPRUNE1", then n_in, width, depth as int32 and the parameter count
+ *   as int64, zero padded) followed by (2 n_in + P) float32.  *need_bytes
+ *   receives the size; h_buf = NULL only queries it; a smaller buffer is
+ *   TN_ENOMEM.  Synchronizes `stream`.
+ * tn_pruner_load: the reverse into d_state (gradients and moments zeroed);
+ *   TN_EINVAL if the header is not a saved model or its shape differs from
+ *   `s`.  Synchronizes `stream`. */
+#define TN_PRUNER_HEADER_BYTES 32
+int tn_pruner_train_step(const tn_mlp_shape* s, void* d_state, const float* d_x, const float* d_t,
+                         const float* d_w, int64_t n, float lr, int32_t step, void* d_ws, float* d_loss,
+                         void* stream);
+int tn_pruner_save(const tn_mlp_shape* s, const void* d_state, void* h_buf, size_t buf_bytes,
+                   size_t* need_bytes, void* stream);
+int tn_pruner_load(const tn_mlp_shape* s, void* d_state, const void* h_buf, size_t buf_bytes, void* stream);
+
 /* Features of every term of a term set (n_terms x TN_N_FEATURES floats, host
  * memory): for up to three corrected noises in position order, presence,
  * log(d_i/d_0), correction one-hot, position in the circuit, past-light-cone

@@ -405,4 +405,60 @@ int tn_mlp_train_step(const tn_mlp_shape* s, void* d_state, const float* d_x, co
     return tn_mlp_adam(s, d_state, lr, step, stream);
 }
 
+int tn_pruner_train_step(const tn_mlp_shape* s, void* d_state, const float* d_x, const float* d_t,
+                         const float* d_w, int64_t n, float lr, int32_t step, void* d_ws, float* d_loss,
+                         void* stream) {
+    return tn_mlp_train_step(s, d_state, d_x, d_t, d_w, n, lr, step, d_ws, d_loss, stream);
+}
+
+// saved model: header {magic, n_in, width, depth, P} then normalizer and parameters
+static const char kPrunerMagic[8] = {'T', 'N', 'P', 'R', 'U', 'N', 'E', '1'};
+
+int tn_pruner_save(const tn_mlp_shape* s, const void* d_state, void* h_buf, size_t buf_bytes, size_t* need_bytes,
+                   void* stream) {
+    return mguard([&] {
+        MlpLayout L = layout_of(s);
+        const size_t body = (size_t)(L.params_off + L.P) * 4;
+        const size_t need = TN_PRUNER_HEADER_BYTES + body;
+        if (need_bytes) *need_bytes = need;
+        if (!h_buf) return;
+        if (!d_state) fail(TN_EINVAL, "null state");
+        if (buf_bytes < need) fail(TN_ENOMEM, "buffer smaller than the saved model");
+        unsigned char* h = (unsigned char*)h_buf;
+        std::memset(h, 0, TN_PRUNER_HEADER_BYTES);
+        std::memcpy(h, kPrunerMagic, 8);
+        const int32_t dims[3] = {s->n_in, s->width, s->depth};
+        std::memcpy(h + 8, dims, sizeof(dims));
+        const int64_t P = L.P;
+        std::memcpy(h + 24, &P, 8);
+        hipStream_t st = (hipStream_t)stream;
+        HIPCHK_M(hipMemcpyAsync(h + TN_PRUNER_HEADER_BYTES, d_state, body, hipMemcpyDeviceToHost, st));
+        HIPCHK_M(hipStreamSynchronize(st));
+    });
+}
+
+int tn_pruner_load(const tn_mlp_shape* s, void* d_state, const void* h_buf, size_t buf_bytes, void* stream) {
+    return mguard([&] {
+        MlpLayout L = layout_of(s);
+        const size_t body = (size_t)(L.params_off + L.P) * 4;
+        if (!d_state || !h_buf) fail(TN_EINVAL, "null pointer");
+        if (buf_bytes < TN_PRUNER_HEADER_BYTES + body) fail(TN_EINVAL, "buffer shorter than the saved model");
+        const unsigned char* h = (const unsigned char*)h_buf;
+        int32_t dims[3];
+        int64_t P;
+        std::memcpy(dims, h + 8, sizeof(dims));
+        std::memcpy(&P, h + 24, 8);
+        if (std::memcmp(h, kPrunerMagic, 8) != 0) fail(TN_EINVAL, "not a saved pruner model");
+        if (dims[0] != s->n_in || dims[1] != s->width || dims[2] != s->depth || P != L.P)
+            fail(TN_EINVAL, "saved model has another shape");
+        hipStream_t st = (hipStream_t)stream;
+        // normalizer and parameters; gradients and Adam moments start from zero
+        std::vector<float> zeros((size_t)(L.total - L.grads_off), 0.0f);
+        HIPCHK_M(hipMemcpyAsync(d_state, h + TN_PRUNER_HEADER_BYTES, body, hipMemcpyHostToDevice, st));
+        HIPCHK_M(hipMemcpyAsync((float*)d_state + L.grads_off, zeros.data(), zeros.size() * 4,
+                                hipMemcpyHostToDevice, st));
+        HIPCHK_M(hipStreamSynchronize(st));
+    });
+}
+
 }  // extern "C"

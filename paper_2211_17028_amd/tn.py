@@ -709,9 +709,12 @@ def _mlp_lib():
         L.tn_terms_features.argtypes = [vp, vp, vp, vp]
         L.tn_prune_threshold.argtypes = [vp, vp, C.c_int64, C.c_double, C.POINTER(C.c_float)]
         L.tn_mlp_log_targets.argtypes = [vp, vp, C.c_int64, C.c_double, vp]
+        L.tn_pruner_train_step.argtypes = [sp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_int32, vp, vp, vp]
+        L.tn_pruner_save.argtypes = [sp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t), vp]
+        L.tn_pruner_load.argtypes = [sp, vp, vp, C.c_size_t, vp]
         for n in ("tn_mlp_sizes", "tn_mlp_init", "tn_mlp_fit_normalizer", "tn_mlp_forward", "tn_mlp_gradients",
                   "tn_mlp_adam", "tn_mlp_train_step", "tn_terms_features", "tn_prune_threshold",
-                  "tn_mlp_log_targets"):
+                  "tn_mlp_log_targets", "tn_pruner_train_step", "tn_pruner_save", "tn_pruner_load"):
             getattr(L, n).restype = C.c_int
         L._mlp_sigs = True
     return L
@@ -739,6 +742,23 @@ def tn_prune_threshold(pred: np.ndarray, x: np.ndarray, budget: float) -> float:
 
 class MLP:
     """Device state of the pruning network (torch-allocated)."""
+
+    def save(self, stream=None) -> bytes:
+        """The model (header, normalizer, parameters) as bytes."""
+        need = C.c_size_t()
+        _check(_mlp_lib().tn_pruner_save(C.byref(self.shape), _ptr(self.state), None, 0, C.byref(need),
+                                         _stream_ptr(stream)))
+        buf = (C.c_uint8 * need.value)()
+        _check(_mlp_lib().tn_pruner_save(C.byref(self.shape), _ptr(self.state), buf, need.value, C.byref(need),
+                                         _stream_ptr(stream)))
+        return bytes(buf)
+
+    def load(self, blob: bytes, stream=None):
+        """Model bytes from save() into this state (optimizer moments reset)."""
+        buf = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        _check(_mlp_lib().tn_pruner_load(C.byref(self.shape), _ptr(self.state), buf, len(blob),
+                                         _stream_ptr(stream)))
+        self.step = 0
 
     def __init__(self, n_in=TN_N_FEATURES, width=128, depth=3, seed=2211170280, max_batch=1 << 16, stream=None):
         import torch

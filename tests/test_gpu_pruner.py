@@ -102,3 +102,21 @@ def test_learned_pruning_beats_the_bound_policy(torch):
           f"bound ranking needs {need} terms for the network's error", flush=True)
     assert drop_m < drop_b
     assert need > k
+
+
+def test_pruner_save_load_round_trip(torch):
+    print("pruner save / load", flush=True)
+    rng = np.random.default_rng(6)
+    net = tn.MLP(n_in=36, width=64, depth=2, seed=3, max_batch=1024)
+    x = torch.from_numpy(rng.standard_normal((500, 36)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal(500).astype(np.float32)).cuda()
+    net.fit_normalizer(x)
+    for _ in range(3):
+        net.train_step(x, t, lr=1e-3)
+    blob = net.save()
+    assert blob[:8] == b"TNPRUNE1" and len(blob) == 32 + 4 * (2 * 36 + net.n_params)
+    other = tn.MLP(n_in=36, width=64, depth=2, seed=99, max_batch=1024)
+    other.load(blob)
+    assert torch.equal(net.forward(x), other.forward(x))
+    with pytest.raises(tn.TNError):
+        tn.MLP(n_in=36, width=32, depth=2, seed=1, max_batch=1024).load(blob)

@@ -484,3 +484,16 @@ def test_trajectories_plan_rejects_enumeration_and_bad_input():
     with pytest.raises(tn.TNError) as e:
         tn.tn_plan_build_trajectories(W.Circuit(3, ops, c.psi, c.target, c.v, 1))
     assert e.value.code == tn.TN_EUNSUPPORTED
+
+
+def test_pruner_save_size_query_and_header_check():
+    shape = tn.tn_mlp_shape(36, 64, 2)
+    L = tn._mlp_lib()
+    need = ctypes.c_size_t()
+    assert L.tn_pruner_save(ctypes.byref(shape), None, None, 0, ctypes.byref(need), None) == tn.TN_OK
+    npar = ctypes.c_int64()
+    assert L.tn_mlp_sizes(ctypes.byref(shape), 1, ctypes.byref(npar), None, None) == tn.TN_OK
+    assert need.value == 32 + 4 * (2 * 36 + npar.value)
+    bad = (ctypes.c_uint8 * need.value)()
+    dummy = ctypes.c_void_p(1)      # rejected before any device access
+    assert L.tn_pruner_load(ctypes.byref(shape), dummy, bad, need.value, None) == tn.TN_EINVAL
