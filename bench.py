@@ -146,6 +146,12 @@ def roofline_of(name, st, per):
         achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS}
+    if roof["bound"] != "hbm" and st["bytes"] > 0:
+        # attainable ceiling at the kernel's algorithmic intensity: min(peak, AI x HBM)
+        ai = st["flops"] / st["bytes"]
+        roof["intensity_flop_per_byte"] = ai
+        roof["attainable"] = min(roof["peak"], ai * HBM_PEAK_GBS / 1000.0)
+        roof["frac_attainable"] = roof["achieved"] / roof["attainable"]
     roof.update({"kernel": name, "launches_per_step": st["launches"] / per,
                  "avg_launch_us": 1000.0 * st["ms"] / st["launches"],
                  "algorithmic_per_launch": (st["bytes"] if roof["bound"] == "hbm" else st["flops"])
