@@ -255,6 +255,53 @@ def trajectories_value(circ, f_exact, reps):
             "error_vs_exact": None if f_exact is None else r["A"][0] - f_exact}
 
 
+def pruning_value(ms_full, reps):
+    """The learned pruning on the 225-qubit workload (level 3, held out):
+    the network trained on the term values of the 25-qubit, 36-qubit and 16 of
+    the packed circuits, threshold from a 1e-7 pruned-mass budget of the
+    training estimates; the pruned term set's estimate timed like the full
+    one (its level-1 pre-pass and scoring reported apart)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2211_17028_amd import pruner, tn
+    t0 = time.perf_counter()
+    data = [pruner.training_data(W.config(2)), pruner.training_data(W.config(3))]
+    for c in W.config(4)[:16]:
+        data.append(pruner.training_data(c))
+    net, hist, (f_dev, xs) = pruner.train(data, epochs=30)
+    train_s = time.perf_counter() - t0
+    total = sum(d[2]["A"][-1] for d in data)
+    tau = pruner.threshold(pruner.score_candidates(net, f_dev.cpu().numpy(), "mlp"), xs, 1e-7 * total)
+    c5 = W.config(5)
+    _, _, full, _ = pruner.full_run(c5)
+    t0 = time.perf_counter()
+    plan = tn.tn_plan_build(c5, c5.level)
+    t1 = tn.tn_terms_enumerate(plan, 1)
+    ex1 = tn.tn_exec_prepare([plan], [t1], tn.exec_opts(use_graph=False))
+    ex1.run()
+    x1, _ = ex1.values()
+    terms = tn.tn_terms_enumerate(plan, c5.level)
+    feats = tn.tn_terms_features(plan, terms, x1)
+    cand, _ = pruner.candidate_mask(terms)
+    keep = (pruner.score_candidates(net, feats[cand], "mlp") >= tau).astype(np.uint8)
+    tp = tn.tn_terms_enumerate(plan, c5.level, keep=keep, min_level=2)
+    ex = tn.tn_exec_prepare([plan], [tp], tn.exec_opts(use_graph=False))
+    select_s = time.perf_counter() - t0
+    r = ex.run()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ex.run()[0]
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    return {"workload": "grid15x15_6L_20adpd_level3", "candidates": int(cand.sum()), "kept": int(keep.sum()),
+            "terms_full": full["n_terms"], "terms_contracted": r["n_contracted"],
+            "contraction_factor": full["n_terms"] / max(1, r["n_contracted"]),
+            "ms_pruned": ms, "ms_full": ms_full, "time_factor": None if not ms_full else ms_full / ms,
+            "error_vs_full": full["A"][-1] - r["A"][-1], "train_s": train_s, "select_s": select_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -271,6 +318,7 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
     ap.add_argument("--no-offdiag", action="store_true", help="skip the off-diagonal element")
     ap.add_argument("--no-trajectories", action="store_true", help="skip the quantum-trajectories comparison")
+    ap.add_argument("--no-pruning", action="store_true", help="skip the learned-pruning measurement")
     ap.add_argument("--exact-only", action="store_true",
                     help="only the exact value of the workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
@@ -457,6 +505,8 @@ def main():
     exact = None if args.no_exact else exact_value(circ, level, res, 5)
     offd = None if args.no_offdiag else offdiagonal_value(circ, level, 20)
     traj = None if args.no_trajectories else trajectories_value(circ, exact["F"] if exact else None, 20)
+    prune = None if args.no_pruning else pruning_value(paper_case["ms_per_estimate"] if paper_case else None,
+                                                       args.steps)
 
     cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
     info = plan.info()
@@ -494,6 +544,7 @@ def main():
         "exact_value": exact,
         "offdiagonal": offd,
         "trajectories": traj,
+        "pruning": prune,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
