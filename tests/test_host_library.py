@@ -497,3 +497,62 @@ def test_pruner_save_size_query_and_header_check():
     bad = (ctypes.c_uint8 * need.value)()
     dummy = ctypes.c_void_p(1)      # rejected before any device access
     assert L.tn_pruner_load(ctypes.byref(shape), dummy, bad, need.value, None) == tn.TN_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# edge cases of the exact value, factored sums, trajectories, off-diagonals
+# ---------------------------------------------------------------------------
+def test_doubled_without_noise_is_the_squared_overlap():
+    c = W.tiny_random_circuit(np.random.default_rng(161), 4, 16, 0, noise="random", level=1, target="product")
+    x, plan, _, _ = _replay_doubled(c)
+    st = dense.ideal_state(c, dense.product_state(c.psi))
+    want = abs(np.vdot(dense.target_vector(c), st)) ** 2
+    assert plan.info()["n_channels"] == 0 and abs(x[0] - want) <= 1e-12
+
+
+def test_factored_level0_and_single_cluster_equal_the_global_sums():
+    rng = np.random.default_rng(162)
+    c = W.tiny_random_circuit(rng, 4, 18, 4, noise="adpd", level=2)
+    plan = tn.tn_plan_build(c, 2)
+    for level in (0, 2):
+        t = tn.tn_terms_enumerate_factored(plan, level)
+        desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(use_graph=False))
+        sim = Sim(desc, cb)
+        _, w = t.get()
+        sim.run([[i for i in range(t.n) if w[i] != 0.0]])
+        x, _ = sim.outputs()
+        st = t.groups[0]
+        h = np.array([x[st[g]:st[g + 1]].sum() for g in range(len(st) - 1)])
+        A = np.zeros(level + 1)
+        assert tn.lib().tn_factored_levels(t.handle, h.ctypes.data, A.ctypes.data) == tn.TN_OK
+        ref = estimate.estimate(c, level, "network")["A"]
+        assert np.allclose(A, ref, rtol=2e-6, atol=0)
+        if plan.info()["n_clusters"] == 1:
+            assert t.n == len(oterms.enumerate_terms(c.n_noises, level))   # one cluster: every term
+
+
+def test_trajectories_never_draw_a_zero_kraus_operator():
+    from oracle import trajectories
+    c = W.tiny_random_circuit(np.random.default_rng(163), 3, 12, 2, noise="random", level=1)
+    kr = W.kraus_ad_pd(0.3, 0.2)                   # three Kraus operators
+    assert len(kr) == 3
+    kr = [kr[0], np.zeros((2, 2), dtype=np.complex128), kr[1], kr[2]]   # an empty slot in between
+    ops = list(c.ops) + [W.Op("noise", (1,), kraus=kr)]
+    c = W.Circuit(c.n_qubits, ops, c.psi, c.target, c.v, 1)
+    u = W.trajectory_uniforms(500, c.n_noises, 163)
+    plan = tn.tn_plan_build_trajectories(c)
+    t = tn.tn_terms_trajectories(plan, u)
+    pat, _ = t.get()
+    assert not np.any(pat[:, -1] == 1)
+    assert np.array_equal(pat, trajectories.sample_indices(c, u))
+
+
+def test_offdiagonal_with_equal_targets_is_the_diagonal_estimate():
+    rng = np.random.default_rng(164)
+    c = W.tiny_random_circuit(rng, 4, 16, 3, noise="adpd", level=2, target="circuit_output")
+    got = np.zeros(3, dtype=np.complex128)
+    for k, ck in enumerate(tn.polarization_circuits(c, c.v, c.v, True)):
+        xs, pat, _ = _replay(ck, 2)
+        got += (1j ** k) / 4 * _levels_from_replay(xs, pat, 2)
+    ref = estimate.estimate(c, 2, "network")["A"]
+    assert np.allclose(got.real, ref, rtol=2e-6, atol=0) and np.all(np.abs(got.imag) <= 1e-9)
