@@ -365,27 +365,42 @@ def main():
     # then the same schedule captured once in a hipGraph and replayed, for
     # comparison (`--graph` times the replay as the headline instead)
     def timed(use_graph):
+        """(result, seconds for the steps with two estimates in flight, prepare
+        seconds, seconds for the same steps one after another)."""
         t0 = time.perf_counter()
         e = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=use_graph, tune=not args.no_tune))
         prep = time.perf_counter() - t0
         for _ in range(args.warmup):
             r = e.run()[0]
         torch.cuda.synchronize()
+        # every step is one whole estimate whose results are collected; the next
+        # one is submitted before the previous one is collected
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r = e.run()[0]
+        prev = e.submit()
+        for _ in range(args.steps - 1):
+            t = e.submit()
+            r = e.collect(prev)[0]
+            prev = t
+        r = e.collect(prev)[0]
         torch.cuda.synchronize()
         el_ = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r_seq = e.run()[0]
+        torch.cuda.synchronize()
+        el_seq = time.perf_counter() - t0
+        assert r_seq["A"] == r["A"]
         del e
-        return r, el_, prep
+        return r, el_, prep, el_seq
 
-    res, el, prep_s = timed(args.graph)
-    res_o, el_o, _ = timed(not args.graph)
+    res, el, prep_s, el_seq = timed(args.graph)
+    res_o, el_o, _, el_o_seq = timed(not args.graph)
     n_contracted = res["n_contracted"]
     ms_per_step = 1000.0 * el / args.steps
     value = n_contracted * args.steps / el
     other = {"mode": "direct launches" if args.graph else "hipGraph replay",
              "value": n_contracted * args.steps / el_o, "ms_per_step": 1000.0 * el_o / args.steps,
+             "ms_per_step_sequential": 1000.0 * el_o_seq / args.steps,
              "A_equal": res_o["A"] == res["A"]}
     # kernel durations: the same schedule launched eagerly, a HIP event pair
     # around every launch on its own stream (events inside a captured graph
@@ -536,7 +551,11 @@ def main():
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
         "kernels": kernels,
-        "timed": "hipGraph replays" if args.graph else "direct launches",
+        "timed": ("hipGraph replays" if args.graph else "direct launches") +
+                 ", two estimates in flight (submit / collect)",
+        "sequential": {"ms_per_step": 1000.0 * el_seq / args.steps,
+                       "value": n_contracted * args.steps / el_seq,
+                       "note": "the same steps one tn_exec_run after another"},
         "other_mode": other,
         "eager": eager,
         "plain": plain,

@@ -263,6 +263,20 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms,
  * per plan (results[n]). */
 int tn_exec_run(tn_exec ex, void* stream, tn_result* results);
 
+/* Pipelined estimates: tn_exec_submit issues one estimate on `stream` (as
+ * tn_exec_run, without waiting) and returns its ticket; tn_exec_collect waits
+ * for that estimate and fills `results` (NULL: only wait).  Consecutive
+ * estimates on one stream run back to back on the GPU (they share the
+ * workspace in stream order), so the host's result handling and the next
+ * issue overlap the GPU work.  Each submitted estimate's results are copied on
+ * the device into one of two host slots: at most two may be outstanding
+ * (TN_ESTATE for a third), tickets are collected once each in submission
+ * order (TN_ESTATE otherwise), and tn_exec_run needs none outstanding.
+ * Submitting needs time_kernels = 0 (TN_EINVAL).  The stream must stay the
+ * same between a submit and its collect. */
+int tn_exec_submit(tn_exec ex, void* stream, int64_t* ticket);
+int tn_exec_collect(tn_exec ex, int64_t ticket, tn_result* results);
+
 /* Device pointer to the per-term values X_t (float64, concatenated over the
  * packed plans in order) and to the per-term amplitudes a_t (complex64 pairs),
  * valid after tn_exec_run. */

@@ -193,6 +193,11 @@ struct tn_exec_s {
     // results of an estimate (level sums, FP32 all-dominant value of every
     // plan), written by the tail kernels into pinned host memory
     int64_t results_bytes = 0;
+    // host results: slot 0 written by the tail kernels; slots 1, 2 copies made
+    // by submitted estimates (at most two outstanding), each results_stride bytes
+    int64_t results_stride = 0;
+    hipEvent_t ev_done[2] = {nullptr, nullptr};
+    int64_t next_ticket = 0, collected = 0;
     void* results_host = nullptr;      // host address
     void* results_dev = nullptr;       // the same memory as the device addresses it
     tn::ConstBuf cbuf;
@@ -2002,6 +2007,76 @@ static int guard(F&& f) {
     }
 }
 
+namespace tn {
+static void issue_estimate(tn_exec_s* ex, hipStream_t s) {
+    HIPCHK(hipEventRecord(ex->ev0, s));
+    if (ex->opts.use_graph) {
+        if (!ex->gexec) {
+            // record on a private stream (the caller's may be the null
+            // stream, which cannot be captured); launch on the caller's
+            if (!ex->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ex->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(ex->cap_stream, hipStreamCaptureModeThreadLocal));
+            run_body(ex, ex->cap_stream);
+            HIPCHK(hipStreamEndCapture(ex->cap_stream, &ex->graph));
+            HIPCHK(hipGraphInstantiate(&ex->gexec, ex->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(ex->gexec, s));
+    } else if (!ex->launches64.empty()) {
+        run_body_threaded(ex, s);
+    } else {
+        run_body(ex, s);
+    }
+}
+
+// per-circuit results from a results region (slot 0 or a submitted copy)
+static void fill_results(tn_exec_s* ex, const void* base, tn_result* results) {
+        for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
+            const PlanExec& pe = ex->plans[pi];
+            const Plan& P = *pe.plan;
+            const Terms& T = *pe.terms;
+            tn_result& r = results[pi];
+            std::memset(&r, 0, sizeof(r));
+            r.level = T.level;
+            r.clamped = P.clamped ? 1 : 0;
+            r.n_terms = T.n;
+            r.n_contracted = pe.n_live;
+            r.n_zero_weight = pe.n_zero;
+            const double* hs = (const double*)((const char*)base + pe.sums.off);
+            std::vector<double> sums(hs, hs + 2 * (T.level + 1));
+            double s = 0, c = 0;
+            for (int u = 0; u <= T.level; ++u) {
+                r.level_sum[u] = sums[2 * u];
+                r.level_comp[u] = sums[2 * u + 1];
+                double x = sums[2 * u];
+                double t = s + x;
+                if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+                else c += (x - t) + s;
+                s = t;
+                r.A[u] = s + c;
+            }
+            // remainder bound: sum over |S| > level of prod ||Mbar|| prod ||M'||
+            std::vector<double> poly(1, 1.0);
+            for (const NoiseSplit& ns : P.noise) {
+                std::vector<double> np(poly.size() + 1, 0.0);
+                for (size_t i = 0; i < poly.size(); ++i) {
+                    np[i] += poly[i] * ns.norm_main;
+                    np[i + 1] += poly[i] * ns.norm_bar;
+                }
+                poly.swap(np);
+            }
+            double b = 0;
+            for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
+            r.bound = P.trajectories ? -1.0 : b;   // a sample mean has no truncation bound
+            // FP32 value of the all-dominant term (diagnostic, written by the finalize)
+            r.x0_fp32 = -1;
+            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
+                r.x0_fp32 = *(const double*)((const char*)base + pe.x0.off);
+        }
+}
+
+}  // namespace tn
+using namespace tn;
+
 extern "C" {
 
 const char* tn_last_error(void) { return last_error_cstr(); }
@@ -2216,7 +2291,8 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         ex->base = (char*)d_ws;
         ex->stream = (hipStream_t)stream;
         HIPCHK(hipGetDevice(&ex->device));
-        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)std::max<int64_t>(8, ex->results_bytes),
+        ex->results_stride = std::max<int64_t>(8, (ex->results_bytes + 7) & ~int64_t(7));
+        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)(3 * ex->results_stride),
                              hipHostMallocMapped | hipHostMallocCoherent));
         HIPCHK(hipHostGetDevicePointer(&ex->results_dev, ex->results_host, 0));
         bind(ex.get());
@@ -2240,6 +2316,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
         if (ex->opts.tune) autotune(ex.get());
         HIPCHK(hipEventCreate(&ex->ev0));
         HIPCHK(hipEventCreate(&ex->ev1));
+        for (auto& e : ex->ev_done) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipStreamSynchronize(ex->stream));
         ex->bound = true;
         *out = reinterpret_cast<tn_exec>(ex.release());
@@ -2251,23 +2328,8 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
         if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
         hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
-        HIPCHK(hipEventRecord(ex->ev0, s));
-        if (ex->opts.use_graph) {
-            if (!ex->gexec) {
-                // record on a private stream (the caller's may be the null
-                // stream, which cannot be captured); launch on the caller's
-                if (!ex->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ex->cap_stream, hipStreamNonBlocking));
-                HIPCHK(hipStreamBeginCapture(ex->cap_stream, hipStreamCaptureModeThreadLocal));
-                run_body(ex, ex->cap_stream);
-                HIPCHK(hipStreamEndCapture(ex->cap_stream, &ex->graph));
-                HIPCHK(hipGraphInstantiate(&ex->gexec, ex->graph, nullptr, nullptr, 0));
-            }
-            HIPCHK(hipGraphLaunch(ex->gexec, s));
-        } else if (!ex->launches64.empty()) {
-            run_body_threaded(ex, s);
-        } else {
-            run_body(ex, s);
-        }
+        if (ex->next_ticket != ex->collected) fail(TN_ESTATE, "submitted estimates not collected yet");
+        issue_estimate(ex, s);
         HIPCHK(hipEventRecord(ex->ev1, s));
         HIPCHK(hipEventSynchronize(ex->ev1));
         float ms = 0;
@@ -2284,49 +2346,39 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
                 ex->kflops[L.kclass] += L.flops;
                 ex->kbytes[L.kclass] += L.bytes;
             }
-        if (!results) return;
-        for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
-            const PlanExec& pe = ex->plans[pi];
-            const Plan& P = *pe.plan;
-            const Terms& T = *pe.terms;
-            tn_result& r = results[pi];
-            std::memset(&r, 0, sizeof(r));
-            r.level = T.level;
-            r.clamped = P.clamped ? 1 : 0;
-            r.n_terms = T.n;
-            r.n_contracted = pe.n_live;
-            r.n_zero_weight = pe.n_zero;
-            const double* hs = (const double*)((const char*)ex->results_host + pe.sums.off);
-            std::vector<double> sums(hs, hs + 2 * (T.level + 1));
-            double s = 0, c = 0;
-            for (int u = 0; u <= T.level; ++u) {
-                r.level_sum[u] = sums[2 * u];
-                r.level_comp[u] = sums[2 * u + 1];
-                double x = sums[2 * u];
-                double t = s + x;
-                if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
-                else c += (x - t) + s;
-                s = t;
-                r.A[u] = s + c;
-            }
-            // remainder bound: sum over |S| > level of prod ||Mbar|| prod ||M'||
-            std::vector<double> poly(1, 1.0);
-            for (const NoiseSplit& ns : P.noise) {
-                std::vector<double> np(poly.size() + 1, 0.0);
-                for (size_t i = 0; i < poly.size(); ++i) {
-                    np[i] += poly[i] * ns.norm_main;
-                    np[i + 1] += poly[i] * ns.norm_bar;
-                }
-                poly.swap(np);
-            }
-            double b = 0;
-            for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
-            r.bound = P.trajectories ? -1.0 : b;   // a sample mean has no truncation bound
-            // FP32 value of the all-dominant term (diagnostic, written by the finalize)
-            r.x0_fp32 = -1;
-            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
-                r.x0_fp32 = *(const double*)((const char*)ex->results_host + pe.x0.off);
-        }
+        if (results) fill_results(ex, ex->results_host, results);
+    });
+}
+
+int tn_exec_submit(tn_exec exh, void* stream, int64_t* ticket) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        if (ex->opts.time_kernels) fail(TN_EINVAL, "per-launch timing needs tn_exec_run");
+        if (ex->next_ticket - ex->collected >= 2) fail(TN_ESTATE, "two estimates outstanding: collect one first");
+        hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
+        issue_estimate(ex, s);
+        const int slot = (int)(ex->next_ticket & 1);
+        const int64_t n2 = ex->results_stride / 8;   // float2-sized words
+        launch_copy_c64((const float*)ex->results_dev,
+                        (float*)((char*)ex->results_dev + (1 + slot) * ex->results_stride), n2, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(ex->ev_done[slot], s));
+        if (ticket) *ticket = ex->next_ticket;
+        ++ex->next_ticket;
+    });
+}
+
+int tn_exec_collect(tn_exec exh, int64_t ticket, tn_result* results) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        if (ticket != ex->collected || ticket >= ex->next_ticket)
+            fail(TN_ESTATE, "collect submitted estimates once each, in order");
+        const int slot = (int)(ticket & 1);
+        HIPCHK(hipEventSynchronize(ex->ev_done[slot]));
+        if (results) fill_results(ex, (const char*)ex->results_host + (1 + slot) * ex->results_stride, results);
+        ++ex->collected;
     });
 }
 
@@ -2421,6 +2473,8 @@ void tn_exec_destroy(tn_exec exh) {
     if (ex->graph) (void)hipGraphDestroy(ex->graph);
     if (ex->ev0) (void)hipEventDestroy(ex->ev0);
     if (ex->ev1) (void)hipEventDestroy(ex->ev1);
+    for (auto e : ex->ev_done)
+        if (e) (void)hipEventDestroy(e);
     if (ex->cap_stream) (void)hipStreamDestroy(ex->cap_stream);
     for (auto* list : {&ex->launches, &ex->launches64})
         for (auto& L : *list) {

@@ -95,7 +95,7 @@ class tn_plan_info(C.Structure):
 EXPORTS = [
     "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate",
     "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels",
-    "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_exec_submit", "tn_exec_collect", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
@@ -137,6 +137,8 @@ def lib():
     L.tn_exec_prepare.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(tn_exec_opts),
                                   vp, C.c_size_t, vp, C.POINTER(C.c_size_t), C.POINTER(vp)]
     L.tn_exec_run.argtypes = [vp, vp, C.POINTER(tn_result)]
+    L.tn_exec_submit.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    L.tn_exec_collect.argtypes = [vp, C.c_int64, C.POINTER(tn_result)]
     L.tn_exec_outputs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64)]
     L.tn_exec_timing.argtypes = [vp] + [C.POINTER(C.c_double)] * 4
     L.tn_contract_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.c_int64, C.c_int64,
@@ -327,6 +329,18 @@ class Exec:
 
     def run(self, stream=None) -> List[dict]:
         return [r.as_dict() for r in self.run_raw(stream)]
+
+    def submit(self, stream=None) -> int:
+        """Issue one estimate without waiting; returns its ticket."""
+        t = C.c_int64()
+        _check(lib().tn_exec_submit(self.handle, _stream_ptr(stream), C.byref(t)))
+        return t.value
+
+    def collect(self, ticket: int) -> List[dict]:
+        """Wait for a submitted estimate (in submission order) and return its results."""
+        res = (tn_result * len(self.plans))()
+        _check(lib().tn_exec_collect(self.handle, ticket, res))
+        return [r.as_dict() for r in res]
 
     def run_raw(self, stream=None):
         """tn_result array of one run (one entry per plan)."""

@@ -730,3 +730,31 @@ def test_trajectories_config2_against_oracle(torch):
     se = x.std(ddof=1) / np.sqrt(len(x))
     print(f"mean {mean:.9f} exact {gold[-1]:.9f} stderr {se:.2e}", flush=True)
     assert abs(mean - gold[-1]) <= 5 * se + 1e-10
+
+
+def test_pipelined_estimates_equal_sequential_runs(torch):
+    """Two estimates in flight (submit / collect) give the same bits as
+    tn_exec_run, every time; a third submit, an out-of-order collect and a
+    run with estimates outstanding are refused."""
+    print("pipelined estimates", flush=True)
+    c = W.config(2)
+    plan = tn.tn_plan_build(c, c.level)
+    terms = tn.tn_terms_enumerate(plan, c.level)
+    for graph in (False, True):
+        ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=graph))
+        ref = ex.run()[0]
+        prev = ex.submit()
+        for _ in range(6):
+            t = ex.submit()
+            assert ex.collect(prev)[0]["A"] == ref["A"]
+            prev = t
+        t2 = ex.submit()
+        with pytest.raises(tn.TNError):
+            ex.submit()                       # a third outstanding estimate
+        with pytest.raises(tn.TNError):
+            ex.collect(t2)                    # out of order
+        with pytest.raises(tn.TNError):
+            ex.run()                          # estimates outstanding
+        assert ex.collect(prev)[0]["A"] == ref["A"]
+        assert ex.collect(t2)[0]["A"] == ref["A"]
+        assert ex.run()[0]["A"] == ref["A"]
