@@ -1,18 +1,19 @@
-"""Benchmark: batched term-network contraction of the level-2 approximation.
+"""Benchmark: batched term-network contraction of Algorithm 1's level-l estimate.
 
-Workload: 25 qubits on a 5x5 grid, 12 layers of Haar SU(2) + CZ (4-colour
-schedule), 10 single-qubit depolarizing noises (p ~ U[1e-4, 5e-3]) at seeded
-random gate locations, input |0...0>, target = the noiseless output state,
-level-2 expansion (436 term networks).  Synthetic, seeded (see workloads/).
+Headline workload: 225 qubits on a 15x15 grid, 6 layers of Haar SU(2) + CZ
+(colours A B C D A B), 20 amplitude+phase-damping noises (rates ~ U[1e-4,
+1e-3]) at seeded random gate locations, input |0...0>, target = the noiseless
+output state, level-3 expansion (32551 term networks).  Synthetic, seeded
+(see workloads/).  The same line carries the 25-qubit grid (level 2), the
+36-qubit QAOA (level 2) and the 64 packed circuits as secondary lines.
 
 One step = one full estimate (every term network contracted, FP64 dominant
 term, per-term values, level sums) with the plan and its schedule prepared
 and all inputs resident in HBM.  The timed steps launch the prepared
-schedule directly (level by level; the same schedule replayed as a captured
-hipGraph is timed beside it and reported as `other_mode`; `--graph` swaps
-the two); a further pass launches it with a HIP event pair around every
-launch for the per-kernel durations of the roofline entry.  Prints ONE JSON
-line.
+schedule directly with two estimates in flight (submit / collect); the same
+steps one after another give the latency (time_to_estimate_ms), and a
+further pass launches the schedule with a HIP event pair around every launch
+for the per-kernel durations of the roofline entry.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -32,43 +33,99 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def cpu_baseline(circ, level, budget_s):
-    """The oracle as it stands, timed on the host on a seeded sample of the
-    same term set: one FP64 network contraction per term."""
-    import numpy as np
-    from oracle import network, terms as oterms
+_oracle_state = {}
+
+
+def _oracle_init(cfg):
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import network
+    _oracle_state["limit"] = threadpool_limits(1)
+    c = W.config(cfg)
+    _oracle_state["net"] = network.KetNetwork(c, diagonal=True)
+    _oracle_state["split"] = network.slot_split(c)
+
+
+def _oracle_terms(tl):
+    from oracle import network
+    for t in tl:
+        network.term_value(_oracle_state["net"], _oracle_state["split"], t)
+    return len(tl)
+
+
+def host_info():
+    model = None
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # noqa: BLE001
-        threads = 1
-    tl = oterms.enumerate_terms(circ.n_noises, level)
-    rng = np.random.default_rng(2211170280)
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"nproc": affinity, "os_cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(cfg, level, single_terms, all_terms, reps=3, max_procs=16):
+    """The oracle as it stands (one FP64 ket-network contraction per term,
+    numpy pairs in its own greedy order), timed on the host on a seeded random
+    sample of the workload's term set: single-threaded (BLAS limited to one
+    thread) and on all cores (one single-threaded process per core, the
+    sample split among them), each the median of `reps` runs; the full term
+    set's time is extrapolated from the rate.  Runs before the GPU is
+    touched (worker processes are forked)."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import terms as oterms
+    tl = oterms.enumerate_terms(__import__("workloads").config(cfg).n_noises, level)
+    rng = np.random.default_rng(2211170280 + cfg)
     order = rng.permutation(len(tl))
-    t0 = time.perf_counter()
-    net = network.KetNetwork(circ, diagonal=True)
-    sp = network.slot_split(circ)
-    setup = time.perf_counter() - t0
-    done = 0
-    t1 = time.perf_counter()
-    for j in order:
-        network.term_value(net, sp, tl[j])
-        done += 1
-        if time.perf_counter() - t1 > budget_s:
-            break
-    el = time.perf_counter() - t1
-    return {"value": done / el, "unit": "contractions/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of {len(tl)} terms of the same workload, seeded random order, "
-                      f"{el:.1f} s of contraction after {setup:.1f} s of network setup; one FP64 "
-                      f"ket-network contraction per term (numpy matmul pairs, greedy order, diagonal gates as shared indices)"}
+    info = host_info()
+    procs = max(1, min(max_procs, info["nproc"] or 1))
+    ctx = mp.get_context("fork")
+    runs1, runsn = [], []
+    sample1 = [tl[j] for j in order[:single_terms]]
+    with ctx.Pool(1, initializer=_oracle_init, initargs=(cfg,)) as pool:
+        pool.map(_oracle_terms, [sample1[:4]])                     # warm
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pool.map(_oracle_terms, [sample1])
+            runs1.append(len(sample1) / (time.perf_counter() - t0))
+    samplen = [tl[j] for j in order[:all_terms]]
+    chunks = [samplen[i::procs] for i in range(procs)]
+    with ctx.Pool(procs, initializer=_oracle_init, initargs=(cfg,)) as pool:
+        pool.map(_oracle_terms, [c[:2] for c in chunks])            # warm every worker
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pool.map(_oracle_terms, chunks, chunksize=1)
+            runsn.append(len(samplen) / (time.perf_counter() - t0))
+    med1, medn = sorted(runs1)[len(runs1) // 2], sorted(runsn)[len(runsn) // 2]
+    return {"value": medn, "unit": "contractions/s", "cores": procs, "kind": "oracle",
+            "sample": f"{len(samplen)} of the {len(tl)} terms (seeded random order), split over "
+                      f"{procs} single-threaded processes, median of {reps} runs; one FP64 ket-network "
+                      f"contraction per term (numpy pairs, the oracle's greedy order, diagonal gates as "
+                      f"shared indices); network setup excluded",
+            "runs": runsn,
+            "single_thread": {"value": med1, "runs": runs1, "sample": f"{len(sample1)} terms, median of {reps}"},
+            "extrapolated_full_estimate_s": {"all_cores": len(tl) / medn, "single_thread": len(tl) / med1},
+            "host": info}
 
 
-def measured_traffic(kernel):
+def traffic_record_path(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    record (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
-    or None when there is no record or the kernel source changed since."""
+    record of `workload` (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of
+    known size), or None when there is no record or the kernel source changed
+    since."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", "traffic_grid5x5_level2.json")
+    rec = traffic_record_path(workload)
     if not os.path.exists(rec):
         return None
     with open(rec) as f:
@@ -255,12 +312,14 @@ def trajectories_value(circ, f_exact, reps):
             "error_vs_exact": None if f_exact is None else r["A"][0] - f_exact}
 
 
-def pruning_value(ms_full, reps):
-    """The learned pruning on the 225-qubit workload (level 3, held out):
-    the network trained on the term values of the 25-qubit, 36-qubit and 16 of
+def pruning_value(c5, plan5, terms5, ms_full, ms_full_seq, reps):
+    """The learned pruning on the 225-qubit workload (level 3, held out): the
+    network trained on the term values of the 25-qubit, 36-qubit and 16 of
     the packed circuits, threshold from a 1e-7 pruned-mass budget of the
-    training estimates; the pruned term set's estimate timed like the full
-    one (its level-1 pre-pass and scoring reported apart)."""
+    training estimates.  Timed twice: the pruned term set's estimate alone
+    (prepared, as the full one), and end to end from the plan: the level-1
+    pre-pass, features, network scores, the pruned enumeration, its prepare
+    and one estimate (what selecting the terms costs on a new circuit)."""
     import numpy as np
     import torch
     import workloads as W
@@ -273,24 +332,16 @@ def pruning_value(ms_full, reps):
     train_s = time.perf_counter() - t0
     total = sum(d[2]["A"][-1] for d in data)
     tau = pruner.threshold(pruner.score_candidates(net, f_dev.cpu().numpy(), "mlp"), xs, 1e-7 * total)
-    c5 = W.config(5)
-    _, _, full, _ = pruner.full_run(c5)
-    t0 = time.perf_counter()
-    plan = tn.tn_plan_build(c5, c5.level)
-    t1 = tn.tn_terms_enumerate(plan, 1)
-    ex1 = tn.tn_exec_prepare([plan], [t1], tn.exec_opts(use_graph=False))
-    ex1.run()
-    x1, _ = ex1.values()
-    terms = tn.tn_terms_enumerate(plan, c5.level)
-    feats = tn.tn_terms_features(plan, terms, x1)
-    cand, _ = pruner.candidate_mask(terms)
-    keep = (pruner.score_candidates(net, feats[cand], "mlp") >= tau).astype(np.uint8)
-    tp = tn.tn_terms_enumerate(plan, c5.level, keep=keep, min_level=2)
-    ex = tn.tn_exec_prepare([plan], [tp], tn.exec_opts(use_graph=False))
-    select_s = time.perf_counter() - t0
+    full = tn.tn_exec_prepare([plan5], [terms5], tn.exec_opts(use_graph=False)).run()[0]
+    # end to end, twice (the first warms the allocator); the second is reported
+    for _ in range(2):
+        sel = pruner.pruned_estimate(c5, net, tau, "mlp")
+    e2e_s = sel["seconds"]
+    keep = sel["keep"]
+    tp = tn.tn_terms_enumerate(plan5, c5.level, keep=keep, min_level=2)
+    ex = tn.tn_exec_prepare([plan5], [tp], tn.exec_opts(use_graph=False))
     r = ex.run()[0]
     torch.cuda.synchronize()
-    # timed as the full estimate it is compared with: two estimates in flight
     t0 = time.perf_counter()
     prev = ex.submit()
     for _ in range(reps - 1):
@@ -300,32 +351,200 @@ def pruning_value(ms_full, reps):
     r = ex.collect(prev)[0]
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / reps
-    return {"workload": "grid15x15_6L_20adpd_level3", "candidates": int(cand.sum()), "kept": int(keep.sum()),
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ex.run()[0]
+    ms_seq = 1000.0 * (time.perf_counter() - t0) / reps
+    gold = os.path.join(ROOT, "tests", "golden", "config5_oracle.txt")
+    g = np.loadtxt(gold) if os.path.exists(gold) else None
+    return {"workload": "grid15x15_6L_20adpd_level3", "candidates": sel["candidates"], "kept": sel["kept"],
             "terms_full": full["n_terms"], "terms_contracted": r["n_contracted"],
-            "contraction_factor": full["n_terms"] / max(1, r["n_contracted"]),
-            "ms_pruned": ms, "ms_full": ms_full, "time_factor": None if not ms_full else ms_full / ms,
-            "error_vs_full": full["A"][-1] - r["A"][-1], "train_s": train_s, "select_s": select_s}
+            "contraction_factor": full["n_contracted"] / max(1, r["n_contracted"]),
+            "ms_pruned": ms, "ms_full": ms_full, "time_factor_estimate_only": ms_full / ms,
+            "ms_pruned_sequential": ms_seq, "ms_full_sequential": ms_full_seq,
+            "end_to_end_ms": 1000.0 * e2e_s,
+            "time_factor": ms_full_seq / (1000.0 * e2e_s),
+            "time_factor_note": "full estimate (prepared, one after another) / pruned estimate end to end "
+                                "from the plan (level-1 pre-pass, features, network scores, pruned "
+                                "enumeration, prepare, one estimate)",
+            "error_vs_full": full["A"][-1] - r["A"][-1],
+            "error_vs_oracle_full": None if g is None else g[-1] - r["A"][-1],
+            "level1_error_vs_oracle_full": None if g is None else g[-1] - full["A"][1],
+            "train_s": train_s}
+
+
+def run_estimates(ex, steps, warmup):
+    """(result, ms per estimate with two in flight, ms per estimate one after
+    another) of a prepared schedule."""
+    import torch
+    for _ in range(warmup):
+        r = ex.run()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prev = ex.submit()
+    for _ in range(steps - 1):
+        t = ex.submit()
+        r = ex.collect(prev)[0]
+        prev = t
+    r = ex.collect(prev)[0]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r_seq = ex.run()
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    assert [x["A"] for x in r_seq] == [x["A"] for x in ex.run()]
+    return r, 1000.0 * el / steps, 1000.0 * el_seq / steps, r_seq
+
+
+def kernel_pass(plans, terms, steps, warmup, tune):
+    """Per-kernel durations: the same schedule launched eagerly with a HIP
+    event pair around every launch on that launch's stream."""
+    import torch
+    from paper_2211_17028_amd import tn
+    ex = tn.tn_exec_prepare(plans, terms, tn.exec_opts(use_graph=False, time_kernels=True, tune=tune))
+    for _ in range(warmup):
+        ex.run()
+    ex.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        re_ = ex.run()
+    torch.cuda.synchronize()
+    eel = time.perf_counter() - t0
+    stats = ex.kernel_stats(reset=True)
+    launches = len([L for L in ex.describe()["launches"] if L["phase"] in ("batch", "batch64", "tail")])
+    del ex
+    return stats, 1000.0 * eel / steps, re_, launches
+
+
+def roofline_entry(stats, steps, workload):
+    """Dominant kernel of the FP32 chain (the critical path; the FP64 pass
+    runs beside it on its own stream and is summed in fp64_side_kernels)."""
+    fp64_names = {k for k in stats if "double" in k or k.startswith("k_tile64") or k.startswith("k_gemm_tiled_c128")}
+    main = {k: v for k, v in stats.items() if k not in fp64_names} or stats
+    dom_name, dom = max(main.items(), key=lambda kv: kv[1]["ms"])
+    roof = roofline_of(dom_name, dom, steps)
+    roof["traffic"] = measured_traffic(dom_name, workload)
+    side = [stats[k] for k in fp64_names]
+    if side:
+        roof["fp64_side_kernels"] = {"kernels": sorted(fp64_names),
+                                     "ms_per_step": sum(v["ms"] for v in side) / steps,
+                                     "launches_per_step": sum(v["launches"] for v in side) / steps}
+    mf = [v for k, v in stats.items() if k.startswith("k_mfma")]
+    if mf:
+        ms_ = sum(v["ms"] for v in mf)
+        roof["fp32_matrix_kernels"] = {"ms_per_step": ms_ / steps,
+                                       "tflops": sum(v["flops"] for v in mf) / (ms_ * 1e-3) / 1e12,
+                                       "frac": sum(v["flops"] for v in mf) / (ms_ * 1e-3) / 1e12
+                                       / FP32_MFMA_PEAK_TFLOPS}
+    kernels = {k: {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps,
+                   "tflops": v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12,
+                   "gbs": v["bytes"] / max(1e-9, v["ms"] * 1e-3) / 1e9}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+    return roof, kernels
+
+
+def golden_err(cfg, A):
+    import numpy as np
+    gold = os.path.join(ROOT, "tests", "golden", f"config{cfg}_oracle.txt")
+    if not os.path.exists(gold):
+        return None
+    g = np.loadtxt(gold)
+    return max(abs(A[u] - g[u]) / abs(g[u]) for u in range(len(g)))
+
+
+def secondary_line(cfg, args, with_roofline=False, with_plain=False):
+    """One more workload, timed like the headline: the 25-qubit grid (level 2,
+    436 terms), the 36-qubit QAOA (level 2, 1771 terms) or the 64 packed
+    circuits (354814 terms)."""
+    import workloads as W
+    from paper_2211_17028_amd import tn
+    cs = W.config(cfg)
+    cs = cs if isinstance(cs, list) else [cs]
+    t0 = time.perf_counter()
+    plans = [tn.tn_plan_build(c, c.level) for c in cs]
+    terms = [tn.tn_terms_enumerate(p, c.level) for p, c in zip(plans, cs)]
+    plan_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ex = tn.tn_exec_prepare(plans, terms, tn.exec_opts(use_graph=False, tune=not args.no_tune))
+    prep_s = time.perf_counter() - t0
+    steps = max(3, args.steps // (4 if cfg == 4 else 1))
+    r, ms, ms_seq, rs = run_estimates(ex, steps, max(1, args.warmup))
+    del ex
+    n_c = sum(x["n_contracted"] for x in rs)
+    name = {2: "grid5x5_12L_10depol_level2", 3: "qaoa36_p2_20adpd_level2", 4: "mixed64_level2or3_packed"}[cfg]
+    line = {"workload": name, "terms": sum(x["n_terms"] for x in rs), "contracted": n_c,
+            "value": n_c / (ms * 1e-3), "unit": "contractions/s", "ms_per_estimate": ms,
+            "time_to_estimate_ms": ms_seq, "plan_s": plan_s, "prepare_s": prep_s,
+            "err_vs_oracle": golden_err(cfg, r["A"]) if cfg != 4 else None}
+    if with_roofline:
+        stats, eager_ms, _, n_launch = kernel_pass(plans, terms, steps, max(1, args.warmup), not args.no_tune)
+        roof, kernels = roofline_entry(stats, steps, name)
+        line.update({"roofline": roof, "kernels": kernels, "launches_per_estimate": n_launch,
+                     "flops_per_estimate": sum(v["flops"] for v in stats.values()) / steps})
+    if with_plain:
+        exp = tn.tn_exec_prepare(plans, terms, tn.exec_opts(mode=tn.TN_MODE_PLAIN, use_graph=False,
+                                                            fp64_level0=False))
+        exp.run()
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp = exp.run()[0]
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        line["plain"] = {"value": rp["n_contracted"] / pel, "ms_per_estimate": 1000 * pel,
+                         "speedup_batched_vs_plain": line["value"] / (rp["n_contracted"] / pel)}
+        del exp
+    return line
+
+
+def plain_rate_c5(plan5, c5):
+    """PLAIN mode (the same kernels, one term at a time, no sharing, no graph)
+    on the 225-qubit workload's level-1 terms (61 networks): every term runs
+    the same steps, so its per-term time is that of the whole term set."""
+    import torch
+    from paper_2211_17028_amd import tn
+    t1 = tn.tn_terms_enumerate(plan5, 1)
+    exp = tn.tn_exec_prepare([plan5], [t1], tn.exec_opts(mode=tn.TN_MODE_PLAIN, use_graph=False,
+                                                         fp64_level0=False))
+    exp.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = exp.run()[0]
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - t0
+    del exp
+    return rp["n_contracted"] / pel, 1000.0 * pel, rp["n_contracted"]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the HBM traffic record of --traffic-kernel from two rocprofv3 --pmc "
-                         "counter files of bench.py --copy-calibration, then exit (no GPU needed)")
-    ap.add_argument("--traffic-kernel", default="k_mfma_group<128,64>")
+                    help="write the HBM traffic record of --traffic-kernel on --traffic-workload from two "
+                         "rocprofv3 --pmc counter files of bench.py --copy-calibration, then exit (no GPU needed)")
+    ap.add_argument("--traffic-kernel", default="k_mfma_group<128,32>")
+    ap.add_argument("--traffic-workload", default="grid5x5_12L_10depol_level2")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload (no secondary lines, no side measurements)")
+    ap.add_argument("--secondary", type=int, default=0,
+                    help="only the secondary line of config 2, 3 or 4 (with its roofline), e.g. for profiling")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-paper-case", action="store_true", help="skip the 225-qubit context measurement")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 25-qubit, 36-qubit and packed lines")
+    ap.add_argument("--cpu-single-terms", type=int, default=1500)
+    ap.add_argument("--cpu-all-terms", type=int, default=12000)
     ap.add_argument("--no-exact", action="store_true", help="skip the exact value (doubled network)")
     ap.add_argument("--no-offdiag", action="store_true", help="skip the off-diagonal element")
     ap.add_argument("--no-trajectories", action="store_true", help="skip the quantum-trajectories comparison")
     ap.add_argument("--no-pruning", action="store_true", help="skip the learned-pruning measurement")
+    ap.add_argument("--no-factored", action="store_true", help="skip the exact cross-term reuse line")
     ap.add_argument("--exact-only", action="store_true",
-                    help="only the exact value of the workload (one estimate for A(l)); prints its JSON")
+                    help="only the exact value of the 25-qubit workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
     ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -333,7 +552,7 @@ def main():
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.traffic_kernel,
-                              os.path.join(ROOT, "profiles", "traffic_grid5x5_level2.json"))
+                              traffic_record_path(args.traffic_workload))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "
@@ -341,9 +560,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
     import workloads as W
+    c5 = W.config(5)
+    level = c5.level
+    # the oracle on the host first, before the GPU is touched (its workers are forked)
+    cpu = None
+    if not (args.no_cpu or args.headline_only or args.secondary or args.exact_only):
+        cpu = cpu_baseline(5, level, args.cpu_single_terms, args.cpu_all_terms)
+        print(f"cpu baseline done: {cpu['value']:.1f} contractions/s on {cpu['cores']} processes", file=sys.stderr,
+              flush=True)
+
+    import torch
     from paper_2211_17028_amd import tn
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
@@ -355,167 +582,71 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    circ = W.config(2)
-    level = circ.level
+    if args.exact_only:
+        c2 = W.config(2)
+        p2 = tn.tn_plan_build(c2, c2.level)
+        t2 = tn.tn_terms_enumerate(p2, c2.level)
+        r1 = tn.tn_exec_prepare([p2], [t2], tn.exec_opts(use_graph=False)).run()[0]
+        print(json.dumps({"exact_value": exact_value(c2, c2.level, r1, args.steps)}), flush=True)
+        return
+    if args.secondary:
+        print(json.dumps({"secondary": secondary_line(args.secondary, args, with_roofline=True)}), flush=True)
+        return
+
+    workload = "grid15x15_6L_20adpd_level3"
     t0 = time.perf_counter()
-    plan = tn.tn_plan_build(circ, level)
+    plan = tn.tn_plan_build(c5, level)
     plan_s = time.perf_counter() - t0
     terms = tn.tn_terms_enumerate(plan, level)
-    if args.exact_only:
-        r1 = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False)).run()[0]
-        print(json.dumps({"exact_value": exact_value(circ, level, r1, args.steps)}), flush=True)
-        return
     # timed region: the prepared schedule run with direct launches (issued
-    # level by level, the FP64 pass on its own stream), inputs resident in HBM;
-    # then the same schedule captured once in a hipGraph and replayed, for
-    # comparison (`--graph` times the replay as the headline instead)
-    def timed(use_graph):
-        """(result, seconds for the steps with two estimates in flight, prepare
-        seconds, seconds for the same steps one after another)."""
-        t0 = time.perf_counter()
-        e = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=use_graph, tune=not args.no_tune))
-        prep = time.perf_counter() - t0
-        for _ in range(args.warmup):
-            r = e.run()[0]
-        torch.cuda.synchronize()
-        # every step is one whole estimate whose results are collected; the next
-        # one is submitted before the previous one is collected
-        t0 = time.perf_counter()
-        prev = e.submit()
-        for _ in range(args.steps - 1):
-            t = e.submit()
-            r = e.collect(prev)[0]
-            prev = t
-        r = e.collect(prev)[0]
-        torch.cuda.synchronize()
-        el_ = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r_seq = e.run()[0]
-        torch.cuda.synchronize()
-        el_seq = time.perf_counter() - t0
-        assert r_seq["A"] == r["A"]
-        del e
-        return r, el_, prep, el_seq
-
-    res, el, prep_s, el_seq = timed(args.graph)
-    res_o, el_o, _, el_o_seq = timed(not args.graph)
+    # level by level, the FP64 pass on its own stream), inputs resident in HBM,
+    # two estimates in flight; the same steps one after another give the
+    # latency of one estimate; the schedule replayed as a hipGraph beside it
+    t0 = time.perf_counter()
+    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=args.graph, tune=not args.no_tune))
+    prep_s = time.perf_counter() - t0
+    res, ms_per_step, ms_seq, _ = run_estimates(ex, args.steps, args.warmup)
+    del ex
+    eo = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=not args.graph, tune=not args.no_tune))
+    res_o, ms_o, ms_o_seq, _ = run_estimates(eo, args.steps, args.warmup)
+    del eo
     n_contracted = res["n_contracted"]
-    ms_per_step = 1000.0 * el / args.steps
-    value = n_contracted * args.steps / el
+    value = n_contracted / (ms_per_step * 1e-3)
     other = {"mode": "direct launches" if args.graph else "hipGraph replay",
-             "value": n_contracted * args.steps / el_o, "ms_per_step": 1000.0 * el_o / args.steps,
-             "ms_per_step_sequential": 1000.0 * el_o_seq / args.steps,
+             "value": n_contracted / (ms_o * 1e-3), "ms_per_step": ms_o, "ms_per_step_sequential": ms_o_seq,
              "A_equal": res_o["A"] == res["A"]}
-    # kernel durations: the same schedule launched eagerly, a HIP event pair
-    # around every launch on its own stream (events inside a captured graph
-    # cannot be timed); same kernels, same inputs, same launch shapes
-    ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, time_kernels=True,
-                                                          tune=not args.no_tune))
-    for _ in range(args.warmup):
-        re_ = ex.run()[0]
-    ex.kernel_stats(reset=True)
+    # tn_estimate: the same estimate through the one-call entry point (its
+    # first call builds, binds and uploads the schedule; later calls with the
+    # same arguments reuse it and upload its constants again)
+    _, full_ws = tn.tn_plan_workspace([plan], [terms])
+    ws = torch.empty(full_ws, dtype=torch.uint8, device="cuda")
+    tn.tn_release_cached()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    r_est = tn.tn_estimate([plan], [terms], ws=ws)[0]
+    est_cold_ms = 1000.0 * (time.perf_counter() - t0)
+    t0 = time.perf_counter()
     for _ in range(args.steps):
-        re_ = ex.run()[0]
-    torch.cuda.synchronize()
-    eel = time.perf_counter() - t0
-    stats = ex.kernel_stats(reset=True)
-    eager = {"value": n_contracted * args.steps / eel, "ms_per_step": 1000.0 * eel / args.steps,
-             "A_equal": re_["A"] == res["A"],
+        r_est = tn.tn_estimate([plan], [terms], ws=ws)[0]
+    est_warm_ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    tn.tn_release_cached()
+    del ws
+    stats, eager_ms, re_, n_launch = kernel_pass([plan], [terms], args.steps, args.warmup, not args.no_tune)
+    roof, kernels = roofline_entry(stats, args.steps, workload)
+    eager = {"value": n_contracted / (eager_ms * 1e-3), "ms_per_step": eager_ms, "A_equal": re_[0]["A"] == res["A"],
              "note": "direct launches with a HIP event pair per launch (kernel durations below)"}
-    del ex
-
-    # parity of the estimate against the stored oracle values
-    err = None
-    gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.txt")
-    if os.path.exists(gold):
-        g = np.loadtxt(gold)
-        err = max(abs(res["A"][u] - g[u]) / abs(g[u]) for u in range(level + 1))
-
-    # dominant kernel: largest accumulated time in the eager pass among the
-    # kernels of the FP32 chain (the critical path; the FP64 pass runs beside
-    # it on its own stream and is reported as `fp64_side_kernels`); its bound
-    # is the matrix cores (FP32 MFMA kernels) or HBM (small-step kernels)
-    fp64_names = {k for k in stats if "double" in k or k.startswith("k_tile64") or k.startswith("k_gemm_tiled_c128")}
-    main = {k: v for k, v in stats.items() if k not in fp64_names} or stats
-    dom_name, dom = max(main.items(), key=lambda kv: kv[1]["ms"])
-    roof = roofline_of(dom_name, dom, args.steps)
-    roof["traffic"] = measured_traffic(dom_name)
-    side = [stats[k] for k in fp64_names]
-    if side:
-        roof["fp64_side_kernels"] = {"kernels": sorted(fp64_names),
-                                     "ms_per_step": sum(v["ms"] for v in side) / args.steps,
-                                     "launches_per_step": sum(v["launches"] for v in side) / args.steps}
-    # the FP32 matrix-core kernels together (the term contractions)
-    mf = [v for k, v in stats.items() if k.startswith("k_mfma")]
-    if mf:
-        ms_ = sum(v["ms"] for v in mf)
-        roof["fp32_matrix_kernels"] = {"ms_per_step": ms_ / args.steps,
-                                       "tflops": sum(v["flops"] for v in mf) / (ms_ * 1e-3) / 1e12,
-                                       "frac": sum(v["flops"] for v in mf) / (ms_ * 1e-3) / 1e12
-                                       / FP32_MFMA_PEAK_TFLOPS}
-    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                   "tflops": v["flops"] / max(1e-9, v["ms"] * 1e-3) / 1e12,
-                   "gbs": v["bytes"] / max(1e-9, v["ms"] * 1e-3) / 1e9}
-               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+    err = golden_err(5, res["A"])
 
     plain = None
-    if not args.no_plain:
-        exp = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(mode=tn.TN_MODE_PLAIN, use_graph=False,
-                                                                fp64_level0=False))
-        exp.run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rp = exp.run()[0]
-        torch.cuda.synchronize()
-        pel = time.perf_counter() - t0
-        plain = {"value": rp["n_contracted"] / pel, "ms_per_estimate": 1000 * pel,
-                 "speedup_batched_vs_plain": (rp["n_contracted"] / pel and value / (rp["n_contracted"] / pel))}
-        del exp
+    if not (args.no_plain or args.headline_only):
+        rate, pms, pn = plain_rate_c5(plan, c5)
+        plain = {"value": rate, "ms_for_sample": pms, "sample_terms": pn,
+                 "note": "PLAIN mode on the workload's level-1 terms (every term runs the same steps)",
+                 "speedup_batched_vs_plain": value / rate}
 
-    # context: the paper's largest quoted case has 225 qubits and 20 noises
-    # (about 1.8 hours on its stated hardware); here the 15x15-grid level-3
-    # workload (32551 terms), graph replay of the prepared schedule
-    paper_case = None
-    if not args.no_paper_case:
-        c5 = W.config(5)
-        t0 = time.perf_counter()
-        p5 = tn.tn_plan_build(c5, c5.level)
-        t5 = tn.tn_terms_enumerate(p5, c5.level)
-        plan5_s = time.perf_counter() - t0
-        e5 = tn.tn_exec_prepare([p5], [t5], tn.exec_opts(use_graph=True))
-        for _ in range(args.warmup):
-            r5 = e5.run()[0]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r5 = e5.run()[0]
-        torch.cuda.synchronize()
-        ms5_graph = 1000.0 * (time.perf_counter() - t0) / args.steps
-        del e5
-        # direct launches, two estimates in flight (as the headline)
-        e5 = tn.tn_exec_prepare([p5], [t5], tn.exec_opts(use_graph=False))
-        for _ in range(args.warmup):
-            r5 = e5.run()[0]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        prev = e5.submit()
-        for _ in range(args.steps - 1):
-            t = e5.submit()
-            r5 = e5.collect(prev)[0]
-            prev = t
-        r5 = e5.collect(prev)[0]
-        torch.cuda.synchronize()
-        ms5 = 1000.0 * (time.perf_counter() - t0) / args.steps
-        g5 = os.path.join(ROOT, "tests", "golden", "config5_oracle.txt")
-        e5err = None
-        if os.path.exists(g5):
-            g = np.loadtxt(g5)
-            e5err = max(abs(r5["A"][u] - g[u]) / abs(g[u]) for u in range(c5.level + 1))
-        del e5
-        # exact cross-term reuse: the same workload's 9 independent clusters
+    factored = None
+    if not (args.no_factored or args.headline_only):
+        # exact cross-term reuse: the workload's 9 independent clusters
         # factored, at level 8 (1.03e9 terms in the full expansion)
         t0 = time.perf_counter()
         fe = tn.FactoredEstimate(c5, 8, opts=tn.exec_opts(use_graph=False))
@@ -531,20 +662,27 @@ def main():
         factored = {"level": 8, "terms_full_expansion": full8, "terms_factored": fe.terms.n,
                     "ms_per_estimate": msf, "plan_prepare_s": f_prep, "A": list(a8)}
         del fe
-        paper_case = {"workload": "grid15x15_6L_20adpd_level3", "qubits": 225, "noises": 20, "level": 3,
-                      "factored": factored,
-                      "terms": r5["n_terms"], "ms_per_estimate": ms5, "ms_per_estimate_graph_sequential": ms5_graph,
-                      "plan_s": plan5_s,
-                      "err_vs_oracle": e5err, "paper_note": "the paper quotes about 1.8 h for 225 qubits "
-                      "with 20 noises on its own hardware and circuits (different circuits; context only)"}
 
-    exact = None if args.no_exact else exact_value(circ, level, res, 5)
-    offd = None if args.no_offdiag else offdiagonal_value(circ, level, 20)
-    traj = None if args.no_trajectories else trajectories_value(circ, exact["F"] if exact else None, 20)
-    prune = None if args.no_pruning else pruning_value(paper_case["ms_per_estimate"] if paper_case else None,
-                                                       args.steps)
+    secondary = None
+    if not (args.no_secondary or args.headline_only):
+        secondary = {
+            "grid5x5_12L_10depol_level2": secondary_line(2, args, with_roofline=True, with_plain=not args.no_plain),
+            "qaoa36_p2_20adpd_level2": secondary_line(3, args),
+            "mixed64_level2or3_packed": secondary_line(4, args),
+        }
+    c2 = W.config(2)
+    exact = None
+    offd = traj = prune = None
+    if not args.headline_only:
+        if not args.no_exact:
+            p2 = tn.tn_plan_build(c2, c2.level)
+            t2 = tn.tn_terms_enumerate(p2, c2.level)
+            r2 = tn.tn_exec_prepare([p2], [t2], tn.exec_opts(use_graph=False)).run()[0]
+            exact = exact_value(c2, c2.level, r2, 5)
+        offd = None if args.no_offdiag else offdiagonal_value(c2, c2.level, 20)
+        traj = None if args.no_trajectories else trajectories_value(c2, exact["F"] if exact else None, 20)
+        prune = None if args.no_pruning else pruning_value(c5, plan, terms, ms_per_step, ms_seq, args.steps)
 
-    cpu = None if args.no_cpu else cpu_baseline(circ, level, args.cpu_budget)
     info = plan.info()
     line = {
         "metric": METRIC,
@@ -554,33 +692,39 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
-        "time_to_estimate_ms": ms_per_step,
+        "time_to_estimate_ms": ms_seq,
+        "time_to_estimate_note": "one estimate's latency: tn_exec_run of the prepared schedule, one after another",
+        "tn_estimate_ms": est_warm_ms,
+        "tn_estimate_first_call_ms": est_cold_ms,
+        "tn_estimate_A_equal": r_est["A"] == res["A"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64",
         "dtype_detail": "complex64 term contractions on FP32 MFMA; complex128 all-dominant term; FP64 sums",
         "data": "synthetic",
-        "config": {"workload": "grid5x5_12L_10depol_level2", "qubits": 25, "layers": 12, "noises": 10,
+        "config": {"workload": workload, "qubits": 225, "layers": 6, "noises": 20,
                    "level": level, "terms": res["n_terms"], "contracted": n_contracted},
         "err_vs_oracle": err,
         "A": res["A"],
+        "T": res["T"],
         "paper_unit_value": 2 * value,
         "plan_s": plan_s,
         "prepare_s": prep_s,
+        "launches_per_estimate": n_launch,
         "flops_per_estimate": sum(v["flops"] for v in stats.values()) / args.steps,
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
         "kernels": kernels,
         "timed": ("hipGraph replays" if args.graph else "direct launches") +
                  ", two estimates in flight (submit / collect)",
-        "sequential": {"ms_per_step": 1000.0 * el_seq / args.steps,
-                       "value": n_contracted * args.steps / el_seq,
-                       "note": "the same steps one tn_exec_run after another"},
         "other_mode": other,
         "eager": eager,
         "plain": plain,
-        "paper_case": paper_case,
+        "paper_note": "the paper quotes about 1.8 h for 225 qubits with 20 noises on its own CPU server "
+                      "and circuits (different circuits, level not stated; context only)",
+        "factored": factored,
+        "secondary": secondary,
         "exact_value": exact,
         "offdiagonal": offd,
         "trajectories": traj,

@@ -298,20 +298,57 @@ int tn_exec_timing(tn_exec ex, double* total_ms, double* gemm_ms, double* permut
                    double* other_ms);
 
 /* ---------------------------------------------------------------------------
- * tn_contract_batch -- contract the ket networks of terms [first, first+count)
- * of each packed plan's term set and write their amplitudes a_t as complex64
- * to d_amp (count values per plan, plan-major).  Asynchronous on `stream`.
+ * tn_contract_batch -- the term contractions of Algorithm 1 (Section IV) for
+ * terms [first, first+count) of each packed plan's term set: their ket
+ * networks are contracted and the amplitudes a_t written as complex64 to
+ * d_amp (count values per plan, plan-major; device memory the caller owns).
+ * a_t is the amplitude with slot tensors sqrt(2) K_{c_s} (K_i as in
+ * tn_plan_noise), so the term value is X_t = w_t 2^-N |a_t|^2 with w_t from
+ * tn_terms_get.  All in FP32 (no FP64 pass).
+ *
+ * Only the range's terms are scheduled.  The schedule is built and bound to
+ * d_ws on the first call with these arguments (plans, term sets, range, d_ws,
+ * ws_bytes) and kept: later calls with the same arguments upload its
+ * constants again (from a page-locked copy) and run it, so any range can be
+ * resumed or repeated cheaply.  At most 8 schedules are kept; those naming a
+ * plan or term set are dropped when it is destroyed (tn_release_cached drops
+ * all).  Asynchronous on `stream`: d_amp is valid once the stream reaches the
+ * call's end, and d_ws must not be used for anything else until then.  Calls
+ * are serialized by the library; two calls sharing d_ws must run on one
+ * stream.
+ *
+ * Errors: TN_EINVAL (null handle, negative or out-of-range range, null d_amp
+ * or d_ws, ws_bytes == 0), TN_ENOMEM (ws_bytes below the range's schedule; no
+ * device call is made), TN_EHIP.  count == 0 does nothing.
  * ------------------------------------------------------------------------- */
 int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, int64_t first,
                       int64_t count, void* d_amp, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * tn_estimate -- Algorithm 1 end to end for n packed plans: prepare, run,
- * synchronize, fill results[n].  Equivalent to tn_exec_prepare + tn_exec_run +
- * tn_exec_destroy with default options.
+ * tn_estimate -- Algorithm 1 end to end (Section III, Problem 1; Section IV,
+ * Algorithm 1's Require / Ensure) for n packed plans: every term contracted,
+ * X_t = w_t |a_t|^2, the level sums T_u and A(l') for l' <= l; the
+ * all-dominant term in FP64.  Synchronizes `stream` and fills results[n].
+ *
+ * Workspace (device memory the caller owns; sizes from tn_plan_workspace):
+ *   ws_bytes >= full_bytes : one schedule over all terms, kept between calls
+ *     with the same arguments as for tn_contract_batch (its constants are
+ *     uploaded again on each call);
+ *   min_bytes <= ws_bytes < full_bytes : each plan's terms run as consecutive
+ *     ranges, each range as large as fits, their X_t gathered in one array
+ *     whose level sums are taken by the same fixed-order kernel (per-term
+ *     values equal the one-schedule ones to FP32 rounding: tile shapes and
+ *     split sums depend on a range's size);
+ *   ws_bytes < min_bytes : TN_ENOMEM before any device call.
+ * Errors: TN_EINVAL (null handle, results or d_ws, ws_bytes == 0), TN_ENOMEM,
+ * TN_EHIP.
  * ------------------------------------------------------------------------- */
 int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_ws,
                 size_t ws_bytes, void* stream, tn_result* results);
+
+/* Drop every schedule kept by tn_estimate / tn_contract_batch (waits for
+ * their last calls' streams). */
+void tn_release_cached(void);
 
 /* ---------------------------------------------------------------------------
  * tn_plan_build_trajectories / tn_terms_trajectories -- the quantum-trajectories
@@ -382,9 +419,13 @@ int tn_factored_levels(tn_terms terms, const double* group_sums, double* A);
  * ------------------------------------------------------------------------- */
 int tn_polarization_combine(const tn_result* r, double* re, double* im);
 
-/* Workspace bytes tn_estimate needs for these plans and term sets. */
+/* Workspace bytes of tn_estimate for these plans and term sets (host only):
+ * full_bytes runs the estimate as one schedule; min_bytes is the least it
+ * accepts (terms in ranges of one: the per-term X array and level sums plus
+ * the largest single-term schedule).  Either pointer may be NULL (not both).
+ * Errors: TN_EINVAL (null handles), planning errors as tn_exec_prepare. */
 int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms,
-                      size_t* need_bytes);
+                      size_t* min_bytes, size_t* full_bytes);
 
 /* Introspection (host only). -------------------------------------------- */
 typedef struct {

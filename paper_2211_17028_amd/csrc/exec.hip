@@ -198,6 +198,7 @@ struct tn_exec_s {
     int64_t results_stride = 0;
     hipEvent_t ev_done[2] = {nullptr, nullptr};
     int64_t next_ticket = 0, collected = 0;
+    hipStream_t submit_stream = nullptr;   // stream of the outstanding submitted estimates
     void* results_host = nullptr;      // host address
     void* results_dev = nullptr;       // the same memory as the device addresses it
     tn::ConstBuf cbuf;
@@ -217,6 +218,7 @@ struct tn_exec_s {
     std::map<int, std::pair<int64_t, double>> kstat;  // kernel id -> (launches, ms) accumulated
     std::map<int, double> kflops, kbytes;             // kernel id -> algorithmic work accumulated
     bool bound = false;
+    ~tn_exec_s();   // joins the side issuer, frees events, streams, graph and host results
 };
 
 namespace tn {
@@ -1294,8 +1296,15 @@ static std::vector<u128> cluster_keys(const Plan& P, const Cluster& cl, const Te
     return uk;
 }
 
+// Term range of a schedule: only terms [lo, hi) of every packed term set are
+// contracted (hi < 0: to the end); the others get X = 0 like pruned terms.
+struct TermRange {
+    int64_t lo = 0, hi = -1;
+};
+
 static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms,
-                           const std::map<int, std::pair<int, double>>* level_tile = nullptr) {
+                           const std::map<int, std::pair<int, double>>* level_tile = nullptr,
+                           TermRange range = TermRange{}) {
     Builder bw;
     bw.ex = ex;
     bw.level_tile = level_tile;
@@ -1316,7 +1325,9 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         pe.terms = &T;
         pe.n_terms = T.n;
         std::vector<int32_t> live_index(T.n, -1);
-        for (int64_t t = 0; t < T.n; ++t) {
+        const int64_t r_lo = std::min<int64_t>(std::max<int64_t>(range.lo, 0), T.n);
+        const int64_t r_hi = range.hi < 0 ? T.n : std::min<int64_t>(range.hi, T.n);
+        for (int64_t t = r_lo; t < r_hi; ++t) {
             if (T.zero[t]) { ++pe.n_zero; continue; }
             if (T.pruned[t]) { ++pe.n_pruned; continue; }
             live_index[t] = (int32_t)pe.live_terms.size();
@@ -1690,6 +1701,30 @@ static void stop_side_issuer(tn_exec_s* ex) {
     ex->issuer.reset();
 }
 
+}  // namespace tn
+
+tn_exec_s::~tn_exec_s() {
+    tn::stop_side_issuer(this);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    for (auto e : ev_done)
+        if (e) (void)hipEventDestroy(e);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto* list : {&launches, &launches64})
+        for (auto& L : *list) {
+            if (L.ev_a) (void)hipEventDestroy(L.ev_a);
+            if (L.ev_b) (void)hipEventDestroy(L.ev_b);
+        }
+    if (results_host) (void)hipHostFree(results_host);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+}
+
+namespace tn {
+
 // Direct launches with the FP64 pass: the side thread issues it after the
 // fork event while this thread issues the FP32 chain; the join waits for both.
 static void run_body_threaded(tn_exec_s* ex, hipStream_t s) {
@@ -2028,50 +2063,372 @@ static void issue_estimate(tn_exec_s* ex, hipStream_t s) {
     }
 }
 
+// One circuit's result from its level sums ((sum, comp) pairs, u = 0..level):
+// A(u) as the compensated running sum, and the truncation bound of the split.
+static void fill_one(const Plan& P, const Terms& T, int64_t n_live, int64_t n_zero, const double* sums,
+                     double x0_fp32, tn_result& r) {
+    std::memset(&r, 0, sizeof(r));
+    r.level = T.level;
+    r.clamped = P.clamped ? 1 : 0;
+    r.n_terms = T.n;
+    r.n_contracted = n_live;
+    r.n_zero_weight = n_zero;
+    double s = 0, c = 0;
+    for (int u = 0; u <= T.level; ++u) {
+        r.level_sum[u] = sums[2 * u];
+        r.level_comp[u] = sums[2 * u + 1];
+        double x = sums[2 * u];
+        double t = s + x;
+        if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+        r.A[u] = s + c;
+    }
+    // remainder bound: sum over |S| > level of prod ||Mbar|| prod ||M'||
+    std::vector<double> poly(1, 1.0);
+    for (const NoiseSplit& ns : P.noise) {
+        std::vector<double> np(poly.size() + 1, 0.0);
+        for (size_t i = 0; i < poly.size(); ++i) {
+            np[i] += poly[i] * ns.norm_main;
+            np[i + 1] += poly[i] * ns.norm_bar;
+        }
+        poly.swap(np);
+    }
+    double b = 0;
+    for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
+    r.bound = P.trajectories ? -1.0 : b;   // a sample mean has no truncation bound
+    r.x0_fp32 = x0_fp32;
+}
+
 // per-circuit results from a results region (slot 0 or a submitted copy)
 static void fill_results(tn_exec_s* ex, const void* base, tn_result* results) {
-        for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
-            const PlanExec& pe = ex->plans[pi];
-            const Plan& P = *pe.plan;
-            const Terms& T = *pe.terms;
-            tn_result& r = results[pi];
-            std::memset(&r, 0, sizeof(r));
-            r.level = T.level;
-            r.clamped = P.clamped ? 1 : 0;
-            r.n_terms = T.n;
-            r.n_contracted = pe.n_live;
-            r.n_zero_weight = pe.n_zero;
-            const double* hs = (const double*)((const char*)base + pe.sums.off);
-            std::vector<double> sums(hs, hs + 2 * (T.level + 1));
-            double s = 0, c = 0;
-            for (int u = 0; u <= T.level; ++u) {
-                r.level_sum[u] = sums[2 * u];
-                r.level_comp[u] = sums[2 * u + 1];
-                double x = sums[2 * u];
-                double t = s + x;
-                if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
-                else c += (x - t) + s;
-                s = t;
-                r.A[u] = s + c;
-            }
-            // remainder bound: sum over |S| > level of prod ||Mbar|| prod ||M'||
-            std::vector<double> poly(1, 1.0);
-            for (const NoiseSplit& ns : P.noise) {
-                std::vector<double> np(poly.size() + 1, 0.0);
-                for (size_t i = 0; i < poly.size(); ++i) {
-                    np[i] += poly[i] * ns.norm_main;
-                    np[i + 1] += poly[i] * ns.norm_bar;
-                }
-                poly.swap(np);
-            }
-            double b = 0;
-            for (size_t i = T.level + 1; i < poly.size(); ++i) b += poly[i];
-            r.bound = P.trajectories ? -1.0 : b;   // a sample mean has no truncation bound
-            // FP32 value of the all-dominant term (diagnostic, written by the finalize)
-            r.x0_fp32 = -1;
-            if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
-                r.x0_fp32 = *(const double*)((const char*)base + pe.x0.off);
+    for (size_t pi = 0; pi < ex->plans.size(); ++pi) {
+        const PlanExec& pe = ex->plans[pi];
+        const double* hs = (const double*)((const char*)base + pe.sums.off);
+        // FP32 value of the all-dominant term (diagnostic, written by the finalize)
+        double x0 = -1;
+        if (pe.zero_term >= 0 && ex->opts.mode == TN_MODE_BATCHED && !pe.fp32_skipped)
+            x0 = *(const double*)((const char*)base + pe.x0.off);
+        fill_one(*pe.plan, *pe.terms, pe.n_live, pe.n_zero, hs, x0, results[pi]);
+    }
+}
+
+// Host part of tn_exec_prepare: the schedule of n packed plans over the terms
+// in `range`, with its constant region staged on the host (no device call).
+static std::unique_ptr<tn_exec_s> build_exec(int n, const tn_plan* plans, const tn_terms* terms,
+                                             const tn_exec_opts* opts, TermRange range) {
+    if (n < 1 || !plans || !terms) fail(TN_EINVAL, "need at least one plan with its terms");
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !terms[i]) fail(TN_EINVAL, "null plan or term handle");
+    auto ex = std::make_unique<tn_exec_s>();
+    if (opts) ex->opts = *opts;
+    else {
+        ex->opts.mode = TN_MODE_BATCHED;
+        ex->opts.use_graph = 0;
+        ex->opts.fp64_level0 = 1;
+    }
+    if (ex->opts.time_kernels && ex->opts.use_graph)
+        fail(TN_EINVAL, "per-launch kernel timing needs eager launches (use_graph = 0): events "
+                        "recorded inside a captured graph cannot be timed");
+    if (ex->opts.mode == TN_MODE_PLAIN) {
+        ex->opts.use_graph = 0;
+        if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
+    }
+    if (n == 1 && ex->opts.mode != TN_MODE_PLAIN && !ex->opts.no_group && !ex->opts.mixed_shapes) {
+        // A level whose matrix-core jobs chose different tile shapes runs
+        // one launch per shape, one after the other.  The schedule is
+        // planned again with the shape carrying most of the level's flops
+        // imposed on the level's small jobs (each at most a quarter of
+        // that shape's flops), which then join its launch; large jobs keep
+        // their own shape (a forced shape costs them more than a launch).
+        // Packed circuits share every level's launches already and keep
+        // each job's shape (measured slower with the merge).
+        tn_exec_s probe;
+        probe.opts = ex->opts;
+        build_schedule(&probe, n, plans, terms, nullptr, range);
+        std::map<int, std::map<int, double>> flops;   // level -> tile -> flops
+        for (const Launch& L : probe.launches)
+            if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) flops[L.level][L.mtile] += L.flops;
+        std::map<int, std::pair<int, double>> level_tile;
+        for (auto& kv : flops) {
+            if (kv.second.size() < 2) continue;
+            auto top = std::max_element(kv.second.begin(), kv.second.end(),
+                                        [](const std::pair<const int, double>& a,
+                                           const std::pair<const int, double>& b) { return a.second < b.second; });
+            level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
         }
+        build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile, range);
+    } else {
+        build_schedule(ex.get(), n, plans, terms, nullptr, range);
+    }
+    return ex;
+}
+
+static size_t exec_need(const tn_exec_s* ex) { return (size_t)(ex->const_bytes + ex->work_bytes); }
+
+// Device part of tn_exec_prepare: bind the schedule to the workspace, upload
+// its constants on `stream` and create its events / side stream.
+static void bind_exec(tn_exec_s* ex, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    const size_t need = exec_need(ex);
+    if (!d_ws) fail(TN_EINVAL, "null workspace");
+    if (ws_bytes < need) {
+        std::ostringstream os;
+        os << "workspace too small: " << ws_bytes << " < " << need << " bytes";
+        fail(TN_ENOMEM, os.str());
+    }
+    ex->base = (char*)d_ws;
+    ex->stream = stream;
+    HIPCHK(hipGetDevice(&ex->device));
+    ex->results_stride = std::max<int64_t>(8, (ex->results_bytes + 7) & ~int64_t(7));
+    HIPCHK(hipHostMalloc(&ex->results_host, (size_t)(3 * ex->results_stride),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer(&ex->results_dev, ex->results_host, 0));
+    bind(ex);
+    bind_multi_tail(ex);
+    if (!ex->launches64.empty()) {
+        HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ex->ev_join, hipEventDisableTiming));
+    }
+    if (ex->opts.time_kernels)
+        for (auto* list : {&ex->launches, &ex->launches64})
+            for (auto& L : *list)
+                if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0) ||
+                    (L.kind == L_GROUP && L.blocks > 0) ||
+                    ((L.kind == L_MGROUP || L.kind == L_MREDUCE) && L.n_tiles > 0)) {
+                    HIPCHK(hipEventCreate(&L.ev_a));
+                    HIPCHK(hipEventCreate(&L.ev_b));
+                }
+    HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
+                          ex->stream));
+    if (ex->opts.tune) autotune(ex);
+    HIPCHK(hipEventCreate(&ex->ev0));
+    HIPCHK(hipEventCreate(&ex->ev1));
+    for (auto& e : ex->ev_done) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(ex->stream));
+    ex->bound = true;
+}
+
+static const tn_exec_opts& estimate_opts() {
+    static tn_exec_opts o = [] {
+        tn_exec_opts x{};
+        x.mode = TN_MODE_BATCHED;
+        x.use_graph = 0;
+        x.fp64_level0 = 1;
+        return x;
+    }();
+    return o;
+}
+
+static const tn_exec_opts& batch_opts() {
+    static tn_exec_opts o = [] {
+        tn_exec_opts x{};
+        x.mode = TN_MODE_BATCHED;
+        x.use_graph = 0;
+        x.fp64_level0 = 0;
+        return x;
+    }();
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Prepared schedules of tn_estimate and tn_contract_batch, kept between calls
+// with the same arguments (plans, term sets, term range, workspace): the host
+// schedule is built and bound once; each call uploads its constant region
+// again from a page-locked copy (the caller may have used the workspace for
+// something else in between) and runs it.  At most kCacheEntries entries;
+// entries naming a plan or term set are dropped when it is destroyed.
+// ---------------------------------------------------------------------------
+struct CachedExec {
+    int kind = 0;                       // 0: tn_estimate, 1: tn_contract_batch
+    std::vector<const void*> plans, terms;
+    TermRange range;
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    int device = 0;
+    std::unique_ptr<tn_exec_s> ex;
+    void* pinned = nullptr;             // page-locked copy of the constant region
+    size_t pinned_bytes = 0;
+    hipStream_t last_stream = nullptr;
+    uint64_t last_use = 0;
+    ~CachedExec() {
+        // the last call's work may still be in flight on its stream
+        (void)hipStreamSynchronize(last_stream);
+        ex.reset();
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+constexpr size_t kCacheEntries = 8;
+
+static std::mutex& cache_mutex() {
+    static std::mutex* m = new std::mutex();   // never destroyed: entries outlive static teardown
+    return *m;
+}
+
+static std::vector<std::unique_ptr<CachedExec>>& cache_entries() {
+    static auto* v = new std::vector<std::unique_ptr<CachedExec>>();
+    return *v;
+}
+
+static uint64_t g_cache_clock = 0;
+
+template <class Pred>
+static void cache_evict_if(Pred pred) {
+    auto& v = cache_entries();
+    for (size_t i = 0; i < v.size();) {
+        if (pred(*v[i])) v.erase(v.begin() + (std::ptrdiff_t)i);
+        else ++i;
+    }
+}
+
+static CachedExec* cache_find(int kind, int n, const tn_plan* plans, const tn_terms* terms, TermRange range,
+                              void* d_ws, size_t ws_bytes) {
+    if (n < 1 || !plans || !terms) return nullptr;
+    for (auto& e : cache_entries()) {
+        if (e->kind != kind || (int)e->plans.size() != n || e->d_ws != d_ws || e->ws_bytes != ws_bytes ||
+            e->range.lo != range.lo || e->range.hi != range.hi)
+            continue;
+        bool same = true;
+        for (int i = 0; i < n && same; ++i) same = e->plans[i] == (const void*)plans[i] && e->terms[i] == (const void*)terms[i];
+        if (!same) continue;
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != e->device) continue;
+        e->last_use = ++g_cache_clock;
+        return e.get();
+    }
+    return nullptr;
+}
+
+static CachedExec* cache_insert(int kind, int n, const tn_plan* plans, const tn_terms* terms, TermRange range,
+                                void* d_ws, size_t ws_bytes, std::unique_ptr<tn_exec_s> ex, hipStream_t s) {
+    auto ce = std::make_unique<CachedExec>();
+    ce->kind = kind;
+    ce->plans.assign((const void* const*)plans, (const void* const*)plans + n);
+    ce->terms.assign((const void* const*)terms, (const void* const*)terms + n);
+    ce->range = range;
+    ce->d_ws = d_ws;
+    ce->ws_bytes = ws_bytes;
+    ce->last_stream = s;
+    bind_exec(ex.get(), d_ws, ws_bytes, s);
+    ce->device = ex->device;
+    ce->pinned_bytes = ex->cbuf.bytes.size();
+    HIPCHK(hipHostMalloc(&ce->pinned, std::max<size_t>(1, ce->pinned_bytes), hipHostMallocDefault));
+    std::memcpy(ce->pinned, ex->cbuf.bytes.data(), ce->pinned_bytes);
+    ce->ex = std::move(ex);
+    ce->last_use = ++g_cache_clock;
+    auto& v = cache_entries();
+    if (v.size() >= kCacheEntries) {
+        auto lru = std::min_element(v.begin(), v.end(), [](const std::unique_ptr<CachedExec>& a,
+                                                            const std::unique_ptr<CachedExec>& b) {
+            return a->last_use < b->last_use;
+        });
+        v.erase(lru);
+    }
+    v.push_back(std::move(ce));
+    return v.back().get();
+}
+
+static void cache_reupload(CachedExec* ce, hipStream_t s) {
+    if (ce->pinned_bytes)
+        HIPCHK(hipMemcpyAsync(ce->ex->base, ce->pinned, ce->pinned_bytes, hipMemcpyHostToDevice, s));
+    ce->last_stream = s;
+}
+
+// ---------------------------------------------------------------------------
+// Estimates in term ranges (a workspace below the one-schedule size): each
+// plan's terms run as consecutive ranges, each range a schedule of its own in
+// the part of the workspace after the plan's X array; every range's X values
+// are copied into that array, whose level sums are then taken by the same
+// fixed-order kernel as in one schedule.
+// ---------------------------------------------------------------------------
+static std::vector<int64_t> level_starts(const Terms& T) {
+    std::vector<int64_t> st(T.level + 2, T.n);
+    for (int u = T.level; u >= 0; --u) {
+        int64_t s = T.n;
+        for (int64_t t = 0; t < T.n; ++t)
+            if (T.lvl[t] == u) { s = t; break; }
+        st[u] = s;
+    }
+    st[T.level + 1] = T.n;
+    for (int u = T.level; u >= 0; --u)
+        if (st[u] > st[u + 1]) st[u] = st[u + 1];
+    return st;
+}
+
+static int64_t chunk_x_bytes(const Terms& T) { return round_up(std::max<int64_t>(1, T.n) * 8, 256); }
+static int64_t chunk_starts_bytes(const Terms& T) { return round_up((int64_t)(T.level + 2) * 8, 256); }
+static int64_t chunk_acc_bytes(const Terms& T) {
+    return chunk_x_bytes(T) + chunk_starts_bytes(T) + round_up((int64_t)(T.level + 1) * 16, 256);
+}
+
+// Smallest workspace of a ranged estimate: every range a single term.  Every
+// single-term schedule other than the all-dominant term's has the same path
+// with one instance per node, so the first live term after term 0 stands for
+// them all; term 0's range holds the FP64 pass.
+static size_t min_workspace(int n, const tn_plan* plans, const tn_terms* terms) {
+    if (n < 1 || !plans || !terms) fail(TN_EINVAL, "need at least one plan with its terms");
+    size_t mx = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !terms[i]) fail(TN_EINVAL, "null plan or term handle");
+        const Terms& T = *reinterpret_cast<const Terms*>(terms[i]);
+        size_t m = 0;
+        if (T.n > 0) m = exec_need(build_exec(1, &plans[i], &terms[i], &estimate_opts(), TermRange{0, 1}).get());
+        for (int64_t t = 1; t < T.n; ++t)
+            if (!T.zero[t] && !T.pruned[t]) {
+                m = std::max(m, exec_need(build_exec(1, &plans[i], &terms[i], &estimate_opts(),
+                                                     TermRange{t, t + 1}).get()));
+                break;
+            }
+        mx = std::max(mx, (size_t)chunk_acc_bytes(T) + m);
+    }
+    return mx;
+}
+
+static void estimate_chunked(int n, const tn_plan* plans, const tn_terms* terms, char* ws, size_t ws_bytes,
+                             hipStream_t s, tn_result* results) {
+    for (int i = 0; i < n; ++i) {
+        const Plan& P = *reinterpret_cast<const Plan*>(plans[i]);
+        const Terms& T = *reinterpret_cast<const Terms*>(terms[i]);
+        const int64_t acc = chunk_acc_bytes(T);
+        if ((size_t)acc >= ws_bytes) fail(TN_ENOMEM, "workspace below the per-term arrays of a ranged estimate");
+        double* d_x = (double*)ws;
+        int64_t* d_starts = (int64_t*)(ws + chunk_x_bytes(T));
+        double* d_sums = (double*)(ws + chunk_x_bytes(T) + chunk_starts_bytes(T));
+        char* sub = ws + acc;
+        const size_t avail = ws_bytes - (size_t)acc;
+        const std::vector<int64_t> starts = level_starts(T);
+        HIPCHK(hipMemcpyAsync(d_starts, starts.data(), starts.size() * 8, hipMemcpyHostToDevice, s));
+        int64_t n_live = 0, n_zero = 0;
+        int64_t lo = 0, cnt = T.n;
+        while (lo < T.n) {
+            cnt = std::min(cnt, T.n - lo);
+            std::unique_ptr<tn_exec_s> ex;
+            for (;;) {
+                ex = build_exec(1, &plans[i], &terms[i], &estimate_opts(), TermRange{lo, lo + cnt});
+                if (exec_need(ex.get()) <= avail) break;
+                if (cnt == 1) fail(TN_ENOMEM, "one term's schedule does not fit the workspace");
+                cnt = (cnt + 1) / 2;
+            }
+            bind_exec(ex.get(), sub, avail, s);
+            issue_estimate(ex.get(), s);
+            const PlanExec& pe = ex->plans[0];
+            HIPCHK(hipMemcpyAsync(d_x + lo, (const char*)resolve(ex.get(), pe.x_out) + lo * 8, (size_t)cnt * 8,
+                                  hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            n_live += pe.n_live;
+            n_zero += pe.n_zero;
+            lo += cnt;
+            cnt *= 2;   // the next range starts its search at twice this one
+        }
+        launch_level_sum(d_x, d_starts, T.level + 1, d_sums, s);
+        HIPCHK(hipGetLastError());
+        std::vector<double> hs(2 * (T.level + 1));
+        HIPCHK(hipMemcpyAsync(hs.data(), d_sums, hs.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_one(P, T, n_live, n_zero, hs.data(), -1.0, results[i]);
+    }
 }
 
 }  // namespace tn
@@ -2225,54 +2582,31 @@ int tn_plan_describe(tn_plan plan, char* buf, size_t* len) {
     });
 }
 
-void tn_plan_destroy(tn_plan plan) { delete reinterpret_cast<Plan*>(plan); }
-void tn_terms_destroy(tn_terms terms) { delete reinterpret_cast<Terms*>(terms); }
+void tn_plan_destroy(tn_plan plan) {
+    if (!plan) return;
+    {
+        std::lock_guard<std::mutex> lk(cache_mutex());
+        cache_evict_if([&](const CachedExec& c) {
+            return std::find(c.plans.begin(), c.plans.end(), (const void*)plan) != c.plans.end();
+        });
+    }
+    delete reinterpret_cast<Plan*>(plan);
+}
+void tn_terms_destroy(tn_terms terms) {
+    if (!terms) return;
+    {
+        std::lock_guard<std::mutex> lk(cache_mutex());
+        cache_evict_if([&](const CachedExec& c) {
+            return std::find(c.terms.begin(), c.terms.end(), (const void*)terms) != c.terms.end();
+        });
+    }
+    delete reinterpret_cast<Terms*>(terms);
+}
 
 int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, const tn_exec_opts* opts,
                     void* d_ws, size_t ws_bytes, void* stream, size_t* need_bytes, tn_exec* out) {
     return guard([&] {
-        if (n < 1 || !plans || !terms) fail(TN_EINVAL, "need at least one plan with its terms");
-        auto ex = std::make_unique<tn_exec_s>();
-        if (opts) ex->opts = *opts;
-        else {
-            ex->opts.mode = TN_MODE_BATCHED;
-            ex->opts.use_graph = 0;
-            ex->opts.fp64_level0 = 1;
-        }
-        if (ex->opts.time_kernels && ex->opts.use_graph)
-            fail(TN_EINVAL, "per-launch kernel timing needs eager launches (use_graph = 0): events "
-                            "recorded inside a captured graph cannot be timed");
-        if (ex->opts.mode == TN_MODE_PLAIN) {
-            ex->opts.use_graph = 0;
-            if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
-        }
-        if (n == 1 && ex->opts.mode != TN_MODE_PLAIN && !ex->opts.no_group && !ex->opts.mixed_shapes) {
-            // A level whose matrix-core jobs chose different tile shapes runs
-            // one launch per shape, one after the other.  The schedule is
-            // planned again with the shape carrying most of the level's flops
-            // imposed on the level's small jobs (each at most a quarter of
-            // that shape's flops), which then join its launch; large jobs keep
-            // their own shape (a forced shape costs them more than a launch).
-            // Packed circuits share every level's launches already and keep
-            // each job's shape (measured slower with the merge).
-            tn_exec_s probe;
-            probe.opts = ex->opts;
-            build_schedule(&probe, n, plans, terms);
-            std::map<int, std::map<int, double>> flops;   // level -> tile -> flops
-            for (const Launch& L : probe.launches)
-                if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) flops[L.level][L.mtile] += L.flops;
-            std::map<int, std::pair<int, double>> level_tile;
-            for (auto& kv : flops) {
-                if (kv.second.size() < 2) continue;
-                auto top = std::max_element(kv.second.begin(), kv.second.end(),
-                                            [](const std::pair<const int, double>& a,
-                                               const std::pair<const int, double>& b) { return a.second < b.second; });
-                level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
-            }
-            build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile);
-        } else {
-            build_schedule(ex.get(), n, plans, terms);
-        }
+        std::unique_ptr<tn_exec_s> ex = build_exec(n, plans, terms, opts, TermRange{});
         const size_t need = (size_t)(ex->const_bytes + ex->work_bytes);
         if (need_bytes) *need_bytes = need;
         if (ws_bytes == 0) {
@@ -2281,44 +2615,8 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             if (out) *out = reinterpret_cast<tn_exec>(ex.release());
             return;
         }
-        if (!d_ws) fail(TN_EINVAL, "null workspace");
-        if (ws_bytes < need) {
-            std::ostringstream os;
-            os << "workspace too small: " << ws_bytes << " < " << need << " bytes";
-            fail(TN_ENOMEM, os.str());
-        }
         if (!out) fail(TN_EINVAL, "null output handle");
-        ex->base = (char*)d_ws;
-        ex->stream = (hipStream_t)stream;
-        HIPCHK(hipGetDevice(&ex->device));
-        ex->results_stride = std::max<int64_t>(8, (ex->results_bytes + 7) & ~int64_t(7));
-        HIPCHK(hipHostMalloc(&ex->results_host, (size_t)(3 * ex->results_stride),
-                             hipHostMallocMapped | hipHostMallocCoherent));
-        HIPCHK(hipHostGetDevicePointer(&ex->results_dev, ex->results_host, 0));
-        bind(ex.get());
-        bind_multi_tail(ex.get());
-        if (!ex->launches64.empty()) {
-            HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&ex->ev_join, hipEventDisableTiming));
-        }
-        if (ex->opts.time_kernels)
-            for (auto* list : {&ex->launches, &ex->launches64})
-                for (auto& L : *list)
-                    if ((L.kind == L_GEMM && L.g.n_inst > 0) || (L.kind == L_PERM && L.p.n_inst > 0) ||
-                        (L.kind == L_GROUP && L.blocks > 0) ||
-                        ((L.kind == L_MGROUP || L.kind == L_MREDUCE) && L.n_tiles > 0)) {
-                        HIPCHK(hipEventCreate(&L.ev_a));
-                        HIPCHK(hipEventCreate(&L.ev_b));
-                    }
-        HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
-                              ex->stream));
-        if (ex->opts.tune) autotune(ex.get());
-        HIPCHK(hipEventCreate(&ex->ev0));
-        HIPCHK(hipEventCreate(&ex->ev1));
-        for (auto& e : ex->ev_done) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        HIPCHK(hipStreamSynchronize(ex->stream));
-        ex->bound = true;
+        bind_exec(ex.get(), d_ws, ws_bytes, (hipStream_t)stream);
         *out = reinterpret_cast<tn_exec>(ex.release());
     });
 }
@@ -2357,6 +2655,11 @@ int tn_exec_submit(tn_exec exh, void* stream, int64_t* ticket) {
         if (ex->opts.time_kernels) fail(TN_EINVAL, "per-launch timing needs tn_exec_run");
         if (ex->next_ticket - ex->collected >= 2) fail(TN_ESTATE, "two estimates outstanding: collect one first");
         hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
+        // outstanding estimates share the workspace and the results slot: a
+        // second one on another stream would run beside the first
+        if (ex->next_ticket != ex->collected && s != ex->submit_stream)
+            fail(TN_EINVAL, "estimates outstanding on another stream: submit on the same stream or collect first");
+        ex->submit_stream = s;
         issue_estimate(ex, s);
         const int slot = (int)(ex->next_ticket & 1);
         const int64_t n2 = ex->results_stride / 8;   // float2-sized words
@@ -2465,83 +2768,97 @@ int tn_exec_const_bytes(tn_exec exh, void* buf, size_t* len) {
     });
 }
 
-void tn_exec_destroy(tn_exec exh) {
-    tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
-    if (!ex) return;
-    stop_side_issuer(ex);
-    if (ex->gexec) (void)hipGraphExecDestroy(ex->gexec);
-    if (ex->graph) (void)hipGraphDestroy(ex->graph);
-    if (ex->ev0) (void)hipEventDestroy(ex->ev0);
-    if (ex->ev1) (void)hipEventDestroy(ex->ev1);
-    for (auto e : ex->ev_done)
-        if (e) (void)hipEventDestroy(e);
-    if (ex->cap_stream) (void)hipStreamDestroy(ex->cap_stream);
-    for (auto* list : {&ex->launches, &ex->launches64})
-        for (auto& L : *list) {
-            if (L.ev_a) (void)hipEventDestroy(L.ev_a);
-            if (L.ev_b) (void)hipEventDestroy(L.ev_b);
-        }
-    if (ex->results_host) (void)hipHostFree(ex->results_host);
-    if (ex->ev_fork) (void)hipEventDestroy(ex->ev_fork);
-    if (ex->ev_join) (void)hipEventDestroy(ex->ev_join);
-    if (ex->side) (void)hipStreamDestroy(ex->side);
-    delete ex;
-}
+void tn_exec_destroy(tn_exec exh) { delete reinterpret_cast<tn_exec_s*>(exh); }
 
-int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms, size_t* need_bytes) {
-    return tn_exec_prepare(n, plans, terms, nullptr, nullptr, 0, nullptr, need_bytes, nullptr);
+int tn_plan_workspace(int32_t n, const tn_plan* plans, const tn_terms* terms, size_t* min_bytes,
+                      size_t* full_bytes) {
+    return guard([&] {
+        if (!min_bytes && !full_bytes) fail(TN_EINVAL, "null output");
+        if (full_bytes) *full_bytes = exec_need(build_exec(n, plans, terms, &estimate_opts(), TermRange{}).get());
+        if (min_bytes) *min_bytes = min_workspace(n, plans, terms);
+    });
 }
 
 int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_ws, size_t ws_bytes,
                 void* stream, tn_result* results) {
-    tn_exec ex = nullptr;
-    size_t need = 0;
-    tn_exec_opts o{};
-    o.mode = TN_MODE_BATCHED;
-    o.use_graph = 0;
-    o.fp64_level0 = 1;
-    int rc = tn_exec_prepare(n, plans, terms, &o, d_ws, ws_bytes, stream, &need, &ex);
-    if (rc != TN_OK) return rc;
-    rc = tn_exec_run(ex, stream, results);
-    tn_exec_destroy(ex);
-    return rc;
+    return guard([&] {
+        if (!results) fail(TN_EINVAL, "null results");
+        if (!d_ws || ws_bytes == 0) fail(TN_EINVAL, "tn_estimate needs a workspace (d_ws, ws_bytes > 0)");
+        hipStream_t s = (hipStream_t)stream;
+        std::lock_guard<std::mutex> lk(cache_mutex());
+        CachedExec* ce = cache_find(0, n, plans, terms, TermRange{}, d_ws, ws_bytes);
+        if (!ce) {
+            std::unique_ptr<tn_exec_s> ex = build_exec(n, plans, terms, &estimate_opts(), TermRange{});
+            if (exec_need(ex.get()) > ws_bytes) {
+                // below the one-schedule size: term ranges one after another
+                const size_t mn = min_workspace(n, plans, terms);
+                if (ws_bytes < mn) {
+                    std::ostringstream os;
+                    os << "workspace too small: " << ws_bytes << " < " << mn
+                       << " bytes (the minimum: one term per range; " << exec_need(ex.get())
+                       << " bytes run the estimate as one schedule)";
+                    fail(TN_ENOMEM, os.str());
+                }
+                estimate_chunked(n, plans, terms, (char*)d_ws, ws_bytes, s, results);
+                return;
+            }
+            ce = cache_insert(0, n, plans, terms, TermRange{}, d_ws, ws_bytes, std::move(ex), s);
+        } else {
+            cache_reupload(ce, s);
+        }
+        tn_exec_s* ex = ce->ex.get();
+        if (ex->next_ticket != ex->collected) fail(TN_ESTATE, "cached schedule has estimates outstanding");
+        issue_estimate(ex, s);
+        HIPCHK(hipEventRecord(ex->ev1, s));
+        HIPCHK(hipEventSynchronize(ex->ev1));
+        fill_results(ex, ex->results_host, results);
+    });
 }
 
 int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, int64_t first, int64_t count,
                       void* d_amp, void* d_ws, size_t ws_bytes, void* stream) {
     return guard([&] {
+        if (n < 1 || !plans || !terms) fail(TN_EINVAL, "need at least one plan with its terms");
         if (first < 0 || count < 0) fail(TN_EINVAL, "bad term range");
-        // restrict each term set to the range by pruning everything outside it
-        std::vector<std::unique_ptr<Terms>> sub;
-        std::vector<tn_terms> th;
         for (int i = 0; i < n; ++i) {
+            if (!plans[i] || !terms[i]) fail(TN_EINVAL, "null plan or term handle");
             const Terms* t = reinterpret_cast<const Terms*>(terms[i]);
             if (first + count > t->n) fail(TN_EINVAL, "term range beyond the term set");
-            auto c = std::make_unique<Terms>(*t);
-            for (int64_t k = 0; k < c->n; ++k)
-                if (k < first || k >= first + count) c->pruned[k] = 1;
-            th.push_back(reinterpret_cast<tn_terms>(c.get()));
-            sub.push_back(std::move(c));
         }
-        tn_exec_opts o{};
-        o.mode = TN_MODE_BATCHED;
-        o.use_graph = 0;
-        o.fp64_level0 = 0;
-        tn_exec ex = nullptr;
-        size_t need = 0;
-        int rc = tn_exec_prepare(n, plans, th.data(), &o, d_ws, ws_bytes, stream, &need, &ex);
-        if (rc != TN_OK) throw Error{rc, tn_last_error()};
-        tn_exec_s* e = reinterpret_cast<tn_exec_s*>(ex);
+        if (count == 0) return;
+        if (!d_amp) fail(TN_EINVAL, "null amplitude output");
+        if (!d_ws || ws_bytes == 0) fail(TN_EINVAL, "tn_contract_batch needs a workspace (d_ws, ws_bytes > 0)");
         hipStream_t s = (hipStream_t)stream;
+        const TermRange range{first, first + count};
+        std::lock_guard<std::mutex> lk(cache_mutex());
+        CachedExec* ce = cache_find(1, n, plans, terms, range, d_ws, ws_bytes);
+        if (!ce) {
+            std::unique_ptr<tn_exec_s> ex = build_exec(n, plans, terms, &batch_opts(), range);
+            if (exec_need(ex.get()) > ws_bytes) {
+                std::ostringstream os;
+                os << "workspace too small for terms [" << first << ", " << first + count << "): " << ws_bytes
+                   << " < " << exec_need(ex.get()) << " bytes";
+                fail(TN_ENOMEM, os.str());
+            }
+            ce = cache_insert(1, n, plans, terms, range, d_ws, ws_bytes, std::move(ex), s);
+        } else {
+            cache_reupload(ce, s);
+        }
+        tn_exec_s* e = ce->ex.get();
+        if (!e->bound) fail(TN_ESTATE, "schedule not bound to the workspace");
         run_body(e, s);
         for (int i = 0; i < n; ++i) {
             const PlanExec& pe = e->plans[i];
             HIPCHK(hipMemcpyAsync((char*)d_amp + (size_t)i * count * 8, (char*)resolve(e, pe.amp_out) + first * 8,
                                   (size_t)count * 8, hipMemcpyDeviceToDevice, s));
         }
-        HIPCHK(hipStreamSynchronize(s));
-        tn_exec_destroy(ex);
+        HIPCHK(hipGetLastError());
     });
+}
+
+void tn_release_cached(void) {
+    std::lock_guard<std::mutex> lk(cache_mutex());
+    cache_evict_if([](const CachedExec&) { return true; });
 }
 
 }  // extern "C"

@@ -92,7 +92,9 @@ def score_candidates(mlp, feats, policy):
 
 def pruned_estimate(circ, mlp, tau, policy="mlp", level=None):
     """Level-1 pre-pass, scoring, pruned estimate.  Returns dict with the
-    result, the kept count and the wall time of the whole procedure."""
+    result, the kept count, the keep flags of the candidates (enumeration
+    order), the pruned run's per-term values and the wall time of the whole
+    procedure."""
     import torch
     level = circ.level if level is None else level
     t0 = time.perf_counter()
@@ -110,5 +112,7 @@ def pruned_estimate(circ, mlp, tau, policy="mlp", level=None):
     ex = tn.tn_exec_prepare([plan], [tp], tn.exec_opts(use_graph=False))
     res = ex.run()[0]
     torch.cuda.synchronize()
-    return {"result": res, "kept": int(keep.sum()), "candidates": int(cand.sum()),
-            "seconds": time.perf_counter() - t0}
+    seconds = time.perf_counter() - t0
+    x, _ = ex.values()
+    return {"result": res, "kept": int(keep.sum()), "candidates": int(cand.sum()), "keep": keep,
+            "x": x, "seconds": seconds}

@@ -97,6 +97,7 @@ EXPORTS = [
     "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels",
     "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_exec_submit", "tn_exec_collect", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
+    "tn_release_cached",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
 ]
@@ -145,7 +146,10 @@ def lib():
                                     vp, vp, C.c_size_t, vp]
     L.tn_estimate.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), vp, C.c_size_t, vp,
                               C.POINTER(tn_result)]
-    L.tn_plan_workspace.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_size_t)]
+    L.tn_plan_workspace.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_size_t),
+                                    C.POINTER(C.c_size_t)]
+    L.tn_release_cached.argtypes = []
+    L.tn_release_cached.restype = None
     L.tn_plan_get_info.argtypes = [vp, C.POINTER(tn_plan_info)]
     L.tn_plan_noise.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(tn_c128),
                                 C.POINTER(C.c_double)]
@@ -563,16 +567,20 @@ def offdiagonal(circ, x, y, level: Optional[int] = None, output: bool = True, ex
     return np.array([complex(re[u], im[u]) for u in range(L + 1)]), [r.as_dict() for r in raw], ex
 
 
-def tn_plan_workspace(plans: Sequence[Plan], terms: Sequence[Terms]) -> int:
-    need = C.c_size_t()
-    _check(lib().tn_plan_workspace(len(plans), _handles(plans), _handles(terms), C.byref(need)))
-    return need.value
+def tn_plan_workspace(plans: Sequence[Plan], terms: Sequence[Terms]):
+    """(min_bytes, full_bytes) of tn_estimate's workspace."""
+    mn, full = C.c_size_t(), C.c_size_t()
+    _check(lib().tn_plan_workspace(len(plans), _handles(plans), _handles(terms), C.byref(mn), C.byref(full)))
+    return mn.value, full.value
 
 
-def tn_estimate(plans: Sequence[Plan], terms: Sequence[Terms], stream=None) -> List[dict]:
+def tn_estimate(plans: Sequence[Plan], terms: Sequence[Terms], stream=None, ws=None) -> List[dict]:
+    """Algorithm 1 end to end through tn_estimate.  ``ws``: a uint8 device
+    tensor used as the workspace (default: one of the full size)."""
     import torch
-    need = tn_plan_workspace(plans, terms)
-    ws = torch.empty(max(256, need), dtype=torch.uint8, device="cuda")
+    if ws is None:
+        _, full = tn_plan_workspace(plans, terms)
+        ws = torch.empty(max(256, full), dtype=torch.uint8, device="cuda")
     res = (tn_result * len(plans))()
     _check(lib().tn_estimate(len(plans), _handles(plans), _handles(terms), C.c_void_p(ws.data_ptr()),
                              ws.numel(), _stream_ptr(stream), res))
@@ -580,17 +588,26 @@ def tn_estimate(plans: Sequence[Plan], terms: Sequence[Terms], stream=None) -> L
 
 
 def tn_contract_batch(plans: Sequence[Plan], terms: Sequence[Terms], first: int, count: int,
-                      stream=None):
-    """Amplitudes a_t (complex64) of terms [first, first+count) per plan, as a
-    torch tensor of shape (len(plans), count)."""
+                      stream=None, ws=None, amp=None):
+    """Amplitudes a_t (complex64, slots sqrt(2) K) of terms [first, first+count)
+    per plan, as a torch tensor of shape (len(plans), count).  ``ws``: the
+    workspace tensor (uint8, device; default: the full estimate's size);
+    ``amp``: an output tensor of at least len(plans) * count complex64."""
     import torch
-    need = tn_plan_workspace(plans, terms)
-    ws = torch.empty(max(256, need), dtype=torch.uint8, device="cuda")
-    amp = torch.zeros((len(plans), max(1, count)), dtype=torch.complex64, device="cuda")
+    if ws is None:
+        _, full = tn_plan_workspace(plans, terms)
+        ws = torch.empty(max(256, full), dtype=torch.uint8, device="cuda")
+    if amp is None:
+        amp = torch.zeros((len(plans), max(1, count)), dtype=torch.complex64, device="cuda")
     _check(lib().tn_contract_batch(len(plans), _handles(plans), _handles(terms), first, count,
                                    C.c_void_p(amp.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream_ptr(stream)))
-    return amp[:, :count]
+    return amp.reshape(len(plans), -1)[:, :count]
+
+
+def tn_release_cached():
+    """Drop the schedules tn_estimate / tn_contract_batch keep between calls."""
+    lib().tn_release_cached()
 
 
 # ---------------------------------------------------------------------------

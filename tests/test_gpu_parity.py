@@ -18,6 +18,7 @@ import pytest
 import workloads as W
 from oracle import estimate, network
 from paper_2211_17028_amd import tn
+from tests import parity_checks as pc
 
 pytestmark = pytest.mark.gpu
 
@@ -136,6 +137,7 @@ def test_config1_against_oracle(torch, level):
     for u in range(level + 1):
         assert abs(res["A"][u] - ref["A"][u]) <= 1e-6 * ref["A"][u], (u, res["A"][u], ref["A"][u])
         assert abs(res["T"][u] - ref["T"][u]) <= 2e-5 * abs(ref["T"][u]) + 1e-12
+    pc.check_against_golden(res["T"], x, pat, ref["T"], ref["X"], network.slot_split(c), degenerate=False)
     if level == 4:
         from oracle import dense
         f = dense.exact_value(c)
@@ -179,54 +181,36 @@ def test_graph_replays_match_eager_and_are_deterministic(torch):
         assert r["T"] == eager["T"]
 
 
-def test_config2_full_size_sampled_terms(torch):
+def _golden(cfg):
+    return (np.loadtxt(os.path.join(GOLD, f"config{cfg}_oracle.txt")),
+            np.loadtxt(os.path.join(GOLD, f"config{cfg}_levels.txt")),
+            np.load(os.path.join(GOLD, f"config{cfg}_terms.npy")))
+
+
+def test_config2_every_term_against_oracle(torch):
     """5x5 grid, 12 layers, 10 depolarizing noises, level 2 (436 terms): every
-    term on the GPU; a sample of position sets against the oracle one by one
-    (depolarizing corrections are degenerate, so sums over each position set
-    are compared)."""
+    term on the GPU against the oracle's stored per-term values (depolarizing
+    corrections are degenerate, so the sums over each of the 56 noise-position
+    sets are compared, each within the summed FP32 bounds of its terms), every
+    T_u against the stored level sums, and every T_u against math.fsum of the
+    same GPU X_t at 1e-12."""
     print("config2 full size", flush=True)
     c = W.config(2)
     res, x, pat, _ = run_gpu(c, 2)
     assert res["n_terms"] == 436
     assert np.all(x >= 0)
     assert res["A"][0] <= res["A"][1] <= res["A"][2] <= 1.0 + 1e-6
-    net = network.KetNetwork(c, diagonal=True)
-    sp = network.slot_split(c)
-    groups = {(): [], (3,): [], (7,): [], (2, 8): []}
-    for j, row in enumerate(pat):
-        key = tuple(i for i, v in enumerate(row) if v)
-        if key in groups:
-            groups[key].append(j)
-    for key, idx in groups.items():
-        ref = sum(network.term_value(net, sp, tuple(int(v) for v in pat[j]))[0] for j in idx)
-        got = sum(x[j] for j in idx)
-        tol = 1e-12 if key == () else 2e-5
-        assert abs(got - ref) <= tol * ref + 1e-13, (key, got, ref)
-    gold = os.path.join(GOLD, "config2_oracle.txt")
-    if os.path.exists(gold):
-        vals = np.loadtxt(gold)
-        for u in range(3):
-            assert abs(res["A"][u] - vals[u]) <= 1e-6 * vals[u], (u, res["A"][u], vals[u])
+    gold_a, gold_t, gold_x = _golden(2)
+    pc.check_against_golden(res["T"], x, pat, gold_t, gold_x, network.slot_split(c), degenerate=True)
+    for u in range(3):
+        assert abs(res["A"][u] - gold_a[u]) <= 1e-6 * gold_a[u], (u, res["A"][u], gold_a[u])
     # the all-dominant term from the FP32 batch (diagnostic, written by the finalize)
     # agrees with its FP64 value to FP32 accuracy
     assert abs(res["x0_fp32"] - x[0]) <= 2e-5 * x[0], (res["x0_fp32"], x[0])
 
 
-ETA32 = 2.0 ** -18   # FP32 amplitude error per unit of the slot-norm product (64 u32)
-
-
 def fp32_term_tol(split, term, ref):
-    """Tolerance of one FP32 term value.  The amplitude a of a term is a
-    contraction of unitary gates, unit states and the slot matrices K_c, so
-    |a| <= prod ||K_c||_2 and its FP32 rounding error is a multiple of
-    u32 * prod ||K_c||_2 (not of |a|: small terms come from cancellation).
-    With X = w |a|^2 and B = w prod ||K_c||_2^2:
-    |X_gpu - X| <= 2 eta sqrt(X B) + eta^2 B, plus 2e-5 X for the rest."""
-    b = 1.0
-    for s, c in enumerate(term):
-        d, k, _ = split[s]
-        b *= d[c] * np.linalg.norm(k[c], 2) ** 2
-    return 2e-5 * ref + 2 * ETA32 * math.sqrt(ref * b) + ETA32 ** 2 * b
+    return pc.fp32_term_tol(split, term, ref)
 
 
 def _sample_terms(pat, w, rng, per_level):
@@ -244,27 +228,30 @@ def _sample_terms(pat, w, rng, per_level):
 def test_full_size_config_against_oracle(torch, cfg):
     """Config 3 (QAOA p=2, 36 qubits, 20 AD+PD, level 2, 1771 terms) and
     config 5 (15x15 grid, 6 layers, 20 AD+PD, level 3, 32551 terms): every
-    term on the GPU; A(l) against the oracle's stored full sums; sampled
-    terms of every level against the oracle one by one (FP32 terms within
-    fp32_term_tol, the FP64 dominant term within 1e-12)."""
+    term on the GPU against the oracle's stored per-term values (FP32 terms
+    within fp32_term_tol, the FP64 dominant term within 1e-12), every T_u
+    against the stored level sums within 2e-5 T_u plus the level's summed
+    term bounds, every T_u against math.fsum of the same GPU X_t at 1e-12,
+    and A(l) against the stored sums at 1e-6."""
     print(f"config{cfg} full size", flush=True)
     c = W.config(cfg)
     res, x, pat, _ = run_gpu(c, c.level)
     assert res["n_terms"] == {3: 1771, 5: 32551}[cfg]
     assert np.all(x >= 0)
     assert all(res["A"][u] <= res["A"][u + 1] + 1e-12 for u in range(c.level))
-    gold = np.loadtxt(os.path.join(GOLD, f"config{cfg}_oracle.txt"))
+    gold_a, gold_t, gold_x = _golden(cfg)
+    pc.check_against_golden(res["T"], x, pat, gold_t, gold_x, network.slot_split(c), degenerate=False)
     for u in range(c.level + 1):
-        assert abs(res["A"][u] - gold[u]) <= 1e-6 * gold[u], (u, res["A"][u], gold[u])
+        assert abs(res["A"][u] - gold_a[u]) <= 1e-6 * gold_a[u], (u, res["A"][u], gold_a[u])
+    # a few terms of every level recomputed by the oracle now (the stored file
+    # is the oracle's)
     net = network.KetNetwork(c, diagonal=True)
     sp = network.slot_split(c)
     w = terms_weights(c)
-    for j in _sample_terms(pat, w, np.random.default_rng(cfg), 4):
+    for j in _sample_terms(pat, w, np.random.default_rng(cfg), 2):
         term = tuple(int(v) for v in pat[j])
         ref, _ = network.term_value(net, sp, term)
-        tol = 1e-12 * ref if j == 0 else fp32_term_tol(sp, term, ref)
-        print(f"term {j} gpu {x[j]:.6e} oracle {ref:.6e} err {abs(x[j] - ref):.2e} tol {tol:.2e}", flush=True)
-        assert abs(x[j] - ref) <= tol + 1e-300, (j, x[j], ref, tol)
+        assert abs(ref - gold_x[j]) <= 1e-13 * ref + 1e-300, (j, ref, gold_x[j])
 
 
 def terms_weights(c):
@@ -292,6 +279,10 @@ def test_packed_uneven_batch_against_oracle(torch):
         pat, w = terms[i].get()
         assert r["n_terms"] == terms[i].n
         assert np.all(x >= 0)
+        lv = (pat != 0).sum(axis=1)
+        for u in range(r["level"] + 1):     # FP64 level sums of the same X_t
+            fs = math.fsum(float(v) for v in x[lv == u])
+            assert abs(r["T"][u] - fs) <= 1e-12 * fs + 1e-300, (c.name, u, r["T"][u], fs)
         assert all(r["A"][u] <= r["A"][u + 1] + 1e-12 for u in range(r["level"]))
         net = network.KetNetwork(c, diagonal=True)
         sp = network.slot_split(c)
@@ -666,9 +657,19 @@ def test_factored_two_block_circuits_against_oracle(torch, seed, kind):
     print(f"factored two blocks {seed} {kind}", flush=True)
     c = two_blocks(seed, kind=kind)
     A, _ = tn.FactoredEstimate(c, 4).run()
-    ref = estimate.estimate(c, 4, "network")["A"]
+    r = estimate.estimate(c, 4, "network")
+    ref = r["A"]
     assert abs(A[0] - ref[0]) <= 1e-12 * ref[0]
-    for u in range(5):   # FP32 corrections: the 1e-6 bar of the level sums
+    # each level's sum T_u = A(u) - A(u-1) within 2e-5 T_u plus the summed FP32
+    # bounds of its terms (and the FP64 rounding of the differences)
+    pat = np.array(r["terms"])
+    tol = pc.term_tols(network.slot_split(c), pat, r["X"])
+    lv = (pat != 0).sum(axis=1)
+    for u in range(1, 5):
+        got, want = A[u] - A[u - 1], ref[u] - ref[u - 1]
+        bound = 2e-5 * abs(r["T"][u]) + tol[lv == u].sum() + 4e-16 * ref[u]
+        assert abs(got - want) <= bound, (u, got, want, bound)
+    for u in range(5):   # and the 1e-6 bar of the level sums
         assert abs(A[u] - ref[u]) <= 1e-6 * ref[u], (u, A[u], ref[u])
 
 
@@ -749,6 +750,9 @@ def test_pipelined_estimates_equal_sequential_runs(torch):
             assert ex.collect(prev)[0]["A"] == ref["A"]
             prev = t
         t2 = ex.submit()
+        other = torch.cuda.Stream()
+        with pytest.raises(tn.TNError):
+            ex.submit(other)                  # outstanding estimates on another stream
         with pytest.raises(tn.TNError):
             ex.submit()                       # a third outstanding estimate
         with pytest.raises(tn.TNError):

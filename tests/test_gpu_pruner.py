@@ -1,12 +1,19 @@
 """GPU tests of the learned pruning (a policy on top of Algorithm 1):
 network kernels against the FP64 reference network, and what the trained
 network gains over pruning by the rigorous per-term bound."""
+import math
+import os
+
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import mlp as omlp
+from oracle import network
 from paper_2211_17028_amd import pruner, tn
+from tests import parity_checks as pc
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -57,10 +64,13 @@ def test_learned_pruning_beats_the_bound_policy(torch):
     """Train on the term values of configs 2-4 (config 4: 16 of its circuits),
     then prune the level-2/3 candidates of config 5 (15x15 grid, level 3,
     held out).  Thresholds of both policies come from the same training
-    budget.  The network's pruned estimate never exceeds the full one (terms
-    are non-negative) and its error stays within 1e-6; at the network's kept
-    count, ranking by the rigorous per-term bound drops more mass, and the
-    bound ranking needs more terms to reach the network's error."""
+    budget.  The pruned run drops exactly the rejected candidates (their
+    values are 0, every other term matches the oracle's stored value), so the
+    pruned estimate is the oracle's full sum minus the dropped values; its
+    error stays within the training budget (1e-7 of the estimate), which is
+    below the candidates' whole mass; at the network's kept count, ranking by
+    the rigorous per-term bound drops more mass, and the bound ranking needs
+    more terms to reach the network's error."""
     print("pruner training", flush=True)
     data = [pruner.training_data(W.config(2)), pruner.training_data(W.config(3))]
     for c in W.config(4)[:16]:
@@ -82,9 +92,40 @@ def test_learned_pruning_beats_the_bound_policy(torch):
     print(f"full {a_full:.12f}; mlp kept {rm['kept']}/{rm['candidates']} err {err_m:.3e}; "
           f"bound kept {rb['kept']}/{rb['candidates']} err {err_b:.3e}", flush=True)
     assert err_m >= -1e-12 and err_b >= -1e-12
-    assert err_m <= 1e-6 * a_full
-    # matched kept count: the bound policy keeps the same number of top-ranked terms
+    # what the pruned run computed: dropped candidates exactly 0, every other
+    # term within its FP32 bound of the oracle's stored value, level sums equal
+    # to math.fsum of its own values
+    gold_a = np.loadtxt(os.path.join(GOLD, "config5_oracle.txt"))
+    gold_x = np.load(os.path.join(GOLD, "config5_terms.npy"))
     cand, live = pruner.candidate_mask(terms)
+    ci = np.flatnonzero(cand)
+    dropped = ci[rm["keep"] == 0]
+    kept = np.setdiff1d(np.flatnonzero(live), dropped)
+    xp = rm["x"]
+    assert np.all(xp[dropped] == 0.0)
+    pat, _ = terms.get()
+    tol = pc.term_tols(network.slot_split(c5), pat, gold_x)
+    assert np.all(np.abs(xp[kept] - gold_x[kept]) <= tol[kept])
+    lv = (pat != 0).sum(axis=1)
+    for u in range(c5.level + 1):
+        fs = math.fsum(float(v) for v in xp[lv == u])
+        assert abs(rm["result"]["T"][u] - fs) <= 1e-12 * fs + 1e-300, (u, rm["result"]["T"][u], fs)
+    # full - pruned = the dropped terms' values: the pruned estimate equals the
+    # oracle's full sum minus its dropped terms, plus the measured FP32
+    # differences of the kept terms, to 1e-12
+    d_mass = math.fsum(float(v) for v in gold_x[dropped])
+    diff_kept = math.fsum(float(v) for v in (xp[kept] - gold_x[kept]))
+    a_pruned = rm["result"]["A"][-1]
+    assert abs(a_pruned - (gold_a[-1] - d_mass) - diff_kept) <= 1e-12 * gold_a[-1], \
+        (a_pruned, gold_a[-1], d_mass, diff_kept)
+    # the pruning error stays within the training budget (1e-7 of the
+    # estimate), far below the candidates' whole mass (pruning them all fails)
+    c_mass = math.fsum(float(v) for v in gold_x[ci])
+    err_gold = gold_a[-1] - a_pruned
+    print(f"dropped mass {d_mass:.3e} of the candidates' {c_mass:.3e}; error {err_gold:.3e}", flush=True)
+    assert err_gold <= 1e-7 * gold_a[-1] < c_mass
+    assert err_gold <= 0.5 * c_mass
+    # matched kept count: the bound policy keeps the same number of top-ranked terms
     n1 = 1 + 3 * c5.n_noises
     x1 = x[:n1]
     f5 = tn.tn_terms_features(plan, terms, x1)[cand]

@@ -99,6 +99,41 @@ def test_error_codes_are_forced_from_the_host():
     assert "out of range" in tn.lib().tn_last_error().decode()
 
 
+def test_workspace_sizes_and_boundary_errors_without_a_device():
+    """tn_plan_workspace's minimum (terms in ranges of one) lies below the
+    one-schedule size; tn_estimate refuses a workspace below the minimum with
+    TN_ENOMEM and tn_contract_batch one below its range's schedule, both before
+    any device call (the pointers here are not device memory: none is
+    touched); malformed arguments give TN_EINVAL."""
+    c = W.config(1, level=2)
+    plan = tn.tn_plan_build(c, 2)
+    terms = tn.tn_terms_enumerate(plan, 2)
+    mn, full = tn.tn_plan_workspace([plan], [terms])
+    assert 0 < mn < full
+    L = tn.lib()
+    P, T = tn._handles([plan]), tn._handles([terms])
+    fake = ctypes.c_void_p(4096)
+    res = (tn.tn_result * 1)()
+
+    assert L.tn_estimate(1, P, T, fake, mn - 1, None, res) == tn.TN_ENOMEM
+    assert "minimum" in L.tn_last_error().decode()
+    assert L.tn_estimate(1, P, T, None, full, None, res) == tn.TN_EINVAL
+    assert L.tn_estimate(1, P, T, fake, 0, None, res) == tn.TN_EINVAL
+    assert L.tn_estimate(1, P, T, fake, full, None, None) == tn.TN_EINVAL
+    amp = ctypes.c_void_p(8192)
+    assert L.tn_contract_batch(1, P, T, 0, 10, amp, fake, 1024, None) == tn.TN_ENOMEM
+    assert L.tn_contract_batch(1, P, T, 0, 10, None, fake, full, None) == tn.TN_EINVAL
+    assert L.tn_contract_batch(1, P, T, 0, 10, amp, fake, 0, None) == tn.TN_EINVAL
+    assert L.tn_contract_batch(1, P, T, 0, 10, amp, None, full, None) == tn.TN_EINVAL
+    assert L.tn_contract_batch(1, P, T, 60, 10, amp, fake, full, None) == tn.TN_EINVAL
+    assert L.tn_contract_batch(1, P, T, -1, 10, amp, fake, full, None) == tn.TN_EINVAL
+    assert L.tn_contract_batch(1, P, T, 5, 0, amp, fake, full, None) == tn.TN_OK
+    assert L.tn_plan_workspace(1, P, T, None, None) == tn.TN_EINVAL
+    # full_bytes is the size of the one schedule tn_exec_prepare builds
+    desc, _ = tn.tn_exec_describe_only([plan], [terms])
+    assert desc["const_bytes"] + desc["work_bytes"] == full
+
+
 def test_level_above_noise_count_is_clamped():
     c = W.tiny_random_circuit(np.random.default_rng(5), 3, 8, 2, noise="adpd", level=5)
     plan = tn.tn_plan_build(c, 5)
