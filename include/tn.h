@@ -147,6 +147,9 @@ typedef struct {
                                 0 = with one plan, jobs with at most a quarter of the flops
                                 of their tree level's main tile shape take that shape and
                                 join its launch */
+    int32_t all_tiles;       /* 1 = matrix-core steps keep their tile launches at every tree
+                                level; 0 = a FP32 level with under 32 MFLOP of work runs all
+                                its steps in its one small-step launch */
 } tn_exec_opts;
 
 /* Accumulated per-kernel timing of the runs since the last reset (needs

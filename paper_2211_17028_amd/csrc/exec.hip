@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <numeric>
 #include <climits>
 #include <condition_variable>
@@ -183,9 +184,14 @@ struct tn_exec_s {
     std::vector<tn::Launch> launches;       // FP32 batched launches, in order (main stream)
     std::vector<tn::Launch> launches64;     // FP64 dominant-term pass (side stream)
     std::vector<tn::Launch> plain_launches; // PLAIN mode per-term body
+    std::vector<tn::Launch> launches_const; // slot-free steps: run once per binding (and upload)
     std::vector<tn::Launch> tail;           // finalize + level sums
     // packed circuits: the tail runs as one finalize and one level-sum launch
     bool multi_tail = false;
+    // circuits of at most kTailMaxTerms terms: finalize + level sums as one
+    // launch, one block per circuit
+    bool fused_tail = false;
+    tn::Ref tail_jobs;
     tn::Ref fin_args, fin_block0, ls_jobs;
     int64_t fin_blocks = 0;
     int n_ls_jobs = 0;
@@ -232,7 +238,8 @@ struct NodeInfo {
     std::vector<u128> keys;    // sorted distinct instance keys
     Ref buf;                   // symbolic: Ref{R_NODE, gid}
     int gid = -1;              // node id in the builder's node table
-    int level = 0;             // 0 for leaves, else 1 + max over the operands
+    int level = 0;             // 0 for leaves; else 1 + max over the operands, where a slot-free
+                               // operand computed at prepare counts as 0 (see fold_const)
     int64_t bytes = 0;
     bool leaf = true;
 };
@@ -272,6 +279,10 @@ constexpr double kSmallJobShare = 0.25;
 // One launch in tile-model units (the 25-qubit workload's 512-tile 128 x 64
 // launch of k = 8 models at 1.0e8 and runs 15 us; a launch costs about 5 us).
 constexpr double kLaunchCost = 3.5e7;
+// A FP32 tree level with less work than this (summed over its steps) runs all
+// its steps in its small-step launch: a grouped tile launch of its own costs
+// more than the tiles save (a dependent launch costs about 10 us end to end).
+constexpr double kSmallLevelFlops = 32.0 * 1024 * 1024;
 
 // Long inner sums of small steps: one block per output element when that is
 // the shorter chain of dependent loads (a thread-per-output sum runs k / 4
@@ -287,6 +298,7 @@ static bool split_by_block(int k_log, int64_t outs) {
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
     Ref a, b, c, oa, ob;
+    int fp64 = 0;              // complex128 job (dominant-term pass) in a launch of either precision
     int64_t n_inst = 0;
     int m_log = 0, n_log = 0, k_log = 0, split = 0, rpt_log = 0;
     int8_t a_row[32] = {}, a_k[32] = {}, b_k[32] = {}, b_col[32] = {};
@@ -329,12 +341,23 @@ struct Builder {
     Arena work;                // FP32 batch (main stream)
     Arena work2;               // FP64 dominant-term pass (side stream, runs concurrently)
     bool grouping = true;      // small steps of one tree level share one launch
+    // Slot-free intermediates (no noise slot below them) are the same for every
+    // term and every estimate: with fold_const their steps go to const32 /
+    // const64 (run once when the schedule is bound), the ones the per-estimate
+    // steps read are kept in the constant region, and the per-estimate tree
+    // levels start above them.
+    bool fold_const = false;
+    std::vector<StepRec>* const32 = nullptr;
+    std::vector<StepRec>* const64 = nullptr;
     bool quantize_tiles = true;  // tile model: whole rounds over the CUs (one circuit)
     int max_ksplit = kSplitDefaultMax;  // largest split of a tile job's inner sum (1 = none)
     bool ksplit_user = false;            // max_ksplit set by the caller (applies to every job)
     // FP32 tile shape imposed per tree level on jobs of at most the given
     // flops (the small jobs join the level's main matrix-core launch)
     const std::map<int, std::pair<int, double>>* level_tile = nullptr;
+    // FP32 tree levels with little work: every step runs in the level's
+    // small-step launch (one launch instead of one per tile shape plus one)
+    const std::set<int>* small_levels = nullptr;
     std::vector<Ref> node_ref;         // concrete buffer of every node (once placed)
     std::vector<char> node_leaf;
     std::vector<int64_t> node_bytes;
@@ -743,7 +766,24 @@ struct Builder {
             NodeInfo& C = nodes[L + j];
             StepRec st;
             st.plan = plan_index;
-            st.level = C.level = 1 + std::max(A.level, B.level);
+            const bool folding = fold_const && mode != 2;
+            const bool folded = folding && C.mask == 0;
+            if (!folding || folded) st.level = C.level = 1 + std::max(A.level, B.level);
+            else st.level = C.level = 1 + std::max(A.mask ? A.level : 0, B.mask ? B.level : 0);
+            // a folded node read by a per-estimate step (or a folded cluster
+            // root) keeps its value for the whole schedule
+            const bool folded_out = folded && (j + 1 == cl.path.size() || nodes[parent[L + j]].mask != 0);
+            auto push_step = [&](StepRec&& sr) {
+                if (!folded) {
+                    steps->push_back(std::move(sr));
+                    return;
+                }
+                if (folded_out && !sr.has_fixed) {
+                    sr.has_fixed = true;
+                    sr.c_fixed = Ref{R_CONST, ex->cbuf.reserve(sr.c_bytes)};
+                }
+                (fp64 ? const64 : const32)->push_back(std::move(sr));
+            };
             C.gid = add_node(Ref{}, false, 0);
             st.a_node = A.gid;
             st.b_node = B.gid;
@@ -905,14 +945,15 @@ struct Builder {
             // their shape would fill a tile: a launch of their own costs more
             const bool long_sum = fp64 && rk > 8 && std::min(FA.size(), FB.size()) >= 5 &&
                                   step_flops >= kMfmaMinFlops;
-            const bool to_tile = (big && step_flops >= kTileMinFlops) || heavy || long_sum;
+            bool to_tile = (big && step_flops >= kTileMinFlops) || heavy || long_sum;
+            if (!fp64 && small_levels && small_levels->count(st.level)) to_tile = false;
             if (grouping && mode != 2 && to_tile) {
                 const int saved_split = max_ksplit;
                 if (long_sum && !big && !heavy && !ksplit_user) max_ksplit = kSplitLongMax;
                 plan_mfma_job(st, A, B, C, K, Bt, FA, FB, ninst, nbatch, posin, by_pos, slice_vec, fp64);
                 max_ksplit = saved_split;
                 node_bytes[C.gid] = C.bytes;
-                steps->push_back(std::move(st));
+                push_step(std::move(st));
                 continue;
             }
             if (grouping && mode != 2) {
@@ -953,6 +994,7 @@ struct Builder {
                 C.bytes = ninst * (int64_t(esz) << C.legs.size());
                 C.buf = Ref{R_NODE, C.gid};
                 GroupJob& jb = st.job;
+                jb.fp64 = fp64;
                 jb.a = R.buf;
                 jb.b = Q.buf;
                 jb.c = C.buf;
@@ -983,7 +1025,7 @@ struct Builder {
                 st.grouped = true;
                 st.c_bytes = C.bytes;
                 node_bytes[C.gid] = C.bytes;
-                steps->push_back(std::move(st));
+                push_step(std::move(st));
                 continue;
             }
             // Gathered operands: an FP32 step that runs on an MFMA tile and would
@@ -1139,7 +1181,7 @@ struct Builder {
             }
             st.c_bytes = C.bytes;
             node_bytes[C.gid] = C.bytes;
-            steps->push_back(std::move(st));
+            push_step(std::move(st));
         }
         return root_out;
     }
@@ -1259,11 +1301,9 @@ struct Builder {
                 if (split_bytes > 0) out->push_back(std::move(R));
             }
             if (!G.hjobs.empty()) {
-                if (G.blocks >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 blocks");
                 G.n_jobs = (int)G.hjobs.size();
-                G.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)G.n_jobs * (int64_t)sizeof(GettJob))};
                 G.plan = steps[grp[0]].plan;
-                out->push_back(std::move(G));
+                out->push_back(std::move(G));   // job records and block table: reserve_group_tables
             }
             if (by_level)
                 for (size_t q = first_launch; q < out->size(); ++q) (*out)[q].level = (int)gi;
@@ -1272,7 +1312,7 @@ struct Builder {
                 for (size_t q = 0; q < st.temp_ids.size(); ++q)
                     wk.release(temp_ref[st.temp_ids[q]].off, st.temp_bytes[q]);
                 for (int nd : {st.a_node, st.b_node})
-                    if (!node_leaf[nd]) wk.release(node_ref[nd].off, node_bytes[nd]);
+                    if (!node_leaf[nd] && node_ref[nd].region == wreg) wk.release(node_ref[nd].off, node_bytes[nd]);
             }
         }
     }
@@ -1302,12 +1342,43 @@ struct TermRange {
     int64_t lo = 0, hi = -1;
 };
 
+// When the dominant-term pass has only small steps (no tile launches), its
+// jobs join the FP32 chain's small-step launch of the same tree level (or,
+// where the FP32 chain has none, run as their own launch in level order on
+// the main stream): no side stream, no fork / join per estimate, and half
+// the launches.  A level's FP32 and FP64 jobs are independent (separate work
+// regions).
+static void merge_fp64_chain(tn_exec_s* ex) {
+    if (ex->launches64.empty() || ex->opts.mode != TN_MODE_BATCHED) return;
+    for (const Launch& L : ex->launches64)
+        if (L.kind != L_GROUP || L.level < 0) return;
+    for (Launch& L64 : ex->launches64) {
+        auto it = std::find_if(ex->launches.begin(), ex->launches.end(),
+                               [&](const Launch& L) { return L.kind == L_GROUP && L.level == L64.level; });
+        if (it != ex->launches.end()) {
+            Launch& G = *it;
+            G.hjobs.insert(G.hjobs.end(), L64.hjobs.begin(), L64.hjobs.end());
+            G.n_jobs = (int)G.hjobs.size();
+            G.blocks += L64.blocks;
+            G.flops += L64.flops;
+            G.bytes += L64.bytes;
+            G.kclass = K_GROUPMIX;
+        } else {
+            auto pos = std::find_if(ex->launches.begin(), ex->launches.end(),
+                                    [&](const Launch& L) { return L.level > L64.level; });
+            ex->launches.insert(pos, L64);
+        }
+    }
+    ex->launches64.clear();
+}
+
 static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms,
                            const std::map<int, std::pair<int, double>>* level_tile = nullptr,
-                           TermRange range = TermRange{}) {
+                           TermRange range = TermRange{}, const std::set<int>* small_levels = nullptr) {
     Builder bw;
     bw.ex = ex;
     bw.level_tile = level_tile;
+    bw.small_levels = small_levels;
     bw.grouping = ex->opts.no_group == 0;
     bw.quantize_tiles = n == 1;
     if (ex->opts.max_ksplit > 0) {
@@ -1315,7 +1386,9 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         bw.ksplit_user = true;
     }
     const bool plain = ex->opts.mode == TN_MODE_PLAIN;
-    std::vector<StepRec> steps32, steps64;
+    std::vector<StepRec> steps32, steps64, const32, const64;
+    bw.const32 = &const32;
+    bw.const64 = &const64;
     for (int pi = 0; pi < n; ++pi) {
         const Plan& P = *reinterpret_cast<const Plan*>(plans[pi]);
         const Terms& T = *reinterpret_cast<const Terms*>(terms[pi]);
@@ -1340,6 +1413,8 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
             std::all_of(T.pat.begin(), T.pat.begin() + P.n_noise, [](int8_t c) { return c == 0; }))
             pe.zero_term = 0;
         const int ncl = (int)P.clusters.size();
+        // a doubled network has no slots: all of it is the value being computed
+        bw.fold_const = !plain && !P.doubled;
         // one live term, the all-dominant one, recomputed in FP64 (a level-0 term
         // set, a doubled network): the FP32 chain would compute a value nothing reads
         pe.fp32_skipped = !plain && ex->opts.fp64_level0 && pe.zero_term == 0 && pe.n_live == 1;
@@ -1457,9 +1532,27 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
         ex->tail.push_back(ls);
         ex->plans.push_back(std::move(pe));
     }
+    // the slot-free steps first (they run once, when the schedule is bound):
+    // their work buffers are released before the per-estimate steps are placed
+    bw.emit(const32, 0, true, &ex->launches_const);
+    bw.emit(const64, 1, true, &ex->launches_const);
+    for (auto& L : ex->launches_const) L.level = -1;
     bw.emit(steps32, 0, true, &ex->launches);
     bw.emit(steps64, 1, true, &ex->launches64);
-    if (n > 1) {
+    merge_fp64_chain(ex);
+    for (auto* list : {&ex->launches_const, &ex->launches, &ex->launches64})
+        for (auto& L : *list)
+            if (L.kind == L_GROUP) {
+                if (L.blocks >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 blocks");
+                L.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)L.n_jobs * (int64_t)sizeof(GettJob))};
+                L.table = Ref{R_CONST, ex->cbuf.reserve(L.blocks * 4)};
+            }
+    int64_t max_terms = 0;
+    for (const PlanExec& pe : ex->plans) max_terms = std::max(max_terms, pe.n_terms);
+    if (max_terms <= kTailMaxTerms) {
+        ex->fused_tail = true;
+        ex->tail_jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(TailJob))};
+    } else if (n > 1) {
         ex->multi_tail = true;
         ex->fin_args = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(FinalizeArgs))};
         ex->fin_block0 = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * 8)};
@@ -1498,6 +1591,7 @@ static void bind(tn_exec_s* ex) {
             L.p.table = (const int32_t*)resolve(ex, L.table);
         } else if (L.kind == L_GROUP) {
             GettJob* d = (GettJob*)(ex->cbuf.bytes.data() + L.jobs.off);
+            int32_t* tab = (int32_t*)(ex->cbuf.bytes.data() + L.table.off);
             int64_t b0 = 0;
             for (int i = 0; i < L.n_jobs; ++i) {
                 const GroupJob& h = L.hjobs[i];
@@ -1518,7 +1612,9 @@ static void bind(tn_exec_s* ex) {
                 std::memcpy(j.a_k, h.a_k, 32);
                 std::memcpy(j.b_k, h.b_k, 32);
                 std::memcpy(j.b_col, h.b_col, 32);
-                b0 += gett_job_blocks(j);
+                const int64_t nb = gett_job_blocks(j);
+                for (int64_t q = 0; q < nb; ++q) tab[b0 + q] = (int32_t)((uint32_t)i | (h.fp64 ? 0x80000000u : 0u));
+                b0 += nb;
                 std::memcpy(d + i, &j, sizeof(GettJob));
             }
         } else if (L.kind == L_MGROUP) {
@@ -1553,6 +1649,7 @@ static void bind(tn_exec_s* ex) {
             L.sf.pattern = (const int8_t*)resolve(ex, L.sf_pattern);
         }
     };
+    for (auto& L : ex->launches_const) fix(L);
     for (auto& L : ex->launches) fix(L);
     for (auto& L : ex->launches64) fix(L);
     for (auto& L : ex->plain_launches) fix(L);
@@ -1582,8 +1679,25 @@ static void bind(tn_exec_s* ex) {
     }
 }
 
-// packed circuits: the per-circuit finalize / level-sum records as two launches
+// packed circuits: the per-circuit finalize / level-sum records as two
+// launches, or the per-circuit records of the one-launch tail
 static void bind_multi_tail(tn_exec_s* ex) {
+    if (ex->fused_tail) {
+        TailJob* tj = (TailJob*)(ex->cbuf.bytes.data() + ex->tail_jobs.off);
+        int nt = 0;
+        for (auto& L : ex->tail) {
+            if (L.kind == L_FINALIZE) {
+                std::memset(tj + nt, 0, sizeof(TailJob));
+                tj[nt].f = L.f;
+            } else if (L.kind == L_LEVELSUM) {
+                tj[nt].starts = (const int64_t*)resolve(ex, L.starts);
+                tj[nt].sums = (double*)resolve(ex, L.sums);
+                tj[nt].n_levels = L.n_levels;
+                ++nt;
+            }
+        }
+        return;
+    }
     if (!ex->multi_tail) return;
     FinalizeArgs* fa = (FinalizeArgs*)(ex->cbuf.bytes.data() + ex->fin_args.off);
     int64_t* b0 = (int64_t*)(ex->cbuf.bytes.data() + ex->fin_block0.off);
@@ -1622,7 +1736,7 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
         else launch_permute_c64(L.p, s);
         break;
     case L_GROUP:
-        launch_gett_group((const GettJob*)resolve(ex, L.jobs), L.n_jobs, L.blocks, L.fp64, s);
+        launch_gett_group((const GettJob*)resolve(ex, L.jobs), (const int32_t*)resolve(ex, L.table), L.blocks, s);
         break;
     case L_MGROUP:
         if (L.fp64)
@@ -1650,6 +1764,12 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
 }
 
 static void run_tail(tn_exec_s* ex, hipStream_t s);
+
+// The slot-free steps, on one stream (FP32 and FP64 chains one after the other).
+static void run_const(tn_exec_s* ex, hipStream_t s) {
+    for (auto& L : ex->launches_const) enqueue(ex, L, s);
+    HIPCHK(hipGetLastError());
+}
 
 static void issue_chain(tn_exec_s* ex, std::vector<Launch>& list, hipStream_t st) {
     for (auto& L : list) {
@@ -1810,7 +1930,9 @@ static void run_tail(tn_exec_s* ex, hipStream_t s) {
             }
         }
     }
-    if (ex->multi_tail) {
+    if (ex->fused_tail) {
+        launch_tail((const TailJob*)resolve(ex, ex->tail_jobs), (int)ex->plans.size(), s);
+    } else if (ex->multi_tail) {
         const int nf = (int)(ex->tail.size() / 2);
         launch_finalize_multi((const FinalizeArgs*)resolve(ex, ex->fin_args), (const int64_t*)resolve(ex, ex->fin_block0),
                               nf, ex->fin_blocks, s);
@@ -1892,7 +2014,8 @@ static std::string describe_exec(const tn_exec_s* ex) {
     os.precision(17);
     os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
        << ",\"work1_bytes\":" << ex->work1_bytes
-       << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms << ",\"launches\":[";
+       << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms
+       << ",\"fused_tail\":" << (ex->fused_tail ? 1 : 0) << ",\"launches\":[";
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
         os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
@@ -1960,7 +2083,8 @@ static std::string describe_exec(const tn_exec_s* ex) {
             os << ",\"kernel\":\"" << kernel_name(L.kclass) << "\",\"blocks\":" << L.blocks << ",\"jobs\":[";
             for (int i = 0; i < L.n_jobs; ++i) {
                 const GroupJob& h = L.hjobs[i];
-                os << (i ? "," : "") << "{\"a\":[" << h.a.region << "," << h.a.off << "],\"b\":[" << h.b.region
+                os << (i ? "," : "") << "{\"fp64\":" << h.fp64 << ",\"a\":[" << h.a.region << "," << h.a.off
+                   << "],\"b\":[" << h.b.region
                    << "," << h.b.off << "],\"c\":[" << h.c.region << "," << h.c.off << "],\"oa\":[" << h.oa.region
                    << "," << h.oa.off << "],\"ob\":[" << h.ob.region << "," << h.ob.off << "],\"n_inst\":"
                    << h.n_inst << ",\"m_log\":" << h.m_log << ",\"n_log\":" << h.n_log << ",\"k_log\":" << h.k_log
@@ -1996,6 +2120,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
         }
         os << ",\"flops\":" << L.flops << ",\"bytes\":" << L.bytes << "}";
     };
+    for (auto& L : ex->launches_const) emit(L, "const");
     for (auto& L : ex->launches64) emit(L, "batch64");
     for (auto& L : ex->launches) emit(L, "batch");
     for (auto& L : ex->plain_launches) emit(L, "plain");
@@ -2134,30 +2259,48 @@ static std::unique_ptr<tn_exec_s> build_exec(int n, const tn_plan* plans, const 
         ex->opts.use_graph = 0;
         if (n != 1) fail(TN_EINVAL, "PLAIN mode runs one plan at a time");
     }
-    if (n == 1 && ex->opts.mode != TN_MODE_PLAIN && !ex->opts.no_group && !ex->opts.mixed_shapes) {
-        // A level whose matrix-core jobs chose different tile shapes runs
-        // one launch per shape, one after the other.  The schedule is
-        // planned again with the shape carrying most of the level's flops
-        // imposed on the level's small jobs (each at most a quarter of
-        // that shape's flops), which then join its launch; large jobs keep
-        // their own shape (a forced shape costs them more than a launch).
-        // Packed circuits share every level's launches already and keep
-        // each job's shape (measured slower with the merge).
+    if (ex->opts.mode != TN_MODE_PLAIN && !ex->opts.no_group) {
+        // The schedule is planned once as a probe, then again with what the
+        // probe shows:
+        //  - FP32 levels with little work run every step in their small-step
+        //    launch (kSmallLevelFlops);
+        //  - with one plan, a level whose matrix-core jobs chose different
+        //    tile shapes runs one launch per shape, one after the other: the
+        //    shape carrying most of the level's flops is imposed on the
+        //    level's small jobs (each at most a quarter of that shape's
+        //    flops), which then join its launch; large jobs keep their own
+        //    shape (a forced shape costs them more than a launch).  Packed
+        //    circuits share every level's launches already and keep each
+        //    job's shape (measured slower with the merge).
         tn_exec_s probe;
         probe.opts = ex->opts;
         build_schedule(&probe, n, plans, terms, nullptr, range);
         std::map<int, std::map<int, double>> flops;   // level -> tile -> flops
-        for (const Launch& L : probe.launches)
-            if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) flops[L.level][L.mtile] += L.flops;
-        std::map<int, std::pair<int, double>> level_tile;
-        for (auto& kv : flops) {
-            if (kv.second.size() < 2) continue;
-            auto top = std::max_element(kv.second.begin(), kv.second.end(),
-                                        [](const std::pair<const int, double>& a,
-                                           const std::pair<const int, double>& b) { return a.second < b.second; });
-            level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
+        std::map<int, double> level_flops;            // level -> FP32 flops
+        std::set<int> tiled;
+        for (const Launch& L : probe.launches) {
+            if (L.fp64 || L.level < 0) continue;
+            level_flops[L.level] += L.flops;
+            if (L.kind == L_MGROUP) {
+                flops[L.level][L.mtile] += L.flops;
+                tiled.insert(L.level);
+            }
         }
-        build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile, range);
+        std::set<int> small;
+        if (!ex->opts.all_tiles)
+            for (int lv : tiled)
+                if (level_flops[lv] < kSmallLevelFlops) small.insert(lv);
+        std::map<int, std::pair<int, double>> level_tile;
+        if (n == 1 && !ex->opts.mixed_shapes)
+            for (auto& kv : flops) {
+                if (kv.second.size() < 2 || small.count(kv.first)) continue;
+                auto top = std::max_element(kv.second.begin(), kv.second.end(),
+                                            [](const std::pair<const int, double>& a,
+                                               const std::pair<const int, double>& b) { return a.second < b.second; });
+                level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
+            }
+        build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile, range,
+                       small.empty() ? nullptr : &small);
     } else {
         build_schedule(ex.get(), n, plans, terms, nullptr, range);
     }
@@ -2201,6 +2344,7 @@ static void bind_exec(tn_exec_s* ex, void* d_ws, size_t ws_bytes, hipStream_t st
                 }
     HIPCHK(hipMemcpyAsync(ex->base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice,
                           ex->stream));
+    run_const(ex, ex->stream);
     if (ex->opts.tune) autotune(ex);
     HIPCHK(hipEventCreate(&ex->ev0));
     HIPCHK(hipEventCreate(&ex->ev1));
@@ -2333,6 +2477,7 @@ static CachedExec* cache_insert(int kind, int n, const tn_plan* plans, const tn_
 static void cache_reupload(CachedExec* ce, hipStream_t s) {
     if (ce->pinned_bytes)
         HIPCHK(hipMemcpyAsync(ce->ex->base, ce->pinned, ce->pinned_bytes, hipMemcpyHostToDevice, s));
+    run_const(ce->ex.get(), s);
     ce->last_stream = s;
 }
 

@@ -70,8 +70,9 @@ struct GettJob {
 };
 // blocks one job takes in a grouped launch
 int64_t gett_job_blocks(const GettJob& j);
-// One launch for all jobs; d_jobs holds n_jobs records in device memory.
-void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s);
+// One launch for all jobs of a level: block b runs job d_block_job[b] & 0x7fffffff
+// (records in device memory), in FP64 when bit 31 is set, else in FP32.
+void launch_gett_group(const GettJob* d_jobs, const int32_t* d_block_job, int64_t blocks, hipStream_t s);
 
 // Grouped FP32 matrix-core contractions.  A job is one step: slices
 // i < n_inst with C_i = A_i B_i, operands in stored order (per-bit positions as
@@ -130,6 +131,7 @@ enum KernelId {
     K_SMALL64 = 20, K_SPLITK64 = 21, K_TILED64 = 22,
     K_PERM32 = 30, K_PERM64 = 31,
     K_GROUP32 = 40, K_GROUP64 = 41, K_TILE64_GROUP = 42, K_SPLIT_REDUCE32 = 43, K_SPLIT_REDUCE64 = 44,
+    K_GROUPMIX = 45,
     K_MFMA_GROUP_BASE = 200,   // + MFMA tile id: grouped matrix-core launch
     K_GATHER_BASE = 100,   // + MFMA tile id: the gathered-operand variant
 };
@@ -176,6 +178,17 @@ struct LevelSumJob {               // one (circuit, level) block of a packed lev
     int32_t u, pad_;
 };
 void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s);
+
+// The tail of one circuit per block (circuits with at most kTailMaxTerms
+// terms): the finalize of every term and the level sums in one launch.
+constexpr int64_t kTailMaxTerms = 65536;
+struct TailJob {
+    FinalizeArgs f;
+    const int64_t* starts;         // n_levels + 1 level starts
+    double* sums;                  // n_levels (sum, comp) pairs
+    int32_t n_levels, pad_;
+};
+void launch_tail(const TailJob* d_jobs, int n_jobs, hipStream_t s);
 
 // Neumaier level sums over contiguous ranges [start[u], start[u+1]).
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,

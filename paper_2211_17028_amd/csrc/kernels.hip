@@ -746,22 +746,24 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
 //   split == 1: one block per output element (few outputs, long inner sums),
 //               partial sums reduced in FP64 through LDS.
 // ---------------------------------------------------------------------------
+struct GettSmem {
+    GettJob J;
+    int64_t ak_lo[256], bk_lo[256];
+    double red_r[256], red_i[256];
+    int64_t a_step[32], b_step[32];
+};
+
 template <typename R, typename C2>
-__global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ jobs, int n_jobs) {
-    __shared__ GettJob J;
-    __shared__ int64_t ak_lo[256], bk_lo[256];
-    __shared__ double red_r[256], red_i[256];
-    __shared__ int64_t a_step[32], b_step[32];
+__device__ __forceinline__ void gett_block(const GettJob* __restrict__ jp, GettSmem& sm) {
+    GettJob& J = sm.J;
+    int64_t* ak_lo = sm.ak_lo;
+    int64_t* bk_lo = sm.bk_lo;
+    double* red_r = sm.red_r;
+    double* red_i = sm.red_i;
+    int64_t* a_step = sm.a_step;
+    int64_t* b_step = sm.b_step;
     const int64_t bid = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = n_jobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].block0 <= bid) lo = mid;
-            else hi = mid - 1;
-        }
-        J = jobs[lo];
-    }
+    if (threadIdx.x == 0) J = *jp;
     __syncthreads();
     const int m_log = J.m_log, n_log = J.n_log, k_log = J.k_log;
     const int mn_log = m_log + n_log;
@@ -906,6 +908,19 @@ __global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ 
             out.y = si[i];
             gst(Cp + ((int64_t)i << n_log), out);
         }
+}
+
+// One launch for the small steps of one tree level: block b runs job
+// block_job[b] & 0x7fffffff, in FP64 when bit 31 is set (the dominant-term
+// pass's jobs of the same level), else in FP32.  The table is built on the
+// host, so a block finds its job with one load.
+__global__ __launch_bounds__(256) void k_gett_group(const GettJob* __restrict__ jobs,
+                                                    const int32_t* __restrict__ block_job) {
+    __shared__ GettSmem sm;
+    const uint32_t e = (uint32_t)block_job[blockIdx.x];
+    const GettJob* jp = jobs + (e & 0x7fffffffu);
+    if (e >> 31) gett_block<double, double2>(jp, sm);
+    else gett_block<float, float2>(jp, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1494,13 +1509,13 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 // X = w |amplitude|^2 (a doubled network's value is the amplitude itself:
 // X = w Re(amplitude)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) {
+__device__ __forceinline__ double finalize_term(const FinalizeArgs& f, int64_t t) {
     const int32_t li = f.live_index[t];
     if (li < 0) {
         f.x_out[t] = 0.0;
         f.amp_out[2 * t] = 0.0f;
         f.amp_out[2 * t + 1] = 0.0f;
-        return;
+        return 0.0;
     }
     double ar = f.scalar_re, ai = f.scalar_im;
     const bool hi = (t == f.zero_term);
@@ -1521,7 +1536,8 @@ __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) 
         ar = nr;
         ai = ni;
     }
-    f.x_out[t] = f.w[t] * (f.re_value ? ar : ar * ar + ai * ai);
+    const double x = f.w[t] * (f.re_value ? ar : ar * ar + ai * ai);
+    f.x_out[t] = x;
     f.amp_out[2 * t] = (float)ar;
     f.amp_out[2 * t + 1] = (float)ai;
     if (hi && f.x0_fp32_out) {
@@ -1536,6 +1552,7 @@ __device__ __forceinline__ void finalize_term(const FinalizeArgs& f, int64_t t) 
         }
         *f.x0_fp32_out = f.w[t] * (f.re_value ? br : br * br + bi * bi);
     }
+    return x;
 }
 
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
@@ -1571,16 +1588,14 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
     s = t;
 }
 
-__device__ __forceinline__ void level_sum_block(const double* x, const int64_t* starts, double* out, int u) {
-    __shared__ double ss[256];
-    __shared__ double cc[256];
-    const int64_t b = starts[u], e = starts[u + 1];
-    double s = 0.0, c = 0.0;
-    for (int64_t i = b + threadIdx.x; i < e; i += 256) neumaier_add(s, c, x[i]);
+// (sum, comp) pairs of a block's threads combined in a fixed tree (NT threads,
+// NT a power of two); thread 0 gets the block's pair.
+template <int NT>
+__device__ __forceinline__ void neumaier_block(double& s, double& c, double* ss, double* cc) {
     ss[threadIdx.x] = s;
     cc[threadIdx.x] = c;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             double s1 = ss[threadIdx.x], c1 = cc[threadIdx.x] + cc[threadIdx.x + w];
             neumaier_add(s1, c1, ss[threadIdx.x + w]);
@@ -1589,9 +1604,34 @@ __device__ __forceinline__ void level_sum_block(const double* x, const int64_t* 
         }
         __syncthreads();
     }
+    s = ss[0];
+    c = cc[0];
+    __syncthreads();
+}
+
+// Thread t adds elements b + t, b + t + 256, ... of [b, e) in that order; the
+// loads of 8 elements are issued before their adds (the adds form a chain).
+__device__ __forceinline__ void level_sum_block(const double* x, const int64_t* starts, double* out, int u) {
+    __shared__ double ss[256];
+    __shared__ double cc[256];
+    const int64_t b = starts[u], e = starts[u + 1];
+    double s = 0.0, c = 0.0;
+    constexpr int U = 8;
+    for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += 256 * U) {
+        double v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = i0 + (int64_t)q * 256;
+            v[q] = i < e ? x[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            if (i0 + (int64_t)q * 256 < e) neumaier_add(s, c, v[q]);
+    }
+    neumaier_block<256>(s, c, ss, cc);
     if (threadIdx.x == 0) {
-        out[2 * u] = ss[0] + cc[0];
-        out[2 * u + 1] = cc[0];
+        out[2 * u] = s + c;
+        out[2 * u + 1] = c;
     }
 }
 
@@ -1603,6 +1643,40 @@ __global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_
 __global__ __launch_bounds__(256) void k_level_sum_multi(const LevelSumJob* __restrict__ jobs) {
     const LevelSumJob j = jobs[blockIdx.x];
     level_sum_block(j.x, j.starts, j.out, j.u);
+}
+
+// The whole tail of one circuit in one block (one block per packed circuit):
+// every term finalized (X_t, a_t written as by k_finalize) and its level sums
+// taken in the same pass.  Level by level, thread t takes the level's terms
+// b + t, b + t + 1024, ... in that order (8 finalized with their loads in
+// flight before they are added), then the block's pairs are combined in a
+// fixed tree: deterministic.
+__global__ __launch_bounds__(1024) void k_tail(const TailJob* __restrict__ jobs) {
+    __shared__ double ss[1024];
+    __shared__ double cc[1024];
+    const TailJob& J = jobs[blockIdx.x];
+    const FinalizeArgs& f = J.f;
+    for (int u = 0; u < J.n_levels; ++u) {
+        const int64_t b = J.starts[u], e = J.starts[u + 1];
+        double s = 0.0, c = 0.0;
+        constexpr int U = 8;
+        for (int64_t t0 = b + threadIdx.x; t0 < e; t0 += 1024 * U) {
+            double v[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int64_t t = t0 + (int64_t)q * 1024;
+                v[q] = t < e ? finalize_term(f, t) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (t0 + (int64_t)q * 1024 < e) neumaier_add(s, c, v[q]);
+        }
+        neumaier_block<1024>(s, c, ss, cc);
+        if (threadIdx.x == 0) {
+            J.sums[2 * u] = s + c;
+            J.sums[2 * u + 1] = c;
+        }
+    }
 }
 
 __global__ void k_slot_fill(SlotFillArgs a) {
@@ -1672,6 +1746,7 @@ const char* kernel_name(int id) {
     case K_PERM64: return "k_permute<double2>";
     case K_GROUP32: return "k_gett_group<float>";
     case K_GROUP64: return "k_gett_group<double>";
+    case K_GROUPMIX: return "k_gett_group<mixed>";
     case K_TILE64_GROUP: return "k_tile64_group";
     case K_SPLIT_REDUCE32: return "k_split_reduce<float>";
     case K_SPLIT_REDUCE64: return "k_split_reduce<double>";
@@ -1684,8 +1759,8 @@ int kernel_class(int id) {
     if (id >= K_GATHER_BASE && id < K_GATHER_BASE + K_MFMA_TILES) return KC_MFMA;
     if (id == K_SMALL32 || id == K_SMALL64) return KC_SMALL;
     if (id == K_SPLITK32 || id == K_SPLITK64) return KC_SPLITK;
-    if (id == K_GROUP32 || id == K_GROUP64 || id == K_TILE64_GROUP || id == K_SPLIT_REDUCE32 ||
-        id == K_SPLIT_REDUCE64)
+    if (id == K_GROUP32 || id == K_GROUP64 || id == K_GROUPMIX || id == K_TILE64_GROUP ||
+        id == K_SPLIT_REDUCE32 || id == K_SPLIT_REDUCE64)
         return KC_GROUP;
     if (id >= K_MFMA_GROUP_BASE && id < K_MFMA_GROUP_BASE + K_MFMA_TILES) return KC_GROUP;
     return KC_TILED;
@@ -1720,12 +1795,9 @@ int64_t gett_job_blocks(const GettJob& j) {
     return j.split ? outs : ((outs >> j.rpt_log) + 255) / 256;
 }
 
-void launch_gett_group(const GettJob* d_jobs, int n_jobs, int64_t blocks, int fp64, hipStream_t s) {
-    if (n_jobs == 0 || blocks == 0) return;
-    if (fp64)
-        hipLaunchKernelGGL((k_gett_group<double, double2>), dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs);
-    else
-        hipLaunchKernelGGL((k_gett_group<float, float2>), dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs);
+void launch_gett_group(const GettJob* d_jobs, const int32_t* d_block_job, int64_t blocks, hipStream_t s) {
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(k_gett_group, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_block_job);
 }
 
 static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s, bool gather) {
@@ -1830,6 +1902,11 @@ void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_level_sum, dim3(n_levels), dim3(256), 0, s, x, starts, out);
+}
+
+void launch_tail(const TailJob* d_jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs == 0) return;
+    hipLaunchKernelGGL(k_tail, dim3(n_jobs), dim3(1024), 0, s, d_jobs);
 }
 
 void launch_slot_fill(const SlotFillArgs& a, hipStream_t s) {

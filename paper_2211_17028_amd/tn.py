@@ -60,7 +60,8 @@ class tn_prune_opts(C.Structure):
 class tn_exec_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("fp64_level0", C.c_int32),
                 ("tune", C.c_int32), ("time_kernels", C.c_int32), ("no_gather", C.c_int32),
-                ("no_group", C.c_int32), ("max_ksplit", C.c_int32), ("mixed_shapes", C.c_int32)]
+                ("no_group", C.c_int32), ("max_ksplit", C.c_int32), ("mixed_shapes", C.c_int32),
+                ("all_tiles", C.c_int32)]
 
 
 class tn_kernel_stat(C.Structure):
@@ -410,10 +411,10 @@ def _stream_ptr(stream):
 
 
 def exec_opts(mode=TN_MODE_BATCHED, use_graph=False, fp64_level0=True, tune=False, time_kernels=False,
-              gather=True, group=True, max_ksplit=0, one_shape_per_level=True):
+              gather=True, group=True, max_ksplit=0, one_shape_per_level=True, all_tiles=False):
     return tn_exec_opts(mode, 1 if use_graph else 0, 1 if fp64_level0 else 0, 1 if tune else 0,
                         1 if time_kernels else 0, 0 if gather else 1, 0 if group else 1, int(max_ksplit),
-                        0 if one_shape_per_level else 1)
+                        0 if one_shape_per_level else 1, 1 if all_tiles else 0)
 
 
 def tn_exec_describe_only(plans: Sequence[Plan], terms: Sequence[Terms], opts=None):

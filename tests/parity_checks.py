@@ -40,8 +40,9 @@ def fp32_term_tol(split, term, ref):
     return 2e-5 * ref + 2 * ETA32 * math.sqrt(max(ref, 0.0) * b) + ETA32 ** 2 * b
 
 
-def term_tols(split, pat, ref):
-    """fp32_term_tol of every term (the all-dominant term: 1e-12 relative)."""
+def term_tols(split, pat, ref, fp64_first=True):
+    """fp32_term_tol of every term; with fp64_first the first entry is the
+    all-dominant term, computed in FP64 (1e-12 relative)."""
     pat = np.asarray(pat, dtype=np.int64)
     ref = np.asarray(ref, dtype=np.float64)
     fac = np.array([[split[s][0][c] * np.linalg.norm(split[s][1][c], 2) ** 2 for c in range(4)]
@@ -50,17 +51,18 @@ def term_tols(split, pat, ref):
     for s in range(pat.shape[1]):
         b *= fac[s][pat[:, s]]
     tol = 2e-5 * ref + 2 * ETA32 * np.sqrt(np.maximum(ref, 0.0) * b) + ETA32 ** 2 * b
-    tol[0] = 1e-12 * ref[0]
+    if fp64_first and len(tol):
+        tol[0] = 1e-12 * ref[0]
     return tol
 
 
-def check_terms(x, ref, pat, split, degenerate):
+def check_terms(x, ref, pat, split, degenerate, fp64_first=True):
     """Every term (or, for degenerate channels, every noise-position group)
     within its FP32 bound; returns the per-term tolerances."""
     x = np.asarray(x, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     assert x.shape == ref.shape, (x.shape, ref.shape)
-    tol = term_tols(split, pat, ref)
+    tol = term_tols(split, pat, ref, fp64_first)
     if degenerate:
         keys = [tuple(np.flatnonzero(row)) for row in pat]
         groups = {}

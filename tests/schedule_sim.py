@@ -184,6 +184,10 @@ class Sim:
 
     def run(self, live_terms_per_plan=None):
         d = self.desc
+        # slot-free steps first: the library runs them once when the schedule is bound
+        for L in d["launches"]:
+            if L["phase"] == "const":
+                self.exec(L)
         batch = [L for L in d["launches"] if L["phase"] in ("batch", "batch64")]
         plain = [L for L in d["launches"] if L["phase"] == "plain"]
         tail = [L for L in d["launches"] if L["phase"] == "tail"]
@@ -211,17 +215,18 @@ class Sim:
         """One grouped launch: every job is an independent gathered contraction
         (same addressing as the gathered GEMM); jobs of one launch never write
         what another job of it reads."""
-        dt = np.complex128 if L["fp64"] else np.complex64
-        esz = np.dtype(dt).itemsize
+        def dtype_of(jb):
+            # a level's launch may hold the FP64 dominant-term pass's jobs too
+            return np.complex128 if jb.get("fp64", L["fp64"]) else np.complex64
         spans = []
         for jb in L["jobs"]:
-            spans.append(self._job_spans(jb, esz))
+            spans.append(self._job_spans(jb, np.dtype(dtype_of(jb)).itemsize))
         for i, (wi, _) in enumerate(spans):
             for j, (wj, rj) in enumerate(spans):
                 for other in ([wj] if i != j else []) + rj:
                     assert not _overlap(wi, other), ("grouped jobs race", i, j, wi, other)
         for jb in L["jobs"]:
-            self.gemm_gather(jb, dt=dt)
+            self.gemm_gather(jb, dt=dtype_of(jb))
 
     def _job_spans(self, jb, esz):
         """(write span, [read spans]) of one grouped job, as (region, start, end) bytes."""

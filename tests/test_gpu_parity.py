@@ -244,14 +244,16 @@ def test_full_size_config_against_oracle(torch, cfg):
     for u in range(c.level + 1):
         assert abs(res["A"][u] - gold_a[u]) <= 1e-6 * gold_a[u], (u, res["A"][u], gold_a[u])
     # a few terms of every level recomputed by the oracle now (the stored file
-    # is the oracle's)
+    # is the oracle's; BLAS threading changes its rounding, which for a small
+    # term is a multiple of eps64 times its bound, not of the term)
     net = network.KetNetwork(c, diagonal=True)
     sp = network.slot_split(c)
     w = terms_weights(c)
     for j in _sample_terms(pat, w, np.random.default_rng(cfg), 2):
         term = tuple(int(v) for v in pat[j])
         ref, _ = network.term_value(net, sp, term)
-        assert abs(ref - gold_x[j]) <= 1e-13 * ref + 1e-300, (j, ref, gold_x[j])
+        tol = 1e-12 * ref + 2.0 ** -40 * math.sqrt(ref * pc.term_bound(sp, term))
+        assert abs(ref - gold_x[j]) <= tol, (j, ref, gold_x[j], tol)
 
 
 def terms_weights(c):

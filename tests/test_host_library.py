@@ -178,13 +178,14 @@ def grouped_by_positions(pat, x):
 
 
 def _replay(circ, level, mode=tn.TN_MODE_BATCHED, fp64=True, gather=True, group=True, max_ksplit=0,
-            one_shape=True):
+            one_shape=True, all_tiles=False):
     plan = tn.tn_plan_build(circ, level)
     t = tn.tn_terms_enumerate(plan, level)
     desc, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(mode=mode, use_graph=False,
                                                                   fp64_level0=fp64, gather=gather,
                                                                   group=group, max_ksplit=max_ksplit,
-                                                                  one_shape_per_level=one_shape))
+                                                                  one_shape_per_level=one_shape,
+                                                                  all_tiles=all_tiles))
     pat, w = t.get()
     live = [i for i in range(t.n) if w[i] != 0.0]
     sim = Sim(desc, cb)
@@ -227,7 +228,12 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge
     c = W.tiny_random_circuit(np.random.default_rng(seed), n, gates, noises, noise="adpd", level=2,
                               target=target)
     r = estimate.estimate(c, 2, "network", reduce=True)
-    x, pat, desc = _replay(c, 2)
+    x_s, _, desc_s = _replay(c, 2)            # levels under 32 MFLOP: all steps in one small-step launch
+    x, pat, desc = _replay(c, 2, all_tiles=True)
+
+    def tile_levels(d):
+        return {L["level"] for L in d["launches"] if L["kind"] == 6 and not L["fp64"] and L["phase"] == "batch"}
+    assert tile_levels(desc_s) < tile_levels(desc), (tile_levels(desc_s), tile_levels(desc))
     assert any(L["kind"] == 6 and not L["fp64"] for L in desc["launches"]), "no grouped matrix-core launch"
     assert any(L["kind"] == 6 and L["fp64"] for L in desc["launches"]), "no grouped FP64 tile launch"
     merges = {j["merge"] for L in desc["launches"] if L["kind"] == 6 for j in L["jobs"]}
@@ -236,11 +242,11 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge
     assert max(splits) == split, splits      # inner sums split over 16 (2^9 terms) or 2 (2^6) tiles
     kinds = [L["kind"] for L in desc["launches"]]
     assert 7 in kinds and all(kinds[q - 1] == 6 for q, kd in enumerate(kinds) if kd == 7)
-    x_2, _, desc_2 = _replay(c, 2, max_ksplit=2)
+    x_2, _, desc_2 = _replay(c, 2, max_ksplit=2, all_tiles=True)
     assert {j["ksplit"] for L in desc_2["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1, 2}
-    x_1, _, desc_1 = _replay(c, 2, max_ksplit=1)
+    x_1, _, desc_1 = _replay(c, 2, max_ksplit=1, all_tiles=True)
     assert {j["ksplit"] for L in desc_1["launches"] if L["kind"] == 6 for j in L["jobs"]} == {1}
-    x_m, _, desc_m = _replay(c, 2, one_shape=False)   # every job its own tile shape
+    x_m, _, desc_m = _replay(c, 2, one_shape=False, all_tiles=True)   # every job its own tile shape
 
     def shapes_per_level(d):
         lv = {}
@@ -254,7 +260,7 @@ def test_schedule_replay_gathered_operands(n, gates, noises, target, seed, merge
     x_t, _, desc_t = _replay(c, 2, gather=False, group=False)
     assert not any(L.get("gather") for L in desc_t["launches"] if L["kind"] == 1)
     x_p, _, desc_p = _replay(c, 2, mode=tn.TN_MODE_PLAIN, fp64=False)
-    for v in (x, x_2, x_1, x_m, x_g, x_t, x_p):
+    for v in (x, x_s, x_2, x_1, x_m, x_g, x_t, x_p):
         assert np.allclose(v, r["X"], rtol=2e-5, atol=1e-10)
 
 

@@ -67,7 +67,10 @@ def test_stored_oracle_values_are_the_oracles(cfg):
     for u in range(c.level + 1):
         for j in rng.choice(np.flatnonzero(lv == u), size=min(3, int((lv == u).sum())), replace=False):
             x, _ = network.term_value(net, sp, tl[j])
-            assert abs(x - gold_x[j]) <= 1e-13 * abs(x) + 1e-300, (j, x, gold_x[j])
+            # BLAS threading changes the oracle's rounding: for a small term a
+            # multiple of eps64 times its bound, not of the term
+            tol = 1e-12 * abs(x) + 2.0 ** -40 * math.sqrt(abs(x) * pc.term_bound(sp, tl[j]))
+            assert abs(x - gold_x[j]) <= tol, (j, x, gold_x[j], tol)
 
 
 @pytest.mark.parametrize("cfg", [2, 3, 5])
