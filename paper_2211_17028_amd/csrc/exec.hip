@@ -295,6 +295,23 @@ static bool split_by_block(int k_log, int64_t outs) {
     return t_block < t_thread;
 }
 
+// Workgroups of a launch go to the 8 XCDs of the chip in turn (block b to XCD
+// b mod 8), and each XCD has its own L2.  Tiles are listed so that tiles
+// sharing an operand panel are neighbours; block b takes tile
+// start(b mod 8) + b / 8, so XCD j runs the j-th eighth of the list in list
+// order and the tiles sharing a panel share an L2.
+constexpr int kNumXcds = 8;
+template <typename T>
+static std::vector<T> xcd_order(const std::vector<T>& v) {
+    const int64_t n = (int64_t)v.size(), q = n / kNumXcds, r = n % kNumXcds;
+    std::vector<T> out(v.size());
+    for (int64_t b = 0; b < n; ++b) {
+        const int64_t j = b % kNumXcds, i = b / kNumXcds;
+        out[b] = v[j * q + std::min<int64_t>(j, r) + i];
+    }
+    return out;
+}
+
 // One grouped contraction (host side of a GettJob).
 struct GroupJob {
     Ref a, b, c, oa, ob;
@@ -1275,6 +1292,7 @@ struct Builder {
                 }
                 if (M.mjobs.empty()) continue;
                 if ((int64_t)tl.size() >= (int64_t(1) << 31)) fail(TN_ETOOBIG, "grouped launch above 2^31 tiles");
+                tl = xcd_order(tl);
                 M.n_tiles = (int64_t)tl.size();
                 M.tiles = Ref{R_CONST, ex->cbuf.add(tl.data(), M.n_tiles * (int64_t)sizeof(MfmaTile))};
                 M.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)M.mjobs.size() * (int64_t)sizeof(MfmaJob))};

@@ -1654,8 +1654,10 @@ __global__ __launch_bounds__(256) void k_level_sum_multi(const LevelSumJob* __re
 __global__ __launch_bounds__(1024) void k_tail(const TailJob* __restrict__ jobs) {
     __shared__ double ss[1024];
     __shared__ double cc[1024];
-    const TailJob& J = jobs[blockIdx.x];
-    const FinalizeArgs& f = J.f;
+    // by value: the record's fields stay in registers (the stores below could
+    // otherwise alias them and force a reload after every term)
+    const TailJob J = jobs[blockIdx.x];
+    const FinalizeArgs f = J.f;
     for (int u = 0; u < J.n_levels; ++u) {
         const int64_t b = J.starts[u], e = J.starts[u + 1];
         double s = 0.0, c = 0.0;

@@ -917,6 +917,165 @@ static std::vector<PathStep> reconfigure(const std::vector<std::vector<int>>& le
     return out;
 }
 
+// Per-estimate depth.  Subtrees with no noise slot below them are computed
+// once per prepared schedule, so an estimate runs only the steps with a slot
+// below them, one tree level per dependent launch (about 10 us each on the
+// target GPU, whatever the level's work).  The cheapest path absorbs constant
+// tensors into a slot's arm one at a time, which costs a level each.  Two
+// rewrites of the tree shorten those chains:
+//   ((Y . C1) . C2) -> Y . (C1 . C2)     (C1, C2 constant: their product is
+//                                         computed once)
+//   ((X . Y) . C)   -> Y . (X . C)        (C constant, X's arm shallower than Y's)
+// Each is kept when it lowers the rewritten node's per-estimate depth and the
+// constant product stays within kDepthMaxConstLegs legs; the rewritten tree is
+// kept when it is shallower, admissible, and dearer by at most kDepthCredit
+// per level saved (about what the matrix cores do in one dependent launch).
+constexpr int kDepthMaxConstLegs = 14;
+constexpr double kDepthCredit = 2e7;   // cost units (complex MACs) of one dependent launch
+
+static int per_estimate_depth(const std::vector<int>& ca, const std::vector<int>& cb,
+                              const std::vector<uint64_t>& mask, int L, int n) {
+    if (n < L || mask[n] == 0) return 0;
+    const int a = per_estimate_depth(ca, cb, mask, L, ca[n]), b = per_estimate_depth(ca, cb, mask, L, cb[n]);
+    return 1 + std::max(a, b);
+}
+
+static std::vector<PathStep> reduce_depth(const std::vector<std::vector<int>>& leaf_legs,
+                                          const std::vector<uint64_t>& leaf_mask, const PathSearch& ps,
+                                          const std::vector<PathStep>& path,
+                                          const std::unordered_map<int, int>& total, int max_log) {
+    const int L = (int)leaf_legs.size();
+    const int NN = L + (int)path.size();
+    if (path.size() < 2) return path;
+    std::vector<int> ca(NN, -1), cb(NN, -1);
+    for (size_t j = 0; j < path.size(); ++j) {
+        ca[L + j] = path[j].a;
+        cb[L + j] = path[j].b;
+    }
+    const int root = NN - 1;
+    std::vector<LegCount> cnt(NN);
+    std::vector<uint64_t> mask(NN, 0);
+    std::vector<int> nres(NN, 0);
+    for (int i = 0; i < L; ++i) {
+        for (int e : leaf_legs[i]) cnt[i].v.push_back({e, 1});
+        mask[i] = leaf_mask[i];
+        nres[i] = (int)leaf_legs[i].size();
+    }
+    std::vector<double> step(NN, 0.0);
+    auto update = [&](int n) {
+        std::vector<int> un, res;
+        cnt[n] = merge_counts(cnt[ca[n]], cnt[cb[n]], total, &un, &res);
+        mask[n] = mask[ca[n]] | mask[cb[n]];
+        nres[n] = (int)res.size();
+        step[n] = ps.instances(mask[n]) * (std::ldexp(1.0, (int)un.size()) + kWriteCost * std::ldexp(1.0, nres[n]));
+    };
+    for (int n = L; n < NN; ++n) update(n);
+    auto total_cost = [&]() {
+        double c = 0;
+        for (int n = L; n < NN; ++n) c += step[n];
+        return c;
+    };
+    auto depth = [&](int n) { return per_estimate_depth(ca, cb, mask, L, n); };
+    const double cost0 = total_cost();
+    const int depth0 = depth(root);
+    std::function<void(int, std::vector<int>&)> postorder = [&](int n, std::vector<int>& out) {
+        if (n < L) return;
+        postorder(ca[n], out);
+        postorder(cb[n], out);
+        out.push_back(n);
+    };
+    // the parent of every node (rebuilt after each rewrite)
+    std::vector<int> par(NN, -1);
+    auto reparent = [&]() {
+        std::fill(par.begin(), par.end(), -1);
+        for (int n = L; n < NN; ++n) par[ca[n]] = par[cb[n]] = n;
+    };
+    reparent();
+    auto refresh_up = [&](int n) {
+        for (int x = n; x >= 0; x = par[x]) update(x);
+    };
+    bool changed = true;
+    for (int pass = 0; pass < 64 && changed; ++pass) {
+        changed = false;
+        std::vector<int> order;
+        postorder(root, order);
+        for (int N : order) {
+            if (mask[N] == 0) continue;
+            int C = ca[N], X = cb[N];
+            if (mask[C] != 0) std::swap(C, X);
+            if (mask[C] != 0 || X < L) continue;           // needs a constant child and an internal other
+            const int d_old = depth(N);
+            // candidate rewrites of N = (X . C)
+            int A = ca[X], B = cb[X];
+            int rule = 0, keep = -1, fold = -1;
+            if (mask[A] == 0 || mask[B] == 0) {
+                // X = (Y . C1): N = Y . (C1 . C2)
+                keep = mask[A] == 0 ? B : A;
+                fold = mask[A] == 0 ? A : B;
+                rule = 1;
+            } else {
+                // X = (P . Q), both with slots: push C into the shallower one
+                keep = depth(A) >= depth(B) ? A : B;
+                fold = keep == A ? B : A;
+                rule = 2;
+            }
+            // save, rewrite: X's id holds the new inner node (fold . C)
+            const int sa = ca[N], sb = cb[N], xa = ca[X], xb = cb[X];
+            ca[X] = fold;
+            cb[X] = C;
+            ca[N] = keep;
+            cb[N] = X;
+            reparent();
+            update(X);
+            refresh_up(N);
+            const bool ok = depth(N) < d_old && nres[X] <= std::min(max_log, rule == 1 ? kDepthMaxConstLegs : max_log) &&
+                            nres[N] <= max_log;
+            if (ok) {
+                changed = true;
+                break;     // the traversal order changed: start a new pass
+            }
+            ca[N] = sa;
+            cb[N] = sb;
+            ca[X] = xa;
+            cb[X] = xb;
+            reparent();
+            update(X);
+            refresh_up(N);
+        }
+    }
+    const double cost1 = total_cost();
+    const int depth1 = depth(root);
+    if (depth1 >= depth0 || cost1 > cost0 + kDepthCredit * (depth0 - depth1)) return path;
+    // emit: post-order, the larger subtree first
+    std::vector<int> nleaves(NN, 1);
+    std::function<void(int)> count = [&](int n) {
+        if (n < L) return;
+        count(ca[n]);
+        count(cb[n]);
+        nleaves[n] = nleaves[ca[n]] + nleaves[cb[n]];
+    };
+    count(root);
+    std::vector<int> order;
+    std::function<void(int)> emit = [&](int n) {
+        if (n < L) return;
+        int x = ca[n], y = cb[n];
+        if (nleaves[y] > nleaves[x]) std::swap(x, y);
+        emit(x);
+        emit(y);
+        order.push_back(n);
+    };
+    emit(root);
+    std::vector<int> newid(NN, -1);
+    for (int i = 0; i < L; ++i) newid[i] = i;
+    std::vector<PathStep> out;
+    for (size_t j = 0; j < order.size(); ++j) {
+        const int n = order[j];
+        out.push_back({newid[ca[n]], newid[cb[n]]});
+        newid[n] = L + (int)j;
+    }
+    return out;
+}
+
 static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, double max_peak, bool reconf) {
     const int nl = (int)p.leaves.size();
     // union-find over shared legs
@@ -1053,6 +1212,12 @@ static void plan_clusters(Plan& p, int trials, uint64_t seed, int max_log, doubl
             os << "no contraction path keeps tensors within 2^" << max_log << " elements and the live set "
                << "within " << max_peak << " elements (best: 2^" << best.max_log << ", " << best.peak << ")";
             fail(TN_ETOOBIG, os.str());
+        }
+        {
+            TrialResult shallow = evaluate_path(leaf_legs, leaf_mask, ps,
+                                                reduce_depth(leaf_legs, leaf_mask, ps, best.path, total, max_log),
+                                                total);
+            if (admissible(shallow)) best = std::move(shallow);
         }
         cl.path = best.path;
         cl.cmacs_per_term = best.cost1;
