@@ -187,14 +187,11 @@ struct tn_exec_s {
     std::vector<tn::Launch> launches_const; // slot-free steps: run once per binding (and upload)
     std::vector<tn::Launch> tail;           // finalize + level sums
     // packed circuits: the tail runs as one finalize and one level-sum launch
-    bool multi_tail = false;
-    // circuits of at most kTailMaxTerms terms: finalize + level sums as one
-    // launch, one block per circuit
-    bool fused_tail = false;
-    tn::Ref tail_jobs;
-    tn::Ref fin_args, fin_block0, ls_jobs;
-    int64_t fin_blocks = 0;
-    int n_ls_jobs = 0;
+    // the tail of all packed circuits: one record per circuit, the per-block
+    // level partials of the term launch
+    tn::Ref tail_jobs, tail_part;
+    int64_t tail_blocks = 0;
+    int tail_levels = 0;
     std::vector<tn::PlanExec> plans;
     // results of an estimate (level sums, FP32 all-dominant value of every
     // plan), written by the tail kernels into pinned host memory
@@ -1565,19 +1562,12 @@ static void build_schedule(tn_exec_s* ex, int n, const tn_plan* plans, const tn_
                 L.jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)L.n_jobs * (int64_t)sizeof(GettJob))};
                 L.table = Ref{R_CONST, ex->cbuf.reserve(L.blocks * 4)};
             }
-    int64_t max_terms = 0;
-    for (const PlanExec& pe : ex->plans) max_terms = std::max(max_terms, pe.n_terms);
-    if (max_terms <= kTailMaxTerms) {
-        ex->fused_tail = true;
-        ex->tail_jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(TailJob))};
-    } else if (n > 1) {
-        ex->multi_tail = true;
-        ex->fin_args = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(FinalizeArgs))};
-        ex->fin_block0 = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * 8)};
-        for (auto& L : ex->tail)
-            if (L.kind == L_LEVELSUM) ex->n_ls_jobs += L.n_levels;
-        ex->ls_jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)ex->n_ls_jobs * (int64_t)sizeof(LevelSumJob))};
+    for (const PlanExec& pe : ex->plans) {
+        ex->tail_blocks += (pe.n_terms + 255) / 256;
+        ex->tail_levels = std::max(ex->tail_levels, pe.terms->level + 1);
     }
+    ex->tail_jobs = Ref{R_CONST, ex->cbuf.reserve((int64_t)n * (int64_t)sizeof(TailJob))};
+    ex->tail_part = Ref{R_CONST, ex->cbuf.reserve(std::max<int64_t>(1, ex->tail_blocks) * 16 * (TN_MAX_LEVEL + 1))};
     ex->const_bytes = round_up((int64_t)ex->cbuf.bytes.size(), 256);
     ex->work1_bytes = round_up(bw.work.peak, 256);
     ex->work_bytes = ex->work1_bytes + round_up(bw.work2.peak, 256);
@@ -1697,50 +1687,25 @@ static void bind(tn_exec_s* ex) {
     }
 }
 
-// packed circuits: the per-circuit finalize / level-sum records as two
-// launches, or the per-circuit records of the one-launch tail
-static void bind_multi_tail(tn_exec_s* ex) {
-    if (ex->fused_tail) {
-        TailJob* tj = (TailJob*)(ex->cbuf.bytes.data() + ex->tail_jobs.off);
-        int nt = 0;
-        for (auto& L : ex->tail) {
-            if (L.kind == L_FINALIZE) {
-                std::memset(tj + nt, 0, sizeof(TailJob));
-                tj[nt].f = L.f;
-            } else if (L.kind == L_LEVELSUM) {
-                tj[nt].starts = (const int64_t*)resolve(ex, L.starts);
-                tj[nt].sums = (double*)resolve(ex, L.sums);
-                tj[nt].n_levels = L.n_levels;
-                ++nt;
-            }
-        }
-        return;
-    }
-    if (!ex->multi_tail) return;
-    FinalizeArgs* fa = (FinalizeArgs*)(ex->cbuf.bytes.data() + ex->fin_args.off);
-    int64_t* b0 = (int64_t*)(ex->cbuf.bytes.data() + ex->fin_block0.off);
-    LevelSumJob* lj = (LevelSumJob*)(ex->cbuf.bytes.data() + ex->ls_jobs.off);
-    int nf = 0, nl = 0;
+// the tail records of all packed circuits (finalize arguments, level starts,
+// results, first block of each circuit in the term launch)
+static void bind_tail(tn_exec_s* ex) {
+    TailJob* tj = (TailJob*)(ex->cbuf.bytes.data() + ex->tail_jobs.off);
+    int nt = 0;
     int64_t blocks = 0;
     for (auto& L : ex->tail) {
         if (L.kind == L_FINALIZE) {
-            std::memcpy(fa + nf, &L.f, sizeof(FinalizeArgs));
-            b0[nf] = blocks;
+            std::memset(tj + nt, 0, sizeof(TailJob));
+            tj[nt].f = L.f;
+            tj[nt].block0 = blocks;
             blocks += (L.f.n_terms + 255) / 256;
-            ++nf;
         } else if (L.kind == L_LEVELSUM) {
-            for (int u = 0; u < L.n_levels; ++u) {
-                LevelSumJob j{};
-                j.x = (const double*)resolve(ex, L.x_out);
-                j.starts = (const int64_t*)resolve(ex, L.starts);
-                j.out = (double*)resolve(ex, L.sums);
-                j.u = u;
-                std::memcpy(lj + nl, &j, sizeof(LevelSumJob));
-                ++nl;
-            }
+            tj[nt].starts = (const int64_t*)resolve(ex, L.starts);
+            tj[nt].sums = (double*)resolve(ex, L.sums);
+            tj[nt].n_levels = L.n_levels;
+            ++nt;
         }
     }
-    ex->fin_blocks = blocks;
 }
 
 static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
@@ -1767,13 +1732,6 @@ static void enqueue(tn_exec_s* ex, Launch& L, hipStream_t s) {
     case L_MREDUCE:
         launch_split_reduce(L.fp64, L.mtile, (const MfmaJob*)resolve(ex, L.jobs),
                             (const MfmaTile*)resolve(ex, L.tiles), L.n_tiles, s);
-        break;
-    case L_FINALIZE:
-        launch_finalize(L.f, s);
-        break;
-    case L_LEVELSUM:
-        launch_level_sum((const double*)resolve(ex, L.x_out), (const int64_t*)resolve(ex, L.starts),
-                         L.n_levels, (double*)resolve(ex, L.sums), s);
         break;
     case L_SLOTFILL:
         launch_slot_fill(L.sf, s);
@@ -1948,16 +1906,8 @@ static void run_tail(tn_exec_s* ex, hipStream_t s) {
             }
         }
     }
-    if (ex->fused_tail) {
-        launch_tail((const TailJob*)resolve(ex, ex->tail_jobs), (int)ex->plans.size(), s);
-    } else if (ex->multi_tail) {
-        const int nf = (int)(ex->tail.size() / 2);
-        launch_finalize_multi((const FinalizeArgs*)resolve(ex, ex->fin_args), (const int64_t*)resolve(ex, ex->fin_block0),
-                              nf, ex->fin_blocks, s);
-        launch_level_sum_multi((const LevelSumJob*)resolve(ex, ex->ls_jobs), ex->n_ls_jobs, s);
-    } else {
-        for (auto& L : ex->tail) enqueue(ex, L, s);
-    }
+    launch_tail((const TailJob*)resolve(ex, ex->tail_jobs), (int)ex->plans.size(), ex->tail_blocks,
+                ex->tail_levels, (double*)resolve(ex, ex->tail_part), s);
     HIPCHK(hipGetLastError());
 }
 
@@ -2033,7 +1983,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
     os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
        << ",\"work1_bytes\":" << ex->work1_bytes
        << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms
-       << ",\"fused_tail\":" << (ex->fused_tail ? 1 : 0) << ",\"launches\":[";
+       << ",\"tail_blocks\":" << ex->tail_blocks << ",\"launches\":[";
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
         os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
@@ -2345,7 +2295,7 @@ static void bind_exec(tn_exec_s* ex, void* d_ws, size_t ws_bytes, hipStream_t st
                          hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer(&ex->results_dev, ex->results_host, 0));
     bind(ex);
-    bind_multi_tail(ex);
+    bind_tail(ex);
     if (!ex->launches64.empty()) {
         HIPCHK(hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&ex->ev_fork, hipEventDisableTiming));

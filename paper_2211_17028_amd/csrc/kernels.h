@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "tn.h"
+
 namespace tn {
 
 // Operand selection for a gathered batch: instance i of the output reads
@@ -167,28 +169,20 @@ struct FinalizeArgs {
     int32_t re_value;              // 1: X = w Re(a) (doubled network), 0: X = w |a|^2
     int32_t pad_;
 };
-void launch_finalize(const FinalizeArgs& f, hipStream_t s);
-// packed circuits: one launch; d_block0[i] = first block of circuit i (256 terms per block)
-void launch_finalize_multi(const FinalizeArgs* d_args, const int64_t* d_block0, int n_plans, int64_t blocks,
-                           hipStream_t s);
-struct LevelSumJob {               // one (circuit, level) block of a packed level-sum launch
-    const double* x;
-    const int64_t* starts;
-    double* out;
-    int32_t u, pad_;
-};
-void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s);
 
-// The tail of one circuit per block (circuits with at most kTailMaxTerms
-// terms): the finalize of every term and the level sums in one launch.
-constexpr int64_t kTailMaxTerms = 65536;
+// The tail of all packed circuits (finalize of every term and the level sums)
+// in two launches: per-block level partials of 256 terms each, then one
+// block per (circuit, level) adding them in block order.
 struct TailJob {
     FinalizeArgs f;
     const int64_t* starts;         // n_levels + 1 level starts
     double* sums;                  // n_levels (sum, comp) pairs
+    int64_t block0;                // first block of this circuit in the term launch
     int32_t n_levels, pad_;
 };
-void launch_tail(const TailJob* d_jobs, int n_jobs, hipStream_t s);
+// d_part: blocks x (TN_MAX_LEVEL + 1) (sum, comp) pairs of scratch
+void launch_tail(const TailJob* d_jobs, int n_jobs, int64_t blocks, int max_levels, double* d_part,
+                 hipStream_t s);
 
 // Neumaier level sums over contiguous ranges [start[u], start[u+1]).
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,

@@ -1555,27 +1555,6 @@ __device__ __forceinline__ double finalize_term(const FinalizeArgs& f, int64_t t
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs f) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < f.n_terms) finalize_term(f, t);
-}
-
-// All packed circuits in one launch: block b belongs to the circuit whose
-// first block is the largest block0 <= b.
-__global__ __launch_bounds__(256) void k_finalize_multi(const FinalizeArgs* __restrict__ fs,
-                                                        const int64_t* __restrict__ block0, int n) {
-    int lo = 0, hi = n - 1;
-    const int64_t b = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (block0[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const FinalizeArgs f = fs[lo];
-    const int64_t t = (b - block0[lo]) * 256 + threadIdx.x;
-    if (t < f.n_terms) finalize_term(f, t);
-}
-
 // ---------------------------------------------------------------------------
 // K4: Neumaier-compensated level sums in a fixed order (deterministic): each
 // thread sums a fixed strided subset, then pairs (sum, comp) are combined in a
@@ -1639,45 +1618,69 @@ __global__ __launch_bounds__(256) void k_level_sum(const double* x, const int64_
     level_sum_block(x, starts, out, blockIdx.x);
 }
 
-// One block per (circuit, level) of all packed circuits.
-__global__ __launch_bounds__(256) void k_level_sum_multi(const LevelSumJob* __restrict__ jobs) {
-    const LevelSumJob j = jobs[blockIdx.x];
-    level_sum_block(j.x, j.starts, j.out, j.u);
+// The tail of all packed circuits in two launches.  k_tail_terms: block b
+// finalizes terms 256 (b - block0) ... of its circuit (X_t = w |a_t|^2 and a_t
+// written to the per-term outputs) and writes, for every level u, the
+// Neumaier pair of its terms of
+// level u (a fixed tree over the block's lanes) to part[b][u].
+// k_tail_sums: block (circuit, u) adds the circuit's block pairs of level u in
+// block order (strided per lane, then a fixed tree): deterministic.
+__device__ __forceinline__ int tail_job_of(const TailJob* __restrict__ jobs, int n_jobs, int64_t b) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
-// The whole tail of one circuit in one block (one block per packed circuit):
-// every term finalized (X_t, a_t written as by k_finalize) and its level sums
-// taken in the same pass.  Level by level, thread t takes the level's terms
-// b + t, b + t + 1024, ... in that order (8 finalized with their loads in
-// flight before they are added), then the block's pairs are combined in a
-// fixed tree: deterministic.
-__global__ __launch_bounds__(1024) void k_tail(const TailJob* __restrict__ jobs) {
-    __shared__ double ss[1024];
-    __shared__ double cc[1024];
-    // by value: the record's fields stay in registers (the stores below could
-    // otherwise alias them and force a reload after every term)
-    const TailJob J = jobs[blockIdx.x];
-    const FinalizeArgs f = J.f;
+__global__ __launch_bounds__(256) void k_tail_terms(const TailJob* __restrict__ jobs, int n_jobs,
+                                                    double* __restrict__ part) {
+    __shared__ double ss[256];
+    __shared__ double cc[256];
+    const int64_t b = blockIdx.x;
+    const TailJob J = jobs[tail_job_of(jobs, n_jobs, b)];
+    const int64_t t0 = (b - J.block0) * 256;
+    const int64_t t = t0 + threadIdx.x;
+    const double x = t < J.f.n_terms ? finalize_term(J.f, t) : 0.0;
+    const int64_t t_end = t0 + 256 < J.f.n_terms ? t0 + 256 : J.f.n_terms;
+    double* out = part + b * (2 * (TN_MAX_LEVEL + 1));
     for (int u = 0; u < J.n_levels; ++u) {
-        const int64_t b = J.starts[u], e = J.starts[u + 1];
-        double s = 0.0, c = 0.0;
-        constexpr int U = 8;
-        for (int64_t t0 = b + threadIdx.x; t0 < e; t0 += 1024 * U) {
-            double v[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int64_t t = t0 + (int64_t)q * 1024;
-                v[q] = t < e ? finalize_term(f, t) : 0.0;
+        const int64_t lb = J.starts[u], le = J.starts[u + 1];
+        if (le <= t0 || lb >= t_end) {           // no term of this block has level u
+            if (threadIdx.x == 0) {
+                out[2 * u] = 0.0;
+                out[2 * u + 1] = 0.0;
             }
-#pragma unroll
-            for (int q = 0; q < U; ++q)
-                if (t0 + (int64_t)q * 1024 < e) neumaier_add(s, c, v[q]);
+            continue;
         }
-        neumaier_block<1024>(s, c, ss, cc);
+        double sv = (t >= lb && t < le) ? x : 0.0, cv = 0.0;
+        neumaier_block<256>(sv, cv, ss, cc);
         if (threadIdx.x == 0) {
-            J.sums[2 * u] = s + c;
-            J.sums[2 * u + 1] = c;
+            out[2 * u] = sv;
+            out[2 * u + 1] = cv;
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tail_sums(const TailJob* __restrict__ jobs, const double* __restrict__ part) {
+    __shared__ double ss[256];
+    __shared__ double cc[256];
+    const TailJob J = jobs[blockIdx.x];
+    const int u = blockIdx.y;
+    if (u >= J.n_levels) return;
+    const int64_t nb = (J.f.n_terms + 255) / 256;
+    double s = 0.0, c = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += 256) {
+        const double* pr = part + (J.block0 + q) * (2 * (TN_MAX_LEVEL + 1)) + 2 * u;
+        neumaier_add(s, c, pr[0]);
+        c += pr[1];
+    }
+    neumaier_block<256>(s, c, ss, cc);
+    if (threadIdx.x == 0) {
+        J.sums[2 * u] = s + c;
+        J.sums[2 * u + 1] = c;
     }
 }
 
@@ -1885,30 +1888,17 @@ static void launch_perm(const PermArgs& p, hipStream_t s) {
 void launch_permute_c64(const PermArgs& p, hipStream_t s) { launch_perm<float2>(p, s); }
 void launch_permute_c128(const PermArgs& p, hipStream_t s) { launch_perm<double2>(p, s); }
 
-void launch_finalize(const FinalizeArgs& f, hipStream_t s) {
-    if (f.n_terms == 0) return;
-    hipLaunchKernelGGL(k_finalize, dim3(grid1(f.n_terms, 256)), dim3(256), 0, s, f);
-}
-
-void launch_finalize_multi(const FinalizeArgs* d_args, const int64_t* d_block0, int n_plans, int64_t blocks,
-                           hipStream_t s) {
-    if (blocks == 0) return;
-    hipLaunchKernelGGL(k_finalize_multi, dim3((unsigned)blocks), dim3(256), 0, s, d_args, d_block0, n_plans);
-}
-
-void launch_level_sum_multi(const LevelSumJob* d_jobs, int n_jobs, hipStream_t s) {
-    if (n_jobs == 0) return;
-    hipLaunchKernelGGL(k_level_sum_multi, dim3(n_jobs), dim3(256), 0, s, d_jobs);
-}
-
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_level_sum, dim3(n_levels), dim3(256), 0, s, x, starts, out);
 }
 
-void launch_tail(const TailJob* d_jobs, int n_jobs, hipStream_t s) {
+void launch_tail(const TailJob* d_jobs, int n_jobs, int64_t blocks, int max_levels, double* d_part,
+                 hipStream_t s) {
     if (n_jobs == 0) return;
-    hipLaunchKernelGGL(k_tail, dim3(n_jobs), dim3(1024), 0, s, d_jobs);
+    if (blocks > 0) hipLaunchKernelGGL(k_tail_terms, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs, d_part);
+    hipLaunchKernelGGL(k_tail_sums, dim3((unsigned)n_jobs, (unsigned)max_levels), dim3(256), 0, s, d_jobs,
+                       (const double*)d_part);
 }
 
 void launch_slot_fill(const SlotFillArgs& a, hipStream_t s) {

@@ -279,7 +279,7 @@ def test_small_levels_run_in_one_launch_and_depth_is_reduced():
     assert sorted(L["level"] for L in batch) == [1, 2, 3, 4, 5, 6]
     assert any(j["fp64"] for L in batch for j in L["jobs"]) and any(not j["fp64"] for L in batch for j in L["jobs"])
     assert any(L["phase"] == "const" for L in d["launches"])
-    assert d["fused_tail"] == 1
+    assert d["tail_blocks"] == (t.n + 255) // 256
     d_all, _ = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(all_tiles=True))
     assert any(L["kind"] == 6 and not L["fp64"] for L in d_all["launches"] if L["phase"] == "batch")
 
