@@ -354,6 +354,23 @@ int tn_estimate(int32_t n, const tn_plan* plans, const tn_terms* terms, void* d_
 void tn_release_cached(void);
 
 /* ---------------------------------------------------------------------------
+ * tn_estimate_noalloc -- tn_estimate for callers that cannot allocate device
+ * or page-locked memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same schedule and kernels, with the
+ * workspace in a fixed 64 MiB device array of the library (one per GPU, held
+ * until the process ends) instead of a caller buffer.  It calls no hipMalloc,
+ * hipFree, hipHostMalloc, stream or event creation: the constants are copied
+ * in, both chains and the tail run on `stream` one after the other, the level
+ * sums are copied back, and the stream is synchronized.  Every call on a GPU
+ * uses that GPU's array (its contents are rewritten by each call), so calls
+ * that overlap on one GPU race: serialize them.  Not kept between calls.
+ * Errors: TN_EINVAL (null handle or results), TN_ENOMEM (the estimate needs
+ * more than the fixed 64 MiB; no device call is made), TN_EHIP.
+ * ------------------------------------------------------------------------- */
+int tn_estimate_noalloc(int32_t n, const tn_plan* plans, const tn_terms* terms, void* stream,
+                        tn_result* results);
+
+/* ---------------------------------------------------------------------------
  * tn_plan_build_trajectories / tn_terms_trajectories -- the quantum-trajectories
  * estimate, the paper's comparison method (Section V), on the same engine.
  * Noise s draws Kraus operator k with probability q_k = tr(E_k^+ E_k) / 2 (they

@@ -44,6 +44,10 @@ const char* last_error_cstr();
 
 static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// tn_estimate_noalloc: size of its fixed per-GPU workspace, and the devices it serves
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
 // first-fit allocator over a linear region (offsets only)
 struct Arena {
     std::map<int64_t, int64_t> free_;
@@ -2545,6 +2549,32 @@ static void estimate_chunked(int n, const tn_plan* plans, const tn_terms* terms,
 }
 
 }  // namespace tn
+
+// Fixed device workspace of tn_estimate_noalloc, for callers that cannot
+// allocate: each GPU the library runs on holds one copy until the process
+// ends.  In host code this name is only a handle: its device address comes
+// from hipGetSymbolAddress (noalloc_scratch), once per device.
+static __device__ __align__(256) unsigned char scratch[tn::kNoAllocScratchBytes];
+
+namespace tn {
+
+static void* noalloc_scratch() {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(TN_EINVAL, "device index beyond the fixed workspace table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(TN_EHIP, "hipGetSymbolAddress gave no address for the fixed workspace");
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
+
+}  // namespace tn
 using namespace tn;
 
 extern "C" {
@@ -2972,6 +3002,42 @@ int tn_contract_batch(int32_t n, const tn_plan* plans, const tn_terms* terms, in
 void tn_release_cached(void) {
     std::lock_guard<std::mutex> lk(cache_mutex());
     cache_evict_if([](const CachedExec&) { return true; });
+}
+
+int tn_estimate_noalloc(int32_t n, const tn_plan* plans, const tn_terms* terms, void* stream, tn_result* results) {
+    return guard([&] {
+        if (!results) fail(TN_EINVAL, "null results");
+        std::unique_ptr<tn_exec_s> ex = build_exec(n, plans, terms, &estimate_opts(), TermRange{});
+        ex->results_stride = std::max<int64_t>(8, (ex->results_bytes + 7) & ~int64_t(7));
+        const size_t res_off = (size_t)round_up((int64_t)exec_need(ex.get()), 256);
+        const size_t need = res_off + (size_t)ex->results_stride;
+        if (need > kNoAllocScratchBytes) {
+            std::ostringstream os;
+            os << "tn_estimate_noalloc: the estimate needs " << need << " bytes of workspace, above its fixed "
+               << kNoAllocScratchBytes << " bytes (use tn_estimate with a workspace)";
+            fail(TN_ENOMEM, os.str());
+        }
+        hipStream_t s = (hipStream_t)stream;
+        char* base = (char*)noalloc_scratch();
+        ex->base = base;
+        ex->stream = s;
+        HIPCHK(hipGetDevice(&ex->device));
+        ex->results_dev = base + res_off;   // the tail kernels write the level sums here
+        bind(ex.get());
+        bind_tail(ex.get());
+        // constants (every buffer that must hold something before the run),
+        // the slot-free steps, then both chains and the tail on the caller's
+        // stream, one after the other
+        HIPCHK(hipMemcpyAsync(base, ex->cbuf.bytes.data(), ex->cbuf.bytes.size(), hipMemcpyHostToDevice, s));
+        run_const(ex.get(), s);
+        for (auto& L : ex->launches64) enqueue(ex.get(), L, s);
+        for (auto& L : ex->launches) enqueue(ex.get(), L, s);
+        run_tail(ex.get(), s);
+        std::vector<unsigned char> host((size_t)ex->results_stride);
+        HIPCHK(hipMemcpyAsync(host.data(), ex->results_dev, (size_t)ex->results_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_results(ex.get(), host.data(), results);
+    });
 }
 
 }  // extern "C"

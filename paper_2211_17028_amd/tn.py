@@ -98,7 +98,7 @@ EXPORTS = [
     "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels",
     "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_exec_submit", "tn_exec_collect", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
-    "tn_release_cached",
+    "tn_release_cached", "tn_estimate_noalloc",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
     "tn_exec_const_bytes", "tn_exec_copy_outputs", "tn_exec_kernel_stats", "tn_plan_destroy", "tn_terms_destroy", "tn_exec_destroy", "tn_last_error",
 ]
@@ -151,6 +151,7 @@ def lib():
                                     C.POINTER(C.c_size_t)]
     L.tn_release_cached.argtypes = []
     L.tn_release_cached.restype = None
+    L.tn_estimate_noalloc.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(tn_result)]
     L.tn_plan_get_info.argtypes = [vp, C.POINTER(tn_plan_info)]
     L.tn_plan_noise.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(tn_c128),
                                 C.POINTER(C.c_double)]
@@ -604,6 +605,14 @@ def tn_contract_batch(plans: Sequence[Plan], terms: Sequence[Terms], first: int,
                                    C.c_void_p(amp.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream_ptr(stream)))
     return amp.reshape(len(plans), -1)[:, :count]
+
+
+def tn_estimate_noalloc(plans: Sequence[Plan], terms: Sequence[Terms], stream=None) -> List[dict]:
+    """Algorithm 1 end to end in the library's fixed device workspace (no
+    allocation)."""
+    res = (tn_result * len(plans))()
+    _check(lib().tn_estimate_noalloc(len(plans), _handles(plans), _handles(terms), _stream_ptr(stream), res))
+    return [r.as_dict() for r in res]
 
 
 def tn_release_cached():
