@@ -149,18 +149,26 @@ def _kernel_key(name):
     return n
 
 
-def traffic_from_counters(fetch_csv, write_csv, kernel, out_path):
+def traffic_from_counters(fetch_csv, write_csv, kernel, out_path, symbol=None, grids=None):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs of
     bench.py --copy-calibration (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch).  Each counter is scaled by what it reads for the 512 MiB
     device-to-device copy of the calibration (the dispatches that write
-    512 MiB), so the figure is in bytes moved."""
+    512 MiB), so the figure is in bytes moved.  `symbol`: the profiler's
+    kernel name to match (default: `kernel`); `grids`: keep only dispatches of
+    these workgroup counts (the launches of one estimate, not those run once
+    when a schedule is bound)."""
     import csv
     import hashlib
 
     def load(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         return rows
+
+    def keep(r):
+        if _kernel_key(r["Kernel_Name"]) != (symbol or kernel):
+            return False
+        return grids is None or int(r["Grid_Size"]) // int(r["Workgroup_Size"]) in grids
     fr, wr = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
     copy_ids = {r["Dispatch_Id"] for r in wr if "copyBuffer" in r["Kernel_Name"]
                 and abs(float(r["Counter_Value"]) - 524288.0) < 1.0}
@@ -171,14 +179,15 @@ def traffic_from_counters(fetch_csv, write_csv, kernel, out_path):
         raise SystemExit("no 512 MiB calibration copy in the counter files")
     fs = 524288.0 / (sum(copy_fetch) / len(copy_fetch))
     ws = 524288.0 / (sum(copy_write) / len(copy_write))
-    kf = [float(r["Counter_Value"]) for r in fr if _kernel_key(r["Kernel_Name"]) == kernel]
-    kw = [float(r["Counter_Value"]) for r in wr if _kernel_key(r["Kernel_Name"]) == kernel]
+    kf = [float(r["Counter_Value"]) for r in fr if keep(r)]
+    kw = [float(r["Counter_Value"]) for r in wr if keep(r)]
     if not kf or not kw:
         raise SystemExit(f"kernel {kernel} not in the counter files")
     f_kib, w_kib = sum(kf) / len(kf), sum(kw) / len(kw)
     with open(os.path.join(ROOT, "paper_2211_17028_amd", "csrc", "kernels.hip"), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     rec = {"kernel": kernel, "kernels_hip_sha256": sha, "dispatches": len(kf),
+           "grids": sorted(grids) if grids else None,
            "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib, "fetch_scale": fs,
            "write_scale": ws, "traffic_bytes_per_launch": 1024.0 * (f_kib * fs + w_kib * ws)}
     with open(out_path, "w") as f:
@@ -525,6 +534,10 @@ def main():
                     help="write the HBM traffic record of --traffic-kernel on --traffic-workload from two "
                          "rocprofv3 --pmc counter files of bench.py --copy-calibration, then exit (no GPU needed)")
     ap.add_argument("--traffic-kernel", default="k_mfma_group<128,32>")
+    ap.add_argument("--traffic-symbol", default=None,
+                    help="the profiler's kernel name when it differs from --traffic-kernel")
+    ap.add_argument("--traffic-grids", default=None,
+                    help="comma-separated workgroup counts of the launches to keep")
     ap.add_argument("--traffic-workload", default="grid5x5_12L_10depol_level2")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -551,8 +564,9 @@ def main():
                     help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.traffic_from:
+        grids = {int(g) for g in args.traffic_grids.split(",")} if args.traffic_grids else None
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.traffic_kernel,
-                              traffic_record_path(args.traffic_workload))
+                              traffic_record_path(args.traffic_workload), args.traffic_symbol, grids)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the term range would "

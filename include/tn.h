@@ -133,10 +133,19 @@ typedef struct {
                                 at the first run, joined by tn_exec_destroy) */
     int32_t fp64_level0;     /* 1 = recompute the all-dominant term in FP64
                                 (tn_estimate always does) */
-    int32_t tune;            /* 1 = pick GEMM tiles by timing (autotuner) */
-    int32_t time_kernels;    /* 1 = HIP events around every batched GEMM / permute
-                                launch, accumulated per kernel (tn_exec_kernel_stats);
-                                needs use_graph = 0 (TN_EINVAL otherwise) */
+    int32_t tune;            /* 1 = pick tiles by timing at prepare (autotuner): per-step
+                                launches (no_group) time each step's GEMM tiles; grouped
+                                launches of one plan: per FP32 tree level with tile
+                                launches, whole estimates with the model's choice are
+                                timed on the workspace against estimates with each tile
+                                shape imposed on the whole level, and a shape is kept only
+                                when it is over 3 % faster; choices are cached per level
+                                signature for the process */
+    int32_t time_kernels;    /* 1 = HIP events around every batched launch, recorded by
+                                the dispatch itself (hipExtLaunchKernelGGL) so they bracket
+                                the kernel and not the queue, accumulated per kernel
+                                (tn_exec_kernel_stats); needs use_graph = 0 (TN_EINVAL
+                                otherwise) */
     int32_t no_gather;       /* 1 = always transpose operands into GEMM order instead of
                                 letting MFMA steps read them in stored order */
     int32_t no_group;        /* 1 = one launch per contraction step instead of one grouped
@@ -255,6 +264,10 @@ int tn_terms_get(tn_terms terms, int8_t* patterns, double* weights);
  *   otherwise d_ws must hold >= *need_bytes bytes (else TN_ENOMEM); the upload
  *   is enqueued on `stream` and *out receives an executable handle bound to
  *   d_ws (the caller keeps d_ws alive and unmodified until tn_exec_destroy).
+ *   With opts->tune = 1 the query reports the largest workspace of the
+ *   schedules the autotuner times; a smaller d_ws that still holds the untuned
+ *   schedule (the query with tune = 0) is accepted, and the autotuner then
+ *   times only the candidates that fit in it.
  *   opts == NULL: batched, direct launches, FP64 dominant-term pass, every
  *   other field 0.
  * ------------------------------------------------------------------------- */

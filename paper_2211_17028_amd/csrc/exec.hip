@@ -182,6 +182,16 @@ struct SideIssuer {
     tn::Error err{0, ""};
 };
 
+// One level of the grouped-launch autotuner: the shape kept (-1: the model's
+// own choice) and the median microseconds of a whole estimate with the model's
+// choice at the level and with each shape imposed on all its jobs (-1: not
+// timed, did not fit the workspace; empty when the choice came from the cache).
+struct TuneRecord {
+    int tile = -1;
+    double model_us = -1.0;
+    std::vector<double> us;
+};
+
 struct tn_exec_s {
     std::unique_ptr<SideIssuer> issuer;     // FP64 pass issued from its own host thread
     int device = 0;
@@ -225,6 +235,12 @@ struct tn_exec_s {
     std::map<int, std::pair<int64_t, double>> kstat;  // kernel id -> (launches, ms) accumulated
     std::map<int, double> kflops, kbytes;             // kernel id -> algorithmic work accumulated
     bool bound = false;
+    // the schedule's planning choices: FP32 levels run in their small-step
+    // launch, and the tile shape imposed per level (tuned levels: on every job)
+    std::set<int> small_levels;
+    std::map<int, std::pair<int, double>> level_tile;
+    // grouped-launch autotuner: per tuned level, what was kept and timed
+    std::map<int, TuneRecord> tuning;
     ~tn_exec_s();   // joins the side issuer, frees events, streams, graph and host results
 };
 
@@ -297,18 +313,29 @@ static bool split_by_block(int k_log, int64_t outs) {
 }
 
 // Workgroups of a launch go to the 8 XCDs of the chip in turn (block b to XCD
-// b mod 8), and each XCD has its own L2.  Tiles are listed so that tiles
-// sharing an operand panel are neighbours; block b takes tile
-// start(b mod 8) + b / 8, so XCD j runs the j-th eighth of the list in list
-// order and the tiles sharing a panel share an L2.
+// b mod 8), and each XCD has its own L2.  A job lists its tiles so that tiles
+// sharing an operand panel are neighbours.  Within the blocks of each job, XCD j
+// takes one contiguous chunk of the job's tiles (as many as the job's blocks on
+// that XCD), so the tiles sharing a panel share an L2, and every XCD gets an
+// equal share of every job: jobs of one launch differ in inner length and tile
+// cost, and chunks over the whole list would give one XCD the costly jobs.
 constexpr int kNumXcds = 8;
 template <typename T>
 static std::vector<T> xcd_order(const std::vector<T>& v) {
-    const int64_t n = (int64_t)v.size(), q = n / kNumXcds, r = n % kNumXcds;
+    const int64_t n = (int64_t)v.size();
     std::vector<T> out(v.size());
-    for (int64_t b = 0; b < n; ++b) {
-        const int64_t j = b % kNumXcds, i = b / kNumXcds;
-        out[b] = v[j * q + std::min<int64_t>(j, r) + i];
+    for (int64_t s = 0; s < n;) {
+        int64_t e = s;
+        while (e < n && v[e].job == v[s].job) ++e;
+        int64_t next[kNumXcds], cnt[kNumXcds] = {};
+        for (int64_t b = s; b < e; ++b) ++cnt[b % kNumXcds];
+        int64_t at = s;
+        for (int j = 0; j < kNumXcds; ++j) {
+            next[j] = at;
+            at += cnt[j];
+        }
+        for (int64_t b = s; b < e; ++b) out[b] = v[next[b % kNumXcds]++];
+        s = e;
     }
     return out;
 }
@@ -552,7 +579,9 @@ struct Builder {
         }
         // a shape imposed by the level takes over when it costs this job at most
         // about one launch more than its own best shape (the launch it saves)
-        if (forced >= 0 && forced_cost <= best_cost + kLaunchCost) {
+        // (a tuned level's shape, max flops = infinity, is imposed on every job)
+        if (forced >= 0 && (forced_cost <= best_cost + kLaunchCost ||
+                            std::isinf(level_tile->at(st.level).second))) {
             best_o = forced_o;
             best_tile = forced;
             best_merge = forced_merge;
@@ -1751,12 +1780,19 @@ static void run_const(tn_exec_s* ex, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
+// A timed launch: grouped kernels carry their events in the dispatch (the
+// kernel's own start and end); per-step kernels get an event pair around them.
+static void issue_timed(tn_exec_s* ex, Launch& L, hipStream_t st) {
+    const bool in_dispatch = L.kind == L_GROUP || L.kind == L_MGROUP || L.kind == L_MREDUCE;
+    if (L.ev_a && in_dispatch) set_launch_events(L.ev_a, L.ev_b);
+    else if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, st));
+    enqueue(ex, L, st);
+    if (L.ev_b && !in_dispatch) HIPCHK(hipEventRecord(L.ev_b, st));
+    set_launch_events(nullptr, nullptr);
+}
+
 static void issue_chain(tn_exec_s* ex, std::vector<Launch>& list, hipStream_t st) {
-    for (auto& L : list) {
-        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, st));
-        enqueue(ex, L, st);
-        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, st));
-    }
+    for (auto& L : list) issue_timed(ex, L, st);
 }
 
 static void side_issuer_main(tn_exec_s* ex) {
@@ -1873,11 +1909,7 @@ static void run_body(tn_exec_s* ex, hipStream_t s) {
         HIPCHK(hipStreamWaitEvent(ex->side, ex->ev_fork, 0));
     }
     auto key = [](const Launch& L) { return L.level >= 0 ? L.level : INT_MAX; };
-    auto issue = [&](Launch& L, hipStream_t st) {
-        if (L.ev_a) HIPCHK(hipEventRecord(L.ev_a, st));
-        enqueue(ex, L, st);
-        if (L.ev_b) HIPCHK(hipEventRecord(L.ev_b, st));
-    };
+    auto issue = [&](Launch& L, hipStream_t st) { issue_timed(ex, L, st); };
     std::vector<Launch>& l32 = ex->launches;
     std::vector<Launch>& l64 = ex->launches64;
     size_t i32 = 0, i64 = 0;
@@ -1987,7 +2019,20 @@ static std::string describe_exec(const tn_exec_s* ex) {
     os << "{\"const_bytes\":" << ex->const_bytes << ",\"work_bytes\":" << ex->work_bytes
        << ",\"work1_bytes\":" << ex->work1_bytes
        << ",\"mode\":" << ex->opts.mode << ",\"plain_terms\":" << ex->plain_terms
-       << ",\"tail_blocks\":" << ex->tail_blocks << ",\"launches\":[";
+       << ",\"tail_blocks\":" << ex->tail_blocks << ",\"tuning\":[";
+    {
+        bool f1 = true;
+        for (auto& kv : ex->tuning) {
+            const TuneRecord& r = kv.second;
+            os << (f1 ? "" : ",") << "{\"level\":" << kv.first << ",\"tile\":" << r.tile;
+            if (r.tile >= 0) os << ",\"bm\":" << mfma_tile_bm(r.tile) << ",\"bn\":" << mfma_tile_bn(r.tile);
+            os << ",\"model_us\":" << r.model_us << ",\"us\":[";
+            for (size_t q = 0; q < r.us.size(); ++q) os << (q ? "," : "") << r.us[q];
+            os << "]}";
+            f1 = false;
+        }
+    }
+    os << "],\"launches\":[";
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
         os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
@@ -2271,6 +2316,8 @@ static std::unique_ptr<tn_exec_s> build_exec(int n, const tn_plan* plans, const 
                                                const std::pair<const int, double>& b) { return a.second < b.second; });
                 level_tile[kv.first] = {top->first, kSmallJobShare * top->second};
             }
+        ex->small_levels = small;
+        ex->level_tile = level_tile;
         build_schedule(ex.get(), n, plans, terms, level_tile.empty() ? nullptr : &level_tile, range,
                        small.empty() ? nullptr : &small);
     } else {
@@ -2280,6 +2327,143 @@ static std::unique_ptr<tn_exec_s> build_exec(int n, const tn_plan* plans, const 
 }
 
 static size_t exec_need(const tn_exec_s* ex) { return (size_t)(ex->const_bytes + ex->work_bytes); }
+
+// Autotuner of the grouped matrix-core launches (one plan).  For every FP32
+// tree level with tile launches, in level order, the schedule with the model's
+// choice at that level (its main shape, small jobs on their own shape where
+// that saves more than a launch) is timed against the schedules with each of
+// the K_MFMA_TILES shapes imposed on all of the level's matrix-core jobs, the
+// levels before it keeping their chosen shapes.  Each candidate is bound to the
+// workspace and timed as whole estimates with HIP events (median of 5 after a
+// warm-up; the FP64 pass runs beside the FP32 chain as in use, and it slows the
+// tile launches it overlaps, which timing a level's launches alone misses).  A
+// shape replaces the model's choice only when its estimate is more than
+// kTuneMargin faster, so a tuned schedule is not slower than the model's beyond
+// timing noise.  Choices are cached by the level's job signature (shapes,
+// slices) for later prepares.
+constexpr double kTuneMargin = 0.03;
+constexpr int kTuneModel = -1;      // the model's own choice kept
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
+static std::string level_signature(const tn_exec_s* ex, int level) {
+    std::ostringstream os;
+    for (const Launch& L : ex->launches)
+        if (L.level == level && (L.kind == L_MGROUP || L.kind == L_GROUP) && !L.fp64) {
+            for (const MJob& j : L.mjobs) os << j.m_log << "." << j.n_log << "." << j.k_log << "." << j.ns << ";";
+            for (const GroupJob& j : L.hjobs) os << "g" << j.m_log << "." << j.n_log << "." << j.k_log << "." << j.n_inst << ";";
+        }
+    return os.str();
+}
+
+// Workspace the autotuner needs: the largest of the model's schedule and of
+// every schedule it times (one level's shape imposed at a time).  Host only.
+static size_t tune_need(const tn_exec_s* ex, int n, const tn_plan* plans, const tn_terms* terms,
+                        TermRange range) {
+    size_t need = exec_need(ex);
+    if (n != 1 || ex->opts.mode != TN_MODE_BATCHED || ex->opts.no_group) return need;
+    std::set<int> levels;
+    for (const Launch& L : ex->launches)
+        if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) levels.insert(L.level);
+    for (int lv : levels)
+        for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+            std::map<int, std::pair<int, double>> lt = ex->level_tile;
+            lt[lv] = {tile, INFINITY};
+            tn_exec_s cand;
+            cand.opts = ex->opts;
+            build_schedule(&cand, n, plans, terms, &lt, range,
+                           ex->small_levels.empty() ? nullptr : &ex->small_levels);
+            need = std::max(need, exec_need(&cand));
+        }
+    return need;
+}
+
+static void bind_exec(tn_exec_s* ex, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+static std::unique_ptr<tn_exec_s> tune_grouped(std::unique_ptr<tn_exec_s> ex, int n, const tn_plan* plans,
+                                               const tn_terms* terms, TermRange range, void* d_ws,
+                                               size_t ws_bytes, hipStream_t s) {
+    if (n != 1 || ex->opts.mode != TN_MODE_BATCHED || ex->opts.no_group) return ex;
+    std::set<int> levels;
+    for (const Launch& L : ex->launches)
+        if (L.kind == L_MGROUP && !L.fp64 && L.level >= 0) levels.insert(L.level);
+    if (levels.empty()) return ex;
+    const std::set<int>* small = ex->small_levels.empty() ? nullptr : &ex->small_levels;
+    // one candidate schedule bound to the workspace and timed as whole
+    // estimates (us), or -1 when it does not fit the workspace
+    auto time_estimate = [&](const std::map<int, std::pair<int, double>>& lt) -> double {
+        auto cand = std::make_unique<tn_exec_s>();
+        cand->opts = ex->opts;
+        cand->opts.tune = 0;
+        cand->opts.time_kernels = 0;
+        cand->opts.use_graph = 0;
+        cand->small_levels = ex->small_levels;
+        cand->level_tile = lt;
+        build_schedule(cand.get(), n, plans, terms, &lt, range, small);
+        if (exec_need(cand.get()) > ws_bytes) return -1.0;
+        bind_exec(cand.get(), d_ws, ws_bytes, s);
+        std::vector<float> ts;
+        for (int rep = 0; rep < 6; ++rep) {
+            issue_estimate(cand.get(), s);
+            HIPCHK(hipEventRecord(cand->ev1, s));
+            HIPCHK(hipEventSynchronize(cand->ev1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, cand->ev0, cand->ev1));
+            if (rep > 0) ts.push_back(ms);
+        }
+        std::sort(ts.begin(), ts.end());
+        return 1000.0 * ts[ts.size() / 2];
+    };
+    // level -> (tile, inf): imposed on every job of the level
+    std::map<int, std::pair<int, double>> chosen;
+    std::map<int, TuneRecord> table;
+    for (int lv : levels) {
+        const std::string sig = level_signature(ex.get(), lv);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(sig);
+            if (it != g_tune_cache.end()) {
+                if (it->second != kTuneModel) chosen[lv] = {it->second, INFINITY};
+                table[lv] = TuneRecord{it->second, -1.0, {}};
+                continue;
+            }
+        }
+        std::map<int, std::pair<int, double>> base = ex->level_tile;
+        for (auto& kv : chosen) base[kv.first] = kv.second;
+        TuneRecord rec{kTuneModel, time_estimate(base), std::vector<double>(K_MFMA_TILES, -1.0)};
+        double best_us = rec.model_us;
+        for (int tile = 0; tile < K_MFMA_TILES; ++tile) {
+            std::map<int, std::pair<int, double>> lt = base;
+            lt[lv] = {tile, INFINITY};
+            rec.us[tile] = time_estimate(lt);
+            if (rec.us[tile] < 0) continue;
+            if (best_us < 0 || rec.us[tile] < (1.0 - kTuneMargin) * best_us) {
+                best_us = rec.us[tile];
+                rec.tile = tile;
+            }
+        }
+        if (rec.tile != kTuneModel) chosen[lv] = {rec.tile, INFINITY};
+        table[lv] = rec;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[sig] = rec.tile;
+    }
+    if (chosen.empty()) {
+        ex->tuning = table;
+        return ex;
+    }
+    auto tuned = std::make_unique<tn_exec_s>();
+    tuned->opts = ex->opts;
+    tuned->small_levels = ex->small_levels;
+    tuned->level_tile = ex->level_tile;
+    for (auto& kv : chosen) tuned->level_tile[kv.first] = kv.second;
+    build_schedule(tuned.get(), n, plans, terms, &tuned->level_tile, range, small);
+    if (exec_need(tuned.get()) > ws_bytes) {
+        ex->tuning = table;
+        return ex;
+    }
+    tuned->tuning = table;
+    return tuned;
+}
 
 // Device part of tn_exec_prepare: bind the schedule to the workspace, upload
 // its constants on `stream` and create its events / side stream.
@@ -2750,7 +2934,7 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
                     void* d_ws, size_t ws_bytes, void* stream, size_t* need_bytes, tn_exec* out) {
     return guard([&] {
         std::unique_ptr<tn_exec_s> ex = build_exec(n, plans, terms, opts, TermRange{});
-        const size_t need = (size_t)(ex->const_bytes + ex->work_bytes);
+        const size_t need = ex->opts.tune ? tune_need(ex.get(), n, plans, terms, TermRange{}) : exec_need(ex.get());
         if (need_bytes) *need_bytes = need;
         if (ws_bytes == 0) {
             // size query; with `out` the caller gets an unbound handle that can
@@ -2759,6 +2943,9 @@ int tn_exec_prepare(int32_t n, const tn_plan* plans, const tn_terms* terms, cons
             return;
         }
         if (!out) fail(TN_EINVAL, "null output handle");
+        if (!d_ws) fail(TN_EINVAL, "null workspace");
+        if (ex->opts.tune && exec_need(ex.get()) <= ws_bytes)
+            ex = tune_grouped(std::move(ex), n, plans, terms, TermRange{}, d_ws, ws_bytes, (hipStream_t)stream);
         bind_exec(ex.get(), d_ws, ws_bytes, (hipStream_t)stream);
         *out = reinterpret_cast<tn_exec>(ex.release());
     });

@@ -70,6 +70,10 @@ struct GettJob {
     int32_t pad_;
     int8_t a_row[32], a_k[32], b_k[32], b_col[32];
 };
+// Events for the next grouped launch issued on this thread (gett, matrix-core
+// and FP64 tile groups, split reductions): recorded at the kernel's start and
+// end by the dispatch (timing of the kernel alone).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // blocks one job takes in a grouped launch
 int64_t gett_job_blocks(const GettJob& j);
 // One launch for all jobs of a level: block b runs job d_block_job[b] & 0x7fffffff

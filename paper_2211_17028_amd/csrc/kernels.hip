@@ -6,6 +6,7 @@
 // instances that step serves.  Complex values are interleaved (re, im).
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdint>
@@ -13,6 +14,28 @@
 #include "kernels.h"
 
 namespace tn {
+
+// Events of the next grouped launch on this thread (set by the executor when
+// it times launches): they are recorded by the dispatch itself at the
+// kernel's start and end, so the interval is the kernel's execution only.
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    g_ev_start = start;
+    g_ev_stop = stop;
+}
+
+template <typename... Args, typename F>
+static void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    if (g_ev_start || g_ev_stop) {
+        hipEvent_t a = g_ev_start, b = g_ev_stop;
+        g_ev_start = g_ev_stop = nullptr;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
+
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -1298,11 +1321,9 @@ void launch_tile64_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tile
                          hipStream_t s) {
     if (n_tiles == 0) return;
     if (tile == 4)
-        hipLaunchKernelGGL((k_tile64_group<2, TILE64_MFMA>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs,
-                           d_tiles);
+        launch_k(k_tile64_group<2, TILE64_MFMA>, dim3((unsigned)n_tiles), dim3(256), s, d_jobs, d_tiles);
     else
-        hipLaunchKernelGGL((k_tile64_group<4, TILE64_MFMA>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs,
-                           d_tiles);
+        launch_k(k_tile64_group<4, TILE64_MFMA>, dim3((unsigned)n_tiles), dim3(256), s, d_jobs, d_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -1391,11 +1412,9 @@ void launch_split_reduce(int fp64, int tile, const MfmaJob* d_jobs, const MfmaTi
     if (n_tiles == 0) return;
     const int bm_log = __builtin_ctz(mfma_tile_bm(tile)), bn_log = __builtin_ctz(mfma_tile_bn(tile));
     if (fp64)
-        hipLaunchKernelGGL((k_split_reduce<double2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles,
-                           bm_log, bn_log);
+        launch_k(k_split_reduce<double2>, dim3((unsigned)n_tiles), dim3(256), s, d_jobs, d_tiles, bm_log, bn_log);
     else
-        hipLaunchKernelGGL((k_split_reduce<float2>), dim3((unsigned)n_tiles), dim3(256), 0, s, d_jobs, d_tiles,
-                           bm_log, bn_log);
+        launch_k(k_split_reduce<float2>, dim3((unsigned)n_tiles), dim3(256), s, d_jobs, d_tiles, bm_log, bn_log);
 }
 
 // ---------------------------------------------------------------------------
@@ -1588,6 +1607,35 @@ __device__ __forceinline__ void neumaier_block(double& s, double& c, double* ss,
     __syncthreads();
 }
 
+// The same with wave shuffles (a fixed butterfly within each wave of 64 lanes),
+// then the waves' pairs added by thread 0 in wave order: one barrier.  Only
+// thread 0's pair is the block's.
+template <int NT>
+__device__ __forceinline__ void neumaier_block_shfl(double& s, double& c, double* ss, double* cc) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+        c += c2;
+        neumaier_add(s, c, s2);
+    }
+    const int w = (int)threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        ss[w] = s;
+        cc[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = ss[0], C = cc[0];
+        for (int q = 1; q < NT / 64; ++q) {
+            C += cc[q];
+            neumaier_add(S, C, ss[q]);
+        }
+        s = S;
+        c = C;
+    }
+    __syncthreads();
+}
+
 // Thread t adds elements b + t, b + t + 256, ... of [b, e) in that order; the
 // loads of 8 elements are issued before their adds (the adds form a chain).
 __device__ __forceinline__ void level_sum_block(const double* x, const int64_t* starts, double* out, int u) {
@@ -1656,7 +1704,7 @@ __global__ __launch_bounds__(256) void k_tail_terms(const TailJob* __restrict__ 
             continue;
         }
         double sv = (t >= lb && t < le) ? x : 0.0, cv = 0.0;
-        neumaier_block<256>(sv, cv, ss, cc);
+        neumaier_block_shfl<256>(sv, cv, ss, cc);
         if (threadIdx.x == 0) {
             out[2 * u] = sv;
             out[2 * u + 1] = cv;
@@ -1677,7 +1725,7 @@ __global__ __launch_bounds__(256) void k_tail_sums(const TailJob* __restrict__ j
         neumaier_add(s, c, pr[0]);
         c += pr[1];
     }
-    neumaier_block<256>(s, c, ss, cc);
+    neumaier_block_shfl<256>(s, c, ss, cc);
     if (threadIdx.x == 0) {
         J.sums[2 * u] = s + c;
         J.sums[2 * u + 1] = c;
@@ -1781,7 +1829,7 @@ void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles,
 #define TN_GLAUNCH(BM_, BN_)                                                                  \
     if (t.bm == BM_ && t.bnc == BN_) {                                                         \
         constexpr int nt = 64 * (BM_ >= 64 ? BM_ / 64 : 1) * (BN_ >= 32 ? BN_ / 32 : 1);       \
-        hipLaunchKernelGGL((k_mfma_group<BM_, BN_>), dim3((unsigned)n_tiles), dim3(nt), 0, s, d_jobs, d_tiles); \
+        launch_k(k_mfma_group<BM_, BN_>, dim3((unsigned)n_tiles), dim3(nt), s, d_jobs, d_tiles);  \
         return;                                                                                \
     }
     TN_GLAUNCH(128, 64)
@@ -1802,7 +1850,7 @@ int64_t gett_job_blocks(const GettJob& j) {
 
 void launch_gett_group(const GettJob* d_jobs, const int32_t* d_block_job, int64_t blocks, hipStream_t s) {
     if (blocks == 0) return;
-    hipLaunchKernelGGL(k_gett_group, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_block_job);
+    launch_k(k_gett_group, dim3((unsigned)blocks), dim3(256), s, d_jobs, d_block_job);
 }
 
 static void launch_mfma_tile(const TileCfg& t, const GemmArgs& g, hipStream_t s, bool gather) {

@@ -306,10 +306,47 @@ def test_packed_uneven_batch_against_oracle(torch):
     assert n_full >= 3
 
 
+def test_autotuned_grouped_schedule_gives_the_same_estimate(torch):
+    """Grouped launches with tile shapes chosen by timing (every FP32 level
+    with tile launches: whole estimates with the model's choice at the level
+    against estimates with each of the 8 shapes imposed on all its jobs):
+    every term within its FP32 bound of the oracle's stored values, the level
+    sums within the parity bar; a level keeps the model's choice unless a
+    shape was more than 3 % faster, and a kept shape is what the level's tile
+    launches use."""
+    print("autotuned grouped config2", flush=True)
+    c = W.config(2)
+    plan = tn.tn_plan_build(c, 2)
+    terms = tn.tn_terms_enumerate(plan, 2)
+    ext = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, tune=True))
+    r1 = ext.run()[0]
+    x, _ = ext.values()
+    pat, _ = terms.get()
+    gold_a, gold_t, gold_x = _golden(2)
+    pc.check_against_golden(r1["T"], x, pat, gold_t, gold_x, network.slot_split(c), degenerate=True)
+    for u in range(3):
+        assert abs(r1["A"][u] - gold_a[u]) <= 1e-6 * gold_a[u]
+    d = ext.describe()
+    tuned = d["tuning"]
+    levels = {L["level"] for L in d["launches"] if L["kind"] == 6 and not L["fp64"] and L["phase"] == "batch"}
+    assert tuned and {t["level"] for t in tuned} == levels, (tuned, levels)
+    for t in tuned:
+        if t["us"]:            # timed here (not a cached choice)
+            timed = [v for v in t["us"] if v >= 0]
+            kept = t["model_us"] if t["tile"] < 0 else t["us"][t["tile"]]
+            assert kept > 0 and all(v >= 0.97 * kept * (1 - 1e-12) for v in timed), t
+            if t["tile"] >= 0:
+                assert kept < 0.97 * t["model_us"], t
+        if t["tile"] >= 0:
+            shapes = {(L["bm"], L["bn"]) for L in d["launches"]
+                      if L["kind"] == 6 and not L["fp64"] and L["level"] == t["level"]}
+            assert shapes == {(t["bm"], t["bn"])}, (t, shapes)
+
+
 def test_autotuned_schedule_gives_the_same_estimate(torch):
-    """Tiles chosen by timing (per-step launches: grouped launches take their
-    tiles from the work model) change rounding only: the estimate stays within
-    the parity bar of the oracle's stored sums and of the untuned run."""
+    """Tiles chosen by timing on the per-step schedule (no grouping) change
+    rounding only: the estimate stays within the parity bar of the oracle's
+    stored sums and of the untuned run."""
     c = W.config(2)
     plan = tn.tn_plan_build(c, 2)
     terms = tn.tn_terms_enumerate(plan, 2)
