@@ -10,10 +10,14 @@ output state, level-3 expansion (32551 term networks).  Synthetic, seeded
 One step = one full estimate (every term network contracted, FP64 dominant
 term, per-term values, level sums) with the plan and its schedule prepared
 and all inputs resident in HBM.  The timed steps launch the prepared
-schedule directly with two estimates in flight (submit / collect); the same
-steps one after another give the latency (time_to_estimate_ms), and a
-further pass launches the schedule with a HIP event pair around every launch
-for the per-kernel durations of the roofline entry.  Prints ONE JSON line.
+schedule directly: by default the K estimates are spread round-robin over 4
+streams, each with its own prepared schedule and two estimates in flight
+(submit / collect), since one estimate of this workload is latency-bound and
+fills few CUs (`one_stream` gives the one-stream figure, --streams 1 makes it
+the headline); the same steps one after another give the latency
+(time_to_estimate_ms), and a further pass launches the schedule with a HIP
+event pair around every launch for the per-kernel durations of the roofline
+entry.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -407,6 +411,40 @@ def run_estimates(ex, steps, warmup):
     return r, 1000.0 * el / steps, 1000.0 * el_seq / steps, r_seq
 
 
+def run_estimates_streams(execs, streams, steps, warmup):
+    """(last result, ms per estimate) of `steps` estimates spread round-robin
+    over prepared schedules of the same estimate, one per stream, each with up
+    to two estimates in flight: independent estimates overlap on the GPU (a
+    latency-bound estimate fills a few of its CUs)."""
+    import torch
+    E = len(execs)
+    pending = [[] for _ in range(E)]
+
+    def step(i):
+        e = i % E
+        if len(pending[e]) == 2:
+            execs[e].collect(pending[e].pop(0))
+        pending[e].append(execs[e].submit(streams[e]))
+
+    def drain():
+        r = None
+        for e in range(E):
+            while pending[e]:
+                r = execs[e].collect(pending[e].pop(0))[0]
+        return r
+
+    for i in range(max(warmup, 2 * E)):
+        step(i)
+    drain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    r = drain()
+    torch.cuda.synchronize()
+    return r, 1000.0 * (time.perf_counter() - t0) / steps
+
+
 def kernel_pass(plans, terms, steps, warmup, tune):
     """Per-kernel durations: the same schedule launched eagerly with a HIP
     event pair around every launch on that launch's stream."""
@@ -559,6 +597,8 @@ def main():
     ap.add_argument("--exact-only", action="store_true",
                     help="only the exact value of the 25-qubit workload (one estimate for A(l)); prints its JSON")
     ap.add_argument("--graph", action="store_true", help="headline from hipGraph replays instead of direct launches")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="headline: independent estimates of the workload on this many streams (1 = one stream)")
     ap.add_argument("--no-tune", action="store_true", help="tiles by shape instead of the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (byte-counter calibration under rocprofv3)")
@@ -619,13 +659,24 @@ def main():
     t0 = time.perf_counter()
     ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=args.graph, tune=not args.no_tune))
     prep_s = time.perf_counter() - t0
-    res, ms_per_step, ms_seq, _ = run_estimates(ex, args.steps, args.warmup)
+    res, ms_one, ms_seq, _ = run_estimates(ex, args.steps, args.warmup)
+    # the same estimate on `streams` streams (one prepared schedule each),
+    # estimates spread round-robin: the throughput of independent estimates
+    ms_per_step, res_multi = ms_one, res
+    if args.streams > 1 and not args.graph:
+        execs = [ex] + [tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, tune=not args.no_tune))
+                        for _ in range(args.streams - 1)]
+        strm = [torch.cuda.Stream() for _ in range(args.streams)]
+        res_multi, ms_per_step = run_estimates_streams(execs, strm, args.steps, args.warmup)
+        del execs, strm
     del ex
     eo = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=not args.graph, tune=not args.no_tune))
     res_o, ms_o, ms_o_seq, _ = run_estimates(eo, args.steps, args.warmup)
     del eo
     n_contracted = res["n_contracted"]
     value = n_contracted / (ms_per_step * 1e-3)
+    one_stream = {"value": n_contracted / (ms_one * 1e-3), "ms_per_step": ms_one,
+                  "note": "one prepared schedule, two estimates in flight on one stream"}
     other = {"mode": "direct launches" if args.graph else "hipGraph replay",
              "value": n_contracted / (ms_o * 1e-3), "ms_per_step": ms_o, "ms_per_step_sequential": ms_o_seq,
              "A_equal": res_o["A"] == res["A"]}
@@ -695,7 +746,7 @@ def main():
             exact = exact_value(c2, c2.level, r2, 5)
         offd = None if args.no_offdiag else offdiagonal_value(c2, c2.level, 20)
         traj = None if args.no_trajectories else trajectories_value(c2, exact["F"] if exact else None, 20)
-        prune = None if args.no_pruning else pruning_value(c5, plan, terms, ms_per_step, ms_seq, args.steps)
+        prune = None if args.no_pruning else pruning_value(c5, plan, terms, ms_one, ms_seq, args.steps)
 
     info = plan.info()
     line = {
@@ -730,8 +781,12 @@ def main():
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
         "kernels": kernels,
-        "timed": ("hipGraph replays" if args.graph else "direct launches") +
-                 ", two estimates in flight (submit / collect)",
+        "timed": ("hipGraph replays, two estimates in flight (submit / collect)" if args.graph or args.streams < 2
+                  else f"direct launches, {args.streams} streams with one prepared schedule each, estimates "
+                       "spread round-robin, two in flight per stream (submit / collect)"),
+        "streams": 1 if args.graph else max(1, args.streams),
+        "one_stream": one_stream,
+        "A_equal_streams": res_multi["A"] == res["A"],
         "other_mode": other,
         "eager": eager,
         "plain": plain,

@@ -284,8 +284,9 @@ int tn_exec_run(tn_exec ex, void* stream, tn_result* results);
  * for that estimate and fills `results` (NULL: only wait).  Consecutive
  * estimates on one stream run back to back on the GPU (they share the
  * workspace in stream order), so the host's result handling and the next
- * issue overlap the GPU work.  Each submitted estimate's results are copied on
- * the device into one of two host slots: at most two may be outstanding
+ * issue overlap the GPU work.  Each submitted estimate's results go into one of
+ * two host slots (written there by the tail kernels with direct launches,
+ * copied there after a graph replay): at most two may be outstanding
  * (TN_ESTATE for a third), tickets are collected once each in submission
  * order (TN_ESTATE otherwise), and tn_exec_run needs none outstanding.
  * Submitting needs time_kernels = 0 (TN_EINVAL).  The stream must stay the

@@ -213,6 +213,9 @@ struct tn_exec_s {
     // host results: slot 0 written by the tail kernels; slots 1, 2 copies made
     // by submitted estimates (at most two outstanding), each results_stride bytes
     int64_t results_stride = 0;
+    // bytes past the results region where the next estimate's tail writes (a
+    // submitted estimate's slot, direct launches only; 0 otherwise)
+    int64_t res_shift = 0;
     hipEvent_t ev_done[2] = {nullptr, nullptr};
     int64_t next_ticket = 0, collected = 0;
     hipStream_t submit_stream = nullptr;   // stream of the outstanding submitted estimates
@@ -1943,7 +1946,7 @@ static void run_tail(tn_exec_s* ex, hipStream_t s) {
         }
     }
     launch_tail((const TailJob*)resolve(ex, ex->tail_jobs), (int)ex->plans.size(), ex->tail_blocks,
-                ex->tail_levels, (double*)resolve(ex, ex->tail_part), s);
+                ex->tail_levels, (double*)resolve(ex, ex->tail_part), ex->res_shift, s);
     HIPCHK(hipGetLastError());
 }
 
@@ -2990,11 +2993,24 @@ int tn_exec_submit(tn_exec exh, void* stream, int64_t* ticket) {
         if (ex->next_ticket != ex->collected && s != ex->submit_stream)
             fail(TN_EINVAL, "estimates outstanding on another stream: submit on the same stream or collect first");
         ex->submit_stream = s;
-        issue_estimate(ex, s);
         const int slot = (int)(ex->next_ticket & 1);
-        const int64_t n2 = ex->results_stride / 8;   // float2-sized words
-        launch_copy_c64((const float*)ex->results_dev,
-                        (float*)((char*)ex->results_dev + (1 + slot) * ex->results_stride), n2, s);
+        if (ex->opts.use_graph) {
+            // the captured tail writes the results region: copied to the slot
+            issue_estimate(ex, s);
+            const int64_t n2 = ex->results_stride / 8;   // float2-sized words
+            launch_copy_c64((const float*)ex->results_dev,
+                            (float*)((char*)ex->results_dev + (1 + slot) * ex->results_stride), n2, s);
+        } else {
+            // direct launches: the tail writes the slot itself
+            ex->res_shift = (1 + slot) * ex->results_stride;
+            try {
+                issue_estimate(ex, s);
+            } catch (...) {
+                ex->res_shift = 0;
+                throw;
+            }
+            ex->res_shift = 0;
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(ex->ev_done[slot], s));
         if (ticket) *ticket = ex->next_ticket;

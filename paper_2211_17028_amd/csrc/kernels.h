@@ -184,9 +184,11 @@ struct TailJob {
     int64_t block0;                // first block of this circuit in the term launch
     int32_t n_levels, pad_;
 };
-// d_part: blocks x (TN_MAX_LEVEL + 1) (sum, comp) pairs of scratch
+// d_part: blocks x (TN_MAX_LEVEL + 1) (sum, comp) pairs of scratch; the level
+// sums and the FP32 diagnostic value go res_shift bytes past the addresses in
+// the jobs (a results slot of a submitted estimate)
 void launch_tail(const TailJob* d_jobs, int n_jobs, int64_t blocks, int max_levels, double* d_part,
-                 hipStream_t s);
+                 int64_t res_shift, hipStream_t s);
 
 // Neumaier level sums over contiguous ranges [start[u], start[u+1]).
 void launch_level_sum(const double* x, const int64_t* starts, int n_levels, double* out_sum_comp,

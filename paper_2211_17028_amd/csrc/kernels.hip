@@ -776,6 +776,91 @@ struct GettSmem {
     int64_t a_step[32], b_step[32];
 };
 
+// One thread of a small step: column c of RPT consecutive rows (the column
+// operand's element is loaded once for all of them; the row operand's
+// elements are shared by the lanes of a wave, which hold consecutive
+// columns).  The loads of P inner indices are issued before their products, so
+// a thread waits once per P inner indices; products are added in inner-index
+// order.
+template <typename R, typename C2, int RPT>
+__device__ __forceinline__ void gett_rows(const GettJob& J, const int64_t* __restrict__ ak_lo,
+                                          const int64_t* __restrict__ bk_lo, const int64_t* __restrict__ a_step,
+                                          const int64_t* __restrict__ b_step, int64_t local) {
+    constexpr int RLOG = RPT == 1 ? 0 : RPT == 2 ? 1 : RPT == 4 ? 2 : 3;
+    constexpr int P = sizeof(R) == 4 ? (RPT == 1 ? 8 : RPT <= 4 ? 4 : 2) : (RPT <= 2 ? 4 : RPT == 4 ? 2 : 1);
+    const int m_log = J.m_log, n_log = J.n_log, k_log = J.k_log;
+    const int mn_log = m_log + n_log;
+    const int64_t k = int64_t(1) << k_log;
+    const int kc_log = k_log < 8 ? k_log : 8;
+    const int kc = 1 << kc_log;
+    const int nstep = k_log - kc_log;
+    const int64_t o = local * 256 + threadIdx.x;
+    if (o >= (J.n_inst << (mn_log - RLOG))) return;
+    const int64_t c = o & ((int64_t(1) << n_log) - 1);
+    const int64_t rest = o >> n_log;
+    const int64_t rg = rest & ((int64_t(1) << (m_log - RLOG)) - 1);
+    const int64_t inst = rest >> (m_log - RLOG);
+    const int64_t r0 = rg << RLOG;
+    const TN_GLOBAL C2* __restrict__ Ap = gload<C2>(J.A) + gload<int64_t>(J.oa)[inst] + deposit(r0, J.a_row, 0, m_log);
+    const TN_GLOBAL C2* __restrict__ Bp = gload<C2>(J.B) + gload<int64_t>(J.ob)[inst] + deposit(c, J.b_col, 0, n_log);
+    int64_t rlo[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) rlo[i] = deposit(i, J.a_row, 0, RLOG);
+    R sr[RPT], si[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) sr[i] = si[i] = 0;
+    int64_t ahh = 0, bhh = 0;
+    for (int64_t h = 0; h < k; h += kc) {
+        const TN_GLOBAL C2* __restrict__ Ah = Ap + ahh;
+        const TN_GLOBAL C2* __restrict__ Bh = Bp + bhh;
+        {
+            const int t = __builtin_ctzll(~(uint64_t)(h >> kc_log));
+            if (t < nstep) {
+                ahh += a_step[t];
+                bhh += b_step[t];
+            }
+        }
+        int p = 0;
+        for (; p + P <= kc; p += P) {
+            C2 b[P], a[P][RPT];
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                b[u] = gld(Bh + bk_lo[p + u]);
+                const int64_t ap = ak_lo[p + u];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) a[u][i] = gld(Ah + (rlo[i] + ap));
+            }
+#pragma unroll
+            for (int u = 0; u < P; ++u)
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    sr[i] += a[u][i].x * b[u].x - a[u][i].y * b[u].y;
+                    si[i] += a[u][i].x * b[u].y + a[u][i].y * b[u].x;
+                }
+        }
+        for (; p < kc; ++p) {
+            const C2 b = gld(Bh + bk_lo[p]);
+            const int64_t ap = ak_lo[p];
+            C2 a[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) a[i] = gld(Ah + (rlo[i] + ap));
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                sr[i] += a[i].x * b.x - a[i].y * b.y;
+                si[i] += a[i].x * b.y + a[i].y * b.x;
+            }
+        }
+    }
+    TN_GLOBAL C2* __restrict__ Cp = gstore<C2>(J.C) + ((inst << mn_log) + (r0 << n_log) + c);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        C2 out;
+        out.x = sr[i];
+        out.y = si[i];
+        gst(Cp + ((int64_t)i << n_log), out);
+    }
+}
+
 template <typename R, typename C2>
 __device__ __forceinline__ void gett_block(const GettJob* __restrict__ jp, GettSmem& sm) {
     GettJob& J = sm.J;
@@ -840,97 +925,34 @@ __device__ __forceinline__ void gett_block(const GettJob* __restrict__ jp, GettS
                     }
             }
         }
-        red_r[threadIdx.x] = (double)sr;
-        red_i[threadIdx.x] = (double)si;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                red_r[threadIdx.x] += red_r[threadIdx.x + w];
-                red_i[threadIdx.x] += red_i[threadIdx.x + w];
-            }
-            __syncthreads();
+        // FP64 sum in a fixed order: a butterfly within each wave (both lanes
+        // of a pair form the same sum), then the four waves in order
+        double vr = (double)sr, vi = (double)si;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            vr += __shfl_xor(vr, off);
+            vi += __shfl_xor(vi, off);
         }
+        if ((threadIdx.x & 63) == 0) {
+            red_r[threadIdx.x >> 6] = vr;
+            red_i[threadIdx.x >> 6] = vi;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             C2 out;
-            out.x = (R)red_r[0];
-            out.y = (R)red_i[0];
+            out.x = (R)(((red_r[0] + red_r[1]) + red_r[2]) + red_r[3]);
+            out.y = (R)(((red_i[0] + red_i[1]) + red_i[2]) + red_i[3]);
             gst(gstore<C2>(J.C) + o, out);
         }
         return;
     }
-    // one thread: column c of 2^rpt_log consecutive rows (the column operand's
-    // element is loaded once for all of them; the row operand's elements are
-    // shared by the lanes of a wave, which hold consecutive columns)
-    constexpr int RMAX = 8;
-    const int rpt_log = J.rpt_log;
-    const int rpt = 1 << rpt_log;
-    const int64_t o = local * 256 + threadIdx.x;
-    if (o >= (J.n_inst << (mn_log - rpt_log))) return;
-    const int64_t c = o & ((int64_t(1) << n_log) - 1);
-    const int64_t rest = o >> n_log;
-    const int64_t rg = rest & ((int64_t(1) << (m_log - rpt_log)) - 1);
-    const int64_t inst = rest >> (m_log - rpt_log);
-    const int64_t r0 = rg << rpt_log;
-    const TN_GLOBAL C2* __restrict__ Ap = gload<C2>(J.A) + gload<int64_t>(J.oa)[inst] + deposit(r0, J.a_row, 0, m_log);
-    const TN_GLOBAL C2* __restrict__ Bp = gload<C2>(J.B) + gload<int64_t>(J.ob)[inst] + deposit(c, J.b_col, 0, n_log);
-    int64_t rlo[RMAX];
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i) rlo[i] = i < rpt ? deposit(i, J.a_row, 0, rpt_log) : 0;
-    R sr[RMAX], si[RMAX];
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i) sr[i] = si[i] = 0;
-    int64_t ahh = 0, bhh = 0;
-    for (int64_t h = 0; h < k; h += kc) {
-        const TN_GLOBAL C2* __restrict__ Ah = Ap + ahh;
-        const TN_GLOBAL C2* __restrict__ Bh = Bp + bhh;
-        {
-            const int t = __builtin_ctzll(~(uint64_t)(h >> kc_log));
-            if (t < nstep) {
-                ahh += a_step[t];
-                bhh += b_step[t];
-            }
-        }
-        if (rpt == 1 && kc >= 4) {
-            // one row: four inner indices per round, loads issued together
-            for (int p = 0; p < kc; p += 4) {
-                C2 a[4], b[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a[u] = gld(Ah + ak_lo[p + u]);
-                    b[u] = gld(Bh + bk_lo[p + u]);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    sr[0] += a[u].x * b[u].x - a[u].y * b[u].y;
-                    si[0] += a[u].x * b[u].y + a[u].y * b[u].x;
-                }
-            }
-        } else {
-            for (int p = 0; p < kc; ++p) {
-                const C2 b = gld(Bh + bk_lo[p]);
-                const int64_t ap = ak_lo[p];
-                C2 a[RMAX];
-#pragma unroll
-                for (int i = 0; i < RMAX; ++i)
-                    if (i < rpt) a[i] = gld(Ah + (rlo[i] + ap));
-#pragma unroll
-                for (int i = 0; i < RMAX; ++i)
-                    if (i < rpt) {
-                        sr[i] += a[i].x * b.x - a[i].y * b.y;
-                        si[i] += a[i].x * b.y + a[i].y * b.x;
-                    }
-            }
-        }
+    // one thread: column c of 2^rpt_log consecutive rows
+    switch (J.rpt_log) {
+        case 0: gett_rows<R, C2, 1>(J, ak_lo, bk_lo, a_step, b_step, local); break;
+        case 1: gett_rows<R, C2, 2>(J, ak_lo, bk_lo, a_step, b_step, local); break;
+        case 2: gett_rows<R, C2, 4>(J, ak_lo, bk_lo, a_step, b_step, local); break;
+        default: gett_rows<R, C2, 8>(J, ak_lo, bk_lo, a_step, b_step, local); break;
     }
-    TN_GLOBAL C2* __restrict__ Cp = gstore<C2>(J.C) + ((inst << mn_log) + (r0 << n_log) + c);
-#pragma unroll
-    for (int i = 0; i < RMAX; ++i)
-        if (i < rpt) {
-            C2 out;
-            out.x = sr[i];
-            out.y = si[i];
-            gst(Cp + ((int64_t)i << n_log), out);
-        }
 }
 
 // One launch for the small steps of one tree level: block b runs job
@@ -1528,52 +1550,6 @@ __global__ __launch_bounds__(256) void k_permute(PermArgs p) {
 // X = w |amplitude|^2 (a doubled network's value is the amplitude itself:
 // X = w Re(amplitude)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double finalize_term(const FinalizeArgs& f, int64_t t) {
-    const int32_t li = f.live_index[t];
-    if (li < 0) {
-        f.x_out[t] = 0.0;
-        f.amp_out[2 * t] = 0.0f;
-        f.amp_out[2 * t + 1] = 0.0f;
-        return 0.0;
-    }
-    double ar = f.scalar_re, ai = f.scalar_im;
-    const bool hi = (t == f.zero_term);
-    for (int c = 0; c < f.n_clusters; ++c) {
-        const int64_t j = f.root_idx[(int64_t)li * f.n_clusters + c];
-        double vr, vi;
-        if (hi) {
-            const double2* r64 = (const double2*)f.root64_ptrs[c];
-            vr = r64[j].x;
-            vi = r64[j].y;
-        } else {
-            const float2* r32 = (const float2*)f.root_ptrs[c];
-            vr = (double)r32[j].x;
-            vi = (double)r32[j].y;
-        }
-        const double nr = ar * vr - ai * vi;
-        const double ni = ar * vi + ai * vr;
-        ar = nr;
-        ai = ni;
-    }
-    const double x = f.w[t] * (f.re_value ? ar : ar * ar + ai * ai);
-    f.x_out[t] = x;
-    f.amp_out[2 * t] = (float)ar;
-    f.amp_out[2 * t + 1] = (float)ai;
-    if (hi && f.x0_fp32_out) {
-        // the same term from the FP32 batch's roots (diagnostic)
-        double br = f.scalar_re, bi = f.scalar_im;
-        for (int c = 0; c < f.n_clusters; ++c) {
-            const float2 v = ((const float2*)f.root_ptrs[c])[f.root_idx[(int64_t)li * f.n_clusters + c]];
-            const double nr = br * v.x - bi * v.y;
-            const double ni = br * v.y + bi * v.x;
-            br = nr;
-            bi = ni;
-        }
-        *f.x0_fp32_out = f.w[t] * (f.re_value ? br : br * br + bi * bi);
-    }
-    return x;
-}
-
 // ---------------------------------------------------------------------------
 // K4: Neumaier-compensated level sums in a fixed order (deterministic): each
 // thread sums a fixed strided subset, then pairs (sum, comp) are combined in a
@@ -1683,16 +1659,97 @@ __device__ __forceinline__ int tail_job_of(const TailJob* __restrict__ jobs, int
     return lo;
 }
 
+// Finalize of one block of 256 terms (FP64): amplitude = scalar * prod of the
+// term's cluster values in cluster order, X = w |amplitude|^2 (a doubled
+// network's value is the amplitude itself: X = w Re(amplitude)).  The term
+// `zero_term` takes its cluster values from the FP64 roots, and its product
+// over the FP32 roots goes to the results as a diagnostic.  The clusters' root
+// addresses are staged in LDS (kFinPtrs per round), and each thread loads
+// kFinBatch cluster indices, then their values, before multiplying, so a term
+// costs two dependent loads per batch.
+constexpr int kFinBatch = 8;
+constexpr int kFinPtrs = 64;
+
 __global__ __launch_bounds__(256) void k_tail_terms(const TailJob* __restrict__ jobs, int n_jobs,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, int64_t res_shift) {
     __shared__ double ss[256];
     __shared__ double cc[256];
+    __shared__ const TN_GLOBAL float2* rp32[kFinPtrs];
+    __shared__ const TN_GLOBAL double2* rp64[kFinPtrs];
     const int64_t b = blockIdx.x;
-    const TailJob J = jobs[tail_job_of(jobs, n_jobs, b)];
+    const TailJob& J = jobs[tail_job_of(jobs, n_jobs, b)];
+    const FinalizeArgs& f = J.f;
     const int64_t t0 = (b - J.block0) * 256;
     const int64_t t = t0 + threadIdx.x;
-    const double x = t < J.f.n_terms ? finalize_term(J.f, t) : 0.0;
-    const int64_t t_end = t0 + 256 < J.f.n_terms ? t0 + 256 : J.f.n_terms;
+    const bool in = t < f.n_terms;
+    const int32_t li = in ? gload<int32_t>(f.live_index)[t] : -1;
+    const bool hi = in && t == f.zero_term;
+    const int ncl = f.n_clusters;
+    const TN_GLOBAL int32_t* __restrict__ ri = gload<int32_t>(f.root_idx) + (int64_t)(li < 0 ? 0 : li) * ncl;
+    double ar = f.scalar_re, ai = f.scalar_im;      // over the FP32 roots
+    double hr = ar, hm = ai;                        // over the FP64 roots (zero_term)
+    for (int c0 = 0; c0 < ncl; c0 += kFinPtrs) {
+        const int nc = ncl - c0 < kFinPtrs ? ncl - c0 : kFinPtrs;
+        __syncthreads();                            // the previous round's addresses are read
+        if ((int)threadIdx.x < nc) {            // (FP64 addresses are 0 without the FP64 pass)
+            const int64_t a32 = gload<int64_t>(f.root_ptrs)[c0 + threadIdx.x];
+            const int64_t a64 = gload<int64_t>(f.root64_ptrs)[c0 + threadIdx.x];
+            rp32[threadIdx.x] = gload<float2>((const void*)a32);
+            rp64[threadIdx.x] = gload<double2>((const void*)a64);
+        }
+        __syncthreads();
+        if (li < 0) continue;
+        for (int q0 = 0; q0 < nc; q0 += kFinBatch) {
+            int32_t j[kFinBatch];
+            float2 v[kFinBatch];
+            // loads past the round's last cluster repeat it (in bounds, not used):
+            // unconditional loads are all issued before the first wait
+#pragma unroll
+            for (int q = 0; q < kFinBatch; ++q) j[q] = ri[c0 + (q0 + q < nc ? q0 + q : nc - 1)];
+#pragma unroll
+            for (int q = 0; q < kFinBatch; ++q) v[q] = gld(rp32[q0 + q < nc ? q0 + q : nc - 1] + j[q]);
+#pragma unroll
+            for (int q = 0; q < kFinBatch; ++q)
+                if (q0 + q < nc) {
+                    const double vr = (double)v[q].x, vi = (double)v[q].y;
+                    const double nr = ar * vr - ai * vi;
+                    const double ni = ar * vi + ai * vr;
+                    ar = nr;
+                    ai = ni;
+                }
+            if (hi) {
+                double2 w[kFinBatch];
+#pragma unroll
+                for (int q = 0; q < kFinBatch; ++q) w[q] = gld(rp64[q0 + q < nc ? q0 + q : nc - 1] + j[q]);
+#pragma unroll
+                for (int q = 0; q < kFinBatch; ++q)
+                    if (q0 + q < nc) {
+                        const double nr = hr * w[q].x - hm * w[q].y;
+                        const double ni = hr * w[q].y + hm * w[q].x;
+                        hr = nr;
+                        hm = ni;
+                    }
+            }
+        }
+    }
+    double x = 0.0;
+    if (in) {
+        if (li < 0) {
+            f.x_out[t] = 0.0;
+            f.amp_out[2 * t] = 0.0f;
+            f.amp_out[2 * t + 1] = 0.0f;
+        } else {
+            const double pr = hi ? hr : ar, pi = hi ? hm : ai;
+            const double wt = f.w[t];
+            x = wt * (f.re_value ? pr : pr * pr + pi * pi);
+            f.x_out[t] = x;
+            f.amp_out[2 * t] = (float)pr;
+            f.amp_out[2 * t + 1] = (float)pi;
+            if (hi && f.x0_fp32_out)
+                *(double*)((char*)f.x0_fp32_out + res_shift) = wt * (f.re_value ? ar : ar * ar + ai * ai);
+        }
+    }
+    const int64_t t_end = t0 + 256 < f.n_terms ? t0 + 256 : f.n_terms;
     double* out = part + b * (2 * (TN_MAX_LEVEL + 1));
     for (int u = 0; u < J.n_levels; ++u) {
         const int64_t lb = J.starts[u], le = J.starts[u + 1];
@@ -1712,7 +1769,8 @@ __global__ __launch_bounds__(256) void k_tail_terms(const TailJob* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_tail_sums(const TailJob* __restrict__ jobs, const double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_tail_sums(const TailJob* __restrict__ jobs, const double* __restrict__ part,
+                                                   int64_t res_shift) {
     __shared__ double ss[256];
     __shared__ double cc[256];
     const TailJob J = jobs[blockIdx.x];
@@ -1727,8 +1785,9 @@ __global__ __launch_bounds__(256) void k_tail_sums(const TailJob* __restrict__ j
     }
     neumaier_block_shfl<256>(s, c, ss, cc);
     if (threadIdx.x == 0) {
-        J.sums[2 * u] = s + c;
-        J.sums[2 * u + 1] = c;
+        double* sums = (double*)((char*)J.sums + res_shift);
+        sums[2 * u] = s + c;
+        sums[2 * u + 1] = c;
     }
 }
 
@@ -1942,11 +2001,12 @@ void launch_level_sum(const double* x, const int64_t* starts, int n_levels, doub
 }
 
 void launch_tail(const TailJob* d_jobs, int n_jobs, int64_t blocks, int max_levels, double* d_part,
-                 hipStream_t s) {
+                 int64_t res_shift, hipStream_t s) {
     if (n_jobs == 0) return;
-    if (blocks > 0) hipLaunchKernelGGL(k_tail_terms, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs, d_part);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_tail_terms, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs, d_part, res_shift);
     hipLaunchKernelGGL(k_tail_sums, dim3((unsigned)n_jobs, (unsigned)max_levels), dim3(256), 0, s, d_jobs,
-                       (const double*)d_part);
+                       (const double*)d_part, res_shift);
 }
 
 void launch_slot_fill(const SlotFillArgs& a, hipStream_t s) {
