@@ -997,6 +997,10 @@ struct Builder {
                                   step_flops >= kMfmaMinFlops;
             bool to_tile = (big && step_flops >= kTileMinFlops) || heavy || long_sum;
             if (!fp64 && small_levels && small_levels->count(st.level)) to_tile = false;
+            // inner sums under 8 terms would fill less than one staged chunk of a
+            // matrix-core tile (the rest zeros), at under 2 flops per byte moved:
+            // such FP32 steps read and write at the small-step kernel's rate
+            if (!fp64 && rk < 3) to_tile = false;
             if (grouping && mode != 2 && to_tile) {
                 const int saved_split = max_ksplit;
                 if (long_sum && !big && !heavy && !ksplit_user) max_ksplit = kSplitLongMax;

@@ -9,6 +9,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 
 #include "kernels.h"
@@ -472,8 +473,18 @@ void k_gemm_mfma_g(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Tuning of the grouped matrix-core kernel (measured on the 25-qubit workload's
+// 128 x 32 level, 848 slices of 256 x 16 x 256 and 134 of 512 x 16 x 64):
+//   MFMA_GROUP_WAVES   register budget: two waves per SIMD leave room for the
+//                      second register set of the two-deep chunk pipeline
+//                      (three spill it); 113 us against 117 us at three waves
+//                      with one chunk of read-ahead;
+//   MFMA_PREFETCH2     loads run two chunks ahead of the MFMAs (the operands of
+//                      tiles that miss in L2 come from HBM in a few us);
+//   MFMA_SKIP_PAD      column blocks past a tile's last slice skip their MFMAs
+//                      (a fifth of that level's tiles hold one slice of two).
 #ifndef MFMA_GROUP_WAVES
-#define MFMA_GROUP_WAVES 3
+#define MFMA_GROUP_WAVES 2
 #endif
 #ifndef MFMA_GROUP_WAVES_128X64
 #define MFMA_GROUP_WAVES_128X64 4
@@ -486,6 +497,12 @@ void k_gemm_mfma_g(GemmArgs g) {
 #endif
 #ifndef MFMA_GROUP_SCHED
 #define MFMA_GROUP_SCHED 1
+#endif
+#ifndef MFMA_PREFETCH2
+#define MFMA_PREFETCH2 1
+#endif
+#ifndef MFMA_SKIP_PAD
+#define MFMA_SKIP_PAD 1
 #endif
 // Grouped matrix-core contractions (FP32 complex on mfma_f32_32x32x2f32, the
 // real embedding of K1).  One block per tile descriptor; the tile's row and
@@ -677,20 +694,23 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     // on 128 x 64 tiles (held to four waves per SIMD, whose 128-register budget
     // the full read-ahead would exceed; a few spills remain outside the loop)
     constexpr int RA = (BM == 128 && BNC == 64) ? MFMA_RA_128X64 : BKC;
-    auto compute = [&](int buf) {
+    // TNA: this wave's column blocks that hold outputs (the others are padding
+    // past the tile's last slice or column, skipped)
+    auto compute = [&](int buf, auto tna) {
+        constexpr int TNA = decltype(tna)::value;
         const float* as = As + buf * ABUF;
         const float* bs = Bs + buf * BBUF;
 #pragma unroll
         for (int g = 0; g < BKC; g += RA) {
             // all operands of the group read first, so the LDS reads of later
             // inner indices are in flight while the MFMAs of earlier ones run
-            float a[RA][TM], b[RA][TN];
+            float a[RA][TM], b[RA][TNA];
 #pragma unroll
             for (int p = 0; p < RA; ++p) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) a[p][i] = as[(g + p) * AP + a_off[i]];
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
+                for (int j = 0; j < TNA; ++j)
                     b[p][j] = __uint_as_float(__float_as_uint(bs[(g + p) * BP + b_off[j]]) ^ b_sign);
             }
 #pragma unroll
@@ -698,32 +718,67 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
-                    for (int j = 0; j < TN; ++j)
+                    for (int j = 0; j < TNA; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][i], b[p][j], acc[i][j], 0, 0, 0);
             // keep the reads ahead of the MFMAs: DS reads of inner index p + 1
             // are scheduled before the MFMAs of inner index p
 #if MFMA_GROUP_SCHED
-            __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, TM + TNA, 0);
 #pragma unroll
             for (int p = 0; p < RA; ++p) {
-                if (p + 1 < RA) __builtin_amdgcn_sched_group_barrier(0x100, TM + TN, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
+                if (p + 1 < RA) __builtin_amdgcn_sched_group_barrier(0x100, TM + TNA, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, TM * TNA, 0);
             }
 #endif
         }
     };
+    // column blocks of 16 holding outputs (padding is a suffix of the tile's
+    // columns: slices past cnt, columns past n): all TN, the first only, or none
+    int tn_act = 0;
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+        if (col_c[wn * (TN * 16) + j * 16] >= 0) tn_act = j + 1;
+    auto compute_active = [&](int buf) {
+        if (!MFMA_SKIP_PAD || tn_act == TN) compute(buf, std::integral_constant<int, TN>{});
+        else if (TN > 1 && tn_act == 1) compute(buf, std::integral_constant<int, 1>{});
+    };
     const int64_t nchunks = c_end - c_begin;
-    // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
-    float2 ra[AE], rb[BE];
-    load(0, ra, rb);
-    stash(0, ra, rb);
-    __syncthreads();
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-        const int buf = (int)(ch & 1);
-        if (ch + 1 < nchunks) load((ch + 1) * BKC, ra, rb);
-        compute(buf);
-        if (ch + 1 < nchunks) stash(buf ^ 1, ra, rb);
+    if (MFMA_PREFETCH2 && !(BM == 128 && BNC == 64)) {
+        // pipeline two chunks deep: LDS holds chunk ch, registers hold chunk
+        // ch + 1, and the loads of chunk ch + 2 are in flight during chunk ch's
+        // MFMAs (a chunk's loads have two chunks of matrix-core work to arrive
+        // from HBM when they miss in L2).  Chunk c is staged in and read from
+        // LDS buffer c & 1; the two register sets alternate with it.  (The
+        // 128 x 64 tile's register budget holds one set.)
+        float2 ra0[AE], rb0[BE], ra1[AE], rb1[BE];
+        load(0, ra0, rb0);
+        stash(0, ra0, rb0);
+        if (nchunks > 1) load(BKC, ra1, rb1);
         __syncthreads();
+        for (int64_t ch = 0; ch < nchunks; ch += 2) {
+            if (ch + 2 < nchunks) load((ch + 2) * BKC, ra0, rb0);
+            compute_active(0);
+            if (ch + 1 < nchunks) stash(1, ra1, rb1);
+            __syncthreads();
+            if (ch + 1 >= nchunks) break;
+            if (ch + 3 < nchunks) load((ch + 3) * BKC, ra1, rb1);
+            compute_active(1);
+            if (ch + 2 < nchunks) stash(0, ra0, rb0);
+            __syncthreads();
+        }
+    } else {
+        // pipeline: LDS holds chunk ch while the loads of chunk ch + 1 are in flight
+        float2 ra[AE], rb[BE];
+        load(0, ra, rb);
+        stash(0, ra, rb);
+        __syncthreads();
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            const int buf = (int)(ch & 1);
+            if (ch + 1 < nchunks) load((ch + 1) * BKC, ra, rb);
+            compute_active(buf);
+            if (ch + 1 < nchunks) stash(buf ^ 1, ra, rb);
+            __syncthreads();
+        }
     }
 
     // split inner sum: this block's part goes to its row-major [BM][BNC] partial
