@@ -346,10 +346,23 @@ def pruning_value(c5, plan5, terms5, ms_full, ms_full_seq, reps):
     total = sum(d[2]["A"][-1] for d in data)
     tau = pruner.threshold(pruner.score_candidates(net, f_dev.cpu().numpy(), "mlp"), xs, 1e-7 * total)
     full = tn.tn_exec_prepare([plan5], [terms5], tn.exec_opts(use_graph=False)).run()[0]
-    # end to end, twice (the first warms the allocator); the second is reported
+    # end to end from the plan, twice each (the first warms the allocator; the
+    # second is reported): the full estimate (enumeration, prepare, one run)
+    # and the pruned one (level-1 pre-pass, features, scores, pruned
+    # enumeration, prepare, one run)
     for _ in range(2):
-        sel = pruner.pruned_estimate(c5, net, tau, "mlp")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tf = tn.tn_terms_enumerate(plan5, c5.level)
+        tn.tn_exec_prepare([plan5], [tf], tn.exec_opts(use_graph=False)).run()
+        torch.cuda.synchronize()
+        full_e2e_s = time.perf_counter() - t0
+    for _ in range(2):
+        sel = pruner.pruned_estimate(c5, net, tau, "mlp", plan=plan5)
     e2e_s = sel["seconds"]
+    for _ in range(2):
+        sel_np = pruner.pruned_estimate(c5, net, tau, "mlp")
+    e2e_plan_s = sel_np["seconds"]
     keep = sel["keep"]
     tp = tn.tn_terms_enumerate(plan5, c5.level, keep=keep, min_level=2)
     ex = tn.tn_exec_prepare([plan5], [tp], tn.exec_opts(use_graph=False))
@@ -376,10 +389,15 @@ def pruning_value(c5, plan5, terms5, ms_full, ms_full_seq, reps):
             "ms_pruned": ms, "ms_full": ms_full, "time_factor_estimate_only": ms_full / ms,
             "ms_pruned_sequential": ms_seq, "ms_full_sequential": ms_full_seq,
             "end_to_end_ms": 1000.0 * e2e_s,
-            "time_factor": ms_full_seq / (1000.0 * e2e_s),
-            "time_factor_note": "full estimate (prepared, one after another) / pruned estimate end to end "
-                                "from the plan (level-1 pre-pass, features, network scores, pruned "
-                                "enumeration, prepare, one estimate)",
+            "end_to_end_full_ms": 1000.0 * full_e2e_s,
+            "end_to_end_with_plan_build_ms": 1000.0 * e2e_plan_s,
+            "time_factor": full_e2e_s / e2e_s,
+            "time_factor_note": "end to end from the plan: full estimate (enumeration, prepare, one run) / "
+                                "pruned estimate (level-1 pre-pass, features, network scores, pruned "
+                                "enumeration, prepare, one run)",
+            "time_factor_prepared": ms_full_seq / (1000.0 * e2e_s),
+            "time_factor_prepared_note": "full estimate with its schedule already prepared (one after another) / "
+                                         "pruned estimate end to end from the plan",
             "error_vs_full": full["A"][-1] - r["A"][-1],
             "error_vs_oracle_full": None if g is None else g[-1] - r["A"][-1],
             "level1_error_vs_oracle_full": None if g is None else g[-1] - full["A"][1],

@@ -90,15 +90,17 @@ def score_candidates(mlp, feats, policy):
     return mlp.forward(torch.from_numpy(np.ascontiguousarray(feats, dtype=np.float32)).cuda()).cpu().numpy()
 
 
-def pruned_estimate(circ, mlp, tau, policy="mlp", level=None):
+def pruned_estimate(circ, mlp, tau, policy="mlp", level=None, plan=None):
     """Level-1 pre-pass, scoring, pruned estimate.  Returns dict with the
     result, the kept count, the keep flags of the candidates (enumeration
     order), the pruned run's per-term values and the wall time of the whole
-    procedure."""
+    procedure (from the plan when `plan` is given: the plan is what the full
+    estimate needs too)."""
     import torch
     level = circ.level if level is None else level
     t0 = time.perf_counter()
-    plan = tn.tn_plan_build(circ, level)
+    if plan is None:
+        plan = tn.tn_plan_build(circ, level)
     t1 = tn.tn_terms_enumerate(plan, 1)
     ex1 = tn.tn_exec_prepare([plan], [t1], tn.exec_opts(use_graph=False))
     ex1.run()
