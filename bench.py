@@ -478,10 +478,39 @@ def kernel_pass(plans, terms, steps, warmup, tune):
         re_ = ex.run()
     torch.cuda.synchronize()
     eel = time.perf_counter() - t0
+    desc = ex.describe()
     stats = ex.kernel_stats(reset=True)
-    launches = len([L for L in ex.describe()["launches"] if L["phase"] in ("batch", "batch64", "tail")])
+    launches = len([L for L in desc["launches"] if L["phase"] in ("batch", "batch64", "tail")])
     del ex
+    kernel_pass.last_desc = desc
     return stats, 1000.0 * eel / steps, re_, launches
+
+
+def launch_floor(n_launch, ex, reps=50):
+    """GPU-side latency of an estimate against the floor of its launch count.
+    Both are queued behind a 1 ms spin kernel, so the host's issue time is
+    hidden and the events time the GPU alone: a chain of `n_launch` dependent
+    one-element kernels (torch's in-place add) on one stream, and one estimate
+    of the prepared schedule `ex` (its own events, tn_exec_timing).  Medians of
+    `reps` (microseconds)."""
+    import torch
+    x = torch.zeros(1, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    floor, est = [], []
+    for _ in range(reps):
+        torch.cuda._sleep(2_000_000)
+        e0.record()
+        for _ in range(n_launch):
+            x.add_(1.0)
+        e1.record()
+        torch.cuda.synchronize()
+        floor.append(1000.0 * e0.elapsed_time(e1))
+        torch.cuda._sleep(2_000_000)
+        ex.run()
+        est.append(1000.0 * ex.timing()[0])
+    floor.sort()
+    est.sort()
+    return floor[len(floor) // 2], est[len(est) // 2]
 
 
 def roofline_entry(stats, steps, workload):
@@ -509,6 +538,31 @@ def roofline_entry(stats, steps, workload):
                    "gbs": v["bytes"] / max(1e-9, v["ms"] * 1e-3) / 1e9}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
     return roof, kernels
+
+
+def launch_roofline(desc, workload):
+    """Roofline entry of the FP32 chain's longest launch (one launch of one tree
+    level, durations from the kernel pass's HIP event pairs): its algorithmic
+    flops (matrix-core launches) or bytes (others) per run / its average
+    duration.  Secondary lines use it because the autotuner can give two levels
+    the same tile shape, whose per-kernel totals then mix both launches."""
+    cand = [L for L in desc["launches"] if L["phase"] == "batch" and L.get("t_n", 0) > 0 and not L["fp64"]]
+    if not cand:
+        return None
+    L = max(cand, key=lambda x: x["t_ms"])
+    name = L.get("kernel", "")
+    st = {"flops": L["flops"] * L["t_n"], "bytes": L["bytes"] * L["t_n"], "ms": L["t_ms"], "launches": L["t_n"]}
+    roof = roofline_of(name, st, L["t_n"])
+    roof["level"] = L["level"]
+    roof["tiles_or_blocks"] = L.get("n_tiles", L.get("blocks"))
+    grids = None
+    rec = traffic_record_path(workload)
+    if os.path.exists(rec):
+        with open(rec) as f:
+            grids = json.load(f).get("grids")
+    tiles = roof["tiles_or_blocks"]
+    roof["traffic"] = measured_traffic(name, workload) if grids and tiles in grids else None
+    return roof
 
 
 def golden_err(cfg, A):
@@ -547,6 +601,12 @@ def secondary_line(cfg, args, with_roofline=False, with_plain=False):
     if with_roofline:
         stats, eager_ms, _, n_launch = kernel_pass(plans, terms, steps, max(1, args.warmup), not args.no_tune)
         roof, kernels = roofline_entry(stats, steps, name)
+        roof_l = launch_roofline(kernel_pass.last_desc, name)
+        if roof_l is not None:
+            for key in ("fp64_side_kernels", "fp32_matrix_kernels"):
+                if key in roof:
+                    roof_l[key] = roof[key]
+            roof = roof_l
         line.update({"roofline": roof, "kernels": kernels, "launches_per_estimate": n_launch,
                      "flops_per_estimate": sum(v["flops"] for v in stats.values()) / steps})
     if with_plain:
@@ -719,6 +779,9 @@ def main():
     eager = {"value": n_contracted / (eager_ms * 1e-3), "ms_per_step": eager_ms, "A_equal": re_[0]["A"] == res["A"],
              "note": "direct launches with a HIP event pair per launch (kernel durations below)"}
     err = golden_err(5, res["A"])
+    ex_f = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=False, tune=not args.no_tune))
+    floor_us, est_gpu_us = launch_floor(n_launch, ex_f)
+    del ex_f
 
     plain = None
     if not (args.no_plain or args.headline_only):
@@ -798,6 +861,13 @@ def main():
         "flops_per_estimate": sum(v["flops"] for v in stats.values()) / args.steps,
         "flops_per_term_plain": info["flops_per_term"],
         "roofline": roof,
+        "latency_floor": {"launches": n_launch, "floor_us": floor_us, "estimate_gpu_us": est_gpu_us,
+                          "frac": floor_us / est_gpu_us,
+                          "note": "GPU-side times, both queued behind a spin kernel so the host's issue time is "
+                                  "hidden (median of 50): floor_us = a chain of as many dependent one-element "
+                                  "kernels on one stream, what an estimate of this many launches cannot go "
+                                  "below on this GPU; estimate_gpu_us = one estimate of the prepared schedule; "
+                                  "frac = floor / estimate"},
         "kernels": kernels,
         "timed": ("hipGraph replays, two estimates in flight (submit / collect)" if args.graph or args.streams < 2
                   else f"direct launches, {args.streams} streams with one prepared schedule each, estimates "

@@ -294,13 +294,25 @@ int tn_exec_run(tn_exec ex, void* stream, tn_result* results);
 int tn_exec_submit(tn_exec ex, void* stream, int64_t* ticket);
 int tn_exec_collect(tn_exec ex, int64_t ticket, tn_result* results);
 
+/* `count` estimates of a prepared schedule on `stream` in one call: issued back
+ * to back with at most two in flight (as tn_exec_submit / tn_exec_collect), the
+ * results of estimate i and packed plan p written to results[i * n + p] (host
+ * array of count * n tn_result, caller-owned); returns when the last one has
+ * finished.  Every estimate recomputes Algorithm 1's level sums from the
+ * resident inputs (Section IV), as tn_exec_run does.  Needs no estimate
+ * outstanding (TN_ESTATE) and time_kernels = 0 (TN_EINVAL); count < 0 or a null
+ * results array with count > 0 is TN_EINVAL.  On an error nothing is left
+ * outstanding. */
+int tn_exec_run_many(tn_exec ex, void* stream, int64_t count, tn_result* results);
+
 /* Device pointer to the per-term values X_t (float64, concatenated over the
  * packed plans in order) and to the per-term amplitudes a_t (complex64 pairs),
  * valid after tn_exec_run. */
 int tn_exec_outputs(tn_exec ex, const double** d_x, const float** d_amp, int64_t* n_total);
 
 /* Fill up to `max` entries of per-kernel statistics; *n receives the count.
- * reset != 0 clears the accumulators after reading. */
+ * reset != 0 clears the accumulators after reading (the per-launch totals that
+ * tn_exec_describe reports as t_ms / t_n included). */
 int tn_exec_kernel_stats(tn_exec ex, int32_t max, tn_kernel_stat* out, int32_t* n, int32_t reset);
 
 /* Copy the per-term values X_t (float64) and amplitudes a_t (complex64 as
@@ -484,7 +496,8 @@ int tn_plan_noise(tn_plan plan, int32_t s, double* d, tn_c128* k, double* rate);
 int tn_plan_describe(tn_plan plan, char* buf, size_t* len);
 
 /* JSON description of a prepared schedule's steps (shapes, instances,
- * modes) into buf; *len receives the needed size. */
+ * modes; with time_kernels, each launch's accumulated duration t_ms over t_n
+ * runs) into buf; *len receives the needed size. */
 int tn_exec_describe(tn_exec ex, char* buf, size_t* len);
 
 /* The staged constant region of a prepared (or size-queried) schedule: fixed

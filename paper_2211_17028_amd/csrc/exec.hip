@@ -125,6 +125,8 @@ struct Launch {
     int tile_hint = -1;
     int kclass = -1;
     double flops = 0, bytes = 0;   // algorithmic work of this launch
+    double t_ms = 0;               // time_kernels: accumulated duration and count of this launch
+    int64_t t_n = 0;
     int plan = 0;
     int plain_root = 0;            // PLAIN mode: output offset advances per term
     int64_t plain_root_stride = 0;
@@ -2043,7 +2045,7 @@ static std::string describe_exec(const tn_exec_s* ex) {
     bool first = true;
     auto emit = [&](const Launch& L, const char* phase) {
         os << (first ? "" : ",") << "{\"phase\":\"" << phase << "\",\"kind\":" << L.kind << ",\"fp64\":" << L.fp64
-           << ",\"plan\":" << L.plan << ",\"level\":" << L.level;
+           << ",\"plan\":" << L.plan << ",\"level\":" << L.level << ",\"t_ms\":" << L.t_ms << ",\"t_n\":" << L.t_n;
         first = false;
         if (L.kind == L_GEMM)
             os << ",\"m_log\":" << L.g.m_log << ",\"n_log\":" << L.g.n_log << ",\"k_log\":" << L.g.k_log
@@ -2980,45 +2982,70 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
                 st.second += dt;
                 ex->kflops[L.kclass] += L.flops;
                 ex->kbytes[L.kclass] += L.bytes;
+                L.t_ms += dt;
+                L.t_n += 1;
             }
         if (results) fill_results(ex, ex->results_host, results);
     });
 }
 
+}  // extern "C"
+
+namespace tn {
+
+// One submitted estimate (tn_exec_submit's body): issued on s, its results
+// written into host slot next_ticket & 1.
+static int64_t submit_one(tn_exec_s* ex, hipStream_t s) {
+    if (ex->opts.time_kernels) fail(TN_EINVAL, "per-launch timing needs tn_exec_run");
+    if (ex->next_ticket - ex->collected >= 2) fail(TN_ESTATE, "two estimates outstanding: collect one first");
+    // outstanding estimates share the workspace and the results slot: a
+    // second one on another stream would run beside the first
+    if (ex->next_ticket != ex->collected && s != ex->submit_stream)
+        fail(TN_EINVAL, "estimates outstanding on another stream: submit on the same stream or collect first");
+    ex->submit_stream = s;
+    const int slot = (int)(ex->next_ticket & 1);
+    if (ex->opts.use_graph) {
+        // the captured tail writes the results region: copied to the slot
+        issue_estimate(ex, s);
+        const int64_t n2 = ex->results_stride / 8;   // float2-sized words
+        launch_copy_c64((const float*)ex->results_dev,
+                        (float*)((char*)ex->results_dev + (1 + slot) * ex->results_stride), n2, s);
+    } else {
+        // direct launches: the tail writes the slot itself
+        ex->res_shift = (1 + slot) * ex->results_stride;
+        try {
+            issue_estimate(ex, s);
+        } catch (...) {
+            ex->res_shift = 0;
+            throw;
+        }
+        ex->res_shift = 0;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ex->ev_done[slot], s));
+    return ex->next_ticket++;
+}
+
+// Wait for the oldest outstanding estimate and fill its results (tn_exec_collect's body).
+static void collect_one(tn_exec_s* ex, int64_t ticket, tn_result* results) {
+    if (ticket != ex->collected || ticket >= ex->next_ticket)
+        fail(TN_ESTATE, "collect submitted estimates once each, in order");
+    const int slot = (int)(ticket & 1);
+    HIPCHK(hipEventSynchronize(ex->ev_done[slot]));
+    if (results) fill_results(ex, (const char*)ex->results_host + (1 + slot) * ex->results_stride, results);
+    ++ex->collected;
+}
+
+}  // namespace tn
+
+extern "C" {
+
 int tn_exec_submit(tn_exec exh, void* stream, int64_t* ticket) {
     return guard([&] {
         tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
         if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
-        if (ex->opts.time_kernels) fail(TN_EINVAL, "per-launch timing needs tn_exec_run");
-        if (ex->next_ticket - ex->collected >= 2) fail(TN_ESTATE, "two estimates outstanding: collect one first");
-        hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
-        // outstanding estimates share the workspace and the results slot: a
-        // second one on another stream would run beside the first
-        if (ex->next_ticket != ex->collected && s != ex->submit_stream)
-            fail(TN_EINVAL, "estimates outstanding on another stream: submit on the same stream or collect first");
-        ex->submit_stream = s;
-        const int slot = (int)(ex->next_ticket & 1);
-        if (ex->opts.use_graph) {
-            // the captured tail writes the results region: copied to the slot
-            issue_estimate(ex, s);
-            const int64_t n2 = ex->results_stride / 8;   // float2-sized words
-            launch_copy_c64((const float*)ex->results_dev,
-                            (float*)((char*)ex->results_dev + (1 + slot) * ex->results_stride), n2, s);
-        } else {
-            // direct launches: the tail writes the slot itself
-            ex->res_shift = (1 + slot) * ex->results_stride;
-            try {
-                issue_estimate(ex, s);
-            } catch (...) {
-                ex->res_shift = 0;
-                throw;
-            }
-            ex->res_shift = 0;
-        }
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(ex->ev_done[slot], s));
-        if (ticket) *ticket = ex->next_ticket;
-        ++ex->next_ticket;
+        const int64_t t = submit_one(ex, stream ? (hipStream_t)stream : ex->stream);
+        if (ticket) *ticket = t;
     });
 }
 
@@ -3026,12 +3053,35 @@ int tn_exec_collect(tn_exec exh, int64_t ticket, tn_result* results) {
     return guard([&] {
         tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
         if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
-        if (ticket != ex->collected || ticket >= ex->next_ticket)
-            fail(TN_ESTATE, "collect submitted estimates once each, in order");
-        const int slot = (int)(ticket & 1);
-        HIPCHK(hipEventSynchronize(ex->ev_done[slot]));
-        if (results) fill_results(ex, (const char*)ex->results_host + (1 + slot) * ex->results_stride, results);
-        ++ex->collected;
+        collect_one(ex, ticket, results);
+    });
+}
+
+int tn_exec_run_many(tn_exec exh, void* stream, int64_t count, tn_result* results) {
+    return guard([&] {
+        tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
+        if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
+        if (count < 0) fail(TN_EINVAL, "negative estimate count");
+        if (count > 0 && !results) fail(TN_EINVAL, "null results");
+        if (ex->next_ticket != ex->collected) fail(TN_ESTATE, "submitted estimates not collected yet");
+        hipStream_t s = stream ? (hipStream_t)stream : ex->stream;
+        const int64_t np = (int64_t)ex->plans.size();
+        int64_t first = ex->next_ticket;
+        try {
+            for (int64_t i = 0; i < count; ++i) {
+                if (i >= 2) collect_one(ex, first + i - 2, results + (i - 2) * np);
+                submit_one(ex, s);
+            }
+            for (int64_t i = std::max<int64_t>(0, count - 2); i < count; ++i)
+                collect_one(ex, first + i, results + i * np);
+        } catch (...) {
+            // leave nothing outstanding: wait for what was issued, drop its results
+            while (ex->collected < ex->next_ticket) {
+                (void)hipEventSynchronize(ex->ev_done[ex->collected & 1]);
+                ++ex->collected;
+            }
+            throw;
+        }
     });
 }
 
@@ -3070,6 +3120,11 @@ int tn_exec_kernel_stats(tn_exec exh, int32_t max, tn_kernel_stat* out, int32_t*
             ex->kstat.clear();
             ex->kflops.clear();
             ex->kbytes.clear();
+            for (auto* list : {&ex->launches, &ex->launches64})
+                for (auto& L : *list) {
+                    L.t_ms = 0;
+                    L.t_n = 0;
+                }
         }
     });
 }

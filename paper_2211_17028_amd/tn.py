@@ -96,7 +96,7 @@ class tn_plan_info(C.Structure):
 EXPORTS = [
     "tn_plan_build", "tn_plan_build_doubled", "tn_polarization_combine", "tn_terms_enumerate",
     "tn_terms_enumerate_factored", "tn_terms_groups", "tn_factored_levels",
-    "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_exec_submit", "tn_exec_collect", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
+    "tn_plan_build_trajectories", "tn_terms_trajectories", "tn_exec_submit", "tn_exec_collect", "tn_exec_run_many", "tn_terms_get", "tn_exec_prepare", "tn_exec_run",
     "tn_exec_outputs", "tn_exec_timing", "tn_contract_batch", "tn_estimate", "tn_plan_workspace",
     "tn_release_cached", "tn_estimate_noalloc",
     "tn_plan_get_info", "tn_plan_noise", "tn_plan_describe", "tn_exec_describe",
@@ -141,6 +141,7 @@ def lib():
     L.tn_exec_run.argtypes = [vp, vp, C.POINTER(tn_result)]
     L.tn_exec_submit.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.tn_exec_collect.argtypes = [vp, C.c_int64, C.POINTER(tn_result)]
+    L.tn_exec_run_many.argtypes = [vp, vp, C.c_int64, C.POINTER(tn_result)]
     L.tn_exec_outputs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64)]
     L.tn_exec_timing.argtypes = [vp] + [C.POINTER(C.c_double)] * 4
     L.tn_contract_batch.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.c_int64, C.c_int64,
@@ -347,6 +348,19 @@ class Exec:
         res = (tn_result * len(self.plans))()
         _check(lib().tn_exec_collect(self.handle, ticket, res))
         return [r.as_dict() for r in res]
+
+    def run_many_raw(self, count: int, stream=None):
+        """tn_result array of `count` estimates issued in one call (two in
+        flight), estimate-major: entry i * n_plans + p."""
+        res = (tn_result * max(1, count * len(self.plans)))()
+        _check(lib().tn_exec_run_many(self.handle, _stream_ptr(stream), count, res))
+        return res
+
+    def run_many(self, count: int, stream=None) -> List[List[dict]]:
+        """Results of `count` estimates issued in one call, one list per estimate."""
+        raw = self.run_many_raw(count, stream)
+        n = len(self.plans)
+        return [[raw[i * n + p].as_dict() for p in range(n)] for i in range(count)]
 
     def run_raw(self, stream=None):
         """tn_result array of one run (one entry per plan)."""

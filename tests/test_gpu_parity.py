@@ -801,3 +801,32 @@ def test_pipelined_estimates_equal_sequential_runs(torch):
         assert ex.collect(prev)[0]["A"] == ref["A"]
         assert ex.collect(t2)[0]["A"] == ref["A"]
         assert ex.run()[0]["A"] == ref["A"]
+
+
+def test_run_many_equals_sequential_runs(torch):
+    """tn_exec_run_many (several estimates in one call, two in flight) gives
+    the same bits as tn_exec_run for every estimate, on the caller's stream and
+    on another; zero estimates is a no-op; it is refused while a submitted
+    estimate is outstanding, and with per-launch timing."""
+    print("run_many", flush=True)
+    for cfg in (5, 2):
+        c = W.config(cfg)
+        plan = tn.tn_plan_build(c, c.level)
+        terms = tn.tn_terms_enumerate(plan, c.level)
+        for graph in (False, True):
+            ex = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(use_graph=graph))
+            ref = ex.run()[0]
+            for count in (1, 2, 7):
+                rs = ex.run_many(count)
+                assert len(rs) == count and all(r[0]["A"] == ref["A"] and r[0]["T"] == ref["T"] for r in rs)
+            other = torch.cuda.Stream()
+            assert all(r[0]["A"] == ref["A"] for r in ex.run_many(5, other))
+            assert ex.run_many(0) == []
+            t = ex.submit()
+            with pytest.raises(tn.TNError):
+                ex.run_many(2)                    # a submitted estimate is outstanding
+            assert ex.collect(t)[0]["A"] == ref["A"]
+            assert ex.run()[0]["A"] == ref["A"]
+    tk = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(time_kernels=True))
+    with pytest.raises(tn.TNError):
+        tk.run_many(2)
