@@ -475,10 +475,13 @@ void k_gemm_mfma_g(GemmArgs g) {
 // ---------------------------------------------------------------------------
 // Tuning of the grouped matrix-core kernel (measured on the 25-qubit workload's
 // 128 x 32 level, 848 slices of 256 x 16 x 256 and 134 of 512 x 16 x 64):
-//   MFMA_GROUP_WAVES   register budget: two waves per SIMD leave room for the
-//                      second register set of the two-deep chunk pipeline
-//                      (three spill it); 113 us against 117 us at three waves
-//                      with one chunk of read-ahead;
+//   MFMA_GROUP_WAVES   register budget of the 64-row waves: two waves per SIMD
+//                      leave room for the second register set of the two-deep
+//                      chunk pipeline (three spill it); 113 us against 117 us at
+//                      three waves with one chunk of read-ahead;
+//   MFMA_ROWS32        32-row waves (below) at four waves per SIMD: 100 us
+//                      against 113 us on that level, and faster on every tile
+//                      shape of 64 or 128 rows but 128 x 64;
 //   MFMA_PREFETCH2     loads run two chunks ahead of the MFMAs (the operands of
 //                      tiles that miss in L2 come from HBM in a few us);
 //   MFMA_SKIP_PAD      column blocks past a tile's last slice skip their MFMAs
@@ -504,6 +507,34 @@ void k_gemm_mfma_g(GemmArgs g) {
 #ifndef MFMA_SKIP_PAD
 #define MFMA_SKIP_PAD 1
 #endif
+#ifndef MFMA_ROWS32
+#define MFMA_ROWS32 1
+#endif
+#ifndef MFMA_ROWS32_128X64
+#define MFMA_ROWS32_128X64 0
+#endif
+#ifndef MFMA_GROUP_WAVES_ROWS32
+#define MFMA_GROUP_WAVES_ROWS32 4
+#endif
+// Wave layout of the grouped kernel: WM x WN waves, each holding TM x TN
+// 32 x 32 real MFMA blocks (32 rows x 16 complex columns each).  With
+// MFMA_ROWS32 the tiles of 64 and 128 rows run 32-row waves (half the
+// accumulators of a 64-row wave), so up to four waves share each SIMD: one
+// wave alone issues FP32 MFMAs at about half the matrix core's rate, two at
+// about 85 %, four at about 94 % (a loop of independent 32 x 32 x 2 MFMAs).
+// The 128 x 64 tile keeps 64-row waves (its 32-row form measured slower: eight
+// waves per block, each re-reading B).
+template <int BM, int BNC>
+struct MfmaGroupShape {
+    static constexpr bool ROWS32 = MFMA_ROWS32 && BM >= 64 && (MFMA_ROWS32_128X64 || !(BM == 128 && BNC == 64));
+    static constexpr int WM = ROWS32 ? BM / 32 : (BM >= 64 ? BM / 64 : 1);
+    static constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int WAVES = ROWS32 ? MFMA_GROUP_WAVES_ROWS32
+                                 : (BM == 64 && BNC == 32) ? 2
+                                 : (BM == 128 && BNC == 64) ? MFMA_GROUP_WAVES_128X64
+                                                            : MFMA_GROUP_WAVES;
+};
 // Grouped matrix-core contractions (FP32 complex on mfma_f32_32x32x2f32, the
 // real embedding of K1).  One block per tile descriptor; the tile's row and
 // column offsets (A / B element offsets, C row / column offsets, -1 = padding)
@@ -511,16 +542,12 @@ void k_gemm_mfma_g(GemmArgs g) {
 // operand can fill one tile (merge modes) and any stored layout is read
 // without a transpose pass.
 // ---------------------------------------------------------------------------
-// (the one-wave 64 x 32 tile is held to two waves per SIMD, which it reaches
-// without spilling)
 template <int BM, int BNC>
-__global__ __launch_bounds__(64 * (BM >= 64 ? BM / 64 : 1) * (BNC >= 32 ? BNC / 32 : 1),
-                             (BM == 64 && BNC == 32) ? 2 : (BM == 128 && BNC == 64) ? MFMA_GROUP_WAVES_128X64
-                                                                                       : MFMA_GROUP_WAVES)
+__global__ __launch_bounds__((MfmaGroupShape<BM, BNC>::NT), (MfmaGroupShape<BM, BNC>::WAVES))
 void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__ tiles) {
-    constexpr int WM = BM >= 64 ? BM / 64 : 1;
-    constexpr int WN = BNC >= 32 ? BNC / 32 : 1;
-    constexpr int NT = 64 * WM * WN;
+    constexpr int WM = MfmaGroupShape<BM, BNC>::WM;
+    constexpr int WN = MfmaGroupShape<BM, BNC>::WN;
+    constexpr int NT = MfmaGroupShape<BM, BNC>::NT;
     constexpr int TM = BM / WM / 32;
     constexpr int TN = BNC / WN / 16;
     constexpr int BKC = MFMA_GROUP_BKC, BKC_LOG = __builtin_ctz(MFMA_GROUP_BKC);
@@ -693,7 +720,8 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
     // operands read ahead per group of RA inner indices: the whole chunk, or two
     // on 128 x 64 tiles (held to four waves per SIMD, whose 128-register budget
     // the full read-ahead would exceed; a few spills remain outside the loop)
-    constexpr int RA = (BM == 128 && BNC == 64) ? MFMA_RA_128X64 : BKC;
+    constexpr bool WIDE = BM == 128 && BNC == 64 && !MfmaGroupShape<BM, BNC>::ROWS32;
+    constexpr int RA = WIDE ? MFMA_RA_128X64 : BKC;
     // TNA: this wave's column blocks that hold outputs (the others are padding
     // past the tile's last slice or column, skipped)
     auto compute = [&](int buf, auto tna) {
@@ -743,7 +771,7 @@ void k_mfma_group(const MfmaJob* __restrict__ jobs, const MfmaTile* __restrict__
         else if (TN > 1 && tn_act == 1) compute(buf, std::integral_constant<int, 1>{});
     };
     const int64_t nchunks = c_end - c_begin;
-    if (MFMA_PREFETCH2 && !(BM == 128 && BNC == 64)) {
+    if (MFMA_PREFETCH2 && !WIDE) {
         // pipeline two chunks deep: LDS holds chunk ch, registers hold chunk
         // ch + 1, and the loads of chunk ch + 2 are in flight during chunk ch's
         // MFMAs (a chunk's loads have two chunks of matrix-core work to arrive
@@ -1942,7 +1970,7 @@ void launch_mfma_group(int tile, const MfmaJob* d_jobs, const MfmaTile* d_tiles,
     const TileCfg& t = kTiles[tile];
 #define TN_GLAUNCH(BM_, BN_)                                                                  \
     if (t.bm == BM_ && t.bnc == BN_) {                                                         \
-        constexpr int nt = 64 * (BM_ >= 64 ? BM_ / 64 : 1) * (BN_ >= 32 ? BN_ / 32 : 1);       \
+        constexpr int nt = MfmaGroupShape<BM_, BN_>::NT;                                      \
         launch_k(k_mfma_group<BM_, BN_>, dim3((unsigned)n_tiles), dim3(nt), s, d_jobs, d_tiles);  \
         return;                                                                                \
     }
