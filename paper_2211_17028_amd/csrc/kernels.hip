@@ -262,9 +262,19 @@ __device__ __forceinline__ void gst(TN_GLOBAL double2* p, double2 v) {
 }
 
 __device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int lo, int hi) {
+    // the positions are the same for every lane (a job record's legs): read
+    // as eight words into scalar registers, then applied without per-lane
+    // branches in a loop that stops at hi
+    const uint32_t* pw = reinterpret_cast<const uint32_t*>(pos);
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = __builtin_amdgcn_readfirstlane(pw[q]);
     int64_t o = 0;
-    for (int j = lo; j < hi; ++j)
-        if ((x >> j) & 1) o |= int64_t(1) << pos[j];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j >= hi) break;
+        if (j >= lo) o |= (int64_t)((x >> j) & 1) << (int)((w[j >> 2] >> (8 * (j & 3))) & 63u);
+    }
     return o;
 }
 
