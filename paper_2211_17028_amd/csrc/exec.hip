@@ -627,6 +627,35 @@ struct Builder {
             std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return oa[x] < oa[y]; });
         if (best_merge == 2)
             std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return ob[x] < ob[y]; });
+        if (best_merge == 2) {
+            // groups of slices sharing B, ordered by the smallest offset of their
+            // A: groups that share an A become neighbours, so their tiles land on
+            // one XCD at about the same time and share its L2 (the 36-qubit
+            // QAOA's 32 x 16 level, 2608 distinct A read by 8208 slices in 1584 B
+            // groups: 1.27 -> 0.85 GB fetched, 297 -> 262 us).  Groups sharing A
+            // (merge 1) keep A's order, whose neighbouring tiles read
+            // neighbouring A panels (the same reordering there measured slower).
+            const std::vector<int64_t>& mk = ob;
+            const std::vector<int64_t>& other = oa;
+            std::vector<std::pair<int64_t, int64_t>> grp;   // (min other offset, first position)
+            std::vector<int64_t> start;
+            for (int64_t i = 0; i < ns;) {
+                int64_t j = i, lo = other[order[i]];
+                while (j < ns && mk[order[j]] == mk[order[i]]) lo = std::min(lo, other[order[j++]]);
+                grp.push_back({lo, i});
+                start.push_back(i);
+                i = j;
+            }
+            start.push_back(ns);
+            std::vector<size_t> gi(grp.size());
+            std::iota(gi.begin(), gi.end(), 0);
+            std::stable_sort(gi.begin(), gi.end(), [&](size_t x, size_t y) { return grp[x].first < grp[y].first; });
+            std::vector<int64_t> reord;
+            reord.reserve(ns);
+            for (size_t g : gi)
+                for (int64_t q = start[g]; q < start[g + 1]; ++q) reord.push_back(order[q]);
+            order.swap(reord);
+        }
         std::vector<int64_t> soa(ns), sob(ns), soc(ns);
         for (int64_t i = 0; i < ns; ++i) {
             soa[i] = oa[order[i]];
