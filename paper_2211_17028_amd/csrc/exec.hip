@@ -2372,14 +2372,14 @@ static size_t exec_need(const tn_exec_s* ex) { return (size_t)(ex->const_bytes +
 // that saves more than a launch) is timed against the schedules with each of
 // the K_MFMA_TILES shapes imposed on all of the level's matrix-core jobs, the
 // levels before it keeping their chosen shapes.  Each candidate is bound to the
-// workspace and timed as whole estimates with HIP events (median of 5 after a
+// workspace and timed as whole estimates with HIP events (median of 11 after a
 // warm-up; the FP64 pass runs beside the FP32 chain as in use, and it slows the
 // tile launches it overlaps, which timing a level's launches alone misses).  A
 // shape replaces the model's choice only when its estimate is more than
 // kTuneMargin faster, so a tuned schedule is not slower than the model's beyond
 // timing noise.  Choices are cached by the level's job signature (shapes,
 // slices) for later prepares.
-constexpr double kTuneMargin = 0.03;
+constexpr double kTuneMargin = 0.05;
 constexpr int kTuneModel = -1;      // the model's own choice kept
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune_cache;
@@ -2441,7 +2441,7 @@ static std::unique_ptr<tn_exec_s> tune_grouped(std::unique_ptr<tn_exec_s> ex, in
         if (exec_need(cand.get()) > ws_bytes) return -1.0;
         bind_exec(cand.get(), d_ws, ws_bytes, s);
         std::vector<float> ts;
-        for (int rep = 0; rep < 6; ++rep) {
+        for (int rep = 0; rep < 12; ++rep) {
             issue_estimate(cand.get(), s);
             HIPCHK(hipEventRecord(cand->ev1, s));
             HIPCHK(hipEventSynchronize(cand->ev1));
