@@ -284,6 +284,38 @@ def test_small_levels_run_in_one_launch_and_depth_is_reduced():
     assert any(L["kind"] == 6 and not L["fp64"] for L in d_all["launches"] if L["phase"] == "batch")
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_merged_slices_are_grouped_and_b_groups_ordered_by_their_a(cfg):
+    """Slice order of the merged matrix-core jobs in the real schedules: a job
+    whose tiles stack slices sharing B holds each B's slices in one run, the
+    runs ordered by their smallest A (neighbouring tiles then share A panels);
+    a job whose tiles put slices sharing A side by side keeps A ascending."""
+    c = W.config(cfg)
+    plan = tn.tn_plan_build(c, c.level)
+    t = tn.tn_terms_enumerate(plan, c.level)
+    d, cb = tn.tn_exec_describe_only([plan], [t], tn.exec_opts(use_graph=False))
+    sim = Sim(d, cb)
+    seen = {1: 0, 2: 0}
+    for L in d["launches"]:
+        if L["kind"] != 6:
+            continue
+        for jb in L["jobs"]:
+            if jb["merge"] == 0:
+                continue
+            ns = jb["ns"]
+            oa = sim.view(jb["oa"], np.int64, ns)
+            ob = sim.view(jb["ob"], np.int64, ns)
+            seen[jb["merge"]] += 1
+            if jb["merge"] == 1:
+                assert np.all(np.diff(oa) >= 0)
+                continue
+            starts = np.flatnonzero(np.r_[True, ob[1:] != ob[:-1]])
+            assert len(starts) == len(np.unique(ob)), "a B's slices split into several runs"
+            mins = [oa[a:b].min() for a, b in zip(starts, np.r_[starts[1:], ns])]
+            assert all(x <= y for x, y in zip(mins, mins[1:]))
+    assert seen[1] > 0 and (cfg != 3 or seen[2] > 0), seen
+
+
 def test_schedule_replay_config1_against_oracle():
     c = W.config(1, level=2)
     x, pat, desc = _replay(c, 2)
