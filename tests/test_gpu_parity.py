@@ -312,7 +312,7 @@ def test_autotuned_grouped_schedule_gives_the_same_estimate(torch):
     against estimates with each of the 8 shapes imposed on all its jobs):
     every term within its FP32 bound of the oracle's stored values, the level
     sums within the parity bar; a level keeps the model's choice unless a
-    shape was more than 3 % faster, and a kept shape is what the level's tile
+    shape was more than 5 % faster, and a kept shape is what the level's tile
     launches use."""
     print("autotuned grouped config2", flush=True)
     c = W.config(2)
@@ -334,9 +334,11 @@ def test_autotuned_grouped_schedule_gives_the_same_estimate(torch):
         if t["us"]:            # timed here (not a cached choice)
             timed = [v for v in t["us"] if v >= 0]
             kept = t["model_us"] if t["tile"] < 0 else t["us"][t["tile"]]
-            assert kept > 0 and all(v >= 0.97 * kept * (1 - 1e-12) for v in timed), t
+            # a shape replaces the model's only when more than 5 % faster
+            # (the autotuner's margin), so nothing timed beats the kept one by more
+            assert kept > 0 and all(v >= 0.95 * kept * (1 - 1e-12) for v in timed), t
             if t["tile"] >= 0:
-                assert kept < 0.97 * t["model_us"], t
+                assert kept < 0.95 * t["model_us"], t
         if t["tile"] >= 0:
             shapes = {(L["bm"], L["bn"]) for L in d["launches"]
                       if L["kind"] == 6 and not L["fp64"] and L["level"] == t["level"]}
