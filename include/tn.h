@@ -305,9 +305,11 @@ int tn_exec_collect(tn_exec ex, int64_t ticket, tn_result* results);
  * outstanding. */
 int tn_exec_run_many(tn_exec ex, void* stream, int64_t count, tn_result* results);
 
-/* Device pointer to the per-term values X_t (float64, concatenated over the
- * packed plans in order) and to the per-term amplitudes a_t (complex64 pairs),
- * valid after tn_exec_run. */
+/* Device pointers to the per-term values X_t (float64) and the per-term
+ * amplitudes a_t (complex64 pairs) of a one-plan exec, n_total terms each,
+ * owned by the exec and valid after tn_exec_run until the next estimate or
+ * tn_exec_destroy.  TN_EINVAL for an exec of several packed plans (their
+ * outputs are separate arrays: tn_exec_copy_outputs takes a plan index). */
 int tn_exec_outputs(tn_exec ex, const double** d_x, const float** d_amp, int64_t* n_total);
 
 /* Fill up to `max` entries of per-kernel statistics; *n receives the count.

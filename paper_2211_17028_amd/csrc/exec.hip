@@ -3118,9 +3118,9 @@ int tn_exec_outputs(tn_exec exh, const double** d_x, const float** d_amp, int64_
     return guard([&] {
         tn_exec_s* ex = reinterpret_cast<tn_exec_s*>(exh);
         if (!ex || !ex->bound) fail(TN_ESTATE, "exec not prepared");
-        if (ex->plans.size() != 1) {
-            // outputs of packed plans are separate arrays; report the first
-        }
+        // each packed plan's outputs are an array of their own
+        if (ex->plans.size() != 1)
+            fail(TN_EINVAL, "packed plans: copy a plan's outputs with tn_exec_copy_outputs");
         if (d_x) *d_x = (const double*)resolve(ex, ex->plans[0].x_out);
         if (d_amp) *d_amp = (const float*)resolve(ex, ex->plans[0].amp_out);
         if (n_total) *n_total = ex->plans[0].n_terms;

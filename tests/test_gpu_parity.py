@@ -274,6 +274,8 @@ def test_packed_uneven_batch_against_oracle(torch):
     terms = [tn.tn_terms_enumerate(p, c.level) for p, c in zip(plans, cs)]
     ex = tn.tn_exec_prepare(plans, terms, tn.exec_opts(use_graph=False))
     results = ex.run()
+    with pytest.raises(tn.TNError):    # packed outputs are per plan: no single device array
+        ex.outputs()
     rng = np.random.default_rng(4)
     n_full = 0
     for i, (c, r) in enumerate(zip(cs, results)):
