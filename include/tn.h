@@ -322,9 +322,15 @@ int tn_exec_kernel_stats(tn_exec ex, int32_t max, tn_kernel_stat* out, int32_t* 
  * either pointer may be NULL).  Synchronous; valid after tn_exec_run. */
 int tn_exec_copy_outputs(tn_exec ex, int32_t plan, double* h_x, float* h_amp);
 
-/* Timing of the last tn_exec_run: total milliseconds on the stream and the
- * summed duration of GEMM / permute / other kernels (HIP events; -1 if the
- * breakdown was not recorded). */
+/* Timing of the last tn_exec_run: total milliseconds on the stream (HIP
+ * events around the estimate) and the summed durations of its contraction
+ * launches (GEMM-shaped: per-step GEMMs, grouped small steps, matrix-core
+ * tiles and their split-sum reduces), permutes and other timed kernels, from
+ * the per-launch HIP events of the launches tn_exec_kernel_stats counts (the
+ * tail launches are not timed one by one).  The breakdown is
+ * recorded when the exec was prepared with per-launch timing
+ * (tn_exec_opts.time_kernels), else each of the three is -1; before the
+ * first tn_exec_run all four are -1. */
 int tn_exec_timing(tn_exec ex, double* total_ms, double* gemm_ms, double* permute_ms,
                    double* other_ms);
 

@@ -3001,11 +3001,17 @@ int tn_exec_run(tn_exec exh, void* stream, tn_result* results) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, ex->ev0, ex->ev1));
         ex->last_ms = ms;
+        // per-launch breakdown (launches timed only with per-launch timing on)
+        const double unrec = ex->opts.time_kernels ? 0.0 : -1.0;
+        ex->gemm_ms = ex->perm_ms = ex->other_ms = unrec;
         for (auto* list : {&ex->launches, &ex->launches64})
           for (auto& L : *list)
             if (L.ev_a) {
                 float dt = 0;
                 HIPCHK(hipEventElapsedTime(&dt, L.ev_a, L.ev_b));
+                const bool contraction = L.kind == L_GEMM || L.kind == L_GROUP || L.kind == L_MGROUP ||
+                                         L.kind == L_MREDUCE;
+                (contraction ? ex->gemm_ms : L.kind == L_PERM ? ex->perm_ms : ex->other_ms) += dt;
                 auto& st = ex->kstat[L.kclass];
                 st.first += 1;
                 st.second += dt;

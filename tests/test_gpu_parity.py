@@ -811,7 +811,8 @@ def test_run_many_equals_sequential_runs(torch):
     """tn_exec_run_many (several estimates in one call, two in flight) gives
     the same bits as tn_exec_run for every estimate, on the caller's stream and
     on another; zero estimates is a no-op; it is refused while a submitted
-    estimate is outstanding, and with per-launch timing."""
+    estimate is outstanding, and with per-launch timing; tn_exec_timing's
+    per-kind breakdown is recorded with per-launch timing and -1 without."""
     print("run_many", flush=True)
     for cfg in (5, 2):
         c = W.config(cfg)
@@ -834,3 +835,12 @@ def test_run_many_equals_sequential_runs(torch):
     tk = tn.tn_exec_prepare([plan], [terms], tn.exec_opts(time_kernels=True))
     with pytest.raises(tn.TNError):
         tk.run_many(2)
+    # timing breakdown: per-launch sums with per-launch timing, -1 without
+    a_tk = tk.run()[0]["A"]
+    assert all(abs(x - y) <= 1e-12 * abs(y) for x, y in zip(a_tk, ref["A"]))
+    total, contraction, permute, other = tk.timing()
+    assert total > 0 and contraction > 0 and permute >= 0 and other >= 0
+    assert contraction + permute + other <= 2 * total    # two streams at most overlap
+    ex.run()
+    total, contraction, permute, other = ex.timing()
+    assert total > 0 and contraction == permute == other == -1
